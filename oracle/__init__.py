@@ -1,0 +1,382 @@
+"""Plain FP64 CPU oracle for the curvilinear PIC hot path (arXiv:1311.2286).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  It shares no code with
+the HIP library and imports nothing from it; the two meet only through the
+seeded input generators, which hold none of the method's arithmetic.
+
+The arithmetic lives in ``oracle.c`` (plain loops, FP64, no FMA contraction);
+this module is ctypes marshalling plus a few one-line numpy reductions
+(charge per cell, energies) and ``OracleSim``, which strings the routines
+together in the order of the PIC cycle (Sec. II: mover, particle-to-grid,
+field solve, grid-to-particle).
+
+Parity pins: every routine here is pinned by a test in ``tests/test_oracle_*``
+against a closed form, an invariant, a brute-force evaluation or a value the
+paper prints.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+IDENTITY, SINUSOIDAL, POLAR_LOG, SPHERICAL_RZ = 0, 1, 2, 3
+PERIODIC, DIRICHLET, NEUMANN = 0, 1, 2
+B1, B2 = 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (FP64, -ffp-contract=off, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+             "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Map(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("dim", ctypes.c_int), ("L", ctypes.c_double * 3),
+                ("eps", ctypes.c_double), ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
+                ("omega", ctypes.c_int)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("bc_lo", ctypes.c_int * 3),
+                ("bc_hi", ctypes.c_int * 3), ("phi_lo", ctypes.c_double * 3),
+                ("phi_hi", ctypes.c_double * 3)]
+
+
+def make_map(kind, dim, L=(1.0, 1.0, 1.0), eps=0.0, r_in=1.0, r_out=2.0, omega=0) -> Map:
+    L = tuple(L) + (1.0,) * (3 - len(L))
+    return Map(kind, dim, (ctypes.c_double * 3)(*L), eps, r_in, r_out, omega)
+
+
+def make_grid(n, bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), phi_lo=(0.0, 0.0, 0.0),
+              phi_hi=(0.0, 0.0, 0.0)) -> Grid:
+    dim = len(n)
+    nn = tuple(n) + (1,) * (3 - dim)
+    f = lambda t, v: tuple(t) + (v,) * (3 - len(t))
+    return Grid(dim, (ctypes.c_int * 3)(*nn), (ctypes.c_int * 3)(*f(bc_lo, 0)),
+                (ctypes.c_int * 3)(*f(bc_hi, 0)), (ctypes.c_double * 3)(*f(phi_lo, 0.0)),
+                (ctypes.c_double * 3)(*f(phi_hi, 0.0)))
+
+
+_lib_handle = None
+
+
+def lib():
+    global _lib_handle
+    if _lib_handle is None:
+        build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        d, i32, u64, u8, u32 = (ctypes.c_double, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint8,
+                                ctypes.c_uint32)
+        lg = ctypes.c_long
+        L.or_map_eval.argtypes = [P(Map), lg, P(d), P(d), P(d), P(d), P(d)]
+        L.or_coef_eval.argtypes = [P(Map), lg, P(d), P(d)]
+        L.or_map_invert.argtypes = [P(Map), lg, P(d), P(d), P(d)]
+        L.or_deposit_fixed.argtypes = [P(Grid), ctypes.c_int, ctypes.c_int, lg, P(i32), P(d),
+                                       P(u8), P(u64)]
+        L.or_deposit_fixed.restype = lg
+        L.or_deposit_f64.argtypes = [P(Grid), ctypes.c_int, lg, P(i32), P(d), P(d)]
+        L.or_deposit_f64.restype = lg
+        L.or_gl8.argtypes = [P(d), P(d)]
+        L.or_ion_background.argtypes = [P(Map), P(Grid), ctypes.c_int, d, P(d)]
+        L.or_poisson_assemble.argtypes = [P(Map), P(Grid), P(d), P(d)]
+        L.or_apply.argtypes = [P(Grid), P(d), P(d), P(d)]
+        L.or_cg.argtypes = [P(Grid), P(d), P(d), P(d), d, ctypes.c_int, P(d)]
+        L.or_poisson_solve.argtypes = [P(Map), P(Grid), P(d), P(d), d, ctypes.c_int, P(d)]
+        L.or_efield.argtypes = [P(Map), P(Grid), P(d), P(d)]
+        L.or_gather.argtypes = [P(Grid), P(d), lg, P(i32), P(d), P(d)]
+        L.or_boris.argtypes = [lg, P(d), P(d), P(d), d, d]
+        L.or_push.argtypes = [P(Map), P(Grid), d, d, P(d), lg, P(i32), P(d), P(d), P(d), P(lg)]
+        L.or_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
+        _lib_handle = L
+    return _lib_handle
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _pts(a):
+    """(n, d) or (n, 3) -> contiguous (n, 3) float64."""
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a[None, :]
+    out = np.zeros((a.shape[0], 3))
+    out[:, :a.shape[1]] = a
+    return out
+
+
+def ncells(g: Grid) -> int:
+    return int(np.prod([g.n[a] for a in range(g.dim)]))
+
+
+def nverts(g: Grid) -> int:
+    return int(np.prod([g.n[a] if g.bc_lo[a] == PERIODIC else g.n[a] + 1 for a in range(g.dim)]))
+
+
+# ---------------------------------------------------------------- maps
+def map_eval(m: Map, xi):
+    xi = _pts(xi)
+    n = xi.shape[0]
+    x = np.zeros((n, 3)); jac = np.zeros((n, 9)); k = np.zeros((n, 9)); J = np.zeros(n)
+    lib().or_map_eval(ctypes.byref(m), n, _p(xi, ctypes.c_double), _p(x, ctypes.c_double),
+                      _p(jac, ctypes.c_double), _p(k, ctypes.c_double), _p(J, ctypes.c_double))
+    return x, jac.reshape(n, 3, 3), k.reshape(n, 3, 3), J
+
+
+def coef_eval(m: Map, xi):
+    xi = _pts(xi)
+    n = xi.shape[0]
+    a = np.zeros((n, 9))
+    lib().or_coef_eval(ctypes.byref(m), n, _p(xi, ctypes.c_double), _p(a, ctypes.c_double))
+    return a.reshape(n, 3, 3)
+
+
+def map_invert(m: Map, x, xi_old=None):
+    x = _pts(x)
+    n = x.shape[0]
+    xi = np.zeros((n, 3))
+    xo = _pts(xi_old) if xi_old is not None else None
+    lib().or_map_invert(ctypes.byref(m), n, _p(x, ctypes.c_double),
+                        _p(xo, ctypes.c_double) if xo is not None else None,
+                        _p(xi, ctypes.c_double))
+    return xi
+
+
+# ---------------------------------------------------------------- deposit
+def deposit_fixed(g: Grid, shape: int, S1: int, cell, off, cell_mask=None):
+    """Integer weights at scale 2^S1 per axis, summed exactly (uint64)."""
+    cell = np.ascontiguousarray(cell, dtype=np.int32)
+    off = _pts(off)
+    Q = np.zeros(ncells(g), dtype=np.uint64)
+    mask = None
+    if cell_mask is not None:
+        mask = np.ascontiguousarray(cell_mask, dtype=np.uint8)
+    r = lib().or_deposit_fixed(ctypes.byref(g), shape, S1, cell.size, _p(cell, ctypes.c_int32),
+                               _p(off, ctypes.c_double),
+                               _p(mask, ctypes.c_uint8) if mask is not None else None,
+                               _p(Q, ctypes.c_uint64))
+    if r < 0:
+        raise MemoryError("oracle deposit")
+    return Q
+
+
+def deposit_f64(g: Grid, shape: int, cell, off):
+    cell = np.ascontiguousarray(cell, dtype=np.int32)
+    off = _pts(off)
+    Q = np.zeros(ncells(g))
+    lib().or_deposit_f64(ctypes.byref(g), shape, cell.size, _p(cell, ctypes.c_int32),
+                         _p(off, ctypes.c_double), _p(Q, ctypes.c_double))
+    return Q
+
+
+def gl8():
+    x = np.zeros(8); w = np.zeros(8)
+    lib().or_gl8(_p(x, ctypes.c_double), _p(w, ctypes.c_double))
+    return x, w
+
+
+def ion_background(m: Map, g: Grid, shape: int, n0: float = 1.0):
+    I = np.zeros(ncells(g))
+    rc = lib().or_ion_background(ctypes.byref(m), ctypes.byref(g), shape, n0, _p(I, ctypes.c_double))
+    if rc:
+        raise ValueError("ion background needs an all-periodic grid")
+    return I
+
+
+# ---------------------------------------------------------------- Poisson
+def stencil_size(g: Grid) -> int:
+    return 27 if g.dim == 3 else 9
+
+
+def poisson_assemble(m: Map, g: Grid):
+    nc = ncells(g)
+    A = np.zeros((nc, stencil_size(g)))
+    bd = np.zeros(nc)
+    rc = lib().or_poisson_assemble(ctypes.byref(m), ctypes.byref(g), _p(A, ctypes.c_double),
+                                   _p(bd, ctypes.c_double))
+    if rc:
+        raise ValueError("unsupported map/boundary combination (%d)" % rc)
+    return A, bd
+
+
+def apply(g: Grid, A, x):
+    x = _f64(x)
+    y = np.zeros(ncells(g))
+    lib().or_apply(ctypes.byref(g), _p(A, ctypes.c_double), _p(x, ctypes.c_double),
+                   _p(y, ctypes.c_double))
+    return y
+
+
+def cg(g: Grid, A, b, x0=None, rtol=1e-13, maxit=100000):
+    b = _f64(b)
+    x = np.zeros(ncells(g)) if x0 is None else _f64(x0).copy()
+    rr = ctypes.c_double(0.0)
+    it = lib().or_cg(ctypes.byref(g), _p(A, ctypes.c_double), _p(b, ctypes.c_double),
+                     _p(x, ctypes.c_double), rtol, maxit, ctypes.byref(rr))
+    return x, it, rr.value
+
+
+def poisson_solve(m: Map, g: Grid, charge, phi0=None, rtol=1e-13, maxit=200000):
+    """A phi = -charge - (wall terms); returns (phi, iterations, relative residual)."""
+    charge = _f64(charge)
+    phi = np.zeros(ncells(g)) if phi0 is None else _f64(phi0).copy()
+    rr = ctypes.c_double(0.0)
+    it = lib().or_poisson_solve(ctypes.byref(m), ctypes.byref(g), _p(charge, ctypes.c_double),
+                                _p(phi, ctypes.c_double), rtol, maxit, ctypes.byref(rr))
+    if it < 0:
+        raise ValueError("unsupported map/boundary combination (%d)" % it)
+    return phi, it, rr.value
+
+
+def efield(m: Map, g: Grid, phi):
+    phi = _f64(phi)
+    Ev = np.zeros((nverts(g), 3))
+    lib().or_efield(ctypes.byref(m), ctypes.byref(g), _p(phi, ctypes.c_double),
+                    _p(Ev, ctypes.c_double))
+    return Ev
+
+
+# ---------------------------------------------------------------- particles
+def gather(g: Grid, Ev, cell, off):
+    cell = np.ascontiguousarray(cell, dtype=np.int32)
+    off = _pts(off)
+    Ev = _f64(Ev)
+    Ep = np.zeros((cell.size, 3))
+    lib().or_gather(ctypes.byref(g), _p(Ev, ctypes.c_double), cell.size, _p(cell, ctypes.c_int32),
+                    _p(off, ctypes.c_double), _p(Ep, ctypes.c_double))
+    return Ep
+
+
+def boris(v, E, B, qm, dt):
+    v = _pts(v).copy()
+    E = _pts(E)
+    Bv = _f64(np.asarray(B, dtype=np.float64).reshape(3))
+    lib().or_boris(v.shape[0], _p(v, ctypes.c_double), _p(E, ctypes.c_double),
+                   _p(Bv, ctypes.c_double), qm, dt)
+    return v
+
+
+def push(m: Map, g: Grid, qm, dt, B, cell, off, vel, Ev):
+    """Gather + Boris + map inversion + boundaries, in place on copies.
+    Returns (cell, off, vel, (absorbed, outflow))."""
+    cell = np.ascontiguousarray(cell, dtype=np.int32).copy()
+    off = _pts(off).copy()
+    vel = _pts(vel).copy()
+    Ev = _f64(Ev)
+    Bv = _f64(np.asarray(B, dtype=np.float64).reshape(3))
+    counts = (ctypes.c_long * 2)()
+    lib().or_push(ctypes.byref(m), ctypes.byref(g), qm, dt, _p(Bv, ctypes.c_double), cell.size,
+                  _p(cell, ctypes.c_int32), _p(off, ctypes.c_double), _p(vel, ctypes.c_double),
+                  _p(Ev, ctypes.c_double), counts)
+    return cell, off, vel, (counts[0], counts[1])
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().or_philox4x32_10(_p(c, ctypes.c_uint32), _p(k, ctypes.c_uint32), _p(o, ctypes.c_uint32))
+    return o
+
+
+# ---------------------------------------------------------------- grid sums
+def charge_from_Q(Qs, species, dim, S1=None, background=None, bg_charge=1.0):
+    """Charge per cell: sum_s q_s w_s Q_s (Q_s scaled by 2^-(d S1) when
+    integer) plus the fixed background charge.  Eq. (pg) times J_c dV."""
+    ch = None
+    for Q, sp in zip(Qs, species):
+        if Q.dtype == np.uint64:
+            # exact integer -> FP64 conversion is a single rounding per cell
+            qv = Q.astype(np.float64) * 2.0 ** (-dim * S1)
+        else:
+            qv = Q
+        t = sp["q"] * sp["w"] * qv
+        ch = t if ch is None else ch + t
+    if background is not None:
+        ch = ch + bg_charge * background
+    return ch
+
+
+def field_energy(charge, phi):
+    """W_E = 1/2 sum_c (J rho dV)_c phi_c."""
+    return 0.5 * float(np.dot(charge, phi))
+
+
+class OracleSim:
+    """The PIC cycle of Sec. II in leap-frog order: gather E^n -> v^{n+1/2} ->
+    xi^{n+1} -> boundaries -> deposit -> charge -> phi^{n+1} -> E^{n+1}.
+
+    species: list of dicts with q, m, w and arrays cell (int32), off (n,3),
+    vel (n,3) in FP64.  deposit: 'fixed' (integer weights) or 'f64'."""
+
+    def __init__(self, m: Map, g: Grid, species, shape=B2, dt=0.1, B=(0.0, 0.0, 0.0),
+                 background=None, deposit="fixed", rtol=1e-13):
+        self.m, self.g, self.sp = m, g, species
+        self.shape, self.dt, self.B = shape, dt, np.asarray(B, dtype=np.float64)
+        self.bg = background
+        self.mode = deposit
+        self.S1 = 24 if g.dim == 2 else 16
+        self.rtol = rtol
+        self.phi = np.zeros(ncells(g))
+        self.step_count = 0
+        self.ke = None
+
+    def deposit(self):
+        if self.mode == "fixed":
+            self.Q = [deposit_fixed(self.g, self.shape, self.S1, s["cell"], s["off"]) for s in self.sp]
+        else:
+            self.Q = [deposit_f64(self.g, self.shape, s["cell"], s["off"]) for s in self.sp]
+        self.charge = charge_from_Q(self.Q, self.sp, self.g.dim, self.S1, self.bg)
+
+    def solve(self):
+        self.phi, self.cg_iters, self.relres = poisson_solve(self.m, self.g, self.charge, self.phi,
+                                                             rtol=self.rtol)
+        self.Ev = efield(self.m, self.g, self.phi)
+
+    def initialize(self):
+        """Deposit, solve, field; then the half-step push-back
+        v^{-1/2} = Boris(v^0, E^0, B, -dt/2)."""
+        self.deposit()
+        self.solve()
+        for s in self.sp:
+            E = gather(self.g, self.Ev, s["cell"], s["off"])
+            s["vel"] = boris(s["vel"], E, self.B, s["q"] / s["m"], -0.5 * self.dt)
+
+    def step(self):
+        ke = 0.0
+        self.counts = []
+        for s in self.sp:
+            v_old = s["vel"].copy()
+            s["cell"], s["off"], s["vel"], cnt = push(self.m, self.g, s["q"] / s["m"], self.dt,
+                                                      self.B, s["cell"], s["off"], s["vel"], self.Ev)
+            alive = s["cell"] >= 0
+            ke += 0.5 * s["m"] * s["w"] * float(np.sum(v_old[alive] * s["vel"][alive]))
+            self.counts.append(cnt)
+        self.ke = ke
+        self.deposit()
+        self.solve()
+        self.step_count += 1
+
+    def field_energy(self):
+        return field_energy(self.charge, self.phi)
