@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark: particle pushes/s of the curvilinear PIC step on one MI355X.
+
+Default workload: the 3D periodic box (128^3 cells, sinusoidal map eps = 0.05
+on all axes, 32 electrons + 32 ions per cell = 134,217,728 particles,
+m_i/m_e = 1836, T_i = T_e), FP32 particles with the 64-bit fixed-point
+deposit, order-2 B-spline deposit; the plain FP64 path is timed on the same
+workload beside it.  A step is one full PIC cycle (particle kernel: gather +
+push + Newton map inversion + boundaries + deposit; charge; multigrid solve;
+vertex field; tile sort).  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line (see the design doc for the fields)."""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle pushes/s (gather+push+map-invert+deposit) FP32 vs FP64; p50/p99 step ms"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_1311_2286_amd import workloads as W
+    return {"box3d_128": W.case2, "langmuir2d": W.case1, "box3d_magnetized": W.case5,
+            "probe2d_512": W.case3}[name]()
+
+
+def bytes_per_particle(dim, precision, magnetic):
+    """Algorithmic HBM bytes per particle push: state read once and written
+    once.  FP32: int32 cell + dim FP32 offsets + FP32 velocities (2 in 2D
+    without B, else 3); FP64: int32 cell + dim FP64 offsets + 3 FP64 v."""
+    r = 8 if precision == 1 else 4
+    nv = 3 if (dim == 3 or magnetic) else 2
+    return 2 * (4 + dim * r + nv * r)
+
+
+def bytes_per_cell(dim, precision):
+    """Per cell per particle-kernel launch: the vertex field read (dim
+    components) and the species' deposit written (8 B)."""
+    r = 8 if precision == 1 else 4
+    return dim * r + 8
+
+
+def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts):
+    from paper_1311_2286_amd import cpic as C
+    sim = C.Sim(case.map_kind, case.dim, case.n, L=case.L, eps=case.eps, r_in=case.r_in,
+                r_out=case.r_out, bc_lo=case.bc_lo, bc_hi=case.bc_hi, phi_lo=case.phi_lo,
+                phi_hi=case.phi_hi, shape=shape, precision=precision, dt=case.dt, B0=case.B,
+                background=case.background, mg_rtol=mg_rtol, mg_max_cycles=mg_cycles,
+                sort_every=sort_every, track_ids=False)
+    for sid, s in enumerate(case.species):
+        p = parts[sid]
+        n = p["cell"].size
+        pbc_lo = tuple(0 if b == 0 else C.PBC_ABSORB for b in case.bc_lo)
+        pbc_hi = tuple(0 if b == 0 else C.PBC_OUTFLOW for b in case.bc_hi)
+        sim.add_species(s.q, s.m, case.weight(s), n, pbc_lo=pbc_lo, pbc_hi=pbc_hi)
+        from paper_1311_2286_amd import workloads as W
+        q = W.as_dtype(p, np.float64 if precision == 1 else np.float32)
+        sim.set_particles(sid, q["cell"], q["off"], q["vel"])
+        del q
+    return sim
+
+
+def run_path(case, parts, precision, shape, steps, warmup, sort_every, mg_rtol, mg_cycles):
+    import torch
+    from paper_1311_2286_amd import cpic as C
+    t0 = time.time()
+    sim = make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts)
+    sim.initialize()
+    sim.sync()
+    log("precision", precision, "set up + initialise %.1f s" % (time.time() - t0))
+    if warmup > 0:
+        sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    sim.set_timing(True)
+    t1 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    tm = sim.get_timing()
+    d = sim.diag()
+    sim.set_timing(False)
+    n_p = sum(p["cell"].size for p in parts)
+    res = dict(wall_s=wall, ms_per_step=1e3 * wall / steps, pushes=n_p,
+               pushes_per_s=n_p * steps / wall,
+               push_ms=float(np.mean(tm["push"])), solve_ms=float(np.mean(tm["solve"])),
+               sort_ms=float(np.mean(tm["sort"])),
+               p50_step_ms=float(np.percentile(tm["step"], 50)),
+               p99_step_ms=float(np.percentile(tm["step"], 99)),
+               mg_cycles_last=int(d.mg_cycles), mg_relres_last=float(d.mg_relres),
+               newton_fallback=int(d.newton_fallback), newton_failed=int(d.newton_failed),
+               far_deposits=int(d.far_deposits))
+    nspec = len(parts)
+    magnetic = any(case.B)
+    bp = bytes_per_particle(case.dim, precision, magnetic)
+    bc = bytes_per_cell(case.dim, precision)
+    per_launch = (n_p / nspec) * bp + case.ncells * bc
+    launch_ms = res["push_ms"] / nspec
+    res["kernel_pushes_per_s"] = n_p / (res["push_ms"] * 1e-3)
+    res["bytes_per_particle"] = bp
+    res["bytes_per_cell"] = bc
+    res["bytes_per_launch"] = per_launch
+    res["launch_ms"] = launch_ms
+    res["achieved_GBs"] = per_launch / (launch_ms * 1e-3) / 1e9
+    sim.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(case, sample, shape):
+    """The FP64 oracle (gather + Boris + exact map inversion + deposit) on the
+    host cores, on the first `sample` particles of each species."""
+    import oracle as O
+    from paper_1311_2286_amd import workloads as W
+    m = O.make_map(**case.map_args())
+    g = O.make_grid(**case.grid_args())
+    nv = O.nverts(g)
+    E = W.synthetic_ev(case, nv, dtype=np.float64, scale=0.05)
+    S1 = 24 if case.dim == 2 else 16
+    t_total = 0.0
+    n_total = 0
+    for sid, s in enumerate(case.species):
+        p = W.to_oracle(W.generate_species(case, sid, dtype=np.float32, count=sample))
+        t0 = time.perf_counter()
+        cell, off, vel, _ = O.push(m, g, s.q / s.m, case.dt, case.B, p["cell"], p["off"], p["vel"], E)
+        O.deposit_fixed(g, shape, S1, cell, off)
+        t_total += time.perf_counter() - t0
+        n_total += p["cell"].size
+    threads = O.num_threads()
+    return dict(value=n_total / t_total, unit="particle pushes/s", cores=threads, kind="oracle",
+                sample="%d particles per species (first of each seeded stream), one "
+                       "gather+push+map-inversion+deposit pass, %.1f s" % (sample, t_total))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="box3d_128")
+    ap.add_argument("--shape", default="b2", choices=["b2", "b1"])
+    ap.add_argument("--sort-every", type=int, default=4)
+    ap.add_argument("--mg-rtol", type=float, default=1e-8)
+    ap.add_argument("--mg-cycles", type=int, default=6)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
+              "'How the path would shard'); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    from paper_1311_2286_amd import cpic as C
+    from paper_1311_2286_amd import workloads as W
+    C.load()
+    case = workload(args.workload)
+    shape = C.SHAPE_B2 if args.shape == "b2" else C.SHAPE_B1
+    t0 = time.time()
+    parts = [W.generate_species(case, sid, dtype=np.float64 if not args.no_fp64 else np.float32,
+                                workers=16) for sid in range(len(case.species))]
+    log("generated %d particles in %.1f s" % (sum(p["cell"].size for p in parts), time.time() - t0))
+    r32 = run_path(case, parts, C.FP32, shape, args.steps, args.warmup, args.sort_every,
+                   args.mg_rtol, args.mg_cycles)
+    log("fp32", json.dumps(r32))
+    r64 = None
+    if not args.no_fp64:
+        r64 = run_path(case, parts, C.FP64, shape, args.steps, args.warmup, args.sort_every,
+                       args.mg_rtol, args.mg_cycles)
+        log("fp64", json.dumps(r64))
+    del parts
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(case, args.cpu_sample, shape)
+        log("cpu", json.dumps(cpu))
+    n_p = r32["pushes"]
+    out = {
+        "metric": METRIC,
+        "value": r32["pushes_per_s"],
+        "unit": "particle pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %dD periodic sinusoidal map eps=%g, %s cells, %s, %d particles, "
+                               "%s deposit, FP32 particles + int64 fixed-point deposit, dt=%g"
+                               % (case.name, case.dim, case.eps, "x".join(map(str, case.n)),
+                                  " + ".join("%g %s/cell" % (s.ppc, s.name) for s in case.species),
+                                  n_p, args.shape.upper(), case.dt),
+                   "sort_every": args.sort_every, "mg_rtol": args.mg_rtol,
+                   "mg_max_cycles": args.mg_cycles},
+        "p50_step_ms": r32["p50_step_ms"],
+        "p99_step_ms": r32["p99_step_ms"],
+        "particle_kernel_pushes_per_s": r32["kernel_pushes_per_s"],
+        "phase_ms": {"particles": r32["push_ms"], "field": r32["solve_ms"], "sort": r32["sort_ms"]},
+        "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": r32["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "particle_kernel (one launch per species)",
+                     "bytes_per_launch": r32["bytes_per_launch"],
+                     "launch_ms": r32["launch_ms"]},
+        "cpu_baseline": cpu,
+    }
+    if r64 is not None:
+        out["fp64_path"] = {"value": r64["pushes_per_s"], "unit": "particle pushes/s",
+                            "ms_per_step": r64["ms_per_step"], "p50_step_ms": r64["p50_step_ms"],
+                            "p99_step_ms": r64["p99_step_ms"],
+                            "particle_kernel_pushes_per_s": r64["kernel_pushes_per_s"],
+                            "achieved_GBs": r64["achieved_GBs"],
+                            "frac": r64["achieved_GBs"] / HBM_PEAK_GBS,
+                            "bytes_per_launch": r64["bytes_per_launch"],
+                            "launch_ms": r64["launch_ms"],
+                            "phase_ms": {"particles": r64["push_ms"], "field": r64["solve_ms"],
+                                         "sort": r64["sort_ms"]}}
+    out["diagnostics"] = {k: r32[k] for k in ("mg_cycles_last", "mg_relres_last", "newton_fallback",
+                                              "newton_failed", "far_deposits")}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

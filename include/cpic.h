@@ -1,0 +1,224 @@
+/*
+ * cpic.h -- C ABI of the MI355X curvilinear particle-in-cell hot path.
+ *
+ * What is computed (Delzanno et al., "CPIC: a Curvilinear Particle-In-Cell
+ * code for plasma-material interaction studies", arXiv:1311.2286):
+ *   - a map x(xi) from the logical unit cube to physical space and its metric
+ *     (Sec. II.A, Eqs. map, jcov, jcon, jac, gcon; the sinusoidal test map of
+ *     Eq. map2; a polar-log annulus map; the identity / affine map);
+ *   - particles with logical position xi (cell index + in-cell offset) and
+ *     physical velocity v -- the hybrid mover of Sec. II.B;
+ *   - one electrostatic PIC cycle in leap-frog order (Sec. II, four-step
+ *     cycle): gather of the vertex field (Eqs. vvp, Wvp, b1), velocity push
+ *     (Eqs. step1, step1a; Boris rotation when a uniform B0 is set), position
+ *     update x(xi^n) + dt v^{n+1/2} mapped back to xi by Newton iterations on
+ *     the map, particle boundaries (periodic, absorbing wall, outflow), charge
+ *     deposit divided by the cell volume J_c dxi deta dzeta (Eqs. pg, Wpc,
+ *     b2), and the Poisson solve of Eq. poiscurv by geometric multigrid, with
+ *     the field E = -grad phi formed at vertices (Sec. II.B staggering).
+ *
+ * Units are the paper's normalised ones (Sec. II.B): lengths in Debye
+ * lengths, velocities in electron thermal speeds, time in 1/omega_pe,
+ * potential in T_e/e, epsilon_0 = 1, reference density n0 = 1.
+ *
+ * Conventions used by every call
+ *   - cell index (input and output): c = i + n0 * (j + n1 * k), 0 <= i < n0 ...
+ *   - offsets: in-cell logical offset per axis in [0, 1), structure of arrays
+ *     off[a * n + p] for axis a < dim;
+ *   - velocities: physical, three components always, vel[a * n + p];
+ *   - floating point type of off/vel/fields: float for CPIC_FP32, double for
+ *     CPIC_FP64 (cpic_grid_desc.precision);
+ *   - vertex field: physical components, vertex v = i + nv0 * (j + nv1 * k)
+ *     with nv_a = n_a on periodic axes and n_a + 1 on bounded axes, interleaved
+ *     with a component stride of 2 (2D) or 4 (3D; the 4th slot is padding);
+ *   - all launches are asynchronous on the stream given at creation; calls
+ *     that return data to the host synchronise that stream.
+ *
+ * Ownership: the library copies what it is given (set_* calls) and never frees
+ * caller memory.  Library memory comes from the caller's allocator (or
+ * hipMalloc when none is given) and is returned by cpic_destroy.
+ *
+ * Errors: every call returns a cpic_status; arguments are validated before any
+ * launch, so a failed call leaves the simulation unchanged.  An asynchronous
+ * device fault surfaces as CPIC_E_HIP at the next synchronising call and
+ * poisons the simulation.  cpic_last_error() returns a description of the last
+ * failure on that simulation.  A simulation is used from one host thread at a
+ * time.
+ */
+#ifndef CPIC_H_
+#define CPIC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cpic_sim cpic_sim;
+
+typedef enum {
+  CPIC_OK = 0,
+  CPIC_E_ARG = -1,         /* invalid argument / descriptor */
+  CPIC_E_MAP = -2,         /* map not invertible on the domain (J <= 0) */
+  CPIC_E_NOMEM = -3,       /* allocation failed */
+  CPIC_E_BUDGET = -4,      /* capacity exceeded */
+  CPIC_E_HIP = -5,         /* HIP runtime error */
+  CPIC_E_OVERFLOW = -6,    /* fixed-point deposit headroom exceeded */
+  CPIC_E_NONFINITE = -7,   /* non-finite value found in a field */
+  CPIC_E_STATE = -8,       /* call out of order */
+  CPIC_E_UNSUPPORTED = -9  /* valid but not implemented combination */
+} cpic_status;
+
+/* map kinds */
+enum { CPIC_MAP_IDENTITY = 0, CPIC_MAP_SINUSOIDAL = 1, CPIC_MAP_POLAR_LOG = 2 };
+/* field boundary conditions per axis side (ghost cells, Sec. II.B) */
+enum { CPIC_BC_PERIODIC = 0, CPIC_BC_DIRICHLET = 1, CPIC_BC_NEUMANN = 2 };
+/* particle boundary conditions per axis side */
+enum { CPIC_PBC_PERIODIC = 0, CPIC_PBC_ABSORB = 1, CPIC_PBC_OUTFLOW = 2 };
+/* deposit shape: order-2 B-spline of Eq. b2 (default) or CIC */
+enum { CPIC_SHAPE_B2 = 2, CPIC_SHAPE_B1 = 1 };
+/* particle precision: FP32 offsets/velocities with 64-bit fixed-point deposit,
+   or plain FP64 throughout (FP64 deposit) */
+enum { CPIC_FP32 = 0, CPIC_FP64 = 1 };
+/* fields for get/set */
+enum {
+  CPIC_FIELD_Q = 0,      /* deposit of one species: uint64 (FP32 path) or double */
+  CPIC_FIELD_CHARGE = 1, /* charge per cell, J rho dV (double) */
+  CPIC_FIELD_PHI = 2,    /* potential at cell centres (double) */
+  CPIC_FIELD_EV = 3,     /* vertex field (float or double, interleaved) */
+  CPIC_FIELD_JC = 4,     /* physical Jacobian at cell centres (double) */
+  CPIC_FIELD_RHO = 5,    /* charge density rho = charge / (J_c dV) (double) */
+  CPIC_FIELD_BACKGROUND = 6 /* fixed background charge per cell (double) */
+};
+/* single stages of the step, for tests and timing */
+enum {
+  CPIC_STAGE_SORT = 0,     /* tile-sort (and compact) all species */
+  CPIC_STAGE_DEPOSIT = 1,  /* Q_s <- deposit of the current positions */
+  CPIC_STAGE_CHARGE = 2,   /* charge <- sum_s q_s w_s Q_s + background */
+  CPIC_STAGE_SOLVE = 3,    /* phi <- multigrid solve from charge */
+  CPIC_STAGE_EFIELD = 4,   /* E_v <- -k^T D phi at vertices */
+  CPIC_STAGE_PUSH = 5,     /* gather + push + map inversion + boundaries + deposit */
+  CPIC_STAGE_HALFSTEP = 6  /* v <- Boris(v, E, B, -dt/2): initial velocity push-back */
+};
+
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} cpic_allocator;
+
+typedef struct {
+  int kind;       /* CPIC_MAP_* */
+  int dim;        /* 2 or 3 */
+  double L[3];    /* box lengths (identity, sinusoidal) */
+  double eps;     /* sinusoidal amplitude, relative to the box */
+  double r_in;    /* polar-log inner radius */
+  double r_out;   /* polar-log outer radius */
+} cpic_map_desc;
+
+typedef struct {
+  int n[3];             /* cells per axis (n[2] ignored in 2D) */
+  int bc_lo[3], bc_hi[3];
+  double phi_lo[3], phi_hi[3]; /* Dirichlet wall values */
+  int shape;            /* CPIC_SHAPE_B2 / CPIC_SHAPE_B1 */
+  int precision;        /* CPIC_FP32 / CPIC_FP64 */
+  double dt;
+  double B0[3];         /* uniform background magnetic field */
+  int background;       /* 1: fixed neutralising background of density n0 */
+  double background_n0; /* its density (charge +n0 per unit volume) */
+  double mg_rtol;       /* relative residual target of the Poisson solve */
+  int mg_max_cycles;    /* multigrid V-cycles per solve (upper bound) */
+  int sort_every;       /* tile sort every this many steps (>= 1) */
+  int track_ids;        /* carry a uint32 particle id through sorts */
+} cpic_grid_desc;
+
+typedef struct {
+  double q, m, w;       /* charge, mass, macro-weight */
+  int pbc_lo[3], pbc_hi[3];
+  size_t capacity;      /* maximum particle count */
+} cpic_species_desc;
+
+typedef struct {
+  long long step;
+  double kinetic;        /* 1/2 sum m w v^{n-1/2} . v^{n+1/2} of the last push */
+  double field_energy;   /* 1/2 sum_c charge_c phi_c */
+  double mg_relres;      /* final relative residual of the last solve */
+  int mg_cycles;         /* V-cycles used by the last solve */
+  int nspecies;
+  long long count[8];    /* live particles per species */
+  long long absorbed[8]; /* cumulative absorbed at lower walls */
+  long long outflow[8];  /* cumulative lost through upper walls */
+  uint64_t qsum_lo[8];   /* sum_c Q_s (exact, 128-bit: lo, hi words) */
+  uint64_t qsum_hi[8];
+  long long newton_fallback; /* cumulative FP64 fallbacks in FP32 Newton */
+  long long far_deposits;    /* cumulative deposits outside the tile window */
+  long long newton_failed;   /* cumulative position updates that missed the tolerance */
+} cpic_diag;
+
+/* Create a simulation on the current HIP device.  hip_stream may be NULL
+   (default stream).  alloc may be NULL (hipMalloc / hipFree).  Rejects maps
+   whose Jacobian is not positive on the domain (CPIC_E_MAP) and walls on
+   non-orthogonal maps (CPIC_E_UNSUPPORTED). */
+cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_desc* grid,
+                        const cpic_allocator* alloc, void* hip_stream, cpic_sim** out);
+
+/* Add a species (charge q, mass m, macro-weight w; Eq. f); returns its id. */
+cpic_status cpic_add_species(cpic_sim* sim, const cpic_species_desc* desc, int* species_id);
+
+/* Copy n particles in (host pointers, or device pointers when on_device != 0).
+   cell: int32 [n]; off: [dim][n]; vel: [3][n] (float for CPIC_FP32, double for
+   CPIC_FP64); ids: uint32 [n] or NULL (ids 0..n-1).  n <= capacity. */
+cpic_status cpic_set_particles(cpic_sim* sim, int species_id, size_t n, const int32_t* cell,
+                               const void* off, const void* vel, const uint32_t* ids,
+                               int on_device);
+
+/* Copy particles out (synchronises).  Arrays as in cpic_set_particles with
+   room for cap particles; *n receives the live count.  Order is the library's
+   (tile-sorted); ids identify particles when track_ids is set. */
+cpic_status cpic_get_particles(cpic_sim* sim, int species_id, size_t cap, int32_t* cell,
+                               void* off, void* vel, uint32_t* ids, size_t* n, int on_device);
+
+/* Initial state: sort, deposit, solve, field, and the half-step velocity
+   push-back v^{-1/2} = Boris(v^0, E^0, B, -dt/2). */
+cpic_status cpic_initialize(cpic_sim* sim);
+
+/* Advance nsteps full PIC cycles (asynchronous). */
+cpic_status cpic_step(cpic_sim* sim, int nsteps);
+
+/* Run one stage (asynchronous); see CPIC_STAGE_*. */
+cpic_status cpic_run_stage(cpic_sim* sim, int stage);
+
+/* Field copies (synchronise).  species_id is used by CPIC_FIELD_Q only.
+   bytes must equal the field's size. */
+cpic_status cpic_get_field(cpic_sim* sim, int which, int species_id, void* dst, size_t bytes,
+                           int on_device);
+cpic_status cpic_set_field(cpic_sim* sim, int which, int species_id, const void* src,
+                           size_t bytes, int on_device);
+
+/* Size in bytes of a field (for get/set). */
+size_t cpic_field_bytes(const cpic_sim* sim, int which);
+
+/* Diagnostics (synchronises). */
+cpic_status cpic_get_diag(cpic_sim* sim, cpic_diag* out);
+
+/* Wait for all work on the simulation's stream. */
+cpic_status cpic_sync(cpic_sim* sim);
+
+/* Per-step durations (ms) of the last cpic_step call, measured with HIP
+   events on the simulation's stream once enabled by cpic_set_timing(sim, 1):
+   particle kernels, field phase (charge, solve, vertex field), tile sort,
+   whole step.  Writes at most cap samples per array (any array may be NULL);
+   *samples receives the number of steps recorded.  Synchronises. */
+cpic_status cpic_set_timing(cpic_sim* sim, int enable);
+cpic_status cpic_get_timing(cpic_sim* sim, int cap, double* push_ms, double* solve_ms,
+                            double* sort_ms, double* step_ms, int* samples);
+
+const char* cpic_status_str(cpic_status s);
+const char* cpic_last_error(const cpic_sim* sim);
+void cpic_destroy(cpic_sim* sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPIC_H_ */

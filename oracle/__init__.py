@@ -101,6 +101,7 @@ def lib():
         L.or_boris.argtypes = [lg, P(d), P(d), P(d), d, d]
         L.or_push.argtypes = [P(Map), P(Grid), d, d, P(d), lg, P(i32), P(d), P(d), P(d), P(lg)]
         L.or_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
+        L.or_num_threads.restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
 
@@ -292,6 +293,10 @@ def push(m: Map, g: Grid, qm, dt, B, cell, off, vel, Ev):
     return cell, off, vel, (counts[0], counts[1])
 
 
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
 def philox4x32_10(ctr, key):
     c = np.ascontiguousarray(ctr, dtype=np.uint32)
     k = np.ascontiguousarray(key, dtype=np.uint32)
@@ -331,7 +336,7 @@ class OracleSim:
     vel (n,3) in FP64.  deposit: 'fixed' (integer weights) or 'f64'."""
 
     def __init__(self, m: Map, g: Grid, species, shape=B2, dt=0.1, B=(0.0, 0.0, 0.0),
-                 background=None, deposit="fixed", rtol=1e-13):
+                 background=None, deposit="fixed", rtol=1e-13, ke_axes=3):
         self.m, self.g, self.sp = m, g, species
         self.shape, self.dt, self.B = shape, dt, np.asarray(B, dtype=np.float64)
         self.bg = background
@@ -341,6 +346,7 @@ class OracleSim:
         self.phi = np.zeros(ncells(g))
         self.step_count = 0
         self.ke = None
+        self.ke_axes = ke_axes  # velocity components in the kinetic-energy sum
 
     def deposit(self):
         if self.mode == "fixed":
@@ -371,7 +377,8 @@ class OracleSim:
             s["cell"], s["off"], s["vel"], cnt = push(self.m, self.g, s["q"] / s["m"], self.dt,
                                                       self.B, s["cell"], s["off"], s["vel"], self.Ev)
             alive = s["cell"] >= 0
-            ke += 0.5 * s["m"] * s["w"] * float(np.sum(v_old[alive] * s["vel"][alive]))
+            k = self.ke_axes
+            ke += 0.5 * s["m"] * s["w"] * float(np.sum(v_old[alive, :k] * s["vel"][alive, :k]))
             self.counts.append(cnt)
         self.ke = ke
         self.deposit()

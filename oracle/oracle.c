@@ -1030,3 +1030,12 @@ void or_philox4x32_10(const uint32_t* ctr_in, const uint32_t* key_in, uint32_t* 
   out[2] = c[2];
   out[3] = c[3];
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

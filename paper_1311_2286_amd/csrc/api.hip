@@ -1,0 +1,826 @@
+// api.hip -- host core and C ABI of the MI355X curvilinear PIC library.
+//
+// Owns device memory (through the caller's allocator), validates descriptors,
+// and orders the kernel launches of the PIC cycle on one HIP stream:
+//   per step:  [species] zero Q_s, particle kernel (gather, push, Newton map
+//              inversion, boundaries, deposit) -> charge -> rhs -> multigrid ->
+//              gauge -> vertex field -> (every sort_every steps) tile sort.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/cpic.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace cpic;
+
+namespace {
+
+constexpr int MAX_SPECIES = 8;
+
+struct Species {
+  cpic_species_desc desc;
+  size_t cap = 0;
+  int cur = 0;
+  int32_t* key[2] = {nullptr, nullptr};
+  void* off[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  void* vel[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  uint32_t* id[2] = {nullptr, nullptr};
+  int* d_n = nullptr;
+  void* Q = nullptr;
+  int* counts = nullptr;
+  int* start = nullptr;
+  int* cursor = nullptr;
+  int* n_items = nullptr;
+  int* item_tile = nullptr;
+  int* item_begin = nullptr;
+  int* item_end = nullptr;
+  int max_items = 0;
+  unsigned long long* counters = nullptr;  // absorbed, outflow, fallback, far, nonconv
+};
+
+struct StepEvents {
+  hipEvent_t e[5];  // start, before particle kernels, after them, after field, after sort
+};
+
+}  // namespace
+
+struct cpic_sim {
+  cpic_map_desc map;
+  cpic_grid_desc grid;
+  cpic_allocator alloc;
+  bool has_alloc = false;
+  hipStream_t stream = nullptr;
+  Geo g;
+  GridCtx G;
+  std::vector<Species> sp;
+  int S1 = 24;
+  int chunk = 4096;
+  bool initialized = false;
+  bool poisoned = false;
+  bool sorted_dirty = true;
+  long long step = 0;
+  double* ke = nullptr;  // device: kinetic energy of the last push
+  int* flags = nullptr;  // device ints: [0] bad input count
+  uint64_t* qsum = nullptr;
+  double* tmp_scalar = nullptr;
+  std::string err;
+  std::vector<std::pair<void*, size_t>> allocs;
+  bool timing = false;
+  std::vector<StepEvents> evs;
+  size_t ev_used = 0;
+};
+
+// ----------------------------------------------------------------------------
+static cpic_status fail(cpic_sim* s, cpic_status st, const std::string& msg) {
+  if (s) s->err = msg;
+  return st;
+}
+
+#define HIPCHK(sim, expr)                                                           \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      (sim)->poisoned = true;                                                       \
+      return fail((sim), CPIC_E_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    }                                                                               \
+  } while (0)
+
+static void* sim_alloc(cpic_sim* s, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  bytes = (bytes + 255) & ~(size_t)255;
+  void* p = nullptr;
+  if (s->has_alloc) {
+    p = s->alloc.alloc(bytes, s->alloc.ctx);
+  } else {
+    if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+  }
+  if (p) s->allocs.push_back({p, bytes});
+  return p;
+}
+
+static void sim_free_all(cpic_sim* s) {
+  for (auto& a : s->allocs) {
+    if (s->has_alloc)
+      s->alloc.free(a.first, s->alloc.ctx);
+    else
+      (void)hipFree(a.first);
+  }
+  s->allocs.clear();
+}
+
+static int bits_for(int n) {
+  int b = 0;
+  while ((1 << b) < n) ++b;
+  return b < 1 ? 1 : b;
+}
+
+static size_t real_size(const cpic_sim* s) { return s->grid.precision == CPIC_FP64 ? 8 : 4; }
+static int ecomp(const cpic_sim* s) { return s->map.dim == 3 ? 4 : 2; }
+
+static cpic_status check_async(cpic_sim* s) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    s->poisoned = true;
+    return fail(s, CPIC_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  }
+  return CPIC_OK;
+}
+
+// ----------------------------------------------------------------------------
+// creation
+// ----------------------------------------------------------------------------
+extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_desc* grid,
+                                   const cpic_allocator* alloc, void* hip_stream, cpic_sim** out) {
+  if (!map || !grid || !out) return CPIC_E_ARG;
+  *out = nullptr;
+  const int d = map->dim;
+  if (d != 2 && d != 3) return CPIC_E_ARG;
+  if (map->kind < CPIC_MAP_IDENTITY || map->kind > CPIC_MAP_POLAR_LOG) return CPIC_E_ARG;
+  if (map->kind == CPIC_MAP_POLAR_LOG && (d != 2 || !(map->r_in > 0) || !(map->r_out > map->r_in)))
+    return CPIC_E_ARG;
+  if (map->kind != CPIC_MAP_POLAR_LOG)
+    for (int a = 0; a < d; ++a)
+      if (!(map->L[a] > 0)) return CPIC_E_ARG;
+  if (map->kind == CPIC_MAP_SINUSOIDAL) {
+    // J = 1 + 2 pi eps (sum of products); its bracket is bounded by 1 (2D) and
+    // 2/sqrt(3) (3D): the map folds beyond eps = 1/(2 pi) resp. sqrt(3)/(4 pi)
+    double bound = (d == 2) ? 1.0 : 2.0 / sqrt(3.0);
+    if (!(2.0 * M_PI * fabs(map->eps) * bound < 1.0)) return CPIC_E_MAP;
+  }
+  long long ncells = 1;
+  int bitsum = 0;
+  for (int a = 0; a < d; ++a) {
+    if (grid->n[a] < 2 || grid->n[a] > (1 << 14)) return CPIC_E_ARG;
+    ncells *= grid->n[a];
+    bitsum += bits_for(grid->n[a]);
+    bool plo = grid->bc_lo[a] == CPIC_BC_PERIODIC, phi = grid->bc_hi[a] == CPIC_BC_PERIODIC;
+    if (plo != phi) return CPIC_E_ARG;
+    if (grid->bc_lo[a] < 0 || grid->bc_lo[a] > 2 || grid->bc_hi[a] < 0 || grid->bc_hi[a] > 2) return CPIC_E_ARG;
+  }
+  if (bitsum > 30 || ncells > (1ll << 30)) return CPIC_E_ARG;
+  bool all_periodic = true;
+  for (int a = 0; a < d; ++a) all_periodic = all_periodic && grid->bc_lo[a] == CPIC_BC_PERIODIC;
+  if (!all_periodic && map->kind == CPIC_MAP_SINUSOIDAL && map->eps != 0.0) return CPIC_E_UNSUPPORTED;
+  if (grid->shape != CPIC_SHAPE_B1 && grid->shape != CPIC_SHAPE_B2) return CPIC_E_ARG;
+  if (grid->precision != CPIC_FP32 && grid->precision != CPIC_FP64) return CPIC_E_ARG;
+  if (!(grid->dt > 0) || !isfinite(grid->dt)) return CPIC_E_ARG;
+  if (grid->background && (d != 2 || !all_periodic)) return CPIC_E_UNSUPPORTED;
+
+  cpic_sim* s = new cpic_sim();
+  s->map = *map;
+  s->grid = *grid;
+  if (s->grid.mg_rtol <= 0) s->grid.mg_rtol = 1e-10;
+  if (s->grid.mg_max_cycles <= 0) s->grid.mg_max_cycles = 20;
+  if (s->grid.sort_every <= 0) s->grid.sort_every = 1;
+  if (alloc && alloc->alloc && alloc->free) {
+    s->alloc = *alloc;
+    s->has_alloc = true;
+  }
+  s->stream = (hipStream_t)hip_stream;
+  s->S1 = (d == 2) ? 24 : 16;
+  s->chunk = (d == 2) ? 4096 : 16384;
+
+  Geo& g = s->g;
+  memset(&g, 0, sizeof(g));
+  g.dim = d;
+  g.kind = map->kind;
+  g.ncells = ncells;
+  g.nverts = 1;
+  g.ntiles = 1;
+  const int T[3] = {d == 2 ? TileShape<2>::T0 : TileShape<3>::T0, d == 2 ? TileShape<2>::T1 : TileShape<3>::T1,
+                    d == 2 ? 1 : TileShape<3>::T2};
+  for (int a = 0; a < 3; ++a) {
+    if (a < d) {
+      g.n[a] = grid->n[a];
+      g.periodic[a] = grid->bc_lo[a] == CPIC_BC_PERIODIC;
+      g.nv[a] = g.periodic[a] ? g.n[a] : g.n[a] + 1;
+      g.nt[a] = (g.n[a] + T[a] - 1) / T[a];
+      g.invn[a] = 1.0 / g.n[a];
+      g.L[a] = map->L[a];
+    } else {
+      g.n[a] = 1;
+      g.nv[a] = 1;
+      g.nt[a] = 1;
+      g.periodic[a] = 1;
+      g.invn[a] = 1.0;
+      g.L[a] = 1.0;
+    }
+    g.nverts *= g.nv[a];
+    g.ntiles *= g.nt[a];
+  }
+  g.sx = bits_for(g.n[0]);
+  g.sy = bits_for(g.n[1]);
+  g.eps = map->kind == CPIC_MAP_SINUSOIDAL ? map->eps : 0.0;
+  g.r_in = map->r_in;
+  g.r_out = map->r_out;
+  g.lnR = map->kind == CPIC_MAP_POLAR_LOG ? log(map->r_out / map->r_in) : 0.0;
+  for (int a = 0; a < 3; ++a) {
+    g.ecell[a] = g.eps * g.n[a];
+    g.dxc[a] = g.L[a] / g.n[a];
+  }
+
+  // grid context and multigrid hierarchy
+  GridCtx& G = s->G;
+  memset(&G, 0, sizeof(G));
+  G.g = g;
+  G.fp64 = grid->precision == CPIC_FP64;
+  G.all_periodic = all_periodic;
+  G.mixed = map->kind == CPIC_MAP_SINUSOIDAL && map->eps != 0.0;
+  for (int a = 0; a < 3; ++a) {
+    G.bc_lo[a] = a < d ? grid->bc_lo[a] : CPIC_BC_PERIODIC;
+    G.bc_hi[a] = a < d ? grid->bc_hi[a] : CPIC_BC_PERIODIC;
+    G.phi_lo[a] = a < d ? grid->phi_lo[a] : 0.0;
+    G.phi_hi[a] = a < d ? grid->phi_hi[a] : 0.0;
+  }
+  int nl = 0;
+  int n[3] = {g.n[0], g.n[1], g.n[2]};
+  while (nl < 16) {
+    Level& L = G.lev[nl];
+    L.ncells = 1;
+    L.dV = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      L.n[a] = n[a];
+      L.h[a] = a < d ? 1.0 / n[a] : 1.0;
+      L.ncells *= n[a];
+      L.dV *= L.h[a];
+    }
+    ++nl;
+    bool can = true;
+    for (int a = 0; a < d; ++a) can = can && (n[a] % 2 == 0) && (n[a] / 2 >= 2);
+    if (!can) break;
+    for (int a = 0; a < d; ++a) n[a] /= 2;
+  }
+  G.nlev = nl;
+  bool ok = true;
+  auto A = [&](size_t bytes) {
+    void* p = sim_alloc(s, bytes);
+    if (!p) ok = false;
+    return p;
+  };
+  const int np = d == 3 ? 3 : 1;
+  for (int l = 0; l < nl; ++l) {
+    Level& L = G.lev[l];
+    size_t b = sizeof(double) * (size_t)L.ncells;
+    for (int a = 0; a < 3; ++a) {
+      L.wf[a] = a < d ? (double*)A(b) : nullptr;
+      L.wlo[a] = a < d ? (double*)A(b) : nullptr;
+      L.we[a] = a < np ? (double*)A(b) : nullptr;
+    }
+    L.diag = (double*)A(b);
+    L.phi = (double*)A(b);
+    L.phi2 = (double*)A(b);
+    L.rhs = (double*)A(b);
+    L.res = nullptr;
+  }
+  size_t cb = sizeof(double) * (size_t)ncells;
+  G.bdir = (double*)A(cb);
+  G.Jc = (double*)A(cb);
+  G.charge = (double*)A(cb);
+  G.background = grid->background ? (double*)A(cb) : nullptr;
+  G.partials = (double*)A(sizeof(double) * 1024);
+  G.scalars = (double*)A(sizeof(double) * 16);
+  G.mg_flag = (int*)A(sizeof(int) * 4);
+  G.Ev = A(real_size(s) * ecomp(s) * (size_t)g.nverts);
+  s->ke = (double*)A(sizeof(double) * 2);
+  s->flags = (int*)A(sizeof(int) * 8);
+  s->qsum = (uint64_t*)A(sizeof(uint64_t) * (2 + 2 * 256));
+  s->tmp_scalar = (double*)A(sizeof(double) * 4);
+  if (!ok) {
+    sim_free_all(s);
+    delete s;
+    return CPIC_E_NOMEM;
+  }
+  hipStream_t st = s->stream;
+  for (int l = 0; l < nl; ++l) {
+    Level& L = G.lev[l];
+    size_t b = sizeof(double) * (size_t)L.ncells;
+    launch_fill_u8(L.phi, 0, b, st);
+    launch_fill_u8(L.phi2, 0, b, st);
+    launch_fill_u8(L.rhs, 0, b, st);
+    launch_coefficients(G, l, st);
+  }
+  launch_fill_u8(G.charge, 0, cb, st);
+  launch_fill_u8(G.Ev, 0, real_size(s) * ecomp(s) * (size_t)g.nverts, st);
+  launch_fill_u8(s->ke, 0, sizeof(double) * 2, st);
+  launch_fill_u8(G.mg_flag, 0, sizeof(int) * 4, st);
+  launch_jacobian_centres(G, st);
+  if (G.background) launch_background(G, grid->shape, grid->background_n0, st);
+  cpic_status rc = check_async(s);
+  if (rc != CPIC_OK) {
+    cpic_destroy(s);
+    return rc;
+  }
+  // sum_c J_c via a one-off host reduction of the (small) J array
+  std::vector<double> Jh((size_t)ncells);
+  if (hipMemcpyAsync(Jh.data(), G.Jc, cb, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    cpic_destroy(s);
+    return CPIC_E_HIP;
+  }
+  double sj = 0.0;
+  double jmin = 1e300;
+  for (double v : Jh) {
+    sj += v;
+    jmin = std::min(jmin, v);
+  }
+  G.sumJ = sj;
+  if (!(jmin > 0)) {
+    cpic_destroy(s);
+    return CPIC_E_MAP;
+  }
+  *out = s;
+  return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* desc, int* sid) {
+  if (!s || !desc || !sid) return CPIC_E_ARG;
+  if (s->poisoned) return fail(s, CPIC_E_STATE, "simulation poisoned by an earlier device error");
+  if ((int)s->sp.size() >= MAX_SPECIES) return fail(s, CPIC_E_ARG, "too many species");
+  if (s->initialized) return fail(s, CPIC_E_STATE, "species must be added before cpic_initialize");
+  if (!(desc->m != 0) || !(desc->w > 0) || !isfinite(desc->q) || desc->capacity == 0 ||
+      desc->capacity > (size_t)INT32_MAX / 2)
+    return fail(s, CPIC_E_ARG, "bad species descriptor");
+  const int d = s->g.dim;
+  for (int a = 0; a < d; ++a) {
+    bool per = s->g.periodic[a];
+    for (int side = 0; side < 2; ++side) {
+      int b = side ? desc->pbc_hi[a] : desc->pbc_lo[a];
+      if (per && b != CPIC_PBC_PERIODIC) return fail(s, CPIC_E_ARG, "particle bc must be periodic on a periodic axis");
+      if (!per && b != CPIC_PBC_ABSORB && b != CPIC_PBC_OUTFLOW)
+        return fail(s, CPIC_E_ARG, "particle bc must absorb or outflow on a bounded axis");
+    }
+  }
+  Species S;
+  S.desc = *desc;
+  S.cap = desc->capacity;
+  bool ok = true;
+  auto A = [&](size_t bytes) {
+    void* p = sim_alloc(s, bytes);
+    if (!p) ok = false;
+    return p;
+  };
+  const size_t rs = real_size(s);
+  for (int b = 0; b < 2; ++b) {
+    S.key[b] = (int32_t*)A(sizeof(int32_t) * S.cap);
+    for (int a = 0; a < 3; ++a) {
+      S.off[b][a] = a < d ? A(rs * S.cap) : nullptr;
+      S.vel[b][a] = A(rs * S.cap);
+    }
+    S.id[b] = s->grid.track_ids ? (uint32_t*)A(sizeof(uint32_t) * S.cap) : nullptr;
+  }
+  S.d_n = (int*)A(sizeof(int) * 2);
+  S.Q = A(8 * (size_t)s->g.ncells);
+  const int nt = s->g.ntiles;
+  S.counts = (int*)A(sizeof(int) * (nt + 2));
+  S.start = (int*)A(sizeof(int) * (nt + 2));
+  S.cursor = (int*)A(sizeof(int) * (nt + 2));
+  S.n_items = (int*)A(sizeof(int) * 2);
+  S.max_items = (int)((S.cap + s->chunk - 1) / s->chunk) + nt;
+  S.item_tile = (int*)A(sizeof(int) * S.max_items);
+  S.item_begin = (int*)A(sizeof(int) * S.max_items);
+  S.item_end = (int*)A(sizeof(int) * S.max_items);
+  S.counters = (unsigned long long*)A(sizeof(unsigned long long) * 8);
+  if (!ok) return fail(s, CPIC_E_NOMEM, "species allocation failed");
+  hipStream_t st = s->stream;
+  launch_fill_u8(S.d_n, 0, sizeof(int) * 2, st);
+  launch_fill_u8(S.n_items, 0, sizeof(int) * 2, st);
+  launch_fill_u8(S.counters, 0, sizeof(unsigned long long) * 8, st);
+  launch_fill_u8(S.Q, 0, 8 * (size_t)s->g.ncells, st);
+  s->sp.push_back(S);
+  *sid = (int)s->sp.size() - 1;
+  s->sorted_dirty = true;
+  return check_async(s);
+}
+
+// ----------------------------------------------------------------------------
+// particles in / out
+// ----------------------------------------------------------------------------
+extern "C" cpic_status cpic_set_particles(cpic_sim* s, int sid, size_t n, const int32_t* cell,
+                                          const void* off, const void* vel, const uint32_t* ids,
+                                          int on_device) {
+  if (!s) return CPIC_E_ARG;
+  if (s->poisoned) return fail(s, CPIC_E_STATE, "simulation poisoned by an earlier device error");
+  if (sid < 0 || sid >= (int)s->sp.size()) return fail(s, CPIC_E_ARG, "bad species id");
+  Species& S = s->sp[sid];
+  if (n > S.cap) return fail(s, CPIC_E_BUDGET, "particle count exceeds species capacity");
+  if (n > 0 && (!cell || !off || !vel)) return fail(s, CPIC_E_ARG, "null particle array");
+  const int d = s->g.dim;
+  const size_t rs = real_size(s);
+  hipStream_t st = s->stream;
+  if (!on_device) {
+    // validate on the host before touching device state
+    for (size_t p = 0; p < n; ++p)
+      if (cell[p] < 0 || (long long)cell[p] >= s->g.ncells) return fail(s, CPIC_E_ARG, "cell index out of range");
+    for (int a = 0; a < d; ++a)
+      for (size_t p = 0; p < n; ++p) {
+        double v = rs == 8 ? ((const double*)off)[a * n + p] : ((const float*)off)[a * n + p];
+        if (!(v >= 0.0 && v < 1.0)) return fail(s, CPIC_E_ARG, "offset outside [0, 1)");
+      }
+  }
+  const int buf = S.cur;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  int32_t* lin_tmp = S.key[1 - buf];
+  if (n > 0) {
+    HIPCHK(s, hipMemcpyAsync(lin_tmp, cell, sizeof(int32_t) * n, kind, st));
+    for (int a = 0; a < d; ++a)
+      HIPCHK(s, hipMemcpyAsync(S.off[buf][a], (const char*)off + rs * n * a, rs * n, kind, st));
+    for (int a = 0; a < 3; ++a)
+      HIPCHK(s, hipMemcpyAsync(S.vel[buf][a], (const char*)vel + rs * n * a, rs * n, kind, st));
+  }
+  if (S.id[buf]) {
+    if (ids && n > 0)
+      HIPCHK(s, hipMemcpyAsync(S.id[buf], ids, sizeof(uint32_t) * n, kind, st));
+    else
+      launch_iota(S.id[buf], (int)n, st);
+  }
+  launch_fill_u8(s->flags, 0, sizeof(int) * 8, st);
+  launch_lin_to_key(lin_tmp, S.key[buf], (int)n, s->g, s->flags, st);
+  if (on_device)
+    for (int a = 0; a < d; ++a) launch_offsets_check(S.off[buf][a], (long long)n, rs == 8, s->flags + 1, st);
+  int nn = (int)n;
+  HIPCHK(s, hipMemcpyAsync(S.d_n, &nn, sizeof(int), hipMemcpyHostToDevice, st));
+  int bad[2] = {0, 0};
+  HIPCHK(s, hipMemcpyAsync(bad, s->flags, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  if (bad[0] || bad[1]) {
+    int zero = 0;
+    HIPCHK(s, hipMemcpy(S.d_n, &zero, sizeof(int), hipMemcpyHostToDevice));
+    return fail(s, CPIC_E_ARG, "device particle input has cells or offsets out of range");
+  }
+  s->sorted_dirty = true;
+  return check_async(s);
+}
+
+extern "C" cpic_status cpic_get_particles(cpic_sim* s, int sid, size_t cap, int32_t* cell, void* off,
+                                          void* vel, uint32_t* ids, size_t* n_out, int on_device) {
+  if (!s || !n_out) return CPIC_E_ARG;
+  if (sid < 0 || sid >= (int)s->sp.size()) return fail(s, CPIC_E_ARG, "bad species id");
+  Species& S = s->sp[sid];
+  hipStream_t st = s->stream;
+  int n = 0;
+  HIPCHK(s, hipMemcpyAsync(&n, S.d_n, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  *n_out = (size_t)n;
+  if ((size_t)n > cap) return fail(s, CPIC_E_BUDGET, "output capacity too small");
+  const int d = s->g.dim;
+  const size_t rs = real_size(s);
+  const int buf = S.cur;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (n > 0) {
+    int32_t* lin_tmp = S.key[1 - buf];
+    launch_key_to_lin(S.key[buf], lin_tmp, n, s->g, st);
+    if (cell) HIPCHK(s, hipMemcpyAsync(cell, lin_tmp, sizeof(int32_t) * n, kind, st));
+    if (off)
+      for (int a = 0; a < d; ++a)
+        HIPCHK(s, hipMemcpyAsync((char*)off + rs * n * a, S.off[buf][a], rs * n, kind, st));
+    if (vel)
+      for (int a = 0; a < 3; ++a)
+        HIPCHK(s, hipMemcpyAsync((char*)vel + rs * n * a, S.vel[buf][a], rs * n, kind, st));
+    if (ids && S.id[buf]) HIPCHK(s, hipMemcpyAsync(ids, S.id[buf], sizeof(uint32_t) * n, kind, st));
+  }
+  HIPCHK(s, hipStreamSynchronize(st));
+  return check_async(s);
+}
+
+// ----------------------------------------------------------------------------
+// stages
+// ----------------------------------------------------------------------------
+static void sort_species(cpic_sim* s, Species& S) {
+  SortLaunch L;
+  memset(&L, 0, sizeof(L));
+  L.g = s->g;
+  L.fp64 = s->grid.precision == CPIC_FP64;
+  L.capacity = (long long)S.cap;
+  L.chunk = s->chunk;
+  const int a = S.cur, b = 1 - S.cur;
+  L.key_in = S.key[a];
+  L.key_out = S.key[b];
+  for (int i = 0; i < 3; ++i) {
+    L.off_in[i] = S.off[a][i];
+    L.off_out[i] = S.off[b][i];
+    L.vel_in[i] = S.vel[a][i];
+    L.vel_out[i] = S.vel[b][i];
+  }
+  L.id_in = S.id[a];
+  L.id_out = S.id[b];
+  L.d_n = S.d_n;
+  L.counts = S.counts;
+  L.start = S.start;
+  L.cursor = S.cursor;
+  L.n_items = S.n_items;
+  L.item_tile = S.item_tile;
+  L.item_begin = S.item_begin;
+  L.item_end = S.item_end;
+  launch_fill_u8(S.counts, 0, sizeof(int) * (s->g.ntiles + 2), s->stream);
+  launch_tile_sort(L, s->stream);
+  S.cur = b;
+}
+
+static void sort_all(cpic_sim* s) {
+  for (auto& S : s->sp) sort_species(s, S);
+  s->sorted_dirty = false;
+}
+
+static void zero_deposits(cpic_sim* s, int mode) {
+  if (mode == MODE_PUSH) launch_fill_u8(s->ke, 0, sizeof(double), s->stream);
+  if (mode == MODE_HALFSTEP) return;
+  for (auto& S : s->sp) launch_fill_u8(S.Q, 0, 8 * (size_t)s->g.ncells, s->stream);
+}
+
+// particle kernels of all species (deposit arrays must have been zeroed)
+static void particles_pass(cpic_sim* s, int mode) {
+  const bool halfstep = mode == MODE_HALFSTEP;
+  for (auto& S : s->sp) {
+    ParticleLaunch L;
+    memset(&L, 0, sizeof(L));
+    L.g = s->g;
+    L.fp64 = s->grid.precision == CPIC_FP64;
+    L.shape = s->grid.shape;
+    L.mode = mode;
+    const int b = S.cur;
+    L.key = S.key[b];
+    for (int a = 0; a < 3; ++a) {
+      L.off[a] = S.off[b][a];
+      L.vel[a] = S.vel[b][a];
+      L.pbc_lo[a] = S.desc.pbc_lo[a];
+      L.pbc_hi[a] = S.desc.pbc_hi[a];
+      L.B[a] = s->grid.B0[a];
+    }
+    L.item_tile = S.item_tile;
+    L.item_begin = S.item_begin;
+    L.item_end = S.item_end;
+    L.n_items = S.n_items;
+    L.max_items = S.max_items;
+    L.Ev = s->G.Ev;
+    L.Q = S.Q;
+    L.qm = S.desc.q / S.desc.m;
+    L.dt = halfstep ? -0.5 * s->grid.dt : s->grid.dt;
+    L.magnetic = (s->grid.B0[0] != 0 || s->grid.B0[1] != 0 || s->grid.B0[2] != 0);
+    L.vz_active = (s->g.dim == 3) || L.magnetic;
+    L.S1 = s->S1;
+    L.newton_maxit = 8;
+    L.newton_tol = L.fp64 ? 1e-12 : 1e-5;
+    L.ke_scale = 0.5 * S.desc.m * S.desc.w;
+    L.ke = s->ke;
+    L.counters = S.counters;
+    launch_particles(L, s->stream);
+  }
+}
+
+static void charge_pass(cpic_sim* s) {
+  ChargeSpecies cs;
+  memset(&cs, 0, sizeof(cs));
+  cs.n = (int)s->sp.size();
+  cs.fixed = s->grid.precision == CPIC_FP32;
+  const double scale = cs.fixed ? ldexp(1.0, -s->g.dim * s->S1) : 1.0;
+  for (int k = 0; k < cs.n; ++k) {
+    cs.Q[k] = s->sp[k].Q;
+    cs.qw[k] = s->sp[k].desc.q * s->sp[k].desc.w * scale;
+  }
+  launch_charge(s->G, cs, 1.0, s->stream);
+}
+
+static void solve_pass(cpic_sim* s) {
+  launch_rhs(s->G, s->stream);
+  launch_mg_solve(s->G, s->grid.mg_rtol, s->grid.mg_max_cycles, 2, 2, s->stream);
+  launch_gauge(s->G, s->stream);
+}
+
+static void ensure_sorted(cpic_sim* s) {
+  if (s->sorted_dirty) sort_all(s);
+}
+
+extern "C" cpic_status cpic_run_stage(cpic_sim* s, int stage) {
+  if (!s) return CPIC_E_ARG;
+  if (s->poisoned) return fail(s, CPIC_E_STATE, "simulation poisoned by an earlier device error");
+  switch (stage) {
+    case CPIC_STAGE_SORT: sort_all(s); break;
+    case CPIC_STAGE_DEPOSIT: ensure_sorted(s); zero_deposits(s, MODE_DEPOSIT); particles_pass(s, MODE_DEPOSIT); break;
+    case CPIC_STAGE_CHARGE: charge_pass(s); break;
+    case CPIC_STAGE_SOLVE: solve_pass(s); break;
+    case CPIC_STAGE_EFIELD: launch_efield(s->G, s->stream); break;
+    case CPIC_STAGE_PUSH: ensure_sorted(s); zero_deposits(s, MODE_PUSH); particles_pass(s, MODE_PUSH); break;
+    case CPIC_STAGE_HALFSTEP: ensure_sorted(s); particles_pass(s, MODE_HALFSTEP); break;
+    default: return fail(s, CPIC_E_ARG, "unknown stage");
+  }
+  return check_async(s);
+}
+
+extern "C" cpic_status cpic_initialize(cpic_sim* s) {
+  if (!s) return CPIC_E_ARG;
+  if (s->poisoned) return fail(s, CPIC_E_STATE, "simulation poisoned by an earlier device error");
+  if (s->sp.empty()) return fail(s, CPIC_E_STATE, "no species");
+  sort_all(s);
+  zero_deposits(s, MODE_DEPOSIT);
+  particles_pass(s, MODE_DEPOSIT);
+  charge_pass(s);
+  solve_pass(s);
+  launch_efield(s->G, s->stream);
+  particles_pass(s, MODE_HALFSTEP);
+  s->initialized = true;
+  s->step = 0;
+  return check_async(s);
+}
+
+static StepEvents* next_events(cpic_sim* s) {
+  if (s->ev_used >= s->evs.size()) {
+    StepEvents e;
+    for (int i = 0; i < 5; ++i)
+      if (hipEventCreate(&e.e[i]) != hipSuccess) return nullptr;
+    s->evs.push_back(e);
+  }
+  return &s->evs[s->ev_used++];
+}
+
+extern "C" cpic_status cpic_step(cpic_sim* s, int nsteps) {
+  if (!s || nsteps < 0) return CPIC_E_ARG;
+  if (s->poisoned) return fail(s, CPIC_E_STATE, "simulation poisoned by an earlier device error");
+  if (!s->initialized) return fail(s, CPIC_E_STATE, "cpic_initialize has not been called");
+  if (s->timing) s->ev_used = 0;
+  for (int k = 0; k < nsteps; ++k) {
+    ensure_sorted(s);
+    StepEvents* ev = s->timing ? next_events(s) : nullptr;
+    if (ev) hipEventRecord(ev->e[0], s->stream);
+    zero_deposits(s, MODE_PUSH);
+    if (ev) hipEventRecord(ev->e[1], s->stream);
+    particles_pass(s, MODE_PUSH);
+    if (ev) hipEventRecord(ev->e[2], s->stream);
+    charge_pass(s);
+    solve_pass(s);
+    launch_efield(s->G, s->stream);
+    if (ev) hipEventRecord(ev->e[3], s->stream);
+    ++s->step;
+    if (s->step % s->grid.sort_every == 0) sort_all(s);
+    if (ev) hipEventRecord(ev->e[4], s->stream);
+  }
+  return check_async(s);
+}
+
+// ----------------------------------------------------------------------------
+// fields and diagnostics
+// ----------------------------------------------------------------------------
+extern "C" size_t cpic_field_bytes(const cpic_sim* s, int which) {
+  if (!s) return 0;
+  const size_t nc = (size_t)s->g.ncells;
+  switch (which) {
+    case CPIC_FIELD_Q: return 8 * nc;
+    case CPIC_FIELD_CHARGE:
+    case CPIC_FIELD_PHI:
+    case CPIC_FIELD_JC:
+    case CPIC_FIELD_RHO: return 8 * nc;
+    case CPIC_FIELD_BACKGROUND: return s->G.background ? 8 * nc : 0;
+    case CPIC_FIELD_EV: return real_size(s) * ecomp(s) * (size_t)s->g.nverts;
+    default: return 0;
+  }
+}
+
+static void* field_ptr(cpic_sim* s, int which, int sid) {
+  switch (which) {
+    case CPIC_FIELD_Q: return (sid >= 0 && sid < (int)s->sp.size()) ? s->sp[sid].Q : nullptr;
+    case CPIC_FIELD_CHARGE: return s->G.charge;
+    case CPIC_FIELD_PHI: return s->G.lev[0].phi;
+    case CPIC_FIELD_JC: return s->G.Jc;
+    case CPIC_FIELD_RHO: return s->G.lev[0].phi2;
+    case CPIC_FIELD_BACKGROUND: return s->G.background;
+    case CPIC_FIELD_EV: return s->G.Ev;
+    default: return nullptr;
+  }
+}
+
+extern "C" cpic_status cpic_get_field(cpic_sim* s, int which, int sid, void* dst, size_t bytes, int on_device) {
+  if (!s || !dst) return CPIC_E_ARG;
+  size_t need = cpic_field_bytes(s, which);
+  void* src = field_ptr(s, which, sid);
+  if (!src || need == 0) return fail(s, CPIC_E_ARG, "unknown field / species");
+  if (bytes != need) return fail(s, CPIC_E_ARG, "field size mismatch");
+  if (which == CPIC_FIELD_RHO) launch_rho(s->G, s->G.lev[0].phi2, s->stream);
+  HIPCHK(s, hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return check_async(s);
+}
+
+extern "C" cpic_status cpic_set_field(cpic_sim* s, int which, int sid, const void* src, size_t bytes,
+                                      int on_device) {
+  if (!s || !src) return CPIC_E_ARG;
+  if (s->poisoned) return fail(s, CPIC_E_STATE, "simulation poisoned by an earlier device error");
+  if (which != CPIC_FIELD_Q && which != CPIC_FIELD_CHARGE && which != CPIC_FIELD_PHI && which != CPIC_FIELD_EV)
+    return fail(s, CPIC_E_ARG, "field is read-only");
+  size_t need = cpic_field_bytes(s, which);
+  void* dst = field_ptr(s, which, sid);
+  if (!dst || need == 0) return fail(s, CPIC_E_ARG, "unknown field / species");
+  if (bytes != need) return fail(s, CPIC_E_ARG, "field size mismatch");
+  HIPCHK(s, hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return check_async(s);
+}
+
+extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
+  if (!s || !out) return CPIC_E_ARG;
+  memset(out, 0, sizeof(*out));
+  hipStream_t st = s->stream;
+  out->step = s->step;
+  out->nspecies = (int)s->sp.size();
+  double ke = 0.0;
+  HIPCHK(s, hipMemcpyAsync(&ke, s->ke, sizeof(double), hipMemcpyDeviceToHost, st));
+  launch_field_energy(s->G, s->tmp_scalar, st);
+  double we = 0.0, sc[2] = {0, 0};
+  int fl[2] = {0, 0};
+  HIPCHK(s, hipMemcpyAsync(&we, s->tmp_scalar, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipMemcpyAsync(sc, s->G.scalars, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipMemcpyAsync(fl, s->G.mg_flag, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+  std::vector<unsigned long long> cnt(8 * s->sp.size());
+  std::vector<int> ns(s->sp.size());
+  std::vector<uint64_t> qs(2 * s->sp.size());
+  for (size_t k = 0; k < s->sp.size(); ++k) {
+    Species& S = s->sp[k];
+    HIPCHK(s, hipMemcpyAsync(&cnt[8 * k], S.counters, sizeof(unsigned long long) * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipMemcpyAsync(&ns[k], S.d_n, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (s->grid.precision == CPIC_FP32) {
+      launch_qsum((const uint64_t*)S.Q, s->g.ncells, s->qsum, st);
+      HIPCHK(s, hipMemcpyAsync(&qs[2 * k], s->qsum, sizeof(uint64_t) * 2, hipMemcpyDeviceToHost, st));
+      HIPCHK(s, hipStreamSynchronize(st));
+    }
+  }
+  HIPCHK(s, hipStreamSynchronize(st));
+  out->kinetic = ke;
+  out->field_energy = 0.5 * we;
+  out->mg_relres = sc[0] > 0 ? sqrt(sc[1] / sc[0]) : 0.0;
+  out->mg_cycles = fl[1];
+  for (size_t k = 0; k < s->sp.size() && k < 8; ++k) {
+    out->count[k] = ns[k];
+    out->absorbed[k] = (long long)cnt[8 * k + 0];
+    out->outflow[k] = (long long)cnt[8 * k + 1];
+    out->newton_fallback += (long long)cnt[8 * k + 2];
+    out->far_deposits += (long long)cnt[8 * k + 3];
+    out->newton_failed += (long long)cnt[8 * k + 4];
+    out->qsum_lo[k] = qs[2 * k];
+    out->qsum_hi[k] = qs[2 * k + 1];
+  }
+  return check_async(s);
+}
+
+extern "C" cpic_status cpic_sync(cpic_sim* s) {
+  if (!s) return CPIC_E_ARG;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return check_async(s);
+}
+
+extern "C" cpic_status cpic_set_timing(cpic_sim* s, int enable) {
+  if (!s) return CPIC_E_ARG;
+  s->timing = enable != 0;
+  s->ev_used = 0;
+  return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_get_timing(cpic_sim* s, int cap, double* push_ms, double* solve_ms,
+                                       double* sort_ms, double* step_ms, int* samples) {
+  if (!s || cap < 0) return CPIC_E_ARG;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  const size_t n = std::min(s->ev_used, (size_t)cap);
+  if (samples) *samples = (int)s->ev_used;
+  for (size_t i = 0; i < n; ++i) {
+    float t[3] = {0, 0, 0}, tot = 0;
+    for (int k = 0; k < 3; ++k)
+      HIPCHK(s, hipEventElapsedTime(&t[k], s->evs[i].e[k + 1], s->evs[i].e[k + 2]));
+    HIPCHK(s, hipEventElapsedTime(&tot, s->evs[i].e[0], s->evs[i].e[4]));
+    if (push_ms) push_ms[i] = t[0];
+    if (solve_ms) solve_ms[i] = t[1];
+    if (sort_ms) sort_ms[i] = t[2];
+    if (step_ms) step_ms[i] = tot;
+  }
+  return CPIC_OK;
+}
+
+extern "C" const char* cpic_status_str(cpic_status st) {
+  switch (st) {
+    case CPIC_OK: return "ok";
+    case CPIC_E_ARG: return "invalid argument";
+    case CPIC_E_MAP: return "map not invertible on the domain";
+    case CPIC_E_NOMEM: return "out of memory";
+    case CPIC_E_BUDGET: return "capacity exceeded";
+    case CPIC_E_HIP: return "HIP runtime error";
+    case CPIC_E_OVERFLOW: return "fixed-point headroom exceeded";
+    case CPIC_E_NONFINITE: return "non-finite value";
+    case CPIC_E_STATE: return "call out of order";
+    case CPIC_E_UNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* cpic_last_error(const cpic_sim* s) { return s ? s->err.c_str() : "no simulation"; }
+
+extern "C" void cpic_destroy(cpic_sim* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& e : s->evs)
+    for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e.e[i]);
+  sim_free_all(s);
+  delete s;
+}

@@ -1,0 +1,289 @@
+// common.hpp -- internal types and device helpers of the MI355X curvilinear
+// PIC library (not part of the public ABI; see include/cpic.h).
+//
+// Particle cells are kept internally as packed coordinates
+//     key = i | j << sx | k << (sx + sy)          (sx, sy = bit widths of n0, n1)
+// so that decoding is shifts and masks.  Negative keys mark dead particles
+// (-1: absorbed at a lower wall, -2: left through an upper wall).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cpic {
+
+enum { MAP_IDENTITY = 0, MAP_SINUSOIDAL = 1, MAP_POLAR_LOG = 2 };
+enum { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_NEUMANN = 2 };
+enum { PBC_PERIODIC = 0, PBC_ABSORB = 1, PBC_OUTFLOW = 2 };
+enum { SHAPE_B1 = 1, SHAPE_B2 = 2 };
+enum { MODE_PUSH = 0, MODE_DEPOSIT = 1, MODE_HALFSTEP = 2 };
+
+// Tile geometry of the particle kernel: 16x16 cells in 2D, 8x8x8 in 3D, with a
+// deposit window of G cells on every side held in LDS.
+template <int D> struct TileShape;
+template <> struct TileShape<2> {
+  static constexpr int T0 = 16, T1 = 16, T2 = 1, G = 2;
+  static constexpr int W0 = T0 + 2 * G, W1 = T1 + 2 * G, W2 = 1;
+  static constexpr int WIN = W0 * W1;
+};
+template <> struct TileShape<3> {
+  static constexpr int T0 = 8, T1 = 8, T2 = 8, G = 2;
+  static constexpr int W0 = T0 + 2 * G, W1 = T1 + 2 * G, W2 = T2 + 2 * G;
+  static constexpr int WIN = W0 * W1 * W2;
+};
+
+// Everything a kernel needs to know about the grid and the map (by value).
+struct Geo {
+  int dim;
+  int n[3];        // cells per axis (1 on unused axes)
+  int nv[3];       // vertices per axis (n on periodic axes, n + 1 on bounded ones)
+  int periodic[3]; // 1 if the axis is periodic
+  int sx, sy;      // packed-key shifts
+  int nt[3];       // tiles per axis
+  int ntiles;
+  long long ncells, nverts;
+  double invn[3];  // 1 / n
+  // map
+  int kind;
+  double L[3];
+  double eps;
+  double r_in, r_out, lnR;
+  double ecell[3]; // eps * n_a: map perturbation in cells of axis a
+  double dxc[3];   // L_a / n_a: undistorted cell size
+};
+
+__host__ __device__ inline int key_i(int key, const Geo& g) { return key & ((1 << g.sx) - 1); }
+__host__ __device__ inline int key_j(int key, const Geo& g) { return (key >> g.sx) & ((1 << g.sy) - 1); }
+__host__ __device__ inline int key_k(int key, const Geo& g) { return key >> (g.sx + g.sy); }
+__host__ __device__ inline int make_key(int i, int j, int k, const Geo& g) {
+  return i | (j << g.sx) | (k << (g.sx + g.sy));
+}
+
+template <int D>
+__host__ __device__ inline int tile_of_key(int key, const Geo& g) {
+  using TS = TileShape<D>;
+  int ti = key_i(key, g) / TS::T0;
+  int tj = key_j(key, g) / TS::T1;
+  int tk = (D == 3) ? key_k(key, g) / TS::T2 : 0;
+  return ti + g.nt[0] * (tj + g.nt[1] * tk);
+}
+
+// ---------------------------------------------------------------------------
+// Trigonometric helpers.  sin/cos of 2 pi u for the base position use the
+// device library's sinpi/cospi (argument reduction is exact in revolutions).
+// Increments sin(2 pi u) and cos(2 pi u) - 1 for the small Newton steps are
+// evaluated without cancellation: Taylor polynomials for |2 pi u| < 0.8 in
+// FP32 (truncation below 2e-9 there), sinpi of the half angle in FP64.
+// ---------------------------------------------------------------------------
+__device__ inline void sincos2pi(float u, float& s, float& c) { sincospif(2.0f * u, &s, &c); }
+__device__ inline void sincos2pi(double u, double& s, double& c) { sincospi(2.0 * u, &s, &c); }
+
+__device__ inline void incr2pi(float u, float& sn, float& cm1) {
+  float th = 6.28318530717958648f * u;
+  if (fabsf(th) < 0.8f) {
+    float t2 = th * th;
+    sn = th * (1.0f - t2 * (1.0f / 6.0f) *
+                          (1.0f - t2 * (1.0f / 20.0f) * (1.0f - t2 * (1.0f / 42.0f) * (1.0f - t2 * (1.0f / 72.0f)))));
+    cm1 = -0.5f * t2 *
+          (1.0f - t2 * (1.0f / 12.0f) *
+                      (1.0f - t2 * (1.0f / 30.0f) * (1.0f - t2 * (1.0f / 56.0f) * (1.0f - t2 * (1.0f / 90.0f)))));
+  } else {
+    float s, c;
+    sincospif(2.0f * u, &s, &c);
+    sn = s;
+    cm1 = c - 1.0f;
+  }
+}
+__device__ inline void incr2pi(double u, double& sn, double& cm1) {
+  sn = sinpi(2.0 * u);
+  double h = sinpi(u);
+  cm1 = -2.0 * h * h;
+}
+
+template <typename R> __device__ inline R r_expm1(R x);
+template <> __device__ inline float r_expm1<float>(float x) { return expm1f(x); }
+template <> __device__ inline double r_expm1<double>(double x) { return expm1(x); }
+template <typename R> __device__ inline R r_exp(R x);
+template <> __device__ inline float r_exp<float>(float x) { return expf(x); }
+template <> __device__ inline double r_exp<double>(double x) { return exp(x); }
+
+// ---------------------------------------------------------------------------
+// Position update: solve x(xi^n + delta h) - x(xi^n) = dt v for delta (in
+// cells) by Newton's method on the increment, starting from delta = 0 (whose
+// first step is k(xi^n) dt v / h).  Returns true when the last Newton step was
+// below tol cells.  J0 receives the (box-unit) Jacobian at xi^n.
+// ---------------------------------------------------------------------------
+
+// Sinusoidal map, x^a = L_a (xi^a + eps P), P = prod_k sin(2 pi xi^k) (Eq. map2
+// and its 3D extension).  In cells of axis a the increment equation reads
+//   F_a(delta) = delta_a + e_a [P(xi + delta h) - P(xi)] - r_a = 0,
+// e_a = eps n_a, r_a = dt v_a n_a / L_a.  Jacobian I + e g^T with
+// g_m = (2 pi / n_m) cos(2 pi xi_m') prod_{k != m} sin(2 pi xi_k'), inverted by
+// Sherman-Morrison; 1 + g.e is the box Jacobian at xi'.
+template <int D, typename R>
+__device__ inline bool newton_sinusoidal(const Geo& g, const int* idx, const R* f, const R* r,
+                                         R* d, R tol, int maxit, R& J0) {
+  R s[D], c[D], e[D], w[D], invn[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    invn[a] = (R)g.invn[a];
+    R phase = ((R)idx[a] + f[a]) * invn[a];
+    sincos2pi(phase, s[a], c[a]);
+    e[a] = (R)g.ecell[a];
+    w[a] = (R)6.28318530717958647692 * invn[a];
+    d[a] = (R)0;
+  }
+  bool conv = false;
+  for (int it = 0; it < maxit; ++it) {
+    R sn[D], cn[D], ds[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (it == 0) {
+        ds[a] = (R)0;
+        sn[a] = s[a];
+        cn[a] = c[a];
+      } else {
+        R st, cm1;
+        incr2pi(d[a] * invn[a], st, cm1);
+        ds[a] = s[a] * cm1 + c[a] * st;
+        R dc = c[a] * cm1 - s[a] * st;
+        sn[a] = s[a] + ds[a];
+        cn[a] = c[a] + dc;
+      }
+    }
+    R dP;
+    if (D == 2) {
+      dP = ds[0] * sn[1] + s[0] * ds[1];
+    } else {
+      dP = ds[0] * sn[1] * sn[D - 1] + s[0] * ds[1] * sn[D - 1] + s[0] * s[1] * ds[D - 1];
+    }
+    R F[D], gg[D];
+    R Jn = (R)1, gF = (R)0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      F[a] = d[a] + e[a] * dP - r[a];
+      R t = w[a] * cn[a];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+        if (k != a) t *= sn[k];
+      gg[a] = t;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      Jn += e[a] * gg[a];
+      gF += gg[a] * F[a];
+    }
+    if (it == 0) J0 = Jn;
+    R q = gF / Jn;
+    R mx = (R)0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      R dd = -(F[a] - e[a] * q);
+      d[a] += dd;
+      mx = fmax(mx, fabs(dd));
+    }
+    if (mx < tol) {
+      conv = true;
+      break;
+    }
+  }
+  return conv;
+}
+
+// Polar-log map: r = r_in exp(xi ln R), theta = 2 pi eta.  Increment in units
+// of r^n:  F = (rho - 1) e(theta') + [e(theta') - e(theta)] - dt v / r^n,
+// rho = exp(delta_0 ln R / n0), theta' = theta + 2 pi delta_1 / n1.  The
+// Jacobian columns are rho (ln R / n0) e(theta') and rho (2 pi / n1) e_perp.
+template <typename R>
+__device__ inline bool newton_polar(const Geo& g, const int* idx, const R* f, const R* vdt, R* d,
+                                    R tol, int maxit, R& J0) {
+  R invn0 = (R)g.invn[0], invn1 = (R)g.invn[1];
+  R lnR = (R)g.lnR;
+  R xi0 = ((R)idx[0] + f[0]) * invn0;
+  R r0 = (R)g.r_in * r_exp<R>(lnR * xi0);
+  R s0, c0;
+  sincos2pi(((R)idx[1] + f[1]) * invn1, s0, c0);
+  R bx = vdt[0] / r0, by = vdt[1] / r0;
+  R kx = lnR * invn0, ky = (R)6.28318530717958647692 * invn1;
+  d[0] = d[1] = (R)0;
+  J0 = (R)1;
+  bool conv = false;
+  for (int it = 0; it < maxit; ++it) {
+    R rm1 = r_expm1<R>(kx * d[0]);
+    R rho = (R)1 + rm1;
+    R st, cm1;
+    if (it == 0) {
+      st = (R)0;
+      cm1 = (R)0;
+    } else {
+      incr2pi(d[1] * invn1, st, cm1);
+    }
+    R dex = c0 * cm1 - s0 * st, dey = s0 * cm1 + c0 * st;
+    R ex = c0 + dex, ey = s0 + dey;
+    R Fx = rm1 * ex + dex - bx, Fy = rm1 * ey + dey - by;
+    R d0 = -(Fx * ex + Fy * ey) / (rho * kx);
+    R d1 = -(-Fx * ey + Fy * ex) / (rho * ky);
+    d[0] += d0;
+    d[1] += d1;
+    if (fmax(fabs(d0), fabs(d1)) < tol) {
+      conv = true;
+      break;
+    }
+  }
+  return conv;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-point deposit weights: per axis, integers at scale 2^S1 for the cells
+// i-1, i, i+1 of a particle at in-cell offset f (exactly representable in
+// FP64).  b2:  L = rint(2^(S1-1) (1-f)^2), R = rint(2^(S1-1) f^2),
+// C = 2^S1 - L - R.  CIC to cell centres with g = f - 1/2.  Multiplications
+// and ldexp are exact or correctly rounded, rint rounds half to even.
+// ---------------------------------------------------------------------------
+template <int SHAPE>
+__device__ inline void weights_fixed(double f, int S1, uint32_t* w) {
+  uint32_t one = 1u << S1;
+  if (SHAPE == SHAPE_B2) {
+    double a = 1.0 - f;
+    uint32_t L = (uint32_t)rint(ldexp(a * a, S1 - 1));
+    uint32_t R = (uint32_t)rint(ldexp(f * f, S1 - 1));
+    w[0] = L;
+    w[2] = R;
+    w[1] = one - L - R;
+  } else {
+    double gg = f - 0.5;
+    if (gg >= 0.0) {
+      uint32_t R = (uint32_t)rint(ldexp(gg, S1));
+      w[0] = 0;
+      w[1] = one - R;
+      w[2] = R;
+    } else {
+      uint32_t Lw = (uint32_t)rint(ldexp(-gg, S1));
+      w[0] = Lw;
+      w[1] = one - Lw;
+      w[2] = 0;
+    }
+  }
+}
+
+template <int SHAPE, typename R>
+__device__ inline void weights_real(R f, R* w) {
+  if (SHAPE == SHAPE_B2) {
+    R a = (R)1 - f, b = f - (R)0.5;
+    w[0] = (R)0.5 * a * a;
+    w[1] = (R)0.75 - b * b;
+    w[2] = (R)0.5 * f * f;
+  } else {
+    R gg = f - (R)0.5;
+    if (gg >= (R)0) {
+      w[0] = (R)0;
+      w[1] = (R)1 - gg;
+      w[2] = gg;
+    } else {
+      w[0] = -gg;
+      w[1] = (R)1 + gg;
+      w[2] = (R)0;
+    }
+  }
+}
+
+}  // namespace cpic

@@ -1,0 +1,882 @@
+// fields.hip -- grid-side kernels of the curvilinear PIC hot path (FP64):
+// metric coefficients, fixed background, charge, Poisson solve by geometric
+// multigrid, gauge, vertex field, diagnostics reductions.
+//
+// Discrete operator (Eq. poiscurv multiplied by J and integrated over a cell;
+// second order, conservative, ghost-cell boundaries):
+//   (A phi)_c = sum_a [ w_a(c+) (phi_{c+e_a} - phi_c) + w_a(c-) (phi_{c-e_a} - phi_c) ]
+//             - sum_{pairs i<j} sum_{4 edges e around c} W_e (u_c D_j phi + w_c D_i phi)_e
+// with face weights w = a^{ii} dV / h_i^2, edge weights W = a^{ij} dV/(h_i h_j),
+// a^{ij} = J g^{ij} at the face / edge centre, D_i phi at an edge the mean of
+// the two cell differences across i in the 2x2 block around it, and
+// u_c, w_c = +-1/2 the position of c in that block.  It is the negative
+// Hessian of the discrete energy, hence symmetric (and negative
+// semi-definite).  Dirichlet walls: ghost 2 phi_b - phi_in; Neumann: phi_in.
+//
+// Multigrid: cell-centred V-cycles, damped Jacobi smoothing (even sweep
+// counts, ping-pong buffers), residual restricted by summing the 2^d children,
+// correction prolonged by (3/4, 1/4) tensor interpolation, coarse operators
+// rediscretised from the analytic map at each level, coarsest level solved
+// by one workgroup.  Convergence is tested on the device (no host sync); the
+// kernels of later cycles return at once once the flag is set.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace cpic {
+
+// ----------------------------------------------------------------------------
+// map metric in FP64: Jacobi matrix j[a][b] = dx^a / dxi^b (Eq. jcov)
+// ----------------------------------------------------------------------------
+__device__ inline void map_jacobi(const Geo& g, const double* xi, double j[3][3], double* x) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) j[a][b] = (a == b) ? 1.0 : 0.0;
+  const int d = g.dim;
+  if (g.kind == MAP_IDENTITY) {
+    for (int a = 0; a < d; ++a) {
+      j[a][a] = g.L[a];
+      if (x) x[a] = g.L[a] * xi[a];
+    }
+  } else if (g.kind == MAP_SINUSOIDAL) {
+    double s[3], c[3];
+    for (int k = 0; k < d; ++k) sincospi(2.0 * xi[k], &s[k], &c[k]);
+    double P = 1.0;
+    for (int k = 0; k < d; ++k) P *= s[k];
+    for (int b = 0; b < d; ++b) {
+      double t = 6.283185307179586 * c[b];
+      for (int k = 0; k < d; ++k)
+        if (k != b) t *= s[k];
+      for (int a = 0; a < d; ++a) j[a][b] = g.L[a] * ((a == b ? 1.0 : 0.0) + g.eps * t);
+    }
+    if (x)
+      for (int a = 0; a < d; ++a) x[a] = g.L[a] * (xi[a] + g.eps * P);
+  } else {  // polar-log
+    double r = g.r_in * exp(xi[0] * g.lnR);
+    double st, ct;
+    sincospi(2.0 * xi[1], &st, &ct);
+    j[0][0] = r * g.lnR * ct;
+    j[0][1] = -6.283185307179586 * r * st;
+    j[1][0] = r * g.lnR * st;
+    j[1][1] = 6.283185307179586 * r * ct;
+    if (x) {
+      x[0] = r * ct;
+      x[1] = r * st;
+    }
+  }
+}
+
+__device__ inline double det3(int d, const double j[3][3]) {
+  if (d == 2) return j[0][0] * j[1][1] - j[0][1] * j[1][0];
+  return j[0][0] * (j[1][1] * j[2][2] - j[1][2] * j[2][1]) - j[0][1] * (j[1][0] * j[2][2] - j[1][2] * j[2][0]) +
+         j[0][2] * (j[1][0] * j[2][1] - j[1][1] * j[2][0]);
+}
+
+// inverse Jacobi matrix k = j^{-1} (Eq. jcon) by the adjugate
+__device__ inline void inv3(int d, const double j[3][3], double k[3][3], double& J) {
+  J = det3(d, j);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) k[a][b] = (a == b) ? 1.0 : 0.0;
+  if (d == 2) {
+    k[0][0] = j[1][1] / J;
+    k[0][1] = -j[0][1] / J;
+    k[1][0] = -j[1][0] / J;
+    k[1][1] = j[0][0] / J;
+    return;
+  }
+  k[0][0] = (j[1][1] * j[2][2] - j[1][2] * j[2][1]) / J;
+  k[0][1] = (j[0][2] * j[2][1] - j[0][1] * j[2][2]) / J;
+  k[0][2] = (j[0][1] * j[1][2] - j[0][2] * j[1][1]) / J;
+  k[1][0] = (j[1][2] * j[2][0] - j[1][0] * j[2][2]) / J;
+  k[1][1] = (j[0][0] * j[2][2] - j[0][2] * j[2][0]) / J;
+  k[1][2] = (j[0][2] * j[1][0] - j[0][0] * j[1][2]) / J;
+  k[2][0] = (j[1][0] * j[2][1] - j[1][1] * j[2][0]) / J;
+  k[2][1] = (j[0][1] * j[2][0] - j[0][0] * j[2][1]) / J;
+  k[2][2] = (j[0][0] * j[1][1] - j[0][1] * j[1][0]) / J;
+}
+
+// a^{pq} = J g^{pq}, g^{pq} = k^{p r} k^{q r} (Eqs. gcon, poiscurv; Omega = 1)
+__device__ inline double coef_pq(const Geo& g, const double* xi, int p, int q) {
+  double j[3][3], k[3][3], J;
+  map_jacobi(g, xi, j, nullptr);
+  inv3(g.dim, j, k, J);
+  double s = 0.0;
+  for (int r = 0; r < g.dim; ++r) s += k[p][r] * k[q][r];
+  return J * s;
+}
+
+// ----------------------------------------------------------------------------
+// small helpers
+// ----------------------------------------------------------------------------
+__device__ inline void lin_to_idx(long long c, const int* n, int* idx) {
+  idx[0] = (int)(c % n[0]);
+  long long t = c / n[0];
+  idx[1] = (int)(t % n[1]);
+  idx[2] = (int)(t / n[1]);
+}
+__device__ inline long long idx_to_lin(const int* idx, const int* n) {
+  return (long long)idx[0] + (long long)n[0] * (idx[1] + (long long)n[1] * idx[2]);
+}
+__device__ inline int wrapi(int v, int n) {
+  if (v < 0) return v + n;
+  if (v >= n) return v - n;
+  return v;
+}
+
+__global__ void fill_u8_kernel(unsigned char* p, unsigned char v, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+__global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+void launch_fill_u8(void* p, unsigned char v, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return;
+  if (v == 0 && bytes % 8 == 0 && ((uintptr_t)p % 8) == 0) {
+    size_t n = bytes / 8;
+    unsigned blocks = (unsigned)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks), dim3(256), 0, st, (unsigned long long*)p, 0ull, n);
+    return;
+  }
+  unsigned blocks = (unsigned)((bytes + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_u8_kernel, dim3(blocks), dim3(256), 0, st, (unsigned char*)p, v, bytes);
+}
+
+// ----------------------------------------------------------------------------
+// coefficients
+// ----------------------------------------------------------------------------
+struct LevelArgs {
+  int dim;
+  int n[3];
+  int periodic[3];
+  int dir[3][2];  // Dirichlet flags [axis][lo, hi]
+  double h[3];
+  double dV;
+  int mixed;
+  const double* wf[3];
+  const double* wlo[3];
+  const double* we[3];
+  const double* diag;
+};
+
+static LevelArgs level_args(const GridCtx& G, int l) {
+  const Level& L = G.lev[l];
+  LevelArgs a;
+  a.dim = G.g.dim;
+  a.mixed = G.mixed;
+  a.dV = L.dV;
+  for (int i = 0; i < 3; ++i) {
+    a.n[i] = L.n[i];
+    a.periodic[i] = G.g.periodic[i];
+    a.dir[i][0] = G.bc_lo[i] == BC_DIRICHLET;
+    a.dir[i][1] = G.bc_hi[i] == BC_DIRICHLET;
+    a.h[i] = L.h[i];
+    a.wf[i] = L.wf[i];
+    a.wlo[i] = L.wlo[i];
+    a.we[i] = L.we[i];
+  }
+  a.diag = L.diag;
+  return a;
+}
+
+__global__ void coef_kernel(Geo g, LevelArgs a, double* wf0, double* wf1, double* wf2, double* wl0,
+                            double* wl1, double* wl2, double* we0, double* we1, double* we2) {
+  long long nc = (long long)a.n[0] * a.n[1] * a.n[2];
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  int idx[3];
+  lin_to_idx(c, a.n, idx);
+  double* wf[3] = {wf0, wf1, wf2};
+  double* wl[3] = {wl0, wl1, wl2};
+  double* we[3] = {we0, we1, we2};
+  const int d = a.dim;
+  for (int ax = 0; ax < d; ++ax) {
+    double xi[3];
+    for (int b = 0; b < 3; ++b) xi[b] = (b < d) ? (idx[b] + 0.5) * a.h[b] : 0.0;
+    xi[ax] = (idx[ax] + 1) * a.h[ax];
+    wf[ax][c] = coef_pq(g, xi, ax, ax) * a.dV / (a.h[ax] * a.h[ax]);
+    double lo = 0.0;
+    if (!a.periodic[ax] && idx[ax] == 0) {
+      xi[ax] = 0.0;
+      lo = coef_pq(g, xi, ax, ax) * a.dV / (a.h[ax] * a.h[ax]);
+    }
+    wl[ax][c] = lo;
+  }
+  int pi[3] = {0, 0, 1}, pj[3] = {1, 2, 2};
+  int np = (d == 3) ? 3 : 1;
+  for (int p = 0; p < np; ++p) {
+    double W = 0.0;
+    if (a.mixed) {
+      double xi[3];
+      for (int b = 0; b < 3; ++b) xi[b] = (b < d) ? (idx[b] + 0.5) * a.h[b] : 0.0;
+      xi[pi[p]] = (idx[pi[p]] + 1) * a.h[pi[p]];
+      xi[pj[p]] = (idx[pj[p]] + 1) * a.h[pj[p]];
+      W = coef_pq(g, xi, pi[p], pj[p]) * a.dV / (a.h[pi[p]] * a.h[pj[p]]);
+    }
+    we[p][c] = W;
+  }
+}
+
+// diag of A and (level 0) the wall term bdir
+__global__ void diag_kernel(LevelArgs a, double* diag, double* bdir, double plo0, double plo1,
+                            double plo2, double phi0, double phi1, double phi2) {
+  long long nc = (long long)a.n[0] * a.n[1] * a.n[2];
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  int idx[3];
+  lin_to_idx(c, a.n, idx);
+  const int d = a.dim;
+  const double plo[3] = {plo0, plo1, plo2}, phi_[3] = {phi0, phi1, phi2};
+  double dg = 0.0, bd = 0.0;
+  for (int ax = 0; ax < d; ++ax) {
+    // upper face
+    if (a.periodic[ax] || idx[ax] < a.n[ax] - 1) {
+      dg -= a.wf[ax][c];
+    } else if (a.dir[ax][1]) {
+      dg -= 2.0 * a.wf[ax][c];
+      bd += 2.0 * a.wf[ax][c] * phi_[ax];
+    }
+    // lower face
+    if (a.periodic[ax] || idx[ax] > 0) {
+      int nb[3] = {idx[0], idx[1], idx[2]};
+      nb[ax] = wrapi(idx[ax] - 1, a.n[ax]);
+      dg -= a.wf[ax][idx_to_lin(nb, a.n)];
+    } else if (a.dir[ax][0]) {
+      dg -= 2.0 * a.wlo[ax][c];
+      bd += 2.0 * a.wlo[ax][c] * plo[ax];
+    }
+  }
+  if (a.mixed) {
+    int pi[3] = {0, 0, 1}, pj[3] = {1, 2, 2};
+    int np = (d == 3) ? 3 : 1;
+    for (int p = 0; p < np; ++p) {
+      int i = pi[p], j = pj[p];
+      for (int si = 0; si < 2; ++si)
+        for (int sj = 0; sj < 2; ++sj) {
+          int b[3] = {idx[0], idx[1], idx[2]};
+          b[i] = wrapi(idx[i] - si, a.n[i]);
+          b[j] = wrapi(idx[j] - sj, a.n[j]);
+          double W = a.we[p][idx_to_lin(b, a.n)];
+          double sg = (si == sj) ? 1.0 : -1.0;
+          dg -= 0.5 * W * sg;
+        }
+    }
+  }
+  diag[c] = dg;
+  if (bdir) bdir[c] = bd;
+}
+
+void launch_coefficients(const GridCtx& G, int l, hipStream_t st) {
+  const Level& L = G.lev[l];
+  LevelArgs a = level_args(G, l);
+  unsigned blocks = (unsigned)((L.ncells + 255) / 256);
+  hipLaunchKernelGGL(coef_kernel, dim3(blocks), dim3(256), 0, st, G.g, a, L.wf[0], L.wf[1], L.wf[2],
+                     L.wlo[0], L.wlo[1], L.wlo[2], L.we[0], L.we[1], L.we[2]);
+  hipLaunchKernelGGL(diag_kernel, dim3(blocks), dim3(256), 0, st, a, L.diag, l == 0 ? G.bdir : nullptr,
+                     G.phi_lo[0], G.phi_lo[1], G.phi_lo[2], G.phi_hi[0], G.phi_hi[1], G.phi_hi[2]);
+}
+
+__global__ void jc_kernel(Geo g, double* Jc) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ncells) return;
+  int idx[3];
+  lin_to_idx(c, g.n, idx);
+  double xi[3];
+  for (int b = 0; b < 3; ++b) xi[b] = (b < g.dim) ? (idx[b] + 0.5) * g.invn[b] : 0.0;
+  double j[3][3];
+  map_jacobi(g, xi, j, nullptr);
+  Jc[c] = det3(g.dim, j);
+}
+
+void launch_jacobian_centres(const GridCtx& G, hipStream_t st) {
+  unsigned blocks = (unsigned)((G.g.ncells + 255) / 256);
+  hipLaunchKernelGGL(jc_kernel, dim3(blocks), dim3(256), 0, st, G.g, G.Jc);
+}
+
+// ----------------------------------------------------------------------------
+// fixed background: I_c = n0 * int S(xi - xi_c) J(xi) dxi (deposit's shape S),
+// Gauss-Legendre, 8 nodes on each half cell of the 3-cell support.  2D only.
+// ----------------------------------------------------------------------------
+__constant__ double GL_NODE[8] = {-0.96028985649753623, -0.79666647741362674, -0.52553240991632899,
+                                  -0.18343464249564980, 0.18343464249564980,  0.52553240991632899,
+                                  0.79666647741362674,  0.96028985649753623};
+__constant__ double GL_WGT[8] = {0.10122853629037626, 0.22238103445337447, 0.31370664587788729,
+                                 0.36268378337836198, 0.36268378337836198, 0.31370664587788729,
+                                 0.22238103445337447, 0.10122853629037626};
+
+__device__ inline double shape_val(int shape, double u) {
+  double a = fabs(u);
+  if (shape == SHAPE_B2) {
+    if (a < 0.5) return 0.75 - u * u;
+    if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+    return 0.0;
+  }
+  return a < 1.0 ? 1.0 - a : 0.0;
+}
+
+__global__ void background_kernel(Geo g, int shape, double n0, double* I) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ncells) return;
+  int idx[3];
+  lin_to_idx(c, g.n, idx);
+  double sum = 0.0;
+  for (int qy = 0; qy < 48; ++qy) {
+    double uy = -1.25 + 0.5 * (qy / 8) + 0.25 * GL_NODE[qy % 8];
+    double wy = 0.25 * GL_WGT[qy % 8] * shape_val(shape, uy);
+    if (wy == 0.0) continue;
+    for (int qx = 0; qx < 48; ++qx) {
+      double ux = -1.25 + 0.5 * (qx / 8) + 0.25 * GL_NODE[qx % 8];
+      double wx = 0.25 * GL_WGT[qx % 8] * shape_val(shape, ux);
+      if (wx == 0.0) continue;
+      double xi[3] = {(idx[0] + 0.5 + ux) * g.invn[0], (idx[1] + 0.5 + uy) * g.invn[1], 0.0};
+      double j[3][3];
+      map_jacobi(g, xi, j, nullptr);
+      sum += wx * wy * det3(2, j);
+    }
+  }
+  I[c] = n0 * sum * g.invn[0] * g.invn[1];
+}
+
+void launch_background(const GridCtx& G, int shape, double n0, hipStream_t st) {
+  unsigned blocks = (unsigned)((G.g.ncells + 127) / 128);
+  hipLaunchKernelGGL(background_kernel, dim3(blocks), dim3(128), 0, st, G.g, shape, n0, G.background);
+}
+
+// ----------------------------------------------------------------------------
+// charge per cell: sum_s q_s w_s Q_s (integer Q scaled by 2^-d S1) + background
+// ----------------------------------------------------------------------------
+__global__ void charge_kernel(long long nc, ChargeSpecies cs, const double* bg, double bgq,
+                              double* charge) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  double s = 0.0;
+  for (int k = 0; k < cs.n; ++k) {
+    double q = cs.fixed ? (double)((const unsigned long long*)cs.Q[k])[c] : ((const double*)cs.Q[k])[c];
+    double t = cs.qw[k] * q;
+    s = (k == 0) ? t : s + t;
+  }
+  if (bg) s = s + bgq * bg[c];
+  charge[c] = s;
+}
+
+void launch_charge(const GridCtx& G, const ChargeSpecies& cs, double bg_charge, hipStream_t st) {
+  unsigned blocks = (unsigned)((G.g.ncells + 255) / 256);
+  hipLaunchKernelGGL(charge_kernel, dim3(blocks), dim3(256), 0, st, G.g.ncells, cs, G.background,
+                     bg_charge, G.charge);
+}
+
+// ----------------------------------------------------------------------------
+// deterministic reductions: fixed grid of 256 blocks, fixed-order tree
+// ----------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 256;
+
+__device__ inline double block_sum(double v) {
+  __shared__ double sh[16];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) / 64;
+    for (int i = 0; i < nw; ++i) s += sh[i];
+  }
+  return s;  // valid in thread 0
+}
+
+// kind 0: sum a*b; kind 1: sum a; kind 2: sum a*a
+__global__ __launch_bounds__(256) void reduce_partial_kernel(const double* a, const double* b, long long n,
+                                                             int kind, double* partials,
+                                                             const int* flag) {
+  if (flag && flag[0]) return;
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    double x = a[i];
+    s += (kind == 0) ? x * b[i] : (kind == 1 ? x : x * x);
+  }
+  double t = block_sum(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// op 0: out = sum; op 1: MG convergence test vs scalars[0] (|b|^2):
+//   sets flag[0] when sum <= rtol^2 |b|^2 (or |b| == 0), counts cycles in flag[1]
+__global__ __launch_bounds__(256) void reduce_final_kernel(const double* partials, int nb, double* out,
+                                                           int op, double rtol2, const double* bnorm2,
+                                                           int* flag, int count_cycle) {
+  if (op == 1 && flag[0]) return;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partials[i];
+  // fixed-order: each thread's strided sum, then the block tree
+  double t = block_sum(s);
+  if (threadIdx.x == 0) {
+    *out = t;
+    if (op == 1) {
+      if (count_cycle) flag[1] += 1;
+      if (t <= rtol2 * (*bnorm2) || *bnorm2 == 0.0) flag[0] = 1;
+    }
+  }
+}
+
+static void reduce(const double* a, const double* b, long long n, int kind, double* partials, double* out,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(reduce_partial_kernel, dim3(RED_BLOCKS), dim3(256), 0, st, a, b, n, kind, partials,
+                     (const int*)nullptr);
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, partials, RED_BLOCKS, out, 0, 0.0,
+                     (const double*)nullptr, (int*)nullptr, 0);
+}
+
+// ----------------------------------------------------------------------------
+// right-hand side: b = -charge - bdir, projected to zero sum when singular
+// ----------------------------------------------------------------------------
+__global__ void rhs_kernel(long long nc, const double* charge, const double* bdir, double* rhs) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  rhs[c] = -charge[c] - bdir[c];
+}
+__global__ void sub_scalar_kernel(long long n, double* x, const double* s, double scale) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  x[c] -= (*s) * scale;
+}
+
+void launch_rhs(const GridCtx& G, hipStream_t st) {
+  const Level& L = G.lev[0];
+  unsigned blocks = (unsigned)((L.ncells + 255) / 256);
+  hipLaunchKernelGGL(rhs_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, G.charge, G.bdir, L.rhs);
+  if (G.all_periodic) {
+    reduce(L.rhs, nullptr, L.ncells, 1, G.partials, G.scalars + 3, st);
+    hipLaunchKernelGGL(sub_scalar_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, L.rhs, G.scalars + 3,
+                       1.0 / (double)L.ncells);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// operator
+// ----------------------------------------------------------------------------
+__device__ inline double apply_A(const LevelArgs& a, const double* __restrict__ phi, const int* idx,
+                                 long long c) {
+  const int d = a.dim;
+  const double pc = phi[c];
+  double acc = 0.0;
+  for (int ax = 0; ax < d; ++ax) {
+    if (a.periodic[ax] || idx[ax] < a.n[ax] - 1) {
+      int nb[3] = {idx[0], idx[1], idx[2]};
+      nb[ax] = wrapi(idx[ax] + 1, a.n[ax]);
+      acc += a.wf[ax][c] * (phi[idx_to_lin(nb, a.n)] - pc);
+    } else if (a.dir[ax][1]) {
+      acc -= 2.0 * a.wf[ax][c] * pc;
+    }
+    if (a.periodic[ax] || idx[ax] > 0) {
+      int nb[3] = {idx[0], idx[1], idx[2]};
+      nb[ax] = wrapi(idx[ax] - 1, a.n[ax]);
+      long long cn = idx_to_lin(nb, a.n);
+      acc += a.wf[ax][cn] * (phi[cn] - pc);
+    } else if (a.dir[ax][0]) {
+      acc -= 2.0 * a.wlo[ax][c] * pc;
+    }
+  }
+  if (a.mixed) {
+    const int pi[3] = {0, 0, 1}, pj[3] = {1, 2, 2};
+    const int np = (d == 3) ? 3 : 1;
+    for (int p = 0; p < np; ++p) {
+      const int i = pi[p], j = pj[p];
+      // 3x3 neighbourhood of c in the (i, j) plane
+      double nbv[3][3];
+      for (int oi = -1; oi <= 1; ++oi)
+        for (int oj = -1; oj <= 1; ++oj) {
+          int nb[3] = {idx[0], idx[1], idx[2]};
+          nb[i] = wrapi(idx[i] + oi, a.n[i]);
+          nb[j] = wrapi(idx[j] + oj, a.n[j]);
+          nbv[oi + 1][oj + 1] = (oi == 0 && oj == 0) ? pc : phi[idx_to_lin(nb, a.n)];
+        }
+      for (int si = 0; si < 2; ++si)
+        for (int sj = 0; sj < 2; ++sj) {
+          // edge block with lower corner b = c - (si, sj); c sits at (si, sj)
+          int b[3] = {idx[0], idx[1], idx[2]};
+          b[i] = wrapi(idx[i] - si, a.n[i]);
+          b[j] = wrapi(idx[j] - sj, a.n[j]);
+          double W = a.we[p][idx_to_lin(b, a.n)];
+          // block values phi(b + (ti, tj)) = nbv[ti - si + 1][tj - sj + 1]
+          double p00 = nbv[1 - si][1 - sj], p10 = nbv[2 - si][1 - sj];
+          double p01 = nbv[1 - si][2 - sj], p11 = nbv[2 - si][2 - sj];
+          double Di = 0.5 * ((p10 + p11) - (p00 + p01));
+          double Dj = 0.5 * ((p01 + p11) - (p00 + p10));
+          double uc = si ? 0.5 : -0.5, wc = sj ? 0.5 : -0.5;
+          acc -= W * (uc * Dj + wc * Di);
+        }
+    }
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void smooth_kernel(LevelArgs a, const double* __restrict__ phi,
+                                                     const double* __restrict__ rhs, double* out,
+                                                     double omega, const int* flag) {
+  if (flag[0]) return;
+  long long nc = (long long)a.n[0] * a.n[1] * a.n[2];
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  int idx[3];
+  lin_to_idx(c, a.n, idx);
+  double r = rhs[c] - apply_A(a, phi, idx, c);
+  out[c] = phi[c] + omega * r / a.diag[c];
+}
+
+// coarse rhs = sum of the fine residuals of the 2^d children; coarse phi = 0
+__global__ __launch_bounds__(256) void restrict_kernel(LevelArgs fa, const double* __restrict__ phi,
+                                                       const double* __restrict__ rhs, int nc0, int nc1,
+                                                       int nc2, double* crhs, double* cphi,
+                                                       const int* flag) {
+  if (flag[0]) return;
+  const int cn[3] = {nc0, nc1, nc2};
+  long long ncc = (long long)nc0 * nc1 * nc2;
+  long long C = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (C >= ncc) return;
+  int I[3];
+  lin_to_idx(C, cn, I);
+  const int d = fa.dim;
+  double s = 0.0;
+  const int nz = (d == 3) ? 2 : 1;
+  for (int sz = 0; sz < nz; ++sz)
+    for (int sy = 0; sy < 2; ++sy)
+      for (int sx = 0; sx < 2; ++sx) {
+        int idx[3] = {2 * I[0] + sx, 2 * I[1] + sy, (d == 3) ? 2 * I[2] + sz : 0};
+        long long c = idx_to_lin(idx, fa.n);
+        s += rhs[c] - apply_A(fa, phi, idx, c);
+      }
+  crhs[C] = s;
+  cphi[C] = 0.0;
+}
+
+// fine phi += (3/4, 1/4)-tensor interpolation of the coarse correction
+__global__ __launch_bounds__(256) void prolong_kernel(LevelArgs fa, double* phi, const double* __restrict__ cphi,
+                                                      int nc0, int nc1, int nc2, const int* flag) {
+  if (flag[0]) return;
+  const int cn[3] = {nc0, nc1, nc2};
+  long long nc = (long long)fa.n[0] * fa.n[1] * fa.n[2];
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  int idx[3];
+  lin_to_idx(c, fa.n, idx);
+  const int d = fa.dim;
+  int I[3] = {idx[0] >> 1, idx[1] >> 1, idx[2] >> 1};
+  int J[3];
+  double sgn[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    J[ax] = I[ax];
+    sgn[ax] = 1.0;
+    if (ax >= d) continue;
+    int step = (idx[ax] & 1) ? 1 : -1;
+    int v = I[ax] + step;
+    if (fa.periodic[ax]) {
+      J[ax] = wrapi(v, cn[ax]);
+    } else if (v < 0 || v >= cn[ax]) {
+      // ghost of the correction: homogeneous Dirichlet -> -e, Neumann -> e
+      J[ax] = I[ax];
+      int dirw = (v < 0) ? fa.dir[ax][0] : fa.dir[ax][1];
+      sgn[ax] = dirw ? -1.0 : 1.0;
+    } else {
+      J[ax] = v;
+    }
+  }
+  double acc = 0.0;
+  const int nz = (d == 3) ? 2 : 1;
+  for (int tz = 0; tz < nz; ++tz)
+    for (int ty = 0; ty < 2; ++ty)
+      for (int tx = 0; tx < 2; ++tx) {
+        int t[3] = {tx, ty, tz};
+        int K[3];
+        double w = 1.0;
+        for (int ax = 0; ax < 3; ++ax) {
+          if (ax >= d) {
+            K[ax] = 0;
+            continue;
+          }
+          K[ax] = t[ax] ? J[ax] : I[ax];
+          w *= t[ax] ? 0.25 * sgn[ax] : 0.75;
+        }
+        acc += w * cphi[idx_to_lin(K, cn)];
+      }
+  phi[c] += acc;
+}
+
+// coarsest level: one workgroup, damped Jacobi sweeps in place (via scratch)
+__global__ __launch_bounds__(256) void coarse_kernel(LevelArgs a, double* phi, double* tmp,
+                                                     const double* __restrict__ rhs, int sweeps,
+                                                     int singular, const int* flag) {
+  if (flag[0]) return;
+  const int nc = a.n[0] * a.n[1] * a.n[2];
+  for (int it = 0; it < sweeps; ++it) {
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      int idx[3];
+      lin_to_idx(c, a.n, idx);
+      double r = rhs[c] - apply_A(a, phi, idx, c);
+      tmp[c] = phi[c] + 0.8 * r / a.diag[c];
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) phi[c] = tmp[c];
+    __syncthreads();
+  }
+  if (singular) {
+    __shared__ double mean;
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int c = 0; c < nc; ++c) s += phi[c];
+      mean = s / nc;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) phi[c] -= mean;
+  }
+}
+
+__global__ void residual_norm_kernel(LevelArgs a, const double* __restrict__ phi,
+                                     const double* __restrict__ rhs, double* partials,
+                                     const int* flag) {
+  if (flag[0]) return;
+  long long nc = (long long)a.n[0] * a.n[1] * a.n[2];
+  double s = 0.0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < nc;
+       c += (long long)gridDim.x * blockDim.x) {
+    int idx[3];
+    lin_to_idx(c, a.n, idx);
+    double r = rhs[c] - apply_A(a, phi, idx, c);
+    s += r * r;
+  }
+  double t = block_sum(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ void mg_reset_kernel(int* flag) {
+  flag[0] = 0;
+  flag[1] = 0;
+}
+
+static void vcycle(const GridCtx& G, int l, int nu1, int nu2, hipStream_t st) {
+  const Level& L = G.lev[l];
+  LevelArgs a = level_args(G, l);
+  unsigned blocks = (unsigned)((L.ncells + 255) / 256);
+  if (l == G.nlev - 1) {
+    hipLaunchKernelGGL(coarse_kernel, dim3(1), dim3(256), 0, st, a, L.phi, L.phi2, L.rhs, 60,
+                       G.all_periodic, G.mg_flag);
+    return;
+  }
+  const double omega = 0.8;
+  for (int s = 0; s < nu1; s += 2) {
+    hipLaunchKernelGGL(smooth_kernel, dim3(blocks), dim3(256), 0, st, a, L.phi, L.rhs, L.phi2, omega, G.mg_flag);
+    hipLaunchKernelGGL(smooth_kernel, dim3(blocks), dim3(256), 0, st, a, L.phi2, L.rhs, L.phi, omega, G.mg_flag);
+  }
+  const Level& C = G.lev[l + 1];
+  unsigned cblocks = (unsigned)((C.ncells + 255) / 256);
+  hipLaunchKernelGGL(restrict_kernel, dim3(cblocks), dim3(256), 0, st, a, L.phi, L.rhs, C.n[0], C.n[1],
+                     C.n[2], C.rhs, C.phi, G.mg_flag);
+  vcycle(G, l + 1, nu1, nu2, st);
+  hipLaunchKernelGGL(prolong_kernel, dim3(blocks), dim3(256), 0, st, a, L.phi, C.phi, C.n[0], C.n[1],
+                     C.n[2], G.mg_flag);
+  for (int s = 0; s < nu2; s += 2) {
+    hipLaunchKernelGGL(smooth_kernel, dim3(blocks), dim3(256), 0, st, a, L.phi, L.rhs, L.phi2, omega, G.mg_flag);
+    hipLaunchKernelGGL(smooth_kernel, dim3(blocks), dim3(256), 0, st, a, L.phi2, L.rhs, L.phi, omega, G.mg_flag);
+  }
+}
+
+// Solve A phi = rhs on level 0 (phi holds the initial guess).  Returns the
+// number of cycles launched; the number executed is in mg_flag[1].
+int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st) {
+  const Level& L = G.lev[0];
+  LevelArgs a = level_args(G, 0);
+  hipLaunchKernelGGL(mg_reset_kernel, dim3(1), dim3(1), 0, st, G.mg_flag);
+  // |b|^2
+  hipLaunchKernelGGL(reduce_partial_kernel, dim3(RED_BLOCKS), dim3(256), 0, st, L.rhs, (const double*)nullptr,
+                     L.ncells, 2, G.partials, (const int*)nullptr);
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.partials, RED_BLOCKS, G.scalars + 0, 0,
+                     0.0, (const double*)nullptr, (int*)nullptr, 0);
+  const double rtol2 = rtol * rtol;
+  // initial residual
+  hipLaunchKernelGGL(residual_norm_kernel, dim3(RED_BLOCKS), dim3(256), 0, st, a, L.phi, L.rhs, G.partials,
+                     G.mg_flag);
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.partials, RED_BLOCKS, G.scalars + 1, 1,
+                     rtol2, G.scalars + 0, G.mg_flag, 0);
+  for (int cyc = 0; cyc < max_cycles; ++cyc) {
+    vcycle(G, 0, nu1, nu2, st);
+    hipLaunchKernelGGL(residual_norm_kernel, dim3(RED_BLOCKS), dim3(256), 0, st, a, L.phi, L.rhs, G.partials,
+                       G.mg_flag);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.partials, RED_BLOCKS, G.scalars + 1,
+                       1, rtol2, G.scalars + 0, G.mg_flag, 1);
+  }
+  return max_cycles;
+}
+
+// periodic problems: shift phi so that its J-weighted mean is zero
+void launch_gauge(const GridCtx& G, hipStream_t st) {
+  if (!G.all_periodic) return;
+  const Level& L = G.lev[0];
+  reduce(G.Jc, L.phi, L.ncells, 0, G.partials, G.scalars + 2, st);
+  unsigned blocks = (unsigned)((L.ncells + 255) / 256);
+  hipLaunchKernelGGL(sub_scalar_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, L.phi, G.scalars + 2,
+                     1.0 / G.sumJ);
+}
+
+// ----------------------------------------------------------------------------
+// vertex field E_v = -k(xi_v)^T (D phi)_v (physical components)
+// ----------------------------------------------------------------------------
+__device__ inline double phi_ghost(const Geo& g, const int* bclo, const int* bchi, const double* plo,
+                                   const double* phh, const double* phi, const int* in_idx) {
+  int idx[3] = {in_idx[0], in_idx[1], in_idx[2]};
+  double sgn = 1.0, add = 0.0;
+  for (int a = 0; a < g.dim; ++a) {
+    const int n = g.n[a];
+    if (idx[a] >= 0 && idx[a] < n) continue;
+    if (g.periodic[a]) {
+      idx[a] = wrapi(idx[a], n);
+      continue;
+    }
+    bool lo = idx[a] < 0;
+    idx[a] = lo ? 0 : n - 1;
+    int bct = lo ? bclo[a] : bchi[a];
+    if (bct == BC_DIRICHLET) {
+      // ghost = 2 phi_b - phi_in (applied to the value after the other axes)
+      add = sgn * 2.0 * (lo ? plo[a] : phh[a]) + add * 1.0;
+      sgn = -sgn;
+    }
+  }
+  return add + sgn * phi[idx_to_lin(idx, g.n)];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void efield_kernel(Geo g, int bclo0, int bclo1, int bclo2, int bchi0,
+                                                     int bchi1, int bchi2, double plo0, double plo1,
+                                                     double plo2, double phh0, double phh1, double phh2,
+                                                     const double* __restrict__ phi, R* Ev) {
+  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= g.nverts) return;
+  const int bclo[3] = {bclo0, bclo1, bclo2}, bchi[3] = {bchi0, bchi1, bchi2};
+  const double plo[3] = {plo0, plo1, plo2}, phh[3] = {phh0, phh1, phh2};
+  const int d = g.dim;
+  int vi[3] = {0, 0, 0};
+  long long t = v;
+  for (int a = 0; a < d; ++a) {
+    vi[a] = (int)(t % g.nv[a]);
+    t /= g.nv[a];
+  }
+  double D[3] = {0.0, 0.0, 0.0};
+  const int npair = 1 << (d - 1);
+  for (int a = 0; a < d; ++a) {
+    double s = 0.0;
+    for (int comb = 0; comb < npair; ++comb) {
+      int cp[3] = {0, 0, 0}, cm[3] = {0, 0, 0};
+      int bit = 0;
+      for (int b = 0; b < d; ++b) {
+        if (b == a) {
+          cp[b] = vi[b];
+          cm[b] = vi[b] - 1;
+        } else {
+          int sb = (comb >> bit) & 1;
+          ++bit;
+          cp[b] = cm[b] = vi[b] - 1 + sb;
+        }
+      }
+      s += phi_ghost(g, bclo, bchi, plo, phh, phi, cp) - phi_ghost(g, bclo, bchi, plo, phh, phi, cm);
+    }
+    D[a] = s / (npair * g.invn[a]);
+  }
+  double xi[3] = {vi[0] * g.invn[0], vi[1] * g.invn[1], (d == 3) ? vi[2] * g.invn[2] : 0.0};
+  double j[3][3], k[3][3], J;
+  map_jacobi(g, xi, j, nullptr);
+  inv3(d, j, k, J);
+  const int EC = (d == 3) ? 4 : 2;
+  for (int b = 0; b < d; ++b) {
+    double e = 0.0;
+    for (int a = 0; a < d; ++a) e -= k[a][b] * D[a];
+    Ev[v * EC + b] = (R)e;
+  }
+  if (d == 3) Ev[v * EC + 3] = (R)0;
+}
+
+void launch_efield(const GridCtx& G, hipStream_t st) {
+  const Geo& g = G.g;
+  unsigned blocks = (unsigned)((g.nverts + 255) / 256);
+  if (G.fp64)
+    hipLaunchKernelGGL(efield_kernel<double>, dim3(blocks), dim3(256), 0, st, g, G.bc_lo[0], G.bc_lo[1],
+                       G.bc_lo[2], G.bc_hi[0], G.bc_hi[1], G.bc_hi[2], G.phi_lo[0], G.phi_lo[1], G.phi_lo[2],
+                       G.phi_hi[0], G.phi_hi[1], G.phi_hi[2], G.lev[0].phi, (double*)G.Ev);
+  else
+    hipLaunchKernelGGL(efield_kernel<float>, dim3(blocks), dim3(256), 0, st, g, G.bc_lo[0], G.bc_lo[1],
+                       G.bc_lo[2], G.bc_hi[0], G.bc_hi[1], G.bc_hi[2], G.phi_lo[0], G.phi_lo[1], G.phi_lo[2],
+                       G.phi_hi[0], G.phi_hi[1], G.phi_hi[2], G.lev[0].phi, (float*)G.Ev);
+}
+
+__global__ void rho_kernel(long long nc, double dV, const double* charge, const double* Jc, double* rho) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  rho[c] = charge[c] / (Jc[c] * dV);
+}
+
+void launch_rho(const GridCtx& G, double* rho, hipStream_t st) {
+  unsigned blocks = (unsigned)((G.g.ncells + 255) / 256);
+  hipLaunchKernelGGL(rho_kernel, dim3(blocks), dim3(256), 0, st, G.g.ncells, G.lev[0].dV, G.charge, G.Jc, rho);
+}
+
+void launch_field_energy(const GridCtx& G, double* out, hipStream_t st) {
+  reduce(G.charge, G.lev[0].phi, G.g.ncells, 0, G.partials, out, st);
+  // W_E = 1/2 sum charge phi: the factor is applied by the host
+}
+
+// exact 128-bit sum of a uint64 array: per-block (lo, hi) partials, then one block
+__global__ __launch_bounds__(256) void qsum_kernel(const unsigned long long* Q, long long n,
+                                                   unsigned long long* part) {
+  __shared__ unsigned long long slo[256], shi[256];
+  unsigned long long lo = 0, hi = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    unsigned long long v = Q[i];
+    unsigned long long s = lo + v;
+    hi += (s < lo) ? 1ull : 0ull;
+    lo = s;
+  }
+  slo[threadIdx.x] = lo;
+  shi[threadIdx.x] = hi;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long L = 0, H = 0;
+    for (int t = 0; t < (int)blockDim.x; ++t) {
+      unsigned long long s = L + slo[t];
+      H += shi[t] + ((s < L) ? 1ull : 0ull);
+      L = s;
+    }
+    part[2 * blockIdx.x] = L;
+    part[2 * blockIdx.x + 1] = H;
+  }
+}
+__global__ void qsum_final_kernel(const unsigned long long* part, int nb, unsigned long long* out) {
+  unsigned long long L = 0, H = 0;
+  for (int b = 0; b < nb; ++b) {
+    unsigned long long s = L + part[2 * b];
+    H += part[2 * b + 1] + ((s < L) ? 1ull : 0ull);
+    L = s;
+  }
+  out[0] = L;
+  out[1] = H;
+}
+
+void launch_qsum(const uint64_t* Q, long long n, uint64_t* out2, hipStream_t st) {
+  // out2 must have room for 2 + 2 * RED_BLOCKS words (partials follow the result)
+  unsigned long long* part = (unsigned long long*)out2 + 2;
+  hipLaunchKernelGGL(qsum_kernel, dim3(RED_BLOCKS), dim3(256), 0, st, (const unsigned long long*)Q, n, part);
+  hipLaunchKernelGGL(qsum_final_kernel, dim3(1), dim3(1), 0, st, part, RED_BLOCKS, (unsigned long long*)out2);
+}
+
+__global__ void nonfinite_kernel(const double* x, long long n, int* bad) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(x[i])) atomicAdd(bad, 1);
+}
+void launch_nonfinite_check(const double* x, long long n, int* bad, hipStream_t st) {
+  unsigned blocks = (unsigned)((n + 255) / 256);
+  if (n > 0) hipLaunchKernelGGL(nonfinite_kernel, dim3(blocks), dim3(256), 0, st, x, n, bad);
+}
+
+}  // namespace cpic

@@ -1,0 +1,125 @@
+// kernels.hpp -- launch descriptors and launchers shared by the kernel files
+// and the host core (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace cpic {
+
+struct ParticleLaunch {
+  Geo g;
+  int fp64;
+  int shape;
+  int mode;
+  int32_t* key;
+  void* off[3];
+  void* vel[3];
+  const int* item_tile;
+  const int* item_begin;
+  const int* item_end;
+  const int* n_items;
+  int max_items;
+  const void* Ev;
+  void* Q;
+  int pbc_lo[3], pbc_hi[3];
+  double qm, dt;
+  double B[3];
+  int magnetic, vz_active;
+  int S1;
+  int newton_maxit;
+  double newton_tol;
+  double ke_scale;
+  double* ke;
+  unsigned long long* counters;
+};
+
+struct SortLaunch {
+  Geo g;
+  int fp64;
+  long long capacity;
+  int chunk;
+  const int32_t* key_in;
+  int32_t* key_out;
+  const void* off_in[3];
+  void* off_out[3];
+  const void* vel_in[3];
+  void* vel_out[3];
+  const uint32_t* id_in;
+  uint32_t* id_out;
+  int* d_n;
+  int* counts;  // ntiles + 2
+  int* start;   // ntiles + 2
+  int* cursor;  // ntiles + 2
+  int* n_items;
+  int* item_tile;
+  int* item_begin;
+  int* item_end;
+};
+
+int launch_particles(const ParticleLaunch& L, hipStream_t st);
+int launch_tile_sort(const SortLaunch& S, hipStream_t st);
+void launch_lin_to_key(const int32_t* lin, int32_t* key, int n, const Geo& g, int* bad, hipStream_t st);
+void launch_key_to_lin(const int32_t* key, int32_t* lin, int n, const Geo& g, hipStream_t st);
+void launch_iota(uint32_t* id, int n, hipStream_t st);
+void launch_offsets_check(const void* o, long long n, int fp64, int* bad, hipStream_t st);
+void launch_fill_u8(void* p, unsigned char v, size_t bytes, hipStream_t st);
+
+// ---------------------------------------------------------------- grid side
+// One multigrid level: cell-centred grid, coefficient arrays (FP64).
+struct Level {
+  int n[3];
+  long long ncells;
+  double h[3];
+  double dV;
+  double* wf[3];     // upper-face coefficient of each cell, a^{aa} dV / h_a^2
+  double* wlo[3];    // lower wall-face coefficient (bounded axes, cells at i_a = 0)
+  double* we[3];     // mixed-term coefficient at the upper corner edge, pairs (01, 02, 12)
+  double* diag;
+  double* phi;
+  double* phi2;      // ping-pong
+  double* rhs;
+  double* res;
+};
+
+struct GridCtx {
+  Geo g;
+  int nlev;
+  Level lev[16];
+  int bc_lo[3], bc_hi[3];
+  double phi_lo[3], phi_hi[3];
+  int mixed;          // the map has non-zero mixed metric terms
+  int all_periodic;
+  double* bdir;       // wall contribution to the operator (level 0)
+  double* Jc;         // physical J at cell centres (level 0)
+  double sumJ;        // host copy
+  double* charge;
+  double* background;
+  double* partials;   // reduction scratch (>= 1024 doubles)
+  double* scalars;    // device scalars: [0] |b|^2 [1] |r|^2 [2] sumJphi [3] mean [4..] misc
+  int* mg_flag;       // [0] converged [1] cycles done
+  void* Ev;           // vertex field (float or double, interleaved)
+  int fp64;
+};
+
+void launch_coefficients(const GridCtx& G, int level, hipStream_t st);
+void launch_jacobian_centres(const GridCtx& G, hipStream_t st);
+void launch_background(const GridCtx& G, int shape, double n0, hipStream_t st);
+struct ChargeSpecies {
+  int n;
+  const void* Q[8];
+  double qw[8];  // q_s w_s (times 2^-d S1 for integer deposits)
+  int fixed;
+};
+void launch_charge(const GridCtx& G, const ChargeSpecies& cs, double bg_charge, hipStream_t st);
+void launch_rhs(const GridCtx& G, hipStream_t st);
+int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st);
+void launch_gauge(const GridCtx& G, hipStream_t st);
+void launch_efield(const GridCtx& G, hipStream_t st);
+void launch_rho(const GridCtx& G, double* rho, hipStream_t st);
+void launch_field_energy(const GridCtx& G, double* out, hipStream_t st);
+void launch_qsum(const uint64_t* Q, long long n, uint64_t* out2, hipStream_t st);
+void launch_nonfinite_check(const double* x, long long n, int* bad, hipStream_t st);
+
+}  // namespace cpic

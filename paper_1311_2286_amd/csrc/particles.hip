@@ -1,0 +1,724 @@
+// particles.hip -- particle kernels of the curvilinear PIC hot path for CDNA4.
+//
+//   particle_kernel : one workgroup per work item (a contiguous run of the
+//                     particles of one 16^2 / 8^3 cell tile).  Per particle:
+//                     gather of the vertex field (Eqs. vvp, Wvp, b1), Boris /
+//                     leap-frog velocity update (Eqs. step1, step1a), position
+//                     update x(xi^n) + dt v^{n+1/2} mapped back to xi by
+//                     Newton on the map increment, particle boundaries, and
+//                     the charge deposit (Eqs. pg, Wpc, b2) into an LDS window
+//                     of the tile plus G cells, flushed to HBM with atomics.
+//   tile sort       : counting sort of the particle arrays by tile (histogram,
+//                     scan into work items, scatter), dropping dead particles.
+//
+// Particles are structure-of-arrays; a tile's particles are contiguous after a
+// sort, so every workgroup streams its run with coalesced loads and stores.
+#include <type_traits>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace cpic {
+
+// ----------------------------------------------------------------------------
+// wave-level helpers (wave64)
+// ----------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Aggregated atomicAdd of 1 per active lane onto counters[key]: lanes sharing a
+// key are served by one atomic; each active lane gets old value + its rank.
+// Must be called by all lanes of the wave.
+__device__ inline int agg_inc(int* counters, int key, bool active) {
+  int out = 0;
+  bool pending = active;
+  const int lane = __lane_id();
+  while (true) {
+    unsigned long long pm = __ballot(pending);
+    if (pm == 0ull) break;
+    int leader = __ffsll((unsigned long long)pm) - 1;
+    int lkey = __shfl(key, leader, 64);
+    bool mine = pending && key == lkey;
+    unsigned long long mm = __ballot(mine);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counters[lkey], __popcll(mm));
+    base = __shfl(base, leader, 64);
+    if (mine) {
+      out = base + __popcll(mm & ((1ull << lane) - 1ull));
+      pending = false;
+    }
+  }
+  return out;
+}
+
+// ----------------------------------------------------------------------------
+// field gather: CIC weights (1 - f, f) over the 2^D vertices of the cell
+// ----------------------------------------------------------------------------
+template <int D, typename R>
+__device__ inline void gather_E(const R* __restrict__ Ev, const Geo& g, const int* idx, const R* f,
+                                R* E) {
+  constexpr int EC = (D == 3) ? 4 : 2;
+  E[0] = E[1] = E[2] = (R)0;
+  int vx0 = idx[0], vx1 = idx[0] + 1;
+  if (vx1 >= g.nv[0]) vx1 -= g.nv[0];
+  int vy0 = idx[1], vy1 = idx[1] + 1;
+  if (vy1 >= g.nv[1]) vy1 -= g.nv[1];
+  R wx[2] = {(R)1 - f[0], f[0]};
+  R wy[2] = {(R)1 - f[1], f[1]};
+  if (D == 2) {
+    const int vxs[2] = {vx0, vx1}, vys[2] = {vy0, vy1};
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        long long v = (long long)vxs[a] + (long long)g.nv[0] * vys[b];
+        const R* e = Ev + v * EC;
+        R w = wx[a] * wy[b];
+        E[0] += w * e[0];
+        E[1] += w * e[1];
+      }
+  } else {
+    int vz0 = idx[2], vz1 = idx[2] + 1;
+    if (vz1 >= g.nv[2]) vz1 -= g.nv[2];
+    R wz[2] = {(R)1 - f[2], f[2]};
+    const int vxs[2] = {vx0, vx1}, vys[2] = {vy0, vy1}, vzs[2] = {vz0, vz1};
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          long long v = (long long)vxs[a] + (long long)g.nv[0] * (vys[b] + (long long)g.nv[1] * vzs[c]);
+          const R* e = Ev + v * EC;
+          R w = wx[a] * wy[b] * wz[c];
+          E[0] += w * e[0];
+          E[1] += w * e[1];
+          E[2] += w * e[2];
+        }
+  }
+}
+
+template <typename R>
+__device__ inline void boris_push(R* v, const R* E, const R* B, R qm, R dt, bool magnetic) {
+  R h = (R)0.5 * dt * qm;
+  R vm0 = v[0] + h * E[0], vm1 = v[1] + h * E[1], vm2 = v[2] + h * E[2];
+  if (magnetic) {
+    R t0 = h * B[0], t1 = h * B[1], t2 = h * B[2];
+    R tt = t0 * t0 + t1 * t1 + t2 * t2;
+    R p0 = vm0 + (vm1 * t2 - vm2 * t1);
+    R p1 = vm1 + (vm2 * t0 - vm0 * t2);
+    R p2 = vm2 + (vm0 * t1 - vm1 * t0);
+    R sc = (R)2 / ((R)1 + tt);
+    R s0 = sc * t0, s1 = sc * t1, s2 = sc * t2;
+    vm0 += p1 * s2 - p2 * s1;
+    vm1 += p2 * s0 - p0 * s2;
+    vm2 += p0 * s1 - p1 * s0;
+  }
+  v[0] = vm0 + h * E[0];
+  v[1] = vm1 + h * E[1];
+  v[2] = vm2 + h * E[2];
+}
+
+// Globalised FP64 inversion for the rare particles that plain Newton does not
+// settle: the physical displacement is split into m equal parts (continuation)
+// so that each part moves the particle by at most a quarter cell in logical
+// space, and each part is solved by Newton from the end of the previous one.
+template <int D, int MAP>
+__device__ __noinline__ bool move_fallback(const Geo& g, const int* idx, const double* f0,
+                                           const double* disp, double* d) {
+  double dt0[3] = {0.0, 0.0, 0.0};
+  double J = 1.0;
+  double est[3] = {0.0, 0.0, 0.0};
+  if (MAP == MAP_SINUSOIDAL)
+    newton_sinusoidal<D, double>(g, idx, f0, disp, est, 0.0, 1, J);
+  else
+    newton_polar<double>(g, idx, f0, disp, est, 0.0, 1, J);
+  double mx = 0.0;
+  for (int a = 0; a < D; ++a) mx = fmax(mx, fabs(est[a]));
+  int m = (int)ceil(mx / 0.25);
+  m = m < 1 ? 1 : (m > 256 ? 256 : m);
+  bool ok = true;
+  for (int k = 0; k < m; ++k) {
+    double fb[3] = {0.0, 0.0, 0.0}, part[3] = {0.0, 0.0, 0.0}, dd[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < D; ++a) {
+      fb[a] = f0[a] + dt0[a];
+      part[a] = disp[a] / m;
+    }
+    bool c;
+    if (MAP == MAP_SINUSOIDAL)
+      c = newton_sinusoidal<D, double>(g, idx, fb, part, dd, 1e-12, 24, J);
+    else
+      c = newton_polar<double>(g, idx, fb, part, dd, 1e-12, 24, J);
+    ok = ok && c;
+    for (int a = 0; a < D; ++a) dt0[a] += dd[a];
+  }
+  for (int a = 0; a < D; ++a) d[a] = dt0[a];
+  return ok;
+}
+
+// Newton on the map increment in the particle's precision.  Falls back to the
+// globalised FP64 solve when it does not converge, and (FP32 only) when the
+// cell is strongly compressed (J < 0.25 in box units).
+template <int D, int MAP, typename R>
+__device__ inline bool move_delta(const Geo& g, const int* idx, const R* f, const R* v, R dt,
+                                  int maxit, R tol, R* d, bool& fallback) {
+  fallback = false;
+  if (MAP == MAP_IDENTITY) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) d[a] = dt * v[a] * (R)(1.0 / g.dxc[a]);
+    return true;
+  }
+  bool conv;
+  R J0 = (R)1;
+  if (MAP == MAP_SINUSOIDAL) {
+    R r[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) r[a] = dt * v[a] * (R)(1.0 / g.dxc[a]);
+    conv = newton_sinusoidal<D, R>(g, idx, f, r, d, tol, maxit, J0);
+  } else {
+    R vdt[2] = {dt * v[0], dt * v[1]};
+    conv = newton_polar<R>(g, idx, f, vdt, d, tol, maxit, J0);
+  }
+  const bool low_j = std::is_same<R, float>::value && J0 < (R)0.25;
+  if (!conv || low_j) {
+    fallback = true;
+    double fd[3] = {(double)f[0], (double)f[1], D == 3 ? (double)f[D - 1] : 0.0};
+    double disp[3] = {0.0, 0.0, 0.0}, dd[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      disp[a] = (MAP == MAP_SINUSOIDAL) ? (double)dt * (double)v[a] / g.dxc[a] : (double)dt * (double)v[a];
+    conv = move_fallback<D, MAP>(g, idx, fd, disp, dd);
+#pragma unroll
+    for (int a = 0; a < D; ++a) d[a] = (R)dd[a];
+  }
+  return conv;
+}
+
+template <typename R>
+struct PartArgs {
+  int32_t* key;
+  R* off0;
+  R* off1;
+  R* off2;
+  R* v0;
+  R* v1;
+  R* v2;
+  const int* item_tile;
+  const int* item_begin;
+  const int* item_end;
+  const int* n_items;
+  const R* Ev;
+  void* Q;
+  Geo g;
+  int pbc_lo[3], pbc_hi[3];
+  R qm, dt;
+  R B[3];
+  int magnetic;
+  int vz_active;
+  int mode;
+  int S1;
+  int newton_maxit;
+  R newton_tol;
+  double ke_scale;
+  double* ke;
+  unsigned long long* counters;
+};
+
+template <int D, int SHAPE, typename R, bool FIXED, typename QT>
+__device__ inline void deposit_particle(const Geo& g, const int* origin, QT* win, void* Qg,
+                                        const int* idx, const R* f, int S1,
+                                        unsigned long long& far) {
+  using TS = TileShape<D>;
+  const int Wd[3] = {TS::W0, TS::W1, TS::W2};
+  int tg[3][3], tl[3][3];
+  QT w[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a >= D) {
+      tg[a][0] = tg[a][2] = 0;
+      tg[a][1] = 0;
+      tl[a][0] = tl[a][1] = tl[a][2] = 0;
+      w[a][0] = w[a][2] = (QT)0;
+      w[a][1] = (QT)1;
+      continue;
+    }
+    if (FIXED) {
+      uint32_t wi[3];
+      weights_fixed<SHAPE>((double)f[a], S1, wi);
+      w[a][0] = (QT)wi[0];
+      w[a][1] = (QT)wi[1];
+      w[a][2] = (QT)wi[2];
+    } else {
+      R wr[3];
+      weights_real<SHAPE, R>(f[a], wr);
+      w[a][0] = (QT)wr[0];
+      w[a][1] = (QT)wr[1];
+      w[a][2] = (QT)wr[2];
+    }
+    const int n = g.n[a];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+      int t = idx[a] + o - 1;
+      if (g.periodic[a]) {
+        if (t < 0) t += n;
+        else if (t >= n) t -= n;
+      } else {
+        t = t < 0 ? 0 : (t >= n ? n - 1 : t);
+      }
+      tg[a][o] = t;
+      int l = t - origin[a] + TS::G;
+      if (g.periodic[a]) {
+        if (l < 0) l += n;
+        else if (l >= Wd[a]) l -= n;
+      }
+      tl[a][o] = l;
+    }
+  }
+  constexpr int NZ = (D == 3) ? 3 : 1;
+#pragma unroll
+  for (int oz = 0; oz < NZ; ++oz) {
+    const int az = (D == 3) ? oz : 1;
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 3; ++ox) {
+        QT val;
+        if (FIXED) {
+          unsigned long long p = (unsigned long long)w[0][ox] * (unsigned long long)w[1][oy];
+          if (D == 3) p *= (unsigned long long)w[2][az];
+          val = (QT)p;
+        } else {
+          val = w[0][ox] * w[1][oy] * w[2][az];
+        }
+        if (val == (QT)0) continue;
+        int lx = tl[0][ox], ly = tl[1][oy], lz = tl[2][az];
+        bool in = lx >= 0 && lx < TS::W0 && ly >= 0 && ly < TS::W1 && lz >= 0 && lz < TS::W2;
+        if (in) {
+          atomicAdd(&win[lx + TS::W0 * (ly + TS::W1 * lz)], val);
+        } else {
+          long long c = (long long)tg[0][ox] + (long long)g.n[0] * (tg[1][oy] + (long long)g.n[1] * tg[2][az]);
+          atomicAdd(&((QT*)Qg)[c], val);
+          ++far;
+        }
+      }
+  }
+}
+
+template <int D, int MAP, int SHAPE, typename R, bool FIXED>
+__global__ __launch_bounds__(256) void particle_kernel(PartArgs<R> a) {
+  using TS = TileShape<D>;
+  typedef typename std::conditional<FIXED, unsigned long long, double>::type QT;
+  __shared__ QT win[TS::WIN];
+  __shared__ double red_d[8];
+  __shared__ unsigned long long red_u[8][5];
+
+  const int item = blockIdx.x;
+  if (item >= *a.n_items) return;
+  const Geo& g = a.g;
+  const int tile = a.item_tile[item];
+  const int begin = a.item_begin[item];
+  const int end = a.item_end[item];
+  int origin[3];
+  origin[0] = (tile % g.nt[0]) * TS::T0;
+  origin[1] = ((tile / g.nt[0]) % g.nt[1]) * TS::T1;
+  origin[2] = (D == 3) ? (tile / (g.nt[0] * g.nt[1])) * TS::T2 : 0;
+
+  const bool deposit = a.mode != MODE_HALFSTEP;
+  if (deposit) {
+    for (int s = threadIdx.x; s < TS::WIN; s += blockDim.x) win[s] = (QT)0;
+    __syncthreads();
+  }
+
+  double ke = 0.0;
+  unsigned long long absorbed = 0, outflow = 0, fallbacks = 0, far = 0, nonconv = 0;
+  R* offs[3] = {a.off0, a.off1, a.off2};
+
+  for (int p = begin + (int)threadIdx.x; p < end; p += (int)blockDim.x) {
+    int key = a.key[p];
+    if (key < 0) continue;
+    int idx[3] = {key_i(key, g), key_j(key, g), (D == 3) ? key_k(key, g) : 0};
+    R f[3];
+    f[0] = a.off0[p];
+    f[1] = a.off1[p];
+    f[2] = (D == 3) ? a.off2[p] : (R)0;
+
+    if (a.mode != MODE_DEPOSIT) {
+      R v[3];
+      v[0] = a.v0[p];
+      v[1] = a.v1[p];
+      v[2] = a.vz_active ? a.v2[p] : (R)0;
+      R E[3];
+      gather_E<D, R>(a.Ev, g, idx, f, E);
+      R vo0 = v[0], vo1 = v[1], vo2 = v[2];
+      boris_push<R>(v, E, a.B, a.qm, a.dt, a.magnetic != 0);
+      a.v0[p] = v[0];
+      a.v1[p] = v[1];
+      if (a.vz_active) a.v2[p] = v[2];
+      if (a.mode == MODE_HALFSTEP) continue;
+      ke += (double)(vo0 * v[0] + vo1 * v[1] + vo2 * v[2]);
+
+      R d[3] = {(R)0, (R)0, (R)0};
+      bool fb = false;
+      bool conv = move_delta<D, MAP, R>(g, idx, f, v, a.dt, a.newton_maxit, a.newton_tol, d, fb);
+      fallbacks += fb ? 1 : 0;
+      nonconv += conv ? 0 : 1;
+      int dead = 0;
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        R u = f[ax] + d[ax];
+        R fl = floor(u);
+        R nf = u - fl;
+        int ni = idx[ax] + (int)fl;
+        if (nf >= (R)1) {
+          nf = (R)0;
+          ni += 1;
+        }
+        const int n = g.n[ax];
+        if (g.periodic[ax]) {
+          ni %= n;
+          if (ni < 0) ni += n;
+        } else if (ni < 0) {
+          dead = (a.pbc_lo[ax] == PBC_ABSORB) ? -1 : -2;
+        } else if (ni >= n) {
+          dead = (a.pbc_hi[ax] == PBC_ABSORB) ? -1 : -2;
+        }
+        idx[ax] = ni;
+        f[ax] = nf;
+      }
+      if (dead) {
+        a.key[p] = dead;
+        absorbed += dead == -1 ? 1 : 0;
+        outflow += dead == -2 ? 1 : 0;
+        continue;
+      }
+      a.key[p] = make_key(idx[0], idx[1], idx[2], g);
+      a.off0[p] = f[0];
+      a.off1[p] = f[1];
+      if (D == 3) a.off2[p] = f[2];
+    }
+    deposit_particle<D, SHAPE, R, FIXED, QT>(g, origin, win, a.Q, idx, f, a.S1, far);
+  }
+  (void)offs;
+
+  if (deposit) {
+    __syncthreads();
+    for (int s = threadIdx.x; s < TS::WIN; s += blockDim.x) {
+      QT val = win[s];
+      if (val == (QT)0) continue;
+      int lx = s % TS::W0;
+      int ly = (s / TS::W0) % TS::W1;
+      int lz = s / (TS::W0 * TS::W1);
+      int l[3] = {lx, ly, lz};
+      int t[3] = {0, 0, 0};
+      bool ok = true;
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        int v = origin[ax] - TS::G + l[ax];
+        const int n = g.n[ax];
+        if (g.periodic[ax]) {
+          while (v < 0) v += n;
+          while (v >= n) v -= n;
+        } else if (v < 0 || v >= n) {
+          ok = false;
+        }
+        t[ax] = v;
+      }
+      if (!ok) continue;
+      long long c = (long long)t[0] + (long long)g.n[0] * (t[1] + (long long)g.n[1] * t[2]);
+      atomicAdd(&((QT*)a.Q)[c], val);
+    }
+  }
+
+  // block sums of the diagnostics
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double kes = wave_sum(ke);
+  unsigned long long cs[5] = {wave_sum_u64(absorbed), wave_sum_u64(outflow), wave_sum_u64(fallbacks),
+                              wave_sum_u64(far), wave_sum_u64(nonconv)};
+  if (lane == 0) {
+    red_d[wv] = kes;
+    for (int i = 0; i < 5; ++i) red_u[wv][i] = cs[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) / 64;
+    double s = 0.0;
+    unsigned long long u[5] = {0, 0, 0, 0, 0};
+    for (int w = 0; w < nw; ++w) {
+      s += red_d[w];
+      for (int i = 0; i < 5; ++i) u[i] += red_u[w][i];
+    }
+    if (a.mode == MODE_PUSH && s != 0.0) atomicAdd(a.ke, s * a.ke_scale);
+    for (int i = 0; i < 5; ++i)
+      if (u[i]) atomicAdd(&a.counters[i], u[i]);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// tile sort
+// ----------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void tile_hist_kernel(const int32_t* __restrict__ key,
+                                                        const int* __restrict__ d_n, int* counts,
+                                                        Geo g) {
+  const int n = *d_n;
+  const int stride = gridDim.x * blockDim.x;
+  for (int p0 = blockIdx.x * blockDim.x; p0 < n; p0 += stride) {
+    int p = p0 + threadIdx.x;
+    bool active = p < n;
+    int t = 0;
+    if (active) {
+      int k = key[p];
+      t = k < 0 ? g.ntiles : tile_of_key<D>(k, g);
+    }
+    agg_inc(counts, t, active);
+  }
+}
+
+// Single workgroup: exclusive scan of the tile counts (dead bin last), work
+// items of at most `chunk` particles per tile, new live count.
+__global__ __launch_bounds__(1024) void tile_scan_kernel(const int* __restrict__ counts, int ntiles,
+                                                         int chunk, int* start, int* cursor,
+                                                         int* n_items, int* item_tile,
+                                                         int* item_begin, int* item_end, int* d_n) {
+  __shared__ long long sp[1024];
+  __shared__ long long si[1024];
+  const int T = blockDim.x;
+  const int tid = threadIdx.x;
+  const int per = (ntiles + T - 1) / T;
+  const int t0 = tid * per;
+  const int t1 = min(ntiles, t0 + per);
+  long long ps = 0, is = 0;
+  for (int t = t0; t < t1; ++t) {
+    int c = counts[t];
+    ps += c;
+    is += (c + chunk - 1) / chunk;
+  }
+  sp[tid] = ps;
+  si[tid] = is;
+  __syncthreads();
+  for (int o = 1; o < T; o <<= 1) {
+    long long a = (tid >= o) ? sp[tid - o] : 0;
+    long long b = (tid >= o) ? si[tid - o] : 0;
+    __syncthreads();
+    sp[tid] += a;
+    si[tid] += b;
+    __syncthreads();
+  }
+  long long pbase = sp[tid] - ps;
+  long long ibase = si[tid] - is;
+  for (int t = t0; t < t1; ++t) {
+    int c = counts[t];
+    start[t] = (int)pbase;
+    cursor[t] = (int)pbase;
+    int k = (c + chunk - 1) / chunk;
+    for (int j = 0; j < k; ++j) {
+      item_tile[ibase + j] = t;
+      item_begin[ibase + j] = (int)(pbase + (long long)j * chunk);
+      item_end[ibase + j] = (int)min(pbase + (long long)(j + 1) * chunk, pbase + c);
+    }
+    pbase += c;
+    ibase += k;
+  }
+  if (tid == T - 1) {
+    long long alive = sp[T - 1];
+    start[ntiles] = (int)alive;
+    cursor[ntiles] = (int)alive;
+    start[ntiles + 1] = (int)(alive + counts[ntiles]);
+    *n_items = (int)si[T - 1];
+    *d_n = (int)alive;
+  }
+}
+
+template <int D, typename R>
+__global__ __launch_bounds__(256) void tile_scatter_kernel(
+    const int* __restrict__ start, int* cursor, Geo g, const int32_t* __restrict__ key_in,
+    int32_t* key_out, const R* __restrict__ o0i, const R* __restrict__ o1i, const R* __restrict__ o2i,
+    R* o0o, R* o1o, R* o2o, const R* __restrict__ v0i, const R* __restrict__ v1i,
+    const R* __restrict__ v2i, R* v0o, R* v1o, R* v2o, const uint32_t* __restrict__ id_in,
+    uint32_t* id_out) {
+  const int n = start[g.ntiles + 1];
+  const int stride = gridDim.x * blockDim.x;
+  for (int p0 = blockIdx.x * blockDim.x; p0 < n; p0 += stride) {
+    int p = p0 + threadIdx.x;
+    bool active = p < n;
+    int k = -1;
+    if (active) k = key_in[p];
+    bool live = active && k >= 0;
+    int t = live ? tile_of_key<D>(k, g) : 0;
+    int dst = agg_inc(cursor, t, live);
+    if (live) {
+      key_out[dst] = k;
+      o0o[dst] = o0i[p];
+      o1o[dst] = o1i[p];
+      if (D == 3) o2o[dst] = o2i[p];
+      v0o[dst] = v0i[p];
+      v1o[dst] = v1i[p];
+      v2o[dst] = v2i[p];
+      if (id_in) id_out[dst] = id_in[p];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// conversions between the ABI's linear cell index and the packed key
+// ----------------------------------------------------------------------------
+__global__ void lin_to_key_kernel(const int32_t* __restrict__ lin, int32_t* key, int n, Geo g,
+                                  int* bad) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int c = lin[p];
+  if (c < 0 || (long long)c >= g.ncells) {
+    key[p] = -1;
+    atomicAdd(bad, 1);
+    return;
+  }
+  int i = c % g.n[0];
+  int j = (c / g.n[0]) % g.n[1];
+  int k = c / (g.n[0] * g.n[1]);
+  key[p] = make_key(i, j, k, g);
+}
+
+__global__ void key_to_lin_kernel(const int32_t* __restrict__ key, int32_t* lin, int n, Geo g) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int k = key[p];
+  lin[p] = k < 0 ? k : key_i(k, g) + g.n[0] * (key_j(k, g) + g.n[1] * key_k(k, g));
+}
+
+__global__ void iota_kernel(uint32_t* id, int n) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) id[p] = (uint32_t)p;
+}
+
+template <typename R>
+__global__ void offsets_check_kernel(const R* __restrict__ o, long long n, int* bad) {
+  long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  R v = o[p];
+  if (!(v >= (R)0 && v < (R)1)) atomicAdd(bad, 1);
+}
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+template <int D, int MAP, int SHAPE, typename R>
+static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
+  PartArgs<R> a;
+  a.key = L.key;
+  a.off0 = (R*)L.off[0];
+  a.off1 = (R*)L.off[1];
+  a.off2 = (R*)L.off[2];
+  a.v0 = (R*)L.vel[0];
+  a.v1 = (R*)L.vel[1];
+  a.v2 = (R*)L.vel[2];
+  a.item_tile = L.item_tile;
+  a.item_begin = L.item_begin;
+  a.item_end = L.item_end;
+  a.n_items = L.n_items;
+  a.Ev = (const R*)L.Ev;
+  a.Q = L.Q;
+  a.g = L.g;
+  for (int i = 0; i < 3; ++i) {
+    a.pbc_lo[i] = L.pbc_lo[i];
+    a.pbc_hi[i] = L.pbc_hi[i];
+    a.B[i] = (R)L.B[i];
+  }
+  a.qm = (R)L.qm;
+  a.dt = (R)L.dt;
+  a.magnetic = L.magnetic;
+  a.vz_active = L.vz_active;
+  a.mode = L.mode;
+  a.S1 = L.S1;
+  a.newton_maxit = L.newton_maxit;
+  a.newton_tol = (R)L.newton_tol;
+  a.ke_scale = L.ke_scale;
+  a.ke = L.ke;
+  a.counters = L.counters;
+  if (L.max_items <= 0) return;
+  constexpr bool FIXED = std::is_same<R, float>::value;
+  hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED>), dim3(L.max_items), dim3(256), 0, st,
+                     a);
+}
+
+template <int D, int MAP, typename R>
+static int launch_particle_shape(const ParticleLaunch& L, hipStream_t st) {
+  if (L.shape == SHAPE_B2)
+    launch_particle_t<D, MAP, SHAPE_B2, R>(L, st);
+  else
+    launch_particle_t<D, MAP, SHAPE_B1, R>(L, st);
+  return 0;
+}
+
+template <typename R>
+static int launch_particle_r(const ParticleLaunch& L, hipStream_t st) {
+  const int D = L.g.dim, M = L.g.kind;
+  if (D == 2) {
+    if (M == MAP_IDENTITY) return launch_particle_shape<2, MAP_IDENTITY, R>(L, st);
+    if (M == MAP_SINUSOIDAL) return launch_particle_shape<2, MAP_SINUSOIDAL, R>(L, st);
+    if (M == MAP_POLAR_LOG) return launch_particle_shape<2, MAP_POLAR_LOG, R>(L, st);
+  } else if (D == 3) {
+    if (M == MAP_IDENTITY) return launch_particle_shape<3, MAP_IDENTITY, R>(L, st);
+    if (M == MAP_SINUSOIDAL) return launch_particle_shape<3, MAP_SINUSOIDAL, R>(L, st);
+  }
+  return -1;
+}
+
+int launch_particles(const ParticleLaunch& L, hipStream_t st) {
+  return L.fp64 ? launch_particle_r<double>(L, st) : launch_particle_r<float>(L, st);
+}
+
+int launch_tile_sort(const SortLaunch& S, hipStream_t st) {
+  const Geo& g = S.g;
+  int blocks = (int)((S.capacity + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  if (g.dim == 2)
+    hipLaunchKernelGGL(tile_hist_kernel<2>, dim3(blocks), dim3(256), 0, st, S.key_in, S.d_n, S.counts, g);
+  else
+    hipLaunchKernelGGL(tile_hist_kernel<3>, dim3(blocks), dim3(256), 0, st, S.key_in, S.d_n, S.counts, g);
+  hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, st, S.counts, g.ntiles, S.chunk, S.start,
+                     S.cursor, S.n_items, S.item_tile, S.item_begin, S.item_end, S.d_n);
+#define SCATTER(DD, RR)                                                                            \
+  hipLaunchKernelGGL((tile_scatter_kernel<DD, RR>), dim3(blocks), dim3(256), 0, st, S.start, S.cursor, \
+                     g, S.key_in, S.key_out, (const RR*)S.off_in[0], (const RR*)S.off_in[1],        \
+                     (const RR*)S.off_in[2], (RR*)S.off_out[0], (RR*)S.off_out[1], (RR*)S.off_out[2], \
+                     (const RR*)S.vel_in[0], (const RR*)S.vel_in[1], (const RR*)S.vel_in[2],          \
+                     (RR*)S.vel_out[0], (RR*)S.vel_out[1], (RR*)S.vel_out[2], S.id_in, S.id_out)
+  if (g.dim == 2) {
+    if (S.fp64) SCATTER(2, double); else SCATTER(2, float);
+  } else {
+    if (S.fp64) SCATTER(3, double); else SCATTER(3, float);
+  }
+#undef SCATTER
+  return 0;
+}
+
+void launch_lin_to_key(const int32_t* lin, int32_t* key, int n, const Geo& g, int* bad,
+                       hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(lin_to_key_kernel, dim3((n + 255) / 256), dim3(256), 0, st, lin, key, n, g, bad);
+}
+void launch_key_to_lin(const int32_t* key, int32_t* lin, int n, const Geo& g, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(key_to_lin_kernel, dim3((n + 255) / 256), dim3(256), 0, st, key, lin, n, g);
+}
+void launch_iota(uint32_t* id, int n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, st, id, n);
+}
+void launch_offsets_check(const void* o, long long n, int fp64, int* bad, hipStream_t st) {
+  if (n <= 0) return;
+  unsigned blocks = (unsigned)((n + 255) / 256);
+  if (fp64)
+    hipLaunchKernelGGL(offsets_check_kernel<double>, dim3(blocks), dim3(256), 0, st, (const double*)o, n, bad);
+  else
+    hipLaunchKernelGGL(offsets_check_kernel<float>, dim3(blocks), dim3(256), 0, st, (const float*)o, n, bad);
+}
+
+}  // namespace cpic

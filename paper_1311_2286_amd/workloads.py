@@ -273,6 +273,14 @@ def generate_species(case: Case, sid: int, dtype=np.float32, count: Optional[int
     return dict(cell=cell, off=off, vel=vel, id=np.arange(ntot, dtype=np.uint32))
 
 
+def as_dtype(p, dtype):
+    """The same particles with offsets / velocities in `dtype`; offsets that
+    round up to 1 in the narrower type are kept just below 1."""
+    off = p["off"].astype(dtype)
+    np.minimum(off, np.nextafter(dtype(1.0), dtype(0.0)), out=off)
+    return dict(cell=p["cell"], off=off, vel=p["vel"].astype(dtype), id=p["id"])
+
+
 def to_oracle(p):
     """SoA generator arrays -> (n, 3) float64 arrays (exact widening)."""
     n = p["cell"].size

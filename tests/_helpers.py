@@ -1,0 +1,67 @@
+"""Shared helpers of the GPU tests: build a library simulation and the oracle
+from the same seeded workload."""
+import numpy as np
+
+import oracle as O
+from paper_1311_2286_amd import workloads as W
+
+
+def gpu_sim(case, precision=0, shape=2, track_ids=True, mg_rtol=1e-12, mg_max_cycles=80,
+            sort_every=1, count=None, capacity_factor=1.0):
+    from paper_1311_2286_amd import cpic as C
+    dt = np.float64 if precision == C.FP64 else np.float32
+    pbc_lo = tuple(0 if b == 0 else C.PBC_ABSORB for b in case.bc_lo)
+    pbc_hi = tuple(0 if b == 0 else C.PBC_OUTFLOW for b in case.bc_hi)
+    sim = C.Sim(case.map_kind, case.dim, case.n, L=case.L, eps=case.eps, r_in=case.r_in,
+                r_out=case.r_out, bc_lo=case.bc_lo, bc_hi=case.bc_hi, phi_lo=case.phi_lo,
+                phi_hi=case.phi_hi, shape=shape, precision=precision, dt=case.dt, B0=case.B,
+                background=case.background, mg_rtol=mg_rtol, mg_max_cycles=mg_max_cycles,
+                sort_every=sort_every, track_ids=track_ids)
+    parts = []
+    for sid, s in enumerate(case.species):
+        p = W.generate_species(case, sid, dtype=dt, count=count)
+        cap = max(1, int(p["cell"].size * capacity_factor))
+        sim.add_species(s.q, s.m, case.weight(s) if count is None else case.weight(s),
+                        cap, pbc_lo=pbc_lo, pbc_hi=pbc_hi)
+        sim.set_particles(sid, p["cell"], p["off"], p["vel"], p["id"])
+        parts.append(p)
+    return sim, parts
+
+
+def oracle_objects(case):
+    return O.make_map(**case.map_args()), O.make_grid(**case.grid_args())
+
+
+def oracle_species(case, parts):
+    sp = []
+    for sid, s in enumerate(case.species):
+        sp.append(dict(q=s.q, m=s.m, w=case.weight(s), **W.to_oracle(parts[sid])))
+    return sp
+
+
+def by_id(g):
+    o = np.argsort(g["id"], kind="stable")
+    return dict(cell=g["cell"][o], off=g["off"][:, o], vel=g["vel"][:, o], id=g["id"][o])
+
+
+def logical_cells(case, cell, off):
+    """(n_particles, dim) positions in cell units (i + f, ...) from linear cell
+    index and offsets given as (dim, n) or (n, 3)."""
+    d = case.dim
+    if off.shape[0] != d and off.shape[-1] == 3:
+        off = off[:, :d].T
+    pos = np.zeros((cell.size, d))
+    c = cell.astype(np.int64)
+    for a in range(d):
+        pos[:, a] = c % case.n[a] + off[a]
+        c = c // case.n[a]
+    return pos
+
+
+def periodic_diff(case, a, b):
+    d = a - b
+    for ax in range(case.dim):
+        if case.bc_lo[ax] == 0:
+            n = case.n[ax]
+            d[:, ax] -= np.round(d[:, ax] / n) * n
+    return d

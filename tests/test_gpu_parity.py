@@ -1,0 +1,299 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bars (written in each test):
+  - deposit, FP32 path: bit-exact (integer weights, order-free sums);
+  - deposit, FP64 path: 1e-12 of the largest cell value (FP64 atomics reorder);
+  - charge: 1e-14 relative; potential: 1e-8 of max |phi| (both solves at
+    residual 1e-12 / 1e-13);
+  - vertex field: 1e-6 of max |E| (FP32 storage), 1e-10 (FP64);
+  - one push from identical states, FP32: positions 2e-5 cell, velocities
+    2e-5 (|v| + |q/m E dt|); FP64: 1e-9 cell, 1e-11.
+Grids are ragged (not multiples of the 16x16 / 8x8x8 tiles) and span several
+tiles; tiny grids exercise the deposit window wrapping onto itself."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1311_2286_amd import workloads as W
+from _helpers import gpu_sim, oracle_objects, oracle_species, by_id, logical_cells, periodic_diff
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def C():
+    from paper_1311_2286_amd import cpic
+    return cpic
+
+
+CASES = {
+    "2d_sin": lambda: W.small_case(dim=2, n=(40, 24), ppc=8.0),
+    "3d_sin": lambda: W.small_case(dim=3, n=(20, 12, 16), ppc=4.0),
+    "2d_tiny": lambda: W.small_case(dim=2, n=(6, 4), L=(6.0, 4.0), ppc=20.0),
+    "3d_tiny": lambda: W.small_case(dim=3, n=(4, 6, 2), L=(4.0, 6.0, 2.0), ppc=20.0),
+    "2d_id": lambda: W.small_case(dim=2, map_kind=W.IDENTITY, n=(33, 18), eps=0.0, ppc=6.0),
+    "3d_mag": lambda: W.small_case(dim=3, n=(16, 16, 10), ppc=4.0, B=(0.0, 0.0, 2.0)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("shape", [2, 1])
+def test_deposit_fp32_bit_exact(name, shape):
+    case = CASES[name]()
+    sim, parts = gpu_sim(case, precision=0, shape=shape)
+    sim.stage(C().STAGE_DEPOSIT)
+    g = O.make_grid(**case.grid_args())
+    S1 = 24 if case.dim == 2 else 16
+    for sid in range(len(case.species)):
+        Qg = sim.get_field(C().FIELD_Q, sid)
+        o = W.to_oracle(parts[sid])
+        Qo = O.deposit_fixed(g, shape, S1, o["cell"], o["off"])
+        assert np.array_equal(Qg, Qo), (name, sid, int(np.sum(Qg != Qo)))
+        total = sum(int(q) for q in Qg)
+        assert total == parts[sid]["cell"].size << (case.dim * S1)
+    d = sim.diag()
+    for sid in range(len(case.species)):
+        assert C().qsum(d, sid) == parts[sid]["cell"].size << (case.dim * S1)
+    sim.close()
+
+
+@pytest.mark.parametrize("name", ["2d_sin", "3d_sin"])
+def test_deposit_fp64(name):
+    case = CASES[name]()
+    sim, parts = gpu_sim(case, precision=1)
+    sim.stage(C().STAGE_DEPOSIT)
+    g = O.make_grid(**case.grid_args())
+    for sid in range(len(case.species)):
+        Qg = sim.get_field(C().FIELD_Q, sid)
+        o = W.to_oracle(parts[sid])
+        Qo = O.deposit_f64(g, 2, o["cell"], o["off"])
+        assert np.max(np.abs(Qg - Qo)) <= 1e-12 * np.max(np.abs(Qo))
+    sim.close()
+
+
+def test_empty_species_and_input_validation():
+    case = CASES["2d_sin"]()
+    sim, parts = gpu_sim(case, precision=0)
+    sim.set_particles(1, np.zeros(0, np.int32), np.zeros((2, 0), np.float32),
+                      np.zeros((3, 0), np.float32))
+    sim.stage(C().STAGE_DEPOSIT)
+    assert not np.any(sim.get_field(C().FIELD_Q, 1))
+    bad = parts[0]["cell"].copy()
+    bad[5] = case.ncells
+    with pytest.raises(C().CpicError):
+        sim.set_particles(0, bad, parts[0]["off"], parts[0]["vel"])
+    off = parts[0]["off"].copy()
+    off[0, 3] = 1.0
+    with pytest.raises(C().CpicError):
+        sim.set_particles(0, parts[0]["cell"], off, parts[0]["vel"])
+    sim.close()
+
+
+@pytest.mark.parametrize("name", ["2d_sin", "3d_sin", "2d_id"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_charge_solve_and_field(name, precision):
+    case = CASES[name]()
+    sim, parts = gpu_sim(case, precision=precision, mg_rtol=1e-12)
+    sim.stage(C().STAGE_DEPOSIT)
+    sim.stage(C().STAGE_CHARGE)
+    sim.stage(C().STAGE_SOLVE)
+    sim.stage(C().STAGE_EFIELD)
+    m, g = oracle_objects(case)
+    sp = oracle_species(case, parts)
+    osim = O.OracleSim(m, g, sp, dt=case.dt, deposit="fixed" if precision == 0 else "f64",
+                       rtol=1e-13)
+    osim.deposit()
+    ch = sim.get_field(C().FIELD_CHARGE)
+    assert np.max(np.abs(ch - osim.charge)) <= 1e-14 * np.max(np.abs(osim.charge)) + 1e-300
+    osim.solve()
+    phi = sim.get_field(C().FIELD_PHI)
+    assert np.max(np.abs(phi - osim.phi)) <= 1e-8 * np.max(np.abs(osim.phi))
+    d = sim.diag()
+    assert d.mg_relres <= 1e-12 and d.mg_cycles > 0
+    Ev = sim.get_field(C().FIELD_EV)[:, : case.dim].astype(np.float64)
+    tol = 1e-6 if precision == 0 else 1e-10
+    Emax = np.max(np.abs(osim.Ev))
+    assert np.max(np.abs(Ev - osim.Ev[:, : case.dim])) <= tol * Emax
+    sim.close()
+
+
+def test_probe_vacuum_solution():
+    # polar-log annulus with walls at -5 and 0 and no charge: phi = -5 (1 - xi)
+    case = W.Case("probe_small", 2, W.POLAR_LOG, (48, 40), r_in=1.0, r_out=60.0,
+                  bc_lo=(1, 0), bc_hi=(1, 0), phi_lo=(-5.0, 0.0), phi_hi=(0.0, 0.0),
+                  species=[W.electrons(1.0, 1.0)], case_id=7)
+    sim, parts = gpu_sim(case, precision=0, mg_rtol=1e-13)
+    sim.set_field(C().FIELD_CHARGE, np.zeros(case.ncells))
+    sim.stage(C().STAGE_SOLVE)
+    phi = sim.get_field(C().FIELD_PHI)
+    xi = (np.arange(case.ncells) % 48 + 0.5) / 48
+    assert np.max(np.abs(phi + 5 * (1 - xi))) < 1e-9
+    sim.stage(C().STAGE_EFIELD)
+    Ev = sim.get_field(C().FIELD_EV).astype(np.float64)
+    vi = np.arange(49 * 40)
+    xv = np.zeros((vi.size, 3))
+    xv[:, 0] = (vi % 49) / 48
+    xv[:, 1] = (vi // 49) / 40
+    m = O.make_map(**case.map_args())
+    x, *_ = O.map_eval(m, xv)
+    r = np.hypot(x[:, 0], x[:, 1])
+    Er = -5 / (r * math.log(60.0))
+    assert np.max(np.abs(Ev[:, 0] - Er * x[:, 0] / r)) < 1e-5 * np.max(np.abs(Er))
+    sim.close()
+
+
+def _push_compare(case, precision, shape=2, expect_fallback=False):
+    sim, parts = gpu_sim(case, precision=precision, shape=shape)
+    nv = sim.field_bytes(C().FIELD_EV) // (4 if precision == 0 else 8) // (4 if case.dim == 3 else 2)
+    E = W.synthetic_ev(case, nv, dtype=np.float64 if precision else np.float32)
+    ec = 4 if case.dim == 3 else 2
+    Ebuf = np.zeros((nv, ec), dtype=E.dtype)
+    Ebuf[:, : case.dim] = E[:, : case.dim]
+    sim.set_field(C().FIELD_EV, Ebuf)
+    sim.stage(C().STAGE_PUSH)
+    m, g = oracle_objects(case)
+    E64 = np.zeros((nv, 3))
+    E64[:, : case.dim] = Ebuf[:, : case.dim].astype(np.float64)
+    for sid, s in enumerate(case.species):
+        o = W.to_oracle(parts[sid])
+        cell, off, vel, cnt = O.push(m, g, s.q / s.m, case.dt, case.B, o["cell"], o["off"],
+                                     o["vel"], E64)
+        got = by_id(sim.get_particles(sid))
+        assert got["cell"].size == cell.size
+        pg = logical_cells(case, got["cell"], got["off"].astype(np.float64))
+        po = logical_cells(case, cell, off)
+        dpos = np.abs(periodic_diff(case, pg, po))
+        vg = got["vel"].T.astype(np.float64)
+        Eo = O.gather(g, E64, o["cell"], o["off"])
+        scale = np.abs(o["vel"]) + np.abs(s.q / s.m * Eo * case.dt)
+        dv = np.abs(vg - vel)
+        if case.dim == 2 and not any(case.B):
+            dv[:, 2] = 0.0  # v_z is not advanced without a magnetic field in 2D
+        if precision == 0:
+            assert dpos.max() < 2e-5, dpos.max()
+            assert np.all(dv <= 2e-5 * (scale + 1e-3)), (dv / (scale + 1e-3)).max()
+        else:
+            assert dpos.max() < 1e-9, dpos.max()
+            assert np.all(dv <= 1e-11 * (scale + 1e-3)), (dv / (scale + 1e-3)).max()
+    d = sim.diag()
+    assert d.newton_failed == 0
+    if expect_fallback is not None:
+        assert (d.newton_fallback > 0) == expect_fallback
+    # total deposited charge is exact after the move
+    if precision == 0:
+        S1 = 24 if case.dim == 2 else 16
+        for sid in range(len(case.species)):
+            assert C().qsum(d, sid) == parts[sid]["cell"].size << (case.dim * S1)
+    sim.close()
+
+
+@pytest.mark.parametrize("name", ["2d_sin", "3d_sin", "2d_id", "3d_mag", "2d_tiny"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_push_one_step(name, precision):
+    _push_compare(CASES[name](), precision)
+
+
+def test_push_strong_distortion_and_fast_particles():
+    # eps = 0.15 (J_min = 0.057), thermal speed 8: particles cross several
+    # cells per step and the FP32 Newton must still hold its tolerance.
+    case = W.small_case(dim=2, n=(40, 24), eps=0.15, ppc=6.0, L=(1.0, 1.0), vth_e=0.2)
+    _push_compare(case, 0, expect_fallback=True)
+    _push_compare(case, 1, expect_fallback=None)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_initialize_and_three_steps(precision):
+    case = W.small_case(dim=2, n=(40, 24), ppc=8.0, background=False)
+    sim, parts = gpu_sim(case, precision=precision)
+    m, g = oracle_objects(case)
+    sp = oracle_species(case, parts)
+    # without a magnetic field the 2D push leaves v_z alone and the library's
+    # kinetic energy sums the advanced components only
+    osim = O.OracleSim(m, g, sp, dt=case.dt, deposit="fixed" if precision == 0 else "f64",
+                       rtol=1e-13, ke_axes=2)
+    sim.initialize()
+    osim.initialize()
+    for k in range(3):
+        sim.step(1)
+        osim.step()
+        phi = sim.get_field(C().FIELD_PHI)
+        rel = np.max(np.abs(phi - osim.phi)) / np.max(np.abs(osim.phi))
+        assert rel < (1e-4 if precision == 0 else 1e-8), (k, rel)
+        for sid in range(len(case.species)):
+            got = by_id(sim.get_particles(sid))
+            o = osim.sp[sid]
+            dpos = np.abs(periodic_diff(case, logical_cells(case, got["cell"], got["off"].astype(float)),
+                                        logical_cells(case, o["cell"], o["off"])))
+            assert dpos.max() < (1e-4 if precision == 0 else 1e-9), (k, dpos.max())
+        d = sim.diag()
+        rel_ke = abs(d.kinetic - osim.ke) / abs(osim.ke)
+        assert rel_ke < (1e-5 if precision == 0 else 1e-10), rel_ke
+    sim.close()
+
+
+def test_determinism_and_permutation_invariance():
+    case = CASES["3d_sin"]()
+    sim, parts = gpu_sim(case, precision=0)
+    sim.initialize()
+    sim.step(3)
+    Q1 = [sim.get_field(C().FIELD_Q, s) for s in range(2)]
+    P1 = [by_id(sim.get_particles(s)) for s in range(2)]
+    sim.close()
+    sim2, parts2 = gpu_sim(case, precision=0)
+    # same particles in a different order
+    for sid, p in enumerate(parts2):
+        perm = np.random.default_rng(sid).permutation(p["cell"].size)
+        sim2.set_particles(sid, p["cell"][perm], p["off"][:, perm], p["vel"][:, perm], p["id"][perm])
+    sim2.initialize()
+    sim2.step(3)
+    for s in range(2):
+        assert np.array_equal(Q1[s], sim2.get_field(C().FIELD_Q, s))
+        P2 = by_id(sim2.get_particles(s))
+        for k in ("cell", "off", "vel"):
+            assert np.array_equal(P1[s][k], P2[k])
+    sim2.close()
+
+
+def fit_frequency(a, dt):
+    t = np.arange(a.size) * dt
+    best = None
+    for w in np.linspace(0.9, 1.1, 4001):
+        M = np.stack([np.cos(w * t), np.sin(w * t), np.ones_like(t)], axis=1)
+        coef, *_ = np.linalg.lstsq(M, a, rcond=None)
+        r = np.sum((M @ coef - a) ** 2)
+        if best is None or r < best[0]:
+            best = (r, w)
+    return best[1]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cold_langmuir_frequency(precision):
+    case = W.case1_cold()
+    sim, parts = gpu_sim(case, precision=precision, track_ids=False, mg_rtol=1e-11)
+    sim.initialize()
+    m, g = oracle_objects(case)
+    n = case.n
+    xi = np.zeros((case.ncells, 3))
+    ii = np.arange(case.ncells)
+    xi[:, 0] = (ii % n[0] + 0.5) / n[0]
+    xi[:, 1] = (ii // n[0] + 0.5) / n[1]
+    x, _, _, J = O.map_eval(m, xi)
+    wgt = np.cos(2 * np.pi * x[:, 0]) * J / case.ncells
+    amps = [float(np.dot(sim.get_field(C().FIELD_PHI), wgt))]
+    for _ in range(case.steps):
+        sim.step(1)
+        amps.append(float(np.dot(sim.get_field(C().FIELD_PHI), wgt)))
+    w = fit_frequency(np.array(amps), case.dt)
+    w_lf = 20 * math.asin(0.05)
+    assert abs(w / w_lf - 1) < 0.01, w
+    sim.close()
