@@ -99,7 +99,8 @@ enum {
   CPIC_STAGE_SOLVE = 3,    /* phi <- multigrid solve from charge */
   CPIC_STAGE_EFIELD = 4,   /* E_v <- -k^T D phi at vertices */
   CPIC_STAGE_PUSH = 5,     /* gather + push + map inversion + boundaries + deposit */
-  CPIC_STAGE_HALFSTEP = 6  /* v <- Boris(v, E, B, -dt/2): initial velocity push-back */
+  CPIC_STAGE_HALFSTEP = 6, /* v <- Boris(v, E, B, -dt/2): initial velocity push-back */
+  CPIC_STAGE_INJECT = 7    /* this step's flux injection (appends, deposits into Q_s) */
 };
 
 typedef struct {
@@ -137,6 +138,14 @@ typedef struct {
   double q, m, w;       /* charge, mass, macro-weight */
   int pbc_lo[3], pbc_hi[3];
   size_t capacity;      /* maximum particle count */
+  /* Maxwellian-at-rest flux injection through the upper face of axis 0 (the
+     outer wall; Sec. III, Test A/B injection): inject != 0 enables it, with
+     density inject_n0 and thermal speed inject_vth; the random stream is
+     Philox4x32-10 keyed by seed.  Needs a bounded axis 0 and an orthogonal
+     map (identity or polar-log). */
+  int inject;
+  double inject_n0, inject_vth;
+  uint64_t seed;
 } cpic_species_desc;
 
 typedef struct {
@@ -154,6 +163,7 @@ typedef struct {
   long long newton_fallback; /* cumulative FP64 fallbacks in FP32 Newton */
   long long far_deposits;    /* cumulative deposits outside the tile window */
   long long newton_failed;   /* cumulative position updates that missed the tolerance */
+  long long injected[8];     /* cumulative injected particles per species */
 } cpic_diag;
 
 /* Create a simulation on the current HIP device.  hip_stream may be NULL

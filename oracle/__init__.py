@@ -102,6 +102,11 @@ def lib():
         L.or_push.argtypes = [P(Map), P(Grid), d, d, P(d), lg, P(i32), P(d), P(d), P(d), P(lg)]
         L.or_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
         L.or_num_threads.restype = ctypes.c_int
+        L.or_face_area.argtypes = [P(Map)]
+        L.or_face_area.restype = d
+        L.or_inject.argtypes = [P(Map), P(Grid), d, d, d, d, u32, u32, u32, u32, lg, P(i32), P(d),
+                                P(d), P(lg)]
+        L.or_inject.restype = lg
         _lib_handle = L
     return _lib_handle
 
@@ -293,6 +298,23 @@ def push(m: Map, g: Grid, qm, dt, B, cell, off, vel, Ev):
     return cell, off, vel, (counts[0], counts[1])
 
 
+def face_area(m: Map) -> float:
+    return float(lib().or_face_area(ctypes.byref(m)))
+
+
+def inject(m: Map, g: Grid, n0, vth, w, dt, seed, step, species, cap=1 << 20):
+    """Particles injected through the upper face of axis 0 in one step:
+    (cell, off (n,3), vel (n,3), number drawn)."""
+    cell = np.zeros(cap, dtype=np.int32)
+    off = np.zeros((cap, 3))
+    vel = np.zeros((cap, 3))
+    drawn = ctypes.c_long(0)
+    n = lib().or_inject(ctypes.byref(m), ctypes.byref(g), n0, vth, w, dt, seed & 0xFFFFFFFF,
+                        (seed >> 32) & 0xFFFFFFFF, step, species, cap, _p(cell, ctypes.c_int32),
+                        _p(off, ctypes.c_double), _p(vel, ctypes.c_double), ctypes.byref(drawn))
+    return cell[:n].copy(), off[:n].copy(), vel[:n].copy(), drawn.value
+
+
 def num_threads() -> int:
     return int(lib().or_num_threads())
 
@@ -380,6 +402,18 @@ class OracleSim:
             k = self.ke_axes
             ke += 0.5 * s["m"] * s["w"] * float(np.sum(v_old[alive, :k] * s["vel"][alive, :k]))
             self.counts.append(cnt)
+            # drop particles that left, then append this step's injection
+            s["cell"], s["off"], s["vel"] = s["cell"][alive], s["off"][alive], s["vel"][alive]
+            inj = s.get("inject")
+            if inj is not None:
+                c, o, v, _ = inject(self.m, self.g, inj["n0"], inj["vth"], s["w"], self.dt,
+                                    inj["seed"], self.step_count, inj["sid"])
+                s["cell"] = np.concatenate([s["cell"], c])
+                s["off"] = np.concatenate([s["off"], o])
+                s["vel"] = np.concatenate([s["vel"], v])
+                s["injected"] = s.get("injected", 0) + c.size
+            s["absorbed"] = s.get("absorbed", 0) + cnt[0]
+            s["outflow"] = s.get("outflow", 0) + cnt[1]
         self.ke = ke
         self.deposit()
         self.solve()

@@ -1039,3 +1039,80 @@ int or_num_threads(void) {
   return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Injection of a Maxwellian at rest through the upper face of axis 0 (the   */
+/* outer wall), Sec. III: per step lambda = n0 v_th / sqrt(2 pi) * A dt / w   */
+/* particles on average (one-sided Maxwellian flux through a face of area A), */
+/* count = floor(lambda) + Bernoulli(frac lambda).  Each particle: uniform    */
+/* tangential logical position, inward normal speed v_th sqrt(-2 ln u)        */
+/* (flux-weighted half-Maxwellian), tangential components N(0, v_th^2) by     */
+/* Box-Muller, then a free flight over a uniform fraction of the step from    */
+/* the face.  Random numbers: Philox4x32-10, key (seed_lo, seed_hi), counter  */
+/* (step, k, species, purpose); u = (r + 1/2) 2^-32.                          */
+/* ------------------------------------------------------------------------ */
+
+static double u01(uint32_t r) { return ((double)r + 0.5) * (1.0 / 4294967296.0); }
+
+double or_face_area(const or_map* m) {
+  if (m->kind == OR_POLAR_LOG) return 2.0 * OR_PI * m->r_out;
+  double A = 1.0;
+  for (int b = 1; b < m->dim; ++b) A *= m->L[b];
+  return A;
+}
+
+long or_inject(const or_map* m, const or_grid* g, double n0, double vth, double w, double dt,
+               uint32_t seed_lo, uint32_t seed_hi, uint32_t step, uint32_t species, long cap,
+               int32_t* cell, double* off, double* vel, long* drawn) {
+  int d = g->dim;
+  double lam = n0 * vth / sqrt(2.0 * OR_PI) * or_face_area(m) * dt / w;
+  uint32_t key[2] = {seed_lo, seed_hi};
+  uint32_t c0[4] = {step, 0xFFFFFFFFu, species, 2u}, r[4];
+  or_philox4x32_10(c0, key, r);
+  long count = (long)floor(lam) + (u01(r[0]) < lam - floor(lam) ? 1 : 0);
+  if (drawn) *drawn = count;
+  long out = 0;
+  for (long k = 0; k < count && out < cap; ++k) {
+    uint32_t ca[4] = {step, (uint32_t)k, species, 0u}, cb[4] = {step, (uint32_t)k, species, 1u};
+    uint32_t ra[4], rb[4];
+    or_philox4x32_10(ca, key, ra);
+    or_philox4x32_10(cb, key, rb);
+    double xi_f[3] = {1.0, u01(ra[0]), (d == 3) ? u01(rb[1]) : 0.0};
+    double vn = vth * sqrt(-2.0 * log(u01(ra[1])));
+    double rho = sqrt(-2.0 * log(u01(ra[2])));
+    double t1 = vth * rho * cos(2.0 * OR_PI * u01(ra[3]));
+    double t2 = vth * rho * sin(2.0 * OR_PI * u01(ra[3]));
+    double frac = u01(rb[0]);
+    double xf[3], j[3][3];
+    map_x_jac(m, xi_f, xf, j);
+    /* orthonormal frame of the (orthogonal) map at the face: columns of j */
+    double e[3][3];
+    for (int b = 0; b < 3; ++b) {
+      double nrm = 0.0;
+      for (int a = 0; a < 3; ++a) nrm += j[a][b] * j[a][b];
+      nrm = sqrt(nrm);
+      for (int a = 0; a < 3; ++a) e[b][a] = j[a][b] / nrm;
+    }
+    double v[3];
+    for (int a = 0; a < 3; ++a) v[a] = -vn * e[0][a] + t1 * e[1][a];
+    if (d == 2)
+      v[2] += t2;
+    else
+      for (int a = 0; a < 3; ++a) v[a] += t2 * e[2][a];
+    double xt[3];
+    for (int a = 0; a < 3; ++a) xt[a] = (a < d) ? xf[a] + frac * dt * v[a] : 0.0;
+    double xi[3];
+    map_invert(m, xt, xi_f, xi);
+    int wa = -1;
+    int32_t c;
+    double o[3];
+    if (place(g, xi, &c, o, &wa) != 0) continue;
+    cell[out] = c;
+    for (int a = 0; a < 3; ++a) {
+      off[3 * out + a] = o[a];
+      vel[3 * out + a] = v[a];
+    }
+    ++out;
+  }
+  return out;
+}

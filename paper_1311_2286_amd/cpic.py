@@ -21,7 +21,8 @@ PBC_PERIODIC, PBC_ABSORB, PBC_OUTFLOW = 0, 1, 2
 SHAPE_B1, SHAPE_B2 = 1, 2
 FP32, FP64 = 0, 1
 FIELD_Q, FIELD_CHARGE, FIELD_PHI, FIELD_EV, FIELD_JC, FIELD_RHO, FIELD_BACKGROUND = range(7)
-STAGE_SORT, STAGE_DEPOSIT, STAGE_CHARGE, STAGE_SOLVE, STAGE_EFIELD, STAGE_PUSH, STAGE_HALFSTEP = range(7)
+(STAGE_SORT, STAGE_DEPOSIT, STAGE_CHARGE, STAGE_SOLVE, STAGE_EFIELD, STAGE_PUSH, STAGE_HALFSTEP,
+ STAGE_INJECT) = range(8)
 
 EXPORTED = ["cpic_create", "cpic_add_species", "cpic_set_particles", "cpic_get_particles",
             "cpic_initialize", "cpic_step", "cpic_run_stage", "cpic_get_field", "cpic_set_field",
@@ -47,7 +48,9 @@ class GridDesc(ctypes.Structure):
 class SpeciesDesc(ctypes.Structure):
     _fields_ = [("q", ctypes.c_double), ("m", ctypes.c_double), ("w", ctypes.c_double),
                 ("pbc_lo", ctypes.c_int * 3), ("pbc_hi", ctypes.c_int * 3),
-                ("capacity", ctypes.c_size_t)]
+                ("capacity", ctypes.c_size_t), ("inject", ctypes.c_int),
+                ("inject_n0", ctypes.c_double), ("inject_vth", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
 
 
 class Allocator(ctypes.Structure):
@@ -63,7 +66,8 @@ class Diag(ctypes.Structure):
                 ("count", ctypes.c_longlong * 8), ("absorbed", ctypes.c_longlong * 8),
                 ("outflow", ctypes.c_longlong * 8), ("qsum_lo", ctypes.c_uint64 * 8),
                 ("qsum_hi", ctypes.c_uint64 * 8), ("newton_fallback", ctypes.c_longlong),
-                ("far_deposits", ctypes.c_longlong), ("newton_failed", ctypes.c_longlong)]
+                ("far_deposits", ctypes.c_longlong), ("newton_failed", ctypes.c_longlong),
+                ("injected", ctypes.c_longlong * 8)]
 
 
 _lib = None
@@ -204,10 +208,14 @@ class Sim:
         return int(np.prod(self.n))
 
     # ---------------------------------------------------------------- species
-    def add_species(self, q, m, w, capacity, pbc_lo=(0, 0, 0), pbc_hi=(0, 0, 0)):
+    def add_species(self, q, m, w, capacity, pbc_lo=(0, 0, 0), pbc_hi=(0, 0, 0), inject=None,
+                    seed=0):
+        """inject: None or dict(n0=..., vth=...) for flux injection at the outer wall."""
         pad = lambda t: tuple(t)[:3] + (0,) * (3 - len(tuple(t)[:3]))
+        inj = inject or {}
         d = SpeciesDesc(q, m, w, (ctypes.c_int * 3)(*pad(pbc_lo)), (ctypes.c_int * 3)(*pad(pbc_hi)),
-                        int(capacity))
+                        int(capacity), int(inject is not None), float(inj.get("n0", 0.0)),
+                        float(inj.get("vth", 0.0)), int(seed))
         sid = ctypes.c_int()
         self._check(self.lib.cpic_add_species(self.h, ctypes.byref(d), ctypes.byref(sid)),
                     "add_species")

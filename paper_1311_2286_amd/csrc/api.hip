@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/cpic.h"
+#include "cpic.h"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -40,7 +40,11 @@ struct Species {
   int* item_begin = nullptr;
   int* item_end = nullptr;
   int max_items = 0;
-  unsigned long long* counters = nullptr;  // absorbed, outflow, fallback, far, nonconv
+  // absorbed, outflow, fallback, far, nonconv, injected, dropped, ids issued
+  unsigned long long* counters = nullptr;
+  double inject_lam = 0.0;
+  int* fb_queue = nullptr;  // particles handed to the FP64 fallback kernel
+  int* fb_count = nullptr;
 };
 
 struct StepEvents {
@@ -60,6 +64,7 @@ struct cpic_sim {
   std::vector<Species> sp;
   int S1 = 24;
   int chunk = 4096;
+  double kappa = 0.0;  // Newton quadratic-convergence constant of the map (cells)
   bool initialized = false;
   bool poisoned = false;
   bool sorted_dirty = true;
@@ -184,6 +189,31 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   s->stream = (hipStream_t)hip_stream;
   s->S1 = (d == 2) ? 24 : 16;
   s->chunk = (d == 2) ? 4096 : 16384;
+  {
+    // Newton on the map increment converges quadratically: the error after a
+    // step s is at most kappa s^2 with kappa = (max |F''|) / 2 * max |F'^{-1}|
+    // (max-norms over the domain, in cells).  Sinusoidal: entries of F'' are
+    // bounded by e_max (2 pi / n_min)^2, |F'^{-1}| by 1 + 2 pi |eps| d n_max /
+    // (n_min J_min).  Polar-log: second derivatives ~ k_max^2, inverse ~ 1/k_min
+    // with k = (ln R / n0, 2 pi / n1).
+    int nmin = grid->n[0], nmax = grid->n[0];
+    for (int a = 1; a < d; ++a) {
+      nmin = std::min(nmin, grid->n[a]);
+      nmax = std::max(nmax, grid->n[a]);
+    }
+    if (map->kind == CPIC_MAP_SINUSOIDAL) {
+      double bound = (d == 2) ? 1.0 : 2.0 / sqrt(3.0);
+      double jmin = 1.0 - 2.0 * M_PI * fabs(map->eps) * bound;
+      double emax = fabs(map->eps) * nmax;
+      double w = 2.0 * M_PI / nmin;
+      double cinv = 1.0 + 2.0 * M_PI * fabs(map->eps) * d * (double)nmax / ((double)nmin * jmin);
+      s->kappa = 0.5 * d * d * emax * w * w * cinv;
+    } else if (map->kind == CPIC_MAP_POLAR_LOG) {
+      double kx = log(map->r_out / map->r_in) / grid->n[0], ky = 2.0 * M_PI / grid->n[1];
+      double kmax = std::max(kx, ky), kmin = std::min(kx, ky);
+      s->kappa = 0.5 * d * d * kmax * kmax / kmin;
+    }
+  }
 
   Geo& g = s->g;
   memset(&g, 0, sizeof(g));
@@ -355,9 +385,25 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
         return fail(s, CPIC_E_ARG, "particle bc must absorb or outflow on a bounded axis");
     }
   }
+  double lam = 0.0;
+  if (desc->inject) {
+    if (s->g.periodic[0]) return fail(s, CPIC_E_ARG, "injection needs a bounded axis 0");
+    if (s->g.kind == CPIC_MAP_SINUSOIDAL) return fail(s, CPIC_E_UNSUPPORTED, "injection needs an orthogonal map");
+    if (!(desc->inject_n0 > 0) || !(desc->inject_vth > 0)) return fail(s, CPIC_E_ARG, "bad injection parameters");
+    // area of the outer face: 2 pi r_out (polar-log, per unit length) or the
+    // product of the other box lengths; one-sided Maxwellian particle flux
+    double A = 1.0;
+    if (s->g.kind == CPIC_MAP_POLAR_LOG)
+      A = 2.0 * M_PI * s->map.r_out;
+    else
+      for (int a = 1; a < d; ++a) A *= s->map.L[a];
+    lam = desc->inject_n0 * desc->inject_vth / sqrt(2.0 * M_PI) * A * s->grid.dt / desc->w;
+    if (lam > 1e8) return fail(s, CPIC_E_ARG, "injection rate too large");
+  }
   Species S;
   S.desc = *desc;
   S.cap = desc->capacity;
+  S.inject_lam = lam;
   bool ok = true;
   auto A = [&](size_t bytes) {
     void* p = sim_alloc(s, bytes);
@@ -385,6 +431,8 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
   S.item_begin = (int*)A(sizeof(int) * S.max_items);
   S.item_end = (int*)A(sizeof(int) * S.max_items);
   S.counters = (unsigned long long*)A(sizeof(unsigned long long) * 8);
+  S.fb_queue = (int*)A(sizeof(int) * S.cap);
+  S.fb_count = (int*)A(sizeof(int) * 2);
   if (!ok) return fail(s, CPIC_E_NOMEM, "species allocation failed");
   hipStream_t st = s->stream;
   launch_fill_u8(S.d_n, 0, sizeof(int) * 2, st);
@@ -444,6 +492,8 @@ extern "C" cpic_status cpic_set_particles(cpic_sim* s, int sid, size_t n, const 
     for (int a = 0; a < d; ++a) launch_offsets_check(S.off[buf][a], (long long)n, rs == 8, s->flags + 1, st);
   int nn = (int)n;
   HIPCHK(s, hipMemcpyAsync(S.d_n, &nn, sizeof(int), hipMemcpyHostToDevice, st));
+  unsigned long long next_id = (unsigned long long)n;  // ids of injected particles start after these
+  HIPCHK(s, hipMemcpyAsync(S.counters + 7, &next_id, sizeof(next_id), hipMemcpyHostToDevice, st));
   int bad[2] = {0, 0};
   HIPCHK(s, hipMemcpyAsync(bad, s->flags, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
   HIPCHK(s, hipStreamSynchronize(st));
@@ -529,7 +579,10 @@ static void sort_all(cpic_sim* s) {
 static void zero_deposits(cpic_sim* s, int mode) {
   if (mode == MODE_PUSH) launch_fill_u8(s->ke, 0, sizeof(double), s->stream);
   if (mode == MODE_HALFSTEP) return;
-  for (auto& S : s->sp) launch_fill_u8(S.Q, 0, 8 * (size_t)s->g.ncells, s->stream);
+  for (auto& S : s->sp) {
+    launch_fill_u8(S.Q, 0, 8 * (size_t)s->g.ncells, s->stream);
+    launch_fill_u8(S.fb_count, 0, sizeof(int) * 2, s->stream);
+  }
 }
 
 // particle kernels of all species (deposit arrays must have been zeroed)
@@ -565,10 +618,55 @@ static void particles_pass(cpic_sim* s, int mode) {
     L.S1 = s->S1;
     L.newton_maxit = 8;
     L.newton_tol = L.fp64 ? 1e-12 : 1e-5;
+    L.kappa = s->kappa;
+    L.fb_queue = S.fb_queue;
+    L.fb_count = S.fb_count;
+    L.fb_cap = (int)S.cap;
     L.ke_scale = 0.5 * S.desc.m * S.desc.w;
     L.ke = s->ke;
     L.counters = S.counters;
     launch_particles(L, s->stream);
+  }
+}
+
+static bool any_injection(const cpic_sim* s) {
+  for (const auto& S : s->sp)
+    if (S.desc.inject) return true;
+  return false;
+}
+
+// Maxwellian-flux injection of every injecting species for step `step`
+static void inject_pass(cpic_sim* s, long long step) {
+  for (size_t k = 0; k < s->sp.size(); ++k) {
+    Species& S = s->sp[k];
+    if (!S.desc.inject) continue;
+    InjectLaunch I;
+    memset(&I, 0, sizeof(I));
+    I.g = s->g;
+    I.fp64 = s->grid.precision == CPIC_FP64;
+    const int b = S.cur;
+    I.key = S.key[b];
+    for (int a = 0; a < 3; ++a) {
+      I.off[a] = S.off[b][a];
+      I.vel[a] = S.vel[b][a];
+    }
+    I.id = S.id[b];
+    I.d_n = S.d_n;
+    I.cap = (int)S.cap;
+    I.Q = S.Q;
+    I.shape = s->grid.shape;
+    I.S1 = s->S1;
+    I.lam = S.inject_lam;
+    I.kappa = s->kappa;
+    I.vth = S.desc.inject_vth;
+    I.dt = s->grid.dt;
+    I.k0 = (uint32_t)(S.desc.seed & 0xFFFFFFFFu);
+    I.k1 = (uint32_t)(S.desc.seed >> 32);
+    I.step = (uint32_t)step;
+    I.species = (uint32_t)k;
+    I.counters = S.counters;
+    I.count_out = S.d_n + 1;
+    launch_inject(I, s->stream);
   }
 }
 
@@ -604,6 +702,7 @@ extern "C" cpic_status cpic_run_stage(cpic_sim* s, int stage) {
     case CPIC_STAGE_CHARGE: charge_pass(s); break;
     case CPIC_STAGE_SOLVE: solve_pass(s); break;
     case CPIC_STAGE_EFIELD: launch_efield(s->G, s->stream); break;
+    case CPIC_STAGE_INJECT: inject_pass(s, s->step); s->sorted_dirty = true; break;
     case CPIC_STAGE_PUSH: ensure_sorted(s); zero_deposits(s, MODE_PUSH); particles_pass(s, MODE_PUSH); break;
     case CPIC_STAGE_HALFSTEP: ensure_sorted(s); particles_pass(s, MODE_HALFSTEP); break;
     default: return fail(s, CPIC_E_ARG, "unknown stage");
@@ -650,12 +749,15 @@ extern "C" cpic_status cpic_step(cpic_sim* s, int nsteps) {
     if (ev) hipEventRecord(ev->e[1], s->stream);
     particles_pass(s, MODE_PUSH);
     if (ev) hipEventRecord(ev->e[2], s->stream);
+    const bool inj = any_injection(s);
+    if (inj) inject_pass(s, s->step);
     charge_pass(s);
     solve_pass(s);
     launch_efield(s->G, s->stream);
     if (ev) hipEventRecord(ev->e[3], s->stream);
     ++s->step;
-    if (s->step % s->grid.sort_every == 0) sort_all(s);
+    // appended particles join a tile at the next sort: sort every step then
+    if (inj || s->step % s->grid.sort_every == 0) sort_all(s);
     if (ev) hipEventRecord(ev->e[4], s->stream);
   }
   return check_async(s);
@@ -760,6 +862,7 @@ extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
     out->newton_fallback += (long long)cnt[8 * k + 2];
     out->far_deposits += (long long)cnt[8 * k + 3];
     out->newton_failed += (long long)cnt[8 * k + 4];
+    out->injected[k] = (long long)cnt[8 * k + 5];
     out->qsum_lo[k] = qs[2 * k];
     out->qsum_hi[k] = qs[2 * k + 1];
   }

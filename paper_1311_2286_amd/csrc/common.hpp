@@ -109,8 +109,11 @@ template <> __device__ inline double r_exp<double>(double x) { return exp(x); }
 // ---------------------------------------------------------------------------
 // Position update: solve x(xi^n + delta h) - x(xi^n) = dt v for delta (in
 // cells) by Newton's method on the increment, starting from delta = 0 (whose
-// first step is k(xi^n) dt v / h).  Returns true when the last Newton step was
-// below tol cells.  J0 receives the (box-unit) Jacobian at xi^n.
+// first step is k(xi^n) dt v / h).  Converged when the last Newton step s is
+// below tol cells, or when the quadratic-convergence bound kappa s^2 on the
+// remaining error is below tol / 4 (kappa = max second derivative over twice
+// the smallest Jacobian of the increment map, from the host).  J0 receives
+// the (box-unit) Jacobian at xi^n.
 // ---------------------------------------------------------------------------
 
 // Sinusoidal map, x^a = L_a (xi^a + eps P), P = prod_k sin(2 pi xi^k) (Eq. map2
@@ -120,8 +123,9 @@ template <> __device__ inline double r_exp<double>(double x) { return exp(x); }
 // g_m = (2 pi / n_m) cos(2 pi xi_m') prod_{k != m} sin(2 pi xi_k'), inverted by
 // Sherman-Morrison; 1 + g.e is the box Jacobian at xi'.
 template <int D, typename R>
-__device__ inline bool newton_sinusoidal(const Geo& g, const int* idx, const R* f, const R* r,
-                                         R* d, R tol, int maxit, R& J0) {
+__device__ __forceinline__ bool newton_sinusoidal(const Geo& g, const int* idx, const R* f,
+                                                  const R* r, R* d, R tol, R kappa, int maxit,
+                                                  R& J0) {
   R s[D], c[D], e[D], w[D], invn[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -181,7 +185,7 @@ __device__ inline bool newton_sinusoidal(const Geo& g, const int* idx, const R* 
       d[a] += dd;
       mx = fmax(mx, fabs(dd));
     }
-    if (mx < tol) {
+    if (mx < tol || kappa * mx * mx < (R)0.25 * tol) {
       conv = true;
       break;
     }
@@ -194,8 +198,8 @@ __device__ inline bool newton_sinusoidal(const Geo& g, const int* idx, const R* 
 // rho = exp(delta_0 ln R / n0), theta' = theta + 2 pi delta_1 / n1.  The
 // Jacobian columns are rho (ln R / n0) e(theta') and rho (2 pi / n1) e_perp.
 template <typename R>
-__device__ inline bool newton_polar(const Geo& g, const int* idx, const R* f, const R* vdt, R* d,
-                                    R tol, int maxit, R& J0) {
+__device__ __forceinline__ bool newton_polar(const Geo& g, const int* idx, const R* f, const R* vdt,
+                                             R* d, R tol, R kappa, int maxit, R& J0) {
   R invn0 = (R)g.invn[0], invn1 = (R)g.invn[1];
   R lnR = (R)g.lnR;
   R xi0 = ((R)idx[0] + f[0]) * invn0;
@@ -224,7 +228,8 @@ __device__ inline bool newton_polar(const Geo& g, const int* idx, const R* f, co
     R d1 = -(-Fx * ey + Fy * ex) / (rho * ky);
     d[0] += d0;
     d[1] += d1;
-    if (fmax(fabs(d0), fabs(d1)) < tol) {
+    R mx = fmax(fabs(d0), fabs(d1));
+    if (mx < tol || kappa * mx * mx < (R)0.25 * tol) {
       conv = true;
       break;
     }
@@ -261,6 +266,70 @@ __device__ inline void weights_fixed(double f, int S1, uint32_t* w) {
       w[0] = Lw;
       w[1] = one - Lw;
       w[2] = 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter-based RNG used by
+// the injection; u = (r + 1/2) 2^-32 maps an output word into (0, 1).
+// ---------------------------------------------------------------------------
+__device__ inline void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                     uint32_t k1, uint32_t* out) {
+  uint32_t c[4] = {c0, c1, c2, c3};
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c[0];
+  out[1] = c[1];
+  out[2] = c[2];
+  out[3] = c[3];
+}
+__device__ inline double unit_open(uint32_t r) { return ((double)r + 0.5) * (1.0 / 4294967296.0); }
+
+// map x(xi) and Jacobi matrix j[a][b] = dx^a / dxi^b in FP64 (Eqs. map, jcov)
+__device__ inline void map_jacobi(const Geo& g, const double* xi, double j[3][3], double* x) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) j[a][b] = (a == b) ? 1.0 : 0.0;
+  const int d = g.dim;
+  if (g.kind == MAP_IDENTITY) {
+    for (int a = 0; a < d; ++a) {
+      j[a][a] = g.L[a];
+      if (x) x[a] = g.L[a] * xi[a];
+    }
+  } else if (g.kind == MAP_SINUSOIDAL) {
+    double s[3], c[3];
+    for (int k = 0; k < d; ++k) sincospi(2.0 * xi[k], &s[k], &c[k]);
+    double P = 1.0;
+    for (int k = 0; k < d; ++k) P *= s[k];
+    for (int b = 0; b < d; ++b) {
+      double t = 6.283185307179586 * c[b];
+      for (int k = 0; k < d; ++k)
+        if (k != b) t *= s[k];
+      for (int a = 0; a < d; ++a) j[a][b] = g.L[a] * ((a == b ? 1.0 : 0.0) + g.eps * t);
+    }
+    if (x)
+      for (int a = 0; a < d; ++a) x[a] = g.L[a] * (xi[a] + g.eps * P);
+  } else {  // polar-log
+    double r = g.r_in * exp(xi[0] * g.lnR);
+    double st, ct;
+    sincospi(2.0 * xi[1], &st, &ct);
+    j[0][0] = r * g.lnR * ct;
+    j[0][1] = -6.283185307179586 * r * st;
+    j[1][0] = r * g.lnR * st;
+    j[1][1] = 6.283185307179586 * r * ct;
+    if (x) {
+      x[0] = r * ct;
+      x[1] = r * st;
     }
   }
 }

@@ -25,45 +25,8 @@
 namespace cpic {
 
 // ----------------------------------------------------------------------------
-// map metric in FP64: Jacobi matrix j[a][b] = dx^a / dxi^b (Eq. jcov)
+// metric helpers in FP64 (the Jacobi matrix itself is map_jacobi, common.hpp)
 // ----------------------------------------------------------------------------
-__device__ inline void map_jacobi(const Geo& g, const double* xi, double j[3][3], double* x) {
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) j[a][b] = (a == b) ? 1.0 : 0.0;
-  const int d = g.dim;
-  if (g.kind == MAP_IDENTITY) {
-    for (int a = 0; a < d; ++a) {
-      j[a][a] = g.L[a];
-      if (x) x[a] = g.L[a] * xi[a];
-    }
-  } else if (g.kind == MAP_SINUSOIDAL) {
-    double s[3], c[3];
-    for (int k = 0; k < d; ++k) sincospi(2.0 * xi[k], &s[k], &c[k]);
-    double P = 1.0;
-    for (int k = 0; k < d; ++k) P *= s[k];
-    for (int b = 0; b < d; ++b) {
-      double t = 6.283185307179586 * c[b];
-      for (int k = 0; k < d; ++k)
-        if (k != b) t *= s[k];
-      for (int a = 0; a < d; ++a) j[a][b] = g.L[a] * ((a == b ? 1.0 : 0.0) + g.eps * t);
-    }
-    if (x)
-      for (int a = 0; a < d; ++a) x[a] = g.L[a] * (xi[a] + g.eps * P);
-  } else {  // polar-log
-    double r = g.r_in * exp(xi[0] * g.lnR);
-    double st, ct;
-    sincospi(2.0 * xi[1], &st, &ct);
-    j[0][0] = r * g.lnR * ct;
-    j[0][1] = -6.283185307179586 * r * st;
-    j[1][0] = r * g.lnR * st;
-    j[1][1] = 6.283185307179586 * r * ct;
-    if (x) {
-      x[0] = r * ct;
-      x[1] = r * st;
-    }
-  }
-}
-
 __device__ inline double det3(int d, const double j[3][3]) {
   if (d == 2) return j[0][0] * j[1][1] - j[0][1] * j[1][0];
   return j[0][0] * (j[1][1] * j[2][2] - j[1][2] * j[2][1]) - j[0][1] * (j[1][0] * j[2][2] - j[1][2] * j[2][0]) +

@@ -30,6 +30,10 @@ struct ParticleLaunch {
   int S1;
   int newton_maxit;
   double newton_tol;
+  double kappa;
+  int* fb_queue;  // FP64 fallback queue (capacity = species capacity)
+  int* fb_count;  // zeroed before each push
+  int fb_cap;
   double ke_scale;
   double* ke;
   unsigned long long* counters;
@@ -58,7 +62,26 @@ struct SortLaunch {
   int* item_end;
 };
 
+struct InjectLaunch {
+  Geo g;
+  int fp64;
+  int32_t* key;
+  void* off[3];
+  void* vel[3];
+  uint32_t* id;
+  int* d_n;
+  int cap;
+  void* Q;
+  int shape;
+  int S1;
+  double lam, vth, dt, kappa;
+  uint32_t k0, k1, step, species;
+  unsigned long long* counters;
+  int* count_out;
+};
+
 int launch_particles(const ParticleLaunch& L, hipStream_t st);
+int launch_inject(const InjectLaunch& I, hipStream_t st);
 int launch_tile_sort(const SortLaunch& S, hipStream_t st);
 void launch_lin_to_key(const int32_t* lin, int32_t* key, int n, const Geo& g, int* bad, hipStream_t st);
 void launch_key_to_lin(const int32_t* key, int32_t* lin, int n, const Geo& g, hipStream_t st);

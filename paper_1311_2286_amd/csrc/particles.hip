@@ -130,15 +130,15 @@ __device__ inline void boris_push(R* v, const R* E, const R* B, R qm, R dt, bool
 // so that each part moves the particle by at most a quarter cell in logical
 // space, and each part is solved by Newton from the end of the previous one.
 template <int D, int MAP>
-__device__ __noinline__ bool move_fallback(const Geo& g, const int* idx, const double* f0,
-                                           const double* disp, double* d) {
+__device__ __forceinline__ bool move_fallback(const Geo& g, const int* idx, const double* f0,
+                                              const double* disp, double kappa, double* d) {
   double dt0[3] = {0.0, 0.0, 0.0};
   double J = 1.0;
   double est[3] = {0.0, 0.0, 0.0};
   if (MAP == MAP_SINUSOIDAL)
-    newton_sinusoidal<D, double>(g, idx, f0, disp, est, 0.0, 1, J);
+    newton_sinusoidal<D, double>(g, idx, f0, disp, est, 0.0, 0.0, 1, J);
   else
-    newton_polar<double>(g, idx, f0, disp, est, 0.0, 1, J);
+    newton_polar<double>(g, idx, f0, disp, est, 0.0, 0.0, 1, J);
   double mx = 0.0;
   for (int a = 0; a < D; ++a) mx = fmax(mx, fabs(est[a]));
   int m = (int)ceil(mx / 0.25);
@@ -152,9 +152,9 @@ __device__ __noinline__ bool move_fallback(const Geo& g, const int* idx, const d
     }
     bool c;
     if (MAP == MAP_SINUSOIDAL)
-      c = newton_sinusoidal<D, double>(g, idx, fb, part, dd, 1e-12, 24, J);
+      c = newton_sinusoidal<D, double>(g, idx, fb, part, dd, 1e-12, kappa, 24, J);
     else
-      c = newton_polar<double>(g, idx, fb, part, dd, 1e-12, 24, J);
+      c = newton_polar<double>(g, idx, fb, part, dd, 1e-12, kappa, 24, J);
     ok = ok && c;
     for (int a = 0; a < D; ++a) dt0[a] += dd[a];
   }
@@ -162,16 +162,16 @@ __device__ __noinline__ bool move_fallback(const Geo& g, const int* idx, const d
   return ok;
 }
 
-// Newton on the map increment in the particle's precision.  Falls back to the
-// globalised FP64 solve when it does not converge, and (FP32 only) when the
-// cell is strongly compressed (J < 0.25 in box units).
+// Newton on the map increment in the particle's precision.  Returns false
+// when it does not converge or (FP32 only) when the cell is strongly
+// compressed (J < 0.25 in box units): such particles are handed to the FP64
+// fallback kernel.  inv_dxc: n_a / L_a.
 template <int D, int MAP, typename R>
-__device__ inline bool move_delta(const Geo& g, const int* idx, const R* f, const R* v, R dt,
-                                  int maxit, R tol, R* d, bool& fallback) {
-  fallback = false;
+__device__ __forceinline__ bool move_delta(const Geo& g, const int* idx, const R* f, const R* v,
+                                           R dt, const R* inv_dxc, int maxit, R tol, R kappa, R* d) {
   if (MAP == MAP_IDENTITY) {
 #pragma unroll
-    for (int a = 0; a < D; ++a) d[a] = dt * v[a] * (R)(1.0 / g.dxc[a]);
+    for (int a = 0; a < D; ++a) d[a] = dt * v[a] * inv_dxc[a];
     return true;
   }
   bool conv;
@@ -179,25 +179,46 @@ __device__ inline bool move_delta(const Geo& g, const int* idx, const R* f, cons
   if (MAP == MAP_SINUSOIDAL) {
     R r[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) r[a] = dt * v[a] * (R)(1.0 / g.dxc[a]);
-    conv = newton_sinusoidal<D, R>(g, idx, f, r, d, tol, maxit, J0);
+    for (int a = 0; a < D; ++a) r[a] = dt * v[a] * inv_dxc[a];
+    conv = newton_sinusoidal<D, R>(g, idx, f, r, d, tol, kappa, maxit, J0);
   } else {
     R vdt[2] = {dt * v[0], dt * v[1]};
-    conv = newton_polar<R>(g, idx, f, vdt, d, tol, maxit, J0);
+    conv = newton_polar<R>(g, idx, f, vdt, d, tol, kappa, maxit, J0);
   }
   const bool low_j = std::is_same<R, float>::value && J0 < (R)0.25;
-  if (!conv || low_j) {
-    fallback = true;
-    double fd[3] = {(double)f[0], (double)f[1], D == 3 ? (double)f[D - 1] : 0.0};
-    double disp[3] = {0.0, 0.0, 0.0}, dd[3] = {0.0, 0.0, 0.0};
+  return conv && !low_j;
+}
+
+// New cell and offset from cell idx, offset f and increment d (cells), with
+// the particle boundaries.  Returns 0 (alive), -1 (absorbed: a wall with an
+// absorbing condition) or -2 (left through an outflow wall).
+template <int D, typename R>
+__device__ __forceinline__ int place_particle(const Geo& g, const int* pbc_lo, const int* pbc_hi,
+                                              int* idx, R* f, const R* d) {
+  int dead = 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a)
-      disp[a] = (MAP == MAP_SINUSOIDAL) ? (double)dt * (double)v[a] / g.dxc[a] : (double)dt * (double)v[a];
-    conv = move_fallback<D, MAP>(g, idx, fd, disp, dd);
-#pragma unroll
-    for (int a = 0; a < D; ++a) d[a] = (R)dd[a];
+  for (int ax = 0; ax < D; ++ax) {
+    R u = f[ax] + d[ax];
+    R fl = floor(u);
+    R nf = u - fl;
+    int ni = idx[ax] + (int)fl;
+    if (nf >= (R)1) {
+      nf = (R)0;
+      ni += 1;
+    }
+    const int n = g.n[ax];
+    if (g.periodic[ax]) {
+      ni %= n;
+      if (ni < 0) ni += n;
+    } else if (ni < 0) {
+      dead = (pbc_lo[ax] == PBC_ABSORB) ? -1 : -2;
+    } else if (ni >= n) {
+      dead = (pbc_hi[ax] == PBC_ABSORB) ? -1 : -2;
+    }
+    idx[ax] = ni;
+    f[ax] = nf;
   }
-  return conv;
+  return dead;
 }
 
 template <typename R>
@@ -225,68 +246,95 @@ struct PartArgs {
   int S1;
   int newton_maxit;
   R newton_tol;
+  R kappa;
+  R inv_dxc[3];
   double ke_scale;
   double* ke;
   unsigned long long* counters;
+  int* fb_queue;  // particles left to the FP64 fallback kernel
+  int* fb_count;
+  int fb_cap;
 };
 
 template <int D, int SHAPE, typename R, bool FIXED, typename QT>
-__device__ inline void deposit_particle(const Geo& g, const int* origin, QT* win, void* Qg,
+__device__ __forceinline__ void deposit_particle(const Geo& g, const int* origin, QT* win, void* Qg,
                                         const int* idx, const R* f, int S1,
                                         unsigned long long& far) {
   using TS = TileShape<D>;
+  typedef typename std::conditional<FIXED, uint32_t, R>::type WT;
   const int Wd[3] = {TS::W0, TS::W1, TS::W2};
-  int tg[3][3], tl[3][3];
-  QT w[3][3];
+  // per axis: weights of cells i-1, i, i+1 and their window-local indices
+  int tl[3][3];
+  WT w[3][3];
+  bool inwin = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (a >= D) {
-      tg[a][0] = tg[a][2] = 0;
-      tg[a][1] = 0;
       tl[a][0] = tl[a][1] = tl[a][2] = 0;
-      w[a][0] = w[a][2] = (QT)0;
-      w[a][1] = (QT)1;
+      w[a][0] = w[a][2] = (WT)0;
+      w[a][1] = (WT)1;
       continue;
     }
     if (FIXED) {
       uint32_t wi[3];
       weights_fixed<SHAPE>((double)f[a], S1, wi);
-      w[a][0] = (QT)wi[0];
-      w[a][1] = (QT)wi[1];
-      w[a][2] = (QT)wi[2];
+      w[a][0] = (WT)wi[0];
+      w[a][1] = (WT)wi[1];
+      w[a][2] = (WT)wi[2];
     } else {
       R wr[3];
       weights_real<SHAPE, R>(f[a], wr);
-      w[a][0] = (QT)wr[0];
-      w[a][1] = (QT)wr[1];
-      w[a][2] = (QT)wr[2];
+      w[a][0] = (WT)wr[0];
+      w[a][1] = (WT)wr[1];
+      w[a][2] = (WT)wr[2];
     }
     const int n = g.n[a];
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
       int t = idx[a] + o - 1;
       if (g.periodic[a]) {
-        if (t < 0) t += n;
-        else if (t >= n) t -= n;
+        t = t < 0 ? t + n : (t >= n ? t - n : t);
       } else {
         t = t < 0 ? 0 : (t >= n ? n - 1 : t);
       }
-      tg[a][o] = t;
       int l = t - origin[a] + TS::G;
-      if (g.periodic[a]) {
-        if (l < 0) l += n;
-        else if (l >= Wd[a]) l -= n;
-      }
+      if (g.periodic[a]) l = l < 0 ? l + n : (l >= Wd[a] ? l - n : l);
       tl[a][o] = l;
+      inwin = inwin && l >= 0 && l < Wd[a];
     }
   }
   constexpr int NZ = (D == 3) ? 3 : 1;
+  if (inwin) {
 #pragma unroll
+    for (int oz = 0; oz < NZ; ++oz) {
+      const int az = (D == 3) ? oz : 1;
+#pragma unroll
+      for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+        for (int ox = 0; ox < 3; ++ox) {
+          QT val;
+          if (FIXED) {
+            if (D == 3)
+              val = (QT)((unsigned long long)(w[0][ox] * w[1][oy]) * (unsigned long long)w[2][az]);
+            else
+              val = (QT)((unsigned long long)w[0][ox] * (unsigned long long)w[1][oy]);
+          } else {
+            val = (QT)(w[0][ox] * w[1][oy] * w[2][az]);
+          }
+          if (val == (QT)0) continue;
+          atomicAdd(&win[tl[0][ox] + TS::W0 * (tl[1][oy] + TS::W1 * tl[2][az])], val);
+        }
+    }
+    return;
+  }
+  // some target outside the window (particle drifted since the last sort):
+  // those go straight to HBM
+#pragma unroll 1
   for (int oz = 0; oz < NZ; ++oz) {
     const int az = (D == 3) ? oz : 1;
-#pragma unroll
+#pragma unroll 1
     for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
+#pragma unroll 1
       for (int ox = 0; ox < 3; ++ox) {
         QT val;
         if (FIXED) {
@@ -294,15 +342,25 @@ __device__ inline void deposit_particle(const Geo& g, const int* origin, QT* win
           if (D == 3) p *= (unsigned long long)w[2][az];
           val = (QT)p;
         } else {
-          val = w[0][ox] * w[1][oy] * w[2][az];
+          val = (QT)(w[0][ox] * w[1][oy] * w[2][az]);
         }
         if (val == (QT)0) continue;
-        int lx = tl[0][ox], ly = tl[1][oy], lz = tl[2][az];
-        bool in = lx >= 0 && lx < TS::W0 && ly >= 0 && ly < TS::W1 && lz >= 0 && lz < TS::W2;
+        const int o3[3] = {ox, oy, az};
+        int lt[3], t[3];
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          lt[a] = tl[a][o3[a]];
+          in = in && lt[a] >= 0 && lt[a] < Wd[a];
+          int v = (a < D) ? idx[a] + o3[a] - 1 : 0;
+          const int n = g.n[a];
+          if (a < D) v = g.periodic[a] ? (v < 0 ? v + n : (v >= n ? v - n : v)) : (v < 0 ? 0 : (v >= n ? n - 1 : v));
+          t[a] = v;
+        }
         if (in) {
-          atomicAdd(&win[lx + TS::W0 * (ly + TS::W1 * lz)], val);
+          atomicAdd(&win[lt[0] + TS::W0 * (lt[1] + TS::W1 * lt[2])], val);
         } else {
-          long long c = (long long)tg[0][ox] + (long long)g.n[0] * (tg[1][oy] + (long long)g.n[1] * tg[2][az]);
+          long long c = (long long)t[0] + (long long)g.n[0] * (t[1] + (long long)g.n[1] * t[2]);
           atomicAdd(&((QT*)Qg)[c], val);
           ++far;
         }
@@ -311,7 +369,8 @@ __device__ inline void deposit_particle(const Geo& g, const int* origin, QT* win
 }
 
 template <int D, int MAP, int SHAPE, typename R, bool FIXED>
-__global__ __launch_bounds__(256) void particle_kernel(PartArgs<R> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void particle_kernel(
+    PartArgs<R> a) {
   using TS = TileShape<D>;
   typedef typename std::conditional<FIXED, unsigned long long, double>::type QT;
   __shared__ QT win[TS::WIN];
@@ -336,8 +395,7 @@ __global__ __launch_bounds__(256) void particle_kernel(PartArgs<R> a) {
   }
 
   double ke = 0.0;
-  unsigned long long absorbed = 0, outflow = 0, fallbacks = 0, far = 0, nonconv = 0;
-  R* offs[3] = {a.off0, a.off1, a.off2};
+  unsigned long long absorbed = 0, outflow = 0, far = 0;
 
   for (int p = begin + (int)threadIdx.x; p < end; p += (int)blockDim.x) {
     int key = a.key[p];
@@ -364,33 +422,15 @@ __global__ __launch_bounds__(256) void particle_kernel(PartArgs<R> a) {
       ke += (double)(vo0 * v[0] + vo1 * v[1] + vo2 * v[2]);
 
       R d[3] = {(R)0, (R)0, (R)0};
-      bool fb = false;
-      bool conv = move_delta<D, MAP, R>(g, idx, f, v, a.dt, a.newton_maxit, a.newton_tol, d, fb);
-      fallbacks += fb ? 1 : 0;
-      nonconv += conv ? 0 : 1;
-      int dead = 0;
-#pragma unroll
-      for (int ax = 0; ax < D; ++ax) {
-        R u = f[ax] + d[ax];
-        R fl = floor(u);
-        R nf = u - fl;
-        int ni = idx[ax] + (int)fl;
-        if (nf >= (R)1) {
-          nf = (R)0;
-          ni += 1;
-        }
-        const int n = g.n[ax];
-        if (g.periodic[ax]) {
-          ni %= n;
-          if (ni < 0) ni += n;
-        } else if (ni < 0) {
-          dead = (a.pbc_lo[ax] == PBC_ABSORB) ? -1 : -2;
-        } else if (ni >= n) {
-          dead = (a.pbc_hi[ax] == PBC_ABSORB) ? -1 : -2;
-        }
-        idx[ax] = ni;
-        f[ax] = nf;
+      bool conv = move_delta<D, MAP, R>(g, idx, f, v, a.dt, a.inv_dxc, a.newton_maxit, a.newton_tol,
+                                        a.kappa, d);
+      if (!conv) {
+        // rare: the FP64 fallback kernel moves and deposits this particle
+        int slot = atomicAdd(a.fb_count, 1);
+        if (slot < a.fb_cap) a.fb_queue[slot] = p;
+        continue;
       }
+      int dead = place_particle<D, R>(g, a.pbc_lo, a.pbc_hi, idx, f, d);
       if (dead) {
         a.key[p] = dead;
         absorbed += dead == -1 ? 1 : 0;
@@ -404,7 +444,6 @@ __global__ __launch_bounds__(256) void particle_kernel(PartArgs<R> a) {
     }
     deposit_particle<D, SHAPE, R, FIXED, QT>(g, origin, win, a.Q, idx, f, a.S1, far);
   }
-  (void)offs;
 
   if (deposit) {
     __syncthreads();
@@ -438,8 +477,8 @@ __global__ __launch_bounds__(256) void particle_kernel(PartArgs<R> a) {
   // block sums of the diagnostics
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double kes = wave_sum(ke);
-  unsigned long long cs[5] = {wave_sum_u64(absorbed), wave_sum_u64(outflow), wave_sum_u64(fallbacks),
-                              wave_sum_u64(far), wave_sum_u64(nonconv)};
+  unsigned long long cs[5] = {wave_sum_u64(absorbed), wave_sum_u64(outflow), 0ull, wave_sum_u64(far),
+                              0ull};
   if (lane == 0) {
     red_d[wv] = kes;
     for (int i = 0; i < 5; ++i) red_u[wv][i] = cs[i];
@@ -457,6 +496,248 @@ __global__ __launch_bounds__(256) void particle_kernel(PartArgs<R> a) {
     for (int i = 0; i < 5; ++i)
       if (u[i]) atomicAdd(&a.counters[i], u[i]);
   }
+}
+
+// Deposit of one particle straight into HBM (global atomics): used for the
+// few particles handled outside the tile kernel (FP64 fallback, injection).
+template <int D, typename R, bool FIXED>
+__device__ inline void deposit_global(const Geo& g, int shape, int S1, const int* idx, const R* f,
+                                      void* Q) {
+  typedef typename std::conditional<FIXED, unsigned long long, double>::type QT;
+  QT w[3][3];
+  int tg[3][3];
+  for (int ax = 0; ax < 3; ++ax) {
+    if (ax >= D) {
+      w[ax][0] = w[ax][2] = (QT)0;
+      w[ax][1] = (QT)1;
+      tg[ax][0] = tg[ax][1] = tg[ax][2] = 0;
+      continue;
+    }
+    if (FIXED) {
+      uint32_t wi[3];
+      if (shape == SHAPE_B2)
+        weights_fixed<SHAPE_B2>((double)f[ax], S1, wi);
+      else
+        weights_fixed<SHAPE_B1>((double)f[ax], S1, wi);
+      for (int o = 0; o < 3; ++o) w[ax][o] = (QT)wi[o];
+    } else {
+      R wr[3];
+      if (shape == SHAPE_B2)
+        weights_real<SHAPE_B2, R>(f[ax], wr);
+      else
+        weights_real<SHAPE_B1, R>(f[ax], wr);
+      for (int o = 0; o < 3; ++o) w[ax][o] = (QT)wr[o];
+    }
+    const int n = g.n[ax];
+    for (int o = 0; o < 3; ++o) {
+      int t = idx[ax] + o - 1;
+      if (g.periodic[ax])
+        t = t < 0 ? t + n : (t >= n ? t - n : t);
+      else
+        t = t < 0 ? 0 : (t >= n ? n - 1 : t);
+      tg[ax][o] = t;
+    }
+  }
+  const int nz = (D == 3) ? 3 : 1;
+  for (int oz = 0; oz < nz; ++oz) {
+    const int az = (D == 3) ? oz : 1;
+    for (int oy = 0; oy < 3; ++oy)
+      for (int ox = 0; ox < 3; ++ox) {
+        QT val;
+        if (FIXED) {
+          unsigned long long p = (unsigned long long)w[0][ox] * (unsigned long long)w[1][oy];
+          if (D == 3) p *= (unsigned long long)w[2][az];
+          val = (QT)p;
+        } else {
+          val = w[0][ox] * w[1][oy] * w[2][az];
+        }
+        if (val == (QT)0) continue;
+        long long c = (long long)tg[0][ox] + (long long)g.n[0] * (tg[1][oy] + (long long)g.n[1] * tg[2][az]);
+        atomicAdd(&((QT*)Q)[c], val);
+      }
+  }
+}
+
+// Particles whose position update was left by the tile kernel: globalised FP64
+// Newton (continuation over the physical displacement), boundaries, deposit.
+// Their new velocity is already stored.
+template <int D, int MAP, typename R, bool FIXED>
+__global__ __launch_bounds__(256) void fallback_kernel(PartArgs<R> a, int shape) {
+  const Geo& g = a.g;
+  const int n = min(*a.fb_count, a.fb_cap);
+  unsigned long long done = 0, failed = 0, absorbed = 0, outflow = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int p = a.fb_queue[i];
+    const int key = a.key[p];
+    int idx[3] = {key_i(key, g), key_j(key, g), (D == 3) ? key_k(key, g) : 0};
+    double f[3] = {(double)a.off0[p], (double)a.off1[p], (D == 3) ? (double)a.off2[p] : 0.0};
+    double v[3] = {(double)a.v0[p], (double)a.v1[p], 0.0};
+    double disp[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0};
+    for (int ax = 0; ax < D; ++ax)
+      disp[ax] = (MAP == MAP_SINUSOIDAL) ? (double)a.dt * v[ax] / g.dxc[ax] : (double)a.dt * v[ax];
+    if (D == 3) disp[D - 1] = (MAP == MAP_SINUSOIDAL) ? (double)a.dt * (double)a.v2[p] / g.dxc[D - 1]
+                                                      : (double)a.dt * (double)a.v2[p];
+    bool ok = move_fallback<D, MAP>(g, idx, f, disp, (double)a.kappa, d);
+    ++done;
+    failed += ok ? 0 : 1;
+    int dead = place_particle<D, double>(g, a.pbc_lo, a.pbc_hi, idx, f, d);
+    if (dead) {
+      a.key[p] = dead;
+      absorbed += dead == -1 ? 1 : 0;
+      outflow += dead == -2 ? 1 : 0;
+      continue;
+    }
+    R fr[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      R r = (R)f[ax];
+      if (r >= (R)1) r = std::is_same<R, float>::value ? (R)0.99999994f : (R)f[ax];
+      fr[ax] = r;
+    }
+    a.key[p] = make_key(idx[0], idx[1], idx[2], g);
+    a.off0[p] = fr[0];
+    a.off1[p] = fr[1];
+    if (D == 3) a.off2[p] = fr[2];
+    deposit_global<D, R, FIXED>(g, shape, a.S1, idx, fr, a.Q);
+  }
+  if (done) {
+    atomicAdd(&a.counters[2], done);
+    if (failed) atomicAdd(&a.counters[4], failed);
+    if (absorbed) atomicAdd(&a.counters[0], absorbed);
+    if (outflow) atomicAdd(&a.counters[1], outflow);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// injection of a Maxwellian at rest through the upper face of axis 0 (the
+// outer wall): per step floor(lambda) + Bernoulli(frac lambda) particles,
+// lambda = n0 v_th / sqrt(2 pi) A dt / w.  Each: uniform tangential logical
+// position on the face, inward normal speed v_th sqrt(-2 ln u) (flux-weighted
+// half-Maxwellian), tangential components N(0, v_th^2) by Box-Muller, and a
+// free flight over a uniform fraction of the step from the face, mapped back
+// to xi by Newton on the map increment.  FP64 throughout (few particles).
+// Random numbers: Philox4x32-10, key (seed), counter (step, k, species, use).
+// Particles are appended after the live ones; their charge is deposited with
+// global atomics (they join a tile at the next sort).
+// ----------------------------------------------------------------------------
+template <typename R>
+struct InjectArgs {
+  Geo g;
+  int32_t* key;
+  R* off[3];
+  R* vel[3];
+  uint32_t* id;
+  const int* d_n;
+  int cap;
+  void* Q;
+  int shape;
+  int S1;
+  double lam, vth, dt, kappa;
+  uint32_t k0, k1, step, species;
+  unsigned long long* counters;  // [5] injected, [6] dropped for capacity, [7] ids issued
+  int* count_out;
+};
+
+__device__ inline int injection_count(double lam, uint32_t k0, uint32_t k1, uint32_t step,
+                                      uint32_t species) {
+  uint32_t r[4];
+  philox4x32_10(step, 0xFFFFFFFFu, species, 2u, k0, k1, r);
+  double fl = floor(lam);
+  return (int)fl + (unit_open(r[0]) < lam - fl ? 1 : 0);
+}
+
+template <int D, int MAP, typename R, bool FIXED>
+__global__ __launch_bounds__(256) void inject_kernel(InjectArgs<R> a) {
+  const Geo& g = a.g;
+  const int count = injection_count(a.lam, a.k0, a.k1, a.step, a.species);
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) *a.count_out = count;
+  if (k >= count) return;
+  const int base = *a.d_n;
+  const long long slot = (long long)base + k;
+  if (slot >= a.cap) {
+    atomicAdd(&a.counters[6], 1ull);
+    return;
+  }
+  uint32_t ra[4], rb[4];
+  philox4x32_10(a.step, (uint32_t)k, a.species, 0u, a.k0, a.k1, ra);
+  philox4x32_10(a.step, (uint32_t)k, a.species, 1u, a.k0, a.k1, rb);
+  double xi_f[3] = {1.0, unit_open(ra[0]), (D == 3) ? unit_open(rb[1]) : 0.0};
+  double vn = a.vth * sqrt(-2.0 * log(unit_open(ra[1])));
+  double rho = sqrt(-2.0 * log(unit_open(ra[2])));
+  double sn, cs;
+  sincospi(2.0 * unit_open(ra[3]), &sn, &cs);
+  double t1 = a.vth * rho * cs, t2 = a.vth * rho * sn;
+  double frac = unit_open(rb[0]);
+  double j[3][3], xf[3];
+  map_jacobi(g, xi_f, j, xf);
+  double e[3][3];
+  for (int b = 0; b < 3; ++b) {
+    double nrm = sqrt(j[0][b] * j[0][b] + j[1][b] * j[1][b] + j[2][b] * j[2][b]);
+    for (int c = 0; c < 3; ++c) e[b][c] = j[c][b] / nrm;
+  }
+  double v[3];
+  for (int c = 0; c < 3; ++c) v[c] = -vn * e[0][c] + t1 * e[1][c];
+  if (D == 2)
+    v[2] += t2;
+  else
+    for (int c = 0; c < 3; ++c) v[c] += t2 * e[2][c];
+  // base: upper face of the last cell along axis 0
+  int idx[3] = {g.n[0] - 1, 0, 0};
+  double f[3] = {1.0, 0.0, 0.0};
+  for (int ax = 1; ax < D; ++ax) {
+    double u = xi_f[ax] * g.n[ax];
+    int i = (int)floor(u);
+    if (i > g.n[ax] - 1) i = g.n[ax] - 1;
+    idx[ax] = i;
+    f[ax] = u - i;
+  }
+  double disp[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < D; ++c) disp[c] = (MAP == MAP_IDENTITY) ? frac * a.dt * v[c] / g.dxc[c] : frac * a.dt * v[c];
+  double d[3] = {0.0, 0.0, 0.0};
+  if (MAP == MAP_IDENTITY) {
+    for (int c = 0; c < D; ++c) d[c] = disp[c];
+  } else {
+    double J;
+    bool ok = (MAP == MAP_POLAR_LOG) ? newton_polar<double>(g, idx, f, disp, d, 1e-12, a.kappa, 24, J)
+                                     : newton_sinusoidal<D, double>(g, idx, f, disp, d, 1e-12, a.kappa, 24, J);
+    if (!ok) move_fallback<D, MAP>(g, idx, f, disp, a.kappa, d);
+  }
+  int dead = 0;
+  R fo[3];
+  for (int ax = 0; ax < D; ++ax) {
+    double u = f[ax] + d[ax];
+    double fl = floor(u);
+    int ni = idx[ax] + (int)fl;
+    double nf = u - fl;
+    const int n = g.n[ax];
+    if (g.periodic[ax]) {
+      ni %= n;
+      if (ni < 0) ni += n;
+    } else if (ni < 0 || ni >= n) {
+      dead = 1;
+    }
+    idx[ax] = ni;
+    R r = (R)nf;
+    if (r >= (R)1) r = (R)0.99999994;  // keep the stored offset inside [0, 1)
+    fo[ax] = r;
+  }
+  for (int ax = D; ax < 3; ++ax) fo[ax] = (R)0;
+  unsigned long long my_id = atomicAdd(&a.counters[7], 1ull);
+  if (a.id) a.id[slot] = (uint32_t)my_id;
+  if (dead) {
+    a.key[slot] = -2;
+    return;
+  }
+  a.key[slot] = make_key(idx[0], idx[1], idx[2], g);
+  for (int ax = 0; ax < D; ++ax) a.off[ax][slot] = fo[ax];
+  for (int c = 0; c < 3; ++c) a.vel[c][slot] = (R)v[c];
+  atomicAdd(&a.counters[5], 1ull);
+  deposit_global<D, R, FIXED>(g, a.shape, a.S1, idx, fo, a.Q);
+}
+
+__global__ void inject_finish_kernel(int* d_n, const int* count, int cap) {
+  int n = *d_n + *count;
+  *d_n = n < cap ? n : cap;
 }
 
 // ----------------------------------------------------------------------------
@@ -637,13 +918,20 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   a.S1 = L.S1;
   a.newton_maxit = L.newton_maxit;
   a.newton_tol = (R)L.newton_tol;
+  a.kappa = (R)L.kappa;
+  for (int i = 0; i < 3; ++i) a.inv_dxc[i] = (R)(1.0 / L.g.dxc[i]);
   a.ke_scale = L.ke_scale;
   a.ke = L.ke;
   a.counters = L.counters;
+  a.fb_queue = L.fb_queue;
+  a.fb_count = L.fb_count;
+  a.fb_cap = L.fb_cap;
   if (L.max_items <= 0) return;
   constexpr bool FIXED = std::is_same<R, float>::value;
   hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED>), dim3(L.max_items), dim3(256), 0, st,
                      a);
+  if (MAP != MAP_IDENTITY && L.mode == MODE_PUSH)
+    hipLaunchKernelGGL((fallback_kernel<D, MAP, R, FIXED>), dim3(64), dim3(256), 0, st, a, L.shape);
 }
 
 template <int D, int MAP, typename R>
@@ -671,6 +959,55 @@ static int launch_particle_r(const ParticleLaunch& L, hipStream_t st) {
 
 int launch_particles(const ParticleLaunch& L, hipStream_t st) {
   return L.fp64 ? launch_particle_r<double>(L, st) : launch_particle_r<float>(L, st);
+}
+
+template <int D, int MAP, typename R>
+static void launch_inject_t(const InjectLaunch& I, hipStream_t st) {
+  InjectArgs<R> a;
+  a.g = I.g;
+  a.key = I.key;
+  for (int i = 0; i < 3; ++i) {
+    a.off[i] = (R*)I.off[i];
+    a.vel[i] = (R*)I.vel[i];
+  }
+  a.id = I.id;
+  a.d_n = I.d_n;
+  a.cap = I.cap;
+  a.Q = I.Q;
+  a.shape = I.shape;
+  a.S1 = I.S1;
+  a.lam = I.lam;
+  a.kappa = I.kappa;
+  a.vth = I.vth;
+  a.dt = I.dt;
+  a.k0 = I.k0;
+  a.k1 = I.k1;
+  a.step = I.step;
+  a.species = I.species;
+  a.counters = I.counters;
+  a.count_out = I.count_out;
+  const int maxc = (int)floor(I.lam) + 1;
+  const unsigned blocks = (unsigned)((maxc + 255) / 256);
+  constexpr bool FIXED = std::is_same<R, float>::value;
+  hipLaunchKernelGGL((inject_kernel<D, MAP, R, FIXED>), dim3(blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(inject_finish_kernel, dim3(1), dim3(1), 0, st, I.d_n, (const int*)I.count_out, I.cap);
+}
+
+template <typename R>
+static int launch_inject_r(const InjectLaunch& I, hipStream_t st) {
+  if (I.g.dim == 2) {
+    if (I.g.kind == MAP_IDENTITY) launch_inject_t<2, MAP_IDENTITY, R>(I, st);
+    else if (I.g.kind == MAP_POLAR_LOG) launch_inject_t<2, MAP_POLAR_LOG, R>(I, st);
+    else return -1;
+  } else {
+    if (I.g.kind == MAP_IDENTITY) launch_inject_t<3, MAP_IDENTITY, R>(I, st);
+    else return -1;
+  }
+  return 0;
+}
+
+int launch_inject(const InjectLaunch& I, hipStream_t st) {
+  return I.fp64 ? launch_inject_r<double>(I, st) : launch_inject_r<float>(I, st);
 }
 
 int launch_tile_sort(const SortLaunch& S, hipStream_t st) {
