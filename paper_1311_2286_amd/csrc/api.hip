@@ -306,6 +306,11 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     L.phi2 = (double*)A(b);
     L.rhs = (double*)A(b);
     L.res = nullptr;
+    // stencil slots: faces x, y (, z); mixed pairs only for non-orthogonal maps
+    for (int k = 0; k < 9; ++k) {
+      bool used = (k < d) || (G.mixed && (d == 3 ? k >= 3 : (k == 3 || k == 4)));
+      L.S[k] = used ? (double*)A(b) : nullptr;
+    }
   }
   size_t cb = sizeof(double) * (size_t)ncells;
   G.bdir = (double*)A(cb);
@@ -313,6 +318,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   G.charge = (double*)A(cb);
   G.background = grid->background ? (double*)A(cb) : nullptr;
   G.partials = (double*)A(sizeof(double) * 1024);
+  G.mg_partials = (double*)A(sizeof(double) * (size_t)((g.n[0] + 63) / 64) * ((g.n[1] + 3) / 4) * g.n[2]);
   G.scalars = (double*)A(sizeof(double) * 16);
   G.mg_flag = (int*)A(sizeof(int) * 4);
   G.Ev = A(real_size(s) * ecomp(s) * (size_t)g.nverts);

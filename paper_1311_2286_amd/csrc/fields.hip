@@ -19,6 +19,8 @@
 // rediscretised from the analytic map at each level, coarsest level solved
 // by one workgroup.  Convergence is tested on the device (no host sync); the
 // kernels of later cycles return at once once the flag is set.
+#include <string.h>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -123,6 +125,7 @@ struct LevelArgs {
   const double* wf[3];
   const double* wlo[3];
   const double* we[3];
+  const double* S[9];
   const double* diag;
 };
 
@@ -142,6 +145,7 @@ static LevelArgs level_args(const GridCtx& G, int l) {
     a.wlo[i] = L.wlo[i];
     a.we[i] = L.we[i];
   }
+  for (int k = 0; k < 9; ++k) a.S[k] = L.S[k];
   a.diag = L.diag;
   return a;
 }
@@ -233,6 +237,43 @@ __global__ void diag_kernel(LevelArgs a, double* diag, double* bdir, double plo0
   if (bdir) bdir[c] = bd;
 }
 
+// Explicit stencil from the face / edge weights.  The energy's face terms
+// couple c and c + e_a with w_a(c).  An edge term W (D_i phi)(D_j phi) over
+// the 2x2 block with lower corner b couples the diagonal pair (b, b+e_i+e_j)
+// with +W/2 and the anti-diagonal pair (b+e_j, b+e_i) with -W/2; face pairs of
+// the block get no mixed contribution.  Upper-half storage:
+//   S[a](c)       = w_a(c)                (a = x, y, z; zero across a wall)
+//   S[+i+j](c)    =  W_ij(c) / 2
+//   S[+i-j](c)    = -W_ij(c - e_j) / 2
+__global__ void stencil_kernel(LevelArgs a, double* S0, double* S1, double* S2, double* S3, double* S4,
+                               double* S5, double* S6, double* S7, double* S8) {
+  long long nc = (long long)a.n[0] * a.n[1] * a.n[2];
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  int idx[3];
+  lin_to_idx(c, a.n, idx);
+  double* S[9] = {S0, S1, S2, S3, S4, S5, S6, S7, S8};
+  const int d = a.dim;
+  for (int ax = 0; ax < d; ++ax) {
+    bool wall = !a.periodic[ax] && idx[ax] == a.n[ax] - 1;
+    S[ax][c] = wall ? 0.0 : a.wf[ax][c];
+  }
+  if (!a.mixed) return;
+  // pairs (i, j) -> (diagonal slot, anti-diagonal slot)
+  const int pi[3] = {0, 0, 1}, pj[3] = {1, 2, 2};
+  const int np = (d == 3) ? 3 : 1;
+  for (int p = 0; p < np; ++p) {
+    const int i = pi[p], j = pj[p];
+    int b[3] = {idx[0], idx[1], idx[2]};
+    b[j] = wrapi(idx[j] - 1, a.n[j]);
+    double Wd = a.we[p][c];
+    double Wa = a.we[p][idx_to_lin(b, a.n)];
+    const int sd = (d == 3) ? 3 + 2 * p : 3, sa = (d == 3) ? 4 + 2 * p : 4;
+    S[sd][c] = 0.5 * Wd;
+    S[sa][c] = -0.5 * Wa;
+  }
+}
+
 void launch_coefficients(const GridCtx& G, int l, hipStream_t st) {
   const Level& L = G.lev[l];
   LevelArgs a = level_args(G, l);
@@ -241,6 +282,8 @@ void launch_coefficients(const GridCtx& G, int l, hipStream_t st) {
                      L.wlo[0], L.wlo[1], L.wlo[2], L.we[0], L.we[1], L.we[2]);
   hipLaunchKernelGGL(diag_kernel, dim3(blocks), dim3(256), 0, st, a, L.diag, l == 0 ? G.bdir : nullptr,
                      G.phi_lo[0], G.phi_lo[1], G.phi_lo[2], G.phi_hi[0], G.phi_hi[1], G.phi_hi[2]);
+  hipLaunchKernelGGL(stencil_kernel, dim3(blocks), dim3(256), 0, st, a, L.S[0], L.S[1], L.S[2], L.S[3],
+                     L.S[4], L.S[5], L.S[6], L.S[7], L.S[8]);
 }
 
 __global__ void jc_kernel(Geo g, double* Jc) {
@@ -340,13 +383,15 @@ constexpr int RED_BLOCKS = 256;
 __device__ inline double block_sum(double v) {
   __shared__ double sh[16];
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int nthreads = blockDim.x * blockDim.y * blockDim.z;
+  const int lane = tid & 63, w = tid >> 6;
   __syncthreads();
   if (lane == 0) sh[w] = v;
   __syncthreads();
   double s = 0.0;
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) / 64;
+  if (tid == 0) {
+    const int nw = (nthreads + 63) / 64;
     for (int i = 0; i < nw; ++i) s += sh[i];
   }
   return s;  // valid in thread 0
@@ -422,73 +467,82 @@ void launch_rhs(const GridCtx& G, hipStream_t st) {
 // ----------------------------------------------------------------------------
 // operator
 // ----------------------------------------------------------------------------
+// (A phi)_c from the explicit stencil: diag, the upper-half coefficients of c
+// and, by symmetry, those stored at the lower neighbours.  Across a wall the
+// lower neighbour term is absent and the upper coefficient is zero.
 __device__ inline double apply_A(const LevelArgs& a, const double* __restrict__ phi, const int* idx,
-                                 long long c) {
-  const int d = a.dim;
-  const double pc = phi[c];
-  double acc = 0.0;
-  for (int ax = 0; ax < d; ++ax) {
-    if (a.periodic[ax] || idx[ax] < a.n[ax] - 1) {
-      int nb[3] = {idx[0], idx[1], idx[2]};
-      nb[ax] = wrapi(idx[ax] + 1, a.n[ax]);
-      acc += a.wf[ax][c] * (phi[idx_to_lin(nb, a.n)] - pc);
-    } else if (a.dir[ax][1]) {
-      acc -= 2.0 * a.wf[ax][c] * pc;
+                                 long long cl) {
+  const int c = (int)cl;
+  const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+  const int sy = n0, sz = n0 * n1;
+  const int dxp = idx[0] + 1 < n0 ? 1 : (a.periodic[0] ? 1 - n0 : 0);
+  const int dxm = idx[0] > 0 ? -1 : (a.periodic[0] ? n0 - 1 : 0);
+  const int dyp = (idx[1] + 1 < n1 ? 1 : (a.periodic[1] ? 1 - n1 : 0)) * sy;
+  const int dym = (idx[1] > 0 ? -1 : (a.periodic[1] ? n1 - 1 : 0)) * sy;
+  double acc = a.diag[c] * phi[c];
+  acc += a.S[0][c] * phi[c + dxp];
+  if (dxm) acc += a.S[0][c + dxm] * phi[c + dxm];
+  acc += a.S[1][c] * phi[c + dyp];
+  if (dym) acc += a.S[1][c + dym] * phi[c + dym];
+  if (a.dim == 3) {
+    const int dzp = (idx[2] + 1 < n2 ? 1 : (a.periodic[2] ? 1 - n2 : 0)) * sz;
+    const int dzm = (idx[2] > 0 ? -1 : (a.periodic[2] ? n2 - 1 : 0)) * sz;
+    acc += a.S[2][c] * phi[c + dzp];
+    if (dzm) acc += a.S[2][c + dzm] * phi[c + dzm];
+    if (a.mixed) {
+      acc += a.S[3][c] * phi[c + dxp + dyp] + a.S[3][c + dxm + dym] * phi[c + dxm + dym];
+      acc += a.S[4][c] * phi[c + dxp + dym] + a.S[4][c + dxm + dyp] * phi[c + dxm + dyp];
+      acc += a.S[5][c] * phi[c + dxp + dzp] + a.S[5][c + dxm + dzm] * phi[c + dxm + dzm];
+      acc += a.S[6][c] * phi[c + dxp + dzm] + a.S[6][c + dxm + dzp] * phi[c + dxm + dzp];
+      acc += a.S[7][c] * phi[c + dyp + dzp] + a.S[7][c + dym + dzm] * phi[c + dym + dzm];
+      acc += a.S[8][c] * phi[c + dyp + dzm] + a.S[8][c + dym + dzp] * phi[c + dym + dzp];
     }
-    if (a.periodic[ax] || idx[ax] > 0) {
-      int nb[3] = {idx[0], idx[1], idx[2]};
-      nb[ax] = wrapi(idx[ax] - 1, a.n[ax]);
-      long long cn = idx_to_lin(nb, a.n);
-      acc += a.wf[ax][cn] * (phi[cn] - pc);
-    } else if (a.dir[ax][0]) {
-      acc -= 2.0 * a.wlo[ax][c] * pc;
-    }
-  }
-  if (a.mixed) {
-    const int pi[3] = {0, 0, 1}, pj[3] = {1, 2, 2};
-    const int np = (d == 3) ? 3 : 1;
-    for (int p = 0; p < np; ++p) {
-      const int i = pi[p], j = pj[p];
-      // 3x3 neighbourhood of c in the (i, j) plane
-      double nbv[3][3];
-      for (int oi = -1; oi <= 1; ++oi)
-        for (int oj = -1; oj <= 1; ++oj) {
-          int nb[3] = {idx[0], idx[1], idx[2]};
-          nb[i] = wrapi(idx[i] + oi, a.n[i]);
-          nb[j] = wrapi(idx[j] + oj, a.n[j]);
-          nbv[oi + 1][oj + 1] = (oi == 0 && oj == 0) ? pc : phi[idx_to_lin(nb, a.n)];
-        }
-      for (int si = 0; si < 2; ++si)
-        for (int sj = 0; sj < 2; ++sj) {
-          // edge block with lower corner b = c - (si, sj); c sits at (si, sj)
-          int b[3] = {idx[0], idx[1], idx[2]};
-          b[i] = wrapi(idx[i] - si, a.n[i]);
-          b[j] = wrapi(idx[j] - sj, a.n[j]);
-          double W = a.we[p][idx_to_lin(b, a.n)];
-          // block values phi(b + (ti, tj)) = nbv[ti - si + 1][tj - sj + 1]
-          double p00 = nbv[1 - si][1 - sj], p10 = nbv[2 - si][1 - sj];
-          double p01 = nbv[1 - si][2 - sj], p11 = nbv[2 - si][2 - sj];
-          double Di = 0.5 * ((p10 + p11) - (p00 + p01));
-          double Dj = 0.5 * ((p01 + p11) - (p00 + p10));
-          double uc = si ? 0.5 : -0.5, wc = sj ? 0.5 : -0.5;
-          acc -= W * (uc * Dj + wc * Di);
-        }
-    }
+  } else if (a.mixed) {
+    acc += a.S[3][c] * phi[c + dxp + dyp] + a.S[3][c + dxm + dym] * phi[c + dxm + dym];
+    acc += a.S[4][c] * phi[c + dxp + dym] + a.S[4][c + dxm + dyp] * phi[c + dxm + dyp];
   }
   return acc;
 }
 
+// Damped Jacobi sweep out = phi + omega (rhs - A phi) / diag, on a 3D launch
+// grid (x threads along i, blockIdx.y/z along j, k).  With partials != null
+// the squared residual of the input is summed per block (fixed order) for the
+// convergence test.
 __global__ __launch_bounds__(256) void smooth_kernel(LevelArgs a, const double* __restrict__ phi,
                                                      const double* __restrict__ rhs, double* out,
-                                                     double omega, const int* flag) {
+                                                     double omega, const int* flag, double* partials) {
   if (flag[0]) return;
-  long long nc = (long long)a.n[0] * a.n[1] * a.n[2];
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
-  int idx[3];
-  lin_to_idx(c, a.n, idx);
-  double r = rhs[c] - apply_A(a, phi, idx, c);
-  out[c] = phi[c] + omega * r / a.diag[c];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  double rr = 0.0;
+  if (i < a.n[0] && j < a.n[1]) {
+    const int idx[3] = {i, j, k};
+    const int c = i + a.n[0] * (j + a.n[1] * k);
+    double r = rhs[c] - apply_A(a, phi, idx, c);
+    out[c] = phi[c] + omega * r / a.diag[c];
+    rr = r * r;
+  }
+  if (partials) {
+    double t = block_sum(rr);
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+      partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = t;
+  }
+}
+
+__device__ inline double restrict_cell(const LevelArgs& fa, const double* __restrict__ phi,
+                                       const double* __restrict__ rhs, const int* I) {
+  const int d = fa.dim;
+  double s = 0.0;
+  const int nz = (d == 3) ? 2 : 1;
+  for (int sz = 0; sz < nz; ++sz)
+    for (int sy = 0; sy < 2; ++sy)
+      for (int sx = 0; sx < 2; ++sx) {
+        int idx[3] = {2 * I[0] + sx, 2 * I[1] + sy, (d == 3) ? 2 * I[2] + sz : 0};
+        int c = idx[0] + fa.n[0] * (idx[1] + fa.n[1] * idx[2]);
+        s += rhs[c] - apply_A(fa, phi, idx, c);
+      }
+  return s;
 }
 
 // coarse rhs = sum of the fine residuals of the 2^d children; coarse phi = 0
@@ -497,36 +551,17 @@ __global__ __launch_bounds__(256) void restrict_kernel(LevelArgs fa, const doubl
                                                        int nc2, double* crhs, double* cphi,
                                                        const int* flag) {
   if (flag[0]) return;
-  const int cn[3] = {nc0, nc1, nc2};
-  long long ncc = (long long)nc0 * nc1 * nc2;
-  long long C = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (C >= ncc) return;
-  int I[3];
-  lin_to_idx(C, cn, I);
-  const int d = fa.dim;
-  double s = 0.0;
-  const int nz = (d == 3) ? 2 : 1;
-  for (int sz = 0; sz < nz; ++sz)
-    for (int sy = 0; sy < 2; ++sy)
-      for (int sx = 0; sx < 2; ++sx) {
-        int idx[3] = {2 * I[0] + sx, 2 * I[1] + sy, (d == 3) ? 2 * I[2] + sz : 0};
-        long long c = idx_to_lin(idx, fa.n);
-        s += rhs[c] - apply_A(fa, phi, idx, c);
-      }
-  crhs[C] = s;
+  const int I[3] = {(int)(blockIdx.x * blockDim.x + threadIdx.x), (int)(blockIdx.y * blockDim.y + threadIdx.y),
+                    (int)blockIdx.z};
+  if (I[0] >= nc0 || I[1] >= nc1) return;
+  const int C = I[0] + nc0 * (I[1] + nc1 * I[2]);
+  crhs[C] = restrict_cell(fa, phi, rhs, I);
   cphi[C] = 0.0;
 }
 
-// fine phi += (3/4, 1/4)-tensor interpolation of the coarse correction
-__global__ __launch_bounds__(256) void prolong_kernel(LevelArgs fa, double* phi, const double* __restrict__ cphi,
-                                                      int nc0, int nc1, int nc2, const int* flag) {
-  if (flag[0]) return;
-  const int cn[3] = {nc0, nc1, nc2};
-  long long nc = (long long)fa.n[0] * fa.n[1] * fa.n[2];
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
-  int idx[3];
-  lin_to_idx(c, fa.n, idx);
+// (3/4, 1/4)-tensor interpolation of the coarse correction at fine cell idx
+__device__ inline double prolong_cell(const LevelArgs& fa, const double* __restrict__ cphi, const int* cn,
+                                      const int* idx) {
   const int d = fa.dim;
   int I[3] = {idx[0] >> 1, idx[1] >> 1, idx[2] >> 1};
   int J[3];
@@ -564,37 +599,100 @@ __global__ __launch_bounds__(256) void prolong_kernel(LevelArgs fa, double* phi,
           K[ax] = t[ax] ? J[ax] : I[ax];
           w *= t[ax] ? 0.25 * sgn[ax] : 0.75;
         }
-        acc += w * cphi[idx_to_lin(K, cn)];
+        acc += w * cphi[K[0] + cn[0] * (K[1] + cn[1] * K[2])];
       }
-  phi[c] += acc;
+  return acc;
 }
 
-// coarsest level: one workgroup, damped Jacobi sweeps in place (via scratch)
-__global__ __launch_bounds__(256) void coarse_kernel(LevelArgs a, double* phi, double* tmp,
-                                                     const double* __restrict__ rhs, int sweeps,
-                                                     int singular, const int* flag) {
+__global__ __launch_bounds__(256) void prolong_kernel(LevelArgs fa, double* phi, const double* __restrict__ cphi,
+                                                      int nc0, int nc1, int nc2, const int* flag) {
   if (flag[0]) return;
+  const int cn[3] = {nc0, nc1, nc2};
+  const int idx[3] = {(int)(blockIdx.x * blockDim.x + threadIdx.x), (int)(blockIdx.y * blockDim.y + threadIdx.y),
+                      (int)blockIdx.z};
+  if (idx[0] >= fa.n[0] || idx[1] >= fa.n[1]) return;
+  const int c = idx[0] + fa.n[0] * (idx[1] + fa.n[1] * idx[2]);
+  phi[c] += prolong_cell(fa, cphi, cn, idx);
+}
+
+// The V-cycle below level ls (all levels of at most SMALL_CELLS cells) in one
+// workgroup: smoothing, restriction, coarsest solve (many damped Jacobi
+// sweeps), prolongation, with workgroup barriers between the phases.
+constexpr int SMALL_CELLS = 4096;
+constexpr int MAX_SMALL = 8;
+struct SmallLevels {
+  int nl;
+  LevelArgs a[MAX_SMALL];
+  double* phi[MAX_SMALL];
+  double* phi2[MAX_SMALL];
+  double* rhs[MAX_SMALL];
+};
+
+__device__ inline void block_smooth(const LevelArgs& a, const double* phi, const double* rhs, double* out,
+                                    double omega) {
   const int nc = a.n[0] * a.n[1] * a.n[2];
-  for (int it = 0; it < sweeps; ++it) {
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-      int idx[3];
-      lin_to_idx(c, a.n, idx);
-      double r = rhs[c] - apply_A(a, phi, idx, c);
-      tmp[c] = phi[c] + 0.8 * r / a.diag[c];
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    int idx[3] = {c % a.n[0], (c / a.n[0]) % a.n[1], c / (a.n[0] * a.n[1])};
+    double r = rhs[c] - apply_A(a, phi, idx, c);
+    out[c] = phi[c] + omega * r / a.diag[c];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels S, int nu1, int nu2, int coarse_sweeps,
+                                                            int singular, const int* flag) {
+  if (flag[0]) return;
+  const double omega = 0.8;
+  const int last = S.nl - 1;
+  for (int l = 0; l < last; ++l) {
+    const LevelArgs& a = S.a[l];
+    for (int s = 0; s < nu1; s += 2) {
+      block_smooth(a, S.phi[l], S.rhs[l], S.phi2[l], omega);
+      block_smooth(a, S.phi2[l], S.rhs[l], S.phi[l], omega);
     }
-    __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) phi[c] = tmp[c];
+    const LevelArgs& ca = S.a[l + 1];
+    const int ncc = ca.n[0] * ca.n[1] * ca.n[2];
+    for (int C = threadIdx.x; C < ncc; C += blockDim.x) {
+      int I[3] = {C % ca.n[0], (C / ca.n[0]) % ca.n[1], C / (ca.n[0] * ca.n[1])};
+      S.rhs[l + 1][C] = restrict_cell(a, S.phi[l], S.rhs[l], I);
+      S.phi[l + 1][C] = 0.0;
+    }
     __syncthreads();
   }
-  if (singular) {
-    __shared__ double mean;
-    if (threadIdx.x == 0) {
+  {
+    const LevelArgs& a = S.a[last];
+    for (int it = 0; it < coarse_sweeps; it += 2) {
+      block_smooth(a, S.phi[last], S.rhs[last], S.phi2[last], omega);
+      block_smooth(a, S.phi2[last], S.rhs[last], S.phi[last], omega);
+    }
+    if (singular) {
+      __shared__ double part[16];
+      const int nc = a.n[0] * a.n[1] * a.n[2];
       double s = 0.0;
-      for (int c = 0; c < nc; ++c) s += phi[c];
-      mean = s / nc;
+      for (int c = threadIdx.x; c < nc; c += blockDim.x) s += S.phi[last][c];
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+      if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+      __syncthreads();
+      double mean = 0.0;
+      for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) mean += part[w];
+      mean /= nc;
+      for (int c = threadIdx.x; c < nc; c += blockDim.x) S.phi[last][c] -= mean;
+      __syncthreads();
+    }
+  }
+  for (int l = last - 1; l >= 0; --l) {
+    const LevelArgs& a = S.a[l];
+    const LevelArgs& ca = S.a[l + 1];
+    const int nc = a.n[0] * a.n[1] * a.n[2];
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      int idx[3] = {c % a.n[0], (c / a.n[0]) % a.n[1], c / (a.n[0] * a.n[1])};
+      S.phi[l][c] += prolong_cell(a, S.phi[l + 1], ca.n, idx);
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) phi[c] -= mean;
+    for (int s = 0; s < nu2; s += 2) {
+      block_smooth(a, S.phi[l], S.rhs[l], S.phi2[l], omega);
+      block_smooth(a, S.phi2[l], S.rhs[l], S.phi[l], omega);
+    }
   }
 }
 
@@ -602,17 +700,19 @@ __global__ void residual_norm_kernel(LevelArgs a, const double* __restrict__ phi
                                      const double* __restrict__ rhs, double* partials,
                                      const int* flag) {
   if (flag[0]) return;
-  long long nc = (long long)a.n[0] * a.n[1] * a.n[2];
-  double s = 0.0;
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < nc;
-       c += (long long)gridDim.x * blockDim.x) {
-    int idx[3];
-    lin_to_idx(c, a.n, idx);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  double rr = 0.0;
+  if (i < a.n[0] && j < a.n[1]) {
+    const int idx[3] = {i, j, k};
+    const int c = i + a.n[0] * (j + a.n[1] * k);
     double r = rhs[c] - apply_A(a, phi, idx, c);
-    s += r * r;
+    rr = r * r;
   }
-  double t = block_sum(s);
-  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  double t = block_sum(rr);
+  if (threadIdx.x == 0 && threadIdx.y == 0)
+    partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = t;
 }
 
 __global__ void mg_reset_kernel(int* flag) {
@@ -620,38 +720,64 @@ __global__ void mg_reset_kernel(int* flag) {
   flag[1] = 0;
 }
 
-static void vcycle(const GridCtx& G, int l, int nu1, int nu2, hipStream_t st) {
-  const Level& L = G.lev[l];
-  LevelArgs a = level_args(G, l);
-  unsigned blocks = (unsigned)((L.ncells + 255) / 256);
-  if (l == G.nlev - 1) {
-    hipLaunchKernelGGL(coarse_kernel, dim3(1), dim3(256), 0, st, a, L.phi, L.phi2, L.rhs, 60,
-                       G.all_periodic, G.mg_flag);
+static dim3 grid3(const Level& L) {
+  return dim3((unsigned)((L.n[0] + 63) / 64), (unsigned)((L.n[1] + 3) / 4), (unsigned)L.n[2]);
+}
+static const dim3 BLOCK3(64, 4, 1);
+
+static int first_small_level(const GridCtx& G) {
+  int ls = G.nlev - 1;
+  while (ls > 0 && G.lev[ls - 1].ncells <= SMALL_CELLS && G.nlev - (ls - 1) <= MAX_SMALL) --ls;
+  return ls;
+}
+
+// One V-cycle from level l.  With partials != null, the last smoothing sweep
+// on level 0 also sums the squared residual (of its input) per block.
+static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, hipStream_t st) {
+  const int ls = first_small_level(G);
+  if (l >= ls) {
+    SmallLevels S;
+    memset(&S, 0, sizeof(S));
+    S.nl = G.nlev - l;
+    for (int k = 0; k < S.nl; ++k) {
+      S.a[k] = level_args(G, l + k);
+      S.phi[k] = G.lev[l + k].phi;
+      S.phi2[k] = G.lev[l + k].phi2;
+      S.rhs[k] = G.lev[l + k].rhs;
+    }
+    hipLaunchKernelGGL(small_vcycle_kernel, dim3(1), dim3(1024), 0, st, S, nu1, nu2, 60, G.all_periodic,
+                       (const int*)G.mg_flag);
     return;
   }
+  const Level& L = G.lev[l];
+  LevelArgs a = level_args(G, l);
+  const dim3 gr = grid3(L);
   const double omega = 0.8;
   for (int s = 0; s < nu1; s += 2) {
-    hipLaunchKernelGGL(smooth_kernel, dim3(blocks), dim3(256), 0, st, a, L.phi, L.rhs, L.phi2, omega, G.mg_flag);
-    hipLaunchKernelGGL(smooth_kernel, dim3(blocks), dim3(256), 0, st, a, L.phi2, L.rhs, L.phi, omega, G.mg_flag);
+    hipLaunchKernelGGL(smooth_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, L.phi2, omega, G.mg_flag, (double*)nullptr);
+    hipLaunchKernelGGL(smooth_kernel, gr, BLOCK3, 0, st, a, L.phi2, L.rhs, L.phi, omega, G.mg_flag, (double*)nullptr);
   }
   const Level& C = G.lev[l + 1];
-  unsigned cblocks = (unsigned)((C.ncells + 255) / 256);
-  hipLaunchKernelGGL(restrict_kernel, dim3(cblocks), dim3(256), 0, st, a, L.phi, L.rhs, C.n[0], C.n[1],
-                     C.n[2], C.rhs, C.phi, G.mg_flag);
-  vcycle(G, l + 1, nu1, nu2, st);
-  hipLaunchKernelGGL(prolong_kernel, dim3(blocks), dim3(256), 0, st, a, L.phi, C.phi, C.n[0], C.n[1],
-                     C.n[2], G.mg_flag);
+  hipLaunchKernelGGL(restrict_kernel, grid3(C), BLOCK3, 0, st, a, L.phi, L.rhs, C.n[0], C.n[1], C.n[2], C.rhs,
+                     C.phi, G.mg_flag);
+  vcycle(G, l + 1, nu1, nu2, nullptr, st);
+  hipLaunchKernelGGL(prolong_kernel, gr, BLOCK3, 0, st, a, L.phi, C.phi, C.n[0], C.n[1], C.n[2], G.mg_flag);
   for (int s = 0; s < nu2; s += 2) {
-    hipLaunchKernelGGL(smooth_kernel, dim3(blocks), dim3(256), 0, st, a, L.phi, L.rhs, L.phi2, omega, G.mg_flag);
-    hipLaunchKernelGGL(smooth_kernel, dim3(blocks), dim3(256), 0, st, a, L.phi2, L.rhs, L.phi, omega, G.mg_flag);
+    hipLaunchKernelGGL(smooth_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, L.phi2, omega, G.mg_flag, (double*)nullptr);
+    hipLaunchKernelGGL(smooth_kernel, gr, BLOCK3, 0, st, a, L.phi2, L.rhs, L.phi, omega, G.mg_flag,
+                       (s + 2 >= nu2) ? partials : (double*)nullptr);
   }
 }
 
 // Solve A phi = rhs on level 0 (phi holds the initial guess).  Returns the
-// number of cycles launched; the number executed is in mg_flag[1].
+// number of cycles launched; the number executed is in mg_flag[1].  The
+// convergence test after a cycle uses the residual entering its last sweep
+// (an upper bound of the final one in practice).
 int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st) {
   const Level& L = G.lev[0];
   LevelArgs a = level_args(G, 0);
+  const dim3 gr = grid3(L);
+  const int nblk = (int)(gr.x * gr.y * gr.z);
   hipLaunchKernelGGL(mg_reset_kernel, dim3(1), dim3(1), 0, st, G.mg_flag);
   // |b|^2
   hipLaunchKernelGGL(reduce_partial_kernel, dim3(RED_BLOCKS), dim3(256), 0, st, L.rhs, (const double*)nullptr,
@@ -660,16 +786,18 @@ int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int 
                      0.0, (const double*)nullptr, (int*)nullptr, 0);
   const double rtol2 = rtol * rtol;
   // initial residual
-  hipLaunchKernelGGL(residual_norm_kernel, dim3(RED_BLOCKS), dim3(256), 0, st, a, L.phi, L.rhs, G.partials,
-                     G.mg_flag);
-  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.partials, RED_BLOCKS, G.scalars + 1, 1,
+  hipLaunchKernelGGL(residual_norm_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, G.mg_partials, G.mg_flag);
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.mg_partials, nblk, G.scalars + 1, 1,
                      rtol2, G.scalars + 0, G.mg_flag, 0);
   for (int cyc = 0; cyc < max_cycles; ++cyc) {
-    vcycle(G, 0, nu1, nu2, st);
-    hipLaunchKernelGGL(residual_norm_kernel, dim3(RED_BLOCKS), dim3(256), 0, st, a, L.phi, L.rhs, G.partials,
-                       G.mg_flag);
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.partials, RED_BLOCKS, G.scalars + 1,
-                       1, rtol2, G.scalars + 0, G.mg_flag, 1);
+    if (first_small_level(G) == 0) {
+      vcycle(G, 0, nu1, nu2, nullptr, st);
+      hipLaunchKernelGGL(residual_norm_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, G.mg_partials, G.mg_flag);
+    } else {
+      vcycle(G, 0, nu1, nu2, G.mg_partials, st);
+    }
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.mg_partials, nblk, G.scalars + 1, 1,
+                       rtol2, G.scalars + 0, G.mg_flag, 1);
   }
   return max_cycles;
 }

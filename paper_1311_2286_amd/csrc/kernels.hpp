@@ -99,6 +99,9 @@ struct Level {
   double* wf[3];     // upper-face coefficient of each cell, a^{aa} dV / h_a^2
   double* wlo[3];    // lower wall-face coefficient (bounded axes, cells at i_a = 0)
   double* we[3];     // mixed-term coefficient at the upper corner edge, pairs (01, 02, 12)
+  // explicit operator, upper half of the symmetric stencil: S[k][c] couples c
+  // and c + o_k, o = (+x, +y, +z, +x+y, +x-y, +x+z, +x-z, +y+z, +y-z)
+  double* S[9];
   double* diag;
   double* phi;
   double* phi2;      // ping-pong
@@ -120,6 +123,7 @@ struct GridCtx {
   double* charge;
   double* background;
   double* partials;   // reduction scratch (>= 1024 doubles)
+  double* mg_partials; // per-block residual sums of the level-0 sweep grid
   double* scalars;    // device scalars: [0] |b|^2 [1] |r|^2 [2] sumJphi [3] mean [4..] misc
   int* mg_flag;       // [0] converged [1] cycles done
   void* Ev;           // vertex field (float or double, interleaved)
