@@ -281,7 +281,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     }
     ++nl;
     bool can = true;
-    for (int a = 0; a < d; ++a) can = can && (n[a] % 2 == 0) && (n[a] / 2 >= 2);
+    for (int a = 0; a < d; ++a) can = can && (n[a] % 2 == 0) && (n[a] / 2 >= 4);
     if (!can) break;
     for (int a = 0; a < d; ++a) n[a] /= 2;
   }
@@ -305,7 +305,8 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     L.phi = (double*)A(b);
     L.phi2 = (double*)A(b);
     L.rhs = (double*)A(b);
-    L.res = nullptr;
+    L.res = (double*)A(b);
+    L.aux = (double*)A(b);
     // stencil slots: faces x, y (, z); mixed pairs only for non-orthogonal maps
     for (int k = 0; k < 9; ++k) {
       bool used = (k < d) || (G.mixed && (d == 3 ? k >= 3 : (k == 3 || k == 4)));

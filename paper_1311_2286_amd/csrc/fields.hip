@@ -545,17 +545,36 @@ __device__ inline double restrict_cell(const LevelArgs& fa, const double* __rest
   return s;
 }
 
-// coarse rhs = sum of the fine residuals of the 2^d children; coarse phi = 0
-__global__ __launch_bounds__(256) void restrict_kernel(LevelArgs fa, const double* __restrict__ phi,
-                                                       const double* __restrict__ rhs, int nc0, int nc1,
-                                                       int nc2, double* crhs, double* cphi,
+// residual r = rhs - A phi (coalesced pass over the fine level)
+__global__ __launch_bounds__(256) void residual_kernel(LevelArgs a, const double* __restrict__ phi,
+                                                       const double* __restrict__ rhs, double* res,
                                                        const int* flag) {
   if (flag[0]) return;
-  const int I[3] = {(int)(blockIdx.x * blockDim.x + threadIdx.x), (int)(blockIdx.y * blockDim.y + threadIdx.y),
-                    (int)blockIdx.z};
-  if (I[0] >= nc0 || I[1] >= nc1) return;
-  const int C = I[0] + nc0 * (I[1] + nc1 * I[2]);
-  crhs[C] = restrict_cell(fa, phi, rhs, I);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= a.n[0] || j >= a.n[1]) return;
+  const int idx[3] = {i, j, k};
+  const int c = i + a.n[0] * (j + a.n[1] * k);
+  res[c] = rhs[c] - apply_A(a, phi, idx, c);
+}
+
+// coarse rhs = sum of the residuals of the 2^d children; coarse phi = 0
+__global__ __launch_bounds__(256) void restrict_kernel(int dim, int nf0, int nf1, const double* __restrict__ res,
+                                                       int nc0, int nc1, double* crhs, double* cphi,
+                                                       const int* flag) {
+  if (flag[0]) return;
+  const int I0 = blockIdx.x * blockDim.x + threadIdx.x, I1 = blockIdx.y * blockDim.y + threadIdx.y;
+  const int I2 = blockIdx.z;
+  if (I0 >= nc0 || I1 >= nc1) return;
+  const int C = I0 + nc0 * (I1 + nc1 * I2);
+  const int f = 2 * I0 + nf0 * (2 * I1 + nf1 * (dim == 3 ? 2 * I2 : 0));
+  double s = res[f] + res[f + 1] + res[f + nf0] + res[f + nf0 + 1];
+  if (dim == 3) {
+    const int fz = f + nf0 * nf1;
+    s += res[fz] + res[fz + 1] + res[fz + nf0] + res[fz + nf0 + 1];
+  }
+  crhs[C] = s;
   cphi[C] = 0.0;
 }
 
@@ -620,13 +639,95 @@ __global__ __launch_bounds__(256) void prolong_kernel(LevelArgs fa, double* phi,
 // sweeps), prolongation, with workgroup barriers between the phases.
 constexpr int SMALL_CELLS = 4096;
 constexpr int MAX_SMALL = 8;
+constexpr int COARSE_LDS = 384;  // coarsest levels up to this many cells are solved in LDS
 struct SmallLevels {
   int nl;
   LevelArgs a[MAX_SMALL];
   double* phi[MAX_SMALL];
   double* phi2[MAX_SMALL];
   double* rhs[MAX_SMALL];
+  double* res[MAX_SMALL];
+  double* aux[MAX_SMALL];
 };
+
+// sum over the workgroup, returned to every thread
+__device__ inline double block_allsum(double v) {
+  __shared__ double sh[16];
+  __shared__ double tot;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) s += sh[i];
+    tot = s;
+  }
+  __syncthreads();
+  return tot;
+}
+
+// Coarsest-level solve inside one workgroup: Jacobi-preconditioned conjugate
+// gradients on -A (A is negative semi-definite) to a relative residual of
+// 1e-13 or maxit iterations; singular (all-periodic) problems are solved on
+// the zero-mean subspace and the result shifted to zero mean.
+__device__ inline void block_cg(const LevelArgs& a, double* x, const double* b, double* r, double* p, double* q,
+                                int maxit, int singular) {
+  const int nc = a.n[0] * a.n[1] * a.n[2];
+  double bmean = 0.0;
+  if (singular) {
+    double s = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) s += b[c];
+    bmean = block_allsum(s) / nc;
+  }
+  double rz = 0.0, bb = 0.0;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    int idx[3] = {c % a.n[0], (c / a.n[0]) % a.n[1], c / (a.n[0] * a.n[1])};
+    double bc = b[c] - bmean;
+    double rc = bc - apply_A(a, x, idx, c);
+    r[c] = rc;
+    double z = rc / a.diag[c];
+    p[c] = z;
+    rz += rc * z;
+    bb += bc * bc;
+  }
+  rz = block_allsum(rz);
+  bb = block_allsum(bb);
+  for (int it = 0; it < maxit; ++it) {
+    double pq = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      int idx[3] = {c % a.n[0], (c / a.n[0]) % a.n[1], c / (a.n[0] * a.n[1])};
+      double qc = apply_A(a, p, idx, c);
+      q[c] = qc;
+      pq += p[c] * qc;
+    }
+    pq = block_allsum(pq);
+    if (pq == 0.0) break;
+    const double alpha = rz / pq;
+    double rr = 0.0, rz2 = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      x[c] += alpha * p[c];
+      double rc = r[c] - alpha * q[c];
+      r[c] = rc;
+      rr += rc * rc;
+      rz2 += rc * rc / a.diag[c];
+    }
+    rr = block_allsum(rr);
+    rz2 = block_allsum(rz2);
+    if (rr <= 1e-26 * bb || rz == 0.0) break;
+    const double beta = rz2 / rz;
+    rz = rz2;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) p[c] = r[c] / a.diag[c] + beta * p[c];
+    __syncthreads();
+  }
+  if (singular) {
+    double s = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) s += x[c];
+    const double mean = block_allsum(s) / nc;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) x[c] -= mean;
+  }
+  __syncthreads();
+}
 
 __device__ inline void block_smooth(const LevelArgs& a, const double* phi, const double* rhs, double* out,
                                     double omega) {
@@ -661,23 +762,29 @@ __global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels S, int n
   }
   {
     const LevelArgs& a = S.a[last];
-    for (int it = 0; it < coarse_sweeps; it += 2) {
-      block_smooth(a, S.phi[last], S.rhs[last], S.phi2[last], omega);
-      block_smooth(a, S.phi2[last], S.rhs[last], S.phi[last], omega);
-    }
-    if (singular) {
-      __shared__ double part[16];
-      const int nc = a.n[0] * a.n[1] * a.n[2];
-      double s = 0.0;
-      for (int c = threadIdx.x; c < nc; c += blockDim.x) s += S.phi[last][c];
-      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-      if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    const int ncl = a.n[0] * a.n[1] * a.n[2];
+    const int maxit = min(2000, 2 * ncl + 20);
+    if (ncl <= COARSE_LDS) {
+      // coarsest level held in LDS: operator, potential, right side, CG vectors
+      __shared__ double lphi[COARSE_LDS], lrhs[COARSE_LDS], ldiag[COARSE_LDS];
+      __shared__ double lr[COARSE_LDS], lp[COARSE_LDS], lq[COARSE_LDS];
+      __shared__ double lS[9][COARSE_LDS];
+      LevelArgs la = a;
+      for (int c = threadIdx.x; c < ncl; c += blockDim.x) {
+        lphi[c] = S.phi[last][c];
+        lrhs[c] = S.rhs[last][c];
+        ldiag[c] = a.diag[c];
+        for (int k = 0; k < 9; ++k)
+          if (a.S[k]) lS[k][c] = a.S[k][c];
+      }
+      la.diag = ldiag;
+      for (int k = 0; k < 9; ++k) la.S[k] = a.S[k] ? lS[k] : nullptr;
       __syncthreads();
-      double mean = 0.0;
-      for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) mean += part[w];
-      mean /= nc;
-      for (int c = threadIdx.x; c < nc; c += blockDim.x) S.phi[last][c] -= mean;
+      block_cg(la, lphi, lrhs, lr, lp, lq, maxit, singular);
+      for (int c = threadIdx.x; c < ncl; c += blockDim.x) S.phi[last][c] = lphi[c];
       __syncthreads();
+    } else {
+      block_cg(a, S.phi[last], S.rhs[last], S.res[last], S.aux[last], S.phi2[last], maxit, singular);
     }
   }
   for (int l = last - 1; l >= 0; --l) {
@@ -744,8 +851,10 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
       S.phi[k] = G.lev[l + k].phi;
       S.phi2[k] = G.lev[l + k].phi2;
       S.rhs[k] = G.lev[l + k].rhs;
+      S.res[k] = G.lev[l + k].res;
+      S.aux[k] = G.lev[l + k].aux;
     }
-    hipLaunchKernelGGL(small_vcycle_kernel, dim3(1), dim3(1024), 0, st, S, nu1, nu2, 60, G.all_periodic,
+    hipLaunchKernelGGL(small_vcycle_kernel, dim3(1), dim3(1024), 0, st, S, nu1, nu2, 40, G.all_periodic,
                        (const int*)G.mg_flag);
     return;
   }
@@ -758,8 +867,9 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
     hipLaunchKernelGGL(smooth_kernel, gr, BLOCK3, 0, st, a, L.phi2, L.rhs, L.phi, omega, G.mg_flag, (double*)nullptr);
   }
   const Level& C = G.lev[l + 1];
-  hipLaunchKernelGGL(restrict_kernel, grid3(C), BLOCK3, 0, st, a, L.phi, L.rhs, C.n[0], C.n[1], C.n[2], C.rhs,
-                     C.phi, G.mg_flag);
+  hipLaunchKernelGGL(residual_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, L.res, G.mg_flag);
+  hipLaunchKernelGGL(restrict_kernel, grid3(C), BLOCK3, 0, st, G.g.dim, L.n[0], L.n[1], (const double*)L.res,
+                     C.n[0], C.n[1], C.rhs, C.phi, G.mg_flag);
   vcycle(G, l + 1, nu1, nu2, nullptr, st);
   hipLaunchKernelGGL(prolong_kernel, gr, BLOCK3, 0, st, a, L.phi, C.phi, C.n[0], C.n[1], C.n[2], G.mg_flag);
   for (int s = 0; s < nu2; s += 2) {

@@ -107,6 +107,7 @@ struct Level {
   double* phi2;      // ping-pong
   double* rhs;
   double* res;
+  double* aux;       // coarsest-level solver vector
 };
 
 struct GridCtx {

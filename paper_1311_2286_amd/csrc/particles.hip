@@ -743,21 +743,89 @@ __global__ void inject_finish_kernel(int* d_n, const int* count, int cap) {
 // ----------------------------------------------------------------------------
 // tile sort
 // ----------------------------------------------------------------------------
+// Each workgroup sorts one chunk of SORT_CHUNK consecutive particles.  Global
+// atomics on the tile counters cost a round trip through the memory-side
+// cache, so the chunk is first histogrammed in LDS over the tile range it
+// spans (particles are nearly tile-sorted: the range is small) and only one
+// global atomic per (chunk, tile) is issued.  Chunks spanning more than
+// SORT_BINS tiles (the first sort of unsorted input) use per-wave aggregated
+// global atomics instead.
+constexpr int SORT_CHUNK = 4096;
+constexpr int SORT_BINS = 2048;
+
+template <int D>
+__device__ inline int tile_or_dead(int k, const Geo& g) {
+  return k < 0 ? g.ntiles : tile_of_key<D>(k, g);
+}
+
+// block-wide min / max of v (thread 0 broadcasts through LDS)
+__device__ inline void block_minmax(int v_min, int v_max, int* out) {
+  __shared__ int smin[8], smax[8];
+  for (int o = 32; o > 0; o >>= 1) {
+    v_min = min(v_min, __shfl_xor(v_min, o, 64));
+    v_max = max(v_max, __shfl_xor(v_max, o, 64));
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    smin[w] = v_min;
+    smax[w] = v_max;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int a = smin[0], b = smax[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+      a = min(a, smin[i]);
+      b = max(b, smax[i]);
+    }
+    out[0] = a;
+    out[1] = b;
+  }
+  __syncthreads();
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void tile_hist_kernel(const int32_t* __restrict__ key,
                                                         const int* __restrict__ d_n, int* counts,
                                                         Geo g) {
+  __shared__ int bins[SORT_BINS];
+  __shared__ int range[2];
+  __shared__ int dead;
   const int n = *d_n;
-  const int stride = gridDim.x * blockDim.x;
-  for (int p0 = blockIdx.x * blockDim.x; p0 < n; p0 += stride) {
-    int p = p0 + threadIdx.x;
-    bool active = p < n;
-    int t = 0;
-    if (active) {
-      int k = key[p];
-      t = k < 0 ? g.ntiles : tile_of_key<D>(k, g);
+  const int p0 = blockIdx.x * SORT_CHUNK;
+  if (p0 >= n) return;
+  const int p1 = min(n, p0 + SORT_CHUNK);
+  int tmin = 1 << 30, tmax = -1;
+  for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    int k = key[p];
+    if (k < 0) continue;
+    int t = tile_of_key<D>(k, g);
+    tmin = min(tmin, t);
+    tmax = max(tmax, t);
+  }
+  if (threadIdx.x == 0) dead = 0;
+  block_minmax(tmin, tmax, range);
+  const int lo = range[0];
+  if (range[1] - lo < SORT_BINS) {
+    for (int b = threadIdx.x; b < SORT_BINS; b += blockDim.x) bins[b] = 0;
+    __syncthreads();
+    for (int q = p0; q < p1; q += blockDim.x) {
+      int p = q + threadIdx.x;
+      int k = p < p1 ? key[p] : 0;
+      bool live = p < p1 && k >= 0;
+      if (p < p1 && k < 0) atomicAdd(&dead, 1);
+      agg_inc(bins, live ? tile_of_key<D>(k, g) - lo : 0, live);
     }
-    agg_inc(counts, t, active);
+    __syncthreads();
+    for (int b = threadIdx.x; b <= range[1] - lo; b += blockDim.x)
+      if (bins[b]) atomicAdd(&counts[lo + b], bins[b]);
+    if (threadIdx.x == 0 && dead) atomicAdd(&counts[g.ntiles], dead);
+  } else {
+    for (int q = p0; q < p1; q += blockDim.x) {
+      int p = q + threadIdx.x;
+      bool active = p < p1;
+      int t = active ? tile_or_dead<D>(key[p], g) : 0;
+      agg_inc(counts, t, active);
+    }
   }
 }
 
@@ -823,16 +891,52 @@ __global__ __launch_bounds__(256) void tile_scatter_kernel(
     R* o0o, R* o1o, R* o2o, const R* __restrict__ v0i, const R* __restrict__ v1i,
     const R* __restrict__ v2i, R* v0o, R* v1o, R* v2o, const uint32_t* __restrict__ id_in,
     uint32_t* id_out) {
+  __shared__ int bins[SORT_BINS];
+  __shared__ int rank[SORT_CHUNK];
+  __shared__ int range[2];
   const int n = start[g.ntiles + 1];
-  const int stride = gridDim.x * blockDim.x;
-  for (int p0 = blockIdx.x * blockDim.x; p0 < n; p0 += stride) {
-    int p = p0 + threadIdx.x;
-    bool active = p < n;
-    int k = -1;
-    if (active) k = key_in[p];
+  const int p0 = blockIdx.x * SORT_CHUNK;
+  if (p0 >= n) return;
+  const int p1 = min(n, p0 + SORT_CHUNK);
+  int tmin = 1 << 30, tmax = -1;
+  for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    int k = key_in[p];
+    if (k < 0) continue;
+    int t = tile_of_key<D>(k, g);
+    tmin = min(tmin, t);
+    tmax = max(tmax, t);
+  }
+  block_minmax(tmin, tmax, range);
+  const int lo = range[0];
+  const bool local = range[1] - lo < SORT_BINS;
+  if (local) {
+    for (int b = threadIdx.x; b < SORT_BINS; b += blockDim.x) bins[b] = 0;
+    __syncthreads();
+    // rank of each particle among the chunk's particles of its tile
+    for (int q = p0; q < p1; q += blockDim.x) {
+      int p = q + threadIdx.x;
+      int k = p < p1 ? key_in[p] : -1;
+      bool live = k >= 0;
+      int r = agg_inc(bins, live ? tile_of_key<D>(k, g) - lo : 0, live);
+      if (p < p1) rank[p - p0] = r;
+    }
+    __syncthreads();
+    // one global reservation per tile present in the chunk
+    for (int b = threadIdx.x; b <= range[1] - lo; b += blockDim.x)
+      bins[b] = bins[b] ? atomicAdd(&cursor[lo + b], bins[b]) : 0;
+    __syncthreads();
+  }
+  for (int q = p0; q < p1; q += blockDim.x) {
+    int p = q + threadIdx.x;
+    bool active = p < p1;
+    int k = active ? key_in[p] : -1;
     bool live = active && k >= 0;
     int t = live ? tile_of_key<D>(k, g) : 0;
-    int dst = agg_inc(cursor, t, live);
+    int dst;
+    if (local)
+      dst = live ? bins[t - lo] + rank[p - p0] : 0;
+    else
+      dst = agg_inc(cursor, t, live);
     if (live) {
       key_out[dst] = k;
       o0o[dst] = o0i[p];
@@ -1012,8 +1116,9 @@ int launch_inject(const InjectLaunch& I, hipStream_t st) {
 
 int launch_tile_sort(const SortLaunch& S, hipStream_t st) {
   const Geo& g = S.g;
-  int blocks = (int)((S.capacity + 255) / 256);
-  if (blocks > 8192) blocks = 8192;
+  // one workgroup per chunk of the buffer's capacity (chunks past the live
+  // count return at once)
+  int blocks = (int)((S.capacity + SORT_CHUNK - 1) / SORT_CHUNK);
   if (blocks < 1) blocks = 1;
   if (g.dim == 2)
     hipLaunchKernelGGL(tile_hist_kernel<2>, dim3(blocks), dim3(256), 0, st, S.key_in, S.d_n, S.counts, g);
