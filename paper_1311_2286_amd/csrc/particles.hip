@@ -368,12 +368,76 @@ __device__ __forceinline__ void deposit_particle(const Geo& g, const int* origin
   }
 }
 
+// Vertex-field window of a tile: vertices origin-1 .. origin+T+1 per axis, so
+// that particles up to one cell outside the tile (drift since the last sort)
+// gather from LDS.  Components are packed (2 in 2D, 3 in 3D; the padding slot
+// of the global array is not staged).
+template <int D> struct FieldWindow {
+  static constexpr int E0 = TileShape<D>::T0 + 3, E1 = TileShape<D>::T1 + 3, E2 = (D == 3) ? TileShape<D>::T2 + 3 : 1;
+  static constexpr int N = E0 * E1 * E2;
+  static constexpr int C = D;  // packed components per vertex
+};
+
+__device__ inline int wrap_local(int v, int origin, int n, bool periodic) {
+  int l = v - origin;
+  if (periodic) l = l < -n / 2 ? l + n : (l >= n - n / 2 ? l - n : l);
+  return l;
+}
+
+// Same weights and summation order as gather_E, so both give identical sums.
+template <int D, typename R>
+__device__ __forceinline__ bool gather_E_window(const R* __restrict__ ewin, const Geo& g, const int* origin,
+                                                const int* idx, const R* f, R* E) {
+  using FW = FieldWindow<D>;
+  const int Ew[3] = {FW::E0, FW::E1, FW::E2};
+  int l[3] = {0, 0, 0};
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    l[a] = wrap_local(idx[a], origin[a] - 1, g.n[a], g.periodic[a] != 0);
+    in = in && l[a] >= 0 && l[a] + 1 < Ew[a];
+  }
+  if (!in) return false;
+  R wx[2] = {(R)1 - f[0], f[0]};
+  R wy[2] = {(R)1 - f[1], f[1]};
+  E[0] = E[1] = E[2] = (R)0;
+  if (D == 2) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const R* e = ewin + FW::C * ((l[0] + c) + FW::E0 * (l[1] + b));
+        R w = wx[c] * wy[b];
+        E[0] += w * e[0];
+        E[1] += w * e[1];
+      }
+  } else {
+    R wz[2] = {(R)1 - f[D - 1], f[D - 1]};
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const R* e = ewin + FW::C * ((l[0] + c) + FW::E0 * ((l[1] + b) + FW::E1 * (l[D - 1] + z)));
+          R w = wx[c] * wy[b] * wz[z];
+          E[0] += w * e[0];
+          E[1] += w * e[1];
+          E[2] += w * e[FW::C - 1];
+        }
+  }
+  return true;
+}
+
 template <int D, int MAP, int SHAPE, typename R, bool FIXED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void particle_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? 5 : 2, 8))) void particle_kernel(
     PartArgs<R> a) {
   using TS = TileShape<D>;
+  using FW = FieldWindow<D>;
+  constexpr int EC = (D == 3) ? 4 : 2;  // components per vertex in the global array
   typedef typename std::conditional<FIXED, unsigned long long, double>::type QT;
   __shared__ QT win[TS::WIN];
+  __shared__ R ewin[FW::N * FW::C];
   __shared__ double red_d[8];
   __shared__ unsigned long long red_u[8][5];
 
@@ -389,30 +453,75 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   origin[2] = (D == 3) ? (tile / (g.nt[0] * g.nt[1])) * TS::T2 : 0;
 
   const bool deposit = a.mode != MODE_HALFSTEP;
-  if (deposit) {
+  if (deposit)
     for (int s = threadIdx.x; s < TS::WIN; s += blockDim.x) win[s] = (QT)0;
-    __syncthreads();
+  if (a.mode != MODE_DEPOSIT) {
+    // stage the vertex field of the tile and a one-cell halo
+    for (int s = threadIdx.x; s < FW::N; s += blockDim.x) {
+      const int l0 = s % FW::E0, l1 = (s / FW::E0) % FW::E1, l2 = s / (FW::E0 * FW::E1);
+      const int lv[3] = {l0, l1, l2};
+      long long v = 0;
+      bool ok = true;
+#pragma unroll
+      for (int ax = D - 1; ax >= 0; --ax) {
+        int x = origin[ax] - 1 + lv[ax];
+        const int nv = g.nv[ax];
+        if (g.periodic[ax])
+          x = ((x % nv) + nv) % nv;
+        else
+          ok = ok && x >= 0 && x < nv;
+        v = v * nv + x;
+      }
+      if (ok) {
+#pragma unroll
+        for (int c = 0; c < FW::C; ++c) ewin[s * FW::C + c] = a.Ev[v * EC + c];
+      }
+    }
   }
+  __syncthreads();
 
   double ke = 0.0;
   unsigned long long absorbed = 0, outflow = 0, far = 0;
 
-  for (int p = begin + (int)threadIdx.x; p < end; p += (int)blockDim.x) {
-    int key = a.key[p];
+  // The state of the thread's next particle is loaded while the current one
+  // is processed, so each wave keeps two particles' loads in flight.
+  const bool need_v = a.mode != MODE_DEPOSIT;
+  int p = begin + (int)threadIdx.x;
+  int nkey = -1;
+  R nf0 = (R)0, nf1 = (R)0, nf2 = (R)0, nv0 = (R)0, nv1 = (R)0, nv2 = (R)0;
+  if (p < end) {
+    nkey = a.key[p];
+    nf0 = a.off0[p];
+    nf1 = a.off1[p];
+    if (D == 3) nf2 = a.off2[p];
+    if (need_v) {
+      nv0 = a.v0[p];
+      nv1 = a.v1[p];
+      if (a.vz_active) nv2 = a.v2[p];
+    }
+  }
+  for (; p < end; p += (int)blockDim.x) {
+    const int key = nkey;
+    R f[3] = {nf0, nf1, nf2};
+    R v[3] = {nv0, nv1, nv2};
+    const int pn = p + (int)blockDim.x;
+    if (pn < end) {
+      nkey = a.key[pn];
+      nf0 = a.off0[pn];
+      nf1 = a.off1[pn];
+      if (D == 3) nf2 = a.off2[pn];
+      if (need_v) {
+        nv0 = a.v0[pn];
+        nv1 = a.v1[pn];
+        if (a.vz_active) nv2 = a.v2[pn];
+      }
+    }
     if (key < 0) continue;
     int idx[3] = {key_i(key, g), key_j(key, g), (D == 3) ? key_k(key, g) : 0};
-    R f[3];
-    f[0] = a.off0[p];
-    f[1] = a.off1[p];
-    f[2] = (D == 3) ? a.off2[p] : (R)0;
 
-    if (a.mode != MODE_DEPOSIT) {
-      R v[3];
-      v[0] = a.v0[p];
-      v[1] = a.v1[p];
-      v[2] = a.vz_active ? a.v2[p] : (R)0;
+    if (need_v) {
       R E[3];
-      gather_E<D, R>(a.Ev, g, idx, f, E);
+      if (!gather_E_window<D, R>(ewin, g, origin, idx, f, E)) gather_E<D, R>(a.Ev, g, idx, f, E);
       R vo0 = v[0], vo1 = v[1], vo2 = v[2];
       boris_push<R>(v, E, a.B, a.qm, a.dt, a.magnetic != 0);
       a.v0[p] = v[0];
