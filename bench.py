@@ -25,6 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "particle_kernel_box3d_128_traffic.md")
+KERNEL_SOURCES = ["paper_1311_2286_amd/csrc/particles.hip", "paper_1311_2286_amd/csrc/common.hpp",
+                  "paper_1311_2286_amd/csrc/kernels.hpp"]
 METRIC = "particle pushes/s (gather+push+map-invert+deposit) FP32 vs FP64; p50/p99 step ms"
 
 
@@ -52,6 +55,52 @@ def bytes_per_cell(dim, precision):
     components) and the species' deposit written (8 B)."""
     r = 8 if precision == 1 else 4
     return dim * r + 8
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name, shape, precision_tag):
+    """HBM bytes per particle-kernel launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by the factor a plain
+    copy of known size gives), or None when the summary is absent, covers
+    another configuration, or was taken on different kernel sources."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    kv = {}
+    with open(TRAFFIC_SUMMARY) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#", "|", "`")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_sha():
+        return None
+    if kv.get("workload") != workload_name or kv.get("shape") != shape or kv.get("precision") != precision_tag:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibrate(nbytes, reps):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters to bytes: each launch reads and writes nbytes."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": nbytes, "copy_bytes_written_per_launch": nbytes,
+                      "launches": reps}), flush=True)
 
 
 def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts):
@@ -160,6 +209,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
@@ -168,6 +219,9 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibrate:
+        copy_calibrate(1 << 30, 5)
+        return
     from paper_1311_2286_amd import cpic as C
     from paper_1311_2286_amd import workloads as W
     C.load()
@@ -216,7 +270,8 @@ def main():
         "particle_kernel_pushes_per_s": r32["kernel_pushes_per_s"],
         "phase_ms": {"particles": r32["push_ms"], "field": r32["solve_ms"], "sort": r32["sort_ms"]},
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": r32["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": r32["achieved_GBs"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, args.shape, "fp32"),
                      "kernel": "particle_kernel (one launch per species)",
                      "bytes_per_launch": r32["bytes_per_launch"],
                      "launch_ms": r32["launch_ms"]},

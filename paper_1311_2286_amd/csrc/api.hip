@@ -323,6 +323,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   G.scalars = (double*)A(sizeof(double) * 16);
   G.mg_flag = (int*)A(sizeof(int) * 4);
   G.Ev = A(real_size(s) * ecomp(s) * (size_t)g.nverts);
+  G.Kv = (double*)A(sizeof(double) * (size_t)(d * d) * (size_t)g.nverts);
   s->ke = (double*)A(sizeof(double) * 2);
   s->flags = (int*)A(sizeof(int) * 8);
   s->qsum = (uint64_t*)A(sizeof(uint64_t) * (2 + 2 * 256));
@@ -346,6 +347,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   launch_fill_u8(s->ke, 0, sizeof(double) * 2, st);
   launch_fill_u8(G.mg_flag, 0, sizeof(int) * 4, st);
   launch_jacobian_centres(G, st);
+  launch_vertex_metric(G, st);
   if (G.background) launch_background(G, grid->shape, grid->background_n0, st);
   cpic_status rc = check_async(s);
   if (rc != CPIC_OK) {

@@ -635,9 +635,11 @@ __global__ __launch_bounds__(256) void prolong_kernel(LevelArgs fa, double* phi,
 }
 
 // The V-cycle below level ls (all levels of at most SMALL_CELLS cells) in one
-// workgroup: smoothing, restriction, coarsest solve (many damped Jacobi
-// sweeps), prolongation, with workgroup barriers between the phases.
-constexpr int SMALL_CELLS = 4096;
+// workgroup: smoothing, restriction, coarsest solve (conjugate gradients, in
+// LDS by one wavefront when the level is small enough), prolongation, with
+// workgroup barriers between the phases.  Each phase costs a few L2 round
+// trips, so only levels of a few hundred cells are worth keeping here.
+constexpr int SMALL_CELLS = 512;
 constexpr int MAX_SMALL = 8;
 constexpr int COARSE_LDS = 384;  // coarsest levels up to this many cells are solved in LDS
 struct SmallLevels {
@@ -668,11 +670,11 @@ __device__ inline double block_allsum(double v) {
 }
 
 // Coarsest-level solve inside one workgroup: Jacobi-preconditioned conjugate
-// gradients on -A (A is negative semi-definite) to a relative residual of
-// 1e-13 or maxit iterations; singular (all-periodic) problems are solved on
+// gradients on -A (A is negative semi-definite) until |r|^2 <= tol2 |b|^2 or
+// maxit iterations; singular (all-periodic) problems are solved on
 // the zero-mean subspace and the result shifted to zero mean.
 __device__ inline void block_cg(const LevelArgs& a, double* x, const double* b, double* r, double* p, double* q,
-                                int maxit, int singular) {
+                                int maxit, int singular, double tol2) {
   const int nc = a.n[0] * a.n[1] * a.n[2];
   double bmean = 0.0;
   if (singular) {
@@ -714,7 +716,7 @@ __device__ inline void block_cg(const LevelArgs& a, double* x, const double* b, 
     }
     rr = block_allsum(rr);
     rz2 = block_allsum(rz2);
-    if (rr <= 1e-26 * bb || rz == 0.0) break;
+    if (rr <= tol2 * bb || rz == 0.0) break;
     const double beta = rz2 / rz;
     rz = rz2;
     for (int c = threadIdx.x; c < nc; c += blockDim.x) p[c] = r[c] / a.diag[c] + beta * p[c];
@@ -729,6 +731,81 @@ __device__ inline void block_cg(const LevelArgs& a, double* x, const double* b, 
   __syncthreads();
 }
 
+// The same Jacobi-preconditioned CG run by one wavefront (lanes 0..63) on
+// vectors held in LDS: reductions are lane shuffles and no workgroup barrier is
+// needed between iterations.  LDS accesses of one wavefront complete in issue
+// order; the fences keep the compiler from reordering them across phases.
+__device__ inline double wave_allsum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline void wave_cg(const LevelArgs& a, double* x, const double* b, double* r, double* p, double* q,
+                               int maxit, int singular, double tol2) {
+  const int nc = a.n[0] * a.n[1] * a.n[2];
+  const int lane = threadIdx.x & 63;
+  double bmean = 0.0;
+  if (singular) {
+    double s = 0.0;
+    for (int c = lane; c < nc; c += 64) s += b[c];
+    bmean = wave_allsum(s) / nc;
+  }
+  double rz = 0.0, bb = 0.0;
+  for (int c = lane; c < nc; c += 64) {
+    int idx[3] = {c % a.n[0], (c / a.n[0]) % a.n[1], c / (a.n[0] * a.n[1])};
+    double bc = b[c] - bmean;
+    double rc = bc - apply_A(a, x, idx, c);
+    r[c] = rc;
+    double z = rc / a.diag[c];
+    p[c] = z;
+    rz += rc * z;
+    bb += bc * bc;
+  }
+  rz = wave_allsum(rz);
+  bb = wave_allsum(bb);
+  wave_sync();
+  for (int it = 0; it < maxit; ++it) {
+    double pq = 0.0;
+    for (int c = lane; c < nc; c += 64) {
+      int idx[3] = {c % a.n[0], (c / a.n[0]) % a.n[1], c / (a.n[0] * a.n[1])};
+      double qc = apply_A(a, p, idx, c);
+      q[c] = qc;
+      pq += p[c] * qc;
+    }
+    pq = wave_allsum(pq);
+    if (pq == 0.0) break;
+    const double alpha = rz / pq;
+    double rr = 0.0, rz2 = 0.0;
+    for (int c = lane; c < nc; c += 64) {
+      x[c] += alpha * p[c];
+      double rc = r[c] - alpha * q[c];
+      r[c] = rc;
+      rr += rc * rc;
+      rz2 += rc * rc / a.diag[c];
+    }
+    rr = wave_allsum(rr);
+    rz2 = wave_allsum(rz2);
+    if (rr <= tol2 * bb || rz == 0.0) break;
+    const double beta = rz2 / rz;
+    rz = rz2;
+    wave_sync();
+    for (int c = lane; c < nc; c += 64) p[c] = r[c] / a.diag[c] + beta * p[c];
+    wave_sync();
+  }
+  if (singular) {
+    double s = 0.0;
+    for (int c = lane; c < nc; c += 64) s += x[c];
+    const double mean = wave_allsum(s) / nc;
+    for (int c = lane; c < nc; c += 64) x[c] -= mean;
+  }
+  wave_sync();
+}
+
 __device__ inline void block_smooth(const LevelArgs& a, const double* phi, const double* rhs, double* out,
                                     double omega) {
   const int nc = a.n[0] * a.n[1] * a.n[2];
@@ -740,7 +817,7 @@ __device__ inline void block_smooth(const LevelArgs& a, const double* phi, const
   __syncthreads();
 }
 
-__global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels S, int nu1, int nu2, int coarse_sweeps,
+__global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels S, int nu1, int nu2, double coarse_tol2,
                                                             int singular, const int* flag) {
   if (flag[0]) return;
   const double omega = 0.8;
@@ -780,11 +857,12 @@ __global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels S, int n
       la.diag = ldiag;
       for (int k = 0; k < 9; ++k) la.S[k] = a.S[k] ? lS[k] : nullptr;
       __syncthreads();
-      block_cg(la, lphi, lrhs, lr, lp, lq, maxit, singular);
+      if (threadIdx.x < 64) wave_cg(la, lphi, lrhs, lr, lp, lq, maxit, singular, coarse_tol2);
+      __syncthreads();
       for (int c = threadIdx.x; c < ncl; c += blockDim.x) S.phi[last][c] = lphi[c];
       __syncthreads();
     } else {
-      block_cg(a, S.phi[last], S.rhs[last], S.res[last], S.aux[last], S.phi2[last], maxit, singular);
+      block_cg(a, S.phi[last], S.rhs[last], S.res[last], S.aux[last], S.phi2[last], maxit, singular, coarse_tol2);
     }
   }
   for (int l = last - 1; l >= 0; --l) {
@@ -854,7 +932,10 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
       S.res[k] = G.lev[l + k].res;
       S.aux[k] = G.lev[l + k].aux;
     }
-    hipLaunchKernelGGL(small_vcycle_kernel, dim3(1), dim3(1024), 0, st, S, nu1, nu2, 40, G.all_periodic,
+    // Inside a V-cycle the coarsest level needs only a modest relative residual
+    // (1e-6); when it is the whole grid it is solved to 1e-13.
+    const double coarse_tol2 = (l == 0 && S.nl == 1) ? 1e-26 : 1e-12;
+    hipLaunchKernelGGL(small_vcycle_kernel, dim3(1), dim3(1024), 0, st, S, nu1, nu2, coarse_tol2, G.all_periodic,
                        (const int*)G.mg_flag);
     return;
   }
@@ -948,51 +1029,96 @@ __device__ inline double phi_ghost(const Geo& g, const int* bclo, const int* bch
   return add + sgn * phi[idx_to_lin(idx, g.n)];
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void efield_kernel(Geo g, int bclo0, int bclo1, int bclo2, int bchi0,
-                                                     int bchi1, int bchi2, double plo0, double plo1,
-                                                     double plo2, double phh0, double phh1, double phh2,
-                                                     const double* __restrict__ phi, R* Ev) {
-  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= g.nverts) return;
-  const int bclo[3] = {bclo0, bclo1, bclo2}, bchi[3] = {bchi0, bchi1, bchi2};
-  const double plo[3] = {plo0, plo1, plo2}, phh[3] = {phh0, phh1, phh2};
+// Inverse Jacobian k = j^-1 of the map at every vertex (FP64, row-major d x d),
+// computed once: the vertex field reuses it every step.
+__global__ __launch_bounds__(256) void vertex_metric_kernel(Geo g, double* Kv) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nv[0] || y >= g.nv[1]) return;
   const int d = g.dim;
-  int vi[3] = {0, 0, 0};
-  long long t = v;
-  for (int a = 0; a < d; ++a) {
-    vi[a] = (int)(t % g.nv[a]);
-    t /= g.nv[a];
-  }
-  double D[3] = {0.0, 0.0, 0.0};
-  const int npair = 1 << (d - 1);
-  for (int a = 0; a < d; ++a) {
-    double s = 0.0;
-    for (int comb = 0; comb < npair; ++comb) {
-      int cp[3] = {0, 0, 0}, cm[3] = {0, 0, 0};
-      int bit = 0;
-      for (int b = 0; b < d; ++b) {
-        if (b == a) {
-          cp[b] = vi[b];
-          cm[b] = vi[b] - 1;
-        } else {
-          int sb = (comb >> bit) & 1;
-          ++bit;
-          cp[b] = cm[b] = vi[b] - 1 + sb;
-        }
-      }
-      s += phi_ghost(g, bclo, bchi, plo, phh, phi, cp) - phi_ghost(g, bclo, bchi, plo, phh, phi, cm);
-    }
-    D[a] = s / (npair * g.invn[a]);
-  }
-  double xi[3] = {vi[0] * g.invn[0], vi[1] * g.invn[1], (d == 3) ? vi[2] * g.invn[2] : 0.0};
+  const long long v = x + (long long)g.nv[0] * (y + (long long)g.nv[1] * z);
+  double xi[3] = {x * g.invn[0], y * g.invn[1], (d == 3) ? z * g.invn[2] : 0.0};
   double j[3][3], k[3][3], J;
   map_jacobi(g, xi, j, nullptr);
   inv3(d, j, k, J);
-  const int EC = (d == 3) ? 4 : 2;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) Kv[v * d * d + a * d + b] = k[a][b];
+}
+
+void launch_vertex_metric(const GridCtx& G, hipStream_t st) {
+  const Geo& g = G.g;
+  dim3 gr((unsigned)((g.nv[0] + 63) / 64), (unsigned)((g.nv[1] + 3) / 4), (unsigned)(g.dim == 3 ? g.nv[2] : 1));
+  hipLaunchKernelGGL(vertex_metric_kernel, gr, dim3(64, 4, 1), 0, st, g, G.Kv);
+}
+
+struct FieldBC {
+  int bclo[3], bchi[3];
+  double plo[3], phh[3];
+};
+
+// E_v = -k^T D phi at vertex (x, y, z): D_a is the difference across axis a of
+// the 2^d cells around the vertex, averaged over the 2^(d-1) cell pairs.
+// Vertices whose cells are all inside the grid (or wrap periodically) read phi
+// directly; the others go through the boundary ghosts.  Both paths sum the
+// pairs in the same order.
+template <int d, typename R>
+__global__ __launch_bounds__(256) void efield_kernel(Geo g, FieldBC bc, const double* __restrict__ phi,
+                                                     const double* __restrict__ Kv, R* Ev) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nv[0] || y >= g.nv[1]) return;
+  const int vi[3] = {x, y, z};
+  const long long v = x + (long long)g.nv[0] * (y + (long long)g.nv[1] * z);
+  // cell index below (lo) and above (hi) the vertex on every axis
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  bool interior = true;
+#pragma unroll
+  for (int a = 0; a < d; ++a) {
+    const int n = g.n[a];
+    lo[a] = vi[a] - 1;
+    hi[a] = vi[a];
+    if (g.periodic[a]) {
+      if (lo[a] < 0) lo[a] += n;
+      if (hi[a] >= n) hi[a] -= n;
+    } else {
+      interior = interior && lo[a] >= 0 && hi[a] < n;
+    }
+  }
+  double D[3] = {0.0, 0.0, 0.0};
+  constexpr int npair = 1 << (d - 1);
+#pragma unroll
+  for (int a = 0; a < d; ++a) {
+    double s = 0.0;
+#pragma unroll
+    for (int comb = 0; comb < npair; ++comb) {
+      int cp[3] = {0, 0, 0}, cm[3] = {0, 0, 0};
+      int bit = 0;
+#pragma unroll
+      for (int b = 0; b < d; ++b) {
+        if (b == a) {
+          cp[b] = interior ? hi[b] : vi[b];
+          cm[b] = interior ? lo[b] : vi[b] - 1;
+        } else {
+          const int sb = (comb >> bit) & 1;
+          ++bit;
+          cp[b] = cm[b] = interior ? (sb ? hi[b] : lo[b]) : vi[b] - 1 + sb;
+        }
+      }
+      if (interior)
+        s += phi[cp[0] + g.n[0] * (cp[1] + g.n[1] * cp[2])] - phi[cm[0] + g.n[0] * (cm[1] + g.n[1] * cm[2])];
+      else
+        s += phi_ghost(g, bc.bclo, bc.bchi, bc.plo, bc.phh, phi, cp) -
+             phi_ghost(g, bc.bclo, bc.bchi, bc.plo, bc.phh, phi, cm);
+    }
+    D[a] = s / (npair * g.invn[a]);
+  }
+  const double* k = Kv + v * d * d;
+  constexpr int EC = (d == 3) ? 4 : 2;
+#pragma unroll
   for (int b = 0; b < d; ++b) {
     double e = 0.0;
-    for (int a = 0; a < d; ++a) e -= k[a][b] * D[a];
+#pragma unroll
+    for (int a = 0; a < d; ++a) e -= k[a * d + b] * D[a];
     Ev[v * EC + b] = (R)e;
   }
   if (d == 3) Ev[v * EC + 3] = (R)0;
@@ -1000,15 +1126,26 @@ __global__ __launch_bounds__(256) void efield_kernel(Geo g, int bclo0, int bclo1
 
 void launch_efield(const GridCtx& G, hipStream_t st) {
   const Geo& g = G.g;
-  unsigned blocks = (unsigned)((g.nverts + 255) / 256);
-  if (G.fp64)
-    hipLaunchKernelGGL(efield_kernel<double>, dim3(blocks), dim3(256), 0, st, g, G.bc_lo[0], G.bc_lo[1],
-                       G.bc_lo[2], G.bc_hi[0], G.bc_hi[1], G.bc_hi[2], G.phi_lo[0], G.phi_lo[1], G.phi_lo[2],
-                       G.phi_hi[0], G.phi_hi[1], G.phi_hi[2], G.lev[0].phi, (double*)G.Ev);
-  else
-    hipLaunchKernelGGL(efield_kernel<float>, dim3(blocks), dim3(256), 0, st, g, G.bc_lo[0], G.bc_lo[1],
-                       G.bc_lo[2], G.bc_hi[0], G.bc_hi[1], G.bc_hi[2], G.phi_lo[0], G.phi_lo[1], G.phi_lo[2],
-                       G.phi_hi[0], G.phi_hi[1], G.phi_hi[2], G.lev[0].phi, (float*)G.Ev);
+  FieldBC bc;
+  for (int a = 0; a < 3; ++a) {
+    bc.bclo[a] = G.bc_lo[a];
+    bc.bchi[a] = G.bc_hi[a];
+    bc.plo[a] = G.phi_lo[a];
+    bc.phh[a] = G.phi_hi[a];
+  }
+  dim3 gr((unsigned)((g.nv[0] + 63) / 64), (unsigned)((g.nv[1] + 3) / 4), (unsigned)(g.dim == 3 ? g.nv[2] : 1));
+  const dim3 bl(64, 4, 1);
+  if (g.dim == 3) {
+    if (G.fp64)
+      hipLaunchKernelGGL((efield_kernel<3, double>), gr, bl, 0, st, g, bc, G.lev[0].phi, G.Kv, (double*)G.Ev);
+    else
+      hipLaunchKernelGGL((efield_kernel<3, float>), gr, bl, 0, st, g, bc, G.lev[0].phi, G.Kv, (float*)G.Ev);
+  } else {
+    if (G.fp64)
+      hipLaunchKernelGGL((efield_kernel<2, double>), gr, bl, 0, st, g, bc, G.lev[0].phi, G.Kv, (double*)G.Ev);
+    else
+      hipLaunchKernelGGL((efield_kernel<2, float>), gr, bl, 0, st, g, bc, G.lev[0].phi, G.Kv, (float*)G.Ev);
+  }
 }
 
 __global__ void rho_kernel(long long nc, double dV, const double* charge, const double* Jc, double* rho) {

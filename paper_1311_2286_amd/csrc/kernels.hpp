@@ -128,6 +128,7 @@ struct GridCtx {
   double* scalars;    // device scalars: [0] |b|^2 [1] |r|^2 [2] sumJphi [3] mean [4..] misc
   int* mg_flag;       // [0] converged [1] cycles done
   void* Ev;           // vertex field (float or double, interleaved)
+  double* Kv;         // inverse Jacobian at vertices, d x d row-major (FP64)
   int fp64;
 };
 
@@ -144,6 +145,7 @@ void launch_charge(const GridCtx& G, const ChargeSpecies& cs, double bg_charge, 
 void launch_rhs(const GridCtx& G, hipStream_t st);
 int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st);
 void launch_gauge(const GridCtx& G, hipStream_t st);
+void launch_vertex_metric(const GridCtx& G, hipStream_t st);
 void launch_efield(const GridCtx& G, hipStream_t st);
 void launch_rho(const GridCtx& G, double* rho, hipStream_t st);
 void launch_field_energy(const GridCtx& G, double* out, hipStream_t st);
