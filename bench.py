@@ -9,7 +9,9 @@ workload beside it.  A step is one full PIC cycle (particle kernel: gather +
 push + Newton map inversion + boundaries + deposit; charge; multigrid solve;
 vertex field; tile sort).  Inputs are resident in HBM before the timed region.
 
-Prints ONE JSON line (see the design doc for the fields)."""
+Prints one JSON line: the throughput over whole steps, the per-phase split,
+the particle kernel against the HBM roofline, the FP64 path beside it and the
+oracle timed on the host cores."""
 from __future__ import annotations
 
 import argparse
@@ -213,8 +215,8 @@ def main():
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
-              "'How the path would shard'); rerun with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
+              "rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"

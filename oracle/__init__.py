@@ -105,7 +105,7 @@ def lib():
         L.or_face_area.argtypes = [P(Map)]
         L.or_face_area.restype = d
         L.or_inject.argtypes = [P(Map), P(Grid), d, d, d, d, u32, u32, u32, u32, lg, P(i32), P(d),
-                                P(d), P(lg)]
+                                P(d), P(lg), P(lg)]
         L.or_inject.restype = lg
         _lib_handle = L
     return _lib_handle
@@ -302,17 +302,23 @@ def face_area(m: Map) -> float:
     return float(lib().or_face_area(ctypes.byref(m)))
 
 
-def inject(m: Map, g: Grid, n0, vth, w, dt, seed, step, species, cap=1 << 20):
+def inject(m: Map, g: Grid, n0, vth, w, dt, seed, step, species, cap=1 << 20, with_index=False):
     """Particles injected through the upper face of axis 0 in one step:
-    (cell, off (n,3), vel (n,3), number drawn)."""
+    (cell, off (n,3), vel (n,3), number drawn[, draw index of each particle]).
+    Particles whose free-streaming start leaves the grid are not kept."""
     cell = np.zeros(cap, dtype=np.int32)
     off = np.zeros((cap, 3))
     vel = np.zeros((cap, 3))
+    kidx = np.zeros(cap, dtype=np.int64)
     drawn = ctypes.c_long(0)
     n = lib().or_inject(ctypes.byref(m), ctypes.byref(g), n0, vth, w, dt, seed & 0xFFFFFFFF,
                         (seed >> 32) & 0xFFFFFFFF, step, species, cap, _p(cell, ctypes.c_int32),
-                        _p(off, ctypes.c_double), _p(vel, ctypes.c_double), ctypes.byref(drawn))
-    return cell[:n].copy(), off[:n].copy(), vel[:n].copy(), drawn.value
+                        _p(off, ctypes.c_double), _p(vel, ctypes.c_double),
+                        _p(kidx, ctypes.c_long), ctypes.byref(drawn))
+    out = (cell[:n].copy(), off[:n].copy(), vel[:n].copy(), drawn.value)
+    if with_index:
+        out = out + (kidx[:n].copy(),)
+    return out
 
 
 def num_threads() -> int:

@@ -1063,7 +1063,7 @@ double or_face_area(const or_map* m) {
 
 long or_inject(const or_map* m, const or_grid* g, double n0, double vth, double w, double dt,
                uint32_t seed_lo, uint32_t seed_hi, uint32_t step, uint32_t species, long cap,
-               int32_t* cell, double* off, double* vel, long* drawn) {
+               int32_t* cell, double* off, double* vel, long* kidx, long* drawn) {
   int d = g->dim;
   double lam = n0 * vth / sqrt(2.0 * OR_PI) * or_face_area(m) * dt / w;
   uint32_t key[2] = {seed_lo, seed_hi};
@@ -1112,6 +1112,7 @@ long or_inject(const or_map* m, const or_grid* g, double n0, double vth, double 
       off[3 * out + a] = o[a];
       vel[3 * out + a] = v[a];
     }
+    if (kidx) kidx[out] = k;
     ++out;
   }
   return out;

@@ -742,7 +742,7 @@ struct InjectArgs {
   int S1;
   double lam, vth, dt, kappa;
   uint32_t k0, k1, step, species;
-  unsigned long long* counters;  // [5] injected, [6] dropped for capacity, [7] ids issued
+  unsigned long long* counters;  // [5] injected, [6] dropped for capacity, [7] next identifier
   int* count_out;
 };
 
@@ -831,8 +831,8 @@ __global__ __launch_bounds__(256) void inject_kernel(InjectArgs<R> a) {
     fo[ax] = r;
   }
   for (int ax = D; ax < 3; ++ax) fo[ax] = (R)0;
-  unsigned long long my_id = atomicAdd(&a.counters[7], 1ull);
-  if (a.id) a.id[slot] = (uint32_t)my_id;
+  // identifiers follow the draw index k, so they do not depend on scheduling
+  if (a.id) a.id[slot] = (uint32_t)(a.counters[7] + (unsigned long long)k);
   if (dead) {
     a.key[slot] = -2;
     return;
@@ -844,9 +844,10 @@ __global__ __launch_bounds__(256) void inject_kernel(InjectArgs<R> a) {
   deposit_global<D, R, FIXED>(g, a.shape, a.S1, idx, fo, a.Q);
 }
 
-__global__ void inject_finish_kernel(int* d_n, const int* count, int cap) {
+__global__ void inject_finish_kernel(int* d_n, const int* count, int cap, unsigned long long* counters) {
   int n = *d_n + *count;
   *d_n = n < cap ? n : cap;
+  counters[7] += (unsigned long long)*count;
 }
 
 // ----------------------------------------------------------------------------
@@ -1203,7 +1204,8 @@ static void launch_inject_t(const InjectLaunch& I, hipStream_t st) {
   const unsigned blocks = (unsigned)((maxc + 255) / 256);
   constexpr bool FIXED = std::is_same<R, float>::value;
   hipLaunchKernelGGL((inject_kernel<D, MAP, R, FIXED>), dim3(blocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(inject_finish_kernel, dim3(1), dim3(1), 0, st, I.d_n, (const int*)I.count_out, I.cap);
+  hipLaunchKernelGGL(inject_finish_kernel, dim3(1), dim3(1), 0, st, I.d_n, (const int*)I.count_out, I.cap,
+                     I.counters);
 }
 
 template <typename R>

@@ -105,9 +105,9 @@ def ions(vth=1.0 / math.sqrt(MASS_RATIO), ppc=64.0, count=None):
 
 
 # ----------------------------------------------------------------------------
-# The five workloads.  Readings (box size = N cells x 1 Debye length for the
-# 3D boxes, dt = 0.1 / omega_pe everywhere, particles/cell counted over both
-# species) are listed in the design doc.
+# The five workloads.  Where the paper leaves them open: the 3D boxes are N
+# cells x 1 Debye length per axis, dt = 0.1 / omega_pe everywhere, and
+# particles per cell count both species, split equally.
 # ----------------------------------------------------------------------------
 def case1(vth=1.0) -> Case:
     """2D periodic Langmuir test: unit square, sinusoidal map eps = 0.1,

@@ -7,7 +7,9 @@ from paper_1311_2286_amd import workloads as W
 
 
 def gpu_sim(case, precision=0, shape=2, track_ids=True, mg_rtol=1e-12, mg_max_cycles=80,
-            sort_every=1, count=None, capacity_factor=1.0):
+            sort_every=1, count=None, capacity_factor=1.0, inject=False, seed=0):
+    """inject: every species gets flux injection at the outer wall with
+    n0 = 1 and its own thermal speed, keyed by `seed`."""
     from paper_1311_2286_amd import cpic as C
     dt = np.float64 if precision == C.FP64 else np.float32
     pbc_lo = tuple(0 if b == 0 else C.PBC_ABSORB for b in case.bc_lo)
@@ -21,8 +23,8 @@ def gpu_sim(case, precision=0, shape=2, track_ids=True, mg_rtol=1e-12, mg_max_cy
     for sid, s in enumerate(case.species):
         p = W.generate_species(case, sid, dtype=dt, count=count)
         cap = max(1, int(p["cell"].size * capacity_factor))
-        sim.add_species(s.q, s.m, case.weight(s) if count is None else case.weight(s),
-                        cap, pbc_lo=pbc_lo, pbc_hi=pbc_hi)
+        sim.add_species(s.q, s.m, case.weight(s), cap, pbc_lo=pbc_lo, pbc_hi=pbc_hi,
+                        inject=dict(n0=1.0, vth=s.vth) if inject else None, seed=seed)
         sim.set_particles(sid, p["cell"], p["off"], p["vel"], p["id"])
         parts.append(p)
     return sim, parts

@@ -1,0 +1,117 @@
+"""GPU parity of the probe problem's particle boundaries: flux injection at
+the outer circle, absorption by the probe, outflow (Sec. "Tests", the
+cylindrical-probe setting), through the C ABI against the FP64 oracle.
+
+Bars:
+  - injection, draw by draw (same Philox counters on both sides): the same
+    draws are kept; logical position within 2e-5 cell (FP32 storage) or 1e-9
+    (FP64); velocity within 1e-6 (FP32 rounding) or 1e-12 relative;
+  - the injected particles' deposit, FP32 path: bit-exact;
+  - three full steps, FP64 path: absorbed, outflow, injected and live counts
+    identical per species; potential within 1e-8 of its maximum."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1311_2286_amd import workloads as W
+from _helpers import gpu_sim, oracle_objects, oracle_species, by_id, logical_cells, periodic_diff
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def C():
+    from paper_1311_2286_amd import cpic
+    return cpic
+
+
+def probe_case(ppc=6.0):
+    # a reduced probe: 48 x 40 cells (ragged against the 16 x 16 tiles),
+    # r_out = 10 so particles cross the annulus within tens of steps
+    return W.Case("probe_small", 2, W.POLAR_LOG, (48, 40), r_in=1.0, r_out=10.0,
+                  bc_lo=(W.DIRICHLET, W.PERIODIC), bc_hi=(W.DIRICHLET, W.PERIODIC),
+                  phi_lo=(-5.0, 0.0), phi_hi=(0.0, 0.0), dt=0.1,
+                  species=[W.electrons(1.0, ppc), W.ions(ppc=ppc)], case_id=9)
+
+
+def _offsets_n3(off_dn):
+    d = off_dn.shape[0]
+    o = np.zeros((off_dn.shape[1], 3))
+    o[:, :d] = off_dn.T.astype(np.float64)
+    return o
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_injection_draw_by_draw(precision):
+    case = probe_case()
+    seed = 77
+    sim, parts = gpu_sim(case, precision=precision, inject=True, seed=seed, capacity_factor=1.5)
+    m, g = oracle_objects(case)
+    nsp = len(case.species)
+    sim.stage(C().STAGE_DEPOSIT)
+    Q0 = [sim.get_field(C().FIELD_Q, sid).copy() for sid in range(nsp)]
+    sim.stage(C().STAGE_INJECT)
+    Q1 = [sim.get_field(C().FIELD_Q, sid).copy() for sid in range(nsp)]
+    d = sim.diag()
+    for sid, s in enumerate(case.species):
+        n_init = parts[sid]["cell"].size
+        cell, off, vel, drawn, kidx = O.inject(m, g, 1.0, s.vth, case.weight(s), case.dt, seed, 0,
+                                               sid, with_index=True)
+        assert drawn > (50 if s.q < 0 else 0)
+        got = by_id(sim.get_particles(sid))
+        new = (got["id"] >= n_init) & (got["cell"] >= 0)
+        assert d.injected[sid] == cell.size == int(new.sum())
+        assert np.array_equal(got["id"][new].astype(np.int64) - n_init, kidx)
+        pg = logical_cells(case, got["cell"][new], got["off"][:, new].astype(np.float64))
+        po = logical_cells(case, cell, off[:, : case.dim].T.copy())
+        dpos = np.abs(periodic_diff(case, pg, po)).max()
+        vg = got["vel"][:, new].T.astype(np.float64)
+        dv = (np.abs(vg - vel) / (np.abs(vel) + 1e-3)).max()
+        if precision == 0:
+            assert dpos < 2e-5, dpos
+            assert dv < 1e-6, dv
+            # the deposit of exactly these particles, at their stored offsets
+            Qi = O.deposit_fixed(g, O.B2, 24, got["cell"][new], _offsets_n3(got["off"][:, new]))
+            assert np.array_equal(Q1[sid] - Q0[sid], Qi)
+        else:
+            assert dpos < 1e-9, dpos
+            assert dv < 1e-12, dv
+            Qi = O.deposit_f64(g, O.B2, got["cell"][new], _offsets_n3(got["off"][:, new]))
+            assert np.max(np.abs((Q1[sid] - Q0[sid]) - Qi)) < 1e-12 * max(1.0, np.max(Qi))
+    sim.close()
+
+
+def test_probe_steps_counts_match_oracle():
+    case = probe_case(ppc=4.0)
+    seed = 78
+    sim, parts = gpu_sim(case, precision=1, inject=True, seed=seed, capacity_factor=1.6,
+                         mg_rtol=1e-13)
+    m, g = oracle_objects(case)
+    sp = oracle_species(case, parts)
+    for sid, s in enumerate(case.species):
+        sp[sid]["inject"] = dict(n0=1.0, vth=s.vth, seed=seed, sid=sid)
+    osim = O.OracleSim(m, g, sp, dt=case.dt, deposit="f64", rtol=1e-13, ke_axes=2)
+    sim.initialize()
+    osim.initialize()
+    for k in range(3):
+        sim.step(1)
+        osim.step()
+        d = sim.diag()
+        for sid in range(len(case.species)):
+            o = osim.sp[sid]
+            assert d.absorbed[sid] == o["absorbed"], (k, sid)
+            assert d.outflow[sid] == o["outflow"], (k, sid)
+            assert d.injected[sid] == o["injected"], (k, sid)
+            assert d.count[sid] == o["cell"].size, (k, sid)
+        phi = sim.get_field(C().FIELD_PHI)
+        assert np.max(np.abs(phi - osim.phi)) < 1e-8 * np.max(np.abs(osim.phi)), k
+    # the probe collects electrons first: some were absorbed over three steps
+    assert sum(osim.sp[s]["absorbed"] for s in range(2)) > 0
+    sim.close()
