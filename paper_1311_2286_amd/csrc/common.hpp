@@ -68,13 +68,29 @@ __host__ __device__ inline int tile_of_key(int key, const Geo& g) {
 }
 
 // ---------------------------------------------------------------------------
-// Trigonometric helpers.  sin/cos of 2 pi u for the base position use the
-// device library's sinpi/cospi (argument reduction is exact in revolutions).
-// Increments sin(2 pi u) and cos(2 pi u) - 1 for the small Newton steps are
-// evaluated without cancellation: Taylor polynomials for |2 pi u| < 0.8 in
-// FP32 (truncation below 2e-9 there), sinpi of the half angle in FP64.
+// Trigonometric helpers.  sin/cos of 2 pi u for the base position: in FP32,
+// u is reduced to the nearest quarter turn, r = u - q/4 with |r| <= 1/8
+// (exact for |u| < 2^21), and sin/cos of x = 2 pi r come from their Taylor
+// series to degree 9 and 8 (truncation below 2e-9 and 3e-8 for
+// |x| <= pi/4), then rotated by q quarter turns; in FP64, the device
+// library's sinpi/cospi.  Increments sin(2 pi u) and cos(2 pi u) - 1 for the
+// small Newton steps are evaluated without cancellation: Taylor polynomials
+// for |2 pi u| < 0.8 in FP32 (truncation below 2e-9 there), sinpi of the half
+// angle in FP64.
 // ---------------------------------------------------------------------------
-__device__ inline void sincos2pi(float u, float& s, float& c) { sincospif(2.0f * u, &s, &c); }
+__device__ inline void sincos2pi(float u, float& s, float& c) {
+  const float q = rintf(4.0f * u);
+  const float x = 6.28318530717958648f * (u - 0.25f * q);
+  const float x2 = x * x;
+  const float sx = x * (1.0f + x2 * (-1.0f / 6.0f + x2 * (1.0f / 120.0f + x2 * (-1.0f / 5040.0f + x2 * (1.0f / 362880.0f)))));
+  const float cx = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24.0f + x2 * (-1.0f / 720.0f + x2 * (1.0f / 40320.0f))));
+  const int k = ((int)q) & 3;
+  // rotate (cos x, sin x) by k quarter turns
+  const float s1 = (k & 1) ? cx : sx;
+  const float c1 = (k & 1) ? sx : cx;
+  s = (k & 2) ? -s1 : s1;
+  c = ((k + 1) & 2) ? -c1 : c1;
+}
 __device__ inline void sincos2pi(double u, double& s, double& c) { sincospi(2.0 * u, &s, &c); }
 
 __device__ inline void incr2pi(float u, float& sn, float& cm1) {

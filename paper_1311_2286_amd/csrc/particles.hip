@@ -263,14 +263,11 @@ __device__ __forceinline__ void deposit_particle(const Geo& g, const int* origin
   using TS = TileShape<D>;
   typedef typename std::conditional<FIXED, uint32_t, R>::type WT;
   const int Wd[3] = {TS::W0, TS::W1, TS::W2};
-  // per axis: weights of cells i-1, i, i+1 and their window-local indices
-  int tl[3][3];
+  // per axis: weights of cells i-1, i, i+1
   WT w[3][3];
-  bool inwin = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (a >= D) {
-      tl[a][0] = tl[a][1] = tl[a][2] = 0;
       w[a][0] = w[a][2] = (WT)0;
       w[a][1] = (WT)1;
       continue;
@@ -287,6 +284,89 @@ __device__ __forceinline__ void deposit_particle(const Geo& g, const int* origin
       w[a][0] = (WT)wr[0];
       w[a][1] = (WT)wr[1];
       w[a][2] = (WT)wr[2];
+    }
+  }
+  // Common case: the targets are consecutive window cells (no wall folding
+  // and inside the window), so one base address serves every target and the
+  // offsets are compile-time constants.  b2 has 3 targets per axis starting at
+  // i - 1; b1 has 2, starting at i - 1 when its lower weight is the non-zero
+  // one (f < 1/2) and at i otherwise.
+  constexpr int NT = (SHAPE == SHAPE_B2) ? 3 : 2;
+  WT wt[3][NT];
+  int lo[3];
+  bool fast = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int sft = -1;
+    if (SHAPE == SHAPE_B2 || a >= D) {
+#pragma unroll
+      for (int o = 0; o < NT; ++o) wt[a][o] = w[a][o];
+      if (a >= D) sft = 0;
+    } else {
+      const bool upper = (f[a] >= (R)0.5);  // same split as the b1 weight rule
+      sft = upper ? 0 : -1;
+      wt[a][0] = upper ? w[a][1] : w[a][0];
+      wt[a][1] = upper ? w[a][2] : w[a][1];
+    }
+    if (a >= D) {
+      lo[a] = 0;
+      continue;
+    }
+    const int n = g.n[a];
+    int l = idx[a] - origin[a] + TS::G;
+    if (g.periodic[a]) {
+      if (l < 0) l += n;
+      else if (l >= Wd[a]) l -= n;
+    } else {
+      fast = fast && idx[a] + sft >= 0 && idx[a] + sft + NT - 1 <= n - 1;
+    }
+    l += sft;
+    fast = fast && l >= 0 && l + NT - 1 <= Wd[a] - 1;
+    lo[a] = l;
+  }
+  if (fast) {
+    QT* base = win + (lo[0] + TS::W0 * (lo[1] + TS::W1 * lo[2]));
+    constexpr int NZ = (D == 3) ? NT : 1;
+#pragma unroll
+    for (int oz = 0; oz < NZ; ++oz)
+#pragma unroll
+      for (int oy = 0; oy < NT; ++oy) {
+        // b2 weights are at most 3/4 of 2^S1 (S1 = 16 in 3D), so the product
+        // of two fits 32 bits and the 24-bit multiplier is exact; a b1 weight
+        // reaches 2^S1 and takes the 64-bit product
+        typedef typename std::conditional<FIXED, unsigned long long, R>::type PT;
+        PT wyz;
+        if (FIXED) {
+          if (D == 3 && SHAPE == SHAPE_B2)
+            wyz = (PT)(uint32_t)__umul24((uint32_t)wt[1][oy], (uint32_t)wt[2][oz]);
+          else if (D == 3)
+            wyz = (PT)wt[1][oy] * (PT)wt[2][oz];
+          else
+            wyz = (PT)wt[1][oy];
+        } else {
+          wyz = (D == 3) ? (PT)(wt[1][oy] * wt[2][oz]) : (PT)wt[1][oy];
+        }
+#pragma unroll
+        for (int ox = 0; ox < NT; ++ox) {
+          QT val;
+          if (FIXED)
+            val = (QT)((unsigned long long)wt[0][ox] * wyz);
+          else
+            val = (QT)(wt[0][ox] * wyz);
+          atomicAdd(base + (ox + TS::W0 * (oy + TS::W1 * oz)), val);
+        }
+      }
+    return;
+  }
+  // general case (walls, a particle near the window edge, tiny periodic grids
+  // whose window overlaps itself): per-target window indices
+  int tl[3][3];
+  bool inwin = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a >= D) {
+      tl[a][0] = tl[a][1] = tl[a][2] = 0;
+      continue;
     }
     const int n = g.n[a];
 #pragma unroll
@@ -305,7 +385,7 @@ __device__ __forceinline__ void deposit_particle(const Geo& g, const int* origin
   }
   constexpr int NZ = (D == 3) ? 3 : 1;
   if (inwin) {
-#pragma unroll
+#pragma unroll 1
     for (int oz = 0; oz < NZ; ++oz) {
       const int az = (D == 3) ? oz : 1;
 #pragma unroll
@@ -315,7 +395,7 @@ __device__ __forceinline__ void deposit_particle(const Geo& g, const int* origin
           QT val;
           if (FIXED) {
             if (D == 3)
-              val = (QT)((unsigned long long)(w[0][ox] * w[1][oy]) * (unsigned long long)w[2][az]);
+              val = (QT)((unsigned long long)w[0][ox] * (unsigned long long)w[1][oy] * (unsigned long long)w[2][az]);
             else
               val = (QT)((unsigned long long)w[0][ox] * (unsigned long long)w[1][oy]);
           } else {
