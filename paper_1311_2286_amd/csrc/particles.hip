@@ -478,6 +478,19 @@ __device__ __forceinline__ bool gather_E_window(const R* __restrict__ ewin, cons
     in = in && l[a] >= 0 && l[a] + 1 < Ew[a];
   }
   if (!in) return false;
+  // all 2^D vertices are loaded first (one base address, constant offsets),
+  // so the LDS latency is paid once per particle
+  const R* e0 = ewin + FW::C * (l[0] + FW::E0 * (l[1] + FW::E1 * l[2]));
+  constexpr int NZ = (D == 3) ? 2 : 1;
+  R ev[NZ][2][2][FW::C];
+#pragma unroll
+  for (int z = 0; z < NZ; ++z)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int k = 0; k < FW::C; ++k) ev[z][b][c][k] = e0[FW::C * (c + FW::E0 * (b + FW::E1 * z)) + k];
   R wx[2] = {(R)1 - f[0], f[0]};
   R wy[2] = {(R)1 - f[1], f[1]};
   E[0] = E[1] = E[2] = (R)0;
@@ -486,24 +499,22 @@ __device__ __forceinline__ bool gather_E_window(const R* __restrict__ ewin, cons
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const R* e = ewin + FW::C * ((l[0] + c) + FW::E0 * (l[1] + b));
         R w = wx[c] * wy[b];
-        E[0] += w * e[0];
-        E[1] += w * e[1];
+        E[0] += w * ev[0][b][c][0];
+        E[1] += w * ev[0][b][c][1];
       }
   } else {
     R wz[2] = {(R)1 - f[D - 1], f[D - 1]};
 #pragma unroll
-    for (int z = 0; z < 2; ++z)
+    for (int z = 0; z < NZ; ++z)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          const R* e = ewin + FW::C * ((l[0] + c) + FW::E0 * ((l[1] + b) + FW::E1 * (l[D - 1] + z)));
           R w = wx[c] * wy[b] * wz[z];
-          E[0] += w * e[0];
-          E[1] += w * e[1];
-          E[2] += w * e[FW::C - 1];
+          E[0] += w * ev[z][b][c][0];
+          E[1] += w * ev[z][b][c][1];
+          E[2] += w * ev[z][b][c][FW::C - 1];
         }
   }
   return true;
