@@ -68,6 +68,7 @@ struct cpic_sim {
   bool initialized = false;
   bool poisoned = false;
   bool sorted_dirty = true;
+  bool phi_prev_valid = false;  // G.phi_prev holds the previous step's potential
   long long step = 0;
   double* ke = nullptr;  // device: kinetic energy of the last push
   int* flags = nullptr;  // device ints: [0] bad input count
@@ -324,6 +325,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   G.mg_flag = (int*)A(sizeof(int) * 4);
   G.Ev = A(real_size(s) * ecomp(s) * (size_t)g.nverts);
   G.Kv = (double*)A(sizeof(double) * (size_t)(d * d) * (size_t)g.nverts);
+  G.phi_prev = (double*)A(cb);
   s->ke = (double*)A(sizeof(double) * 2);
   s->flags = (int*)A(sizeof(int) * 8);
   s->qsum = (uint64_t*)A(sizeof(uint64_t) * (2 + 2 * 256));
@@ -348,6 +350,10 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   launch_fill_u8(G.mg_flag, 0, sizeof(int) * 4, st);
   launch_jacobian_centres(G, st);
   launch_vertex_metric(G, st);
+  if (compute_smoother_bounds(G, st) != 0) {
+    cpic_destroy(s);
+    return CPIC_E_HIP;
+  }
   if (G.background) launch_background(G, grid->shape, grid->background_n0, st);
   cpic_status rc = check_async(s);
   if (rc != CPIC_OK) {
@@ -732,6 +738,7 @@ extern "C" cpic_status cpic_initialize(cpic_sim* s) {
   particles_pass(s, MODE_HALFSTEP);
   s->initialized = true;
   s->step = 0;
+  s->phi_prev_valid = false;
   return check_async(s);
 }
 
@@ -761,6 +768,9 @@ extern "C" cpic_status cpic_step(cpic_sim* s, int nsteps) {
     const bool inj = any_injection(s);
     if (inj) inject_pass(s, s->step);
     charge_pass(s);
+    // initial guess of the solve: phi extrapolated linearly from the last two steps
+    launch_extrapolate_guess(s->G, s->phi_prev_valid ? 1 : 0, s->stream);
+    s->phi_prev_valid = true;
     solve_pass(s);
     launch_efield(s->G, s->stream);
     if (ev) hipEventRecord(ev->e[3], s->stream);
@@ -829,6 +839,8 @@ extern "C" cpic_status cpic_set_field(cpic_sim* s, int which, int sid, const voi
   HIPCHK(s, hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
+  // a potential set from outside starts a new time history
+  if (which == CPIC_FIELD_PHI) s->phi_prev_valid = false;
   return check_async(s);
 }
 

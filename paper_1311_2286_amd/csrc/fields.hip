@@ -21,6 +21,8 @@
 // kernels of later cycles return at once once the flag is set.
 #include <string.h>
 
+#include <vector>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -504,13 +506,16 @@ __device__ inline double apply_A(const LevelArgs& a, const double* __restrict__ 
   return acc;
 }
 
-// Damped Jacobi sweep out = phi + omega (rhs - A phi) / diag, on a 3D launch
-// grid (x threads along i, blockIdx.y/z along j, k).  With partials != null
-// the squared residual of the input is summed per block (fixed order) for the
-// convergence test.
+// One smoothing step on a 3D launch grid (x threads along i, blockIdx.y/z
+// along j, k):  r = rhs - A phi,  dn = cr r / diag + cd dprev,  out = phi + dn
+// (and dout = dn when requested).  cd = 0 is a damped Jacobi sweep; the
+// Chebyshev steps of the multigrid smoother use the three-term recurrence.
+// With partials != null the squared residual of the input is summed per block
+// (fixed order) for the convergence test.
 __global__ __launch_bounds__(256) void smooth_kernel(LevelArgs a, const double* __restrict__ phi,
                                                      const double* __restrict__ rhs, double* out,
-                                                     double omega, const int* flag, double* partials) {
+                                                     double cr, double cd, const double* dprev, double* dout,
+                                                     const int* flag, double* partials) {
   if (flag[0]) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -520,7 +525,10 @@ __global__ __launch_bounds__(256) void smooth_kernel(LevelArgs a, const double* 
     const int idx[3] = {i, j, k};
     const int c = i + a.n[0] * (j + a.n[1] * k);
     double r = rhs[c] - apply_A(a, phi, idx, c);
-    out[c] = phi[c] + omega * r / a.diag[c];
+    double dn = cr * r / a.diag[c];
+    if (dprev) dn += cd * dprev[c];
+    out[c] = phi[c] + dn;
+    if (dout) dout[c] = dn;
     rr = r * r;
   }
   if (partials) {
@@ -528,6 +536,38 @@ __global__ __launch_bounds__(256) void smooth_kernel(LevelArgs a, const double* 
     if (threadIdx.x == 0 && threadIdx.y == 0)
       partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = t;
   }
+}
+
+// Gershgorin bound of D^-1 A per cell: sum over off-diagonal |A_cj| / |A_cc|
+// (same neighbour pattern as apply_A); 1 + its maximum bounds the spectrum.
+__global__ __launch_bounds__(256) void gershgorin_kernel(LevelArgs a, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= a.n[0] || j >= a.n[1]) return;
+  const int idx[3] = {i, j, k};
+  const int c = i + a.n[0] * (j + a.n[1] * k);
+  const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+  const int sy = n0, sz = n0 * n1;
+  const int dxm = idx[0] > 0 ? -1 : (a.periodic[0] ? n0 - 1 : 0);
+  const int dym = (idx[1] > 0 ? -1 : (a.periodic[1] ? n1 - 1 : 0)) * sy;
+  const int dxp = idx[0] + 1 < n0 ? 1 : (a.periodic[0] ? 1 - n0 : 0);
+  const int dyp = (idx[1] + 1 < n1 ? 1 : (a.periodic[1] ? 1 - n1 : 0)) * sy;
+  double s = fabs(a.S[0][c]) + (dxm ? fabs(a.S[0][c + dxm]) : 0.0) + fabs(a.S[1][c]) +
+             (dym ? fabs(a.S[1][c + dym]) : 0.0);
+  if (a.dim == 3) {
+    const int dzm = (idx[2] > 0 ? -1 : (a.periodic[2] ? n2 - 1 : 0)) * sz;
+    const int dzp = (idx[2] + 1 < n2 ? 1 : (a.periodic[2] ? 1 - n2 : 0)) * sz;
+    s += fabs(a.S[2][c]) + (dzm ? fabs(a.S[2][c + dzm]) : 0.0);
+    if (a.mixed) {
+      s += fabs(a.S[3][c]) + fabs(a.S[3][c + dxm + dym]) + fabs(a.S[4][c]) + fabs(a.S[4][c + dxm + dyp]);
+      s += fabs(a.S[5][c]) + fabs(a.S[5][c + dxm + dzm]) + fabs(a.S[6][c]) + fabs(a.S[6][c + dxm + dzp]);
+      s += fabs(a.S[7][c]) + fabs(a.S[7][c + dym + dzm]) + fabs(a.S[8][c]) + fabs(a.S[8][c + dym + dzp]);
+    }
+  } else if (a.mixed) {
+    s += fabs(a.S[3][c]) + fabs(a.S[3][c + dxm + dym]) + fabs(a.S[4][c]) + fabs(a.S[4][c + dxm + dyp]);
+  }
+  out[c] = s / fabs(a.diag[c]);
 }
 
 __device__ inline double restrict_cell(const LevelArgs& fa, const double* __restrict__ phi,
@@ -916,6 +956,72 @@ static int first_small_level(const GridCtx& G) {
   return ls;
 }
 
+// nu (even) Chebyshev smoothing steps on level l, targeting the upper part
+// [lam_max / 8, lam_max] of the spectrum of D^-1 A (the modes the coarse grid
+// cannot represent), lam_max from the Gershgorin bound; phi and phi2 alternate
+// and the result ends in phi.  With partials != null the last step sums the
+// squared residual of its input.
+static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStream_t st) {
+  const Level& L = G.lev[l];
+  LevelArgs a = level_args(G, l);
+  const dim3 gr = grid3(L);
+  const double lmax = L.lam_max, lmin = L.lam_max / 8.0;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  for (int s = 0; s < nu; ++s) {
+    const double* in = (s & 1) ? L.phi2 : L.phi;
+    double* out = (s & 1) ? L.phi : L.phi2;
+    double cr, cd;
+    if (s == 0) {
+      cr = 1.0 / theta;
+      cd = 0.0;
+    } else {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      cr = 2.0 * rn / delta;
+      cd = rn * rho;
+      rho = rn;
+    }
+    const bool last = s + 1 == nu;
+    hipLaunchKernelGGL(smooth_kernel, gr, BLOCK3, 0, st, a, in, L.rhs, out, cr, cd,
+                       (const double*)(s == 0 ? nullptr : L.aux), last ? (double*)nullptr : L.aux, G.mg_flag,
+                       last ? partials : (double*)nullptr);
+  }
+}
+
+// Upper spectral bound of D^-1 A on every level (once, at set-up).
+int compute_smoother_bounds(GridCtx& G, hipStream_t st) {
+  for (int l = 0; l < G.nlev; ++l) {
+    Level& L = G.lev[l];
+    LevelArgs a = level_args(G, l);
+    hipLaunchKernelGGL(gershgorin_kernel, grid3(L), BLOCK3, 0, st, a, L.res);
+    std::vector<double> h((size_t)L.ncells);
+    if (hipMemcpyAsync(h.data(), L.res, sizeof(double) * (size_t)L.ncells, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return -1;
+    double m = 0.0;
+    for (double v : h) m = v > m ? v : m;
+    L.lam_max = 1.0 + m;
+  }
+  return 0;
+}
+
+// phi <- 2 phi - prev, prev <- old phi (linear extrapolation in time of the
+// initial guess); with extrapolate = 0 only prev <- phi.
+__global__ void extrapolate_kernel(long long n, double* phi, double* prev, int extrapolate) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double t = phi[c];
+  if (extrapolate) phi[c] = 2.0 * t - prev[c];
+  prev[c] = t;
+}
+
+void launch_extrapolate_guess(const GridCtx& G, int extrapolate, hipStream_t st) {
+  const Level& L = G.lev[0];
+  unsigned blocks = (unsigned)((L.ncells + 255) / 256);
+  hipLaunchKernelGGL(extrapolate_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, L.phi, G.phi_prev, extrapolate);
+}
+
 // One V-cycle from level l.  With partials != null, the last smoothing sweep
 // on level 0 also sums the squared residual (of its input) per block.
 static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, hipStream_t st) {
@@ -942,22 +1048,14 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
   const Level& L = G.lev[l];
   LevelArgs a = level_args(G, l);
   const dim3 gr = grid3(L);
-  const double omega = 0.8;
-  for (int s = 0; s < nu1; s += 2) {
-    hipLaunchKernelGGL(smooth_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, L.phi2, omega, G.mg_flag, (double*)nullptr);
-    hipLaunchKernelGGL(smooth_kernel, gr, BLOCK3, 0, st, a, L.phi2, L.rhs, L.phi, omega, G.mg_flag, (double*)nullptr);
-  }
+  chebyshev(G, l, nu1, nullptr, st);
   const Level& C = G.lev[l + 1];
   hipLaunchKernelGGL(residual_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, L.res, G.mg_flag);
   hipLaunchKernelGGL(restrict_kernel, grid3(C), BLOCK3, 0, st, G.g.dim, L.n[0], L.n[1], (const double*)L.res,
                      C.n[0], C.n[1], C.rhs, C.phi, G.mg_flag);
   vcycle(G, l + 1, nu1, nu2, nullptr, st);
   hipLaunchKernelGGL(prolong_kernel, gr, BLOCK3, 0, st, a, L.phi, C.phi, C.n[0], C.n[1], C.n[2], G.mg_flag);
-  for (int s = 0; s < nu2; s += 2) {
-    hipLaunchKernelGGL(smooth_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, L.phi2, omega, G.mg_flag, (double*)nullptr);
-    hipLaunchKernelGGL(smooth_kernel, gr, BLOCK3, 0, st, a, L.phi2, L.rhs, L.phi, omega, G.mg_flag,
-                       (s + 2 >= nu2) ? partials : (double*)nullptr);
-  }
+  chebyshev(G, l, nu2, partials, st);
 }
 
 // Solve A phi = rhs on level 0 (phi holds the initial guess).  Returns the

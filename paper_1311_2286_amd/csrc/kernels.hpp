@@ -107,7 +107,8 @@ struct Level {
   double* phi2;      // ping-pong
   double* rhs;
   double* res;
-  double* aux;       // coarsest-level solver vector
+  double* aux;       // Chebyshev direction; coarsest-level solver vector
+  double lam_max;    // upper bound of the spectrum of D^-1 A (host)
 };
 
 struct GridCtx {
@@ -129,6 +130,7 @@ struct GridCtx {
   int* mg_flag;       // [0] converged [1] cycles done
   void* Ev;           // vertex field (float or double, interleaved)
   double* Kv;         // inverse Jacobian at vertices, d x d row-major (FP64)
+  double* phi_prev;   // level-0 potential of the previous step
   int fp64;
 };
 
@@ -144,6 +146,8 @@ struct ChargeSpecies {
 void launch_charge(const GridCtx& G, const ChargeSpecies& cs, double bg_charge, hipStream_t st);
 void launch_rhs(const GridCtx& G, hipStream_t st);
 int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st);
+int compute_smoother_bounds(GridCtx& G, hipStream_t st);
+void launch_extrapolate_guess(const GridCtx& G, int extrapolate, hipStream_t st);
 void launch_gauge(const GridCtx& G, hipStream_t st);
 void launch_vertex_metric(const GridCtx& G, hipStream_t st);
 void launch_efield(const GridCtx& G, hipStream_t st);
