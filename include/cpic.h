@@ -67,7 +67,8 @@ typedef enum {
   CPIC_E_OVERFLOW = -6,    /* fixed-point deposit headroom exceeded */
   CPIC_E_NONFINITE = -7,   /* non-finite value found in a field */
   CPIC_E_STATE = -8,       /* call out of order */
-  CPIC_E_UNSUPPORTED = -9  /* valid but not implemented combination */
+  CPIC_E_UNSUPPORTED = -9, /* valid but not implemented combination */
+  CPIC_E_PENDING = 1       /* serving: the work is not finished yet (not an error) */
 } cpic_status;
 
 /* map kinds */
@@ -215,11 +216,12 @@ cpic_status cpic_get_diag(cpic_sim* sim, cpic_diag* out);
 /* Wait for all work on the simulation's stream. */
 cpic_status cpic_sync(cpic_sim* sim);
 
-/* Per-step durations (ms) of the last cpic_step call, measured with HIP
-   events on the simulation's stream once enabled by cpic_set_timing(sim, 1):
-   particle kernels, field phase (charge, solve, vertex field), tile sort,
-   whole step.  Writes at most cap samples per array (any array may be NULL);
-   *samples receives the number of steps recorded.  Synchronises. */
+/* Per-step durations (ms) of every step since timing was last enabled by
+   cpic_set_timing(sim, 1) (which clears the record), measured with HIP events
+   on the simulation's stream: particle kernels, field phase (charge, solve,
+   vertex field), tile sort, whole step.  Writes at most cap samples per array
+   (any array may be NULL); *samples receives the number of steps recorded.
+   Synchronises. */
 cpic_status cpic_set_timing(cpic_sim* sim, int enable);
 cpic_status cpic_get_timing(cpic_sim* sim, int cap, double* push_ms, double* solve_ms,
                             double* sort_ms, double* step_ms, int* samples);
@@ -227,6 +229,78 @@ cpic_status cpic_get_timing(cpic_sim* sim, int cap, double* push_ms, double* sol
 const char* cpic_status_str(cpic_status s);
 const char* cpic_last_error(const cpic_sim* sim);
 void cpic_destroy(cpic_sim* sim);
+
+/* ------------------------------------------------------------------ serving
+ * A request loop over independent simulation cases, such as the parameter
+ * sweeps of the paper's probe studies (object potential, plasma temperature;
+ * Sec. "Tests").  Cases are admitted in submission order whenever a slot is
+ * free and their device memory fits the HBM budget (admission is exact: a
+ * case's allocations are counted against the budget while it is created, and
+ * a case that does not fit waits until a running case finishes).  Admitted
+ * cases stay resident and each pump iteration advances every running case by
+ * one step, each slot on its own HIP stream, so their work overlaps on the
+ * GPU.  A case's result does not depend on which other cases ran beside it.
+ * The server is single-threaded: call it from one host thread. */
+#define CPIC_MAX_SPECIES 8
+typedef struct cpic_server cpic_server;
+
+typedef struct {
+  cpic_map_desc map;
+  cpic_grid_desc grid;
+  int nspecies;                             /* 1..CPIC_MAX_SPECIES */
+  cpic_species_desc species[CPIC_MAX_SPECIES]; /* capacity 0 means the initial count */
+  size_t count[CPIC_MAX_SPECIES];           /* initial particles per species */
+  const int32_t* cell[CPIC_MAX_SPECIES];    /* host arrays laid out as for cpic_set_particles; */
+  const void* off[CPIC_MAX_SPECIES];        /* copied at submit (the caller may free them after) */
+  const void* vel[CPIC_MAX_SPECIES];
+  int nsteps;                               /* steps after cpic_initialize, >= 1 */
+  double* phi_out;                          /* optional host array of n cells: the potential after
+                                               the last step, written before the case reports done */
+} cpic_case_desc;
+
+typedef struct {
+  int status;             /* CPIC_OK when finished; else why the case failed (CPIC_E_BUDGET: it can
+                             never fit the budget) */
+  int steps;
+  double kinetic, field_energy, mg_relres; /* as cpic_diag after the last step */
+  int nspecies;
+  long long count[CPIC_MAX_SPECIES], absorbed[CPIC_MAX_SPECIES], outflow[CPIC_MAX_SPECIES],
+      injected[CPIC_MAX_SPECIES];
+  uint64_t qsum_lo[CPIC_MAX_SPECIES], qsum_hi[CPIC_MAX_SPECIES];
+  long long pushes;       /* particle pushes over all steps */
+  double queue_ms;        /* submit -> admission (host clock) */
+  double service_ms;      /* admission -> completion (host clock) */
+  double step_p50_ms, step_p99_ms; /* per-step durations from HIP events on the case's stream */
+} cpic_case_result;
+
+typedef struct {
+  long long submitted, completed, failed, queued, active;
+  long long peak_active;  /* most cases resident at once */
+  size_t budget_bytes, used_bytes, peak_bytes;
+  long long pushes;       /* over completed cases */
+  long long step_samples;
+  double step_p50_ms, step_p99_ms; /* over every step of every completed case */
+} cpic_server_stats;
+
+/* hbm_budget_bytes: device memory the cases may hold together; max_slots:
+   cases resident at once (1..64); alloc: as for cpic_create (NULL: hipMalloc);
+   hip_stream: NULL to give every slot its own stream (created and destroyed
+   by the server), else every case runs on that stream. */
+cpic_status cpic_server_create(size_t hbm_budget_bytes, int max_slots, const cpic_allocator* alloc,
+                               void* hip_stream, cpic_server** out);
+/* Queue a case; *ticket identifies it.  Validates the description (CPIC_E_ARG)
+   and copies the particle arrays. */
+cpic_status cpic_server_submit(cpic_server* srv, const cpic_case_desc* desc, uint64_t* ticket);
+/* Run up to max_iterations rounds of: admit, one step of every running case,
+   retire finished cases.  Returns CPIC_OK when nothing is queued or running
+   afterwards, CPIC_E_PENDING otherwise. */
+cpic_status cpic_server_pump(cpic_server* srv, int max_iterations);
+/* CPIC_E_PENDING until the case is done, then CPIC_OK with *out filled
+   (out->status tells whether it succeeded); CPIC_E_ARG for an unknown ticket. */
+cpic_status cpic_server_poll(cpic_server* srv, uint64_t ticket, cpic_case_result* out);
+cpic_status cpic_server_get_stats(cpic_server* srv, cpic_server_stats* out);
+/* Frees every resident case and the server's streams. */
+void cpic_server_destroy(cpic_server* srv);
 
 #ifdef __cplusplus
 }

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcpic.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["particles.hip", "fields.hip", "api.hip"]
+SOURCES = ["particles.hip", "fields.hip", "api.hip", "server.hip"]
 ARCH = os.environ.get("CPIC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

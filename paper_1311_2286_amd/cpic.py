@@ -27,7 +27,11 @@ FIELD_Q, FIELD_CHARGE, FIELD_PHI, FIELD_EV, FIELD_JC, FIELD_RHO, FIELD_BACKGROUN
 EXPORTED = ["cpic_create", "cpic_add_species", "cpic_set_particles", "cpic_get_particles",
             "cpic_initialize", "cpic_step", "cpic_run_stage", "cpic_get_field", "cpic_set_field",
             "cpic_field_bytes", "cpic_get_diag", "cpic_sync", "cpic_set_timing", "cpic_get_timing",
-            "cpic_status_str", "cpic_last_error", "cpic_destroy"]
+            "cpic_status_str", "cpic_last_error", "cpic_destroy", "cpic_server_create",
+            "cpic_server_submit", "cpic_server_pump", "cpic_server_poll", "cpic_server_get_stats",
+            "cpic_server_destroy"]
+MAX_SPECIES = 8
+E_PENDING = 1
 
 
 class MapDesc(ctypes.Structure):
@@ -70,6 +74,37 @@ class Diag(ctypes.Structure):
                 ("injected", ctypes.c_longlong * 8)]
 
 
+class CaseDesc(ctypes.Structure):
+    _fields_ = [("map", MapDesc), ("grid", GridDesc), ("nspecies", ctypes.c_int),
+                ("species", SpeciesDesc * MAX_SPECIES), ("count", ctypes.c_size_t * MAX_SPECIES),
+                ("cell", ctypes.c_void_p * MAX_SPECIES), ("off", ctypes.c_void_p * MAX_SPECIES),
+                ("vel", ctypes.c_void_p * MAX_SPECIES), ("nsteps", ctypes.c_int),
+                ("phi_out", ctypes.c_void_p)]
+
+
+class CaseResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("steps", ctypes.c_int), ("kinetic", ctypes.c_double),
+                ("field_energy", ctypes.c_double), ("mg_relres", ctypes.c_double),
+                ("nspecies", ctypes.c_int), ("count", ctypes.c_longlong * MAX_SPECIES),
+                ("absorbed", ctypes.c_longlong * MAX_SPECIES),
+                ("outflow", ctypes.c_longlong * MAX_SPECIES),
+                ("injected", ctypes.c_longlong * MAX_SPECIES),
+                ("qsum_lo", ctypes.c_uint64 * MAX_SPECIES), ("qsum_hi", ctypes.c_uint64 * MAX_SPECIES),
+                ("pushes", ctypes.c_longlong), ("queue_ms", ctypes.c_double),
+                ("service_ms", ctypes.c_double), ("step_p50_ms", ctypes.c_double),
+                ("step_p99_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong),
+                ("failed", ctypes.c_longlong), ("queued", ctypes.c_longlong),
+                ("active", ctypes.c_longlong), ("peak_active", ctypes.c_longlong),
+                ("budget_bytes", ctypes.c_size_t),
+                ("used_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
+                ("pushes", ctypes.c_longlong), ("step_samples", ctypes.c_longlong),
+                ("step_p50_ms", ctypes.c_double), ("step_p99_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -103,10 +138,18 @@ def load():
     L.cpic_last_error.restype = ctypes.c_char_p
     L.cpic_destroy.argtypes = [vp]
     L.cpic_destroy.restype = None
+    L.cpic_server_create.argtypes = [sz, i32, P(Allocator), vp, P(vp)]
+    L.cpic_server_submit.argtypes = [vp, P(CaseDesc), P(ctypes.c_uint64)]
+    L.cpic_server_pump.argtypes = [vp, i32]
+    L.cpic_server_poll.argtypes = [vp, ctypes.c_uint64, P(CaseResult)]
+    L.cpic_server_get_stats.argtypes = [vp, P(ServerStats)]
+    L.cpic_server_destroy.argtypes = [vp]
+    L.cpic_server_destroy.restype = None
     for name in ("cpic_create", "cpic_add_species", "cpic_set_particles", "cpic_get_particles",
                  "cpic_initialize", "cpic_step", "cpic_run_stage", "cpic_get_field",
                  "cpic_set_field", "cpic_get_diag", "cpic_sync", "cpic_set_timing",
-                 "cpic_get_timing"):
+                 "cpic_get_timing", "cpic_server_create", "cpic_server_submit",
+                 "cpic_server_pump", "cpic_server_poll", "cpic_server_get_stats"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -148,6 +191,34 @@ def _ptr(a):
     if isinstance(a, np.ndarray):
         return a.ctypes.data_as(ctypes.c_void_p)
     return ctypes.c_void_p(a.data_ptr())  # torch tensor
+
+
+def _pad(t, v):
+    return tuple(t)[:3] + (v,) * (3 - len(tuple(t)[:3]))
+
+
+def make_map_desc(map_kind, dim, L=(1.0, 1.0, 1.0), eps=0.0, r_in=1.0, r_out=2.0):
+    return MapDesc(map_kind, dim, (ctypes.c_double * 3)(*_pad(L, 1.0)), eps, r_in, r_out)
+
+
+def make_grid_desc(n, bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), phi_lo=(0.0, 0.0, 0.0),
+                   phi_hi=(0.0, 0.0, 0.0), shape=SHAPE_B2, precision=FP32, dt=0.1,
+                   B0=(0.0, 0.0, 0.0), background=False, background_n0=1.0, mg_rtol=1e-10,
+                   mg_max_cycles=30, sort_every=1, track_ids=False):
+    return GridDesc((ctypes.c_int * 3)(*_pad(n, 1)), (ctypes.c_int * 3)(*_pad(bc_lo, 0)),
+                    (ctypes.c_int * 3)(*_pad(bc_hi, 0)), (ctypes.c_double * 3)(*_pad(phi_lo, 0.0)),
+                    (ctypes.c_double * 3)(*_pad(phi_hi, 0.0)), shape, precision, dt,
+                    (ctypes.c_double * 3)(*_pad(B0, 0.0)), int(background), background_n0,
+                    mg_rtol, mg_max_cycles, sort_every, int(track_ids))
+
+
+def make_species_desc(q, m, w, capacity=0, pbc_lo=(0, 0, 0), pbc_hi=(0, 0, 0), inject=None,
+                      seed=0):
+    inj = inject or {}
+    return SpeciesDesc(q, m, w, (ctypes.c_int * 3)(*_pad(pbc_lo, 0)),
+                       (ctypes.c_int * 3)(*_pad(pbc_hi, 0)), int(capacity),
+                       int(inject is not None), float(inj.get("n0", 0.0)),
+                       float(inj.get("vth", 0.0)), int(seed))
 
 
 class Sim:
@@ -313,3 +384,89 @@ class Sim:
 
 def qsum(d: Diag, sid: int) -> int:
     return int(d.qsum_lo[sid]) + (int(d.qsum_hi[sid]) << 64)
+
+
+class Server:
+    """The serving loop of include/cpic.h: cases admitted by slot and HBM
+    budget, advanced one step per pump iteration on per-slot streams."""
+
+    def __init__(self, budget_bytes, max_slots, torch_alloc=True, stream=None):
+        self.lib = load()
+        self._alloc = TorchAllocator() if torch_alloc else None
+        self._keep = {}  # ticket -> host arrays that must outlive submit (phi_out)
+        h = ctypes.c_void_p()
+        st = self.lib.cpic_server_create(int(budget_bytes), int(max_slots),
+                                         ctypes.byref(self._alloc.struct) if self._alloc else None,
+                                         ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if st != 0:
+            raise CpicError(st, "cpic_server_create")
+        self.h = h
+
+    def submit(self, map_desc, grid_desc, species, particles, nsteps, want_phi=False):
+        """species: list of SpeciesDesc; particles: list of dicts cell [n], off [dim, n],
+        vel [3, n] (numpy, the grid's precision).  Returns the ticket."""
+        d = CaseDesc()
+        d.map = map_desc
+        d.grid = grid_desc
+        d.nspecies = len(species)
+        rdt = np.float64 if grid_desc.precision == FP64 else np.float32
+        held = []
+        for k, (sd, p) in enumerate(zip(species, particles)):
+            d.species[k] = sd
+            cell = np.ascontiguousarray(p["cell"], dtype=np.int32)
+            off = np.ascontiguousarray(p["off"], dtype=rdt)
+            vel = np.ascontiguousarray(p["vel"], dtype=rdt)
+            held += [cell, off, vel]
+            d.count[k] = cell.size
+            d.cell[k] = cell.ctypes.data
+            d.off[k] = off.ctypes.data
+            d.vel[k] = vel.ctypes.data
+        d.nsteps = int(nsteps)
+        phi = None
+        if want_phi:
+            phi = np.zeros(int(np.prod(list(grid_desc.n)[: map_desc.dim])), dtype=np.float64)
+            d.phi_out = phi.ctypes.data
+        t = ctypes.c_uint64()
+        st = self.lib.cpic_server_submit(self.h, ctypes.byref(d), ctypes.byref(t))
+        if st != 0:
+            raise CpicError(st, "cpic_server_submit")
+        self._keep[t.value] = phi
+        return t.value
+
+    def pump(self, max_iterations=1):
+        st = self.lib.cpic_server_pump(self.h, int(max_iterations))
+        if st not in (0, E_PENDING):
+            raise CpicError(st, "cpic_server_pump")
+        return st == 0
+
+    def poll(self, ticket):
+        """None while pending, else a dict of the case result (phi when requested)."""
+        r = CaseResult()
+        st = self.lib.cpic_server_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(r))
+        if st == E_PENDING:
+            return None
+        if st != 0:
+            raise CpicError(st, "cpic_server_poll")
+        out = {f: getattr(r, f) for f, _ in CaseResult._fields_}
+        for f in ("count", "absorbed", "outflow", "injected", "qsum_lo", "qsum_hi"):
+            out[f] = list(out[f])[: r.nspecies]
+        out["phi"] = self._keep.get(ticket)
+        return out
+
+    def stats(self):
+        s = ServerStats()
+        st = self.lib.cpic_server_get_stats(self.h, ctypes.byref(s))
+        if st != 0:
+            raise CpicError(st, "cpic_server_get_stats")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cpic_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -756,7 +756,6 @@ extern "C" cpic_status cpic_step(cpic_sim* s, int nsteps) {
   if (!s || nsteps < 0) return CPIC_E_ARG;
   if (s->poisoned) return fail(s, CPIC_E_STATE, "simulation poisoned by an earlier device error");
   if (!s->initialized) return fail(s, CPIC_E_STATE, "cpic_initialize has not been called");
-  if (s->timing) s->ev_used = 0;
   for (int k = 0; k < nsteps; ++k) {
     ensure_sorted(s);
     StepEvents* ev = s->timing ? next_events(s) : nullptr;
@@ -934,6 +933,7 @@ extern "C" const char* cpic_status_str(cpic_status st) {
     case CPIC_E_NONFINITE: return "non-finite value";
     case CPIC_E_STATE: return "call out of order";
     case CPIC_E_UNSUPPORTED: return "unsupported combination";
+    case CPIC_E_PENDING: return "pending";
   }
   return "unknown status";
 }

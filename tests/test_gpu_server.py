@@ -1,0 +1,119 @@
+"""GPU tests of the serving loop (cpic_server_* in include/cpic.h): independent
+2D periodic sinusoidal-map cases (the paper's distorted-mesh test setting,
+Eq. map2) of different grids, perturbation amplitudes and temperatures,
+admitted by slot and HBM budget and advanced together on per-slot streams.
+
+Bars:
+  - a case's result (kinetic and field energy, exact charge sums, counts and
+    the final potential) is bitwise the same run alone, in a mix with other
+    cases, and as a plain simulation outside the server;
+  - the budget is never exceeded, cases that do not fit wait for memory and
+    then complete; a case larger than the whole budget fails with
+    CPIC_E_BUDGET without disturbing the others."""
+import numpy as np
+import pytest
+
+from paper_1311_2286_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def C():
+    from paper_1311_2286_amd import cpic
+    return cpic
+
+
+def serving_case(n, eps, ppc, vth, case_id):
+    return W.Case("serve_%d" % case_id, 2, W.SINUSOIDAL, (n, n), L=(float(n), float(n)), eps=eps,
+                  dt=0.1, species=[W.electrons(vth, ppc)], background=True, delta=0.01,
+                  case_id=case_id)
+
+
+def descs(case):
+    c = C()
+    m = c.make_map_desc(case.map_kind, case.dim, case.L, case.eps)
+    g = c.make_grid_desc(case.n, shape=c.SHAPE_B2, precision=c.FP32, dt=case.dt, background=True,
+                         background_n0=1.0, mg_rtol=1e-10, mg_max_cycles=40, sort_every=4)
+    sp = [c.make_species_desc(s.q, s.m, case.weight(s)) for s in case.species]
+    parts = [W.generate_species(case, sid, dtype=np.float32) for sid in range(len(case.species))]
+    return m, g, sp, parts
+
+
+CASES = [serving_case(32, 0.10, 16.0, 1.0, 401), serving_case(48, 0.05, 12.0, 0.7, 402),
+         serving_case(64, 0.15, 8.0, 1.5, 403)]
+NSTEPS = 12
+
+
+def run_server(case_list, slots, budget, want_phi=True):
+    prepared = [descs(case) for case in case_list]
+    srv = C().Server(budget, slots)
+    tickets = [srv.submit(m, g, sp, parts, NSTEPS, want_phi=want_phi) for m, g, sp, parts in prepared]
+    for _ in range(100000):
+        if srv.pump(8):
+            break
+    res = [srv.poll(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    return res, stats
+
+
+def same(a, b):
+    for f in ("status", "steps", "kinetic", "field_energy", "count", "qsum_lo", "qsum_hi", "absorbed",
+              "outflow", "injected", "pushes"):
+        assert a[f] == b[f], (f, a[f], b[f])
+    assert np.array_equal(a["phi"], b["phi"])
+
+
+def test_case_result_is_the_same_alone_in_a_mix_and_outside_the_server():
+    A = CASES[0]
+    alone, st1 = run_server([A], slots=1, budget=1 << 30)
+    assert alone[0]["status"] == 0 and alone[0]["steps"] == NSTEPS
+    mixed, st2 = run_server([CASES[2], A, CASES[1]], slots=3, budget=1 << 30)
+    assert all(r["status"] == 0 for r in mixed)
+    same(alone[0], mixed[1])
+    assert st2["completed"] == 3 and st2["step_samples"] == 3 * NSTEPS
+    assert st2["pushes"] == sum(r["pushes"] for r in mixed)
+    assert 0 < st2["step_p50_ms"] <= st2["step_p99_ms"]
+    # the same case as a plain simulation
+    c = C()
+    m, g, sp, parts = descs(A)
+    sim = c.Sim(A.map_kind, 2, A.n, L=A.L, eps=A.eps, dt=A.dt, background=True, mg_rtol=1e-10,
+                mg_max_cycles=40, sort_every=4)
+    sim.add_species(A.species[0].q, A.species[0].m, A.weight(A.species[0]), parts[0]["cell"].size)
+    sim.set_particles(0, parts[0]["cell"], parts[0]["off"], parts[0]["vel"])
+    sim.initialize()
+    sim.step(NSTEPS)
+    d = sim.diag()
+    assert d.kinetic == alone[0]["kinetic"] and d.field_energy == alone[0]["field_energy"]
+    assert np.array_equal(sim.get_field(c.FIELD_PHI), alone[0]["phi"])
+    sim.close()
+
+
+def test_admission_by_budget_and_a_case_that_never_fits():
+    # three cases of the same size (different seeds); a budget of 1.5 cases
+    # lets one run at a time although three slots are free
+    same_size = [serving_case(64, 0.15, 8.0, 1.5, 410 + k) for k in range(3)]
+    _, st = run_server(same_size[:1], slots=1, budget=1 << 30, want_phi=False)
+    one = st["peak_bytes"]
+    budget = int(one * 1.5)
+    res, st = run_server(same_size, slots=3, budget=budget, want_phi=False)
+    assert all(r["status"] == 0 for r in res)
+    assert st["peak_bytes"] <= budget and st["completed"] == 3
+    assert st["peak_active"] == 1
+    # with room for all three they run together
+    res, st = run_server(same_size, slots=3, budget=4 * one, want_phi=False)
+    assert all(r["status"] == 0 for r in res) and st["peak_active"] == 3
+    # a case larger than the whole budget fails; the others complete
+    big = serving_case(256, 0.05, 16.0, 1.0, 404)
+    res, st = run_server([CASES[0], big, CASES[1]], slots=2, budget=budget, want_phi=False)
+    assert res[0]["status"] == 0 and res[2]["status"] == 0
+    assert res[1]["status"] == -4  # CPIC_E_BUDGET
+    assert st["failed"] == 1 and st["completed"] == 2
