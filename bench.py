@@ -198,6 +198,91 @@ def cpu_baseline(case, sample, shape):
                        "gather+push+map-inversion+deposit pass, %.1f s" % (sample, t_total))
 
 
+def serving_requests(nreq, seed=1311):
+    """The serving stream: 2D periodic sinusoidal-map cases, eps ~ U[0, 0.15],
+    L = N, grid from {32^2, 64^2, 128^2, 256^2}, 16..128 electrons per cell
+    on a fixed ion background, v_th ~ U[0.5, 2], dt = 0.1."""
+    from paper_1311_2286_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(nreq):
+        n = int(rng.choice([32, 64, 128, 256]))
+        eps = float(rng.uniform(0.0, 0.15))
+        ppc = int(rng.integers(16, 129))
+        vth = float(rng.uniform(0.5, 2.0))
+        out.append(W.Case("serve_%d" % k, 2, W.SINUSOIDAL, (n, n), L=(float(n), float(n)), eps=eps,
+                          dt=0.1, species=[W.electrons(vth, float(ppc))], background=True,
+                          delta=0.01, case_id=1000 + k))
+    return out
+
+
+def serving_descs(case, mg_rtol, mg_cycles):
+    from paper_1311_2286_amd import cpic as C
+    from paper_1311_2286_amd import workloads as W
+    m = C.make_map_desc(case.map_kind, case.dim, case.L, case.eps)
+    g = C.make_grid_desc(case.n, shape=C.SHAPE_B2, precision=C.FP32, dt=case.dt, background=True,
+                         background_n0=1.0, mg_rtol=mg_rtol, mg_max_cycles=mg_cycles, sort_every=4)
+    sp = [C.make_species_desc(s.q, s.m, case.weight(s)) for s in case.species]
+    parts = [W.generate_species(case, sid, dtype=np.float32, workers=16)
+             for sid in range(len(case.species))]
+    return m, g, sp, parts
+
+
+def run_serving(nreq, nsteps, budget, slots, load, mg_rtol, mg_cycles, seed=1311):
+    """Poisson arrivals at rate load / tau (tau: mean service time of a case
+    alone, measured first on a sample of the requests); every request is
+    submitted when its arrival time has passed, and the server is pumped one
+    iteration at a time.  Returns the served throughput and latencies."""
+    from paper_1311_2286_amd import cpic as C
+    reqs = serving_requests(nreq, seed)
+    t0 = time.time()
+    prepared = [serving_descs(c, mg_rtol, mg_cycles) for c in reqs]
+    log("serving: generated %d requests (%d particles) in %.1f s"
+        % (nreq, sum(p[3][0]["cell"].size for p in prepared), time.time() - t0))
+    # tau: each of a sample of requests alone
+    sample = list(range(0, nreq, max(1, nreq // 4)))[:4]
+    taus = []
+    for k in sample:
+        srv = C.Server(budget, 1)
+        t = srv.submit(*prepared[k], nsteps)
+        while not srv.pump(16):
+            pass
+        taus.append(srv.poll(t)["service_ms"] / 1e3)
+        srv.close()
+    tau = float(np.mean(taus))
+    rate = load / tau
+    rng = np.random.default_rng(seed + 1)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=nreq))
+    srv = C.Server(budget, slots)
+    tickets = []
+    t_start = time.perf_counter()
+    k = 0
+    while True:
+        now = time.perf_counter() - t_start
+        while k < nreq and arrivals[k] <= now:
+            tickets.append(srv.submit(*prepared[k], nsteps))
+            k += 1
+        idle = srv.pump(1)
+        if idle and k == nreq:
+            break
+        if idle:
+            time.sleep(max(0.0, min(0.01, arrivals[k] - (time.perf_counter() - t_start))))
+    wall = time.perf_counter() - t_start
+    res = [srv.poll(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    lat = [r["queue_ms"] + r["service_ms"] for r in res]
+    ok = sum(1 for r in res if r["status"] == 0)
+    return {"requests": nreq, "completed": ok, "steps_per_request": nsteps, "load": load,
+            "tau_s": tau, "arrival_rate_per_s": rate, "wall_s": wall,
+            "pushes": st["pushes"], "pushes_per_s": st["pushes"] / wall,
+            "step_p50_ms": st["step_p50_ms"], "step_p99_ms": st["step_p99_ms"],
+            "request_latency_p50_s": float(np.percentile(lat, 50)) / 1e3,
+            "request_latency_p99_s": float(np.percentile(lat, 99)) / 1e3,
+            "peak_active": st["peak_active"], "peak_bytes": st["peak_bytes"],
+            "budget_bytes": budget, "slots": slots}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +300,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--serve", action="store_true",
+                    help="only run the serving stream (64 requests, 500 steps each)")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=500)
+    ap.add_argument("--serve-load", type=float, default=8.0,
+                    help="arrival rate in units of 1 / (mean service time alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path; "
@@ -225,6 +316,20 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibrate:
         copy_calibrate(1 << 30, 5)
+        return
+    if args.serve:
+        from paper_1311_2286_amd import cpic as C
+        C.load()
+        sv = run_serving(args.serve_requests, args.serve_steps, 1 << 30, 32, args.serve_load,
+                         args.mg_rtol, args.mg_cycles)
+        print(json.dumps({"metric": "served particle pushes/s; p50/p99 step ms", "value": sv["pushes_per_s"],
+                          "unit": "particle pushes/s", "n_gpus": 1, "higher_is_better": True,
+                          "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": "serving stream: %d requests, 2D periodic sinusoidal "
+                                                 "maps, grids 32^2..256^2, %d steps each, HBM budget "
+                                                 "1 GiB, 32 slots" % (args.serve_requests,
+                                                                      args.serve_steps)},
+                          "serving": sv}), flush=True)
         return
     from paper_1311_2286_amd import cpic as C
     from paper_1311_2286_amd import workloads as W
