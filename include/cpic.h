@@ -165,6 +165,7 @@ typedef struct {
   long long far_deposits;    /* cumulative deposits outside the tile window */
   long long newton_failed;   /* cumulative position updates that missed the tolerance */
   long long injected[8];     /* cumulative injected particles per species */
+  int step_graphs;           /* step variants recorded as HIP graphs (graph mode) */
 } cpic_diag;
 
 /* Create a simulation on the current HIP device.  hip_stream may be NULL
@@ -226,6 +227,17 @@ cpic_status cpic_set_timing(cpic_sim* sim, int enable);
 cpic_status cpic_get_timing(cpic_sim* sim, int cap, double* push_ms, double* solve_ms,
                             double* sort_ms, double* step_ms, int* samples);
 
+/* Graph mode (enable != 0): each distinct variant of a step (buffer parity of
+   every species after the last sort, whether this step sorts, whether the
+   solve's initial guess is extrapolated) is recorded once as a HIP graph by
+   stream capture and replayed by later steps, so a step costs one launch on
+   the host.  Results are bitwise those of the ordinary path.  Steps with flux
+   injection always run the ordinary path.  With timing enabled, a replayed
+   step reports only its whole duration (the phase durations read 0).  Off by
+   default.  Capture needs a stream other than the null stream; on the null
+   stream every step runs the ordinary path (cpic_diag.step_graphs stays 0). */
+cpic_status cpic_set_graphs(cpic_sim* sim, int enable);
+
 const char* cpic_status_str(cpic_status s);
 const char* cpic_last_error(const cpic_sim* sim);
 void cpic_destroy(cpic_sim* sim);
@@ -240,7 +252,9 @@ void cpic_destroy(cpic_sim* sim);
  * cases stay resident and each pump iteration advances every running case by
  * one step, each slot on its own HIP stream, so their work overlaps on the
  * GPU.  A case's result does not depend on which other cases ran beside it.
- * The server is single-threaded: call it from one host thread. */
+ * The server is single-threaded: call it from one host thread.  Its cases
+ * step in graph mode (cpic_set_graphs) unless the environment variable
+ * CPIC_SERVER_NO_GRAPHS is set. */
 #define CPIC_MAX_SPECIES 8
 typedef struct cpic_server cpic_server;
 

@@ -27,7 +27,7 @@ FIELD_Q, FIELD_CHARGE, FIELD_PHI, FIELD_EV, FIELD_JC, FIELD_RHO, FIELD_BACKGROUN
 EXPORTED = ["cpic_create", "cpic_add_species", "cpic_set_particles", "cpic_get_particles",
             "cpic_initialize", "cpic_step", "cpic_run_stage", "cpic_get_field", "cpic_set_field",
             "cpic_field_bytes", "cpic_get_diag", "cpic_sync", "cpic_set_timing", "cpic_get_timing",
-            "cpic_status_str", "cpic_last_error", "cpic_destroy", "cpic_server_create",
+            "cpic_status_str", "cpic_last_error", "cpic_destroy", "cpic_set_graphs", "cpic_server_create",
             "cpic_server_submit", "cpic_server_pump", "cpic_server_poll", "cpic_server_get_stats",
             "cpic_server_destroy"]
 MAX_SPECIES = 8
@@ -71,7 +71,7 @@ class Diag(ctypes.Structure):
                 ("outflow", ctypes.c_longlong * 8), ("qsum_lo", ctypes.c_uint64 * 8),
                 ("qsum_hi", ctypes.c_uint64 * 8), ("newton_fallback", ctypes.c_longlong),
                 ("far_deposits", ctypes.c_longlong), ("newton_failed", ctypes.c_longlong),
-                ("injected", ctypes.c_longlong * 8)]
+                ("injected", ctypes.c_longlong * 8), ("step_graphs", ctypes.c_int)]
 
 
 class CaseDesc(ctypes.Structure):
@@ -138,6 +138,7 @@ def load():
     L.cpic_last_error.restype = ctypes.c_char_p
     L.cpic_destroy.argtypes = [vp]
     L.cpic_destroy.restype = None
+    L.cpic_set_graphs.argtypes = [vp, i32]
     L.cpic_server_create.argtypes = [sz, i32, P(Allocator), vp, P(vp)]
     L.cpic_server_submit.argtypes = [vp, P(CaseDesc), P(ctypes.c_uint64)]
     L.cpic_server_pump.argtypes = [vp, i32]
@@ -148,7 +149,7 @@ def load():
     for name in ("cpic_create", "cpic_add_species", "cpic_set_particles", "cpic_get_particles",
                  "cpic_initialize", "cpic_step", "cpic_run_stage", "cpic_get_field",
                  "cpic_set_field", "cpic_get_diag", "cpic_sync", "cpic_set_timing",
-                 "cpic_get_timing", "cpic_server_create", "cpic_server_submit",
+                 "cpic_get_timing", "cpic_set_graphs", "cpic_server_create", "cpic_server_submit",
                  "cpic_server_pump", "cpic_server_poll", "cpic_server_get_stats"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -369,6 +370,10 @@ class Sim:
         d = Diag()
         self._check(self.lib.cpic_get_diag(self.h, ctypes.byref(d)), "get_diag")
         return d
+
+    def set_graphs(self, on=True):
+        """Replay recorded HIP graphs of the step (needs a non-null stream)."""
+        self._check(self.lib.cpic_set_graphs(self.h, int(on)), "set_graphs")
 
     def set_timing(self, on=True):
         self._check(self.lib.cpic_set_timing(self.h, int(on)), "set_timing")

@@ -40,6 +40,7 @@ struct Species {
   int* item_begin = nullptr;
   int* item_end = nullptr;
   int max_items = 0;
+  double* ke_part = nullptr;
   // absorbed, outflow, fallback, far, nonconv, injected, dropped, ids issued
   unsigned long long* counters = nullptr;
   double inject_lam = 0.0;
@@ -69,6 +70,13 @@ struct cpic_sim {
   bool poisoned = false;
   bool sorted_dirty = true;
   bool phi_prev_valid = false;  // G.phi_prev holds the previous step's potential
+  bool graphs = false;          // replay recorded HIP graphs of the step
+  struct StepGraph {
+    uint32_t key;
+    hipGraphExec_t exec;
+    std::vector<int> cur_after;
+  };
+  std::vector<StepGraph> step_graphs;
   long long step = 0;
   double* ke = nullptr;  // device: kinetic energy of the last push
   int* flags = nullptr;  // device ints: [0] bad input count
@@ -445,6 +453,7 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
   S.item_tile = (int*)A(sizeof(int) * S.max_items);
   S.item_begin = (int*)A(sizeof(int) * S.max_items);
   S.item_end = (int*)A(sizeof(int) * S.max_items);
+  S.ke_part = (double*)A(sizeof(double) * S.max_items);
   S.counters = (unsigned long long*)A(sizeof(unsigned long long) * 8);
   S.fb_queue = (int*)A(sizeof(int) * S.cap);
   S.fb_count = (int*)A(sizeof(int) * 2);
@@ -639,8 +648,21 @@ static void particles_pass(cpic_sim* s, int mode) {
     L.fb_cap = (int)S.cap;
     L.ke_scale = 0.5 * S.desc.m * S.desc.w;
     L.ke = s->ke;
+    L.ke_part = S.ke_part;
     L.counters = S.counters;
     launch_particles(L, s->stream);
+  }
+  if (mode == MODE_PUSH) {
+    KeReduce r;
+    memset(&r, 0, sizeof(r));
+    r.nspecies = (int)s->sp.size();
+    for (int k = 0; k < r.nspecies; ++k) {
+      r.part[k] = s->sp[k].ke_part;
+      r.n_items[k] = s->sp[k].n_items;
+      r.scale[k] = 0.5 * s->sp[k].desc.m * s->sp[k].desc.w;
+    }
+    r.out = s->ke;
+    launch_ke_reduce(r, s->stream);
   }
 }
 
@@ -752,6 +774,81 @@ static StepEvents* next_events(cpic_sim* s) {
   return &s->evs[s->ev_used++];
 }
 
+// The kernels of one step after ensure_sorted (asynchronous, no host reads).
+static void step_body(cpic_sim* s, StepEvents* ev, bool inj, bool do_sort) {
+  if (ev) hipEventRecord(ev->e[0], s->stream);
+  zero_deposits(s, MODE_PUSH);
+  if (ev) hipEventRecord(ev->e[1], s->stream);
+  particles_pass(s, MODE_PUSH);
+  if (ev) hipEventRecord(ev->e[2], s->stream);
+  if (inj) inject_pass(s, s->step);
+  charge_pass(s);
+  // initial guess of the solve: phi extrapolated linearly from the last two steps
+  launch_extrapolate_guess(s->G, s->phi_prev_valid ? 1 : 0, s->stream);
+  s->phi_prev_valid = true;
+  solve_pass(s);
+  launch_efield(s->G, s->stream);
+  if (ev) hipEventRecord(ev->e[3], s->stream);
+  ++s->step;
+  if (do_sort) sort_all(s);
+  if (ev) hipEventRecord(ev->e[4], s->stream);
+}
+
+// One step as a HIP graph: every step variant (buffer parity of each species,
+// sort or not, extrapolated guess or not) is recorded once by stream capture
+// and replayed afterwards; the host state a replay stands for (buffer parity,
+// step count) is applied here.  Returns false when capture is not possible.
+static bool graph_step(cpic_sim* s, bool do_sort, StepEvents* ev) {
+  uint32_t key = (do_sort ? 1u : 0u) | (s->phi_prev_valid ? 2u : 0u);
+  for (size_t k = 0; k < s->sp.size(); ++k) key |= (uint32_t)s->sp[k].cur << (2 + k);
+  if (ev) {
+    hipEventRecord(ev->e[0], s->stream);
+    for (int i = 1; i < 4; ++i) hipEventRecord(ev->e[i], s->stream);
+  }
+  for (auto& gph : s->step_graphs) {
+    if (gph.key != key) continue;
+    if (hipGraphLaunch(gph.exec, s->stream) != hipSuccess) return false;
+    for (size_t k = 0; k < s->sp.size(); ++k) s->sp[k].cur = gph.cur_after[k];
+    s->phi_prev_valid = true;
+    ++s->step;
+    if (do_sort) s->sorted_dirty = false;
+    if (ev) hipEventRecord(ev->e[4], s->stream);
+    return true;
+  }
+  // record: the capture runs the host logic of the step (which advances the
+  // host state) while the kernels go into the graph instead of the GPU
+  std::vector<int> cur_before;
+  for (auto& S : s->sp) cur_before.push_back(S.cur);
+  const bool prev_before = s->phi_prev_valid;
+  const long long step_before = s->step;
+  if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();  // e.g. the null stream cannot be captured
+    return false;
+  }
+  step_body(s, nullptr, false, do_sort);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ok = hipStreamEndCapture(s->stream, &graph) == hipSuccess && graph &&
+            hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (graph) (void)hipGraphDestroy(graph);
+  if (!ok || hipGraphLaunch(exec, s->stream) != hipSuccess) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    // nothing ran: restore the host state and let the caller step eagerly
+    for (size_t k = 0; k < s->sp.size(); ++k) s->sp[k].cur = cur_before[k];
+    s->phi_prev_valid = prev_before;
+    s->step = step_before;
+    (void)hipGetLastError();
+    return false;
+  }
+  cpic_sim::StepGraph gph;
+  gph.key = key;
+  gph.exec = exec;
+  for (auto& S : s->sp) gph.cur_after.push_back(S.cur);
+  s->step_graphs.push_back(gph);
+  if (ev) hipEventRecord(ev->e[4], s->stream);
+  return true;
+}
+
 extern "C" cpic_status cpic_step(cpic_sim* s, int nsteps) {
   if (!s || nsteps < 0) return CPIC_E_ARG;
   if (s->poisoned) return fail(s, CPIC_E_STATE, "simulation poisoned by an earlier device error");
@@ -759,26 +856,20 @@ extern "C" cpic_status cpic_step(cpic_sim* s, int nsteps) {
   for (int k = 0; k < nsteps; ++k) {
     ensure_sorted(s);
     StepEvents* ev = s->timing ? next_events(s) : nullptr;
-    if (ev) hipEventRecord(ev->e[0], s->stream);
-    zero_deposits(s, MODE_PUSH);
-    if (ev) hipEventRecord(ev->e[1], s->stream);
-    particles_pass(s, MODE_PUSH);
-    if (ev) hipEventRecord(ev->e[2], s->stream);
     const bool inj = any_injection(s);
-    if (inj) inject_pass(s, s->step);
-    charge_pass(s);
-    // initial guess of the solve: phi extrapolated linearly from the last two steps
-    launch_extrapolate_guess(s->G, s->phi_prev_valid ? 1 : 0, s->stream);
-    s->phi_prev_valid = true;
-    solve_pass(s);
-    launch_efield(s->G, s->stream);
-    if (ev) hipEventRecord(ev->e[3], s->stream);
-    ++s->step;
     // appended particles join a tile at the next sort: sort every step then
-    if (inj || s->step % s->grid.sort_every == 0) sort_all(s);
-    if (ev) hipEventRecord(ev->e[4], s->stream);
+    const bool do_sort = inj || (s->step + 1) % s->grid.sort_every == 0;
+    // injection draws depend on the step number, a kernel argument: no graphs
+    if (s->graphs && !inj && graph_step(s, do_sort, ev)) continue;
+    step_body(s, ev, inj, do_sort);
   }
   return check_async(s);
+}
+
+extern "C" cpic_status cpic_set_graphs(cpic_sim* s, int enable) {
+  if (!s) return CPIC_E_ARG;
+  s->graphs = enable != 0;
+  return CPIC_OK;
 }
 
 // ----------------------------------------------------------------------------
@@ -849,6 +940,7 @@ extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
   hipStream_t st = s->stream;
   out->step = s->step;
   out->nspecies = (int)s->sp.size();
+  out->step_graphs = (int)s->step_graphs.size();
   double ke = 0.0;
   HIPCHK(s, hipMemcpyAsync(&ke, s->ke, sizeof(double), hipMemcpyDeviceToHost, st));
   launch_field_energy(s->G, s->tmp_scalar, st);
@@ -943,6 +1035,7 @@ extern "C" const char* cpic_last_error(const cpic_sim* s) { return s ? s->err.c_
 extern "C" void cpic_destroy(cpic_sim* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
+  for (auto& gph : s->step_graphs) (void)hipGraphExecDestroy(gph.exec);
   for (auto& e : s->evs)
     for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e.e[i]);
   sim_free_all(s);

@@ -36,7 +36,16 @@ struct ParticleLaunch {
   int fb_cap;
   double ke_scale;
   double* ke;
+  double* ke_part;  // [max_items] per-item kinetic energy sums (PUSH)
   unsigned long long* counters;
+};
+
+struct KeReduce {
+  int nspecies;
+  const double* part[8];
+  const int* n_items[8];
+  double scale[8];
+  double* out;
 };
 
 struct SortLaunch {
@@ -81,6 +90,7 @@ struct InjectLaunch {
 };
 
 int launch_particles(const ParticleLaunch& L, hipStream_t st);
+void launch_ke_reduce(const KeReduce& r, hipStream_t st);
 int launch_inject(const InjectLaunch& I, hipStream_t st);
 int launch_tile_sort(const SortLaunch& S, hipStream_t st);
 void launch_lin_to_key(const int32_t* lin, int32_t* key, int n, const Geo& g, int* bad, hipStream_t st);

@@ -250,6 +250,7 @@ struct PartArgs {
   R inv_dxc[3];
   double ke_scale;
   double* ke;
+  double* ke_part;
   unsigned long long* counters;
   int* fb_queue;  // particles left to the FP64 fallback kernel
   int* fb_count;
@@ -692,7 +693,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? 5 :
       s += red_d[w];
       for (int i = 0; i < 5; ++i) u[i] += red_u[w][i];
     }
-    if (a.mode == MODE_PUSH && s != 0.0) atomicAdd(a.ke, s * a.ke_scale);
+    // per-item slot, summed in a fixed order afterwards (deterministic energy)
+    if (a.mode == MODE_PUSH) a.ke_part[item] = s;
     for (int i = 0; i < 5; ++i)
       if (u[i]) atomicAdd(&a.counters[i], u[i]);
   }
@@ -1226,6 +1228,7 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   a.kappa = (R)L.kappa;
   for (int i = 0; i < 3; ++i) a.inv_dxc[i] = (R)(1.0 / L.g.dxc[i]);
   a.ke_scale = L.ke_scale;
+  a.ke_part = L.ke_part;
   a.ke = L.ke;
   a.counters = L.counters;
   a.fb_queue = L.fb_queue;
@@ -1314,6 +1317,31 @@ static int launch_inject_r(const InjectLaunch& I, hipStream_t st) {
 
 int launch_inject(const InjectLaunch& I, hipStream_t st) {
   return I.fp64 ? launch_inject_r<double>(I, st) : launch_inject_r<float>(I, st);
+}
+
+// Kinetic energy of the step: the per-item sums of every species added in a
+// fixed order (strided per thread, then a fixed tree), species by species.
+__global__ __launch_bounds__(256) void ke_reduce_kernel(KeReduce r) {
+  __shared__ double sh[256];
+  double total = 0.0;
+  for (int k = 0; k < r.nspecies; ++k) {
+    const int n = *r.n_items[k];
+    double t = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) t += r.part[k][i];
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    total += r.scale[k] * sh[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *r.out = total;
+}
+
+void launch_ke_reduce(const KeReduce& r, hipStream_t st) {
+  hipLaunchKernelGGL(ke_reduce_kernel, dim3(1), dim3(256), 0, st, r);
 }
 
 int launch_tile_sort(const SortLaunch& S, hipStream_t st) {

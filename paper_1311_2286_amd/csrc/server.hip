@@ -4,6 +4,7 @@
 // per-step latencies collected when a case finishes.  Host code on top of the
 // public C ABI (cpic.h) and the HIP runtime.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -66,6 +67,7 @@ struct cpic_server {
   long long submitted = 0, completed = 0, failed = 0, pushes = 0, peak_active = 0;
   std::vector<double> step_samples;
   cpic_allocator counting;  // handed to every case
+  bool no_graphs = false;   // cases step without recorded graphs (CPIC_SERVER_NO_GRAPHS set)
 };
 
 namespace {
@@ -123,6 +125,8 @@ int admit_one(cpic_server* s, Case* c, int slot) {
   }
   if (rc == CPIC_OK) rc = cpic_initialize(sim);
   if (rc == CPIC_OK) rc = cpic_set_timing(sim, 1);
+  // one host launch per step: the loop over many small cases is host-bound otherwise
+  if (rc == CPIC_OK && !s->no_graphs) rc = cpic_set_graphs(sim, 1);
   if (rc != CPIC_OK) {
     cpic_destroy(sim);
     return rc;
@@ -248,6 +252,7 @@ extern "C" cpic_status cpic_server_create(size_t hbm_budget_bytes, int max_slots
     }
   }
   s->slot_busy.assign((size_t)max_slots, 0);
+  s->no_graphs = getenv("CPIC_SERVER_NO_GRAPHS") != nullptr;
   *out = s;
   return CPIC_OK;
 }
