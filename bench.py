@@ -105,13 +105,26 @@ def copy_calibrate(nbytes, reps):
                       "launches": reps}), flush=True)
 
 
-def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts):
+_STREAM = None
+
+
+def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, graphs=False):
+    """graphs: step in graph mode, on a stream of its own (default priority)."""
+    global _STREAM
+    import torch
     from paper_1311_2286_amd import cpic as C
+    stream = None
+    if graphs:
+        if _STREAM is None:
+            _STREAM = torch.cuda.Stream()
+        stream = _STREAM.cuda_stream
     sim = C.Sim(case.map_kind, case.dim, case.n, L=case.L, eps=case.eps, r_in=case.r_in,
                 r_out=case.r_out, bc_lo=case.bc_lo, bc_hi=case.bc_hi, phi_lo=case.phi_lo,
                 phi_hi=case.phi_hi, shape=shape, precision=precision, dt=case.dt, B0=case.B,
                 background=case.background, mg_rtol=mg_rtol, mg_max_cycles=mg_cycles,
-                sort_every=sort_every, track_ids=False)
+                sort_every=sort_every, track_ids=False, stream=stream)
+    if graphs:
+        sim.set_graphs(True)
     for sid, s in enumerate(case.species):
         p = parts[sid]
         n = p["cell"].size
@@ -125,11 +138,12 @@ def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts):
     return sim
 
 
-def run_path(case, parts, precision, shape, steps, warmup, sort_every, mg_rtol, mg_cycles):
+def run_path(case, parts, precision, shape, steps, warmup, sort_every, mg_rtol, mg_cycles,
+             graphs=False):
     import torch
     from paper_1311_2286_amd import cpic as C
     t0 = time.time()
-    sim = make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts)
+    sim = make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, graphs)
     sim.initialize()
     sim.sync()
     log("precision", precision, "set up + initialise %.1f s" % (time.time() - t0))
