@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from _golden import paper_value
 
 pytestmark = pytest.mark.filterwarnings("ignore")
 
@@ -34,8 +35,8 @@ def test_sinusoidal_2d_jacobian_closed_form():
 
 
 def test_cell_size_ratio_printed_in_paper():
-    # "the ratio of the largest to smallest cell size is 4.4" at eps = 0.1:
-    # J ranges over [1 - 2 pi eps, 1 + 2 pi eps].
+    # the paper gives the largest-to-smallest cell size ratio of the eps = 0.1
+    # map to one decimal (tests/golden); J ranges over [1 - 2 pi eps, 1 + 2 pi eps]
     m = O.make_map(O.SINUSOIDAL, 2, (1.0, 1.0), 0.1)
     g = (np.arange(400) + 0.5) / 400
     X, Y = np.meshgrid(g, g, indexing="ij")
@@ -43,7 +44,7 @@ def test_cell_size_ratio_printed_in_paper():
     _, _, _, J = O.map_eval(m, xi)
     ratio = J.max() / J.min()
     assert abs(ratio - (1 + 0.2 * np.pi) / (1 - 0.2 * np.pi)) < 2e-3
-    assert round(ratio, 1) == 4.4
+    assert round(ratio, 1) == paper_value("cell_size_ratio_eps_0.1")
 
 
 def test_sinusoidal_3d_jacobian_closed_form_and_singular_eps():
