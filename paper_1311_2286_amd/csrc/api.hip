@@ -71,8 +71,10 @@ struct cpic_sim {
   bool sorted_dirty = true;
   bool phi_prev_valid = false;  // G.phi_prev holds the previous step's potential
   bool graphs = false;          // replay recorded HIP graphs of the step
+  int* cycles_host = nullptr;   // pinned: V-cycles of a recent solve (written by async copies)
+  bool cycles_known = false;
   struct StepGraph {
-    uint32_t key;
+    uint64_t key;
     hipGraphExec_t exec;
     std::vector<int> cur_after;
   };
@@ -358,6 +360,12 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   launch_fill_u8(G.mg_flag, 0, sizeof(int) * 4, st);
   launch_jacobian_centres(G, st);
   launch_vertex_metric(G, st);
+  if (hipHostMalloc((void**)&s->cycles_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    s->cycles_host = nullptr;
+    cpic_destroy(s);
+    return CPIC_E_NOMEM;
+  }
+  *s->cycles_host = -1;
   if (compute_smoother_bounds(G, st) != 0) {
     cpic_destroy(s);
     return CPIC_E_HIP;
@@ -720,10 +728,27 @@ static void charge_pass(cpic_sim* s) {
   launch_charge(s->G, cs, 1.0, s->stream);
 }
 
-static void solve_pass(cpic_sim* s) {
+// cycles: V-cycles to launch (the solve stops on the device once converged;
+// cycles launched after that return at once but still cost their launches)
+static void solve_pass(cpic_sim* s, int cycles = -1) {
   launch_rhs(s->G, s->stream);
-  launch_mg_solve(s->G, s->grid.mg_rtol, s->grid.mg_max_cycles, 2, 2, s->stream);
+  launch_mg_solve(s->G, s->grid.mg_rtol, cycles > 0 ? cycles : s->grid.mg_max_cycles, 2, 2, s->stream);
   launch_gauge(s->G, s->stream);
+}
+
+// Cycles to launch in a time step: two more than the last solve whose count
+// has reached the host (copied back asynchronously), at most the cap; the cap
+// until a count is known.
+static int step_cycles(const cpic_sim* s) {
+  const int last = s->cycles_host ? *(volatile int*)s->cycles_host : -1;
+  if (last < 0 || !s->cycles_known) return s->grid.mg_max_cycles;
+  return std::min(s->grid.mg_max_cycles, last + 2);
+}
+
+static void record_cycles(cpic_sim* s) {
+  if (!s->cycles_host) return;
+  (void)hipMemcpyAsync(s->cycles_host, s->G.mg_flag + 1, sizeof(int), hipMemcpyDeviceToHost, s->stream);
+  s->cycles_known = true;
 }
 
 static void ensure_sorted(cpic_sim* s) {
@@ -761,6 +786,7 @@ extern "C" cpic_status cpic_initialize(cpic_sim* s) {
   s->initialized = true;
   s->step = 0;
   s->phi_prev_valid = false;
+  s->cycles_known = false;
   return check_async(s);
 }
 
@@ -775,7 +801,7 @@ static StepEvents* next_events(cpic_sim* s) {
 }
 
 // The kernels of one step after ensure_sorted (asynchronous, no host reads).
-static void step_body(cpic_sim* s, StepEvents* ev, bool inj, bool do_sort) {
+static void step_body(cpic_sim* s, StepEvents* ev, bool inj, bool do_sort, int cycles) {
   if (ev) hipEventRecord(ev->e[0], s->stream);
   zero_deposits(s, MODE_PUSH);
   if (ev) hipEventRecord(ev->e[1], s->stream);
@@ -786,7 +812,7 @@ static void step_body(cpic_sim* s, StepEvents* ev, bool inj, bool do_sort) {
   // initial guess of the solve: phi extrapolated linearly from the last two steps
   launch_extrapolate_guess(s->G, s->phi_prev_valid ? 1 : 0, s->stream);
   s->phi_prev_valid = true;
-  solve_pass(s);
+  solve_pass(s, cycles);
   launch_efield(s->G, s->stream);
   if (ev) hipEventRecord(ev->e[3], s->stream);
   ++s->step;
@@ -798,9 +824,9 @@ static void step_body(cpic_sim* s, StepEvents* ev, bool inj, bool do_sort) {
 // sort or not, extrapolated guess or not) is recorded once by stream capture
 // and replayed afterwards; the host state a replay stands for (buffer parity,
 // step count) is applied here.  Returns false when capture is not possible.
-static bool graph_step(cpic_sim* s, bool do_sort, StepEvents* ev) {
-  uint32_t key = (do_sort ? 1u : 0u) | (s->phi_prev_valid ? 2u : 0u);
-  for (size_t k = 0; k < s->sp.size(); ++k) key |= (uint32_t)s->sp[k].cur << (2 + k);
+static bool graph_step(cpic_sim* s, bool do_sort, int cycles, StepEvents* ev) {
+  uint64_t key = (do_sort ? 1u : 0u) | (s->phi_prev_valid ? 2u : 0u) | ((uint64_t)cycles << 16);
+  for (size_t k = 0; k < s->sp.size(); ++k) key |= (uint64_t)s->sp[k].cur << (2 + k);
   if (ev) {
     hipEventRecord(ev->e[0], s->stream);
     for (int i = 1; i < 4; ++i) hipEventRecord(ev->e[i], s->stream);
@@ -825,7 +851,7 @@ static bool graph_step(cpic_sim* s, bool do_sort, StepEvents* ev) {
     (void)hipGetLastError();  // e.g. the null stream cannot be captured
     return false;
   }
-  step_body(s, nullptr, false, do_sort);
+  step_body(s, nullptr, false, do_sort, cycles);
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool ok = hipStreamEndCapture(s->stream, &graph) == hipSuccess && graph &&
@@ -859,9 +885,10 @@ extern "C" cpic_status cpic_step(cpic_sim* s, int nsteps) {
     const bool inj = any_injection(s);
     // appended particles join a tile at the next sort: sort every step then
     const bool do_sort = inj || (s->step + 1) % s->grid.sort_every == 0;
+    const int cycles = step_cycles(s);
     // injection draws depend on the step number, a kernel argument: no graphs
-    if (s->graphs && !inj && graph_step(s, do_sort, ev)) continue;
-    step_body(s, ev, inj, do_sort);
+    if (!(s->graphs && !inj && graph_step(s, do_sort, cycles, ev))) step_body(s, ev, inj, do_sort, cycles);
+    record_cycles(s);
   }
   return check_async(s);
 }
@@ -931,6 +958,7 @@ extern "C" cpic_status cpic_set_field(cpic_sim* s, int which, int sid, const voi
   HIPCHK(s, hipStreamSynchronize(s->stream));
   // a potential set from outside starts a new time history
   if (which == CPIC_FIELD_PHI) s->phi_prev_valid = false;
+  if (which == CPIC_FIELD_PHI || which == CPIC_FIELD_CHARGE) s->cycles_known = false;
   return check_async(s);
 }
 
@@ -1036,6 +1064,7 @@ extern "C" void cpic_destroy(cpic_sim* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
   for (auto& gph : s->step_graphs) (void)hipGraphExecDestroy(gph.exec);
+  if (s->cycles_host) (void)hipHostFree(s->cycles_host);
   for (auto& e : s->evs)
     for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e.e[i]);
   sim_free_all(s);

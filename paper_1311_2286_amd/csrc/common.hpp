@@ -95,7 +95,13 @@ __device__ inline void sincos2pi(double u, double& s, double& c) { sincospi(2.0 
 
 __device__ inline void incr2pi(float u, float& sn, float& cm1) {
   float th = 6.28318530717958648f * u;
-  if (fabsf(th) < 0.8f) {
+  if (fabsf(th) < 0.1f) {
+    // the common Newton step (a fraction of a cell on a grid of many cells):
+    // truncation below 3e-11 at degree 5 and 6
+    float t2 = th * th;
+    sn = th * (1.0f - t2 * (1.0f / 6.0f) * (1.0f - t2 * (1.0f / 20.0f)));
+    cm1 = -0.5f * t2 * (1.0f - t2 * (1.0f / 12.0f) * (1.0f - t2 * (1.0f / 30.0f)));
+  } else if (fabsf(th) < 0.8f) {
     float t2 = th * th;
     sn = th * (1.0f - t2 * (1.0f / 6.0f) *
                           (1.0f - t2 * (1.0f / 20.0f) * (1.0f - t2 * (1.0f / 42.0f) * (1.0f - t2 * (1.0f / 72.0f)))));
@@ -121,6 +127,11 @@ template <> __device__ inline double r_expm1<double>(double x) { return expm1(x)
 template <typename R> __device__ inline R r_exp(R x);
 template <> __device__ inline float r_exp<float>(float x) { return expf(x); }
 template <> __device__ inline double r_exp<double>(double x) { return exp(x); }
+
+// reciprocal for the Newton steps: the hardware approximation (1 ulp) in FP32,
+// where the step tolerance is 1e-5 cell; correctly rounded in FP64
+__device__ inline float newton_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double newton_rcp(double x) { return 1.0 / x; }
 
 // ---------------------------------------------------------------------------
 // Position update: solve x(xi^n + delta h) - x(xi^n) = dt v for delta (in
@@ -150,25 +161,41 @@ __device__ __forceinline__ bool newton_sinusoidal(const Geo& g, const int* idx, 
     sincos2pi(phase, s[a], c[a]);
     e[a] = (R)g.ecell[a];
     w[a] = (R)6.28318530717958647692 * invn[a];
-    d[a] = (R)0;
   }
-  bool conv = false;
-  for (int it = 0; it < maxit; ++it) {
+  // first step from delta = 0, where F = -r: delta = r - e (g.r) / J
+  {
+    R gg[D];
+    R Jn = (R)1, gr = (R)0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      R t = w[a] * c[a];
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+        if (k != a) t *= s[k];
+      gg[a] = t;
+      Jn += e[a] * t;
+      gr += t * r[a];
+    }
+    J0 = Jn;
+    const R q = gr * newton_rcp(Jn);
+    R mx = (R)0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      d[a] = r[a] - e[a] * q;
+      mx = fmax(mx, fabs(d[a]));
+    }
+    if (mx < tol || kappa * mx * mx < (R)0.25 * tol) return true;
+  }
+  for (int it = 1; it < maxit; ++it) {
     R sn[D], cn[D], ds[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      if (it == 0) {
-        ds[a] = (R)0;
-        sn[a] = s[a];
-        cn[a] = c[a];
-      } else {
-        R st, cm1;
-        incr2pi(d[a] * invn[a], st, cm1);
-        ds[a] = s[a] * cm1 + c[a] * st;
-        R dc = c[a] * cm1 - s[a] * st;
-        sn[a] = s[a] + ds[a];
-        cn[a] = c[a] + dc;
-      }
+      R st, cm1;
+      incr2pi(d[a] * invn[a], st, cm1);
+      ds[a] = s[a] * cm1 + c[a] * st;
+      R dc = c[a] * cm1 - s[a] * st;
+      sn[a] = s[a] + ds[a];
+      cn[a] = c[a] + dc;
     }
     R dP;
     if (D == 2) {
@@ -192,8 +219,7 @@ __device__ __forceinline__ bool newton_sinusoidal(const Geo& g, const int* idx, 
       Jn += e[a] * gg[a];
       gF += gg[a] * F[a];
     }
-    if (it == 0) J0 = Jn;
-    R q = gF / Jn;
+    R q = gF * newton_rcp(Jn);
     R mx = (R)0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -201,12 +227,9 @@ __device__ __forceinline__ bool newton_sinusoidal(const Geo& g, const int* idx, 
       d[a] += dd;
       mx = fmax(mx, fabs(dd));
     }
-    if (mx < tol || kappa * mx * mx < (R)0.25 * tol) {
-      conv = true;
-      break;
-    }
+    if (mx < tol || kappa * mx * mx < (R)0.25 * tol) return true;
   }
-  return conv;
+  return false;
 }
 
 // Polar-log map: r = r_in exp(xi ln R), theta = 2 pi eta.  Increment in units

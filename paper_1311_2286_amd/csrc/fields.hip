@@ -961,7 +961,8 @@ static int first_small_level(const GridCtx& G) {
 // cannot represent), lam_max from the Gershgorin bound; phi and phi2 alternate
 // and the result ends in phi.  With partials != null the last step sums the
 // squared residual of its input.
-static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStream_t st) {
+static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStream_t st,
+                      double* first_partials = nullptr, double rtol2 = 0.0) {
   const Level& L = G.lev[l];
   LevelArgs a = level_args(G, l);
   const dim3 gr = grid3(L);
@@ -982,9 +983,17 @@ static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStre
       rho = rn;
     }
     const bool last = s + 1 == nu;
+    double* pp = last ? partials : (s == 0 ? first_partials : nullptr);
     hipLaunchKernelGGL(smooth_kernel, gr, BLOCK3, 0, st, a, in, L.rhs, out, cr, cd,
                        (const double*)(s == 0 ? nullptr : L.aux), last ? (double*)nullptr : L.aux, G.mg_flag,
-                       last ? partials : (double*)nullptr);
+                       pp);
+    if (s == 0 && first_partials) {
+      // the residual entering the first step is the solve's initial residual:
+      // stop here when the initial guess already meets the tolerance
+      const int nblk = (int)(gr.x * gr.y * gr.z);
+      hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, (const double*)first_partials, nblk,
+                         G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 0);
+    }
   }
 }
 
@@ -1024,7 +1033,8 @@ void launch_extrapolate_guess(const GridCtx& G, int extrapolate, hipStream_t st)
 
 // One V-cycle from level l.  With partials != null, the last smoothing sweep
 // on level 0 also sums the squared residual (of its input) per block.
-static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, hipStream_t st) {
+static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, hipStream_t st,
+                   double* first_partials = nullptr, double rtol2 = 0.0) {
   const int ls = first_small_level(G);
   if (l >= ls) {
     SmallLevels S;
@@ -1048,7 +1058,7 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
   const Level& L = G.lev[l];
   LevelArgs a = level_args(G, l);
   const dim3 gr = grid3(L);
-  chebyshev(G, l, nu1, nullptr, st);
+  chebyshev(G, l, nu1, nullptr, st, first_partials, rtol2);
   const Level& C = G.lev[l + 1];
   hipLaunchKernelGGL(residual_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, L.res, G.mg_flag);
   hipLaunchKernelGGL(restrict_kernel, grid3(C), BLOCK3, 0, st, G.g.dim, L.n[0], L.n[1], (const double*)L.res,
@@ -1074,16 +1084,20 @@ int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int 
   hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.partials, RED_BLOCKS, G.scalars + 0, 0,
                      0.0, (const double*)nullptr, (int*)nullptr, 0);
   const double rtol2 = rtol * rtol;
-  // initial residual
-  hipLaunchKernelGGL(residual_norm_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, G.mg_partials, G.mg_flag);
-  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.mg_partials, nblk, G.scalars + 1, 1,
-                     rtol2, G.scalars + 0, G.mg_flag, 0);
+  const bool small = first_small_level(G) == 0;
+  if (small) {
+    // initial residual (on a multi-workgroup level 0 the first smoothing step
+    // of the first cycle computes it)
+    hipLaunchKernelGGL(residual_norm_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, G.mg_partials, G.mg_flag);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.mg_partials, nblk, G.scalars + 1, 1,
+                       rtol2, G.scalars + 0, G.mg_flag, 0);
+  }
   for (int cyc = 0; cyc < max_cycles; ++cyc) {
-    if (first_small_level(G) == 0) {
+    if (small) {
       vcycle(G, 0, nu1, nu2, nullptr, st);
       hipLaunchKernelGGL(residual_norm_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, G.mg_partials, G.mg_flag);
     } else {
-      vcycle(G, 0, nu1, nu2, G.mg_partials, st);
+      vcycle(G, 0, nu1, nu2, G.mg_partials, st, cyc == 0 ? G.mg_partials : nullptr, rtol2);
     }
     hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.mg_partials, nblk, G.scalars + 1, 1,
                        rtol2, G.scalars + 0, G.mg_flag, 1);

@@ -69,8 +69,9 @@ def test_graph_steps_are_bitwise_the_ordinary_steps(name, precision):
         a.step(1)
         b.step(1)
         db = _same(a, b, precision == 0)
-    # variants: sort or not x buffer parity, and the first (not extrapolated) step
-    assert 3 <= db.step_graphs <= 5, db.step_graphs
+    # variants: sort or not x buffer parity x cycles launched, and the first
+    # (not extrapolated) step: graphs were recorded and reused
+    assert 3 <= db.step_graphs < 8, db.step_graphs
     a.step(7)
     b.step(7)
     _same(a, b, precision == 0)
