@@ -104,6 +104,14 @@ enum {
   CPIC_STAGE_INJECT = 7    /* this step's flux injection (appends, deposits into Q_s) */
 };
 
+/* Poisson solve method (cpic_grid_desc.mg_method) */
+enum {
+  CPIC_MG_FCG = 0,    /* flexible conjugate gradients, one V-cycle per iteration as the
+                         preconditioner (default: converges on strongly distorted,
+                         anisotropic grids where V-cycles alone can diverge) */
+  CPIC_MG_VCYCLE = 1  /* plain V-cycles */
+};
+
 typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);
@@ -130,9 +138,10 @@ typedef struct {
   int background;       /* 1: fixed neutralising background of density n0 */
   double background_n0; /* its density (charge +n0 per unit volume) */
   double mg_rtol;       /* relative residual target of the Poisson solve */
-  int mg_max_cycles;    /* multigrid V-cycles per solve (upper bound) */
+  int mg_max_cycles;    /* V-cycles per solve (upper bound; one per FCG iteration) */
   int sort_every;       /* tile sort every this many steps (>= 1) */
   int track_ids;        /* carry a uint32 particle id through sorts */
+  int mg_method;        /* CPIC_MG_FCG (0) or CPIC_MG_VCYCLE */
 } cpic_grid_desc;
 
 typedef struct {

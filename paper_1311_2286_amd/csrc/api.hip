@@ -186,6 +186,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   if (grid->precision != CPIC_FP32 && grid->precision != CPIC_FP64) return CPIC_E_ARG;
   if (!(grid->dt > 0) || !isfinite(grid->dt)) return CPIC_E_ARG;
   if (grid->background && (d != 2 || !all_periodic)) return CPIC_E_UNSUPPORTED;
+  if (grid->mg_method != CPIC_MG_FCG && grid->mg_method != CPIC_MG_VCYCLE) return CPIC_E_ARG;
 
   cpic_sim* s = new cpic_sim();
   s->map = *map;
@@ -330,7 +331,16 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   G.charge = (double*)A(cb);
   G.background = grid->background ? (double*)A(cb) : nullptr;
   G.partials = (double*)A(sizeof(double) * 1024);
-  G.mg_partials = (double*)A(sizeof(double) * (size_t)((g.n[0] + 63) / 64) * ((g.n[1] + 3) / 4) * g.n[2]);
+  const size_t sweep_blocks = (size_t)((g.n[0] + 63) / 64) * ((g.n[1] + 3) / 4) * g.n[2];
+  G.mg_partials = (double*)A(sizeof(double) * sweep_blocks);
+  if (grid->mg_method == CPIC_MG_FCG) {
+    G.kr = (double*)A(cb);
+    G.kz = (double*)A(cb);
+    G.kp = (double*)A(cb);
+    G.kq = (double*)A(cb);
+    G.kw = (double*)A(cb);
+    G.k_partials = (double*)A(sizeof(double) * 3 * sweep_blocks);
+  }
   G.scalars = (double*)A(sizeof(double) * 16);
   G.mg_flag = (int*)A(sizeof(int) * 4);
   G.Ev = A(real_size(s) * ecomp(s) * (size_t)g.nverts);
@@ -572,7 +582,7 @@ extern "C" cpic_status cpic_get_particles(cpic_sim* s, int sid, size_t cap, int3
 // ----------------------------------------------------------------------------
 // stages
 // ----------------------------------------------------------------------------
-static void sort_species(cpic_sim* s, Species& S) {
+static void sort_species(cpic_sim* s, Species& S, bool counts_ready) {
   SortLaunch L;
   memset(&L, 0, sizeof(L));
   L.g = s->g;
@@ -598,13 +608,14 @@ static void sort_species(cpic_sim* s, Species& S) {
   L.item_tile = S.item_tile;
   L.item_begin = S.item_begin;
   L.item_end = S.item_end;
-  launch_fill_u8(S.counts, 0, sizeof(int) * (s->g.ntiles + 2), s->stream);
+  L.counts_ready = counts_ready ? 1 : 0;
   launch_tile_sort(L, s->stream);
   S.cur = b;
 }
 
-static void sort_all(cpic_sim* s) {
-  for (auto& S : s->sp) sort_species(s, S);
+// counts_ready: the step's particle and injection kernels counted the tiles
+static void sort_all(cpic_sim* s, bool counts_ready = false) {
+  for (auto& S : s->sp) sort_species(s, S, counts_ready);
   s->sorted_dirty = false;
 }
 
@@ -618,7 +629,7 @@ static void zero_deposits(cpic_sim* s, int mode) {
 }
 
 // particle kernels of all species (deposit arrays must have been zeroed)
-static void particles_pass(cpic_sim* s, int mode) {
+static void particles_pass(cpic_sim* s, int mode, bool count_tiles = false) {
   const bool halfstep = mode == MODE_HALFSTEP;
   for (auto& S : s->sp) {
     ParticleLaunch L;
@@ -657,6 +668,7 @@ static void particles_pass(cpic_sim* s, int mode) {
     L.ke_scale = 0.5 * S.desc.m * S.desc.w;
     L.ke = s->ke;
     L.ke_part = S.ke_part;
+    L.tile_counts = (count_tiles && mode == MODE_PUSH) ? S.counts : nullptr;
     L.counters = S.counters;
     launch_particles(L, s->stream);
   }
@@ -681,7 +693,7 @@ static bool any_injection(const cpic_sim* s) {
 }
 
 // Maxwellian-flux injection of every injecting species for step `step`
-static void inject_pass(cpic_sim* s, long long step) {
+static void inject_pass(cpic_sim* s, long long step, bool count_tiles = false) {
   for (size_t k = 0; k < s->sp.size(); ++k) {
     Species& S = s->sp[k];
     if (!S.desc.inject) continue;
@@ -711,6 +723,7 @@ static void inject_pass(cpic_sim* s, long long step) {
     I.species = (uint32_t)k;
     I.counters = S.counters;
     I.count_out = S.d_n + 1;
+    I.tile_counts = count_tiles ? S.counts : nullptr;
     launch_inject(I, s->stream);
   }
 }
@@ -804,10 +817,14 @@ static StepEvents* next_events(cpic_sim* s) {
 static void step_body(cpic_sim* s, StepEvents* ev, bool inj, bool do_sort, int cycles) {
   if (ev) hipEventRecord(ev->e[0], s->stream);
   zero_deposits(s, MODE_PUSH);
+  // a step that ends with a tile sort counts the new tiles in its particle
+  // and injection kernels (the sort then needs no histogram pass)
+  if (do_sort)
+    for (auto& S : s->sp) launch_fill_u8(S.counts, 0, sizeof(int) * (size_t)(s->g.ntiles + 2), s->stream);
   if (ev) hipEventRecord(ev->e[1], s->stream);
-  particles_pass(s, MODE_PUSH);
+  particles_pass(s, MODE_PUSH, do_sort);
   if (ev) hipEventRecord(ev->e[2], s->stream);
-  if (inj) inject_pass(s, s->step);
+  if (inj) inject_pass(s, s->step, do_sort);
   charge_pass(s);
   // initial guess of the solve: phi extrapolated linearly from the last two steps
   launch_extrapolate_guess(s->G, s->phi_prev_valid ? 1 : 0, s->stream);
@@ -816,7 +833,7 @@ static void step_body(cpic_sim* s, StepEvents* ev, bool inj, bool do_sort, int c
   launch_efield(s->G, s->stream);
   if (ev) hipEventRecord(ev->e[3], s->stream);
   ++s->step;
-  if (do_sort) sort_all(s);
+  if (do_sort) sort_all(s, true);
   if (ev) hipEventRecord(ev->e[4], s->stream);
 }
 

@@ -1034,7 +1034,7 @@ void launch_extrapolate_guess(const GridCtx& G, int extrapolate, hipStream_t st)
 // One V-cycle from level l.  With partials != null, the last smoothing sweep
 // on level 0 also sums the squared residual (of its input) per block.
 static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, hipStream_t st,
-                   double* first_partials = nullptr, double rtol2 = 0.0) {
+                   double* first_partials, double rtol2) {
   const int ls = first_small_level(G);
   if (l >= ls) {
     SmallLevels S;
@@ -1063,15 +1063,162 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
   hipLaunchKernelGGL(residual_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, L.res, G.mg_flag);
   hipLaunchKernelGGL(restrict_kernel, grid3(C), BLOCK3, 0, st, G.g.dim, L.n[0], L.n[1], (const double*)L.res,
                      C.n[0], C.n[1], C.rhs, C.phi, G.mg_flag);
-  vcycle(G, l + 1, nu1, nu2, nullptr, st);
+  vcycle(G, l + 1, nu1, nu2, nullptr, st, nullptr, 0.0);
   hipLaunchKernelGGL(prolong_kernel, gr, BLOCK3, 0, st, a, L.phi, C.phi, C.n[0], C.n[1], C.n[2], G.mg_flag);
   chebyshev(G, l, nu2, partials, st);
 }
 
+// ----------------------------------------------------------------------------
+// Flexible conjugate gradients, truncated to one previous direction, with one
+// V-cycle (zero initial guess) as the preconditioner.  The V-cycle is not a
+// symmetric operator (summing restriction, bilinear prolongation), which the
+// flexible form tolerates; the outer iteration removes the few modes a
+// V-cycle alone amplifies on strongly distorted, anisotropic grids.  Per
+// iteration k (A symmetric, p_{k-1} . r_k = 0 by the choice of alpha):
+//   z = V(r), w = A z,
+//   beta = -(q_{k-1} . z) / (p_{k-1} . q_{k-1})          (0 on the first),
+//   p = z + beta p_{k-1},  q = A p = w + beta q_{k-1},
+//   p . q = z . w + 2 beta (q_{k-1} . z) + beta^2 (p_{k-1} . q_{k-1}),
+//   alpha = (z . r) / (p . q),  x += alpha p,  r -= alpha q.
+// Device scalars: [4] z.w  [5] q.z  [6] z.r  [7] p.q  [8] alpha  [9] beta.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fcg_residual_kernel(LevelArgs a, const double* __restrict__ x,
+                                                           const double* __restrict__ b, double* r, double* z,
+                                                           double* partials, const int* flag) {
+  if (flag[0]) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  double rr = 0.0;
+  if (i < a.n[0] && j < a.n[1]) {
+    const int idx[3] = {i, j, k};
+    const int c = i + a.n[0] * (j + a.n[1] * k);
+    const double v = b[c] - apply_A(a, x, idx, c);
+    r[c] = v;
+    z[c] = 0.0;
+    rr = v * v;
+  }
+  const double t = block_sum(rr);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = t;
+}
+
+// w = A z and the block sums of z.w, q.z (first iteration: 0), z.r
+__global__ __launch_bounds__(256) void fcg_apply_kernel(LevelArgs a, const double* __restrict__ z,
+                                                        const double* __restrict__ r, const double* __restrict__ q,
+                                                        double* w, double* partials, int nblk, int first,
+                                                        const int* flag) {
+  if (flag[0]) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  double zw = 0.0, qz = 0.0, zr = 0.0;
+  if (i < a.n[0] && j < a.n[1]) {
+    const int idx[3] = {i, j, k};
+    const int c = i + a.n[0] * (j + a.n[1] * k);
+    const double wc = apply_A(a, z, idx, c);
+    const double zc = z[c];
+    w[c] = wc;
+    zw = zc * wc;
+    qz = first ? 0.0 : q[c] * zc;
+    zr = zc * r[c];
+  }
+  const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  double t = block_sum(zw);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[blk] = t;
+  t = block_sum(qz);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[nblk + blk] = t;
+  t = block_sum(zr);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[2 * nblk + blk] = t;
+}
+
+// one workgroup: the three sums (fixed order), then beta, p.q and alpha
+__global__ __launch_bounds__(256) void fcg_coef_kernel(const double* __restrict__ partials, int nblk, double* sc,
+                                                       int first, const int* flag) {
+  if (flag[0]) return;
+  double v[3];
+  for (int m = 0; m < 3; ++m) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partials[m * nblk + i];
+    v[m] = block_sum(s);
+  }
+  if (threadIdx.x == 0) {
+    const double zw = v[0], qz = v[1], zr = v[2];
+    const double pq_prev = sc[7];
+    const double beta = (first || pq_prev == 0.0) ? 0.0 : -qz / pq_prev;
+    const double pq = zw + 2.0 * beta * qz + beta * beta * pq_prev;
+    sc[4] = zw;
+    sc[5] = qz;
+    sc[6] = zr;
+    sc[7] = pq;
+    // A and the V-cycle are both negative definite (on the zero-mean space
+    // when singular), so p.q and z.r share their sign; p.q = 0 only once r = 0
+    sc[8] = pq != 0.0 ? zr / pq : 0.0;
+    sc[9] = beta;
+  }
+}
+
+// p, q, x, r updated; z cleared for the next V-cycle; block sums of |r|^2
+__global__ __launch_bounds__(256) void fcg_update_kernel(LevelArgs a, const double* __restrict__ sc, double* z,
+                                                         double* p, const double* __restrict__ w, double* q,
+                                                         double* x, double* r, int first, double* partials,
+                                                         const int* flag) {
+  if (flag[0]) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  double rr = 0.0;
+  if (i < a.n[0] && j < a.n[1]) {
+    const int c = i + a.n[0] * (j + a.n[1] * k);
+    const double alpha = sc[8], beta = sc[9];
+    const double zc = z[c];
+    const double pc = first ? zc : zc + beta * p[c];
+    const double qc = first ? w[c] : w[c] + beta * q[c];
+    p[c] = pc;
+    q[c] = qc;
+    x[c] += alpha * pc;
+    const double rc = r[c] - alpha * qc;
+    r[c] = rc;
+    z[c] = 0.0;
+    rr = rc * rc;
+  }
+  const double t = block_sum(rr);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = t;
+}
+
+static int launch_fcg_solve(const GridCtx& G, double rtol2, int max_iter, int nu1, int nu2, hipStream_t st) {
+  const Level& L = G.lev[0];
+  LevelArgs a = level_args(G, 0);
+  const dim3 gr = grid3(L);
+  const int nblk = (int)(gr.x * gr.y * gr.z);
+  // the V-cycle runs on (z, r) in place of level 0's (phi, rhs)
+  GridCtx Gk = G;
+  Gk.lev[0].phi = G.kz;
+  Gk.lev[0].rhs = G.kr;
+  hipLaunchKernelGGL(fcg_residual_kernel, gr, BLOCK3, 0, st, a, (const double*)L.phi, (const double*)L.rhs, G.kr,
+                     G.kz, G.mg_partials, G.mg_flag);
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.mg_partials, nblk, G.scalars + 1, 1, rtol2,
+                     G.scalars + 0, G.mg_flag, 0);
+  for (int it = 0; it < max_iter; ++it) {
+    const int first = it == 0;
+    vcycle(Gk, 0, nu1, nu2, nullptr, st, nullptr, 0.0);
+    hipLaunchKernelGGL(fcg_apply_kernel, gr, BLOCK3, 0, st, a, (const double*)G.kz, (const double*)G.kr,
+                       (const double*)G.kq, G.kw, G.k_partials, nblk, first, G.mg_flag);
+    hipLaunchKernelGGL(fcg_coef_kernel, dim3(1), dim3(256), 0, st, (const double*)G.k_partials, nblk, G.scalars,
+                       first, G.mg_flag);
+    hipLaunchKernelGGL(fcg_update_kernel, gr, BLOCK3, 0, st, a, (const double*)G.scalars, G.kz, G.kp,
+                       (const double*)G.kw, G.kq, L.phi, G.kr, first, G.mg_partials, G.mg_flag);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.mg_partials, nblk, G.scalars + 1, 1, rtol2,
+                       G.scalars + 0, G.mg_flag, 1);
+  }
+  return max_iter;
+}
+
 // Solve A phi = rhs on level 0 (phi holds the initial guess).  Returns the
-// number of cycles launched; the number executed is in mg_flag[1].  The
-// convergence test after a cycle uses the residual entering its last sweep
-// (an upper bound of the final one in practice).
+// number of cycles launched; the number executed is in mg_flag[1].  With the
+// Krylov vectors present each cycle is one flexible-CG iteration and the test
+// uses the updated residual; with plain V-cycles the test after a cycle uses
+// the residual entering its last sweep (an upper bound of the final one in
+// practice).
 int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st) {
   const Level& L = G.lev[0];
   LevelArgs a = level_args(G, 0);
@@ -1084,6 +1231,7 @@ int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int 
   hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.partials, RED_BLOCKS, G.scalars + 0, 0,
                      0.0, (const double*)nullptr, (int*)nullptr, 0);
   const double rtol2 = rtol * rtol;
+  if (G.kr) return launch_fcg_solve(G, rtol2, max_cycles, nu1, nu2, st);
   const bool small = first_small_level(G) == 0;
   if (small) {
     // initial residual (on a multi-workgroup level 0 the first smoothing step
@@ -1094,7 +1242,7 @@ int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int 
   }
   for (int cyc = 0; cyc < max_cycles; ++cyc) {
     if (small) {
-      vcycle(G, 0, nu1, nu2, nullptr, st);
+      vcycle(G, 0, nu1, nu2, nullptr, st, nullptr, 0.0);
       hipLaunchKernelGGL(residual_norm_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, G.mg_partials, G.mg_flag);
     } else {
       vcycle(G, 0, nu1, nu2, G.mg_partials, st, cyc == 0 ? G.mg_partials : nullptr, rtol2);

@@ -37,6 +37,7 @@ struct ParticleLaunch {
   double ke_scale;
   double* ke;
   double* ke_part;  // [max_items] per-item kinetic energy sums (PUSH)
+  int* tile_counts; // when set: per-tile counts of the new positions for the next sort
   unsigned long long* counters;
 };
 
@@ -63,6 +64,7 @@ struct SortLaunch {
   uint32_t* id_out;
   int* d_n;
   int* counts;  // ntiles + 2
+  int counts_ready;  // counts already made by the step's kernels (else a histogram pass)
   int* start;   // ntiles + 2
   int* cursor;  // ntiles + 2
   int* n_items;
@@ -87,6 +89,7 @@ struct InjectLaunch {
   uint32_t k0, k1, step, species;
   unsigned long long* counters;
   int* count_out;
+  int* tile_counts;
 };
 
 int launch_particles(const ParticleLaunch& L, hipStream_t st);
@@ -141,6 +144,13 @@ struct GridCtx {
   void* Ev;           // vertex field (float or double, interleaved)
   double* Kv;         // inverse Jacobian at vertices, d x d row-major (FP64)
   double* phi_prev;   // level-0 potential of the previous step
+  // flexible conjugate gradients around the V-cycle (null when plain V-cycles)
+  double* kr;         // residual b - A x
+  double* kz;         // preconditioned residual (V-cycle iterate)
+  double* kp;         // search direction
+  double* kq;         // A p
+  double* kw;         // A z
+  double* k_partials; // 3 x level-0 sweep blocks
   int fp64;
 };
 

@@ -251,6 +251,7 @@ struct PartArgs {
   double ke_scale;
   double* ke;
   double* ke_part;
+  int* tcount;  // when set (steps followed by a tile sort): live particles per new tile, dead last
   unsigned long long* counters;
   int* fb_queue;  // particles left to the FP64 fallback kernel
   int* fb_count;
@@ -449,6 +450,35 @@ __device__ __forceinline__ void deposit_particle(const Geo& g, const int* origin
   }
 }
 
+// Tile of a particle's new cell, counted for the next tile sort: in the
+// workgroup's bins when it is this tile or a neighbour (wrapping on periodic
+// axes), else straight into the global count.
+template <int D>
+__device__ __forceinline__ void count_new_tile(const Geo& g, const int* idx, int tci, int tcj, int tck,
+                                               int* tbins, int* tcount) {
+  using TS = TileShape<D>;
+  const int tn[3] = {idx[0] / TS::T0, idx[1] / TS::T1, (D == 3) ? idx[2] / TS::T2 : 0};
+  const int tc[3] = {tci, tcj, tck};
+  int b = 0, mul = 1;
+  bool near = true;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    int dd = tn[ax] - tc[ax];
+    if (g.periodic[ax]) {
+      const int nt = g.nt[ax];
+      if (dd > 1) dd -= nt;
+      if (dd < -1) dd += nt;
+    }
+    near = near && dd >= -1 && dd <= 1;
+    b += (dd + 1) * mul;
+    mul *= 3;
+  }
+  if (near)
+    atomicAdd(&tbins[b], 1);
+  else
+    atomicAdd(&tcount[tn[0] + g.nt[0] * (tn[1] + g.nt[1] * tn[2])], 1);
+}
+
 // Vertex-field window of a tile: vertices origin-1 .. origin+T+1 per axis, so
 // that particles up to one cell outside the tile (drift since the last sort)
 // gather from LDS.  Components are packed (2 in 2D, 3 in 3D; the padding slot
@@ -532,6 +562,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? 5 :
   __shared__ R ewin[FW::N * FW::C];
   __shared__ double red_d[8];
   __shared__ unsigned long long red_u[8][5];
+  __shared__ int tbins[28];  // new tiles of the particles: the 27 around this tile, then dead
 
   const int item = blockIdx.x;
   if (item >= *a.n_items) return;
@@ -545,8 +576,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? 5 :
   origin[2] = (D == 3) ? (tile / (g.nt[0] * g.nt[1])) * TS::T2 : 0;
 
   const bool deposit = a.mode != MODE_HALFSTEP;
+  const bool tcount = a.tcount != nullptr && a.mode == MODE_PUSH;
   if (deposit)
     for (int s = threadIdx.x; s < TS::WIN; s += blockDim.x) win[s] = (QT)0;
+  if (threadIdx.x < 28) tbins[threadIdx.x] = 0;
+  const int tci = tile % g.nt[0], tcj = (tile / g.nt[0]) % g.nt[1], tck = tile / (g.nt[0] * g.nt[1]);
   if (a.mode != MODE_DEPOSIT) {
     // stage the vertex field of the tile and a one-cell halo
     for (int s = threadIdx.x; s < FW::N; s += blockDim.x) {
@@ -608,7 +642,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? 5 :
         if (a.vz_active) nv2 = a.v2[pn];
       }
     }
-    if (key < 0) continue;
+    if (key < 0) {
+      if (tcount) atomicAdd(&tbins[27], 1);
+      continue;
+    }
     int idx[3] = {key_i(key, g), key_j(key, g), (D == 3) ? key_k(key, g) : 0};
 
     if (need_v) {
@@ -636,9 +673,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? 5 :
         a.key[p] = dead;
         absorbed += dead == -1 ? 1 : 0;
         outflow += dead == -2 ? 1 : 0;
+        if (tcount) atomicAdd(&tbins[27], 1);
         continue;
       }
       a.key[p] = make_key(idx[0], idx[1], idx[2], g);
+      if (tcount) count_new_tile<D>(g, idx, tci, tcj, tck, tbins, a.tcount);
       a.off0[p] = f[0];
       a.off1[p] = f[1];
       if (D == 3) a.off2[p] = f[2];
@@ -672,6 +711,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? 5 :
       if (!ok) continue;
       long long c = (long long)t[0] + (long long)g.n[0] * (t[1] + (long long)g.n[1] * t[2]);
       atomicAdd(&((QT*)a.Q)[c], val);
+    }
+  }
+
+  if (tcount) {
+    __syncthreads();
+    if (threadIdx.x < 27) {
+      const int c = tbins[threadIdx.x];
+      if (c) {
+        const int dd[3] = {(int)threadIdx.x % 3 - 1, ((int)threadIdx.x / 3) % 3 - 1, (int)threadIdx.x / 9 - 1};
+        const int tc[3] = {tci, tcj, tck};
+        int t[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const int nt = g.nt[ax];
+          t[ax] = tc[ax] + dd[ax];
+          t[ax] = t[ax] < 0 ? t[ax] + nt : (t[ax] >= nt ? t[ax] - nt : t[ax]);
+        }
+        atomicAdd(&a.tcount[t[0] + g.nt[0] * (t[1] + g.nt[1] * t[2])], c);
+      }
+    } else if (threadIdx.x == 27 && tbins[27]) {
+      atomicAdd(&a.tcount[g.ntiles], tbins[27]);
     }
   }
 
@@ -787,7 +847,13 @@ __global__ __launch_bounds__(256) void fallback_kernel(PartArgs<R> a, int shape)
       a.key[p] = dead;
       absorbed += dead == -1 ? 1 : 0;
       outflow += dead == -2 ? 1 : 0;
+      if (a.tcount) atomicAdd(&a.tcount[g.ntiles], 1);
       continue;
+    }
+    if (a.tcount) {
+      using TS = TileShape<D>;
+      atomicAdd(&a.tcount[idx[0] / TS::T0 + g.nt[0] * (idx[1] / TS::T1 + g.nt[1] * ((D == 3) ? idx[2] / TS::T2 : 0))],
+                1);
     }
     R fr[3];
     for (int ax = 0; ax < 3; ++ax) {
@@ -837,6 +903,7 @@ struct InjectArgs {
   uint32_t k0, k1, step, species;
   unsigned long long* counters;  // [5] injected, [6] dropped for capacity, [7] next identifier
   int* count_out;
+  int* tcount;  // when set: the injected particles' tiles are counted for the next sort
 };
 
 __device__ inline int injection_count(double lam, uint32_t k0, uint32_t k1, uint32_t step,
@@ -928,9 +995,15 @@ __global__ __launch_bounds__(256) void inject_kernel(InjectArgs<R> a) {
   if (a.id) a.id[slot] = (uint32_t)(a.counters[7] + (unsigned long long)k);
   if (dead) {
     a.key[slot] = -2;
+    if (a.tcount) atomicAdd(&a.tcount[g.ntiles], 1);
     return;
   }
   a.key[slot] = make_key(idx[0], idx[1], idx[2], g);
+  if (a.tcount) {
+    using TS = TileShape<D>;
+    atomicAdd(&a.tcount[idx[0] / TS::T0 + g.nt[0] * (idx[1] / TS::T1 + g.nt[1] * ((D == 3) ? idx[2] / TS::T2 : 0))],
+              1);
+  }
   for (int ax = 0; ax < D; ++ax) a.off[ax][slot] = fo[ax];
   for (int c = 0; c < 3; ++c) a.vel[c][slot] = (R)v[c];
   atomicAdd(&a.counters[5], 1ull);
@@ -1229,6 +1302,7 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   for (int i = 0; i < 3; ++i) a.inv_dxc[i] = (R)(1.0 / L.g.dxc[i]);
   a.ke_scale = L.ke_scale;
   a.ke_part = L.ke_part;
+  a.tcount = L.tile_counts;
   a.ke = L.ke;
   a.counters = L.counters;
   a.fb_queue = L.fb_queue;
@@ -1294,6 +1368,7 @@ static void launch_inject_t(const InjectLaunch& I, hipStream_t st) {
   a.species = I.species;
   a.counters = I.counters;
   a.count_out = I.count_out;
+  a.tcount = I.tile_counts;
   const int maxc = (int)floor(I.lam) + 1;
   const unsigned blocks = (unsigned)((maxc + 255) / 256);
   constexpr bool FIXED = std::is_same<R, float>::value;
@@ -1350,10 +1425,13 @@ int launch_tile_sort(const SortLaunch& S, hipStream_t st) {
   // count return at once)
   int blocks = (int)((S.capacity + SORT_CHUNK - 1) / SORT_CHUNK);
   if (blocks < 1) blocks = 1;
-  if (g.dim == 2)
-    hipLaunchKernelGGL(tile_hist_kernel<2>, dim3(blocks), dim3(256), 0, st, S.key_in, S.d_n, S.counts, g);
-  else
-    hipLaunchKernelGGL(tile_hist_kernel<3>, dim3(blocks), dim3(256), 0, st, S.key_in, S.d_n, S.counts, g);
+  if (!S.counts_ready) {
+    launch_fill_u8(S.counts, 0, sizeof(int) * (size_t)(g.ntiles + 2), st);
+    if (g.dim == 2)
+      hipLaunchKernelGGL(tile_hist_kernel<2>, dim3(blocks), dim3(256), 0, st, S.key_in, S.d_n, S.counts, g);
+    else
+      hipLaunchKernelGGL(tile_hist_kernel<3>, dim3(blocks), dim3(256), 0, st, S.key_in, S.d_n, S.counts, g);
+  }
   hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, st, S.counts, g.ntiles, S.chunk, S.start,
                      S.cursor, S.n_items, S.item_tile, S.item_begin, S.item_end, S.d_n);
 #define SCATTER(DD, RR)                                                                            \

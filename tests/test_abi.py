@@ -56,3 +56,33 @@ def test_status_strings_and_argument_validation_without_gpu():
     g.bc_lo[0] = g.bc_hi[0] = 0
     g.n[2] = 8
     assert L.cpic_create(ctypes.byref(m3), ctypes.byref(g), None, None, ctypes.byref(h)) == -2
+
+
+def test_python_structures_match_the_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    that a C compiler gives the matching struct of include/cpic.h."""
+    import shutil
+    import subprocess
+    from paper_1311_2286_amd import cpic
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = [("cpic_allocator", cpic.Allocator), ("cpic_map_desc", cpic.MapDesc),
+             ("cpic_grid_desc", cpic.GridDesc), ("cpic_species_desc", cpic.SpeciesDesc),
+             ("cpic_diag", cpic.Diag), ("cpic_case_desc", cpic.CaseDesc),
+             ("cpic_case_result", cpic.CaseResult), ("cpic_server_stats", cpic.ServerStats)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "cpic.h"', "int main(void) {"]
+    expect = []
+    for cname, py in pairs:
+        lines.append('  printf("%%zu\\n", sizeof(%s));' % cname)
+        expect.append(ctypes.sizeof(py))
+        for fname, _ in py._fields_:
+            lines.append('  printf("%%zu\\n", offsetof(%s, %s));' % (cname, fname))
+            expect.append(getattr(py, fname).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == expect
