@@ -334,8 +334,18 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   const size_t sweep_blocks = (size_t)((g.n[0] + 63) / 64) * ((g.n[1] + 3) / 4) * g.n[2];
   G.mg_partials = (double*)A(sizeof(double) * sweep_blocks);
   if (grid->mg_method == CPIC_MG_FCG) {
+    for (int l = 0; l < nl; ++l) {
+      Level& L = G.lev[l];
+      const size_t fb = sizeof(float) * (size_t)L.ncells;
+      for (int k = 0; k < 9; ++k) L.f_S[k] = L.S[k] ? (float*)A(fb) : nullptr;
+      L.f_diag = (float*)A(fb);
+      L.f_phi = (float*)A(fb);
+      L.f_phi2 = (float*)A(fb);
+      L.f_rhs = (float*)A(fb);
+      L.f_res = (float*)A(fb);
+      L.f_aux = (float*)A(fb);
+    }
     G.kr = (double*)A(cb);
-    G.kz = (double*)A(cb);
     G.kp = (double*)A(cb);
     G.kq = (double*)A(cb);
     G.kw = (double*)A(cb);
@@ -363,7 +373,12 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     launch_fill_u8(L.phi2, 0, b, st);
     launch_fill_u8(L.rhs, 0, b, st);
     launch_coefficients(G, l, st);
+    if (L.f_phi) {
+      const size_t fb = sizeof(float) * (size_t)L.ncells;
+      for (float* v : {L.f_phi, L.f_phi2, L.f_rhs, L.f_res, L.f_aux}) launch_fill_u8(v, 0, fb, st);
+    }
   }
+  launch_operator_f32(G, st);
   launch_fill_u8(G.charge, 0, cb, st);
   launch_fill_u8(G.Ev, 0, real_size(s) * ecomp(s) * (size_t)g.nverts, st);
   launch_fill_u8(s->ke, 0, sizeof(double) * 2, st);

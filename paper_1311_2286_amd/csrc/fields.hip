@@ -116,7 +116,10 @@ void launch_fill_u8(void* p, unsigned char v, size_t bytes, hipStream_t st) {
 // ----------------------------------------------------------------------------
 // coefficients
 // ----------------------------------------------------------------------------
-struct LevelArgs {
+// T: type of the operator coefficients (FP64; FP32 for the V-cycle used as a
+// preconditioner of the flexible-CG solve)
+template <typename T>
+struct LevelArgsT {
   int dim;
   int n[3];
   int periodic[3];
@@ -127,9 +130,10 @@ struct LevelArgs {
   const double* wf[3];
   const double* wlo[3];
   const double* we[3];
-  const double* S[9];
-  const double* diag;
+  const T* S[9];
+  const T* diag;
 };
+using LevelArgs = LevelArgsT<double>;
 
 static LevelArgs level_args(const GridCtx& G, int l) {
   const Level& L = G.lev[l];
@@ -150,6 +154,52 @@ static LevelArgs level_args(const GridCtx& G, int l) {
   for (int k = 0; k < 9; ++k) a.S[k] = L.S[k];
   a.diag = L.diag;
   return a;
+}
+
+// the FP32 copy of a level's operator
+static LevelArgsT<float> level_args_f32(const GridCtx& G, int l) {
+  const LevelArgs d = level_args(G, l);
+  const Level& L = G.lev[l];
+  LevelArgsT<float> a;
+  a.dim = d.dim;
+  a.mixed = d.mixed;
+  a.dV = d.dV;
+  for (int i = 0; i < 3; ++i) {
+    a.n[i] = d.n[i];
+    a.periodic[i] = d.periodic[i];
+    a.dir[i][0] = d.dir[i][0];
+    a.dir[i][1] = d.dir[i][1];
+    a.h[i] = d.h[i];
+    a.wf[i] = d.wf[i];
+    a.wlo[i] = d.wlo[i];
+    a.we[i] = d.we[i];
+  }
+  for (int k = 0; k < 9; ++k) a.S[k] = L.f_S[k];
+  a.diag = L.f_diag;
+  return a;
+}
+
+template <typename T> static LevelArgsT<T> level_args_t(const GridCtx& G, int l);
+template <> LevelArgsT<double> level_args_t<double>(const GridCtx& G, int l) { return level_args(G, l); }
+template <> LevelArgsT<float> level_args_t<float>(const GridCtx& G, int l) { return level_args_f32(G, l); }
+
+// the V-cycle vectors of a level in precision T
+template <typename T>
+struct LevelVec {
+  T* phi;
+  T* phi2;
+  T* rhs;
+  T* res;
+  T* aux;
+};
+template <typename T> static LevelVec<T> level_vec(const GridCtx& G, int l);
+template <> LevelVec<double> level_vec<double>(const GridCtx& G, int l) {
+  const Level& L = G.lev[l];
+  return {L.phi, L.phi2, L.rhs, L.res, L.aux};
+}
+template <> LevelVec<float> level_vec<float>(const GridCtx& G, int l) {
+  const Level& L = G.lev[l];
+  return {L.f_phi, L.f_phi2, L.f_rhs, L.f_res, L.f_aux};
 }
 
 __global__ void coef_kernel(Geo g, LevelArgs a, double* wf0, double* wf1, double* wf2, double* wl0,
@@ -416,7 +466,7 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const double* a, co
 
 // op 0: out = sum; op 1: MG convergence test vs scalars[0] (|b|^2):
 //   sets flag[0] when sum <= rtol^2 |b|^2 (or |b| == 0), counts cycles in flag[1]
-__global__ __launch_bounds__(256) void reduce_final_kernel(const double* partials, int nb, double* out,
+__global__ __launch_bounds__(1024) void reduce_final_kernel(const double* partials, int nb, double* out,
                                                            int op, double rtol2, const double* bnorm2,
                                                            int* flag, int count_cycle) {
   if (op == 1 && flag[0]) return;
@@ -472,8 +522,8 @@ void launch_rhs(const GridCtx& G, hipStream_t st) {
 // (A phi)_c from the explicit stencil: diag, the upper-half coefficients of c
 // and, by symmetry, those stored at the lower neighbours.  Across a wall the
 // lower neighbour term is absent and the upper coefficient is zero.
-__device__ inline double apply_A(const LevelArgs& a, const double* __restrict__ phi, const int* idx,
-                                 long long cl) {
+template <typename T, typename TV>
+__device__ inline T apply_A(const LevelArgsT<T>& a, const TV* __restrict__ phi_in, const int* idx, long long cl) {
   const int c = (int)cl;
   const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
   const int sy = n0, sz = n0 * n1;
@@ -481,7 +531,11 @@ __device__ inline double apply_A(const LevelArgs& a, const double* __restrict__ 
   const int dxm = idx[0] > 0 ? -1 : (a.periodic[0] ? n0 - 1 : 0);
   const int dyp = (idx[1] + 1 < n1 ? 1 : (a.periodic[1] ? 1 - n1 : 0)) * sy;
   const int dym = (idx[1] > 0 ? -1 : (a.periodic[1] ? n1 - 1 : 0)) * sy;
-  double acc = a.diag[c] * phi[c];
+  struct Rd {
+    const TV* p;
+    __device__ T operator[](long long i) const { return (T)p[i]; }
+  } phi{phi_in};
+  T acc = a.diag[c] * phi[c];
   acc += a.S[0][c] * phi[c + dxp];
   if (dxm) acc += a.S[0][c + dxm] * phi[c + dxm];
   acc += a.S[1][c] * phi[c + dyp];
@@ -512,10 +566,10 @@ __device__ inline double apply_A(const LevelArgs& a, const double* __restrict__ 
 // Chebyshev steps of the multigrid smoother use the three-term recurrence.
 // With partials != null the squared residual of the input is summed per block
 // (fixed order) for the convergence test.
-__global__ __launch_bounds__(256) void smooth_kernel(LevelArgs a, const double* __restrict__ phi,
-                                                     const double* __restrict__ rhs, double* out,
-                                                     double cr, double cd, const double* dprev, double* dout,
-                                                     const int* flag, double* partials) {
+template <typename T>
+__global__ __launch_bounds__(256) void smooth_kernel(LevelArgsT<T> a, const T* __restrict__ phi,
+                                                     const T* __restrict__ rhs, T* out, double cr, double cd,
+                                                     const T* dprev, T* dout, const int* flag, double* partials) {
   if (flag[0]) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -524,12 +578,12 @@ __global__ __launch_bounds__(256) void smooth_kernel(LevelArgs a, const double* 
   if (i < a.n[0] && j < a.n[1]) {
     const int idx[3] = {i, j, k};
     const int c = i + a.n[0] * (j + a.n[1] * k);
-    double r = rhs[c] - apply_A(a, phi, idx, c);
-    double dn = cr * r / a.diag[c];
-    if (dprev) dn += cd * dprev[c];
+    const T r = rhs[c] - apply_A(a, phi, idx, c);
+    T dn = (T)cr * r / a.diag[c];
+    if (dprev) dn += (T)cd * dprev[c];
     out[c] = phi[c] + dn;
     if (dout) dout[c] = dn;
-    rr = r * r;
+    rr = (double)r * (double)r;
   }
   if (partials) {
     double t = block_sum(rr);
@@ -570,10 +624,11 @@ __global__ __launch_bounds__(256) void gershgorin_kernel(LevelArgs a, double* ou
   out[c] = s / fabs(a.diag[c]);
 }
 
-__device__ inline double restrict_cell(const LevelArgs& fa, const double* __restrict__ phi,
-                                       const double* __restrict__ rhs, const int* I) {
+template <typename T>
+__device__ inline T restrict_cell(const LevelArgsT<T>& fa, const T* __restrict__ phi, const T* __restrict__ rhs,
+                                  const int* I) {
   const int d = fa.dim;
-  double s = 0.0;
+  T s = (T)0;
   const int nz = (d == 3) ? 2 : 1;
   for (int sz = 0; sz < nz; ++sz)
     for (int sy = 0; sy < 2; ++sy)
@@ -586,9 +641,9 @@ __device__ inline double restrict_cell(const LevelArgs& fa, const double* __rest
 }
 
 // residual r = rhs - A phi (coalesced pass over the fine level)
-__global__ __launch_bounds__(256) void residual_kernel(LevelArgs a, const double* __restrict__ phi,
-                                                       const double* __restrict__ rhs, double* res,
-                                                       const int* flag) {
+template <typename T>
+__global__ __launch_bounds__(256) void residual_kernel(LevelArgsT<T> a, const T* __restrict__ phi,
+                                                       const T* __restrict__ rhs, T* res, const int* flag) {
   if (flag[0]) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -600,34 +655,35 @@ __global__ __launch_bounds__(256) void residual_kernel(LevelArgs a, const double
 }
 
 // coarse rhs = sum of the residuals of the 2^d children; coarse phi = 0
-__global__ __launch_bounds__(256) void restrict_kernel(int dim, int nf0, int nf1, const double* __restrict__ res,
-                                                       int nc0, int nc1, double* crhs, double* cphi,
-                                                       const int* flag) {
+template <typename T>
+__global__ __launch_bounds__(256) void restrict_kernel(int dim, int nf0, int nf1, const T* __restrict__ res,
+                                                       int nc0, int nc1, T* crhs, T* cphi, const int* flag) {
   if (flag[0]) return;
   const int I0 = blockIdx.x * blockDim.x + threadIdx.x, I1 = blockIdx.y * blockDim.y + threadIdx.y;
   const int I2 = blockIdx.z;
   if (I0 >= nc0 || I1 >= nc1) return;
   const int C = I0 + nc0 * (I1 + nc1 * I2);
   const int f = 2 * I0 + nf0 * (2 * I1 + nf1 * (dim == 3 ? 2 * I2 : 0));
-  double s = res[f] + res[f + 1] + res[f + nf0] + res[f + nf0 + 1];
+  T s = res[f] + res[f + 1] + res[f + nf0] + res[f + nf0 + 1];
   if (dim == 3) {
     const int fz = f + nf0 * nf1;
     s += res[fz] + res[fz + 1] + res[fz + nf0] + res[fz + nf0 + 1];
   }
   crhs[C] = s;
-  cphi[C] = 0.0;
+  cphi[C] = (T)0;
 }
 
 // (3/4, 1/4)-tensor interpolation of the coarse correction at fine cell idx
-__device__ inline double prolong_cell(const LevelArgs& fa, const double* __restrict__ cphi, const int* cn,
-                                      const int* idx) {
+template <typename T>
+__device__ inline T prolong_cell(const LevelArgsT<T>& fa, const T* __restrict__ cphi, const int* cn,
+                                 const int* idx) {
   const int d = fa.dim;
   int I[3] = {idx[0] >> 1, idx[1] >> 1, idx[2] >> 1};
   int J[3];
-  double sgn[3];
+  T sgn[3];
   for (int ax = 0; ax < 3; ++ax) {
     J[ax] = I[ax];
-    sgn[ax] = 1.0;
+    sgn[ax] = (T)1;
     if (ax >= d) continue;
     int step = (idx[ax] & 1) ? 1 : -1;
     int v = I[ax] + step;
@@ -637,34 +693,35 @@ __device__ inline double prolong_cell(const LevelArgs& fa, const double* __restr
       // ghost of the correction: homogeneous Dirichlet -> -e, Neumann -> e
       J[ax] = I[ax];
       int dirw = (v < 0) ? fa.dir[ax][0] : fa.dir[ax][1];
-      sgn[ax] = dirw ? -1.0 : 1.0;
+      sgn[ax] = dirw ? (T)-1 : (T)1;
     } else {
       J[ax] = v;
     }
   }
-  double acc = 0.0;
+  T acc = (T)0;
   const int nz = (d == 3) ? 2 : 1;
   for (int tz = 0; tz < nz; ++tz)
     for (int ty = 0; ty < 2; ++ty)
       for (int tx = 0; tx < 2; ++tx) {
         int t[3] = {tx, ty, tz};
         int K[3];
-        double w = 1.0;
+        T w = (T)1;
         for (int ax = 0; ax < 3; ++ax) {
           if (ax >= d) {
             K[ax] = 0;
             continue;
           }
           K[ax] = t[ax] ? J[ax] : I[ax];
-          w *= t[ax] ? 0.25 * sgn[ax] : 0.75;
+          w *= t[ax] ? (T)0.25 * sgn[ax] : (T)0.75;
         }
         acc += w * cphi[K[0] + cn[0] * (K[1] + cn[1] * K[2])];
       }
   return acc;
 }
 
-__global__ __launch_bounds__(256) void prolong_kernel(LevelArgs fa, double* phi, const double* __restrict__ cphi,
-                                                      int nc0, int nc1, int nc2, const int* flag) {
+template <typename T>
+__global__ __launch_bounds__(256) void prolong_kernel(LevelArgsT<T> fa, T* phi, const T* __restrict__ cphi, int nc0,
+                                                      int nc1, int nc2, const int* flag) {
   if (flag[0]) return;
   const int cn[3] = {nc0, nc1, nc2};
   const int idx[3] = {(int)(blockIdx.x * blockDim.x + threadIdx.x), (int)(blockIdx.y * blockDim.y + threadIdx.y),
@@ -682,14 +739,15 @@ __global__ __launch_bounds__(256) void prolong_kernel(LevelArgs fa, double* phi,
 constexpr int SMALL_CELLS = 512;
 constexpr int MAX_SMALL = 8;
 constexpr int COARSE_LDS = 384;  // coarsest levels up to this many cells are solved in LDS
+template <typename T>
 struct SmallLevels {
   int nl;
-  LevelArgs a[MAX_SMALL];
-  double* phi[MAX_SMALL];
-  double* phi2[MAX_SMALL];
-  double* rhs[MAX_SMALL];
-  double* res[MAX_SMALL];
-  double* aux[MAX_SMALL];
+  LevelArgsT<T> a[MAX_SMALL];
+  T* phi[MAX_SMALL];
+  T* phi2[MAX_SMALL];
+  T* rhs[MAX_SMALL];
+  T* res[MAX_SMALL];
+  T* aux[MAX_SMALL];
 };
 
 // sum over the workgroup, returned to every thread
@@ -713,8 +771,9 @@ __device__ inline double block_allsum(double v) {
 // gradients on -A (A is negative semi-definite) until |r|^2 <= tol2 |b|^2 or
 // maxit iterations; singular (all-periodic) problems are solved on
 // the zero-mean subspace and the result shifted to zero mean.
-__device__ inline void block_cg(const LevelArgs& a, double* x, const double* b, double* r, double* p, double* q,
-                                int maxit, int singular, double tol2) {
+template <typename T>
+__device__ inline void block_cg(const LevelArgsT<T>& a, T* x, const T* b, T* r, T* p, T* q, int maxit, int singular,
+                                double tol2) {
   const int nc = a.n[0] * a.n[1] * a.n[2];
   double bmean = 0.0;
   if (singular) {
@@ -785,8 +844,9 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-__device__ inline void wave_cg(const LevelArgs& a, double* x, const double* b, double* r, double* p, double* q,
-                               int maxit, int singular, double tol2) {
+template <typename T>
+__device__ inline void wave_cg(const LevelArgsT<T>& a, T* x, const T* b, T* r, T* p, T* q, int maxit, int singular,
+                               double tol2) {
   const int nc = a.n[0] * a.n[1] * a.n[2];
   const int lane = threadIdx.x & 63;
   double bmean = 0.0;
@@ -846,29 +906,30 @@ __device__ inline void wave_cg(const LevelArgs& a, double* x, const double* b, d
   wave_sync();
 }
 
-__device__ inline void block_smooth(const LevelArgs& a, const double* phi, const double* rhs, double* out,
-                                    double omega) {
+template <typename T>
+__device__ inline void block_smooth(const LevelArgsT<T>& a, const T* phi, const T* rhs, T* out, T omega) {
   const int nc = a.n[0] * a.n[1] * a.n[2];
   for (int c = threadIdx.x; c < nc; c += blockDim.x) {
     int idx[3] = {c % a.n[0], (c / a.n[0]) % a.n[1], c / (a.n[0] * a.n[1])};
-    double r = rhs[c] - apply_A(a, phi, idx, c);
+    const T r = rhs[c] - apply_A(a, phi, idx, c);
     out[c] = phi[c] + omega * r / a.diag[c];
   }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels S, int nu1, int nu2, double coarse_tol2,
+template <typename T>
+__global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels<T> S, int nu1, int nu2, double coarse_tol2,
                                                             int singular, const int* flag) {
   if (flag[0]) return;
-  const double omega = 0.8;
+  const T omega = (T)0.8;
   const int last = S.nl - 1;
   for (int l = 0; l < last; ++l) {
-    const LevelArgs& a = S.a[l];
+    const LevelArgsT<T>& a = S.a[l];
     for (int s = 0; s < nu1; s += 2) {
       block_smooth(a, S.phi[l], S.rhs[l], S.phi2[l], omega);
       block_smooth(a, S.phi2[l], S.rhs[l], S.phi[l], omega);
     }
-    const LevelArgs& ca = S.a[l + 1];
+    const LevelArgsT<T>& ca = S.a[l + 1];
     const int ncc = ca.n[0] * ca.n[1] * ca.n[2];
     for (int C = threadIdx.x; C < ncc; C += blockDim.x) {
       int I[3] = {C % ca.n[0], (C / ca.n[0]) % ca.n[1], C / (ca.n[0] * ca.n[1])};
@@ -878,15 +939,15 @@ __global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels S, int n
     __syncthreads();
   }
   {
-    const LevelArgs& a = S.a[last];
+    const LevelArgsT<T>& a = S.a[last];
     const int ncl = a.n[0] * a.n[1] * a.n[2];
     const int maxit = min(2000, 2 * ncl + 20);
     if (ncl <= COARSE_LDS) {
       // coarsest level held in LDS: operator, potential, right side, CG vectors
-      __shared__ double lphi[COARSE_LDS], lrhs[COARSE_LDS], ldiag[COARSE_LDS];
-      __shared__ double lr[COARSE_LDS], lp[COARSE_LDS], lq[COARSE_LDS];
-      __shared__ double lS[9][COARSE_LDS];
-      LevelArgs la = a;
+      __shared__ T lphi[COARSE_LDS], lrhs[COARSE_LDS], ldiag[COARSE_LDS];
+      __shared__ T lr[COARSE_LDS], lp[COARSE_LDS], lq[COARSE_LDS];
+      __shared__ T lS[9][COARSE_LDS];
+      LevelArgsT<T> la = a;
       for (int c = threadIdx.x; c < ncl; c += blockDim.x) {
         lphi[c] = S.phi[last][c];
         lrhs[c] = S.rhs[last][c];
@@ -906,8 +967,8 @@ __global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels S, int n
     }
   }
   for (int l = last - 1; l >= 0; --l) {
-    const LevelArgs& a = S.a[l];
-    const LevelArgs& ca = S.a[l + 1];
+    const LevelArgsT<T>& a = S.a[l];
+    const LevelArgsT<T>& ca = S.a[l + 1];
     const int nc = a.n[0] * a.n[1] * a.n[2];
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
       int idx[3] = {c % a.n[0], (c / a.n[0]) % a.n[1], c / (a.n[0] * a.n[1])};
@@ -961,17 +1022,19 @@ static int first_small_level(const GridCtx& G) {
 // cannot represent), lam_max from the Gershgorin bound; phi and phi2 alternate
 // and the result ends in phi.  With partials != null the last step sums the
 // squared residual of its input.
+template <typename T>
 static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStream_t st,
                       double* first_partials = nullptr, double rtol2 = 0.0) {
   const Level& L = G.lev[l];
-  LevelArgs a = level_args(G, l);
+  const LevelArgsT<T> a = level_args_t<T>(G, l);
+  const LevelVec<T> v = level_vec<T>(G, l);
   const dim3 gr = grid3(L);
   const double lmax = L.lam_max, lmin = L.lam_max / 8.0;
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   double rho = 1.0 / sigma;
   for (int s = 0; s < nu; ++s) {
-    const double* in = (s & 1) ? L.phi2 : L.phi;
-    double* out = (s & 1) ? L.phi : L.phi2;
+    const T* in = (s & 1) ? v.phi2 : v.phi;
+    T* out = (s & 1) ? v.phi : v.phi2;
     double cr, cd;
     if (s == 0) {
       cr = 1.0 / theta;
@@ -984,20 +1047,18 @@ static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStre
     }
     const bool last = s + 1 == nu;
     double* pp = last ? partials : (s == 0 ? first_partials : nullptr);
-    hipLaunchKernelGGL(smooth_kernel, gr, BLOCK3, 0, st, a, in, L.rhs, out, cr, cd,
-                       (const double*)(s == 0 ? nullptr : L.aux), last ? (double*)nullptr : L.aux, G.mg_flag,
-                       pp);
+    hipLaunchKernelGGL(smooth_kernel<T>, gr, BLOCK3, 0, st, a, in, (const T*)v.rhs, out, cr, cd,
+                       (const T*)(s == 0 ? nullptr : v.aux), last ? (T*)nullptr : v.aux, (const int*)G.mg_flag, pp);
     if (s == 0 && first_partials) {
       // the residual entering the first step is the solve's initial residual:
       // stop here when the initial guess already meets the tolerance
       const int nblk = (int)(gr.x * gr.y * gr.z);
-      hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, (const double*)first_partials, nblk,
+      hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(1024), 0, st, (const double*)first_partials, nblk,
                          G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 0);
     }
   }
 }
 
-// Upper spectral bound of D^-1 A on every level (once, at set-up).
 int compute_smoother_bounds(GridCtx& G, hipStream_t st) {
   for (int l = 0; l < G.nlev; ++l) {
     Level& L = G.lev[l];
@@ -1031,41 +1092,48 @@ void launch_extrapolate_guess(const GridCtx& G, int extrapolate, hipStream_t st)
   hipLaunchKernelGGL(extrapolate_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, L.phi, G.phi_prev, extrapolate);
 }
 
-// One V-cycle from level l.  With partials != null, the last smoothing sweep
-// on level 0 also sums the squared residual (of its input) per block.
+// One V-cycle from level l in precision T.  With partials != null, the last
+// smoothing sweep on level 0 also sums the squared residual (of its input) per
+// block.
+template <typename T>
 static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, hipStream_t st,
-                   double* first_partials, double rtol2) {
+                   double* first_partials = nullptr, double rtol2 = 0.0) {
   const int ls = first_small_level(G);
   if (l >= ls) {
-    SmallLevels S;
+    SmallLevels<T> S;
     memset(&S, 0, sizeof(S));
     S.nl = G.nlev - l;
     for (int k = 0; k < S.nl; ++k) {
-      S.a[k] = level_args(G, l + k);
-      S.phi[k] = G.lev[l + k].phi;
-      S.phi2[k] = G.lev[l + k].phi2;
-      S.rhs[k] = G.lev[l + k].rhs;
-      S.res[k] = G.lev[l + k].res;
-      S.aux[k] = G.lev[l + k].aux;
+      const LevelVec<T> v = level_vec<T>(G, l + k);
+      S.a[k] = level_args_t<T>(G, l + k);
+      S.phi[k] = v.phi;
+      S.phi2[k] = v.phi2;
+      S.rhs[k] = v.rhs;
+      S.res[k] = v.res;
+      S.aux[k] = v.aux;
     }
     // Inside a V-cycle the coarsest level needs only a modest relative residual
-    // (1e-6); when it is the whole grid it is solved to 1e-13.
-    const double coarse_tol2 = (l == 0 && S.nl == 1) ? 1e-26 : 1e-12;
-    hipLaunchKernelGGL(small_vcycle_kernel, dim3(1), dim3(1024), 0, st, S, nu1, nu2, coarse_tol2, G.all_periodic,
-                       (const int*)G.mg_flag);
+    // (1e-6); when it is the whole grid of an FP64 solve it is solved to 1e-13.
+    const double coarse_tol2 = (l == 0 && S.nl == 1 && sizeof(T) == 8) ? 1e-26 : 1e-12;
+    hipLaunchKernelGGL(small_vcycle_kernel<T>, dim3(1), dim3(1024), 0, st, S, nu1, nu2, coarse_tol2,
+                       G.all_periodic, (const int*)G.mg_flag);
     return;
   }
   const Level& L = G.lev[l];
-  LevelArgs a = level_args(G, l);
+  const LevelArgsT<T> a = level_args_t<T>(G, l);
+  const LevelVec<T> v = level_vec<T>(G, l);
   const dim3 gr = grid3(L);
-  chebyshev(G, l, nu1, nullptr, st, first_partials, rtol2);
+  chebyshev<T>(G, l, nu1, nullptr, st, first_partials, rtol2);
   const Level& C = G.lev[l + 1];
-  hipLaunchKernelGGL(residual_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, L.res, G.mg_flag);
-  hipLaunchKernelGGL(restrict_kernel, grid3(C), BLOCK3, 0, st, G.g.dim, L.n[0], L.n[1], (const double*)L.res,
-                     C.n[0], C.n[1], C.rhs, C.phi, G.mg_flag);
-  vcycle(G, l + 1, nu1, nu2, nullptr, st, nullptr, 0.0);
-  hipLaunchKernelGGL(prolong_kernel, gr, BLOCK3, 0, st, a, L.phi, C.phi, C.n[0], C.n[1], C.n[2], G.mg_flag);
-  chebyshev(G, l, nu2, partials, st);
+  const LevelVec<T> cv = level_vec<T>(G, l + 1);
+  hipLaunchKernelGGL(residual_kernel<T>, gr, BLOCK3, 0, st, a, (const T*)v.phi, (const T*)v.rhs, v.res,
+                     (const int*)G.mg_flag);
+  hipLaunchKernelGGL(restrict_kernel<T>, grid3(C), BLOCK3, 0, st, G.g.dim, L.n[0], L.n[1], (const T*)v.res, C.n[0],
+                     C.n[1], cv.rhs, cv.phi, (const int*)G.mg_flag);
+  vcycle<T>(G, l + 1, nu1, nu2, nullptr, st);
+  hipLaunchKernelGGL(prolong_kernel<T>, gr, BLOCK3, 0, st, a, v.phi, (const T*)cv.phi, C.n[0], C.n[1], C.n[2],
+                     (const int*)G.mg_flag);
+  chebyshev<T>(G, l, nu2, partials, st);
 }
 
 // ----------------------------------------------------------------------------
@@ -1073,18 +1141,22 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
 // V-cycle (zero initial guess) as the preconditioner.  The V-cycle is not a
 // symmetric operator (summing restriction, bilinear prolongation), which the
 // flexible form tolerates; the outer iteration removes the few modes a
-// V-cycle alone amplifies on strongly distorted, anisotropic grids.  Per
-// iteration k (A symmetric, p_{k-1} . r_k = 0 by the choice of alpha):
+// V-cycle alone amplifies on strongly distorted, anisotropic grids.  The
+// V-cycle runs on the FP32 copy of the hierarchy (it only has to approximate
+// A^-1); the outer iteration keeps x, r and the operator in FP64, so the
+// attainable residual is that of FP64.  Per iteration k (A symmetric,
+// p_{k-1} . r_k = 0 by the choice of alpha):
 //   z = V(r), w = A z,
 //   beta = -(q_{k-1} . z) / (p_{k-1} . q_{k-1})          (0 on the first),
 //   p = z + beta p_{k-1},  q = A p = w + beta q_{k-1},
 //   p . q = z . w + 2 beta (q_{k-1} . z) + beta^2 (p_{k-1} . q_{k-1}),
 //   alpha = (z . r) / (p . q),  x += alpha p,  r -= alpha q.
+// Level 0's FP32 vectors hold z (phi) and the FP32 copy of r (rhs).
 // Device scalars: [4] z.w  [5] q.z  [6] z.r  [7] p.q  [8] alpha  [9] beta.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void fcg_residual_kernel(LevelArgs a, const double* __restrict__ x,
-                                                           const double* __restrict__ b, double* r, double* z,
-                                                           double* partials, const int* flag) {
+                                                           const double* __restrict__ b, double* r, float* r32,
+                                                           float* z, double* partials, const int* flag) {
   if (flag[0]) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -1095,7 +1167,8 @@ __global__ __launch_bounds__(256) void fcg_residual_kernel(LevelArgs a, const do
     const int c = i + a.n[0] * (j + a.n[1] * k);
     const double v = b[c] - apply_A(a, x, idx, c);
     r[c] = v;
-    z[c] = 0.0;
+    r32[c] = (float)v;
+    z[c] = 0.0f;
     rr = v * v;
   }
   const double t = block_sum(rr);
@@ -1103,7 +1176,7 @@ __global__ __launch_bounds__(256) void fcg_residual_kernel(LevelArgs a, const do
 }
 
 // w = A z and the block sums of z.w, q.z (first iteration: 0), z.r
-__global__ __launch_bounds__(256) void fcg_apply_kernel(LevelArgs a, const double* __restrict__ z,
+__global__ __launch_bounds__(256) void fcg_apply_kernel(LevelArgs a, const float* __restrict__ z,
                                                         const double* __restrict__ r, const double* __restrict__ q,
                                                         double* w, double* partials, int nblk, int first,
                                                         const int* flag) {
@@ -1116,7 +1189,7 @@ __global__ __launch_bounds__(256) void fcg_apply_kernel(LevelArgs a, const doubl
     const int idx[3] = {i, j, k};
     const int c = i + a.n[0] * (j + a.n[1] * k);
     const double wc = apply_A(a, z, idx, c);
-    const double zc = z[c];
+    const double zc = (double)z[c];
     w[c] = wc;
     zw = zc * wc;
     qz = first ? 0.0 : q[c] * zc;
@@ -1132,8 +1205,8 @@ __global__ __launch_bounds__(256) void fcg_apply_kernel(LevelArgs a, const doubl
 }
 
 // one workgroup: the three sums (fixed order), then beta, p.q and alpha
-__global__ __launch_bounds__(256) void fcg_coef_kernel(const double* __restrict__ partials, int nblk, double* sc,
-                                                       int first, const int* flag) {
+__global__ __launch_bounds__(1024) void fcg_coef_kernel(const double* __restrict__ partials, int nblk, double* sc,
+                                                        int first, const int* flag) {
   if (flag[0]) return;
   double v[3];
   for (int m = 0; m < 3; ++m) {
@@ -1157,11 +1230,12 @@ __global__ __launch_bounds__(256) void fcg_coef_kernel(const double* __restrict_
   }
 }
 
-// p, q, x, r updated; z cleared for the next V-cycle; block sums of |r|^2
-__global__ __launch_bounds__(256) void fcg_update_kernel(LevelArgs a, const double* __restrict__ sc, double* z,
+// p, q, x, r updated; the FP32 copy of r and a cleared z for the next V-cycle;
+// block sums of |r|^2
+__global__ __launch_bounds__(256) void fcg_update_kernel(LevelArgs a, const double* __restrict__ sc, float* z,
                                                          double* p, const double* __restrict__ w, double* q,
-                                                         double* x, double* r, int first, double* partials,
-                                                         const int* flag) {
+                                                         double* x, double* r, float* r32, int first,
+                                                         double* partials, const int* flag) {
   if (flag[0]) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -1170,7 +1244,7 @@ __global__ __launch_bounds__(256) void fcg_update_kernel(LevelArgs a, const doub
   if (i < a.n[0] && j < a.n[1]) {
     const int c = i + a.n[0] * (j + a.n[1] * k);
     const double alpha = sc[8], beta = sc[9];
-    const double zc = z[c];
+    const double zc = (double)z[c];
     const double pc = first ? zc : zc + beta * p[c];
     const double qc = first ? w[c] : w[c] + beta * q[c];
     p[c] = pc;
@@ -1178,7 +1252,8 @@ __global__ __launch_bounds__(256) void fcg_update_kernel(LevelArgs a, const doub
     x[c] += alpha * pc;
     const double rc = r[c] - alpha * qc;
     r[c] = rc;
-    z[c] = 0.0;
+    r32[c] = (float)rc;
+    z[c] = 0.0f;
     rr = rc * rc;
   }
   const double t = block_sum(rr);
@@ -1190,27 +1265,42 @@ static int launch_fcg_solve(const GridCtx& G, double rtol2, int max_iter, int nu
   LevelArgs a = level_args(G, 0);
   const dim3 gr = grid3(L);
   const int nblk = (int)(gr.x * gr.y * gr.z);
-  // the V-cycle runs on (z, r) in place of level 0's (phi, rhs)
-  GridCtx Gk = G;
-  Gk.lev[0].phi = G.kz;
-  Gk.lev[0].rhs = G.kr;
   hipLaunchKernelGGL(fcg_residual_kernel, gr, BLOCK3, 0, st, a, (const double*)L.phi, (const double*)L.rhs, G.kr,
-                     G.kz, G.mg_partials, G.mg_flag);
-  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.mg_partials, nblk, G.scalars + 1, 1, rtol2,
-                     G.scalars + 0, G.mg_flag, 0);
+                     L.f_rhs, L.f_phi, G.mg_partials, (const int*)G.mg_flag);
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(1024), 0, st, (const double*)G.mg_partials, nblk,
+                     G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 0);
   for (int it = 0; it < max_iter; ++it) {
     const int first = it == 0;
-    vcycle(Gk, 0, nu1, nu2, nullptr, st, nullptr, 0.0);
-    hipLaunchKernelGGL(fcg_apply_kernel, gr, BLOCK3, 0, st, a, (const double*)G.kz, (const double*)G.kr,
-                       (const double*)G.kq, G.kw, G.k_partials, nblk, first, G.mg_flag);
-    hipLaunchKernelGGL(fcg_coef_kernel, dim3(1), dim3(256), 0, st, (const double*)G.k_partials, nblk, G.scalars,
-                       first, G.mg_flag);
-    hipLaunchKernelGGL(fcg_update_kernel, gr, BLOCK3, 0, st, a, (const double*)G.scalars, G.kz, G.kp,
-                       (const double*)G.kw, G.kq, L.phi, G.kr, first, G.mg_partials, G.mg_flag);
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.mg_partials, nblk, G.scalars + 1, 1, rtol2,
-                       G.scalars + 0, G.mg_flag, 1);
+    vcycle<float>(G, 0, nu1, nu2, nullptr, st);
+    hipLaunchKernelGGL(fcg_apply_kernel, gr, BLOCK3, 0, st, a, (const float*)L.f_phi, (const double*)G.kr,
+                       (const double*)G.kq, G.kw, G.k_partials, nblk, first, (const int*)G.mg_flag);
+    hipLaunchKernelGGL(fcg_coef_kernel, dim3(1), dim3(1024), 0, st, (const double*)G.k_partials, nblk, G.scalars,
+                       first, (const int*)G.mg_flag);
+    hipLaunchKernelGGL(fcg_update_kernel, gr, BLOCK3, 0, st, a, (const double*)G.scalars, L.f_phi, G.kp,
+                       (const double*)G.kw, G.kq, L.phi, G.kr, L.f_rhs, first, G.mg_partials,
+                       (const int*)G.mg_flag);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(1024), 0, st, (const double*)G.mg_partials, nblk,
+                       G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 1);
   }
   return max_iter;
+}
+
+// FP32 copy of every level's operator (the preconditioner's hierarchy)
+__global__ void to_f32_kernel(long long n, const double* __restrict__ src, float* dst) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) dst[c] = (float)src[c];
+}
+
+void launch_operator_f32(const GridCtx& G, hipStream_t st) {
+  for (int l = 0; l < G.nlev; ++l) {
+    const Level& L = G.lev[l];
+    if (!L.f_diag) continue;
+    const unsigned blocks = (unsigned)((L.ncells + 255) / 256);
+    hipLaunchKernelGGL(to_f32_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.diag, L.f_diag);
+    for (int k = 0; k < 9; ++k)
+      if (L.S[k] && L.f_S[k])
+        hipLaunchKernelGGL(to_f32_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.S[k], L.f_S[k]);
+  }
 }
 
 // Solve A phi = rhs on level 0 (phi holds the initial guess).  Returns the
@@ -1237,17 +1327,17 @@ int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int 
     // initial residual (on a multi-workgroup level 0 the first smoothing step
     // of the first cycle computes it)
     hipLaunchKernelGGL(residual_norm_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, G.mg_partials, G.mg_flag);
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.mg_partials, nblk, G.scalars + 1, 1,
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(1024), 0, st, G.mg_partials, nblk, G.scalars + 1, 1,
                        rtol2, G.scalars + 0, G.mg_flag, 0);
   }
   for (int cyc = 0; cyc < max_cycles; ++cyc) {
     if (small) {
-      vcycle(G, 0, nu1, nu2, nullptr, st, nullptr, 0.0);
+      vcycle<double>(G, 0, nu1, nu2, nullptr, st);
       hipLaunchKernelGGL(residual_norm_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, G.mg_partials, G.mg_flag);
     } else {
-      vcycle(G, 0, nu1, nu2, G.mg_partials, st, cyc == 0 ? G.mg_partials : nullptr, rtol2);
+      vcycle<double>(G, 0, nu1, nu2, G.mg_partials, st, cyc == 0 ? G.mg_partials : nullptr, rtol2);
     }
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.mg_partials, nblk, G.scalars + 1, 1,
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(1024), 0, st, G.mg_partials, nblk, G.scalars + 1, 1,
                        rtol2, G.scalars + 0, G.mg_flag, 1);
   }
   return max_cycles;

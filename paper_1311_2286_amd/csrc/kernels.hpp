@@ -122,6 +122,16 @@ struct Level {
   double* res;
   double* aux;       // Chebyshev direction; coarsest-level solver vector
   double lam_max;    // upper bound of the spectrum of D^-1 A (host)
+  // FP32 copy of the operator and the V-cycle vectors, for the preconditioner
+  // of the flexible-CG solve (null with plain V-cycles); on level 0, f_phi is
+  // the preconditioned residual z and f_rhs the FP32 copy of the residual
+  float* f_S[9];
+  float* f_diag;
+  float* f_phi;
+  float* f_phi2;
+  float* f_rhs;
+  float* f_res;
+  float* f_aux;
 };
 
 struct GridCtx {
@@ -146,7 +156,6 @@ struct GridCtx {
   double* phi_prev;   // level-0 potential of the previous step
   // flexible conjugate gradients around the V-cycle (null when plain V-cycles)
   double* kr;         // residual b - A x
-  double* kz;         // preconditioned residual (V-cycle iterate)
   double* kp;         // search direction
   double* kq;         // A p
   double* kw;         // A z
@@ -167,6 +176,7 @@ void launch_charge(const GridCtx& G, const ChargeSpecies& cs, double bg_charge, 
 void launch_rhs(const GridCtx& G, hipStream_t st);
 int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st);
 int compute_smoother_bounds(GridCtx& G, hipStream_t st);
+void launch_operator_f32(const GridCtx& G, hipStream_t st);
 void launch_extrapolate_guess(const GridCtx& G, int extrapolate, hipStream_t st);
 void launch_gauge(const GridCtx& G, hipStream_t st);
 void launch_vertex_metric(const GridCtx& G, hipStream_t st);
