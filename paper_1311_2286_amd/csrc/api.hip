@@ -333,6 +333,11 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   G.partials = (double*)A(sizeof(double) * 1024);
   const size_t sweep_blocks = (size_t)((g.n[0] + 63) / 64) * ((g.n[1] + 3) / 4) * g.n[2];
   G.mg_partials = (double*)A(sizeof(double) * sweep_blocks);
+  if (G.lev[nl - 1].ncells <= DENSE_MAX) {
+    const size_t nn = (size_t)G.lev[nl - 1].ncells * (size_t)G.lev[nl - 1].ncells;
+    G.cinv64 = (double*)A(sizeof(double) * nn);
+    if (grid->mg_method == CPIC_MG_FCG) G.cinv32 = (float*)A(sizeof(float) * nn);
+  }
   if (grid->mg_method == CPIC_MG_FCG) {
     for (int l = 0; l < nl; ++l) {
       Level& L = G.lev[l];
@@ -391,7 +396,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     return CPIC_E_NOMEM;
   }
   *s->cycles_host = -1;
-  if (compute_smoother_bounds(G, st) != 0) {
+  if (compute_smoother_bounds(G, st) != 0 || setup_coarse_inverse(G, st) != 0) {
     cpic_destroy(s);
     return CPIC_E_HIP;
   }

@@ -21,6 +21,7 @@
 // kernels of later cycles return at once once the flag is set.
 #include <string.h>
 
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -742,6 +743,7 @@ constexpr int COARSE_LDS = 384;  // coarsest levels up to this many cells are so
 template <typename T>
 struct SmallLevels {
   int nl;
+  const T* cinv;  // dense inverse of the coarsest operator (column-major), or null
   LevelArgsT<T> a[MAX_SMALL];
   T* phi[MAX_SMALL];
   T* phi2[MAX_SMALL];
@@ -942,7 +944,25 @@ __global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels<T> S, in
     const LevelArgsT<T>& a = S.a[last];
     const int ncl = a.n[0] * a.n[1] * a.n[2];
     const int maxit = min(2000, 2 * ncl + 20);
-    if (ncl <= COARSE_LDS) {
+    if (S.cinv) {
+      // exact coarsest solve by the precomputed inverse (the pseudo-inverse on
+      // the zero-mean space when singular): x_i = sum_j Minv_ij b_j
+      __shared__ T lb[DENSE_MAX];
+      double bmean = 0.0;
+      if (singular) {
+        double sb = 0.0;
+        for (int c = threadIdx.x; c < ncl; c += blockDim.x) sb += (double)S.rhs[last][c];
+        bmean = block_allsum(sb) / ncl;
+      }
+      for (int c = threadIdx.x; c < ncl; c += blockDim.x) lb[c] = (T)((double)S.rhs[last][c] - bmean);
+      __syncthreads();
+      for (int i = threadIdx.x; i < ncl; i += blockDim.x) {
+        T acc = (T)0;
+        for (int j = 0; j < ncl; ++j) acc += S.cinv[(size_t)j * ncl + i] * lb[j];
+        S.phi[last][i] = acc;
+      }
+      __syncthreads();
+    } else if (ncl <= COARSE_LDS) {
       // coarsest level held in LDS: operator, potential, right side, CG vectors
       __shared__ T lphi[COARSE_LDS], lrhs[COARSE_LDS], ldiag[COARSE_LDS];
       __shared__ T lr[COARSE_LDS], lp[COARSE_LDS], lq[COARSE_LDS];
@@ -1010,6 +1030,88 @@ static dim3 grid3(const Level& L) {
   return dim3((unsigned)((L.n[0] + 63) / 64), (unsigned)((L.n[1] + 3) / 4), (unsigned)L.n[2]);
 }
 static const dim3 BLOCK3(64, 4, 1);
+
+template <typename T> static const T* coarse_inverse(const GridCtx& G);
+template <> const double* coarse_inverse<double>(const GridCtx& G) { return G.cinv64; }
+template <> const float* coarse_inverse<float>(const GridCtx& G) { return G.cinv32; }
+
+// column j of the coarsest operator, A e_j (one workgroup per column)
+__global__ __launch_bounds__(256) void dense_operator_kernel(LevelArgs a, double* M) {
+  __shared__ double e[DENSE_MAX];
+  const int n = a.n[0] * a.n[1] * a.n[2];
+  const int j = blockIdx.x;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) e[c] = c == j ? 1.0 : 0.0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int idx[3] = {i % a.n[0], (i / a.n[0]) % a.n[1], i / (a.n[0] * a.n[1])};
+    M[(size_t)j * n + i] = apply_A(a, (const double*)e, idx, i);
+  }
+}
+
+// Dense inverse of the coarsest operator (at set-up, on the host by
+// Gauss-Jordan elimination with partial pivoting).  Singular (all-periodic)
+// problems: A has the constant null vector 1 and 1^T A = 0, so
+// B = A - beta 1 1^T is invertible and for zero-sum b the solution of B x = b
+// has zero sum and solves A x = b.  The inverse is stored in FP64 and FP32.
+int setup_coarse_inverse(GridCtx& G, hipStream_t st) {
+  if (!G.cinv64) return 0;
+  const int l = G.nlev - 1;
+  const int n = (int)G.lev[l].ncells;
+  LevelArgs a = level_args(G, l);
+  hipLaunchKernelGGL(dense_operator_kernel, dim3(n), dim3(256), 0, st, a, G.cinv64);
+  std::vector<double> M((size_t)n * n), Inv((size_t)n * n, 0.0);
+  if (hipMemcpyAsync(M.data(), G.cinv64, sizeof(double) * M.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return -1;
+  if (G.all_periodic) {
+    double dsum = 0.0;
+    for (int i = 0; i < n; ++i) dsum += M[(size_t)i * n + i];
+    const double beta = dsum / n / n;  // B's eigenvalue on 1 is -beta n, about the mean diagonal
+    for (double& v : M) v -= beta;
+  }
+  // row-major working copy (A symmetric, so the column-major M reads the same)
+  for (int i = 0; i < n; ++i) Inv[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(M[(size_t)r * n + c]) > fabs(M[(size_t)piv * n + c])) piv = r;
+    if (M[(size_t)piv * n + c] == 0.0) return -1;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(M[(size_t)piv * n + k], M[(size_t)c * n + k]);
+        std::swap(Inv[(size_t)piv * n + k], Inv[(size_t)c * n + k]);
+      }
+    const double inv = 1.0 / M[(size_t)c * n + c];
+    for (int k = 0; k < n; ++k) {
+      M[(size_t)c * n + k] *= inv;
+      Inv[(size_t)c * n + k] *= inv;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = M[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        M[(size_t)r * n + k] -= f * M[(size_t)c * n + k];
+        Inv[(size_t)r * n + k] -= f * Inv[(size_t)c * n + k];
+      }
+    }
+  }
+  // column-major storage for the device (thread i reads row i along j):
+  // element (i, j) at j * n + i
+  std::vector<double> T64((size_t)n * n);
+  std::vector<float> T32((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      T64[(size_t)j * n + i] = Inv[(size_t)i * n + j];
+      T32[(size_t)j * n + i] = (float)Inv[(size_t)i * n + j];
+    }
+  if (hipMemcpyAsync(G.cinv64, T64.data(), sizeof(double) * T64.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+    return -1;
+  if (G.cinv32 &&
+      hipMemcpyAsync(G.cinv32, T32.data(), sizeof(float) * T32.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+    return -1;
+  return hipStreamSynchronize(st) == hipSuccess ? 0 : -1;
+}
 
 static int first_small_level(const GridCtx& G) {
   int ls = G.nlev - 1;
@@ -1103,6 +1205,7 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
     SmallLevels<T> S;
     memset(&S, 0, sizeof(S));
     S.nl = G.nlev - l;
+    S.cinv = coarse_inverse<T>(G);
     for (int k = 0; k < S.nl; ++k) {
       const LevelVec<T> v = level_vec<T>(G, l + k);
       S.a[k] = level_args_t<T>(G, l + k);

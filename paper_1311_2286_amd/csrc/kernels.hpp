@@ -155,6 +155,8 @@ struct GridCtx {
   double* Kv;         // inverse Jacobian at vertices, d x d row-major (FP64)
   double* phi_prev;   // level-0 potential of the previous step
   // flexible conjugate gradients around the V-cycle (null when plain V-cycles)
+  double* cinv64;     // dense inverse of the coarsest operator (<= DENSE_MAX cells), or null
+  float* cinv32;      // its FP32 copy (flexible-CG preconditioner)
   double* kr;         // residual b - A x
   double* kp;         // search direction
   double* kq;         // A p
@@ -177,6 +179,8 @@ void launch_rhs(const GridCtx& G, hipStream_t st);
 int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st);
 int compute_smoother_bounds(GridCtx& G, hipStream_t st);
 void launch_operator_f32(const GridCtx& G, hipStream_t st);
+int setup_coarse_inverse(GridCtx& G, hipStream_t st);
+constexpr int DENSE_MAX = 640;  // coarsest levels up to this many cells are solved by a dense inverse
 void launch_extrapolate_guess(const GridCtx& G, int extrapolate, hipStream_t st);
 void launch_gauge(const GridCtx& G, hipStream_t st);
 void launch_vertex_metric(const GridCtx& G, hipStream_t st);
