@@ -100,6 +100,8 @@ def lib():
         L.or_gather.argtypes = [P(Grid), P(d), lg, P(i32), P(d), P(d)]
         L.or_boris.argtypes = [lg, P(d), P(d), P(d), d, d]
         L.or_push.argtypes = [P(Map), P(Grid), d, d, P(d), lg, P(i32), P(d), P(d), P(d), P(lg)]
+        L.or_push_pc.argtypes = [P(Map), P(Grid), d, d, P(d), lg, P(i32), P(d), P(d), P(d),
+                                 ctypes.c_int, P(lg)]
         L.or_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
         L.or_num_threads.restype = ctypes.c_int
         L.or_face_area.argtypes = [P(Map)]
@@ -295,6 +297,22 @@ def push(m: Map, g: Grid, qm, dt, B, cell, off, vel, Ev):
     lib().or_push(ctypes.byref(m), ctypes.byref(g), qm, dt, _p(Bv, ctypes.c_double), cell.size,
                   _p(cell, ctypes.c_int32), _p(off, ctypes.c_double), _p(vel, ctypes.c_double),
                   _p(Ev, ctypes.c_double), counts)
+    return cell, off, vel, (counts[0], counts[1])
+
+
+def push_pc(m: Map, g: Grid, qm, dt, B, cell, off, vel, Ev, kmode=0):
+    """As ``push`` with the predictor-corrector position update (Eqs. step2-
+    step4): k interpolated from the vertices (kmode 0, the paper's method) or
+    evaluated from the map at the point (kmode 1)."""
+    cell = np.ascontiguousarray(cell, dtype=np.int32).copy()
+    off = _pts(off).copy()
+    vel = _pts(vel).copy()
+    Ev = _f64(Ev)
+    Bv = _f64(np.asarray(B, dtype=np.float64).reshape(3))
+    counts = (ctypes.c_long * 2)()
+    lib().or_push_pc(ctypes.byref(m), ctypes.byref(g), qm, dt, _p(Bv, ctypes.c_double), cell.size,
+                     _p(cell, ctypes.c_int32), _p(off, ctypes.c_double), _p(vel, ctypes.c_double),
+                     _p(Ev, ctypes.c_double), int(kmode), counts)
     return cell, off, vel, (counts[0], counts[1])
 
 

@@ -1001,6 +1001,121 @@ int or_push(const or_map* m, const or_grid* g, double qm, double dt, const doubl
 }
 
 /* ------------------------------------------------------------------------ */
+/* Predictor-corrector hybrid position update (Sec. "Particle mover",        */
+/* Eqs. hybridx, step2, step3, step4).  The logical position moves with      */
+/* d xi^i / dt = k^ij v^j, k = (dx/dxi)^{-1}:                                */
+/*   predictor  xi' = xi^n + (dt/2) k(xi^n) v^{n+1/2},                       */
+/*   corrector  xi^{n+1} = xi^n + dt k(xi') v^{n+1/2}.                       */
+/* k is known at the vertices (the map's inverse Jacobian there) and carried */
+/* to a position by the CIC vertex weights of Eq. Wvp with b1, Eq. step3 --  */
+/* at xi^n as well as at xi'.  kmode 1 evaluates k from the map at the       */
+/* position itself instead (no interpolation); it exists to pin the time     */
+/* discretisation separately from the interpolation.                        */
+/* ------------------------------------------------------------------------ */
+
+static void k_exact(const or_map* m, int d, const double* xi, double k[3][3]) {
+  double x[3], j[3][3];
+  map_x_jac(m, xi, x, j);
+  inv_d(d, j, k);
+}
+
+/* k at logical point xi.  Interpolation (kmode 0): the cell holding xi, the
+   2^d vertices of that cell weighted by prod_a (1 - f_a or f_a).  On a
+   periodic axis xi is taken modulo 1; on a bounded axis it is clamped into
+   [0, 1] (the predictor point of a particle about to leave). */
+static void k_at(const or_map* m, const or_grid* g, int kmode, const double* xi_in, double k[3][3]) {
+  int d = g->dim;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) k[a][b] = 0.0;
+  if (kmode == 1) {
+    double xi[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) xi[a] = xi_in[a];
+    k_exact(m, d, xi, k);
+    return;
+  }
+  int idx[3] = {0, 0, 0};
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < d; ++a) {
+    double u = xi_in[a] * g->n[a];
+    if (g->bc_lo[a] == OR_PERIODIC) {
+      u -= g->n[a] * floor(u / g->n[a]);
+    } else {
+      if (u < 0.0) u = 0.0;
+      if (u > g->n[a]) u = g->n[a];
+    }
+    int i = (int)floor(u);
+    if (i >= g->n[a]) i = g->n[a] - 1;
+    if (i < 0) i = 0;
+    idx[a] = i;
+    f[a] = u - i;
+  }
+  int nk = (d == 3) ? 2 : 1;
+  for (int cz = 0; cz < nk; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        int cc[3] = {cx, cy, cz};
+        double w = 1.0, xv[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < d; ++a) {
+          w *= cc[a] ? f[a] : 1.0 - f[a];
+          xv[a] = (double)(idx[a] + cc[a]) / g->n[a]; /* vertex position */
+        }
+        double kv[3][3];
+        k_exact(m, d, xv, kv);
+        for (int a = 0; a < d; ++a)
+          for (int b = 0; b < d; ++b) k[a][b] += w * kv[a][b];
+      }
+}
+
+/* One mover pass with the predictor-corrector position update; gather,
+   Boris and boundaries as in or_push. */
+int or_push_pc(const or_map* m, const or_grid* g, double qm, double dt, const double* B, long np,
+               int32_t* cell, double* off, double* vel, const double* Ev, int kmode, long* counts) {
+  int d = g->dim;
+  long absorbed = 0, outflow = 0;
+#pragma omp parallel for schedule(static) reduction(+ : absorbed, outflow)
+  for (long p = 0; p < np; ++p) {
+    if (cell[p] < 0) continue;
+    double E[3];
+    gather_one(g, Ev, cell[p], off + 3 * p, E);
+    boris(vel + 3 * p, E, B, qm, dt);
+    const double* v = vel + 3 * p;
+    int idx[3];
+    cell_coords(g, cell[p], idx);
+    double xi0[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) xi0[a] = (idx[a] + off[3 * p + a]) / g->n[a];
+    double k0[3][3], k1[3][3];
+    k_at(m, g, kmode, xi0, k0);
+    double xip[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) {
+      double s = 0.0;
+      for (int b = 0; b < d; ++b) s += k0[a][b] * v[b];
+      xip[a] = xi0[a] + 0.5 * dt * s;
+    }
+    k_at(m, g, kmode, xip, k1);
+    double xi1[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) {
+      double s = 0.0;
+      for (int b = 0; b < d; ++b) s += k1[a][b] * v[b];
+      xi1[a] = xi0[a] + dt * s;
+    }
+    int wa = -1;
+    int st = place(g, xi1, &cell[p], off + 3 * p, &wa);
+    if (st == 1) {
+      cell[p] = -1;
+      absorbed++;
+    } else if (st == 2) {
+      cell[p] = -2;
+      outflow++;
+    }
+  }
+  if (counts) {
+    counts[0] = absorbed;
+    counts[1] = outflow;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter-based RNG.      */
 /* ------------------------------------------------------------------------ */
 
