@@ -112,6 +112,17 @@ enum {
   CPIC_MG_VCYCLE = 1  /* plain V-cycles */
 };
 
+/* Position update of the mover (cpic_grid_desc.mover) */
+enum {
+  CPIC_MOVER_NEWTON = 0, /* x(xi^n) + dt v^{n+1/2} mapped back to logical space by Newton
+                            on the analytic map (default) */
+  CPIC_MOVER_PC = 1      /* the paper's predictor-corrector hybrid update (Sec. "Particle
+                            mover", Eqs. step2-step4): xi' = xi^n + (dt/2) k(xi^n) v,
+                            xi^{n+1} = xi^n + dt k(xi') v, with the inverse Jacobian k
+                            tabulated at the vertices and carried to the particle by the
+                            CIC vertex weights (Eq. step3) */
+};
+
 typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);
@@ -142,6 +153,7 @@ typedef struct {
   int sort_every;       /* tile sort every this many steps (>= 1) */
   int track_ids;        /* carry a uint32 particle id through sorts */
   int mg_method;        /* CPIC_MG_FCG (0) or CPIC_MG_VCYCLE */
+  int mover;            /* CPIC_MOVER_NEWTON (0) or CPIC_MOVER_PC */
 } cpic_grid_desc;
 
 typedef struct {

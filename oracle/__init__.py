@@ -379,10 +379,11 @@ class OracleSim:
     xi^{n+1} -> boundaries -> deposit -> charge -> phi^{n+1} -> E^{n+1}.
 
     species: list of dicts with q, m, w and arrays cell (int32), off (n,3),
-    vel (n,3) in FP64.  deposit: 'fixed' (integer weights) or 'f64'."""
+    vel (n,3) in FP64.  deposit: 'fixed' (integer weights) or 'f64'.  mover:
+    'exact' (map inversion) or 'pc' (predictor-corrector, Eqs. step2-step4)."""
 
     def __init__(self, m: Map, g: Grid, species, shape=B2, dt=0.1, B=(0.0, 0.0, 0.0),
-                 background=None, deposit="fixed", rtol=1e-13, ke_axes=3):
+                 background=None, deposit="fixed", rtol=1e-13, ke_axes=3, mover="exact"):
         self.m, self.g, self.sp = m, g, species
         self.shape, self.dt, self.B = shape, dt, np.asarray(B, dtype=np.float64)
         self.bg = background
@@ -393,6 +394,7 @@ class OracleSim:
         self.step_count = 0
         self.ke = None
         self.ke_axes = ke_axes  # velocity components in the kinetic-energy sum
+        self.mover = push_pc if mover == "pc" else push
 
     def deposit(self):
         if self.mode == "fixed":
@@ -420,8 +422,8 @@ class OracleSim:
         self.counts = []
         for s in self.sp:
             v_old = s["vel"].copy()
-            s["cell"], s["off"], s["vel"], cnt = push(self.m, self.g, s["q"] / s["m"], self.dt,
-                                                      self.B, s["cell"], s["off"], s["vel"], self.Ev)
+            s["cell"], s["off"], s["vel"], cnt = self.mover(self.m, self.g, s["q"] / s["m"], self.dt,
+                                                            self.B, s["cell"], s["off"], s["vel"], self.Ev)
             alive = s["cell"] >= 0
             k = self.ke_axes
             ke += 0.5 * s["m"] * s["w"] * float(np.sum(v_old[alive, :k] * s["vel"][alive, :k]))

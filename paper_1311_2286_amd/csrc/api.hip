@@ -70,6 +70,7 @@ struct cpic_sim {
   bool poisoned = false;
   bool sorted_dirty = true;
   bool phi_prev_valid = false;  // G.phi_prev holds the previous step's potential
+  void* kc = nullptr;           // predictor-corrector mover: vertex table of n_a dxi^a/dx^b
   bool graphs = false;          // replay recorded HIP graphs of the step
   int* cycles_host = nullptr;   // pinned: V-cycles of a recent solve (written by async copies)
   bool cycles_known = false;
@@ -187,6 +188,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   if (!(grid->dt > 0) || !isfinite(grid->dt)) return CPIC_E_ARG;
   if (grid->background && (d != 2 || !all_periodic)) return CPIC_E_UNSUPPORTED;
   if (grid->mg_method != CPIC_MG_FCG && grid->mg_method != CPIC_MG_VCYCLE) return CPIC_E_ARG;
+  if (grid->mover != CPIC_MOVER_NEWTON && grid->mover != CPIC_MOVER_PC) return CPIC_E_ARG;
 
   cpic_sim* s = new cpic_sim();
   s->map = *map;
@@ -360,6 +362,8 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   G.mg_flag = (int*)A(sizeof(int) * 4);
   G.Ev = A(real_size(s) * ecomp(s) * (size_t)g.nverts);
   G.Kv = (double*)A(sizeof(double) * (size_t)(d * d) * (size_t)g.nverts);
+  // predictor-corrector table: d x d per vertex padded to 4 (2D) or 12 (3D) values
+  if (grid->mover == CPIC_MOVER_PC) s->kc = A(real_size(s) * (size_t)(d == 3 ? 12 : 4) * (size_t)g.nverts);
   G.phi_prev = (double*)A(cb);
   s->ke = (double*)A(sizeof(double) * 2);
   s->flags = (int*)A(sizeof(int) * 8);
@@ -390,6 +394,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   launch_fill_u8(G.mg_flag, 0, sizeof(int) * 4, st);
   launch_jacobian_centres(G, st);
   launch_vertex_metric(G, st);
+  if (s->kc) launch_kc_table(g, G.Kv, s->kc, G.fp64, st);
   if (hipHostMalloc((void**)&s->cycles_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
     s->cycles_host = nullptr;
     cpic_destroy(s);
@@ -689,6 +694,7 @@ static void particles_pass(cpic_sim* s, int mode, bool count_tiles = false) {
     L.ke = s->ke;
     L.ke_part = S.ke_part;
     L.tile_counts = (count_tiles && mode == MODE_PUSH) ? S.counts : nullptr;
+    L.kc = s->kc;
     L.counters = S.counters;
     launch_particles(L, s->stream);
   }

@@ -12,6 +12,9 @@
 namespace cpic {
 
 enum { MAP_IDENTITY = 0, MAP_SINUSOIDAL = 1, MAP_POLAR_LOG = 2 };
+// particle-kernel variant that moves with the tabulated inverse Jacobian (the
+// predictor-corrector update), whatever the map
+constexpr int MAP_TABLE_PC = 3;
 enum { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_NEUMANN = 2 };
 enum { PBC_PERIODIC = 0, PBC_ABSORB = 1, PBC_OUTFLOW = 2 };
 enum { SHAPE_B1 = 1, SHAPE_B2 = 2 };

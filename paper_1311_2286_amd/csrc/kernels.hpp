@@ -38,6 +38,7 @@ struct ParticleLaunch {
   double* ke;
   double* ke_part;  // [max_items] per-item kinetic energy sums (PUSH)
   int* tile_counts; // when set: per-tile counts of the new positions for the next sort
+  const void* kc;   // when set: predictor-corrector mover with this vertex table (R, D x D per vertex)
   unsigned long long* counters;
 };
 
@@ -93,6 +94,7 @@ struct InjectLaunch {
 };
 
 int launch_particles(const ParticleLaunch& L, hipStream_t st);
+void launch_kc_table(const Geo& g, const double* Kv, void* kc, int fp64, hipStream_t st);
 void launch_ke_reduce(const KeReduce& r, hipStream_t st);
 int launch_inject(const InjectLaunch& I, hipStream_t st);
 int launch_tile_sort(const SortLaunch& S, hipStream_t st);

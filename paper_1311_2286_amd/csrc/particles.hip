@@ -189,6 +189,92 @@ __device__ __forceinline__ bool move_delta(const Geo& g, const int* idx, const R
   return conv && !low_j;
 }
 
+// values per vertex in the kc table: D x D padded to a multiple of 4
+template <int D> constexpr int KC_STRIDE = D == 3 ? 12 : 4;
+
+// Inverse Jacobian in cells per unit length, kc_ab = n_a dxi^a/dx^b, carried
+// from the vertex table to the point (cell cidx, offset cf) by the CIC vertex
+// weights (Eq. step3 with the b1 weights of Eq. Wvp).  Vertex n of a periodic
+// axis is vertex 0.
+template <int D, typename R>
+__device__ __forceinline__ void kc_interp(const Geo& g, const R* __restrict__ kc, const int* cidx, const R* cf,
+                                          R* k) {
+#pragma unroll
+  for (int e = 0; e < D * D; ++e) k[e] = (R)0;
+#pragma unroll
+  for (int corner = 0; corner < (1 << D); ++corner) {
+    long long v = 0;
+    R w = (R)1;
+#pragma unroll
+    for (int ax = D - 1; ax >= 0; --ax) {
+      const int c = (corner >> ax) & 1;
+      int vi = cidx[ax] + c;
+      if (vi >= g.nv[ax]) vi -= g.nv[ax];
+      v = v * g.nv[ax] + vi;
+      w *= c ? cf[ax] : (R)1 - cf[ax];
+    }
+    R kv[KC_STRIDE<D>];
+    using V4 = typename std::conditional<std::is_same<R, float>::value, float4, double4>::type;
+    const V4* src = reinterpret_cast<const V4*>(kc + v * KC_STRIDE<D>);
+#pragma unroll
+    for (int q = 0; q < KC_STRIDE<D> / 4; ++q) {
+      const V4 t = src[q];
+      kv[4 * q + 0] = t.x;
+      kv[4 * q + 1] = t.y;
+      kv[4 * q + 2] = t.z;
+      kv[4 * q + 3] = t.w;
+    }
+#pragma unroll
+    for (int e = 0; e < D * D; ++e) k[e] += w * kv[e];
+  }
+}
+
+// Predictor-corrector position update (Eqs. step2-step4) in cells:
+//   predictor  u' = (idx + f) + (dt/2) kc(idx, f) v,
+//   corrector  d  = dt kc(u') v,
+// the predictor point wrapped on periodic axes and clamped into the grid on
+// bounded ones for the interpolation of kc.
+template <int D, typename R>
+__device__ __forceinline__ void move_pc(const Geo& g, const R* __restrict__ kc, const int* idx, const R* f,
+                                        const R* v, R dt, R* d) {
+  R k[D * D];
+  kc_interp<D, R>(g, kc, idx, f, k);
+  int pidx[3] = {0, 0, 0};
+  R pf[3] = {(R)0, (R)0, (R)0};
+  const R h = (R)0.5 * dt;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    R s = (R)0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) s += k[a * D + b] * v[b];
+    const R u = (R)idx[a] + f[a] + h * s;
+    const R fl = floor(u);
+    int i = (int)fl;
+    R fr = u - fl;
+    const int n = g.n[a];
+    if (g.periodic[a]) {
+      i %= n;
+      if (i < 0) i += n;
+    } else if (u < (R)0) {
+      i = 0;
+      fr = (R)0;
+    } else if (i >= n) {
+      i = n - 1;
+      fr = (R)1;
+    }
+    pidx[a] = i;
+    pf[a] = fr;
+  }
+  kc_interp<D, R>(g, kc, pidx, pf, k);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    R s = (R)0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) s += k[a * D + b] * v[b];
+    d[a] = dt * s;
+  }
+}
+
 // New cell and offset from cell idx, offset f and increment d (cells), with
 // the particle boundaries.  Returns 0 (alive), -1 (absorbed: a wall with an
 // absorbing condition) or -2 (left through an outflow wall).
@@ -235,6 +321,8 @@ struct PartArgs {
   const int* item_end;
   const int* n_items;
   const R* Ev;
+  const R* kc;  // predictor-corrector mover: n_a dxi^a/dx^b at every vertex (row-major D x D,
+                // padded to KC_STRIDE<D> values so a vertex is whole 16-byte loads)
   void* Q;
   Geo g;
   int pbc_lo[3], pbc_hi[3];
@@ -552,7 +640,7 @@ __device__ __forceinline__ bool gather_E_window(const R* __restrict__ ewin, cons
 }
 
 template <int D, int MAP, int SHAPE, typename R, bool FIXED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? 5 : 2, 8))) void particle_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel(
     PartArgs<R> a) {
   using TS = TileShape<D>;
   using FW = FieldWindow<D>;
@@ -660,7 +748,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? 5 :
       ke += (double)(vo0 * v[0] + vo1 * v[1] + vo2 * v[2]);
 
       R d[3] = {(R)0, (R)0, (R)0};
-      bool conv = move_delta<D, MAP, R>(g, idx, f, v, a.dt, a.inv_dxc, a.newton_maxit, a.newton_tol,
+      bool conv;
+      if constexpr (MAP == MAP_TABLE_PC) {
+        move_pc<D, R>(g, a.kc, idx, f, v, a.dt, d);
+        conv = true;
+      } else
+        conv = move_delta<D, MAP, R>(g, idx, f, v, a.dt, a.inv_dxc, a.newton_maxit, a.newton_tol,
                                         a.kappa, d);
       if (!conv) {
         // rare: the FP64 fallback kernel moves and deposits this particle
@@ -1283,6 +1376,7 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   a.item_end = L.item_end;
   a.n_items = L.n_items;
   a.Ev = (const R*)L.Ev;
+  a.kc = (const R*)L.kc;
   a.Q = L.Q;
   a.g = L.g;
   for (int i = 0; i < 3; ++i) {
@@ -1312,8 +1406,10 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   constexpr bool FIXED = std::is_same<R, float>::value;
   hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED>), dim3(L.max_items), dim3(256), 0, st,
                      a);
-  if (MAP != MAP_IDENTITY && L.mode == MODE_PUSH)
-    hipLaunchKernelGGL((fallback_kernel<D, MAP, R, FIXED>), dim3(64), dim3(256), 0, st, a, L.shape);
+  if constexpr (MAP != MAP_IDENTITY && MAP != MAP_TABLE_PC) {
+    if (L.mode == MODE_PUSH)
+      hipLaunchKernelGGL((fallback_kernel<D, MAP, R, FIXED>), dim3(64), dim3(256), 0, st, a, L.shape);
+  }
 }
 
 template <int D, int MAP, typename R>
@@ -1328,6 +1424,11 @@ static int launch_particle_shape(const ParticleLaunch& L, hipStream_t st) {
 template <typename R>
 static int launch_particle_r(const ParticleLaunch& L, hipStream_t st) {
   const int D = L.g.dim, M = L.g.kind;
+  if (L.kc) {
+    if (D == 2) return launch_particle_shape<2, MAP_TABLE_PC, R>(L, st);
+    if (D == 3) return launch_particle_shape<3, MAP_TABLE_PC, R>(L, st);
+    return -1;
+  }
   if (D == 2) {
     if (M == MAP_IDENTITY) return launch_particle_shape<2, MAP_IDENTITY, R>(L, st);
     if (M == MAP_SINUSOIDAL) return launch_particle_shape<2, MAP_SINUSOIDAL, R>(L, st);
@@ -1337,6 +1438,29 @@ static int launch_particle_r(const ParticleLaunch& L, hipStream_t st) {
     if (M == MAP_SINUSOIDAL) return launch_particle_shape<3, MAP_SINUSOIDAL, R>(L, st);
   }
   return -1;
+}
+
+// kc = n_a k_ab at every vertex from the FP64 inverse-Jacobian table
+template <typename R>
+__global__ void kc_table_kernel(long long nverts, int d, const double* __restrict__ Kv, double n0, double n1,
+                                double n2, R* kc) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nverts) return;
+  const double n[3] = {n0, n1, n2};
+  const int stride = d == 3 ? KC_STRIDE<3> : KC_STRIDE<2>;
+  for (int e = 0; e < stride; ++e) kc[v * stride + e] = (R)0;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) kc[v * stride + a * d + b] = (R)(n[a] * Kv[v * d * d + a * d + b]);
+}
+
+void launch_kc_table(const Geo& g, const double* Kv, void* kc, int fp64, hipStream_t st) {
+  const unsigned blocks = (unsigned)((g.nverts + 255) / 256);
+  if (fp64)
+    hipLaunchKernelGGL(kc_table_kernel<double>, dim3(blocks), dim3(256), 0, st, (long long)g.nverts, g.dim, Kv,
+                       (double)g.n[0], (double)g.n[1], (double)g.n[2], (double*)kc);
+  else
+    hipLaunchKernelGGL(kc_table_kernel<float>, dim3(blocks), dim3(256), 0, st, (long long)g.nverts, g.dim, Kv,
+                       (double)g.n[0], (double)g.n[1], (double)g.n[2], (float*)kc);
 }
 
 int launch_particles(const ParticleLaunch& L, hipStream_t st) {
