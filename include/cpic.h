@@ -150,7 +150,10 @@ typedef struct {
   double background_n0; /* its density (charge +n0 per unit volume) */
   double mg_rtol;       /* relative residual target of the Poisson solve */
   int mg_max_cycles;    /* V-cycles per solve (upper bound; one per FCG iteration) */
-  int sort_every;       /* tile sort every this many steps (>= 1) */
+  int sort_every;       /* tile sort of a species at most every this many steps (>= 1): then,
+                           unless (steps since its last sort) x (largest particle increment seen,
+                           in cells) is below one cell -- slow species are sorted less often,
+                           at least every 16 sort_every steps; injecting species every step */
   int track_ids;        /* carry a uint32 particle id through sorts */
   int mg_method;        /* CPIC_MG_FCG (0) or CPIC_MG_VCYCLE */
   int mover;            /* CPIC_MOVER_NEWTON (0) or CPIC_MOVER_PC */
@@ -187,6 +190,8 @@ typedef struct {
   long long newton_failed;   /* cumulative position updates that missed the tolerance */
   long long injected[8];     /* cumulative injected particles per species */
   int step_graphs;           /* step variants recorded as HIP graphs (graph mode) */
+  long long sorts[8];        /* tile sorts per species so far (a species whose particles
+                                drift less than a cell between sorts is sorted less often) */
 } cpic_diag;
 
 /* Create a simulation on the current HIP device.  hip_stream may be NULL

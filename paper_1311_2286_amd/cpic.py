@@ -73,7 +73,8 @@ class Diag(ctypes.Structure):
                 ("outflow", ctypes.c_longlong * 8), ("qsum_lo", ctypes.c_uint64 * 8),
                 ("qsum_hi", ctypes.c_uint64 * 8), ("newton_fallback", ctypes.c_longlong),
                 ("far_deposits", ctypes.c_longlong), ("newton_failed", ctypes.c_longlong),
-                ("injected", ctypes.c_longlong * 8), ("step_graphs", ctypes.c_int)]
+                ("injected", ctypes.c_longlong * 8), ("step_graphs", ctypes.c_int),
+                ("sorts", ctypes.c_longlong * 8)]
 
 
 class CaseDesc(ctypes.Structure):

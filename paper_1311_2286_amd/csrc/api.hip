@@ -46,6 +46,8 @@ struct Species {
   double inject_lam = 0.0;
   int* fb_queue = nullptr;  // particles handed to the FP64 fallback kernel
   int* fb_count = nullptr;
+  int since_sort = 0;       // steps since this species' last tile sort
+  long long sorts = 0;      // tile sorts so far
 };
 
 struct StepEvents {
@@ -74,6 +76,8 @@ struct cpic_sim {
   bool graphs = false;          // replay recorded HIP graphs of the step
   int* cycles_host = nullptr;   // pinned: V-cycles of a recent solve (written by async copies)
   bool cycles_known = false;
+  unsigned* drift_dev = nullptr;   // per species: running max of a particle's increment (cells, FP32 bits)
+  unsigned* drift_host = nullptr;  // pinned copy of a recent drift_dev (written by async copies)
   struct StepGraph {
     uint64_t key;
     hipGraphExec_t exec;
@@ -360,6 +364,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   }
   G.scalars = (double*)A(sizeof(double) * 16);
   G.mg_flag = (int*)A(sizeof(int) * 4);
+  s->drift_dev = (unsigned*)A(sizeof(unsigned) * 8);
   G.Ev = A(real_size(s) * ecomp(s) * (size_t)g.nverts);
   G.Kv = (double*)A(sizeof(double) * (size_t)(d * d) * (size_t)g.nverts);
   // predictor-corrector table: d x d per vertex padded to 4 (2D) or 12 (3D) values
@@ -392,6 +397,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   launch_fill_u8(G.Ev, 0, real_size(s) * ecomp(s) * (size_t)g.nverts, st);
   launch_fill_u8(s->ke, 0, sizeof(double) * 2, st);
   launch_fill_u8(G.mg_flag, 0, sizeof(int) * 4, st);
+  launch_fill_u8(s->drift_dev, 0, sizeof(unsigned) * 8, st);
   launch_jacobian_centres(G, st);
   launch_vertex_metric(G, st);
   if (s->kc) launch_kc_table(g, G.Kv, s->kc, G.fp64, st);
@@ -401,6 +407,12 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     return CPIC_E_NOMEM;
   }
   *s->cycles_host = -1;
+  if (hipHostMalloc((void**)&s->drift_host, sizeof(unsigned) * 8, hipHostMallocDefault) != hipSuccess) {
+    s->drift_host = nullptr;
+    cpic_destroy(s);
+    return CPIC_E_NOMEM;
+  }
+  memset(s->drift_host, 0, sizeof(unsigned) * 8);
   if (compute_smoother_bounds(G, st) != 0 || setup_coarse_inverse(G, st) != 0) {
     cpic_destroy(s);
     return CPIC_E_HIP;
@@ -554,6 +566,9 @@ extern "C" cpic_status cpic_set_particles(cpic_sim* s, int sid, size_t n, const 
       launch_iota(S.id[buf], (int)n, st);
   }
   launch_fill_u8(s->flags, 0, sizeof(int) * 8, st);
+  // new particles: their drift is unknown again
+  launch_fill_u8(s->drift_dev + sid, 0, sizeof(unsigned), st);
+  if (s->drift_host) s->drift_host[sid] = 0u;
   launch_lin_to_key(lin_tmp, S.key[buf], (int)n, s->g, s->flags, st);
   if (on_device)
     for (int a = 0; a < d; ++a) launch_offsets_check(S.off[buf][a], (long long)n, rs == 8, s->flags + 1, st);
@@ -638,9 +653,21 @@ static void sort_species(cpic_sim* s, Species& S, bool counts_ready) {
   S.cur = b;
 }
 
-// counts_ready: the step's particle and injection kernels counted the tiles
-static void sort_all(cpic_sim* s, bool counts_ready = false) {
-  for (auto& S : s->sp) sort_species(s, S, counts_ready);
+static unsigned all_species(const cpic_sim* s) { return (1u << s->sp.size()) - 1u; }
+
+// Tile sort of the species in `mask`; counts_ready: the step's particle and
+// injection kernels counted their tiles.
+static void sort_species_mask(cpic_sim* s, unsigned mask, bool counts_ready) {
+  for (size_t k = 0; k < s->sp.size(); ++k)
+    if (mask >> k & 1u) sort_species(s, s->sp[k], counts_ready);
+}
+
+static void sort_all(cpic_sim* s) {
+  sort_species_mask(s, all_species(s), false);
+  for (auto& S : s->sp) {
+    S.since_sort = 0;
+    ++S.sorts;
+  }
   s->sorted_dirty = false;
 }
 
@@ -654,9 +681,11 @@ static void zero_deposits(cpic_sim* s, int mode) {
 }
 
 // particle kernels of all species (deposit arrays must have been zeroed)
-static void particles_pass(cpic_sim* s, int mode, bool count_tiles = false) {
+// count_mask: species whose new tiles are counted for a sort at the end of the step
+static void particles_pass(cpic_sim* s, int mode, unsigned count_mask = 0) {
   const bool halfstep = mode == MODE_HALFSTEP;
-  for (auto& S : s->sp) {
+  for (size_t k = 0; k < s->sp.size(); ++k) {
+    Species& S = s->sp[k];
     ParticleLaunch L;
     memset(&L, 0, sizeof(L));
     L.g = s->g;
@@ -693,8 +722,9 @@ static void particles_pass(cpic_sim* s, int mode, bool count_tiles = false) {
     L.ke_scale = 0.5 * S.desc.m * S.desc.w;
     L.ke = s->ke;
     L.ke_part = S.ke_part;
-    L.tile_counts = (count_tiles && mode == MODE_PUSH) ? S.counts : nullptr;
+    L.tile_counts = ((count_mask >> k & 1u) && mode == MODE_PUSH) ? S.counts : nullptr;
     L.kc = s->kc;
+    L.drift = mode == MODE_PUSH ? s->drift_dev + k : nullptr;
     L.counters = S.counters;
     launch_particles(L, s->stream);
   }
@@ -719,7 +749,7 @@ static bool any_injection(const cpic_sim* s) {
 }
 
 // Maxwellian-flux injection of every injecting species for step `step`
-static void inject_pass(cpic_sim* s, long long step, bool count_tiles = false) {
+static void inject_pass(cpic_sim* s, long long step, unsigned count_mask = 0) {
   for (size_t k = 0; k < s->sp.size(); ++k) {
     Species& S = s->sp[k];
     if (!S.desc.inject) continue;
@@ -749,7 +779,7 @@ static void inject_pass(cpic_sim* s, long long step, bool count_tiles = false) {
     I.species = (uint32_t)k;
     I.counters = S.counters;
     I.count_out = S.d_n + 1;
-    I.tile_counts = count_tiles ? S.counts : nullptr;
+    I.tile_counts = (count_mask >> k & 1u) ? S.counts : nullptr;
     launch_inject(I, s->stream);
   }
 }
@@ -788,6 +818,32 @@ static void record_cycles(cpic_sim* s) {
   if (!s->cycles_host) return;
   (void)hipMemcpyAsync(s->cycles_host, s->G.mg_flag + 1, sizeof(int), hipMemcpyDeviceToHost, s->stream);
   s->cycles_known = true;
+}
+
+// Species to tile-sort at the end of the coming step.  A species sorts at
+// most every sort_every steps; it sorts then unless a bound on its particles'
+// drift since its last sort (steps x the largest increment seen so far,
+// copied back asynchronously) is below one cell, the slack of the tile
+// windows, and at least every 16 sort_every steps.  Injecting species sort
+// every step (appended particles join a tile at a sort).
+static unsigned sort_mask(const cpic_sim* s) {
+  const int K = s->grid.sort_every;
+  unsigned mask = 0;
+  for (size_t k = 0; k < s->sp.size(); ++k) {
+    const Species& S = s->sp[k];
+    const int after = S.since_sort + 1;
+    bool sort = S.desc.inject != 0;
+    if (!sort && after >= K) {
+      float dmax = 0.0f;
+      if (s->drift_host) {
+        const unsigned bits = ((volatile unsigned*)s->drift_host)[k];
+        memcpy(&dmax, &bits, sizeof(dmax));
+      }
+      sort = !(dmax > 0.0f) || (float)after * dmax >= 1.0f || after >= 16 * K;
+    }
+    if (sort) mask |= 1u << k;
+  }
+  return mask;
 }
 
 static void ensure_sorted(cpic_sim* s) {
@@ -839,18 +895,20 @@ static StepEvents* next_events(cpic_sim* s) {
   return &s->evs[s->ev_used++];
 }
 
-// The kernels of one step after ensure_sorted (asynchronous, no host reads).
-static void step_body(cpic_sim* s, StepEvents* ev, bool inj, bool do_sort, int cycles) {
+// The kernels of one step after ensure_sorted (asynchronous, no host reads);
+// the species in sort_mask are tile-sorted at its end.
+static void step_body(cpic_sim* s, StepEvents* ev, bool inj, unsigned sort_mask, int cycles) {
   if (ev) hipEventRecord(ev->e[0], s->stream);
   zero_deposits(s, MODE_PUSH);
-  // a step that ends with a tile sort counts the new tiles in its particle
-  // and injection kernels (the sort then needs no histogram pass)
-  if (do_sort)
-    for (auto& S : s->sp) launch_fill_u8(S.counts, 0, sizeof(int) * (size_t)(s->g.ntiles + 2), s->stream);
+  // a species sorted at the end of the step has its new tiles counted by the
+  // step's particle and injection kernels (the sort then needs no histogram)
+  for (size_t k = 0; k < s->sp.size(); ++k)
+    if (sort_mask >> k & 1u)
+      launch_fill_u8(s->sp[k].counts, 0, sizeof(int) * (size_t)(s->g.ntiles + 2), s->stream);
   if (ev) hipEventRecord(ev->e[1], s->stream);
-  particles_pass(s, MODE_PUSH, do_sort);
+  particles_pass(s, MODE_PUSH, sort_mask);
   if (ev) hipEventRecord(ev->e[2], s->stream);
-  if (inj) inject_pass(s, s->step, do_sort);
+  if (inj) inject_pass(s, s->step, sort_mask);
   charge_pass(s);
   // initial guess of the solve: phi extrapolated linearly from the last two steps
   launch_extrapolate_guess(s->G, s->phi_prev_valid ? 1 : 0, s->stream);
@@ -859,7 +917,7 @@ static void step_body(cpic_sim* s, StepEvents* ev, bool inj, bool do_sort, int c
   launch_efield(s->G, s->stream);
   if (ev) hipEventRecord(ev->e[3], s->stream);
   ++s->step;
-  if (do_sort) sort_all(s, true);
+  sort_species_mask(s, sort_mask, true);
   if (ev) hipEventRecord(ev->e[4], s->stream);
 }
 
@@ -867,8 +925,8 @@ static void step_body(cpic_sim* s, StepEvents* ev, bool inj, bool do_sort, int c
 // sort or not, extrapolated guess or not) is recorded once by stream capture
 // and replayed afterwards; the host state a replay stands for (buffer parity,
 // step count) is applied here.  Returns false when capture is not possible.
-static bool graph_step(cpic_sim* s, bool do_sort, int cycles, StepEvents* ev) {
-  uint64_t key = (do_sort ? 1u : 0u) | (s->phi_prev_valid ? 2u : 0u) | ((uint64_t)cycles << 16);
+static bool graph_step(cpic_sim* s, unsigned sort_mask, int cycles, StepEvents* ev) {
+  uint64_t key = (s->phi_prev_valid ? 2u : 0u) | ((uint64_t)cycles << 16) | ((uint64_t)sort_mask << 32);
   for (size_t k = 0; k < s->sp.size(); ++k) key |= (uint64_t)s->sp[k].cur << (2 + k);
   if (ev) {
     hipEventRecord(ev->e[0], s->stream);
@@ -880,7 +938,6 @@ static bool graph_step(cpic_sim* s, bool do_sort, int cycles, StepEvents* ev) {
     for (size_t k = 0; k < s->sp.size(); ++k) s->sp[k].cur = gph.cur_after[k];
     s->phi_prev_valid = true;
     ++s->step;
-    if (do_sort) s->sorted_dirty = false;
     if (ev) hipEventRecord(ev->e[4], s->stream);
     return true;
   }
@@ -894,7 +951,7 @@ static bool graph_step(cpic_sim* s, bool do_sort, int cycles, StepEvents* ev) {
     (void)hipGetLastError();  // e.g. the null stream cannot be captured
     return false;
   }
-  step_body(s, nullptr, false, do_sort, cycles);
+  step_body(s, nullptr, false, sort_mask, cycles);
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool ok = hipStreamEndCapture(s->stream, &graph) == hipSuccess && graph &&
@@ -926,12 +983,23 @@ extern "C" cpic_status cpic_step(cpic_sim* s, int nsteps) {
     ensure_sorted(s);
     StepEvents* ev = s->timing ? next_events(s) : nullptr;
     const bool inj = any_injection(s);
-    // appended particles join a tile at the next sort: sort every step then
-    const bool do_sort = inj || (s->step + 1) % s->grid.sort_every == 0;
+    const unsigned mask = sort_mask(s);
     const int cycles = step_cycles(s);
     // injection draws depend on the step number, a kernel argument: no graphs
-    if (!(s->graphs && !inj && graph_step(s, do_sort, cycles, ev))) step_body(s, ev, inj, do_sort, cycles);
+    if (!(s->graphs && !inj && graph_step(s, mask, cycles, ev))) step_body(s, ev, inj, mask, cycles);
+    for (size_t q = 0; q < s->sp.size(); ++q) {
+      Species& S = s->sp[q];
+      if (mask >> q & 1u) {
+        S.since_sort = 0;
+        ++S.sorts;
+      } else {
+        ++S.since_sort;
+      }
+    }
     record_cycles(s);
+    if (s->drift_host)
+      (void)hipMemcpyAsync(s->drift_host, s->drift_dev, sizeof(unsigned) * s->sp.size(), hipMemcpyDeviceToHost,
+                           s->stream);
   }
   return check_async(s);
 }
@@ -1046,6 +1114,7 @@ extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
     out->far_deposits += (long long)cnt[8 * k + 3];
     out->newton_failed += (long long)cnt[8 * k + 4];
     out->injected[k] = (long long)cnt[8 * k + 5];
+    out->sorts[k] = s->sp[k].sorts;
     out->qsum_lo[k] = qs[2 * k];
     out->qsum_hi[k] = qs[2 * k + 1];
   }
@@ -1108,6 +1177,7 @@ extern "C" void cpic_destroy(cpic_sim* s) {
   (void)hipStreamSynchronize(s->stream);
   for (auto& gph : s->step_graphs) (void)hipGraphExecDestroy(gph.exec);
   if (s->cycles_host) (void)hipHostFree(s->cycles_host);
+  if (s->drift_host) (void)hipHostFree(s->drift_host);
   for (auto& e : s->evs)
     for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e.e[i]);
   sim_free_all(s);

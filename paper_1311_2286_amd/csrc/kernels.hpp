@@ -39,6 +39,7 @@ struct ParticleLaunch {
   double* ke_part;  // [max_items] per-item kinetic energy sums (PUSH)
   int* tile_counts; // when set: per-tile counts of the new positions for the next sort
   const void* kc;   // when set: predictor-corrector mover with this vertex table (R, D x D per vertex)
+  unsigned* drift;  // PUSH: running maximum of the particles' increments (cells, FP32 bits)
   unsigned long long* counters;
 };
 

@@ -340,6 +340,7 @@ struct PartArgs {
   double* ke;
   double* ke_part;
   int* tcount;  // when set (steps followed by a tile sort): live particles per new tile, dead last
+  unsigned* drift;  // PUSH: running maximum of a particle's increment (cells, FP32 bits)
   unsigned long long* counters;
   int* fb_queue;  // particles left to the FP64 fallback kernel
   int* fb_count;
@@ -696,6 +697,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
 
   double ke = 0.0;
   unsigned long long absorbed = 0, outflow = 0, far = 0;
+  float dmax = 0.0f;  // largest increment of this thread's particles (cells)
 
   // The state of the thread's next particle is loaded while the current one
   // is processed, so each wave keeps two particles' loads in flight.
@@ -761,6 +763,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
         if (slot < a.fb_cap) a.fb_queue[slot] = p;
         continue;
       }
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) dmax = fmaxf(dmax, fabsf((float)d[ax]));
       int dead = place_particle<D, R>(g, a.pbc_lo, a.pbc_hi, idx, f, d);
       if (dead) {
         a.key[p] = dead;
@@ -830,6 +834,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
 
   // block sums of the diagnostics
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (a.drift && a.mode == MODE_PUSH) {
+    for (int o = 32; o > 0; o >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, o, 64));
+    // non-negative floats order like their bit patterns
+    if (lane == 0 && dmax > 0.0f) atomicMax(a.drift, __float_as_uint(dmax));
+  }
   double kes = wave_sum(ke);
   unsigned long long cs[5] = {wave_sum_u64(absorbed), wave_sum_u64(outflow), 0ull, wave_sum_u64(far),
                               0ull};
@@ -935,6 +944,11 @@ __global__ __launch_bounds__(256) void fallback_kernel(PartArgs<R> a, int shape)
     bool ok = move_fallback<D, MAP>(g, idx, f, disp, (double)a.kappa, d);
     ++done;
     failed += ok ? 0 : 1;
+    if (a.drift) {
+      float m = 0.0f;
+      for (int ax = 0; ax < D; ++ax) m = fmaxf(m, (float)fabs(d[ax]));
+      atomicMax(a.drift, __float_as_uint(m));
+    }
     int dead = place_particle<D, double>(g, a.pbc_lo, a.pbc_hi, idx, f, d);
     if (dead) {
       a.key[p] = dead;
@@ -1397,6 +1411,7 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   a.ke_scale = L.ke_scale;
   a.ke_part = L.ke_part;
   a.tcount = L.tile_counts;
+  a.drift = L.drift;
   a.ke = L.ke;
   a.counters = L.counters;
   a.fb_queue = L.fb_queue;

@@ -3,8 +3,11 @@ and injection kernels of that step count the particles' new tiles themselves
 (the sort then runs no histogram pass).
 
 Bars:
-  - after a step that sorts, each species is stored in non-decreasing tile
+  - after a step that sorts a species, it is stored in non-decreasing tile
     order, every identifier once, the live count that of the diagnostics;
+  - a species whose particles drift less than a cell between sorts is sorted
+    less often than sort_every asks (ions against electrons), with bitwise
+    the same physics as sorting every species every step (FP32 path);
   - FP32 path (integer deposit, per-particle arithmetic): a run that sorts
     every step and a run that never sorts give bitwise the same particles
     (matched by identifier) and potential, with particles fast enough to leave
@@ -46,9 +49,9 @@ def tiles_of(case, cell):
     return i // T[0] + nt[0] * (j // T[1] + nt[1] * (k // T[2]))
 
 
-def check_sorted_storage(case, sim):
+def check_sorted_storage(case, sim, species=None):
     d = sim.diag()
-    for sid in range(len(case.species)):
+    for sid in (range(len(case.species)) if species is None else species):
         p = sim.get_particles(sid)
         assert p["cell"].size == d.count[sid]
         assert np.all(p["cell"] >= 0)
@@ -76,9 +79,11 @@ def test_sort_every_step_is_bitwise_no_sort(dim):
     a.initialize()
     b.initialize()
     for k in range(4):
+        before = list(a.diag().sorts)
         a.step(1)
         b.step(1)
-        check_sorted_storage(case, a)
+        after = list(a.diag().sorts)
+        check_sorted_storage(case, a, [s for s in range(len(case.species)) if after[s] > before[s]])
         assert np.array_equal(a.get_field(C().FIELD_PHI), b.get_field(C().FIELD_PHI)), k
         for sid in range(len(case.species)):
             pa, pb = by_id(a.get_particles(sid)), by_id(b.get_particles(sid))
@@ -90,6 +95,32 @@ def test_sort_every_step_is_bitwise_no_sort(dim):
         assert d.far_deposits > 0
     else:
         assert d.newton_fallback > 0
+    a.close()
+    b.close()
+
+
+def test_slow_species_sort_less_often_with_the_same_physics():
+    case = W.small_case(dim=3, n=(20, 12, 16), ppc=4.0, case_id=122)
+    a, _ = gpu_sim(case, precision=0, sort_every=2)
+    b, _ = gpu_sim(case, precision=0, sort_every=1)
+    a.initialize()
+    b.initialize()
+    for k in range(12):
+        before = list(a.diag().sorts)
+        a.step(1)
+        b.step(1)
+        after = list(a.diag().sorts)
+        check_sorted_storage(case, a, [s for s in range(2) if after[s] > before[s]])
+        assert np.array_equal(a.get_field(C().FIELD_PHI), b.get_field(C().FIELD_PHI)), k
+    d = a.diag()
+    # electrons (v_th 1, dt 0.1, unit cells): up to every second step; ions
+    # (43 times slower) not again within 12 steps after the initial sort
+    assert d.sorts[0] >= 4, list(d.sorts)
+    assert d.sorts[1] < d.sorts[0], list(d.sorts)
+    for sid in range(2):
+        pa, pb = by_id(a.get_particles(sid)), by_id(b.get_particles(sid))
+        for f in ("id", "cell", "off", "vel"):
+            assert np.array_equal(pa[f], pb[f]), (sid, f)
     a.close()
     b.close()
 
