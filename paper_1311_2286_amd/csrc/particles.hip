@@ -539,9 +539,15 @@ __device__ __forceinline__ void deposit_particle(const Geo& g, const int* origin
   }
 }
 
-// Tile of a particle's new cell, counted for the next tile sort: in the
-// workgroup's bins when it is this tile or a neighbour (wrapping on periodic
-// axes), else straight into the global count.
+// Tile of a particle's new cell, counted for the next tile sort.  Staying in
+// this tile (the common case) is not counted here: the workgroup derives it
+// at the end from its particle count and the other bins.  A neighbouring
+// tile (wrapping on periodic axes) goes to the workgroup's bins, a farther
+// one straight into the global count (and bin TB_FAR).
+// new-tile bins of a workgroup: 27 tiles around its own (dx + 3 dy + 9 dz,
+// offsets + 1), dead, farther tiles, particles left to the FP64 fallback
+constexpr int TB_OWN = 13, TB_DEAD = 27, TB_FAR = 28, TB_FALLBACK = 29, TB_N = 30;
+
 template <int D>
 __device__ __forceinline__ void count_new_tile(const Geo& g, const int* idx, int tci, int tcj, int tck,
                                                int* tbins, int* tcount) {
@@ -562,10 +568,12 @@ __device__ __forceinline__ void count_new_tile(const Geo& g, const int* idx, int
     b += (dd + 1) * mul;
     mul *= 3;
   }
-  if (near)
-    atomicAdd(&tbins[b], 1);
-  else
+  if (near) {
+    if (b != TB_OWN) atomicAdd(&tbins[b], 1);
+  } else {
     atomicAdd(&tcount[tn[0] + g.nt[0] * (tn[1] + g.nt[1] * tn[2])], 1);
+    atomicAdd(&tbins[TB_FAR], 1);
+  }
 }
 
 // Vertex-field window of a tile: vertices origin-1 .. origin+T+1 per axis, so
@@ -651,7 +659,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
   __shared__ R ewin[FW::N * FW::C];
   __shared__ double red_d[8];
   __shared__ unsigned long long red_u[8][5];
-  __shared__ int tbins[28];  // new tiles of the particles: the 27 around this tile, then dead
+  __shared__ int tbins[TB_N];  // new tiles of the particles (see count_new_tile)
 
   const int item = blockIdx.x;
   if (item >= *a.n_items) return;
@@ -668,7 +676,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
   const bool tcount = a.tcount != nullptr && a.mode == MODE_PUSH;
   if (deposit)
     for (int s = threadIdx.x; s < TS::WIN; s += blockDim.x) win[s] = (QT)0;
-  if (threadIdx.x < 28) tbins[threadIdx.x] = 0;
+  if (threadIdx.x < TB_N) tbins[threadIdx.x] = 0;
   const int tci = tile % g.nt[0], tcj = (tile / g.nt[0]) % g.nt[1], tck = tile / (g.nt[0] * g.nt[1]);
   if (a.mode != MODE_DEPOSIT) {
     // stage the vertex field of the tile and a one-cell halo
@@ -698,6 +706,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
   double ke = 0.0;
   unsigned long long absorbed = 0, outflow = 0, far = 0;
   float dmax = 0.0f;  // largest increment of this thread's particles (cells)
+
 
   // The state of the thread's next particle is loaded while the current one
   // is processed, so each wave keeps two particles' loads in flight.
@@ -733,7 +742,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
       }
     }
     if (key < 0) {
-      if (tcount) atomicAdd(&tbins[27], 1);
+      if (tcount) atomicAdd(&tbins[TB_DEAD], 1);
       continue;
     }
     int idx[3] = {key_i(key, g), key_j(key, g), (D == 3) ? key_k(key, g) : 0};
@@ -758,9 +767,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
         conv = move_delta<D, MAP, R>(g, idx, f, v, a.dt, a.inv_dxc, a.newton_maxit, a.newton_tol,
                                         a.kappa, d);
       if (!conv) {
-        // rare: the FP64 fallback kernel moves and deposits this particle
+        // rare: the FP64 fallback kernel moves, deposits and counts this particle
         int slot = atomicAdd(a.fb_count, 1);
         if (slot < a.fb_cap) a.fb_queue[slot] = p;
+        if (tcount) atomicAdd(&tbins[TB_FALLBACK], 1);
         continue;
       }
 #pragma unroll
@@ -770,7 +780,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
         a.key[p] = dead;
         absorbed += dead == -1 ? 1 : 0;
         outflow += dead == -2 ? 1 : 0;
-        if (tcount) atomicAdd(&tbins[27], 1);
+        if (tcount) atomicAdd(&tbins[TB_DEAD], 1);
         continue;
       }
       a.key[p] = make_key(idx[0], idx[1], idx[2], g);
@@ -813,6 +823,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
 
   if (tcount) {
     __syncthreads();
+    if (threadIdx.x == 0) {
+      int other = 0;
+      for (int b = 0; b < TB_N; ++b) other += b == TB_OWN ? 0 : tbins[b];
+      // the item's bounds are read again rather than kept live across the loop
+      tbins[TB_OWN] = (a.item_end[item] - a.item_begin[item]) - other;
+    }
+    __syncthreads();
     if (threadIdx.x < 27) {
       const int c = tbins[threadIdx.x];
       if (c) {
@@ -827,8 +844,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
         }
         atomicAdd(&a.tcount[t[0] + g.nt[0] * (t[1] + g.nt[1] * t[2])], c);
       }
-    } else if (threadIdx.x == 27 && tbins[27]) {
-      atomicAdd(&a.tcount[g.ntiles], tbins[27]);
+    } else if (threadIdx.x == TB_DEAD && tbins[TB_DEAD]) {
+      atomicAdd(&a.tcount[g.ntiles], tbins[TB_DEAD]);
     }
   }
 
