@@ -28,7 +28,10 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 IDENTITY, SINUSOIDAL, POLAR_LOG, SPHERICAL_RZ = 0, 1, 2, 3
-PERIODIC, DIRICHLET, NEUMANN = 0, 1, 2
+# FLOATING: a conducting wall of unknown potential at the lower face of axis 0
+# whose charge is what the particles absorbed there (Gauss' law); handled by
+# poisson_solve_floating and OracleSim, which pass the C routines a Dirichlet copy
+PERIODIC, DIRICHLET, NEUMANN, FLOATING = 0, 1, 2, 3
 B1, B2 = 1, 2
 
 
@@ -106,8 +109,12 @@ def lib():
         L.or_num_threads.restype = ctypes.c_int
         L.or_face_area.argtypes = [P(Map)]
         L.or_face_area.restype = d
-        L.or_inject.argtypes = [P(Map), P(Grid), d, d, d, d, u32, u32, u32, u32, lg, P(i32), P(d),
+        L.or_inject.argtypes = [P(Map), P(Grid), d, d, d, d, d, u32, u32, u32, u32, lg, P(i32), P(d),
                                 P(d), P(lg), P(lg)]
+        L.or_drift_flux.argtypes = [d, d, d]
+        L.or_drift_flux.restype = d
+        L.or_wall_flux.argtypes = [P(Map), P(Grid), P(d), d]
+        L.or_wall_flux.restype = d
         L.or_inject.restype = lg
         _lib_handle = L
     return _lib_handle
@@ -320,16 +327,18 @@ def face_area(m: Map) -> float:
     return float(lib().or_face_area(ctypes.byref(m)))
 
 
-def inject(m: Map, g: Grid, n0, vth, w, dt, seed, step, species, cap=1 << 20, with_index=False):
+def inject(m: Map, g: Grid, n0, vth, w, dt, seed, step, species, cap=1 << 20, with_index=False,
+           drift=0.0):
     """Particles injected through the upper face of axis 0 in one step:
     (cell, off (n,3), vel (n,3), number drawn[, draw index of each particle]).
-    Particles whose free-streaming start leaves the grid are not kept."""
+    Particles whose free-streaming start leaves the grid are not kept.  drift:
+    speed of the Maxwellian's drift along the inward normal (0: at rest)."""
     cell = np.zeros(cap, dtype=np.int32)
     off = np.zeros((cap, 3))
     vel = np.zeros((cap, 3))
     kidx = np.zeros(cap, dtype=np.int64)
     drawn = ctypes.c_long(0)
-    n = lib().or_inject(ctypes.byref(m), ctypes.byref(g), n0, vth, w, dt, seed & 0xFFFFFFFF,
+    n = lib().or_inject(ctypes.byref(m), ctypes.byref(g), n0, vth, float(drift), w, dt, seed & 0xFFFFFFFF,
                         (seed >> 32) & 0xFFFFFFFF, step, species, cap, _p(cell, ctypes.c_int32),
                         _p(off, ctypes.c_double), _p(vel, ctypes.c_double),
                         _p(kidx, ctypes.c_long), ctypes.byref(drawn))
@@ -337,6 +346,46 @@ def inject(m: Map, g: Grid, n0, vth, w, dt, seed, step, species, cap=1 << 20, wi
     if with_index:
         out = out + (kidx[:n].copy(),)
     return out
+
+
+def drift_flux(n0, vth, s):
+    """Inward flux of a Maxwellian drifting inward at s thermal speeds."""
+    return float(lib().or_drift_flux(n0, vth, s))
+
+
+def wall_flux(m: Map, g: Grid, phi, phib):
+    """Discrete flux of E through the lower face of axis 0 held at phib."""
+    return float(lib().or_wall_flux(ctypes.byref(m), ctypes.byref(g), _p(_f64(phi), ctypes.c_double), phib))
+
+
+def _grid_with_wall(g: Grid, value, others_zero):
+    """Copy of g with the lower face of axis 0 a Dirichlet wall at `value`
+    (and, if others_zero, every other Dirichlet value 0)."""
+    bl = list(g.bc_lo)
+    bl[0] = DIRICHLET
+    pl = [0.0] * 3 if others_zero else list(g.phi_lo)
+    ph = [0.0] * 3 if others_zero else list(g.phi_hi)
+    pl[0] = value
+    return Grid(g.dim, (ctypes.c_int * 3)(*g.n), (ctypes.c_int * 3)(*bl), (ctypes.c_int * 3)(*g.bc_hi),
+                (ctypes.c_double * 3)(*pl), (ctypes.c_double * 3)(*ph))
+
+
+def poisson_solve_floating(m: Map, g: Grid, charge, Qw, phi0=None, phi1=None, rtol=1e-13):
+    """Solve with a floating conducting wall at the lower face of axis 0 that
+    holds charge Qw (Gauss' law: the flux of E through it equals Qw), by
+    superposition: phi = phi_0 + phi_w phi_1, phi_0 the solution with the wall
+    at 0, phi_1 the charge-free solution with the wall at 1 and every other
+    wall at 0, phi_w = (Qw - F(phi_0)) / F(phi_1).  Returns (phi, phi_w,
+    phi_0, phi_1); phi0/phi1 are initial guess and precomputed phi_1."""
+    g0 = _grid_with_wall(g, 0.0, False)
+    p0, _, _ = poisson_solve(m, g0, charge, phi0, rtol=rtol)
+    if phi1 is None:
+        g1 = _grid_with_wall(g, 1.0, True)
+        phi1, _, _ = poisson_solve(m, g1, np.zeros(ncells(g)), rtol=rtol)
+    F0 = wall_flux(m, g0, p0, 0.0)
+    F1 = wall_flux(m, g, phi1, 1.0)
+    pw = (Qw - F0) / F1
+    return p0 + pw * phi1, pw, p0, phi1
 
 
 def num_threads() -> int:
@@ -380,7 +429,9 @@ class OracleSim:
 
     species: list of dicts with q, m, w and arrays cell (int32), off (n,3),
     vel (n,3) in FP64.  deposit: 'fixed' (integer weights) or 'f64'.  mover:
-    'exact' (map inversion) or 'pc' (predictor-corrector, Eqs. step2-step4)."""
+    'exact' (map inversion) or 'pc' (predictor-corrector, Eqs. step2-step4).
+    A FLOATING lower face of axis 0 holds the charge of the particles absorbed
+    there (q w per particle, from the start) and floats at phi_wall."""
 
     def __init__(self, m: Map, g: Grid, species, shape=B2, dt=0.1, B=(0.0, 0.0, 0.0),
                  background=None, deposit="fixed", rtol=1e-13, ke_axes=3, mover="exact"):
@@ -395,6 +446,11 @@ class OracleSim:
         self.ke = None
         self.ke_axes = ke_axes  # velocity components in the kinetic-energy sum
         self.mover = push_pc if mover == "pc" else push
+        self.floating = g.bc_lo[0] == FLOATING
+        self.phi_wall = 0.0
+        self.wall_charge = 0.0
+        self.phi0 = None
+        self.phi1 = None
 
     def deposit(self):
         if self.mode == "fixed":
@@ -404,6 +460,12 @@ class OracleSim:
         self.charge = charge_from_Q(self.Q, self.sp, self.g.dim, self.S1, self.bg)
 
     def solve(self):
+        if self.floating:
+            self.wall_charge = sum(s["q"] * s["w"] * s.get("absorbed", 0) for s in self.sp)
+            self.phi, self.phi_wall, self.phi0, self.phi1 = poisson_solve_floating(
+                self.m, self.g, self.charge, self.wall_charge, self.phi0, self.phi1, rtol=self.rtol)
+            self.Ev = efield(self.m, _grid_with_wall(self.g, self.phi_wall, False), self.phi)
+            return
         self.phi, self.cg_iters, self.relres = poisson_solve(self.m, self.g, self.charge, self.phi,
                                                              rtol=self.rtol)
         self.Ev = efield(self.m, self.g, self.phi)
@@ -433,7 +495,7 @@ class OracleSim:
             inj = s.get("inject")
             if inj is not None:
                 c, o, v, _ = inject(self.m, self.g, inj["n0"], inj["vth"], s["w"], self.dt,
-                                    inj["seed"], self.step_count, inj["sid"])
+                                    inj["seed"], self.step_count, inj["sid"], drift=inj.get("drift", 0.0))
                 s["cell"] = np.concatenate([s["cell"], c])
                 s["off"] = np.concatenate([s["off"], o])
                 s["vel"] = np.concatenate([s["vel"], v])
@@ -446,4 +508,6 @@ class OracleSim:
         self.step_count += 1
 
     def field_energy(self):
-        return field_energy(self.charge, self.phi)
+        """1/2 sum charge phi, plus 1/2 Q_wall phi_wall with a floating wall."""
+        return field_energy(self.charge, self.phi) + (0.5 * self.wall_charge * self.phi_wall
+                                                      if self.floating else 0.0)

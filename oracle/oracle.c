@@ -785,6 +785,32 @@ int or_poisson_solve(const or_map* m, const or_grid* g, const double* charge, do
 /* average over the 2^(d-1) cell pairs around v of the difference across a.  */
 /* ------------------------------------------------------------------------ */
 
+/* Field flux through the lower face of axis 0 (a conducting wall at
+   potential phib): sum over the face cells c of 2 w_c (phib - phi_c), w_c the
+   face coefficient a^{00} dV / h_0^2 of the discrete operator -- the discrete
+   form of the surface integral of E . n, which Gauss' law sets equal to the
+   charge the wall holds. */
+double or_wall_flux(const or_map* m, const or_grid* g, const double* phi, double phib) {
+  int d = g->dim;
+  double h[3] = {1.0, 1.0, 1.0};
+  for (int a = 0; a < d; ++a) h[a] = 1.0 / g->n[a];
+  double dV = h[0] * h[1] * h[2];
+  double F = 0.0;
+  for (long c = 0; c < ncells(g); ++c) {
+    int idx[3];
+    cell_coords(g, c, idx);
+    if (idx[0] != 0) continue;
+    double xi[3];
+    for (int a = 0; a < 3; ++a) xi[a] = (a < d) ? (idx[a] + 0.5) * h[a] : 0.0;
+    xi[0] = 0.0;
+    double a9[3][3];
+    coef_at(m, xi, a9);
+    double w = a9[0][0] * dV / (h[0] * h[0]);
+    F += 2.0 * w * (phib - phi[c]);
+  }
+  return F;
+}
+
 static double phi_at(const or_grid* g, const double* phi, const int* idx_in) {
   int idx[3] = {idx_in[0], idx_in[1], idx_in[2]};
   for (int a = 0; a < g->dim; ++a) {
@@ -1176,11 +1202,39 @@ double or_face_area(const or_map* m) {
   return A;
 }
 
-long or_inject(const or_map* m, const or_grid* g, double n0, double vth, double w, double dt,
+/* Inward flux of a Maxwellian of thermal speed vth drifting with speed
+   u = s vth along the inward normal: n0 vth (phi(s) + s Phi(s)), phi and Phi
+   the standard normal density and distribution (s = 0: n0 vth / sqrt(2 pi)). */
+double or_drift_flux(double n0, double vth, double s) {
+  return n0 * vth * (exp(-0.5 * s * s) / sqrt(2.0 * OR_PI) + s * 0.5 * (1.0 + erf(s / sqrt(2.0))));
+}
+
+/* Inward normal speed of one injected particle (units of vth), distributed
+   as w exp(-(w - s)^2 / 2) on w > 0 (the flux-weighted drifting Maxwellian).
+   s = 0: w = sqrt(-2 ln U).  s > 0: rejection from the normal N(s + delta, 1),
+   delta = 1 / mode = 2 / (s + sqrt(s^2 + 4)); the ratio of target to proposal
+   is w exp((s - mu) w + const), so a proposal w > 0 is kept with probability
+   delta w exp(1 - delta w).  Attempt t uses the Philox block of counter
+   (step, k, species, 3 + t); 64 attempts at most (the last proposal is kept). */
+static double inject_normal_speed(double s, const uint32_t* key, uint32_t step, uint32_t k, uint32_t species,
+                                  double u_rayleigh) {
+  if (s <= 0.0) return sqrt(-2.0 * log(u_rayleigh));
+  double delta = 2.0 / (s + sqrt(s * s + 4.0)), mu = s + delta, w = mu;
+  for (uint32_t t = 0; t < 64; ++t) {
+    uint32_t c[4] = {step, k, species, 3u + t}, r[4];
+    or_philox4x32_10(c, key, r);
+    w = mu + sqrt(-2.0 * log(u01(r[0]))) * cos(2.0 * OR_PI * u01(r[1]));
+    if (w > 0.0 && u01(r[2]) < delta * w * exp(1.0 - delta * w)) return w;
+  }
+  return w > 0.0 ? w : mu;
+}
+
+long or_inject(const or_map* m, const or_grid* g, double n0, double vth, double drift, double w, double dt,
                uint32_t seed_lo, uint32_t seed_hi, uint32_t step, uint32_t species, long cap,
                int32_t* cell, double* off, double* vel, long* kidx, long* drawn) {
   int d = g->dim;
-  double lam = n0 * vth / sqrt(2.0 * OR_PI) * or_face_area(m) * dt / w;
+  const double s_drift = drift / vth;
+  double lam = or_drift_flux(n0, vth, s_drift) * or_face_area(m) * dt / w;
   uint32_t key[2] = {seed_lo, seed_hi};
   uint32_t c0[4] = {step, 0xFFFFFFFFu, species, 2u}, r[4];
   or_philox4x32_10(c0, key, r);
@@ -1193,7 +1247,7 @@ long or_inject(const or_map* m, const or_grid* g, double n0, double vth, double 
     or_philox4x32_10(ca, key, ra);
     or_philox4x32_10(cb, key, rb);
     double xi_f[3] = {1.0, u01(ra[0]), (d == 3) ? u01(rb[1]) : 0.0};
-    double vn = vth * sqrt(-2.0 * log(u01(ra[1])));
+    double vn = vth * inject_normal_speed(s_drift, key, step, (uint32_t)k, species, u01(ra[1]));
     double rho = sqrt(-2.0 * log(u01(ra[2])));
     double t1 = vth * rho * cos(2.0 * OR_PI * u01(ra[3]));
     double t2 = vth * rho * sin(2.0 * OR_PI * u01(ra[3]));
