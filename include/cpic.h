@@ -73,8 +73,12 @@ typedef enum {
 
 /* map kinds */
 enum { CPIC_MAP_IDENTITY = 0, CPIC_MAP_SINUSOIDAL = 1, CPIC_MAP_POLAR_LOG = 2 };
-/* field boundary conditions per axis side (ghost cells, Sec. II.B) */
-enum { CPIC_BC_PERIODIC = 0, CPIC_BC_DIRICHLET = 1, CPIC_BC_NEUMANN = 2 };
+/* field boundary conditions per axis side (ghost cells, Sec. II.B).
+   CPIC_BC_FLOATING (lower side of axis 0 only, every other axis periodic): a
+   conducting wall whose potential floats so that Gauss' law holds -- the
+   flux of E through it equals the charge of the particles it absorbed
+   (Sec. "Tests", charging of a conducting planar wall). */
+enum { CPIC_BC_PERIODIC = 0, CPIC_BC_DIRICHLET = 1, CPIC_BC_NEUMANN = 2, CPIC_BC_FLOATING = 3 };
 /* particle boundary conditions per axis side */
 enum { CPIC_PBC_PERIODIC = 0, CPIC_PBC_ABSORB = 1, CPIC_PBC_OUTFLOW = 2 };
 /* deposit shape: order-2 B-spline of Eq. b2 (default) or CIC */
@@ -163,14 +167,17 @@ typedef struct {
   double q, m, w;       /* charge, mass, macro-weight */
   int pbc_lo[3], pbc_hi[3];
   size_t capacity;      /* maximum particle count */
-  /* Maxwellian-at-rest flux injection through the upper face of axis 0 (the
-     outer wall; Sec. III, Test A/B injection): inject != 0 enables it, with
-     density inject_n0 and thermal speed inject_vth; the random stream is
+  /* Maxwellian flux injection through the upper face of axis 0 (the outer
+     wall; Sec. "Tests": plasma injected from the boundary opposite the
+     object): inject != 0 enables it, with density inject_n0, thermal speed
+     inject_vth and a drift of speed inject_drift (>= 0) along the inward
+     normal (the planar-wall test's ions; 0: at rest); the random stream is
      Philox4x32-10 keyed by seed.  Needs a bounded axis 0 and an orthogonal
      map (identity or polar-log). */
   int inject;
   double inject_n0, inject_vth;
   uint64_t seed;
+  double inject_drift;
 } cpic_species_desc;
 
 typedef struct {
@@ -192,6 +199,8 @@ typedef struct {
   int step_graphs;           /* step variants recorded as HIP graphs (graph mode) */
   long long sorts[8];        /* tile sorts per species so far (a species whose particles
                                 drift less than a cell between sorts is sorted less often) */
+  double phi_wall;           /* potential of a floating wall (CPIC_BC_FLOATING), else 0 */
+  double wall_charge;        /* charge it holds: sum of q w over the particles it absorbed */
 } cpic_diag;
 
 /* Create a simulation on the current HIP device.  hip_stream may be NULL

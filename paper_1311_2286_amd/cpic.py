@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcpic.so")
 
 MAP_IDENTITY, MAP_SINUSOIDAL, MAP_POLAR_LOG = 0, 1, 2
-BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2
+BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN, BC_FLOATING = 0, 1, 2, 3
 PBC_PERIODIC, PBC_ABSORB, PBC_OUTFLOW = 0, 1, 2
 SHAPE_B1, SHAPE_B2 = 1, 2
 FP32, FP64 = 0, 1
@@ -56,7 +56,7 @@ class SpeciesDesc(ctypes.Structure):
                 ("pbc_lo", ctypes.c_int * 3), ("pbc_hi", ctypes.c_int * 3),
                 ("capacity", ctypes.c_size_t), ("inject", ctypes.c_int),
                 ("inject_n0", ctypes.c_double), ("inject_vth", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("inject_drift", ctypes.c_double)]
 
 
 class Allocator(ctypes.Structure):
@@ -74,7 +74,8 @@ class Diag(ctypes.Structure):
                 ("qsum_hi", ctypes.c_uint64 * 8), ("newton_fallback", ctypes.c_longlong),
                 ("far_deposits", ctypes.c_longlong), ("newton_failed", ctypes.c_longlong),
                 ("injected", ctypes.c_longlong * 8), ("step_graphs", ctypes.c_int),
-                ("sorts", ctypes.c_longlong * 8)]
+                ("sorts", ctypes.c_longlong * 8), ("phi_wall", ctypes.c_double),
+                ("wall_charge", ctypes.c_double)]
 
 
 class CaseDesc(ctypes.Structure):
@@ -222,7 +223,7 @@ def make_species_desc(q, m, w, capacity=0, pbc_lo=(0, 0, 0), pbc_hi=(0, 0, 0), i
     return SpeciesDesc(q, m, w, (ctypes.c_int * 3)(*_pad(pbc_lo, 0)),
                        (ctypes.c_int * 3)(*_pad(pbc_hi, 0)), int(capacity),
                        int(inject is not None), float(inj.get("n0", 0.0)),
-                       float(inj.get("vth", 0.0)), int(seed))
+                       float(inj.get("vth", 0.0)), int(seed), float(inj.get("drift", 0.0)))
 
 
 class Sim:
@@ -285,12 +286,9 @@ class Sim:
     # ---------------------------------------------------------------- species
     def add_species(self, q, m, w, capacity, pbc_lo=(0, 0, 0), pbc_hi=(0, 0, 0), inject=None,
                     seed=0):
-        """inject: None or dict(n0=..., vth=...) for flux injection at the outer wall."""
-        pad = lambda t: tuple(t)[:3] + (0,) * (3 - len(tuple(t)[:3]))
-        inj = inject or {}
-        d = SpeciesDesc(q, m, w, (ctypes.c_int * 3)(*pad(pbc_lo)), (ctypes.c_int * 3)(*pad(pbc_hi)),
-                        int(capacity), int(inject is not None), float(inj.get("n0", 0.0)),
-                        float(inj.get("vth", 0.0)), int(seed))
+        """inject: None or dict(n0=..., vth=...[, drift=...]) for flux injection at the
+        outer wall (drift: speed along the inward normal)."""
+        d = make_species_desc(q, m, w, capacity, pbc_lo, pbc_hi, inject, seed)
         sid = ctypes.c_int()
         self._check(self.lib.cpic_add_species(self.h, ctypes.byref(d), ctypes.byref(sid)),
                     "add_species")

@@ -181,8 +181,14 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     bitsum += bits_for(grid->n[a]);
     bool plo = grid->bc_lo[a] == CPIC_BC_PERIODIC, phi = grid->bc_hi[a] == CPIC_BC_PERIODIC;
     if (plo != phi) return CPIC_E_ARG;
-    if (grid->bc_lo[a] < 0 || grid->bc_lo[a] > 2 || grid->bc_hi[a] < 0 || grid->bc_hi[a] > 2) return CPIC_E_ARG;
+    const int lo_max = a == 0 ? CPIC_BC_FLOATING : CPIC_BC_NEUMANN;
+    if (grid->bc_lo[a] < 0 || grid->bc_lo[a] > lo_max || grid->bc_hi[a] < 0 || grid->bc_hi[a] > CPIC_BC_NEUMANN)
+      return CPIC_E_ARG;
   }
+  const bool floating = grid->bc_lo[0] == CPIC_BC_FLOATING;
+  if (floating)
+    for (int a = 1; a < d; ++a)
+      if (grid->bc_lo[a] != CPIC_BC_PERIODIC) return CPIC_E_UNSUPPORTED;
   if (bitsum > 30 || ncells > (1ll << 30)) return CPIC_E_ARG;
   bool all_periodic = true;
   for (int a = 0; a < d; ++a) all_periodic = all_periodic && grid->bc_lo[a] == CPIC_BC_PERIODIC;
@@ -285,6 +291,12 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     G.phi_lo[a] = a < d ? grid->phi_lo[a] : 0.0;
     G.phi_hi[a] = a < d ? grid->phi_hi[a] : 0.0;
   }
+  if (floating) {
+    // the operator sees the floating wall as a Dirichlet wall at 0 (phi_0)
+    G.floating = 1;
+    G.bc_lo[0] = CPIC_BC_DIRICHLET;
+    G.phi_lo[0] = 0.0;
+  }
   int nl = 0;
   int n[3] = {g.n[0], g.n[1], g.n[2]};
   while (nl < 16) {
@@ -333,6 +345,12 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   }
   size_t cb = sizeof(double) * (size_t)ncells;
   G.bdir = (double*)A(cb);
+  if (floating) {
+    G.phi1 = (double*)A(cb);
+    G.bdir1 = (double*)A(cb);
+    G.phi_full = (double*)A(cb);
+    G.E1 = A(real_size(s) * ecomp(s) * (size_t)g.nverts);
+  }
   G.Jc = (double*)A(cb);
   G.charge = (double*)A(cb);
   G.background = grid->background ? (double*)A(cb) : nullptr;
@@ -413,7 +431,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     return CPIC_E_NOMEM;
   }
   memset(s->drift_host, 0, sizeof(unsigned) * 8);
-  if (compute_smoother_bounds(G, st) != 0 || setup_coarse_inverse(G, st) != 0) {
+  if (compute_smoother_bounds(G, st) != 0 || setup_coarse_inverse(G, st) != 0 || setup_floating_wall(G, st) != 0) {
     cpic_destroy(s);
     return CPIC_E_HIP;
   }
@@ -467,7 +485,9 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
   if (desc->inject) {
     if (s->g.periodic[0]) return fail(s, CPIC_E_ARG, "injection needs a bounded axis 0");
     if (s->g.kind == CPIC_MAP_SINUSOIDAL) return fail(s, CPIC_E_UNSUPPORTED, "injection needs an orthogonal map");
-    if (!(desc->inject_n0 > 0) || !(desc->inject_vth > 0)) return fail(s, CPIC_E_ARG, "bad injection parameters");
+    if (!(desc->inject_n0 > 0) || !(desc->inject_vth > 0) || !(desc->inject_drift >= 0) ||
+        !isfinite(desc->inject_drift))
+      return fail(s, CPIC_E_ARG, "bad injection parameters");
     // area of the outer face: 2 pi r_out (polar-log, per unit length) or the
     // product of the other box lengths; one-sided Maxwellian particle flux
     double A = 1.0;
@@ -475,7 +495,12 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
       A = 2.0 * M_PI * s->map.r_out;
     else
       for (int a = 1; a < d; ++a) A *= s->map.L[a];
-    lam = desc->inject_n0 * desc->inject_vth / sqrt(2.0 * M_PI) * A * s->grid.dt / desc->w;
+    // inward flux of a Maxwellian drifting inward at s thermal speeds:
+    // n0 vth (phi(s) + s Phi(s)), phi / Phi the standard normal density / CDF
+    const double sd = desc->inject_drift / desc->inject_vth;
+    const double flux = desc->inject_n0 * desc->inject_vth *
+                        (exp(-0.5 * sd * sd) / sqrt(2.0 * M_PI) + sd * 0.5 * (1.0 + erf(sd / sqrt(2.0))));
+    lam = flux * A * s->grid.dt / desc->w;
     if (lam > 1e8) return fail(s, CPIC_E_ARG, "injection rate too large");
   }
   Species S;
@@ -772,6 +797,7 @@ static void inject_pass(cpic_sim* s, long long step, unsigned count_mask = 0) {
     I.lam = S.inject_lam;
     I.kappa = s->kappa;
     I.vth = S.desc.inject_vth;
+    I.s_drift = S.desc.inject_drift / S.desc.inject_vth;
     I.dt = s->grid.dt;
     I.k0 = (uint32_t)(S.desc.seed & 0xFFFFFFFFu);
     I.k1 = (uint32_t)(S.desc.seed >> 32);
@@ -802,6 +828,16 @@ static void charge_pass(cpic_sim* s) {
 static void solve_pass(cpic_sim* s, int cycles = -1) {
   launch_rhs(s->G, s->stream);
   launch_mg_solve(s->G, s->grid.mg_rtol, cycles > 0 ? cycles : s->grid.mg_max_cycles, 2, 2, s->stream);
+  if (s->G.floating) {
+    WallCharge wc;
+    memset(&wc, 0, sizeof(wc));
+    wc.nsp = (int)s->sp.size();
+    for (size_t k = 0; k < s->sp.size(); ++k) {
+      wc.absorbed[k] = s->sp[k].counters;  // [0]: absorbed at the lower face of axis 0
+      wc.qw[k] = s->sp[k].desc.q * s->sp[k].desc.w;
+    }
+    launch_floating_wall(s->G, wc, s->stream);
+  }
   launch_gauge(s->G, s->stream);
 }
 
@@ -1032,7 +1068,7 @@ static void* field_ptr(cpic_sim* s, int which, int sid) {
   switch (which) {
     case CPIC_FIELD_Q: return (sid >= 0 && sid < (int)s->sp.size()) ? s->sp[sid].Q : nullptr;
     case CPIC_FIELD_CHARGE: return s->G.charge;
-    case CPIC_FIELD_PHI: return s->G.lev[0].phi;
+    case CPIC_FIELD_PHI: return s->G.floating ? s->G.phi_full : s->G.lev[0].phi;
     case CPIC_FIELD_JC: return s->G.Jc;
     case CPIC_FIELD_RHO: return s->G.lev[0].phi2;
     case CPIC_FIELD_BACKGROUND: return s->G.background;
@@ -1060,6 +1096,8 @@ extern "C" cpic_status cpic_set_field(cpic_sim* s, int which, int sid, const voi
   if (s->poisoned) return fail(s, CPIC_E_STATE, "simulation poisoned by an earlier device error");
   if (which != CPIC_FIELD_Q && which != CPIC_FIELD_CHARGE && which != CPIC_FIELD_PHI && which != CPIC_FIELD_EV)
     return fail(s, CPIC_E_ARG, "field is read-only");
+  if (which == CPIC_FIELD_PHI && s->G.floating)
+    return fail(s, CPIC_E_UNSUPPORTED, "the potential of a floating-wall problem follows from its solve");
   size_t need = cpic_field_bytes(s, which);
   void* dst = field_ptr(s, which, sid);
   if (!dst || need == 0) return fail(s, CPIC_E_ARG, "unknown field / species");
@@ -1083,10 +1121,11 @@ extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
   double ke = 0.0;
   HIPCHK(s, hipMemcpyAsync(&ke, s->ke, sizeof(double), hipMemcpyDeviceToHost, st));
   launch_field_energy(s->G, s->tmp_scalar, st);
-  double we = 0.0, sc[2] = {0, 0};
+  double we = 0.0, sc[2] = {0, 0}, wall[2] = {0, 0};
   int fl[2] = {0, 0};
   HIPCHK(s, hipMemcpyAsync(&we, s->tmp_scalar, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(s, hipMemcpyAsync(sc, s->G.scalars, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+  if (s->G.floating) HIPCHK(s, hipMemcpyAsync(wall, s->G.scalars + 10, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
   HIPCHK(s, hipMemcpyAsync(fl, s->G.mg_flag, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
   std::vector<unsigned long long> cnt(8 * s->sp.size());
   std::vector<int> ns(s->sp.size());
@@ -1103,7 +1142,10 @@ extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
   }
   HIPCHK(s, hipStreamSynchronize(st));
   out->kinetic = ke;
-  out->field_energy = 0.5 * we;
+  // with a floating wall, the energy of its charge 1/2 Q_w phi_w is included
+  out->field_energy = 0.5 * we + 0.5 * wall[1] * wall[0];
+  out->phi_wall = wall[0];
+  out->wall_charge = wall[1];
   out->mg_relres = sc[0] > 0 ? sqrt(sc[1] / sc[0]) : 0.0;
   out->mg_cycles = fl[1];
   for (size_t k = 0; k < s->sp.size() && k < 8; ++k) {

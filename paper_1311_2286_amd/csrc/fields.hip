@@ -625,6 +625,28 @@ __global__ __launch_bounds__(256) void gershgorin_kernel(LevelArgs a, double* ou
   out[c] = s / fabs(a.diag[c]);
 }
 
+// residual r = rhs - A phi (coalesced pass over the fine level)
+template <typename T>
+__global__ __launch_bounds__(256) void residual_kernel(LevelArgsT<T> a, const T* __restrict__ phi,
+                                                       const T* __restrict__ rhs, T* res, const int* flag) {
+  if (flag[0]) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= a.n[0] || j >= a.n[1]) return;
+  const int idx[3] = {i, j, k};
+  const int c = i + a.n[0] * (j + a.n[1] * k);
+  res[c] = rhs[c] - apply_A(a, phi, idx, c);
+}
+
+// Two restrictions.  Summing the 2^d children's residuals is the cheaper and,
+// on near-isotropic grids, the faster one; but with the bilinear prolongation
+// it makes the V-cycle non-symmetric, and flexible CG can then stall on
+// strongly anisotropic operators.  There the transpose of the prolongation is
+// used, which makes the V-cycle symmetric and keeps the conjugate-gradient
+// convergence guarantee (the choice is made once, at set-up).
+//
+// Summing restriction of the residual computed on the fly (small levels):
 template <typename T>
 __device__ inline T restrict_cell(const LevelArgsT<T>& fa, const T* __restrict__ phi, const T* __restrict__ rhs,
                                   const int* I) {
@@ -641,24 +663,10 @@ __device__ inline T restrict_cell(const LevelArgsT<T>& fa, const T* __restrict__
   return s;
 }
 
-// residual r = rhs - A phi (coalesced pass over the fine level)
+// summing restriction of a residual array (multi-workgroup levels)
 template <typename T>
-__global__ __launch_bounds__(256) void residual_kernel(LevelArgsT<T> a, const T* __restrict__ phi,
-                                                       const T* __restrict__ rhs, T* res, const int* flag) {
-  if (flag[0]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= a.n[0] || j >= a.n[1]) return;
-  const int idx[3] = {i, j, k};
-  const int c = i + a.n[0] * (j + a.n[1] * k);
-  res[c] = rhs[c] - apply_A(a, phi, idx, c);
-}
-
-// coarse rhs = sum of the residuals of the 2^d children; coarse phi = 0
-template <typename T>
-__global__ __launch_bounds__(256) void restrict_kernel(int dim, int nf0, int nf1, const T* __restrict__ res,
-                                                       int nc0, int nc1, T* crhs, T* cphi, const int* flag) {
+__global__ __launch_bounds__(256) void restrict_sum_kernel(int dim, int nf0, int nf1, const T* __restrict__ res,
+                                                           int nc0, int nc1, T* crhs, T* cphi, const int* flag) {
   if (flag[0]) return;
   const int I0 = blockIdx.x * blockDim.x + threadIdx.x, I1 = blockIdx.y * blockDim.y + threadIdx.y;
   const int I2 = blockIdx.z;
@@ -671,6 +679,72 @@ __global__ __launch_bounds__(256) void restrict_kernel(int dim, int nf0, int nf1
     s += res[fz] + res[fz + 1] + res[fz + nf0] + res[fz + nf0 + 1];
   }
   crhs[C] = s;
+  cphi[C] = (T)0;
+}
+
+// Transpose of the prolongation:  Per axis, coarse
+// cell I receives from fine cells 2I and 2I+1 with weight 3/4 and from 2I-1
+// and 2I+2 with weight 1/4; at a wall the prolongation's ghost (-e Dirichlet,
+// +e Neumann) folds the outer 1/4 back onto I.  Weights multiply over axes.
+template <typename T>
+__device__ inline int restrict_taps(const LevelArgsT<T>& fa, int ax, int I, int nc, int* f, T* w) {
+  const int nf = fa.n[ax];
+  if (ax >= fa.dim) {
+    f[0] = 0;
+    w[0] = (T)1;
+    return 1;
+  }
+  int k = 0;
+  T in_lo = (T)0.75, in_hi = (T)0.75;
+  if (I > 0 || fa.periodic[ax]) {
+    f[k] = wrapi(2 * I - 1, nf);
+    w[k++] = (T)0.25;
+  } else {
+    in_lo += fa.dir[ax][0] ? (T)-0.25 : (T)0.25;
+  }
+  if (I < nc - 1 || fa.periodic[ax]) {
+    f[k] = wrapi(2 * I + 2, nf);
+    w[k++] = (T)0.25;
+  } else {
+    in_hi += fa.dir[ax][1] ? (T)-0.25 : (T)0.25;
+  }
+  f[k] = 2 * I;
+  w[k++] = in_lo;
+  f[k] = 2 * I + 1;
+  w[k++] = in_hi;
+  return k;
+}
+
+template <typename T>
+__device__ inline T restrict_transpose(const LevelArgsT<T>& fa, const T* __restrict__ res, const int* cn,
+                                       const int* I) {
+  int fx[4], fy[4], fz[4];
+  T wx[4], wy[4], wz[4];
+  const int kx = restrict_taps(fa, 0, I[0], cn[0], fx, wx);
+  const int ky = restrict_taps(fa, 1, I[1], cn[1], fy, wy);
+  const int kz = restrict_taps(fa, 2, I[2], cn[2], fz, wz);
+  T s = (T)0;
+  for (int c = 0; c < kz; ++c)
+    for (int b = 0; b < ky; ++b) {
+      const T wyz = wy[b] * wz[c];
+      const int row = fa.n[0] * (fy[b] + fa.n[1] * fz[c]);
+      for (int a = 0; a < kx; ++a) s += wx[a] * wyz * res[fx[a] + row];
+    }
+  return s;
+}
+
+// coarse rhs = P^T (fine residual); coarse phi = 0
+template <typename T>
+__global__ __launch_bounds__(256) void restrict_kernel(LevelArgsT<T> fa, const T* __restrict__ res, int nc0, int nc1,
+                                                       int nc2, T* crhs, T* cphi, const int* flag) {
+  if (flag[0]) return;
+  const int I0 = blockIdx.x * blockDim.x + threadIdx.x, I1 = blockIdx.y * blockDim.y + threadIdx.y;
+  const int I2 = blockIdx.z;
+  if (I0 >= nc0 || I1 >= nc1) return;
+  const int cn[3] = {nc0, nc1, nc2};
+  const int I[3] = {I0, I1, I2};
+  const int C = I0 + nc0 * (I1 + nc1 * I2);
+  crhs[C] = restrict_transpose(fa, res, cn, I);
   cphi[C] = (T)0;
 }
 
@@ -743,6 +817,7 @@ constexpr int COARSE_LDS = 384;  // coarsest levels up to this many cells are so
 template <typename T>
 struct SmallLevels {
   int nl;
+  int transpose;  // restriction: transpose of the prolongation (else summing)
   const T* cinv;  // dense inverse of the coarsest operator (column-major), or null
   LevelArgsT<T> a[MAX_SMALL];
   T* phi[MAX_SMALL];
@@ -933,9 +1008,17 @@ __global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels<T> S, in
     }
     const LevelArgsT<T>& ca = S.a[l + 1];
     const int ncc = ca.n[0] * ca.n[1] * ca.n[2];
+    if (S.transpose) {
+      const int nc = a.n[0] * a.n[1] * a.n[2];
+      for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        int idx[3] = {c % a.n[0], (c / a.n[0]) % a.n[1], c / (a.n[0] * a.n[1])};
+        S.res[l][c] = S.rhs[l][c] - apply_A(a, S.phi[l], idx, c);
+      }
+      __syncthreads();
+    }
     for (int C = threadIdx.x; C < ncc; C += blockDim.x) {
       int I[3] = {C % ca.n[0], (C / ca.n[0]) % ca.n[1], C / (ca.n[0] * ca.n[1])};
-      S.rhs[l + 1][C] = restrict_cell(a, S.phi[l], S.rhs[l], I);
+      S.rhs[l + 1][C] = S.transpose ? restrict_transpose(a, S.res[l], ca.n, I) : restrict_cell(a, S.phi[l], S.rhs[l], I);
       S.phi[l + 1][C] = 0.0;
     }
     __syncthreads();
@@ -1161,7 +1244,40 @@ static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStre
   }
 }
 
+// Largest ratio of a cell's face coefficients (w_a = J g^aa dV / h_a^2) on
+// level 0: the operator's anisotropy.
+__global__ __launch_bounds__(256) void anisotropy_kernel(LevelArgs a, unsigned* out) {
+  const long long nc = (long long)a.n[0] * a.n[1] * a.n[2];
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  double wmax = 0.0, wmin = 1e300;
+  for (int ax = 0; ax < a.dim; ++ax) {
+    const double w = a.wf[ax][c];
+    wmax = fmax(wmax, w);
+    wmin = fmin(wmin, w);
+  }
+  if (wmin > 0.0) atomicMax(out, __float_as_uint((float)(wmax / wmin)));
+}
+
+// Upper spectral bound of D^-1 A on every level (once, at set-up), and the
+// restriction: the transpose of the prolongation on operators whose face
+// coefficients differ by more than ANISO_TRANSPOSE within a cell.
 int compute_smoother_bounds(GridCtx& G, hipStream_t st) {
+  {
+    const Level& L = G.lev[0];
+    unsigned* tmp = (unsigned*)G.mg_flag + 2;
+    launch_fill_u8(tmp, 0, sizeof(unsigned), st);
+    hipLaunchKernelGGL(anisotropy_kernel, dim3((unsigned)((L.ncells + 255) / 256)), dim3(256), 0, st, level_args(G, 0),
+                       tmp);
+    unsigned bits = 0;
+    if (hipMemcpyAsync(&bits, tmp, sizeof(bits), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return -1;
+    float ratio;
+    memcpy(&ratio, &bits, sizeof(ratio));
+    G.anisotropy = ratio;
+    G.restrict_transpose = ratio > ANISO_TRANSPOSE ? 1 : 0;
+  }
   for (int l = 0; l < G.nlev; ++l) {
     Level& L = G.lev[l];
     LevelArgs a = level_args(G, l);
@@ -1206,6 +1322,7 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
     memset(&S, 0, sizeof(S));
     S.nl = G.nlev - l;
     S.cinv = coarse_inverse<T>(G);
+    S.transpose = G.restrict_transpose;
     for (int k = 0; k < S.nl; ++k) {
       const LevelVec<T> v = level_vec<T>(G, l + k);
       S.a[k] = level_args_t<T>(G, l + k);
@@ -1231,8 +1348,12 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
   const LevelVec<T> cv = level_vec<T>(G, l + 1);
   hipLaunchKernelGGL(residual_kernel<T>, gr, BLOCK3, 0, st, a, (const T*)v.phi, (const T*)v.rhs, v.res,
                      (const int*)G.mg_flag);
-  hipLaunchKernelGGL(restrict_kernel<T>, grid3(C), BLOCK3, 0, st, G.g.dim, L.n[0], L.n[1], (const T*)v.res, C.n[0],
-                     C.n[1], cv.rhs, cv.phi, (const int*)G.mg_flag);
+  if (G.restrict_transpose)
+    hipLaunchKernelGGL(restrict_kernel<T>, grid3(C), BLOCK3, 0, st, a, (const T*)v.res, C.n[0], C.n[1], C.n[2],
+                       cv.rhs, cv.phi, (const int*)G.mg_flag);
+  else
+    hipLaunchKernelGGL(restrict_sum_kernel<T>, grid3(C), BLOCK3, 0, st, G.g.dim, L.n[0], L.n[1], (const T*)v.res,
+                       C.n[0], C.n[1], cv.rhs, cv.phi, (const int*)G.mg_flag);
   vcycle<T>(G, l + 1, nu1, nu2, nullptr, st);
   hipLaunchKernelGGL(prolong_kernel<T>, gr, BLOCK3, 0, st, a, v.phi, (const T*)cv.phi, C.n[0], C.n[1], C.n[2],
                      (const int*)G.mg_flag);
@@ -1446,6 +1567,12 @@ int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int 
   return max_cycles;
 }
 
+template <typename R>
+__global__ void axpy_scalar_kernel(long long n, const R* __restrict__ x, const double* __restrict__ a, R* y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += (R)(*a) * x[i];
+}
+
 // periodic problems: shift phi so that its J-weighted mean is zero
 void launch_gauge(const GridCtx& G, hipStream_t st) {
   if (!G.all_periodic) return;
@@ -1599,6 +1726,108 @@ void launch_efield(const GridCtx& G, hipStream_t st) {
     else
       hipLaunchKernelGGL((efield_kernel<2, float>), gr, bl, 0, st, g, bc, G.lev[0].phi, G.Kv, (float*)G.Ev);
   }
+  if (G.floating) {
+    // E of phi_0 (wall at 0) plus phi_w times E of phi_1
+    const long long n = (long long)g.nverts * (g.dim == 3 ? 4 : 2);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (G.fp64)
+      hipLaunchKernelGGL(axpy_scalar_kernel<double>, dim3(blocks), dim3(256), 0, st, n, (const double*)G.E1,
+                         (const double*)(G.scalars + 10), (double*)G.Ev);
+    else
+      hipLaunchKernelGGL(axpy_scalar_kernel<float>, dim3(blocks), dim3(256), 0, st, n, (const float*)G.E1,
+                         (const double*)(G.scalars + 10), (float*)G.Ev);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Floating conducting wall at the lower face of axis 0 (Sec. "Tests": the
+// planar wall charges with the particles it absorbs and Gauss' law holds
+// there).  By superposition phi = phi_0 + phi_w phi_1: phi_0 solves the
+// problem with the wall at 0, phi_1 the charge-free problem with the wall at
+// 1 and every other wall at 0, and phi_w = (Q_w - F(phi_0)) / F(phi_1), where
+// F is the discrete flux of E through the wall, sum over its cells of
+// 2 w_lo (phi_b - phi_c), and Q_w the absorbed charge.
+// ----------------------------------------------------------------------------
+__device__ inline double wall_flux_sum(const LevelArgs& a, const double* phi, double phib) {
+  const int nw = a.n[1] * a.n[2];
+  double f = 0.0;
+  for (int t = threadIdx.x; t < nw; t += blockDim.x) {
+    const int c = a.n[0] * t;  // cell (0, j, k)
+    f += 2.0 * a.wlo[0][c] * (phib - phi[c]);
+  }
+  return block_sum(f);
+}
+
+__global__ __launch_bounds__(1024) void wall_flux_kernel(LevelArgs a, const double* __restrict__ phi, double phib,
+                                                         double* out) {
+  const double f = wall_flux_sum(a, phi, phib);
+  if (threadIdx.x == 0) *out = f;
+}
+
+__global__ __launch_bounds__(1024) void floating_wall_kernel(LevelArgs a, const double* __restrict__ phi0,
+                                                             WallCharge wc, double* sc) {
+  const double F0 = wall_flux_sum(a, phi0, 0.0);
+  if (threadIdx.x == 0) {
+    double Q = 0.0;
+    for (int s = 0; s < wc.nsp; ++s) Q += wc.qw[s] * (double)wc.absorbed[s][0];
+    sc[10] = (Q - F0) / sc[12];
+    sc[11] = Q;
+  }
+}
+
+__global__ void phi_full_kernel(long long n, const double* __restrict__ phi0, const double* __restrict__ phi1,
+                                const double* __restrict__ sc, double* out) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) out[c] = phi0[c] + sc[10] * phi1[c];
+}
+
+void launch_floating_wall(const GridCtx& G, const WallCharge& wc, hipStream_t st) {
+  const Level& L = G.lev[0];
+  hipLaunchKernelGGL(floating_wall_kernel, dim3(1), dim3(1024), 0, st, level_args(G, 0), (const double*)L.phi, wc,
+                     G.scalars);
+  const unsigned blocks = (unsigned)((L.ncells + 255) / 256);
+  hipLaunchKernelGGL(phi_full_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.phi,
+                     (const double*)G.phi1, (const double*)G.scalars, G.phi_full);
+}
+
+// At set-up: phi_1, its vertex field and F(phi_1).
+int setup_floating_wall(GridCtx& G, hipStream_t st) {
+  if (!G.floating) return 0;
+  Level& L = G.lev[0];
+  const LevelArgs a = level_args(G, 0);
+  const size_t cb = sizeof(double) * (size_t)L.ncells;
+  const unsigned blocks = (unsigned)((L.ncells + 255) / 256);
+  // wall term of a unit potential on the floating wall alone (the diagonal
+  // written to the scratch vector aux is the operator's own)
+  hipLaunchKernelGGL(diag_kernel, dim3(blocks), dim3(256), 0, st, a, L.aux, G.bdir1, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0);
+  // charge-free solve: rhs = -bdir1 (phi_full serves as the zero charge)
+  launch_fill_u8(G.phi_full, 0, cb, st);
+  launch_fill_u8(L.phi, 0, cb, st);
+  GridCtx G1 = G;
+  G1.bdir = G.bdir1;
+  G1.charge = G.phi_full;
+  launch_rhs(G1, st);
+  launch_mg_solve(G1, 1e-13, 200, 2, 2, st);
+  if (hipMemcpyAsync(G.phi1, L.phi, cb, hipMemcpyDeviceToDevice, st) != hipSuccess) return -1;
+  launch_fill_u8(L.phi, 0, cb, st);
+  // its vertex field, with the wall at 1 and every other wall at 0
+  GridCtx G2 = G;
+  G2.floating = 0;
+  G2.lev[0].phi = G.phi1;
+  G2.Ev = G.E1;
+  for (int ax = 0; ax < 3; ++ax) G2.phi_lo[ax] = G2.phi_hi[ax] = 0.0;
+  G2.phi_lo[0] = 1.0;
+  launch_efield(G2, st);
+  hipLaunchKernelGGL(wall_flux_kernel, dim3(1), dim3(1024), 0, st, a, (const double*)G.phi1, 1.0, G.scalars + 12);
+  double F1 = 0.0;
+  if (hipMemcpyAsync(&F1, G.scalars + 12, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return -1;
+  // a unit wall potential drives a positive flux into a charge-free domain
+  if (!(F1 > 0.0)) return -1;
+  launch_fill_u8(G.phi_full, 0, cb, st);
+  launch_fill_u8(G.scalars + 10, 0, 2 * sizeof(double), st);
+  return 0;
 }
 
 __global__ void rho_kernel(long long nc, double dV, const double* charge, const double* Jc, double* rho) {
@@ -1613,7 +1842,7 @@ void launch_rho(const GridCtx& G, double* rho, hipStream_t st) {
 }
 
 void launch_field_energy(const GridCtx& G, double* out, hipStream_t st) {
-  reduce(G.charge, G.lev[0].phi, G.g.ncells, 0, G.partials, out, st);
+  reduce(G.charge, G.floating ? G.phi_full : G.lev[0].phi, G.g.ncells, 0, G.partials, out, st);
   // W_E = 1/2 sum charge phi: the factor is applied by the host
 }
 

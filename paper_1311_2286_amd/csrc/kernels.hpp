@@ -88,6 +88,7 @@ struct InjectLaunch {
   int shape;
   int S1;
   double lam, vth, dt, kappa;
+  double s_drift;  // inward drift of the injected Maxwellian in thermal speeds
   uint32_t k0, k1, step, species;
   unsigned long long* counters;
   int* count_out;
@@ -158,6 +159,15 @@ struct GridCtx {
   double* Kv;         // inverse Jacobian at vertices, d x d row-major (FP64)
   double* phi_prev;   // level-0 potential of the previous step
   // flexible conjugate gradients around the V-cycle (null when plain V-cycles)
+  // floating conducting wall at the lower face of axis 0 (the operator sees it
+  // as a Dirichlet wall at 0; the potential is phi_0 + phi_w phi_1)
+  int floating;
+  double* phi1;       // charge-free potential of the wall at 1, every other wall at 0
+  double* bdir1;      // its wall term
+  void* E1;           // its vertex field (particle precision)
+  double* phi_full;   // phi_0 + phi_w phi_1 (the potential); scalars [10] phi_w [11] Q_w [12] F(phi_1)
+  double anisotropy;      // largest ratio of a level-0 cell's face coefficients
+  int restrict_transpose; // restriction = transpose of the prolongation (else summing)
   double* cinv64;     // dense inverse of the coarsest operator (<= DENSE_MAX cells), or null
   float* cinv32;      // its FP32 copy (flexible-CG preconditioner)
   double* kr;         // residual b - A x
@@ -183,7 +193,18 @@ int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int 
 int compute_smoother_bounds(GridCtx& G, hipStream_t st);
 void launch_operator_f32(const GridCtx& G, hipStream_t st);
 int setup_coarse_inverse(GridCtx& G, hipStream_t st);
+int setup_floating_wall(GridCtx& G, hipStream_t st);
+// charge of a floating wall: sum over species of q w (particles it absorbed)
+struct WallCharge {
+  int nsp;
+  const unsigned long long* absorbed[8];
+  double qw[8];
+};
+void launch_floating_wall(const GridCtx& G, const WallCharge& wc, hipStream_t st);
 constexpr int DENSE_MAX = 640;  // coarsest levels up to this many cells are solved by a dense inverse
+// operators more anisotropic than this (face-coefficient ratio within a cell)
+// use the transpose of the prolongation as restriction
+constexpr double ANISO_TRANSPOSE = 4.0;
 void launch_extrapolate_guess(const GridCtx& G, int extrapolate, hipStream_t st);
 void launch_gauge(const GridCtx& G, hipStream_t st);
 void launch_vertex_metric(const GridCtx& G, hipStream_t st);

@@ -1024,6 +1024,7 @@ struct InjectArgs {
   int shape;
   int S1;
   double lam, vth, dt, kappa;
+  double s_drift;  // inward drift of the injected Maxwellian in thermal speeds (0: at rest)
   uint32_t k0, k1, step, species;
   unsigned long long* counters;  // [5] injected, [6] dropped for capacity, [7] next identifier
   int* count_out;
@@ -1036,6 +1037,29 @@ __device__ inline int injection_count(double lam, uint32_t k0, uint32_t k1, uint
   philox4x32_10(step, 0xFFFFFFFFu, species, 2u, k0, k1, r);
   double fl = floor(lam);
   return (int)fl + (unit_open(r[0]) < lam - fl ? 1 : 0);
+}
+
+// Inward normal speed (thermal units) of injected particle k: distributed as
+// w exp(-(w - s)^2 / 2) on w > 0 (flux-weighted drifting Maxwellian).  s = 0:
+// sqrt(-2 ln u).  s > 0: proposals from N(s + delta, 1), delta the inverse of
+// the distribution's mode 2 / (s + sqrt(s^2 + 4)), each kept with probability
+// delta w exp(1 - delta w) (the target over proposal ratio, scaled to a
+// maximum of 1); attempt t draws from counter (step, k, species, 3 + t), at
+// most 64 attempts.
+__device__ inline double inject_normal_speed(double s, uint32_t k0, uint32_t k1, uint32_t step, uint32_t k,
+                                             uint32_t species, double u_rayleigh) {
+  if (s <= 0.0) return sqrt(-2.0 * log(u_rayleigh));
+  const double delta = 2.0 / (s + sqrt(s * s + 4.0)), mu = s + delta;
+  double w = mu;
+  for (uint32_t t = 0; t < 64; ++t) {
+    uint32_t r[4];
+    philox4x32_10(step, k, species, 3u + t, k0, k1, r);
+    double sn, cs;
+    sincospi(2.0 * unit_open(r[1]), &sn, &cs);
+    w = mu + sqrt(-2.0 * log(unit_open(r[0]))) * cs;
+    if (w > 0.0 && unit_open(r[2]) < delta * w * exp(1.0 - delta * w)) return w;
+  }
+  return w > 0.0 ? w : mu;
 }
 
 template <int D, int MAP, typename R, bool FIXED>
@@ -1055,7 +1079,7 @@ __global__ __launch_bounds__(256) void inject_kernel(InjectArgs<R> a) {
   philox4x32_10(a.step, (uint32_t)k, a.species, 0u, a.k0, a.k1, ra);
   philox4x32_10(a.step, (uint32_t)k, a.species, 1u, a.k0, a.k1, rb);
   double xi_f[3] = {1.0, unit_open(ra[0]), (D == 3) ? unit_open(rb[1]) : 0.0};
-  double vn = a.vth * sqrt(-2.0 * log(unit_open(ra[1])));
+  double vn = a.vth * inject_normal_speed(a.s_drift, a.k0, a.k1, a.step, (uint32_t)k, a.species, unit_open(ra[1]));
   double rho = sqrt(-2.0 * log(unit_open(ra[2])));
   double sn, cs;
   sincospi(2.0 * unit_open(ra[3]), &sn, &cs);
@@ -1517,6 +1541,7 @@ static void launch_inject_t(const InjectLaunch& I, hipStream_t st) {
   a.lam = I.lam;
   a.kappa = I.kappa;
   a.vth = I.vth;
+  a.s_drift = I.s_drift;
   a.dt = I.dt;
   a.k0 = I.k0;
   a.k1 = I.k1;

@@ -28,7 +28,7 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 IDENTITY, SINUSOIDAL, POLAR_LOG = 0, 1, 2
-PERIODIC, DIRICHLET, NEUMANN = 0, 1, 2
+PERIODIC, DIRICHLET, NEUMANN, FLOATING = 0, 1, 2, 3
 B1, B2 = 1, 2
 FP32, FP64 = 0, 1
 BASE_SEED = 1311
@@ -44,6 +44,8 @@ class Species:
     vth: float
     ppc: float  # macro-particles per cell of this species (mean)
     count: Optional[int] = None  # overrides ppc * ncells
+    w: Optional[float] = None  # macro-weight, for species that start empty
+    drift: float = 0.0  # injection: drift along the inward normal, in thermal speeds
 
 
 @dataclasses.dataclass
@@ -83,7 +85,9 @@ class Case:
         return int(round(s.ppc * self.ncells))
 
     def weight(self, s: Species) -> float:
-        """Macro-weight w_s = n0 * volume / N_s (n0 = 1)."""
+        """Macro-weight w_s = n0 * volume / N_s (n0 = 1), unless given."""
+        if s.w is not None:
+            return s.w
         return self.volume() / self.count(s)
 
     def map_args(self):
@@ -145,6 +149,23 @@ def case5() -> Case:
     return Case("box3d_magnetized", 3, SINUSOIDAL, (256, 256, 128), L=(256.0, 256.0, 128.0),
                 eps=0.05, dt=0.1, B=(0.0, 0.0, 2.0),
                 species=[electrons(1.0, 16.0), ions(ppc=16.0)], delta=0.01, steps=100, case_id=5)
+
+
+def planar_wall(n=128, ppc=64.0, case_id=6):
+    """The paper's planar-wall test (Sec. "Tests", charging and shielding of a
+    conducting planar wall): a 20 x 5 Debye-length box on the identity map,
+    n x n cells, a floating absorbing wall at x = 0, phi = 0 and outflow at
+    x = L_x, periodic in y; initially empty, filled by flux injection at
+    x = L_x of electrons (Maxwellian at rest, v_th = 1) and ions (m_i/m_e = 1836,
+    T_i = T_e, drifting toward the wall at 2.1 ion thermal speeds), source
+    density 1; omega_pe dt = 0.05.  Macro-weight: ppc particles per cell per
+    species at unit density."""
+    L = (20.0, 5.0)
+    w = L[0] * L[1] / (ppc * n * n)
+    e = Species("e", -1.0, 1.0, 1.0, 0.0, count=0, w=w)
+    i = Species("i", 1.0, MASS_RATIO, 1.0 / math.sqrt(MASS_RATIO), 0.0, count=0, w=w, drift=2.1)
+    return Case("planar_wall_%d" % n, 2, IDENTITY, (n, n), L=L, bc_lo=(FLOATING, PERIODIC),
+                bc_hi=(DIRICHLET, PERIODIC), dt=0.05, species=[e, i], steps=24000, case_id=case_id)
 
 
 def small_case(dim=2, map_kind=SINUSOIDAL, n=None, eps=None, ppc=8.0, two_species=True,

@@ -24,7 +24,7 @@ def gpu_sim(case, precision=0, shape=2, track_ids=True, mg_rtol=1e-12, mg_max_cy
         p = W.generate_species(case, sid, dtype=dt, count=count)
         cap = max(1, int(p["cell"].size * capacity_factor))
         sim.add_species(s.q, s.m, case.weight(s), cap, pbc_lo=pbc_lo, pbc_hi=pbc_hi,
-                        inject=dict(n0=1.0, vth=s.vth) if inject else None, seed=seed)
+                        inject=dict(n0=1.0, vth=s.vth, drift=s.drift * s.vth) if inject else None, seed=seed)
         sim.set_particles(sid, p["cell"], p["off"], p["vel"], p["id"])
         parts.append(p)
     return sim, parts
