@@ -334,6 +334,54 @@ def extra_workload(name, shape_name, precision, steps, warmup, sort_every, mg_rt
     return out
 
 
+def field_solve_mms(sizes=(1024, 2048, 4096), rtol=1e-10, reps=3):
+    """The field solve alone on the paper's manufactured-solution test (spherical
+    r-z map, Omega = r, Eq. mms; Table t1's grids and tolerance): cycles, time
+    per solve from a zero initial guess and the RMS error against Eq. mms.
+    Each grid is solved once to learn its cycle count, then timed with two
+    cycles of slack, as the time step launches its solves."""
+    from paper_1311_2286_amd import cpic as C
+    from paper_1311_2286_amd import workloads as W
+    import torch
+    out = []
+    for N in sizes:
+        charge, exact = W.spherical_mms_input(N)
+        zeros = np.zeros(N * N)
+        row = {"grid": "%d^2" % N}
+        cap = 60
+        for attempt in range(2):
+            sim = C.Sim(W.SPHERICAL_RZ, 2, (N, N), r_in=W.MMS_R1, r_out=W.MMS_R2, omega=1,
+                        bc_lo=(C.BC_DIRICHLET, C.BC_NEUMANN), bc_hi=(C.BC_DIRICHLET, C.BC_NEUMANN),
+                        precision=C.FP64, mg_rtol=rtol, mg_max_cycles=cap)
+            try:
+                sim.set_field(C.FIELD_CHARGE, charge)
+                times = []
+                for r in range(reps if attempt else 1):
+                    sim.set_field(C.FIELD_PHI, zeros)
+                    sim.sync()
+                    t0 = time.perf_counter()
+                    sim.stage(C.STAGE_SOLVE)
+                    sim.sync()
+                    times.append(time.perf_counter() - t0)
+                d = sim.diag()
+                phi = sim.get_field(C.FIELD_PHI)
+            finally:
+                sim.close()
+            if attempt == 0:
+                cap = d.mg_cycles + 2
+                continue
+            row.update({"cycles": d.mg_cycles, "relres": d.mg_relres, "launched_cycles": cap,
+                        "solve_ms": 1e3 * float(np.median(times)),
+                        "l2_error": float(np.sqrt(np.mean((phi - exact) ** 2)))})
+        del charge, exact, zeros
+        torch.cuda.empty_cache()
+        log("mms", json.dumps(row))
+        out.append(row)
+    return {"workload": "field solve of the spherical r-z manufactured solution (Omega = r), FCG with "
+                        "one FP32 V-cycle per iteration, rtol %g, from a zero initial guess" % rtol,
+            "grids": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -418,6 +466,10 @@ def main():
                                             args.mg_cycles, mover)
             except Exception as e:  # reported, never fatal for the headline line
                 extra[key] = {"error": repr(e)}
+        try:
+            extra["field_solve_mms"] = field_solve_mms()
+        except Exception as e:
+            extra["field_solve_mms"] = {"error": repr(e)}
     n_p = r32["pushes"]
     out = {
         "metric": METRIC,

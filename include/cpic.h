@@ -71,8 +71,13 @@ typedef enum {
   CPIC_E_PENDING = 1       /* serving: the work is not finished yet (not an error) */
 } cpic_status;
 
-/* map kinds */
-enum { CPIC_MAP_IDENTITY = 0, CPIC_MAP_SINUSOIDAL = 1, CPIC_MAP_POLAR_LOG = 2 };
+/* map kinds.  CPIC_MAP_SPHERICAL_RZ (2D): the meridian half plane of a
+   spherical shell in cylindrical coordinates, r = rho sin(pi (1 - eta)),
+   z = rho cos(pi (1 - eta)), rho = r_in + (r_out - r_in) xi (Sec. "Field
+   solver", Eqs. r and z); with cpic_map_desc.omega = 1 it is the paper's
+   manufactured-solution test of the solver.  It serves the field solve only:
+   cpic_add_species returns CPIC_E_UNSUPPORTED on it. */
+enum { CPIC_MAP_IDENTITY = 0, CPIC_MAP_SINUSOIDAL = 1, CPIC_MAP_POLAR_LOG = 2, CPIC_MAP_SPHERICAL_RZ = 3 };
 /* field boundary conditions per axis side (ghost cells, Sec. II.B).
    CPIC_BC_FLOATING (lower side of axis 0 only, every other axis periodic): a
    conducting wall whose potential floats so that Gauss' law holds -- the
@@ -140,6 +145,13 @@ typedef struct {
   double eps;     /* sinusoidal amplitude, relative to the box */
   double r_in;    /* polar-log inner radius */
   double r_out;   /* polar-log outer radius */
+  /* geometric factor Omega of the Poisson operator, d_i(Omega J g^ij d_j phi)
+     = -Omega J rho (Sec. "Field solver", Eq. poiscurv): 0 -> Omega = 1;
+     1 -> Omega = x^1, the radius of an axisymmetric r-z plane (2D identity or
+     spherical r-z map with a bounded axis 0, else CPIC_E_UNSUPPORTED).  With
+     Omega = x^1, CPIC_FIELD_CHARGE is the right side Omega J rho dV of the
+     solve, and the map serves the field solve only (no species). */
+  int omega;
 } cpic_map_desc;
 
 typedef struct {

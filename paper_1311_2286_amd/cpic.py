@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcpic.so")
 
-MAP_IDENTITY, MAP_SINUSOIDAL, MAP_POLAR_LOG = 0, 1, 2
+MAP_IDENTITY, MAP_SINUSOIDAL, MAP_POLAR_LOG, MAP_SPHERICAL_RZ = 0, 1, 2, 3
 BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN, BC_FLOATING = 0, 1, 2, 3
 PBC_PERIODIC, PBC_ABSORB, PBC_OUTFLOW = 0, 1, 2
 SHAPE_B1, SHAPE_B2 = 1, 2
@@ -38,7 +38,8 @@ E_PENDING = 1
 
 class MapDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("dim", ctypes.c_int), ("L", ctypes.c_double * 3),
-                ("eps", ctypes.c_double), ("r_in", ctypes.c_double), ("r_out", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
+                ("omega", ctypes.c_int)]
 
 
 class GridDesc(ctypes.Structure):
@@ -202,8 +203,8 @@ def _pad(t, v):
     return tuple(t)[:3] + (v,) * (3 - len(tuple(t)[:3]))
 
 
-def make_map_desc(map_kind, dim, L=(1.0, 1.0, 1.0), eps=0.0, r_in=1.0, r_out=2.0):
-    return MapDesc(map_kind, dim, (ctypes.c_double * 3)(*_pad(L, 1.0)), eps, r_in, r_out)
+def make_map_desc(map_kind, dim, L=(1.0, 1.0, 1.0), eps=0.0, r_in=1.0, r_out=2.0, omega=0):
+    return MapDesc(map_kind, dim, (ctypes.c_double * 3)(*_pad(L, 1.0)), eps, r_in, r_out, int(omega))
 
 
 def make_grid_desc(n, bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), phi_lo=(0.0, 0.0, 0.0),
@@ -233,14 +234,14 @@ class Sim:
                  bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), phi_lo=(0.0, 0.0, 0.0), phi_hi=(0.0, 0.0, 0.0),
                  shape=SHAPE_B2, precision=FP32, dt=0.1, B0=(0.0, 0.0, 0.0), background=False,
                  background_n0=1.0, mg_rtol=1e-10, mg_max_cycles=30, sort_every=1, track_ids=False,
-                 stream=None, torch_alloc=True, mg_method=0, mover=0):
+                 stream=None, torch_alloc=True, mg_method=0, mover=0, omega=0):
         self.lib = load()
         pad = lambda t, v: tuple(t)[:3] + (v,) * (3 - len(tuple(t)[:3]))
         self.dim = dim
         self.n = tuple(n)[:dim]
         self.precision = precision
         self.rdtype = np.float64 if precision == FP64 else np.float32
-        m = MapDesc(map_kind, dim, (ctypes.c_double * 3)(*pad(L, 1.0)), eps, r_in, r_out)
+        m = MapDesc(map_kind, dim, (ctypes.c_double * 3)(*pad(L, 1.0)), eps, r_in, r_out, int(omega))
         g = GridDesc((ctypes.c_int * 3)(*pad(n, 1)), (ctypes.c_int * 3)(*pad(bc_lo, 0)),
                      (ctypes.c_int * 3)(*pad(bc_hi, 0)), (ctypes.c_double * 3)(*pad(phi_lo, 0.0)),
                      (ctypes.c_double * 3)(*pad(phi_hi, 0.0)), shape, precision, dt,

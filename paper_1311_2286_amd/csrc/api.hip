@@ -161,10 +161,16 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   *out = nullptr;
   const int d = map->dim;
   if (d != 2 && d != 3) return CPIC_E_ARG;
-  if (map->kind < CPIC_MAP_IDENTITY || map->kind > CPIC_MAP_POLAR_LOG) return CPIC_E_ARG;
-  if (map->kind == CPIC_MAP_POLAR_LOG && (d != 2 || !(map->r_in > 0) || !(map->r_out > map->r_in)))
-    return CPIC_E_ARG;
-  if (map->kind != CPIC_MAP_POLAR_LOG)
+  if (map->kind < CPIC_MAP_IDENTITY || map->kind > CPIC_MAP_SPHERICAL_RZ) return CPIC_E_ARG;
+  const bool radial = map->kind == CPIC_MAP_POLAR_LOG || map->kind == CPIC_MAP_SPHERICAL_RZ;
+  if (radial && (d != 2 || !(map->r_in > 0) || !(map->r_out > map->r_in))) return CPIC_E_ARG;
+  // Omega = x^1 is the radius of an r-z plane: it must stay >= 0, which holds
+  // on the identity map (bounded axis 0) and the spherical r-z map
+  if (map->omega != 0 && map->omega != 1) return CPIC_E_ARG;
+  if (map->omega && (d != 2 || (map->kind != CPIC_MAP_IDENTITY && map->kind != CPIC_MAP_SPHERICAL_RZ) ||
+                     grid->bc_lo[0] == CPIC_BC_PERIODIC))
+    return CPIC_E_UNSUPPORTED;
+  if (!radial)
     for (int a = 0; a < d; ++a)
       if (!(map->L[a] > 0)) return CPIC_E_ARG;
   if (map->kind == CPIC_MAP_SINUSOIDAL) {
@@ -273,6 +279,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   g.r_in = map->r_in;
   g.r_out = map->r_out;
   g.lnR = map->kind == CPIC_MAP_POLAR_LOG ? log(map->r_out / map->r_in) : 0.0;
+  g.omega = map->omega;
   for (int a = 0; a < 3; ++a) {
     g.ecell[a] = g.eps * g.n[a];
     g.dxc[a] = g.L[a] / g.n[a];
@@ -471,6 +478,8 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
   if (!(desc->m != 0) || !(desc->w > 0) || !isfinite(desc->q) || desc->capacity == 0 ||
       desc->capacity > (size_t)INT32_MAX / 2)
     return fail(s, CPIC_E_ARG, "bad species descriptor");
+  if (s->g.kind == CPIC_MAP_SPHERICAL_RZ || s->g.omega)
+    return fail(s, CPIC_E_UNSUPPORTED, "the spherical r-z map and Omega = r serve the field solve only");
   const int d = s->g.dim;
   for (int a = 0; a < d; ++a) {
     bool per = s->g.periodic[a];

@@ -11,10 +11,12 @@
 
 namespace cpic {
 
-enum { MAP_IDENTITY = 0, MAP_SINUSOIDAL = 1, MAP_POLAR_LOG = 2 };
+// MAP_SPHERICAL_RZ (the r-z half plane of a spherical shell) serves the field
+// solve only: no particle kernel is built for it
+enum { MAP_IDENTITY = 0, MAP_SINUSOIDAL = 1, MAP_POLAR_LOG = 2, MAP_SPHERICAL_RZ = 3 };
 // particle-kernel variant that moves with the tabulated inverse Jacobian (the
 // predictor-corrector update), whatever the map
-constexpr int MAP_TABLE_PC = 3;
+constexpr int MAP_TABLE_PC = 4;
 enum { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_NEUMANN = 2 };
 enum { PBC_PERIODIC = 0, PBC_ABSORB = 1, PBC_OUTFLOW = 2 };
 enum { SHAPE_B1 = 1, SHAPE_B2 = 2 };
@@ -50,6 +52,7 @@ struct Geo {
   double L[3];
   double eps;
   double r_in, r_out, lnR;
+  int omega;       // 1: geometric factor Omega = x^1 (radius of an axisymmetric r-z plane), else 1
   double ecell[3]; // eps * n_a: map perturbation in cells of axis a
   double dxc[3];   // L_a / n_a: undistorted cell size
 };
@@ -361,6 +364,20 @@ __device__ inline void map_jacobi(const Geo& g, const double* xi, double j[3][3]
     }
     if (x)
       for (int a = 0; a < d; ++a) x[a] = g.L[a] * (xi[a] + g.eps * P);
+  } else if (g.kind == MAP_SPHERICAL_RZ) {
+    // (r, z) = rho (sin t, cos t), rho = r_in + (r_out - r_in) xi^1,
+    // t = pi (1 - xi^2) (Sec. "Field solver", Eqs. r and z)
+    const double D = g.r_out - g.r_in, rho = g.r_in + D * xi[0];
+    double st, ct;
+    sincospi(1.0 - xi[1], &st, &ct);
+    j[0][0] = D * st;
+    j[0][1] = -3.141592653589793 * rho * ct;
+    j[1][0] = D * ct;
+    j[1][1] = 3.141592653589793 * rho * st;
+    if (x) {
+      x[0] = rho * st;
+      x[1] = rho * ct;
+    }
   } else {  // polar-log
     double r = g.r_in * exp(xi[0] * g.lnR);
     double st, ct;

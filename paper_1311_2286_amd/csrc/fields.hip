@@ -61,14 +61,15 @@ __device__ inline void inv3(int d, const double j[3][3], double k[3][3], double&
   k[2][2] = (j[0][0] * j[1][1] - j[0][1] * j[1][0]) / J;
 }
 
-// a^{pq} = J g^{pq}, g^{pq} = k^{p r} k^{q r} (Eqs. gcon, poiscurv; Omega = 1)
+// a^{pq} = Omega J g^{pq}, g^{pq} = k^{p r} k^{q r} (Eqs. gcon, poiscurv), with
+// the geometric factor Omega = x^1 when g.omega is set, else 1
 __device__ inline double coef_pq(const Geo& g, const double* xi, int p, int q) {
-  double j[3][3], k[3][3], J;
-  map_jacobi(g, xi, j, nullptr);
+  double j[3][3], k[3][3], J, x[3];
+  map_jacobi(g, xi, j, x);
   inv3(g.dim, j, k, J);
   double s = 0.0;
   for (int r = 0; r < g.dim; ++r) s += k[p][r] * k[q][r];
-  return J * s;
+  return (g.omega ? x[0] : 1.0) * J * s;
 }
 
 // ----------------------------------------------------------------------------

@@ -27,7 +27,7 @@ from typing import List, Optional, Tuple
 
 import numpy as np
 
-IDENTITY, SINUSOIDAL, POLAR_LOG = 0, 1, 2
+IDENTITY, SINUSOIDAL, POLAR_LOG = 0, 1, 2  # map kinds (SPHERICAL_RZ below)
 PERIODIC, DIRICHLET, NEUMANN, FLOATING = 0, 1, 2, 3
 B1, B2 = 1, 2
 FP32, FP64 = 0, 1
@@ -346,3 +346,45 @@ def synthetic_ev(case: Case, nverts: int, dtype=np.float32, seed: int = BASE_SEE
     if case.dim == 2:
         E[:, 2] = 0
     return E
+
+
+# ----------------------------------------------------------------------------
+# Manufactured-solution input of the field solver (Sec. "Field solver",
+# Eqs. r, z, mms; Table t1)
+# ----------------------------------------------------------------------------
+SPHERICAL_RZ = 3
+MMS_R1, MMS_R2 = 1.0, 10.0
+
+
+def spherical_mms_input(n0: int, n1: Optional[int] = None):
+    """Right side and exact potential of the paper's spherical r-z test.
+
+    The map is (r, z) = rho (sin t, cos t), rho = r_1 + (r_2 - r_1) xi,
+    t = pi (1 - eta), r_1 = 1, r_2 = 10, with the geometric factor Omega = r;
+    the potential is phi = sin((r_2 - r_1)^2 xi (1 - xi)) cos(pi eta^2).  The
+    right side per cell is Omega J (-lap phi) / (n0 n1) at the cell centre,
+    lap the axisymmetric spherical Laplacian written out in (rho, t), and
+    J = pi (r_2 - r_1) rho the map's Jacobian (closed form).  Returns
+    (charge, exact phi), cell index i + n0 j."""
+    n1 = n0 if n1 is None else n1
+    D = MMS_R2 - MMS_R1
+    A = D * D
+    u = (np.arange(n0) + 0.5) / n0
+    v = (np.arange(n1) + 0.5) / n1
+    u, v = np.meshgrid(u, v, indexing="xy")  # [j, i]: i fastest when raveled
+    u, v = u.ravel(), v.ravel()
+    arg = A * u * (1 - u)
+    sa, ca = np.sin(arg), np.cos(arg)
+    ce, se = np.cos(np.pi * v * v), np.sin(np.pi * v * v)
+    phi = sa * ce
+    rho = MMS_R1 + D * u
+    t = np.pi * (1 - v)
+    # derivatives in rho and t: d/drho = (1/D) d/dxi, d/dt = -(1/pi) d/deta
+    p_r = A * (1 - 2 * u) * ca * ce / D
+    p_rr = (-2 * A * ca - A * A * (1 - 2 * u) ** 2 * sa) * ce / (D * D)
+    p_t = sa * se * 2 * np.pi * v / np.pi
+    p_tt = -sa * (ce * (2 * np.pi * v) ** 2 + se * 2 * np.pi) / (np.pi * np.pi)
+    lap = p_rr + 2 * p_r / rho + (p_tt + np.cos(t) / np.sin(t) * p_t) / (rho * rho)
+    omega = rho * np.sin(t)
+    J = np.pi * D * rho
+    return -lap * omega * J / (n0 * n1), phi

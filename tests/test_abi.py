@@ -56,6 +56,18 @@ def test_status_strings_and_argument_validation_without_gpu():
     g.bc_lo[0] = g.bc_hi[0] = 0
     g.n[2] = 8
     assert L.cpic_create(ctypes.byref(m3), ctypes.byref(g), None, None, ctypes.byref(h)) == -2
+    # the spherical r-z map: 2D, 0 < r_in < r_out; Omega = x^1 needs a bounded
+    # axis 0 and a map on which x^1 >= 0 (identity or spherical r-z)
+    g.n[2] = 0
+    sph = cpic.MapDesc(cpic.MAP_SPHERICAL_RZ, 2, (ctypes.c_double * 3)(1, 1, 1), 0.0, 2.0, 1.0, 1)
+    assert L.cpic_create(ctypes.byref(sph), ctypes.byref(g), None, None, ctypes.byref(h)) == -1
+    sph.r_in, sph.r_out = 1.0, 10.0
+    assert L.cpic_create(ctypes.byref(sph), ctypes.byref(g), None, None, ctypes.byref(h)) == -9  # periodic axis 0
+    sph.omega = 2
+    assert L.cpic_create(ctypes.byref(sph), ctypes.byref(g), None, None, ctypes.byref(h)) == -1
+    m.omega = 1
+    g.bc_lo[0] = g.bc_hi[0] = cpic.BC_DIRICHLET
+    assert L.cpic_create(ctypes.byref(m), ctypes.byref(g), None, None, ctypes.byref(h)) == -9  # sinusoidal
 
 
 def test_python_structures_match_the_header_layout(tmp_path):

@@ -4,7 +4,8 @@ field solver) and the vertex electric field.
 Pins: operator symmetry / null space, an FFT solve of the undistorted periodic
 problem, manufactured solutions with second-order convergence (error ratio
 -> 4 per doubling, Table I), the paper's own spherical r-z manufactured
-solution (Eqs. r, z, mms with Omega = r), and the exact vacuum solution of the
+solution (Eqs. r, z, mms with Omega = r) against Table t1's printed L2 errors
+and error ratios, and the exact vacuum solution of the
 cylindrical probe (phi linear in xi between the walls)."""
 import math
 
@@ -13,17 +14,7 @@ import pytest
 
 import oracle as O
 from _golden import paper_value
-
-
-def cell_centres(n):
-    d = len(n)
-    axes = [(np.arange(n[a]) + 0.5) / n[a] for a in range(d)]
-    G = np.meshgrid(*axes, indexing="ij")
-    # linear index i + n0 (j + n1 k): flatten in Fortran order
-    xi = np.zeros((int(np.prod(n)), 3))
-    for a in range(d):
-        xi[:, a] = G[a].ravel(order="F")
-    return xi
+from _mms import cell_centres, spherical_mms
 
 
 def dense(g, A):
@@ -123,36 +114,7 @@ def _polar_case(N):
 
 
 def _paper_mms_case(N):
-    # Eqs. (r), (z): r = rho sin(pi (1 - eta)), z = rho cos(pi (1 - eta)),
-    # rho = r1 + (r2 - r1) xi; Omega = r; Eq. (mms):
-    # phi = sin((r2 - r1)^2 xi (1 - xi)) cos(pi eta^2).  Boundary values:
-    # phi = 0 at xi = 0, 1; d phi / d eta = 0 at eta = 0, 1 (the symmetry axis).
-    r1, r2 = 1.0, 10.0
-    D = r2 - r1
-    A = D * D
-    m = O.make_map(O.SPHERICAL_RZ, 2, r_in=r1, r_out=r2, omega=1)
-    g = O.make_grid((N, N), bc_lo=(O.DIRICHLET, O.NEUMANN), bc_hi=(O.DIRICHLET, O.NEUMANN))
-    xi = cell_centres((N, N))
-    x, _, _, J = O.map_eval(m, xi)
-    u, v = xi[:, 0], xi[:, 1]
-    arg = A * u * (1 - u)
-    ce = np.cos(np.pi * v ** 2)
-    se = np.sin(np.pi * v ** 2)
-    phi = np.sin(arg) * ce
-    p_u = A * (1 - 2 * u) * np.cos(arg) * ce
-    p_uu = (-2 * A * np.cos(arg) - A * A * (1 - 2 * u) ** 2 * np.sin(arg)) * ce
-    p_v = -np.sin(arg) * se * 2 * np.pi * v
-    p_vv = -np.sin(arg) * (ce * (2 * np.pi * v) ** 2 + se * 2 * np.pi)
-    rho_s = r1 + D * u
-    th = np.pi * (1 - v)
-    # spherical Laplacian of phi(rho, theta), axisymmetric
-    p_r = p_u / D
-    p_rr = p_uu / D ** 2
-    p_t = -p_v / np.pi
-    p_tt = p_vv / np.pi ** 2
-    lap = p_rr + 2 * p_r / rho_s + (p_tt + np.cos(th) / np.sin(th) * p_t) / rho_s ** 2
-    Om = x[:, 0]
-    charge = -lap * Om * J / N ** 2
+    m, g, phi, charge = spherical_mms(N)
     return m, g, phi, charge
 
 
@@ -164,12 +126,17 @@ def test_manufactured_solutions_second_order(make_case, sizes):
     assert abs(ratios[-1] - 4.0) < 0.25, (errs, ratios)
 
 
-def test_paper_spherical_mms_ratio_tends_to_four():
-    # Table t1's error ratios (tests/golden): second order, 4.0 from 256^2 on;
-    # the absolute L2 values depend on a norm the paper does not state (parity
-    # unpinned).  Here 32^2 .. 256^2: the ratio of the last refinement matches
-    # the paper's 256^2 value, the one before its 128^2 value.
-    errs = _mms_errors(_paper_mms_case, (32, 64, 128, 256))
+def test_paper_spherical_mms_matches_table_t1():
+    # Table t1 (tests/golden): the L2 errors, read as the RMS over the cell
+    # centres, within 10 % of the printed values (printed to two digits; a
+    # dropped or mis-signed term of the operator or of the right side moves
+    # them by far more), and the error ratios: second order, 4.0 from 256^2
+    # on.  16^2 .. 256^2 here; the GPU test continues to 2048^2.
+    sizes = (16, 32, 64, 128, 256)
+    errs = _mms_errors(_paper_mms_case, sizes)
+    for N, e in zip(sizes, errs):
+        ref = paper_value("mms_l2_%d" % N)
+        assert abs(e - ref) < 0.1 * ref, (N, e, ref)
     ratios = errs[:-1] / errs[1:]
     assert abs(ratios[-1] - paper_value("mms_error_ratio_256")) < 0.15, (errs, ratios)
     assert abs(ratios[-2] - paper_value("mms_error_ratio_128")) < 0.3, (errs, ratios)
@@ -231,3 +198,15 @@ def test_efield_linear_potential_exact_on_distorted_map():
     Ev = O.efield(m, g, phi).reshape(11, 13, 3)
     assert np.allclose(Ev[1:-1, 1:-1, 0], -3.0, atol=1e-12)
     assert np.allclose(Ev[1:-1, 1:-1, 1], 0.0, atol=1e-12)
+
+
+def test_benchmark_mms_input_is_the_oracle_case():
+    # the benchmark builds the right side of the same test with the map's
+    # closed-form Jacobian J = pi (r_2 - r_1) rho; the oracle case takes x and J
+    # from the oracle's map evaluation
+    from paper_1311_2286_amd import workloads as W
+    for n in ((48, 40), (64, 64)):
+        _, _, exact, charge = spherical_mms(*n)
+        c2, e2 = W.spherical_mms_input(*n)
+        assert np.max(np.abs(c2 - charge)) < 1e-13 * np.max(np.abs(charge))
+        assert np.max(np.abs(e2 - exact)) < 1e-14
