@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-IDENTITY, SINUSOIDAL, POLAR_LOG, SPHERICAL_RZ = 0, 1, 2, 3
+IDENTITY, SINUSOIDAL, POLAR_LOG, SPHERICAL_RZ, TABULATED = 0, 1, 2, 3, 4
 # FLOATING: a conducting wall of unknown potential at the lower face of axis 0
 # whose charge is what the particles absorbed there (Gauss' law); handled by
 # poisson_solve_floating and OracleSim, which pass the C routines a Dirichlet copy
@@ -49,7 +49,8 @@ def build(force: bool = True) -> str:
 class Map(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("dim", ctypes.c_int), ("L", ctypes.c_double * 3),
                 ("eps", ctypes.c_double), ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
-                ("omega", ctypes.c_int)]
+                ("omega", ctypes.c_int), ("tn", ctypes.c_int * 3), ("tper", ctypes.c_int * 3),
+                ("tx", ctypes.POINTER(ctypes.c_double))]
 
 
 class Grid(ctypes.Structure):
@@ -61,6 +62,37 @@ class Grid(ctypes.Structure):
 def make_map(kind, dim, L=(1.0, 1.0, 1.0), eps=0.0, r_in=1.0, r_out=2.0, omega=0) -> Map:
     L = tuple(L) + (1.0,) * (3 - len(L))
     return Map(kind, dim, (ctypes.c_double * 3)(*L), eps, r_in, r_out, omega)
+
+
+def make_tabulated_map(dim, n, periodic, table, L=(1.0, 1.0, 1.0)) -> Map:
+    """A map known at the cell vertices only: table[a] holds x^a at every
+    vertex (vertex (i, j, k) at i + nv0 (j + nv1 k), nv_a = n_a on a periodic
+    axis, n_a + 1 on a bounded one); on a periodic axis a the map continues as
+    x(xi + e_a) = x(xi) + L_a e_a."""
+    n = tuple(n)[:dim] + (1,) * (3 - dim)
+    per = tuple(int(bool(p)) for p in periodic)[:dim] + (1,) * (3 - dim)
+    tn = tuple((n[a] if per[a] else n[a] + 1) if a < dim else 1 for a in range(3))
+    tab = np.ascontiguousarray(np.asarray(table, dtype=np.float64).reshape(dim, -1))
+    assert tab.shape[1] == tn[0] * tn[1] * tn[2]
+    L = tuple(L) + (1.0,) * (3 - len(L))
+    m = Map(TABULATED, dim, (ctypes.c_double * 3)(*L), 0.0, 1.0, 2.0, 0, (ctypes.c_int * 3)(*tn),
+            (ctypes.c_int * 3)(*per), tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    m._table = tab  # keeps the table alive while the map is
+    return m
+
+
+def sample_map_vertices(m: Map, n, periodic):
+    """The analytic map m at the vertices of an n grid, as a tabulated map's
+    table (shape (dim, nverts))."""
+    dim = m.dim
+    nv = [(n[a] if periodic[a] else n[a] + 1) for a in range(dim)]
+    axes = [np.arange(nv[a]) / n[a] for a in range(dim)]
+    G = np.meshgrid(*axes, indexing="ij")
+    xi = np.zeros((int(np.prod(nv)), 3))
+    for a in range(dim):
+        xi[:, a] = G[a].ravel(order="F")
+    x, _, _, _ = map_eval(m, xi)
+    return np.ascontiguousarray(x[:, :dim].T)
 
 
 def make_grid(n, bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), phi_lo=(0.0, 0.0, 0.0),

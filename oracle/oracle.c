@@ -32,7 +32,7 @@
 
 #define OR_PI 3.14159265358979323846
 
-enum { OR_IDENTITY = 0, OR_SINUSOIDAL = 1, OR_POLAR_LOG = 2, OR_SPHERICAL_RZ = 3 };
+enum { OR_IDENTITY = 0, OR_SINUSOIDAL = 1, OR_POLAR_LOG = 2, OR_SPHERICAL_RZ = 3, OR_TABULATED = 4 };
 enum { OR_PERIODIC = 0, OR_DIRICHLET = 1, OR_NEUMANN = 2 };
 enum { OR_B1 = 1, OR_B2 = 2 };
 
@@ -43,6 +43,14 @@ typedef struct {
   double eps;
   double r_in, r_out;
   int omega; /* 0: Omega = 1; 1: Omega = x^1 (cylindrical r) */
+  /* OR_TABULATED: the map known at the cell vertices only.  tx holds x^a at
+     the vertices, d arrays of tn0 tn1 tn2 values (vertex (i, j, k) at
+     i + tn0 (j + tn1 k)); tn_a = n_a vertices on a periodic axis (tper_a = 1),
+     where the map continues as x(xi + e_a) = x(xi) + L_a e_a, and n_a + 1 on a
+     bounded one. */
+  int tn[3];
+  int tper[3];
+  const double* tx;
 } or_map;
 
 typedef struct {
@@ -56,8 +64,109 @@ typedef struct {
 /* Maps and metrics: Eqs. (map), (jcov), (jcon), (jac), (gcon), (poiscurv).   */
 /* ------------------------------------------------------------------------ */
 
+/* Tabulated map (Sec. "Curvilinear formulation": the metric coefficients of
+   a map known at the cell vertices come from finite differences of it).
+   tab_x: x at vertex iv, whose indices on a periodic axis may lie outside
+   [0, n): the table entry of the wrapped vertex plus the whole periods. */
+static int tab_cells(const or_map* m, int a) { return m->tper[a] ? m->tn[a] : m->tn[a] - 1; }
+
+static void tab_x(const or_map* m, const int* iv, double* x) {
+  int d = m->dim;
+  int w[3] = {0, 0, 0};
+  double per[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < d; ++a) {
+    w[a] = iv[a];
+    if (m->tper[a]) {
+      int n = m->tn[a];
+      int r = ((iv[a] % n) + n) % n;
+      per[a] = (double)((iv[a] - r) / n);
+      w[a] = r;
+    }
+  }
+  long nv = (long)m->tn[0] * m->tn[1] * (d == 3 ? m->tn[2] : 1);
+  long lin = w[0] + (long)m->tn[0] * (w[1] + (long)m->tn[1] * w[2]);
+  for (int a = 0; a < 3; ++a) x[a] = 0.0;
+  for (int a = 0; a < d; ++a) x[a] = m->tx[a * nv + lin] + per[a] * m->L[a];
+}
+
+/* Jacobi matrix at vertex iv: dx/dxi^b by the centred difference over the two
+   neighbouring vertices (spacing 2/n_b), and at the two ends of a bounded axis
+   by the second-order one-sided difference over three vertices. */
+static void tab_jac_vertex(const or_map* m, const int* iv, double j[3][3]) {
+  int d = m->dim;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) j[a][b] = (a == b) ? 1.0 : 0.0;
+  for (int b = 0; b < d; ++b) {
+    int n = tab_cells(m, b);
+    int p0[3] = {iv[0], iv[1], iv[2]}, p1[3] = {iv[0], iv[1], iv[2]}, p2[3] = {iv[0], iv[1], iv[2]};
+    double x0[3], x1[3], x2[3];
+    if (m->tper[b] || (iv[b] > 0 && iv[b] < n)) {
+      p0[b] = iv[b] - 1;
+      p1[b] = iv[b] + 1;
+      tab_x(m, p0, x0);
+      tab_x(m, p1, x1);
+      for (int a = 0; a < d; ++a) j[a][b] = (x1[a] - x0[a]) * n / 2.0;
+    } else {
+      int s = (iv[b] == 0) ? 1 : -1; /* direction into the domain */
+      p1[b] = iv[b] + s;
+      p2[b] = iv[b] + 2 * s;
+      tab_x(m, p0, x0);
+      tab_x(m, p1, x1);
+      tab_x(m, p2, x2);
+      for (int a = 0; a < d; ++a) j[a][b] = s * (-3.0 * x0[a] + 4.0 * x1[a] - x2[a]) * n / 2.0;
+    }
+  }
+}
+
+/* Between vertices: x and the Jacobi matrix are the multilinear blends of the
+   values at the 2^d vertices of the cell holding xi (weights prod_a (1 - f_a)
+   or f_a); a point outside a bounded axis is taken on its wall. */
+static void tab_x_jac(const or_map* m, const double* xi, double* x, double j[3][3]) {
+  int d = m->dim;
+  int base[3] = {0, 0, 0};
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < d; ++a) {
+    int n = tab_cells(m, a);
+    double u = xi[a] * n;
+    if (!m->tper[a]) {
+      if (u < 0.0) u = 0.0;
+      if (u > n) u = n;
+    }
+    int i = (int)floor(u);
+    if (!m->tper[a] && i > n - 1) i = n - 1;
+    base[a] = i;
+    f[a] = u - i;
+  }
+  for (int a = 0; a < 3; ++a) {
+    x[a] = 0.0;
+    for (int b = 0; b < 3; ++b) j[a][b] = 0.0;
+  }
+  int nc = 1 << d;
+  for (int c = 0; c < nc; ++c) {
+    int iv[3] = {0, 0, 0};
+    double w = 1.0;
+    for (int a = 0; a < d; ++a) {
+      int up = (c >> a) & 1;
+      iv[a] = base[a] + up;
+      w *= up ? f[a] : 1.0 - f[a];
+    }
+    double xv[3], jv[3][3];
+    tab_x(m, iv, xv);
+    tab_jac_vertex(m, iv, jv);
+    for (int a = 0; a < d; ++a) {
+      x[a] += w * xv[a];
+      for (int b = 0; b < d; ++b) j[a][b] += w * jv[a][b];
+    }
+  }
+  for (int a = d; a < 3; ++a) j[a][a] = 1.0;
+}
+
 /* x(xi) and the Jacobi matrix j[a][b] = dx^a / dxi^b (Eq. jcov). */
 static void map_x_jac(const or_map* m, const double* xi, double* x, double j[3][3]) {
+  if (m->kind == OR_TABULATED) {
+    tab_x_jac(m, xi, x, j);
+    return;
+  }
   int d = m->dim;
   for (int a = 0; a < 3; ++a) {
     x[a] = 0.0;
@@ -553,7 +662,10 @@ int or_poisson_assemble(const or_map* m, const or_grid* g, double* A, double* bd
   for (int a = 0; a < d; ++a) h[a] = 1.0 / g->n[a];
   double dV = h[0] * h[1] * h[2];
   int bounded = !all_periodic(g);
-  if (bounded && m->kind == OR_SINUSOIDAL && m->eps != 0.0) return -2; /* mixed terms at walls */
+  /* with walls the mixed terms are dropped in every plane that holds a bounded
+     axis: accepted only for maps orthogonal there (a tabulated map: up to its
+     sampling error) */
+  if (bounded && m->kind == OR_SINUSOIDAL && m->eps != 0.0) return -2;
   memset(A, 0, sizeof(double) * (size_t)nc * (size_t)S);
   memset(bdir, 0, sizeof(double) * (size_t)nc);
   for (long c = 0; c < nc; ++c) {
