@@ -76,8 +76,24 @@ typedef enum {
    z = rho cos(pi (1 - eta)), rho = r_in + (r_out - r_in) xi (Sec. "Field
    solver", Eqs. r and z); with cpic_map_desc.omega = 1 it is the paper's
    manufactured-solution test of the solver.  It serves the field solve only:
-   cpic_add_species returns CPIC_E_UNSUPPORTED on it. */
-enum { CPIC_MAP_IDENTITY = 0, CPIC_MAP_SINUSOIDAL = 1, CPIC_MAP_POLAR_LOG = 2, CPIC_MAP_SPHERICAL_RZ = 3 };
+   cpic_add_species returns CPIC_E_UNSUPPORTED on it.
+   CPIC_MAP_TABULATED (2D, 3D): a map known only at the cell vertices
+   (cpic_map_desc.vertices), as a mesh generator gives it; the Jacobi matrix,
+   J, g^ij and k come from finite differences of the vertex coordinates (Sec.
+   "Curvilinear formulation"): centred over the two neighbours, second-order
+   one-sided at the ends of a bounded axis, blended multilinearly between
+   vertices.  Particles move with CPIC_MOVER_PC only (no analytic map to invert)
+   and cannot be injected; with walls the map must be orthogonal, up to its
+   sampling error, in every plane that holds a bounded axis (the columns of j
+   within acos(0.05) of a right angle at every vertex, else
+   CPIC_E_UNSUPPORTED); J <= 0 at a vertex or cell centre gives CPIC_E_MAP. */
+enum {
+  CPIC_MAP_IDENTITY = 0,
+  CPIC_MAP_SINUSOIDAL = 1,
+  CPIC_MAP_POLAR_LOG = 2,
+  CPIC_MAP_SPHERICAL_RZ = 3,
+  CPIC_MAP_TABULATED = 4
+};
 /* field boundary conditions per axis side (ghost cells, Sec. II.B).
    CPIC_BC_FLOATING (lower side of axis 0 only, every other axis periodic): a
    conducting wall whose potential floats so that Gauss' law holds -- the
@@ -141,7 +157,7 @@ typedef struct {
 typedef struct {
   int kind;       /* CPIC_MAP_* */
   int dim;        /* 2 or 3 */
-  double L[3];    /* box lengths (identity, sinusoidal) */
+  double L[3];    /* box lengths (identity, sinusoidal); period shifts (tabulated) */
   double eps;     /* sinusoidal amplitude, relative to the box */
   double r_in;    /* polar-log inner radius */
   double r_out;   /* polar-log outer radius */
@@ -152,6 +168,14 @@ typedef struct {
      Omega = x^1, CPIC_FIELD_CHARGE is the right side Omega J rho dV of the
      solve, and the map serves the field solve only (no species). */
   int omega;
+  /* CPIC_MAP_TABULATED: physical coordinates at the logical vertices, host
+     memory owned by the caller and read during cpic_create only: d arrays of
+     nv0 nv1 (nv2) doubles (x^1 at every vertex, then x^2, ...), vertex
+     (i, j, k) at i + nv0 (j + nv1 k), nv_a = n_a on a periodic axis and
+     n_a + 1 on a bounded one.  On a periodic axis a the map continues as
+     x(xi + e_a) = x(xi) + L_a e_a (L_a >= 0; 0 for an axis that closes on
+     itself, such as an angle).  Ignored by the other kinds. */
+  const double* vertices;
 } cpic_map_desc;
 
 typedef struct {
@@ -306,7 +330,7 @@ void cpic_destroy(cpic_sim* sim);
 typedef struct cpic_server cpic_server;
 
 typedef struct {
-  cpic_map_desc map;
+  cpic_map_desc map;                        /* a tabulated map's vertices are copied at submit */
   cpic_grid_desc grid;
   int nspecies;                             /* 1..CPIC_MAX_SPECIES */
   cpic_species_desc species[CPIC_MAX_SPECIES]; /* capacity 0 means the initial count */

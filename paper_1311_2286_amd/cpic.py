@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcpic.so")
 
-MAP_IDENTITY, MAP_SINUSOIDAL, MAP_POLAR_LOG, MAP_SPHERICAL_RZ = 0, 1, 2, 3
+MAP_IDENTITY, MAP_SINUSOIDAL, MAP_POLAR_LOG, MAP_SPHERICAL_RZ, MAP_TABULATED = 0, 1, 2, 3, 4
 BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN, BC_FLOATING = 0, 1, 2, 3
 PBC_PERIODIC, PBC_ABSORB, PBC_OUTFLOW = 0, 1, 2
 SHAPE_B1, SHAPE_B2 = 1, 2
@@ -39,7 +39,7 @@ E_PENDING = 1
 class MapDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("dim", ctypes.c_int), ("L", ctypes.c_double * 3),
                 ("eps", ctypes.c_double), ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
-                ("omega", ctypes.c_int)]
+                ("omega", ctypes.c_int), ("vertices", ctypes.c_void_p)]
 
 
 class GridDesc(ctypes.Structure):
@@ -234,14 +234,18 @@ class Sim:
                  bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), phi_lo=(0.0, 0.0, 0.0), phi_hi=(0.0, 0.0, 0.0),
                  shape=SHAPE_B2, precision=FP32, dt=0.1, B0=(0.0, 0.0, 0.0), background=False,
                  background_n0=1.0, mg_rtol=1e-10, mg_max_cycles=30, sort_every=1, track_ids=False,
-                 stream=None, torch_alloc=True, mg_method=0, mover=0, omega=0):
+                 stream=None, torch_alloc=True, mg_method=0, mover=0, omega=0, vertices=None):
         self.lib = load()
         pad = lambda t, v: tuple(t)[:3] + (v,) * (3 - len(tuple(t)[:3]))
         self.dim = dim
         self.n = tuple(n)[:dim]
         self.precision = precision
         self.rdtype = np.float64 if precision == FP64 else np.float32
-        m = MapDesc(map_kind, dim, (ctypes.c_double * 3)(*pad(L, 1.0)), eps, r_in, r_out, int(omega))
+        vtab = None
+        if vertices is not None:  # tabulated map: (dim, nverts) vertex coordinates, read by cpic_create
+            vtab = np.ascontiguousarray(vertices, dtype=np.float64)
+        m = MapDesc(map_kind, dim, (ctypes.c_double * 3)(*pad(L, 1.0)), eps, r_in, r_out, int(omega),
+                    vtab.ctypes.data if vtab is not None else None)
         g = GridDesc((ctypes.c_int * 3)(*pad(n, 1)), (ctypes.c_int * 3)(*pad(bc_lo, 0)),
                      (ctypes.c_int * 3)(*pad(bc_hi, 0)), (ctypes.c_double * 3)(*pad(phi_lo, 0.0)),
                      (ctypes.c_double * 3)(*pad(phi_hi, 0.0)), shape, precision, dt,

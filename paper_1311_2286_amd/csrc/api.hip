@@ -161,7 +161,9 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   *out = nullptr;
   const int d = map->dim;
   if (d != 2 && d != 3) return CPIC_E_ARG;
-  if (map->kind < CPIC_MAP_IDENTITY || map->kind > CPIC_MAP_SPHERICAL_RZ) return CPIC_E_ARG;
+  if (map->kind < CPIC_MAP_IDENTITY || map->kind > CPIC_MAP_TABULATED) return CPIC_E_ARG;
+  const bool tabulated = map->kind == CPIC_MAP_TABULATED;
+  if (tabulated && !map->vertices) return CPIC_E_ARG;
   const bool radial = map->kind == CPIC_MAP_POLAR_LOG || map->kind == CPIC_MAP_SPHERICAL_RZ;
   if (radial && (d != 2 || !(map->r_in > 0) || !(map->r_out > map->r_in))) return CPIC_E_ARG;
   // Omega = x^1 is the radius of an r-z plane: it must stay >= 0, which holds
@@ -170,9 +172,15 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   if (map->omega && (d != 2 || (map->kind != CPIC_MAP_IDENTITY && map->kind != CPIC_MAP_SPHERICAL_RZ) ||
                      grid->bc_lo[0] == CPIC_BC_PERIODIC))
     return CPIC_E_UNSUPPORTED;
-  if (!radial)
+  if (tabulated) {
+    // L_a: the shift of x^a per period of a periodic axis (0: the map closes
+    // on itself, e.g. an angle)
+    for (int a = 0; a < d; ++a)
+      if (!(map->L[a] >= 0) || !isfinite(map->L[a])) return CPIC_E_ARG;
+  } else if (!radial) {
     for (int a = 0; a < d; ++a)
       if (!(map->L[a] > 0)) return CPIC_E_ARG;
+  }
   if (map->kind == CPIC_MAP_SINUSOIDAL) {
     // J = 1 + 2 pi eps (sum of products); its bracket is bounded by 1 (2D) and
     // 2/sqrt(3) (3D): the map folds beyond eps = 1/(2 pi) resp. sqrt(3)/(4 pi)
@@ -291,7 +299,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   G.g = g;
   G.fp64 = grid->precision == CPIC_FP64;
   G.all_periodic = all_periodic;
-  G.mixed = map->kind == CPIC_MAP_SINUSOIDAL && map->eps != 0.0;
+  G.mixed = (map->kind == CPIC_MAP_SINUSOIDAL && map->eps != 0.0) || tabulated;
   for (int a = 0; a < 3; ++a) {
     G.bc_lo[a] = a < d ? grid->bc_lo[a] : CPIC_BC_PERIODIC;
     G.bc_hi[a] = a < d ? grid->bc_hi[a] : CPIC_BC_PERIODIC;
@@ -392,6 +400,8 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   s->drift_dev = (unsigned*)A(sizeof(unsigned) * 8);
   G.Ev = A(real_size(s) * ecomp(s) * (size_t)g.nverts);
   G.Kv = (double*)A(sizeof(double) * (size_t)(d * d) * (size_t)g.nverts);
+  double* xtab = tabulated ? (double*)A(sizeof(double) * (size_t)d * (size_t)g.nverts) : nullptr;
+  double* jtab = tabulated ? (double*)A(sizeof(double) * (size_t)(d * d) * (size_t)g.nverts) : nullptr;
   // predictor-corrector table: d x d per vertex padded to 4 (2D) or 12 (3D) values
   if (grid->mover == CPIC_MOVER_PC) s->kc = A(real_size(s) * (size_t)(d == 3 ? 12 : 4) * (size_t)g.nverts);
   G.phi_prev = (double*)A(cb);
@@ -405,6 +415,32 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     return CPIC_E_NOMEM;
   }
   hipStream_t st = s->stream;
+  // tabulated map: vertex coordinates in (d values per vertex), then the Jacobi
+  // matrices by finite differences; every metric below is taken from them
+  std::vector<double> xh;
+  if (tabulated) {
+    const size_t nv = (size_t)g.nverts;
+    xh.resize((size_t)d * nv);
+    bool finite = true;
+    for (size_t v = 0; v < nv; ++v)
+      for (int a = 0; a < d; ++a) {
+        const double x = map->vertices[(size_t)a * nv + v];
+        finite = finite && isfinite(x);
+        xh[v * d + a] = x;
+      }
+    if (!finite) {
+      sim_free_all(s);
+      delete s;
+      return CPIC_E_ARG;
+    }
+    s->g.xtab = G.g.xtab = xtab;
+    s->g.jtab = G.g.jtab = jtab;
+    if (hipMemcpyAsync(xtab, xh.data(), sizeof(double) * xh.size(), hipMemcpyHostToDevice, st) != hipSuccess) {
+      cpic_destroy(s);
+      return CPIC_E_HIP;
+    }
+    launch_map_table(G.g, jtab, st);
+  }
   for (int l = 0; l < nl; ++l) {
     Level& L = G.lev[l];
     size_t b = sizeof(double) * (size_t)L.ncells;
@@ -466,6 +502,43 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     cpic_destroy(s);
     return CPIC_E_MAP;
   }
+  if (tabulated) {
+    // the tabulated map must fold nowhere (J > 0 at every vertex as at every
+    // cell centre) and, with walls, be orthogonal in every plane that holds a
+    // bounded axis (the operator keeps mixed terms only between periodic
+    // axes): there the columns of j may deviate from a right angle by at most
+    // acos(0.05) -- the sampling error of an orthogonal map
+    const size_t nv = (size_t)g.nverts, dd = (size_t)(d * d);
+    std::vector<double> jh(dd * nv);
+    if (hipMemcpyAsync(jh.data(), jtab, sizeof(double) * jh.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      cpic_destroy(s);
+      return CPIC_E_HIP;
+    }
+    cpic_status bad = CPIC_OK;
+    for (size_t v = 0; v < nv && bad == CPIC_OK; ++v) {
+      const double* j = jh.data() + v * dd;
+      double det = (d == 2) ? j[0] * j[3] - j[1] * j[2]
+                            : j[0] * (j[4] * j[8] - j[5] * j[7]) - j[1] * (j[3] * j[8] - j[5] * j[6]) +
+                                  j[2] * (j[3] * j[7] - j[4] * j[6]);
+      if (!(det > 0)) bad = CPIC_E_MAP;
+      for (int p = 0; p < d && bad == CPIC_OK; ++p)
+        for (int q = p + 1; q < d; ++q) {
+          if (g.periodic[p] && g.periodic[q]) continue;
+          double dot = 0.0, np2 = 0.0, nq2 = 0.0;
+          for (int a = 0; a < d; ++a) {
+            dot += j[a * d + p] * j[a * d + q];
+            np2 += j[a * d + p] * j[a * d + p];
+            nq2 += j[a * d + q] * j[a * d + q];
+          }
+          if (fabs(dot) > 0.05 * sqrt(np2 * nq2)) bad = CPIC_E_UNSUPPORTED;
+        }
+    }
+    if (bad != CPIC_OK) {
+      cpic_destroy(s);
+      return bad;
+    }
+  }
   *out = s;
   return CPIC_OK;
 }
@@ -480,6 +553,8 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
     return fail(s, CPIC_E_ARG, "bad species descriptor");
   if (s->g.kind == CPIC_MAP_SPHERICAL_RZ || s->g.omega)
     return fail(s, CPIC_E_UNSUPPORTED, "the spherical r-z map and Omega = r serve the field solve only");
+  if (s->g.kind == CPIC_MAP_TABULATED && s->grid.mover != CPIC_MOVER_PC)
+    return fail(s, CPIC_E_UNSUPPORTED, "a tabulated map moves particles with the predictor-corrector update");
   const int d = s->g.dim;
   for (int a = 0; a < d; ++a) {
     bool per = s->g.periodic[a];
@@ -493,7 +568,8 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
   double lam = 0.0;
   if (desc->inject) {
     if (s->g.periodic[0]) return fail(s, CPIC_E_ARG, "injection needs a bounded axis 0");
-    if (s->g.kind == CPIC_MAP_SINUSOIDAL) return fail(s, CPIC_E_UNSUPPORTED, "injection needs an orthogonal map");
+    if (s->g.kind != CPIC_MAP_IDENTITY && s->g.kind != CPIC_MAP_POLAR_LOG)
+      return fail(s, CPIC_E_UNSUPPORTED, "injection needs an orthogonal analytic map");
     if (!(desc->inject_n0 > 0) || !(desc->inject_vth > 0) || !(desc->inject_drift >= 0) ||
         !isfinite(desc->inject_drift))
       return fail(s, CPIC_E_ARG, "bad injection parameters");

@@ -12,11 +12,12 @@
 namespace cpic {
 
 // MAP_SPHERICAL_RZ (the r-z half plane of a spherical shell) serves the field
-// solve only: no particle kernel is built for it
-enum { MAP_IDENTITY = 0, MAP_SINUSOIDAL = 1, MAP_POLAR_LOG = 2, MAP_SPHERICAL_RZ = 3 };
+// solve only: no particle kernel is built for it.  MAP_TABULATED: the map known
+// at the vertices only (particles move with the predictor-corrector update)
+enum { MAP_IDENTITY = 0, MAP_SINUSOIDAL = 1, MAP_POLAR_LOG = 2, MAP_SPHERICAL_RZ = 3, MAP_TABULATED = 4 };
 // particle-kernel variant that moves with the tabulated inverse Jacobian (the
 // predictor-corrector update), whatever the map
-constexpr int MAP_TABLE_PC = 4;
+constexpr int MAP_TABLE_PC = 5;
 enum { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_NEUMANN = 2 };
 enum { PBC_PERIODIC = 0, PBC_ABSORB = 1, PBC_OUTFLOW = 2 };
 enum { SHAPE_B1 = 1, SHAPE_B2 = 2 };
@@ -53,6 +54,11 @@ struct Geo {
   double eps;
   double r_in, r_out, lnR;
   int omega;       // 1: geometric factor Omega = x^1 (radius of an axisymmetric r-z plane), else 1
+  // tabulated map: x at the vertices (d per vertex) and the Jacobi matrix there
+  // from finite differences of it (d x d per vertex, row-major); on a periodic
+  // axis a the map continues as x(xi + e_a) = x(xi) + L_a e_a
+  const double* xtab;
+  const double* jtab;
   double ecell[3]; // eps * n_a: map perturbation in cells of axis a
   double dxc[3];   // L_a / n_a: undistorted cell size
 };
@@ -346,7 +352,47 @@ __device__ inline void map_jacobi(const Geo& g, const double* xi, double j[3][3]
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) j[a][b] = (a == b) ? 1.0 : 0.0;
   const int d = g.dim;
-  if (g.kind == MAP_IDENTITY) {
+  if (g.kind == MAP_TABULATED) {
+    // multilinear blend of the values at the 2^d vertices of the cell holding
+    // xi; a point beyond a bounded axis is taken on its wall
+    int base[3] = {0, 0, 0};
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) {
+      double u = xi[a] * g.n[a];
+      if (!g.periodic[a]) u = fmin(fmax(u, 0.0), (double)g.n[a]);
+      int i = (int)floor(u);
+      if (!g.periodic[a] && i > g.n[a] - 1) i = g.n[a] - 1;
+      base[a] = i;
+      f[a] = u - i;
+    }
+    for (int a = 0; a < d; ++a) {
+      j[a][a] = 0.0;
+      if (x) x[a] = 0.0;
+    }
+    for (int c = 0; c < (1 << d); ++c) {
+      double w = 1.0, per[3] = {0.0, 0.0, 0.0};
+      long long v = 0, stride = 1;
+      for (int a = 0; a < d; ++a) {
+        const int up = (c >> a) & 1;
+        int i = base[a] + up;
+        w *= up ? f[a] : 1.0 - f[a];
+        if (g.periodic[a]) {
+          int r = i % g.n[a];
+          if (r < 0) r += g.n[a];
+          per[a] = (double)((i - r) / g.n[a]);
+          i = r;
+        }
+        v += stride * i;
+        stride *= g.nv[a];
+      }
+      const double* xv = g.xtab + v * d;
+      const double* jv = g.jtab + v * d * d;
+      for (int a = 0; a < d; ++a) {
+        if (x) x[a] += w * (xv[a] + per[a] * g.L[a]);
+        for (int b = 0; b < d; ++b) j[a][b] += w * jv[a * d + b];
+      }
+    }
+  } else if (g.kind == MAP_IDENTITY) {
     for (int a = 0; a < d; ++a) {
       j[a][a] = g.L[a];
       if (x) x[a] = g.L[a] * xi[a];

@@ -231,7 +231,9 @@ __global__ void coef_kernel(Geo g, LevelArgs a, double* wf0, double* wf1, double
   int np = (d == 3) ? 3 : 1;
   for (int p = 0; p < np; ++p) {
     double W = 0.0;
-    if (a.mixed) {
+    // mixed terms only in planes of two periodic axes: with walls the map must
+    // be orthogonal in the planes that hold a bounded axis
+    if (a.mixed && a.periodic[pi[p]] && a.periodic[pj[p]]) {
       double xi[3];
       for (int b = 0; b < 3; ++b) xi[b] = (b < d) ? (idx[b] + 0.5) * a.h[b] : 0.0;
       xi[pi[p]] = (idx[pi[p]] + 1) * a.h[pi[p]];
@@ -1608,6 +1610,66 @@ __device__ inline double phi_ghost(const Geo& g, const int* bclo, const int* bch
     }
   }
   return add + sgn * phi[idx_to_lin(idx, g.n)];
+}
+
+// Tabulated map: the Jacobi matrix at every vertex by finite differences of
+// the vertex coordinates (Sec. "Curvilinear formulation"): centred over the
+// two neighbours, second-order one-sided over three vertices at the ends of a
+// bounded axis; across a periodic seam the neighbour carries a whole period.
+__device__ inline double tab_coord(const Geo& g, int a, int i, int jj, int k) {
+  int iv[3] = {i, jj, k};
+  double per = 0.0;
+  long long v = 0, stride = 1;
+  for (int b = 0; b < g.dim; ++b) {
+    int t = iv[b];
+    if (g.periodic[b]) {
+      if (t < 0) {
+        t += g.n[b];
+        if (b == a) per = -1.0;
+      } else if (t >= g.n[b]) {
+        t -= g.n[b];
+        if (b == a) per = 1.0;
+      }
+    }
+    v += stride * t;
+    stride *= g.nv[b];
+  }
+  return g.xtab[v * g.dim + a] + per * g.L[a];
+}
+
+__global__ __launch_bounds__(256) void map_table_kernel(Geo g, double* jtab) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= g.nverts) return;
+  const int d = g.dim;
+  int iv[3] = {(int)(v % g.nv[0]), (int)((v / g.nv[0]) % g.nv[1]), d == 3 ? (int)(v / ((long long)g.nv[0] * g.nv[1])) : 0};
+  for (int b = 0; b < d; ++b) {
+    const double half_n = 0.5 * g.n[b];
+    int lo[3] = {iv[0], iv[1], iv[2]}, hi[3] = {iv[0], iv[1], iv[2]}, far[3] = {iv[0], iv[1], iv[2]};
+    const bool interior = g.periodic[b] || (iv[b] > 0 && iv[b] < g.n[b]);
+    const int s = interior ? 0 : (iv[b] == 0 ? 1 : -1);  // one-sided: direction into the domain
+    if (interior) {
+      lo[b] = iv[b] - 1;
+      hi[b] = iv[b] + 1;
+    } else {
+      hi[b] = iv[b] + s;
+      far[b] = iv[b] + 2 * s;
+    }
+    for (int a = 0; a < d; ++a) {
+      double dv;
+      if (interior) {
+        dv = (tab_coord(g, a, hi[0], hi[1], hi[2]) - tab_coord(g, a, lo[0], lo[1], lo[2])) * half_n;
+      } else {
+        dv = s * (-3.0 * tab_coord(g, a, iv[0], iv[1], iv[2]) + 4.0 * tab_coord(g, a, hi[0], hi[1], hi[2]) -
+                  tab_coord(g, a, far[0], far[1], far[2])) * half_n;
+      }
+      jtab[v * d * d + a * d + b] = dv;
+    }
+  }
+}
+
+void launch_map_table(const Geo& g, double* jtab, hipStream_t st) {
+  const unsigned blocks = (unsigned)((g.nverts + 255) / 256);
+  hipLaunchKernelGGL(map_table_kernel, dim3(blocks), dim3(256), 0, st, g, jtab);
 }
 
 // Inverse Jacobian k = j^-1 of the map at every vertex (FP64, row-major d x d),

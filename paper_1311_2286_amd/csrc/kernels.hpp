@@ -208,6 +208,7 @@ constexpr double ANISO_TRANSPOSE = 4.0;
 void launch_extrapolate_guess(const GridCtx& G, int extrapolate, hipStream_t st);
 void launch_gauge(const GridCtx& G, hipStream_t st);
 void launch_vertex_metric(const GridCtx& G, hipStream_t st);
+void launch_map_table(const Geo& g, double* jtab, hipStream_t st);
 void launch_efield(const GridCtx& G, hipStream_t st);
 void launch_rho(const GridCtx& G, double* rho, hipStream_t st);
 void launch_field_energy(const GridCtx& G, double* out, hipStream_t st);

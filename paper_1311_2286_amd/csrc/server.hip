@@ -36,6 +36,7 @@ struct Case {
   uint64_t ticket = 0;
   cpic_case_desc desc;
   std::vector<std::vector<unsigned char>> cell, off, vel;  // host copies per species
+  std::vector<double> vertices;                             // host copy of a tabulated map
   cpic_sim* sim = nullptr;
   hipStream_t stream = nullptr;
   int slot = -1;
@@ -265,6 +266,23 @@ extern "C" cpic_status cpic_server_submit(cpic_server* s, const cpic_case_desc* 
   const size_t r = real_bytes(d->grid);
   Case* c = new Case();
   c->desc = *d;
+  if (d->map.kind == CPIC_MAP_TABULATED) {
+    if (!d->map.vertices) {
+      delete c;
+      return CPIC_E_ARG;
+    }
+    size_t nv = 1;
+    for (int a = 0; a < dim; ++a) {
+      const int n = d->grid.n[a];
+      if (n < 1) {
+        delete c;
+        return CPIC_E_ARG;
+      }
+      nv *= (size_t)(d->grid.bc_lo[a] == CPIC_BC_PERIODIC ? n : n + 1);
+    }
+    c->vertices.assign(d->map.vertices, d->map.vertices + (size_t)dim * nv);
+    c->desc.map.vertices = c->vertices.data();
+  }
   c->cell.resize((size_t)d->nspecies);
   c->off.resize((size_t)d->nspecies);
   c->vel.resize((size_t)d->nspecies);

@@ -69,6 +69,9 @@ class Case:
     delta: float = 0.0  # density perturbation amplitude, cos(2 pi x^1 / L_1)
     steps: int = 100
     case_id: int = 0
+    # run on the map sampled at the vertices (a tabulated map) instead of the
+    # analytic one; particles are still loaded from the analytic map's density
+    tabulated: bool = False
 
     @property
     def ncells(self) -> int:
@@ -98,6 +101,35 @@ class Case:
         pad = lambda t, v: tuple(t[: self.dim]) + (v,) * (3 - self.dim)
         return dict(n=tuple(self.n), bc_lo=pad(self.bc_lo, 0), bc_hi=pad(self.bc_hi, 0),
                     phi_lo=pad(self.phi_lo, 0.0), phi_hi=pad(self.phi_hi, 0.0))
+
+
+def vertex_table(case: Case) -> np.ndarray:
+    """The case's analytic map at the logical vertices, as a tabulated map's
+    vertex coordinates: shape (dim, nverts), vertex i + nv0 (j + nv1 k), nv_a =
+    n_a on a periodic axis, n_a + 1 on a bounded one.  Closed forms: identity
+    x = L xi; sinusoidal x^a = L_a (xi^a + eps prod_k sin(2 pi xi^k)); polar-log
+    (r cos 2 pi eta, r sin 2 pi eta), r = r_in (r_out / r_in)^xi."""
+    d = case.dim
+    nv = [case.n[a] if case.bc_lo[a] == PERIODIC else case.n[a] + 1 for a in range(d)]
+    axes = [np.arange(nv[a]) / case.n[a] for a in range(d)]
+    G = [g.ravel() for g in np.meshgrid(*axes[::-1], indexing="ij")[::-1]]  # axis 0 fastest
+    if case.map_kind == POLAR_LOG:
+        r = case.r_in * (case.r_out / case.r_in) ** G[0]
+        return np.stack([r * np.cos(2 * np.pi * G[1]), r * np.sin(2 * np.pi * G[1])])
+    P = np.ones_like(G[0])
+    if case.map_kind == SINUSOIDAL:
+        for a in range(d):
+            P = P * np.sin(2 * np.pi * G[a])
+    eps = case.eps if case.map_kind == SINUSOIDAL else 0.0
+    return np.stack([case.L[a] * (G[a] + eps * P) for a in range(d)])
+
+
+def table_shift(case: Case) -> Tuple[float, ...]:
+    """Shift of x^a per period of each axis of the tabulated map: the box
+    length, or 0 for the polar angle (the map closes on itself)."""
+    if case.map_kind == POLAR_LOG:
+        return (1.0, 0.0)
+    return tuple(case.L[: case.dim])
 
 
 def electrons(vth=1.0, ppc=64.0, count=None):

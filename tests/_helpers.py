@@ -14,11 +14,14 @@ def gpu_sim(case, precision=0, shape=2, track_ids=True, mg_rtol=1e-12, mg_max_cy
     dt = np.float64 if precision == C.FP64 else np.float32
     pbc_lo = tuple(0 if b == 0 else C.PBC_ABSORB for b in case.bc_lo)
     pbc_hi = tuple(0 if b == 0 else C.PBC_OUTFLOW for b in case.bc_hi)
-    sim = C.Sim(case.map_kind, case.dim, case.n, L=case.L, eps=case.eps, r_in=case.r_in,
+    kind, L, vertices = case.map_kind, case.L, None
+    if case.tabulated:
+        kind, L, vertices = C.MAP_TABULATED, W.table_shift(case), W.vertex_table(case)
+    sim = C.Sim(kind, case.dim, case.n, L=L, eps=case.eps, r_in=case.r_in,
                 r_out=case.r_out, bc_lo=case.bc_lo, bc_hi=case.bc_hi, phi_lo=case.phi_lo,
                 phi_hi=case.phi_hi, shape=shape, precision=precision, dt=case.dt, B0=case.B,
                 background=case.background, mg_rtol=mg_rtol, mg_max_cycles=mg_max_cycles,
-                sort_every=sort_every, track_ids=track_ids, stream=stream, mover=mover)
+                sort_every=sort_every, track_ids=track_ids, stream=stream, mover=mover, vertices=vertices)
     parts = []
     for sid, s in enumerate(case.species):
         p = W.generate_species(case, sid, dtype=dt, count=count)
@@ -31,7 +34,12 @@ def gpu_sim(case, precision=0, shape=2, track_ids=True, mg_rtol=1e-12, mg_max_cy
 
 
 def oracle_objects(case):
-    return O.make_map(**case.map_args()), O.make_grid(**case.grid_args())
+    g = O.make_grid(**case.grid_args())
+    if case.tabulated:
+        per = [int(case.bc_lo[a] == W.PERIODIC) for a in range(case.dim)]
+        m = O.make_tabulated_map(case.dim, case.n, per, W.vertex_table(case), L=W.table_shift(case))
+        return m, g
+    return O.make_map(**case.map_args()), g
 
 
 def oracle_species(case, parts):

@@ -7,8 +7,11 @@ Bars: one push from identical states, FP32: positions 2e-5 cell, velocities
 Three full steps, FP64, 2D sinusoidal map: potential within 1e-8 of its
 maximum and every particle within 1e-9 cell of the oracle run with the same
 mover.  Cases: 2D and 3D sinusoidal maps (ragged, several tiles), the
-identity map, a magnetised 3D box, the polar-log annulus with walls, and
-particles fast enough to leave the interpolation cell in the predictor."""
+identity map, a magnetised 3D box, the polar-log annulus with walls,
+particles fast enough to leave the interpolation cell in the predictor, and
+the sinusoidal and polar-log maps given as vertex tables (tabulated maps)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -47,6 +50,13 @@ CASES = {
     "2d_fast": lambda: W.small_case(dim=2, n=(40, 24), eps=0.15, ppc=6.0, L=(1.0, 1.0), vth_e=0.2,
                                     case_id=144),
     "probe": probe_case,
+    # the same maps known at the vertices only (tabulated, metric by finite
+    # differences), walls included
+    "2d_sin_tab": lambda: dataclasses.replace(W.small_case(dim=2, n=(40, 24), ppc=8.0, case_id=145),
+                                              tabulated=True),
+    "3d_sin_tab": lambda: dataclasses.replace(W.small_case(dim=3, n=(20, 12, 16), ppc=4.0, case_id=146),
+                                              tabulated=True),
+    "probe_tab": lambda: dataclasses.replace(probe_case(), tabulated=True, case_id=147),
 }
 
 
@@ -99,8 +109,9 @@ def test_push_one_step(name, precision):
     sim.close()
 
 
-def test_three_steps_fp64_match_the_oracle():
-    case = CASES["2d_sin"]()
+@pytest.mark.parametrize("name", ["2d_sin", "2d_sin_tab"])
+def test_three_steps_fp64_match_the_oracle(name):
+    case = CASES[name]()
     sim, parts = gpu_sim(case, precision=1, mover=C().MOVER_PC, mg_rtol=1e-13)
     m, g = oracle_objects(case)
     osim = O.OracleSim(m, g, oracle_species(case, parts), dt=case.dt, deposit="f64", rtol=1e-13, ke_axes=2,
