@@ -334,6 +334,67 @@ def extra_workload(name, shape_name, precision, steps, warmup, sort_every, mg_rt
     return out
 
 
+def mover_timing(steps=200, dts=(0.001, 0.002, 0.004, 0.01, 0.025, 0.05)):
+    """The paper's mover-timing test (Sec. "Particle mover", Tables t2 and t3):
+    unit square, sinusoidal map with eps = 0 and 0.1, 64^2 cells, 100 electrons
+    per cell (v_th = 1), fixed fields, periodic boundaries.  Times the particle
+    stage (gather, push, position update, boundaries, deposit) per particle and
+    step for both position updates, the tile sort (every step) beside it;
+    normalised like the tables, to the Newton mover at eps = 0, dt = 0.001."""
+    from paper_1311_2286_amd import cpic as C
+    from paper_1311_2286_amd import workloads as W
+    import torch
+    rows = []
+    for mover in (C.MOVER_NEWTON, C.MOVER_PC):
+        for eps in (0.0, 0.1):
+            case = W.Case("mover64", 2, W.SINUSOIDAL, (64, 64), L=(1.0, 1.0), eps=eps,
+                          species=[W.electrons(1.0, 100.0)], case_id=170)
+            p = W.generate_species(case, 0, dtype=np.float32)
+            for dt in dts:
+                sim = C.Sim(W.SINUSOIDAL, 2, (64, 64), L=(1.0, 1.0), eps=eps, dt=dt, precision=C.FP32,
+                            mover=mover)
+                try:
+                    sim.add_species(-1.0, 1.0, 1.0 / p["cell"].size, p["cell"].size)
+                    sim.set_particles(0, p["cell"], p["off"], p["vel"])
+                    nv = sim.field_bytes(C.FIELD_EV) // 8
+                    sim.set_field(C.FIELD_EV, W.synthetic_ev(case, nv, scale=0.5)[:, :2].copy())
+                    st = torch.cuda.current_stream()
+                    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                    push_ms = sort_ms = 0.0
+                    for k in range(steps + 5):
+                        ev[0].record(st)
+                        sim.stage(C.STAGE_PUSH)
+                        ev[1].record(st)
+                        sim.stage(C.STAGE_SORT)
+                        ev[2].record(st)
+                        st.synchronize()
+                        if k >= 5:
+                            push_ms += ev[0].elapsed_time(ev[1])
+                            sort_ms += ev[1].elapsed_time(ev[2])
+                    d = sim.diag()
+                    rows.append({"mover": "newton" if mover == C.MOVER_NEWTON else "predictor-corrector",
+                                 "eps": eps, "dt": dt,
+                                 "ns_per_particle_step": 1e6 * push_ms / steps / p["cell"].size,
+                                 "sort_ns_per_particle_step": 1e6 * sort_ms / steps / p["cell"].size,
+                                 "newton_fallback": int(d.newton_fallback),
+                                 "far_deposits": int(d.far_deposits)})
+                finally:
+                    sim.close()
+            del p
+    ref = rows[0]["ns_per_particle_step"]
+    for r in rows:
+        r["normalised"] = r["ns_per_particle_step"] / ref
+    ratio = {}
+    for mv in ("newton", "predictor-corrector"):
+        t = {(r["eps"], r["dt"]): r["ns_per_particle_step"] for r in rows if r["mover"] == mv}
+        ratio[mv] = {str(dt): t[(0.1, dt)] / t[(0.0, dt)] for dt in dts}
+    out = {"workload": "mover timing: unit square, sinusoidal map eps 0 / 0.1, 64^2 cells, 100 e/cell "
+                       "(409,600), v_th 1, fixed fields, periodic, %d steps per point, FP32" % steps,
+           "rows": rows, "eps_0.1_over_eps_0": ratio}
+    log("mover", json.dumps(ratio))
+    return out
+
+
 def field_solve_mms(sizes=(1024, 2048, 4096), rtol=1e-10, reps=3):
     """The field solve alone on the paper's manufactured-solution test (spherical
     r-z map, Omega = r, Eq. mms; Table t1's grids and tolerance): cycles, time
@@ -470,6 +531,10 @@ def main():
             extra["field_solve_mms"] = field_solve_mms()
         except Exception as e:
             extra["field_solve_mms"] = {"error": repr(e)}
+        try:
+            extra["mover_timing"] = mover_timing()
+        except Exception as e:
+            extra["mover_timing"] = {"error": repr(e)}
     n_p = r32["pushes"]
     out = {
         "metric": METRIC,
