@@ -196,9 +196,20 @@ def run_path(case, parts, precision, shape, steps, warmup, sort_every, mg_rtol, 
     return res
 
 
-def cpu_baseline(case, sample, shape):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case, sample, shape, single_sample=1 << 18):
     """The FP64 oracle (gather + Boris + exact map inversion + deposit) on the
-    host cores, on the first `sample` particles of each species."""
+    host cores, on the first `sample` particles of each species, with all of
+    the oracle's OpenMP threads; and on the first `single_sample` with one."""
     import oracle as O
     from paper_1311_2286_amd import workloads as W
     m = O.make_map(**case.map_args())
@@ -206,19 +217,33 @@ def cpu_baseline(case, sample, shape):
     nv = O.nverts(g)
     E = W.synthetic_ev(case, nv, dtype=np.float64, scale=0.05)
     S1 = 24 if case.dim == 2 else 16
-    t_total = 0.0
-    n_total = 0
-    for sid, s in enumerate(case.species):
-        p = W.to_oracle(W.generate_species(case, sid, dtype=np.float32, count=sample))
-        t0 = time.perf_counter()
-        cell, off, vel, _ = O.push(m, g, s.q / s.m, case.dt, case.B, p["cell"], p["off"], p["vel"], E)
-        O.deposit_fixed(g, shape, S1, cell, off)
-        t_total += time.perf_counter() - t0
-        n_total += p["cell"].size
     threads = O.num_threads()
-    return dict(value=n_total / t_total, unit="particle pushes/s", cores=threads, kind="oracle",
+
+    def run(count):
+        t_total, n_total = 0.0, 0
+        for sid, s in enumerate(case.species):
+            p = W.to_oracle(W.generate_species(case, sid, dtype=np.float32, count=count, workers=16))
+            t0 = time.perf_counter()
+            cell, off, vel, _ = O.push(m, g, s.q / s.m, case.dt, case.B, p["cell"], p["off"], p["vel"], E)
+            O.deposit_fixed(g, shape, S1, cell, off)
+            t_total += time.perf_counter() - t0
+            n_total += p["cell"].size
+            del p, cell, off, vel
+        return n_total, t_total
+
+    n_all, t_all = run(sample)
+    O.set_num_threads(1)
+    try:
+        n_one, t_one = run(single_sample)
+    finally:
+        O.set_num_threads(threads)
+    return dict(value=n_all / t_all, unit="particle pushes/s", cores=threads, kind="oracle",
                 sample="%d particles per species (first of each seeded stream), one "
-                       "gather+push+map-inversion+deposit pass, %.1f s" % (sample, t_total))
+                       "gather+push+map-inversion+deposit pass, %.1f s on %d threads"
+                       % (sample, t_all, threads),
+                single_thread_value=n_one / t_one,
+                single_thread_sample="%d particles per species, %.1f s on 1 thread" % (single_sample, t_one),
+                cpu_model=_cpu_model())
 
 
 def serving_requests(nreq, seed=1311):
@@ -457,7 +482,8 @@ def main():
     ap.add_argument("--mg-cycles", type=int, default=10)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    # about 10-20 s of oracle work on the box's 16 host threads
+    ap.add_argument("--cpu-sample", type=int, default=24 << 20)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (B1 deposit, probe, magnetised box)")
     ap.add_argument("--copy-calibrate", action="store_true",
@@ -519,6 +545,7 @@ def main():
     if not args.no_extra:
         for key, (name, shp, prec, steps, mover) in {
                 "box3d_128_b1": ("box3d_128", "b1", C.FP32, 10, 0),
+                "box3d_128_b1_fp64": ("box3d_128", "b1", C.FP64, 10, 0),
                 "box3d_128_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC),
                 "probe2d_512": ("probe2d_512", "b2", C.FP32, 20, 0),
                 "box3d_magnetized": ("box3d_magnetized", "b2", C.FP32, 10, 0)}.items():

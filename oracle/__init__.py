@@ -424,6 +424,10 @@ def num_threads() -> int:
     return int(lib().or_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    lib().or_set_num_threads(int(n))
+
+
 def philox4x32_10(ctr, key):
     c = np.ascontiguousarray(ctr, dtype=np.uint32)
     k = np.ascontiguousarray(key, dtype=np.uint32)

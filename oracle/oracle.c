@@ -1293,6 +1293,14 @@ int or_num_threads(void) {
 #endif
 }
 
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Injection of a Maxwellian at rest through the upper face of axis 0 (the   */
 /* outer wall), Sec. III: per step lambda = n0 v_th / sqrt(2 pi) * A dt / w   */
