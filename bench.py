@@ -420,6 +420,42 @@ def mover_timing(steps=200, dts=(0.001, 0.002, 0.004, 0.01, 0.025, 0.05)):
     return out
 
 
+def field_solve_anisotropic(N=2048, stretches=(10.0, 40.0), rtol=1e-10):
+    """The field solve on strongly anisotropic grids: identity map, N^2 cells,
+    box 1 x Ly (face-coefficient ratio Ly^2), Dirichlet walls, a smooth right
+    side, zero initial guess; the preconditioner relaxes along lines there."""
+    from paper_1311_2286_amd import cpic as C
+    import torch
+    xi = (np.arange(N) + 0.5) / N
+    u, v = np.meshgrid(xi, xi, indexing="xy")
+    charge = (np.sin(3 * np.pi * u) * np.sin(5 * np.pi * v)).ravel() / N ** 2
+    rows = []
+    for Ly in stretches:
+        cap, times = 400, []
+        for attempt in range(2):
+            sim = C.Sim(C.MAP_IDENTITY, 2, (N, N), L=(1.0, Ly), bc_lo=(1, 1), bc_hi=(1, 1), precision=C.FP64,
+                        mg_rtol=rtol, mg_max_cycles=cap)
+            try:
+                sim.set_field(C.FIELD_CHARGE, charge)
+                for r in range(3 if attempt else 1):
+                    sim.set_field(C.FIELD_PHI, np.zeros(N * N))
+                    sim.sync()
+                    t0 = time.perf_counter()
+                    sim.stage(C.STAGE_SOLVE)
+                    sim.sync()
+                    times.append(time.perf_counter() - t0)
+                d = sim.diag()
+            finally:
+                sim.close()
+            cap = d.mg_cycles + 2
+        rows.append({"grid": "%d^2" % N, "box": [1.0, Ly], "coefficient_ratio": Ly * Ly, "cycles": d.mg_cycles,
+                     "relres": d.mg_relres, "solve_ms": 1e3 * float(np.median(times[1:]))})
+        log("aniso", json.dumps(rows[-1]))
+    torch.cuda.empty_cache()
+    return {"workload": "field solve on stretched grids (identity map, Dirichlet walls), rtol %g" % rtol,
+            "grids": rows}
+
+
 def field_solve_mms(sizes=(1024, 2048, 4096), rtol=1e-10, reps=3):
     """The field solve alone on the paper's manufactured-solution test (spherical
     r-z map, Omega = r, Eq. mms; Table t1's grids and tolerance): cycles, time
@@ -558,6 +594,10 @@ def main():
             extra["field_solve_mms"] = field_solve_mms()
         except Exception as e:
             extra["field_solve_mms"] = {"error": repr(e)}
+        try:
+            extra["field_solve_anisotropic"] = field_solve_anisotropic()
+        except Exception as e:
+            extra["field_solve_anisotropic"] = {"error": repr(e)}
         try:
             extra["mover_timing"] = mover_timing()
         except Exception as e:

@@ -596,6 +596,142 @@ __global__ __launch_bounds__(256) void smooth_kernel(LevelArgsT<T> a, const T* _
   }
 }
 
+// Line relaxation on segments (anisotropic operators): every thread owns a
+// run of LINE_SEG consecutive cells along axis `ax`; the residual
+// r = rhs - A phi of the whole operator is formed for them, the tridiagonal
+// part of A along the axis restricted to the run is solved by Thomas
+// elimination (couplings to cells outside the run stay in r: block Jacobi over
+// runs), and out = phi + omega delta.  Sweeps along every axis in turn smooth
+// the error along whichever direction couples strongly, the role line
+// relaxation plays in the paper's solver on anisotropic problems.  Residuals,
+// diagonals and couplings go through LDS, so that every global access is
+// coalesced: along axis 0 the workgroup's runs cover one contiguous range of
+// cells (runs of 16 stored at a stride of 17 words, free of bank conflicts);
+// along the other axes the threads of a workgroup take adjacent columns.
+constexpr int LINE_SEG = 8;
+constexpr int LINE_PAD = LINE_SEG + 1;
+constexpr double LINE_OMEGA = 1.0;
+// line relaxation replaces the Chebyshev smoother of the preconditioner once
+// the operator's anisotropy (largest ratio of a cell's face coefficients)
+// exceeds this; below it the cheaper point smoother wins in time
+constexpr double LINE_ANISO = 50.0;
+
+template <typename T>
+__device__ inline void line_thomas(const T* lr_in, const T* ld, const T* lu, T* lr_out, int len, int step) {
+  // lower coupling of cell m = upper coupling of cell m - 1 (symmetric A)
+  T cp[LINE_SEG], dp[LINE_SEG];
+  T prev_cp = (T)0, prev_dp = (T)0, lo = (T)0;
+#pragma unroll
+  for (int m = 0; m < LINE_SEG; ++m) {
+    if (m < len) {
+      const T den = ld[m * step] - lo * prev_cp;
+      const T up = lu[m * step];
+      cp[m] = up / den;
+      dp[m] = (lr_in[m * step] - lo * prev_dp) / den;
+      prev_cp = cp[m];
+      prev_dp = dp[m];
+      lo = up;
+    }
+  }
+  T next = (T)0;
+#pragma unroll
+  for (int m = LINE_SEG - 1; m >= 0; --m) {
+    if (m < len) {
+      next = dp[m] - cp[m] * next;
+      lr_out[m * step] = next;
+    }
+  }
+}
+
+// runs along axis 0
+template <typename T>
+__global__ __launch_bounds__(256) void line_x_kernel(LevelArgsT<T> a, const T* __restrict__ phi,
+                                                     const T* __restrict__ rhs, T* out, T omega, const int* flag) {
+  __shared__ T lr[256 * LINE_PAD], ld[256 * LINE_PAD], lu[256 * LINE_PAD];
+  if (flag[0]) return;
+  const int n0 = a.n[0], n1 = a.n[1];
+  const long long nrows = (long long)n1 * a.n[2];
+  const int nseg = (n0 + LINE_SEG - 1) / LINE_SEG;
+  const long long total = (long long)nseg * nrows;
+  const long long t0 = (long long)blockIdx.x * 256;
+  const long long t1 = min(t0 + 255, total - 1);  // last run of the workgroup
+  const long long row0 = t0 / nseg, row1 = t1 / nseg;
+  const int s0 = (int)(t0 % nseg), s1 = (int)(t1 % nseg);
+  const long long cfirst = row0 * n0 + (long long)s0 * LINE_SEG;
+  const long long cend = row1 * n0 + min(n0, (s1 + 1) * LINE_SEG);
+  for (long long c = cfirst + threadIdx.x; c < cend; c += 256) {
+    const long long row = c / n0;
+    const int i = (int)(c - row * n0);
+    const int idx[3] = {i, (int)(row % n1), (int)(row / n1)};
+    const int m = i % LINE_SEG;
+    const long long run = (row - row0) * nseg + i / LINE_SEG - s0;
+    const int o = (int)run * LINE_PAD + m;
+    lr[o] = rhs[c] - apply_A(a, phi, idx, c);
+    ld[o] = a.diag[c];
+    lu[o] = (m + 1 < LINE_SEG && i + 1 < n0) ? (T)a.S[0][c] : (T)0;
+  }
+  __syncthreads();
+  const long long t = t0 + threadIdx.x;
+  if (t <= t1) {
+    const int sg = (int)(t % nseg);
+    const int len = min(LINE_SEG, n0 - sg * LINE_SEG);
+    const int o = threadIdx.x * LINE_PAD;
+    line_thomas(lr + o, ld + o, lu + o, lr + o, len, 1);
+  }
+  __syncthreads();
+  for (long long c = cfirst + threadIdx.x; c < cend; c += 256) {
+    const long long row = c / n0;
+    const int i = (int)(c - row * n0);
+    const long long run = (row - row0) * nseg + i / LINE_SEG - s0;
+    out[c] = phi[c] + omega * lr[(int)run * LINE_PAD + i % LINE_SEG];
+  }
+}
+
+// runs along axis 1 or 2: thread = column (adjacent along axis 0)
+template <typename T>
+__global__ __launch_bounds__(256) void line_yz_kernel(LevelArgsT<T> a, int ax, const T* __restrict__ phi,
+                                                      const T* __restrict__ rhs, T* out, T omega,
+                                                      const int* flag) {
+  __shared__ T lr[LINE_SEG * 256], ld[LINE_SEG * 256], lu[LINE_SEG * 256];
+  if (flag[0]) return;
+  const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+  const int nax = a.n[ax];
+  const int nseg = (nax + LINE_SEG - 1) / LINE_SEG;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)n0 * nseg * (ax == 1 ? n2 : n1);
+  const bool live = t < total;
+  int idx[3] = {0, 0, 0};
+  if (live) {
+    idx[0] = (int)(t % n0);
+    const long long r = t / n0;
+    if (ax == 1) {
+      idx[1] = (int)(r % nseg) * LINE_SEG;
+      idx[2] = (int)(r / nseg);
+    } else {
+      idx[1] = (int)(r % n1);
+      idx[2] = (int)(r / n1) * LINE_SEG;
+    }
+  }
+  const int start = idx[ax];
+  const int len = live ? min(LINE_SEG, nax - start) : 0;
+  const long long stride = ax == 1 ? (long long)n0 : (long long)n0 * n1;
+  const long long c0 = idx[0] + (long long)n0 * (idx[1] + (long long)n1 * idx[2]);
+  const int tx = threadIdx.x;
+  for (int m = 0; m < len; ++m) {
+    const long long c = c0 + m * stride;
+    int id[3] = {idx[0], idx[1], idx[2]};
+    id[ax] = start + m;
+    lr[m * 256 + tx] = rhs[c] - apply_A(a, phi, id, c);
+    ld[m * 256 + tx] = a.diag[c];
+    lu[m * 256 + tx] = (m + 1 < len) ? (T)a.S[ax][c] : (T)0;
+  }
+  if (len > 0) line_thomas(lr + tx, ld + tx, lu + tx, lr + tx, len, 256);
+  for (int m = 0; m < len; ++m) {
+    const long long c = c0 + m * stride;
+    out[c] = phi[c] + omega * lr[m * 256 + tx];
+  }
+}
+
 // Gershgorin bound of D^-1 A per cell: sum over off-diagonal |A_cj| / |A_cc|
 // (same neighbour pattern as apply_A); 1 + its maximum bounds the spectrum.
 __global__ __launch_bounds__(256) void gershgorin_kernel(LevelArgs a, double* out) {
@@ -1313,6 +1449,51 @@ void launch_extrapolate_guess(const GridCtx& G, int extrapolate, hipStream_t st)
   hipLaunchKernelGGL(extrapolate_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, L.phi, G.phi_prev, extrapolate);
 }
 
+// nu sweeps of segment line relaxation along every axis (phi -> phi2 -> phi ...;
+// nu * dim is even, so the result is back in phi)
+template <typename T>
+static void line_sweeps(const GridCtx& G, int l, int nu, bool reverse, hipStream_t st) {
+  const Level& L = G.lev[l];
+  const LevelArgsT<T> a = level_args_t<T>(G, l);
+  const LevelVec<T> v = level_vec<T>(G, l);
+  const int d = G.g.dim;
+  int k = 0;
+  for (int s = 0; s < nu; ++s)
+    for (int q = 0; q < d; ++q, ++k) {
+      const int ax = reverse ? d - 1 - q : q;
+      const T* in = (k & 1) ? v.phi2 : v.phi;
+      T* out = (k & 1) ? v.phi : v.phi2;
+      const long long nseg = (L.n[ax] + LINE_SEG - 1) / LINE_SEG;
+      const long long nthreads = nseg * (L.ncells / L.n[ax]);
+      const dim3 blocks((unsigned)((nthreads + 255) / 256));
+      if (ax == 0)
+        hipLaunchKernelGGL(line_x_kernel<T>, blocks, dim3(256), 0, st, a, in, (const T*)v.rhs, out, (T)LINE_OMEGA,
+                           (const int*)G.mg_flag);
+      else
+        hipLaunchKernelGGL(line_yz_kernel<T>, blocks, dim3(256), 0, st, a, ax, in, (const T*)v.rhs, out,
+                           (T)LINE_OMEGA, (const int*)G.mg_flag);
+    }
+}
+
+// the smoother of a multi-workgroup level: segment line relaxation for the
+// preconditioner of an anisotropic operator (its summed residual is not
+// needed there), Chebyshev otherwise
+template <typename T>
+static void smooth_level(const GridCtx& G, int l, int nu, bool post, double* partials, hipStream_t st,
+                         double* first_partials = nullptr, double rtol2 = 0.0) {
+  if constexpr (sizeof(T) == 4) {
+    // one sweep along every axis in place of two point-smoothing steps (2D;
+    // in 3D two, so that the result ends in phi), the post-smoothing in
+    // reverse axis order so that the V-cycle stays symmetric
+    const int nl = G.g.dim == 2 ? nu / 2 : nu;
+    if (G.anisotropy > LINE_ANISO && !partials && !first_partials && nl > 0 && (nl * G.g.dim) % 2 == 0) {
+      line_sweeps<T>(G, l, nl, post, st);
+      return;
+    }
+  }
+  chebyshev<T>(G, l, nu, partials, st, first_partials, rtol2);
+}
+
 // One V-cycle from level l in precision T.  With partials != null, the last
 // smoothing sweep on level 0 also sums the squared residual (of its input) per
 // block.
@@ -1346,7 +1527,7 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
   const LevelArgsT<T> a = level_args_t<T>(G, l);
   const LevelVec<T> v = level_vec<T>(G, l);
   const dim3 gr = grid3(L);
-  chebyshev<T>(G, l, nu1, nullptr, st, first_partials, rtol2);
+  smooth_level<T>(G, l, nu1, false, nullptr, st, first_partials, rtol2);
   const Level& C = G.lev[l + 1];
   const LevelVec<T> cv = level_vec<T>(G, l + 1);
   hipLaunchKernelGGL(residual_kernel<T>, gr, BLOCK3, 0, st, a, (const T*)v.phi, (const T*)v.rhs, v.res,
@@ -1360,7 +1541,7 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
   vcycle<T>(G, l + 1, nu1, nu2, nullptr, st);
   hipLaunchKernelGGL(prolong_kernel<T>, gr, BLOCK3, 0, st, a, v.phi, (const T*)cv.phi, C.n[0], C.n[1], C.n[2],
                      (const int*)G.mg_flag);
-  chebyshev<T>(G, l, nu2, partials, st);
+  smooth_level<T>(G, l, nu2, true, partials, st);
 }
 
 // ----------------------------------------------------------------------------
