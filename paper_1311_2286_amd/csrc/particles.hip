@@ -189,6 +189,19 @@ __device__ __forceinline__ bool move_delta(const Geo& g, const int* idx, const R
   return conv && !low_j;
 }
 
+// LDS window of vertex data of a tile: its vertices and a one-cell halo
+template <int D> struct FieldWindow {
+  static constexpr int E0 = TileShape<D>::T0 + 3, E1 = TileShape<D>::T1 + 3, E2 = (D == 3) ? TileShape<D>::T2 + 3 : 1;
+  static constexpr int N = E0 * E1 * E2;
+  static constexpr int C = D;  // packed components per vertex
+};
+
+__device__ inline int wrap_local(int v, int origin, int n, bool periodic) {
+  int l = v - origin;
+  if (periodic) l = l < -n / 2 ? l + n : (l >= n - n / 2 ? l - n : l);
+  return l;
+}
+
 // values per vertex in the kc table: D x D padded to a multiple of 4
 template <int D> constexpr int KC_STRIDE = D == 3 ? 12 : 4;
 
@@ -229,16 +242,53 @@ __device__ __forceinline__ void kc_interp(const Geo& g, const R* __restrict__ kc
   }
 }
 
+// kc at (cidx, cf) from the tile's LDS copy of the table (D x D values per
+// vertex, the window of the field: the tile and a one-cell halo); false when a
+// vertex of the cell lies outside it.  Same weights and summation order as
+// kc_interp, so both give identical sums.
+template <int D, typename R>
+__device__ __forceinline__ bool kc_interp_window(const R* __restrict__ kwin, const Geo& g, const int* origin,
+                                                 const int* cidx, const R* cf, R* k) {
+  using FW = FieldWindow<D>;
+  const int Ew[3] = {FW::E0, FW::E1, FW::E2};
+  int l[3] = {0, 0, 0};
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    l[a] = wrap_local(cidx[a], origin[a] - 1, g.n[a], g.periodic[a] != 0);
+    in = in && l[a] >= 0 && l[a] + 1 < Ew[a];
+  }
+  if (!in) return false;
+  constexpr int KD = D * D;
+  const R* k0 = kwin + KD * (l[0] + FW::E0 * (l[1] + FW::E1 * l[2]));
+#pragma unroll
+  for (int e = 0; e < KD; ++e) k[e] = (R)0;
+#pragma unroll
+  for (int corner = 0; corner < (1 << D); ++corner) {
+    R w = (R)1;
+    int off = 0;
+#pragma unroll
+    for (int ax = D - 1; ax >= 0; --ax) {
+      const int c = (corner >> ax) & 1;
+      w *= c ? cf[ax] : (R)1 - cf[ax];
+      off += c * (ax == 0 ? 1 : (ax == 1 ? FW::E0 : FW::E0 * FW::E1));
+    }
+#pragma unroll
+    for (int e = 0; e < KD; ++e) k[e] += w * k0[KD * off + e];
+  }
+  return true;
+}
+
 // Predictor-corrector position update (Eqs. step2-step4) in cells:
 //   predictor  u' = (idx + f) + (dt/2) kc(idx, f) v,
 //   corrector  d  = dt kc(u') v,
 // the predictor point wrapped on periodic axes and clamped into the grid on
 // bounded ones for the interpolation of kc.
-template <int D, typename R>
-__device__ __forceinline__ void move_pc(const Geo& g, const R* __restrict__ kc, const int* idx, const R* f,
-                                        const R* v, R dt, R* d) {
+template <int D, typename R, bool WIN>
+__device__ __forceinline__ void move_pc(const Geo& g, const R* __restrict__ kc, const R* __restrict__ kwin,
+                                        const int* origin, const int* idx, const R* f, const R* v, R dt, R* d) {
   R k[D * D];
-  kc_interp<D, R>(g, kc, idx, f, k);
+  if (!(WIN && kc_interp_window<D, R>(kwin, g, origin, idx, f, k))) kc_interp<D, R>(g, kc, idx, f, k);
   int pidx[3] = {0, 0, 0};
   R pf[3] = {(R)0, (R)0, (R)0};
   const R h = (R)0.5 * dt;
@@ -265,7 +315,7 @@ __device__ __forceinline__ void move_pc(const Geo& g, const R* __restrict__ kc, 
     pidx[a] = i;
     pf[a] = fr;
   }
-  kc_interp<D, R>(g, kc, pidx, pf, k);
+  if (!(WIN && kc_interp_window<D, R>(kwin, g, origin, pidx, pf, k))) kc_interp<D, R>(g, kc, pidx, pf, k);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     R s = (R)0;
@@ -580,18 +630,6 @@ __device__ __forceinline__ void count_new_tile(const Geo& g, const int* idx, int
 // that particles up to one cell outside the tile (drift since the last sort)
 // gather from LDS.  Components are packed (2 in 2D, 3 in 3D; the padding slot
 // of the global array is not staged).
-template <int D> struct FieldWindow {
-  static constexpr int E0 = TileShape<D>::T0 + 3, E1 = TileShape<D>::T1 + 3, E2 = (D == 3) ? TileShape<D>::T2 + 3 : 1;
-  static constexpr int N = E0 * E1 * E2;
-  static constexpr int C = D;  // packed components per vertex
-};
-
-__device__ inline int wrap_local(int v, int origin, int n, bool periodic) {
-  int l = v - origin;
-  if (periodic) l = l < -n / 2 ? l + n : (l >= n - n / 2 ? l - n : l);
-  return l;
-}
-
 // Same weights and summation order as gather_E, so both give identical sums.
 template <int D, typename R>
 __device__ __forceinline__ bool gather_E_window(const R* __restrict__ ewin, const Geo& g, const int* origin,
@@ -657,6 +695,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
   typedef typename std::conditional<FIXED, unsigned long long, double>::type QT;
   __shared__ QT win[TS::WIN];
   __shared__ R ewin[FW::N * FW::C];
+  // predictor-corrector (FP32): the k table of the same window in LDS
+  constexpr bool KWIN = MAP == MAP_TABLE_PC && std::is_same<R, float>::value;
+  constexpr int KD = D * D;
+  __shared__ R kwin[KWIN ? FW::N * KD : 1];
   __shared__ double red_d[8];
   __shared__ unsigned long long red_u[8][5];
   __shared__ int tbins[TB_N];  // new tiles of the particles (see count_new_tile)
@@ -698,6 +740,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
       if (ok) {
 #pragma unroll
         for (int c = 0; c < FW::C; ++c) ewin[s * FW::C + c] = a.Ev[v * EC + c];
+        if constexpr (KWIN) {
+#pragma unroll
+          for (int e = 0; e < KD; ++e) kwin[s * KD + e] = a.kc[v * KC_STRIDE<D> + e];
+        }
       }
     }
   }
@@ -761,7 +807,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
       R d[3] = {(R)0, (R)0, (R)0};
       bool conv;
       if constexpr (MAP == MAP_TABLE_PC) {
-        move_pc<D, R>(g, a.kc, idx, f, v, a.dt, d);
+        move_pc<D, R, KWIN>(g, a.kc, kwin, origin, idx, f, v, a.dt, d);
         conv = true;
       } else
         conv = move_delta<D, MAP, R>(g, idx, f, v, a.dt, a.inv_dxc, a.newton_maxit, a.newton_tol,
