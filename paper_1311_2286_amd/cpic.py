@@ -203,8 +203,15 @@ def _pad(t, v):
     return tuple(t)[:3] + (v,) * (3 - len(tuple(t)[:3]))
 
 
-def make_map_desc(map_kind, dim, L=(1.0, 1.0, 1.0), eps=0.0, r_in=1.0, r_out=2.0, omega=0):
-    return MapDesc(map_kind, dim, (ctypes.c_double * 3)(*_pad(L, 1.0)), eps, r_in, r_out, int(omega))
+def make_map_desc(map_kind, dim, L=(1.0, 1.0, 1.0), eps=0.0, r_in=1.0, r_out=2.0, omega=0, vertices=None):
+    """vertices: a tabulated map's (dim, nverts) float64 array; the caller keeps
+    it alive until the descriptor has been used (cpic_create, or a server submit,
+    which copies it)."""
+    ptr = None
+    if vertices is not None:
+        assert vertices.dtype == np.float64 and vertices.flags["C_CONTIGUOUS"]
+        ptr = vertices.ctypes.data
+    return MapDesc(map_kind, dim, (ctypes.c_double * 3)(*_pad(L, 1.0)), eps, r_in, r_out, int(omega), ptr)
 
 
 def make_grid_desc(n, bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), phi_lo=(0.0, 0.0, 0.0),

@@ -121,3 +121,37 @@ def test_admission_by_budget_and_a_case_that_never_fits():
     assert res[0]["status"] == 0 and res[2]["status"] == 0
     assert res[1]["status"] == -4  # CPIC_E_BUDGET
     assert st["failed"] == 1 and st["completed"] == 2
+
+
+def test_tabulated_map_case_is_copied_at_submit_and_matches_a_plain_run():
+    # a case on a map known at its vertices (the sinusoidal map sampled there),
+    # moved by the predictor-corrector update; the vertex table is overwritten
+    # right after submit: the server works from its own copy
+    c = C()
+    case = serving_case(48, 0.10, 12.0, 1.0, 420)
+    vt = np.ascontiguousarray(W.vertex_table(case))
+    m = c.make_map_desc(c.MAP_TABULATED, 2, W.table_shift(case), vertices=vt)
+    g = c.make_grid_desc(case.n, shape=c.SHAPE_B2, precision=c.FP32, dt=case.dt, background=True,
+                         background_n0=1.0, mg_rtol=1e-10, mg_max_cycles=40, sort_every=4, mover=c.MOVER_PC)
+    sp = [c.make_species_desc(s.q, s.m, case.weight(s)) for s in case.species]
+    parts = [W.generate_species(case, 0, dtype=np.float32)]
+    srv = c.Server(1 << 30, 2)
+    t = srv.submit(m, g, sp, parts, NSTEPS, want_phi=True)
+    vt[:] = np.nan
+    for _ in range(100000):
+        if srv.pump(8):
+            break
+    res = srv.poll(t)
+    srv.close()
+    assert res["status"] == 0 and res["steps"] == NSTEPS
+    sim = c.Sim(c.MAP_TABULATED, 2, case.n, L=W.table_shift(case), dt=case.dt, background=True, mg_rtol=1e-10,
+                mg_max_cycles=40, sort_every=4, mover=c.MOVER_PC, vertices=W.vertex_table(case))
+    sim.add_species(case.species[0].q, case.species[0].m, case.weight(case.species[0]), parts[0]["cell"].size)
+    sim.set_particles(0, parts[0]["cell"], parts[0]["off"], parts[0]["vel"])
+    sim.initialize()
+    sim.step(NSTEPS)
+    d = sim.diag()
+    assert abs(d.kinetic - res["kinetic"]) <= 1e-13 * abs(d.kinetic)
+    assert d.field_energy == res["field_energy"]
+    assert np.array_equal(sim.get_field(c.FIELD_PHI), res["phi"])
+    sim.close()
