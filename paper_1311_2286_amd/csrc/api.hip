@@ -926,13 +926,15 @@ static void solve_pass(cpic_sim* s, int cycles = -1) {
   launch_gauge(s->G, s->stream);
 }
 
-// Cycles to launch in a time step: two more than the last solve whose count
+// Cycles to launch in a time step: one more than the last solve whose count
 // has reached the host (copied back asynchronously), at most the cap; the cap
-// until a count is known.
+// until a count is known.  The count moves slowly from step to step; a solve
+// that would need more stops at the launched count, its relative residual in
+// the diagnostics, and the next step launches more.
 static int step_cycles(const cpic_sim* s) {
   const int last = s->cycles_host ? *(volatile int*)s->cycles_host : -1;
   if (last < 0 || !s->cycles_known) return s->grid.mg_max_cycles;
-  return std::min(s->grid.mg_max_cycles, last + 2);
+  return std::min(s->grid.mg_max_cycles, last + 1);
 }
 
 static void record_cycles(cpic_sim* s) {
