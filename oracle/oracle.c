@@ -307,11 +307,87 @@ static double sin_product(int d, const double* xi) {
   return P;
 }
 
+/* The tabulated map inside one cell (lower vertex `base`, indices taken with
+   periodic continuation): x(f) = sum over the cell's 2^d vertices of
+   prod_a (1 - f_a or f_a) X_vertex, the multilinear interpolant of the vertex
+   coordinates, and its derivative jf[a][b] = dx^a / df_b.  f may lie outside
+   [0, 1]: the cell's polynomial extended (used beyond a wall). */
+static void tab_cell(const or_map* m, const int* base, const double* f, double* x, double jf[3][3]) {
+  int d = m->dim;
+  for (int a = 0; a < 3; ++a) {
+    x[a] = 0.0;
+    for (int b = 0; b < 3; ++b) jf[a][b] = 0.0;
+  }
+  for (int c = 0; c < (1 << d); ++c) {
+    int iv[3] = {0, 0, 0};
+    double w = 1.0, dw[3] = {1.0, 1.0, 1.0};
+    for (int a = 0; a < d; ++a) {
+      int up = (c >> a) & 1;
+      iv[a] = base[a] + up;
+      double wa = up ? f[a] : 1.0 - f[a];
+      for (int b = 0; b < d; ++b) dw[b] *= (b == a) ? (up ? 1.0 : -1.0) : wa;
+      w *= wa;
+    }
+    double xv[3];
+    tab_x(m, iv, xv);
+    for (int a = 0; a < d; ++a) {
+      x[a] += w * xv[a];
+      for (int b = 0; b < d; ++b) jf[a][b] += dw[b] * xv[a];
+    }
+  }
+}
+
+/* Inverse of the tabulated map by Newton iterations on the position u in
+   cells, starting at xi_old (or the grid centre): each iteration takes the
+   cell holding u (on a bounded axis the boundary cell beyond the wall, whose
+   polynomial is extended there), solves its linearisation at u and moves u,
+   at most one cell per axis per iteration; converged when the step is below
+   1e-14 cell. */
+static int tab_invert(const or_map* m, const double* x, const double* xi_old, double* xi) {
+  int d = m->dim;
+  int n[3] = {1, 1, 1};
+  double u[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < d; ++a) {
+    n[a] = tab_cells(m, a);
+    u[a] = xi_old ? xi_old[a] * n[a] : 0.5 * n[a];
+  }
+  for (int it = 0; it < 500; ++it) {
+    int base[3] = {0, 0, 0};
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) {
+      int c = (int)floor(u[a]);
+      if (!m->tper[a]) c = c < 0 ? 0 : (c > n[a] - 1 ? n[a] - 1 : c);
+      base[a] = c;
+      f[a] = u[a] - c;
+    }
+    double xc[3], jf[3][3], k[3][3], du[3];
+    tab_cell(m, base, f, xc, jf);
+    for (int a = d; a < 3; ++a) jf[a][a] = 1.0;
+    inv_d(d, jf, k);
+    double big = 0.0;
+    for (int a = 0; a < d; ++a) {
+      du[a] = 0.0;
+      for (int b = 0; b < d; ++b) du[a] += k[a][b] * (x[b] - xc[b]);
+      if (fabs(du[a]) > big) big = fabs(du[a]);
+    }
+    double scale = big > 1.0 ? 1.0 / big : 1.0;
+    for (int a = 0; a < d; ++a) u[a] += scale * du[a];
+    if (big < 1e-14) {
+      for (int a = 0; a < 3; ++a) xi[a] = (a < d) ? u[a] / n[a] : 0.0;
+      return 0;
+    }
+  }
+  for (int a = 0; a < 3; ++a) xi[a] = (a < d) ? u[a] / n[a] : 0.0;
+  return -1;
+}
+
 /* Returns 0 on success.  xi_old is used only to pick the periodic image of the
-   angular coordinate of the polar map. */
+   angular coordinate of the polar map, and the starting cell of a tabulated
+   map's inversion. */
 static int map_invert(const or_map* m, const double* x, const double* xi_old, double* xi) {
   int d = m->dim;
   for (int a = 0; a < 3; ++a) xi[a] = 0.0;
+  if (m->kind == OR_TABULATED) return tab_invert(m, x, xi_old, xi);
   if (m->kind == OR_IDENTITY) {
     for (int a = 0; a < d; ++a) xi[a] = x[a] / m->L[a];
     return 0;

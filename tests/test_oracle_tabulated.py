@@ -13,7 +13,12 @@ Expected values, none computed by the tabulated map itself:
     coefficients converge to the analytic ones at second order in h (error
     ratio 4 per doubling);
   - Poisson solves and the predictor-corrector mover on the sampled map
-    converge at second order to those on the analytic map."""
+    converge at second order to those on the analytic map;
+  - the inverse of the tabulated map (the piecewise multilinear interpolant
+    of the vertex coordinates): round trips to 1e-12, an affine map inverted
+    exactly (also beyond its walls, where the boundary cells' polynomials
+    continue), and the hybrid mover with this inversion within O(h^2) of the
+    mover on the analytic map."""
 import numpy as np
 import pytest
 
@@ -181,3 +186,67 @@ def test_pc_mover_on_the_sampled_map_converges_second_order():
     e = np.array(errs)
     r = e[:-1] / e[1:]
     assert abs(r[-1] - 4.0) < 0.3 and np.all(r > 3.0), (e, r)
+
+
+def test_inverse_of_the_tabulated_map():
+    # round trip inside the grid, from a nearby old position, on the sampled
+    # sinusoidal map (periodic) and the sampled annulus (walls); an affine map
+    # is inverted exactly (closed form A^-1 (x - b))
+    rng = np.random.default_rng(11)
+    m = O.make_map(O.SINUSOIDAL, 2, (1.0, 1.0), 0.1)
+    t = O.make_tabulated_map(2, (24, 20), (1, 1), O.sample_map_vertices(m, (24, 20), (1, 1)))
+    xi = np.zeros((400, 3))
+    xi[:, :2] = rng.random((400, 2))
+    x = O.map_eval(t, xi)[0]
+    old = xi.copy()
+    old[:, :2] += rng.normal(scale=0.05, size=(400, 2))
+    back = O.map_invert(t, x, old)
+    dd = back[:, :2] - xi[:, :2]
+    assert np.abs(dd - np.round(dd)).max() < 1e-12
+    A = np.array([[2.0, 0.3], [-0.4, 1.5]])
+    bvec = np.array([0.2, -0.1])
+    n = (7, 5)
+    xv = _vertices(n, (0, 0))
+    ta = O.make_tabulated_map(2, n, (0, 0), (xv[:, :2] @ A.T + bvec).T)
+    pts = np.zeros((300, 3))
+    pts[:, :2] = rng.random((300, 2)) * 1.2 - 0.1  # some beyond the walls: the extended map
+    y = np.zeros((300, 3))
+    y[:, :2] = pts[:, :2] @ A.T + bvec
+    inv = O.map_invert(ta, y, np.full((300, 3), 0.5))
+    np.testing.assert_allclose(inv[:, :2], pts[:, :2], atol=1e-12)
+
+
+def test_exact_mover_on_the_sampled_map_converges_second_order():
+    # the hybrid mover with exact inversion of the tabulated (piecewise
+    # multilinear) map tends to the mover on the analytic map as h^2: the
+    # difference is that of the interpolation error of x at the old and the
+    # new position, O(h^2) but oscillating on the grid scale, so the bar is
+    # the envelope: err N^2 about constant, a factor >= 8 over two doublings
+    m = O.make_map(O.SINUSOIDAL, 2, (1.0, 1.0), 0.1)
+    rng = np.random.default_rng(12)
+    npart = 400
+    xi0 = rng.random((npart, 2))
+    vel = np.zeros((npart, 3))
+    vel[:, :2] = rng.normal(size=(npart, 2))
+    errs = []
+    for N in (32, 64, 128):
+        n = (N, N)
+        g = O.make_grid(n)
+        t = O.make_tabulated_map(2, n, (1, 1), O.sample_map_vertices(m, n, (1, 1)))
+        u = xi0 * N
+        idx = np.floor(u).astype(np.int64)
+        cell = (idx[:, 0] + N * idx[:, 1]).astype(np.int32)
+        off = np.zeros((npart, 3))
+        off[:, :2] = u - idx
+        Ev = np.zeros((N * N, 3))
+        res = []
+        for mm in (m, t):
+            c, o, _, _ = O.push(mm, g, -1.0, 0.05, (0.0, 0.0, 0.0), cell, off, vel, Ev)
+            ci = np.stack([c % N, c // N], axis=1)
+            res.append((ci + o[:, :2]) / N)
+        d = res[1] - res[0]
+        d -= np.round(d)
+        errs.append(np.abs(d).max())
+    e = np.array(errs)
+    scaled = e * np.array([32, 64, 128]) ** 2
+    assert e[0] / e[-1] >= 8 and scaled.max() <= 2 * scaled.min(), (e, scaled)
