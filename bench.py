@@ -119,11 +119,16 @@ def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, grap
         if _STREAM is None:
             _STREAM = torch.cuda.Stream()
         stream = _STREAM.cuda_stream
-    sim = C.Sim(case.map_kind, case.dim, case.n, L=case.L, eps=case.eps, r_in=case.r_in,
+    from paper_1311_2286_amd import workloads as W
+    kind, L, vertices = case.map_kind, case.L, None
+    if case.tabulated:  # the map known at its vertices only
+        kind, L, vertices = C.MAP_TABULATED, W.table_shift(case), W.vertex_table(case)
+    sim = C.Sim(kind, case.dim, case.n, L=L, eps=case.eps, r_in=case.r_in,
                 r_out=case.r_out, bc_lo=case.bc_lo, bc_hi=case.bc_hi, phi_lo=case.phi_lo,
                 phi_hi=case.phi_hi, shape=shape, precision=precision, dt=case.dt, B0=case.B,
                 background=case.background, mg_rtol=mg_rtol, mg_max_cycles=mg_cycles,
-                sort_every=sort_every, track_ids=False, stream=stream, mover=mover)
+                sort_every=sort_every, track_ids=False, stream=stream, mover=mover, vertices=vertices)
+    del vertices
     if graphs:
         sim.set_graphs(True)
     bounded = any(b != 0 for b in case.bc_lo[: case.dim])
@@ -331,12 +336,17 @@ def run_serving(nreq, nsteps, budget, slots, load, mg_rtol, mg_cycles, seed=1311
             "budget_bytes": budget, "slots": slots}
 
 
-def extra_workload(name, shape_name, precision, steps, warmup, sort_every, mg_rtol, mg_cycles, mover=0):
-    """Throughput of another workload (same fields as the headline path)."""
+def extra_workload(name, shape_name, precision, steps, warmup, sort_every, mg_rtol, mg_cycles, mover=0,
+                   tabulated=False):
+    """Throughput of another workload (same fields as the headline path);
+    tabulated: on its map sampled at the vertices (a tabulated map)."""
     from paper_1311_2286_amd import cpic as C
     from paper_1311_2286_amd import workloads as W
+    import dataclasses
     import torch
     case = workload(name)
+    if tabulated:
+        case = dataclasses.replace(case, tabulated=True)
     shape = C.SHAPE_B2 if shape_name == "b2" else C.SHAPE_B1
     t0 = time.time()
     parts = [W.generate_species(case, sid, dtype=np.float64 if precision == C.FP64 else np.float32,
@@ -346,8 +356,9 @@ def extra_workload(name, shape_name, precision, steps, warmup, sort_every, mg_rt
     r = run_path(case, parts, precision, shape, steps, warmup, sort_every, mg_rtol, mg_cycles, mover=mover)
     del parts
     torch.cuda.empty_cache()
-    out = {"workload": "%s, %s deposit, %s%s" % (name, shape_name.upper(), "FP64" if precision else "FP32",
-                                                ", predictor-corrector mover" if mover else ""),
+    out = {"workload": "%s%s, %s deposit, %s%s" % (name, ", tabulated map" if tabulated else "", shape_name.upper(),
+                                                  "FP64" if precision else "FP32",
+                                                  ", predictor-corrector mover" if mover else ""),
            "particles": r["pushes"], "steps": steps, "pushes_per_s": r["pushes_per_s"],
            "ms_per_step": r["ms_per_step"], "p50_step_ms": r["p50_step_ms"], "p99_step_ms": r["p99_step_ms"],
            "particle_kernel_pushes_per_s": r["kernel_pushes_per_s"], "achieved_GBs": r["achieved_GBs"],
@@ -579,15 +590,17 @@ def main():
         log("cpu", json.dumps(cpu))
     extra = {}
     if not args.no_extra:
-        for key, (name, shp, prec, steps, mover) in {
-                "box3d_128_b1": ("box3d_128", "b1", C.FP32, 10, 0),
-                "box3d_128_b1_fp64": ("box3d_128", "b1", C.FP64, 10, 0),
-                "box3d_128_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC),
-                "probe2d_512": ("probe2d_512", "b2", C.FP32, 20, 0),
-                "box3d_magnetized": ("box3d_magnetized", "b2", C.FP32, 10, 0)}.items():
+        for key, (name, shp, prec, steps, mover, tab) in {
+                "box3d_128_b1": ("box3d_128", "b1", C.FP32, 10, 0, False),
+                "box3d_128_b1_fp64": ("box3d_128", "b1", C.FP64, 10, 0, False),
+                "box3d_128_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC, False),
+                "box3d_128_tabulated": ("box3d_128", "b2", C.FP32, 10, 0, True),
+                "box3d_128_tabulated_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC, True),
+                "probe2d_512": ("probe2d_512", "b2", C.FP32, 20, 0, False),
+                "box3d_magnetized": ("box3d_magnetized", "b2", C.FP32, 10, 0, False)}.items():
             try:
                 extra[key] = extra_workload(name, shp, prec, steps, 2, args.sort_every, args.mg_rtol,
-                                            args.mg_cycles, mover)
+                                            args.mg_cycles, mover, tab)
             except Exception as e:  # reported, never fatal for the headline line
                 extra[key] = {"error": repr(e)}
         try:

@@ -82,8 +82,12 @@ typedef enum {
    J, g^ij and k come from finite differences of the vertex coordinates (Sec.
    "Curvilinear formulation"): centred over the two neighbours, second-order
    one-sided at the ends of a bounded axis, blended multilinearly between
-   vertices.  Particles move with CPIC_MOVER_PC only (no analytic map to invert)
-   and cannot be injected; with walls the map must be orthogonal, up to its
+   vertices.  For the position update the map between vertices is the
+   multilinear interpolant of the vertex coordinates: CPIC_MOVER_NEWTON inverts
+   it by Newton iterations on the position in cells (FP64, the polynomial of
+   the cell holding the iterate, continued beyond a wall by the boundary
+   cell's), CPIC_MOVER_PC uses the inverse-Jacobian table as on any map.
+   Particles cannot be injected; with walls the map must be orthogonal, up to its
    sampling error, in every plane that holds a bounded axis (the columns of j
    within acos(0.05) of a right angle at every vertex, else
    CPIC_E_UNSUPPORTED); J <= 0 at a vertex or cell centre gives CPIC_E_MAP. */

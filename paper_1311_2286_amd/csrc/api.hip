@@ -553,8 +553,6 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
     return fail(s, CPIC_E_ARG, "bad species descriptor");
   if (s->g.kind == CPIC_MAP_SPHERICAL_RZ || s->g.omega)
     return fail(s, CPIC_E_UNSUPPORTED, "the spherical r-z map and Omega = r serve the field solve only");
-  if (s->g.kind == CPIC_MAP_TABULATED && s->grid.mover != CPIC_MOVER_PC)
-    return fail(s, CPIC_E_UNSUPPORTED, "a tabulated map moves particles with the predictor-corrector update");
   const int d = s->g.dim;
   for (int a = 0; a < d; ++a) {
     bool per = s->g.periodic[a];

@@ -129,9 +129,114 @@ __device__ inline void boris_push(R* v, const R* E, const R* B, R qm, R dt, bool
 // settle: the physical displacement is split into m equal parts (continuation)
 // so that each part moves the particle by at most a quarter cell in logical
 // space, and each part is solved by Newton from the end of the previous one.
+// Tabulated map, the mover's view: between vertices the map is the
+// multilinear interpolant of the vertex coordinates (piecewise multilinear,
+// continuous).  x and J = dx/du at u (cells) from the cell holding u; on a
+// bounded axis the boundary cell's polynomial continues beyond the wall.
+template <int D>
+__device__ inline void tab_cell_xj(const Geo& g, const double* u, double* x, double (*J)[3]) {
+  int base[3] = {0, 0, 0};
+  double f[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int c = (int)floor(u[a]);
+    if (!g.periodic[a]) c = min(max(c, 0), g.n[a] - 1);
+    base[a] = c;
+    f[a] = u[a] - c;
+    x[a] = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) J[a][b] = 0.0;
+  }
+#pragma unroll
+  for (int corner = 0; corner < (1 << D); ++corner) {
+    double w = 1.0, dw[3] = {1.0, 1.0, 1.0}, per[3] = {0.0, 0.0, 0.0};
+    long long v = 0, stride = 1;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int up = (corner >> a) & 1;
+      int i = base[a] + up;
+      const double wa = up ? f[a] : 1.0 - f[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b) dw[b] *= (b == a) ? (up ? 1.0 : -1.0) : wa;
+      w *= wa;
+      if (g.periodic[a]) {
+        int r = i % g.n[a];
+        if (r < 0) r += g.n[a];
+        per[a] = (double)((i - r) / g.n[a]);
+        i = r;
+      }
+      v += stride * i;
+      stride *= g.nv[a];
+    }
+    const double* xv = g.xtab + v * D;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double xa = xv[a] + per[a] * g.L[a];
+      x[a] += w * xa;
+#pragma unroll
+      for (int b = 0; b < D; ++b) J[a][b] += dw[b] * xa;
+    }
+  }
+}
+
+// x^{-1}(x(u0) + disp) on a tabulated map by Newton on the position u in cells
+// (each iteration with the polynomial of the cell holding u, a step of at most
+// one cell per axis); d = u - u0.  Converged once a step is below 1e-9 cell.
+template <int D>
+__device__ inline bool move_tab(const Geo& g, const int* idx, const double* f0, const double* disp, int maxit,
+                                double* d) {
+  double u0[3] = {0.0, 0.0, 0.0}, u[3], tgt[3], x[3], J[3][3];
+#pragma unroll
+  for (int a = 0; a < D; ++a) u0[a] = idx[a] + f0[a];
+  tab_cell_xj<D>(g, u0, x, J);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = u0[a];
+    tgt[a] = a < D ? x[a] + disp[a] : 0.0;
+  }
+  bool conv = false;
+  for (int it = 0; it < maxit; ++it) {
+    if (it > 0) tab_cell_xj<D>(g, u, x, J);
+    double r[3] = {0.0, 0.0, 0.0}, du[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) r[a] = tgt[a] - x[a];
+    if (D == 2) {
+      const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      du[0] = (J[1][1] * r[0] - J[0][1] * r[1]) / det;
+      du[1] = (J[0][0] * r[1] - J[1][0] * r[0]) / det;
+    } else {
+      const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1], c01 = J[0][2] * J[2][1] - J[0][1] * J[2][2],
+                   c02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+      const double c10 = J[1][2] * J[2][0] - J[1][0] * J[2][2], c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0],
+                   c12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+      const double c20 = J[1][0] * J[2][1] - J[1][1] * J[2][0], c21 = J[0][1] * J[2][0] - J[0][0] * J[2][1],
+                   c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      const double det = J[0][0] * c00 + J[0][1] * c10 + J[0][2] * c20;
+      du[0] = (c00 * r[0] + c01 * r[1] + c02 * r[2]) / det;
+      du[1] = (c10 * r[0] + c11 * r[1] + c12 * r[2]) / det;
+      du[2] = (c20 * r[0] + c21 * r[1] + c22 * r[2]) / det;
+    }
+    double big = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) big = fmax(big, fabs(du[a]));
+    if (!(big < 1e30)) break;  // singular cell: not converged
+    const double sc = big > 1.0 ? 1.0 / big : 1.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) u[a] += sc * du[a];
+    if (big < 1e-9) {
+      conv = true;
+      break;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) d[a] = u[a] - u0[a];
+  return conv;
+}
+
 template <int D, int MAP>
 __device__ __forceinline__ bool move_fallback(const Geo& g, const int* idx, const double* f0,
                                               const double* disp, double kappa, double* d) {
+  if constexpr (MAP == MAP_TABULATED) return move_tab<D>(g, idx, f0, disp, 96, d);
   double dt0[3] = {0.0, 0.0, 0.0};
   double J = 1.0;
   double est[3] = {0.0, 0.0, 0.0};
@@ -687,7 +792,7 @@ __device__ __forceinline__ bool gather_E_window(const R* __restrict__ ewin, cons
 }
 
 template <int D, int MAP, int SHAPE, typename R, bool FIXED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && MAP != MAP_TABULATED) ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel(
     PartArgs<R> a) {
   using TS = TileShape<D>;
   using FW = FieldWindow<D>;
@@ -809,6 +914,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIXED ? ((D
       if constexpr (MAP == MAP_TABLE_PC) {
         move_pc<D, R, KWIN>(g, a.kc, kwin, origin, idx, f, v, a.dt, d);
         conv = true;
+      } else if constexpr (MAP == MAP_TABULATED) {
+        double f64[3] = {(double)f[0], (double)f[1], (double)f[2]}, disp[3], dd[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) disp[ax] = (double)a.dt * (double)v[ax];
+        conv = move_tab<D>(g, idx, f64, disp, 16, dd);
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) d[ax] = (R)dd[ax];
       } else
         conv = move_delta<D, MAP, R>(g, idx, f, v, a.dt, a.inv_dxc, a.newton_maxit, a.newton_tol,
                                         a.kappa, d);
@@ -1529,6 +1641,11 @@ static int launch_particle_r(const ParticleLaunch& L, hipStream_t st) {
   if (L.kc) {
     if (D == 2) return launch_particle_shape<2, MAP_TABLE_PC, R>(L, st);
     if (D == 3) return launch_particle_shape<3, MAP_TABLE_PC, R>(L, st);
+    return -1;
+  }
+  if (M == MAP_TABULATED) {
+    if (D == 2) return launch_particle_shape<2, MAP_TABULATED, R>(L, st);
+    if (D == 3) return launch_particle_shape<3, MAP_TABULATED, R>(L, st);
     return -1;
   }
   if (D == 2) {

@@ -8,9 +8,11 @@ Cases: the 2D and 3D sinusoidal maps (periodic, mixed terms) and the
 polar-log annulus with walls, each sampled at its vertices.  The GPU solve on
 the sampled map converges at second order (or faster) in h to the solve on
 the analytic map (difference ratio at least 3.5 per doubling).  Tables that fold, or that are not
-orthogonal at walls, are refused at creation; species need the
-predictor-corrector mover.  (Pushes and full steps on tabulated maps are in
-the predictor-corrector tests.)"""
+orthogonal at walls, are refused at creation.  Pushes with the Newton
+mover (inverting the multilinear interpolant of the vertex coordinates) match
+the oracle's inversion of the same map, one push in FP32 and FP64 and three
+full FP64 steps; the predictor-corrector mover on tabulated maps is in its own
+tests."""
 import dataclasses
 
 import numpy as np
@@ -160,11 +162,68 @@ def test_tables_that_fold_or_skew_at_walls_are_refused():
     _create(pc, W.vertex_table(pc)).close()
 
 
-def test_species_need_the_predictor_corrector_mover():
-    cp = C()
-    case = CASES["2d_sin"]()
-    sim = _create(case, W.vertex_table(case))
-    with pytest.raises(cp.CpicError) as e:
-        sim.add_species(-1.0, 1.0, 1.0, 100)
-    assert e.value.status == -9
+PUSH_CASES = {
+    "2d_sin": lambda: dataclasses.replace(W.small_case(dim=2, n=(40, 24), ppc=8.0, case_id=164), tabulated=True),
+    "3d_sin": lambda: dataclasses.replace(W.small_case(dim=3, n=(20, 12, 16), ppc=4.0, case_id=165),
+                                          tabulated=True),
+    "probe": lambda: dataclasses.replace(probe_case(), tabulated=True, case_id=166),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PUSH_CASES))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_newton_push_on_the_tabulated_map(name, precision):
+    # the hybrid mover inverting the tabulated map (its multilinear
+    # interpolant) by Newton, against the oracle's inversion of the same map;
+    # bars as for the analytic maps
+    from _helpers import by_id, logical_cells, periodic_diff
+    case = PUSH_CASES[name]()
+    sim, parts = gpu_sim(case, precision=precision, mover=C().MOVER_NEWTON)
+    ec = 4 if case.dim == 3 else 2
+    nv = sim.field_bytes(C().FIELD_EV) // (4 if precision == 0 else 8) // ec
+    E = W.synthetic_ev(case, nv, dtype=np.float64 if precision else np.float32)
+    Ebuf = np.zeros((nv, ec), dtype=E.dtype)
+    Ebuf[:, : case.dim] = E[:, : case.dim]
+    sim.set_field(C().FIELD_EV, Ebuf)
+    sim.stage(C().STAGE_PUSH)
+    m, g = oracle_objects(case)
+    E64 = np.zeros((nv, 3))
+    E64[:, : case.dim] = Ebuf[:, : case.dim].astype(np.float64)
+    d = sim.diag()
+    for sid, s in enumerate(case.species):
+        o = W.to_oracle(parts[sid])
+        cell, off, vel, cnt = O.push(m, g, s.q / s.m, case.dt, case.B, o["cell"], o["off"], o["vel"], E64)
+        assert (d.absorbed[sid], d.outflow[sid]) == cnt
+        got = by_id(sim.get_particles(sid, cap=parts[sid]["cell"].size))
+        alive = cell >= 0
+        gl = got["cell"] >= 0
+        assert np.array_equal(gl, alive)
+        pg = logical_cells(case, got["cell"][gl], got["off"][:, gl].astype(np.float64))
+        po = logical_cells(case, cell[alive], off[alive])
+        dpos = np.abs(periodic_diff(case, pg, po))
+        assert dpos.max() < (2e-5 if precision == 0 else 1e-9), dpos.max()
+    assert d.newton_failed == 0
+    sim.close()
+
+
+def test_newton_three_steps_fp64_match_the_oracle():
+    from _helpers import by_id, logical_cells, periodic_diff
+    case = PUSH_CASES["2d_sin"]()
+    sim, parts = gpu_sim(case, precision=1, mover=C().MOVER_NEWTON, mg_rtol=1e-13)
+    m, g = oracle_objects(case)
+    osim = O.OracleSim(m, g, oracle_species(case, parts), dt=case.dt, deposit="f64", rtol=1e-13, ke_axes=2)
+    sim.initialize()
+    osim.initialize()
+    for k in range(3):
+        sim.step(1)
+        osim.step()
+        phi = sim.get_field(C().FIELD_PHI)
+        assert np.max(np.abs(phi - osim.phi)) < 1e-8 * np.max(np.abs(osim.phi)), k
+    for sid in range(len(case.species)):
+        got = by_id(sim.get_particles(sid))
+        o = osim.sp[sid]
+        order = np.argsort(parts[sid]["id"])
+        pg = logical_cells(case, got["cell"], got["off"].astype(np.float64))
+        po = logical_cells(case, o["cell"][order], o["off"][order])
+        assert np.abs(periodic_diff(case, pg, po)).max() < 1e-9
     sim.close()
