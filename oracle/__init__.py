@@ -135,6 +135,8 @@ def lib():
         L.or_gather.argtypes = [P(Grid), P(d), lg, P(i32), P(d), P(d)]
         L.or_boris.argtypes = [lg, P(d), P(d), P(d), d, d]
         L.or_push.argtypes = [P(Map), P(Grid), d, d, P(d), lg, P(i32), P(d), P(d), P(d), P(lg)]
+        L.or_push_cyclo.argtypes = [P(Map), P(Grid), d, d, P(d), lg, P(i32), P(d), P(d), P(d), P(lg)]
+        L.or_cyclotronic.argtypes = [lg, P(d), P(d), P(d), d, d, P(d)]
         L.or_push_pc.argtypes = [P(Map), P(Grid), d, d, P(d), lg, P(i32), P(d), P(d), P(d),
                                  ctypes.c_int, P(lg)]
         L.or_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
@@ -339,6 +341,33 @@ def push(m: Map, g: Grid, qm, dt, B, cell, off, vel, Ev):
     return cell, off, vel, (counts[0], counts[1])
 
 
+def push_cyclo(m: Map, g: Grid, qm, dt, B, cell, off, vel, Ev):
+    """As ``push`` with the cyclotronic velocity step (electric impulse, then
+    exact gyration in the uniform B; the position moves by dt times the mean
+    velocity of the gyration)."""
+    cell = np.ascontiguousarray(cell, dtype=np.int32).copy()
+    off = _pts(off).copy()
+    vel = _pts(vel).copy()
+    Ev = _f64(Ev)
+    Bv = _f64(np.asarray(B, dtype=np.float64).reshape(3))
+    counts = (ctypes.c_long * 2)()
+    lib().or_push_cyclo(ctypes.byref(m), ctypes.byref(g), qm, dt, _p(Bv, ctypes.c_double), cell.size,
+                        _p(cell, ctypes.c_int32), _p(off, ctypes.c_double), _p(vel, ctypes.c_double),
+                        _p(Ev, ctypes.c_double), counts)
+    return cell, off, vel, (counts[0], counts[1])
+
+
+def cyclotronic(v, E, B, qm, dt):
+    """The cyclotronic velocity step alone: (new velocity, mean velocity)."""
+    v = _pts(v).copy()
+    E = _pts(E)
+    Bv = _f64(np.asarray(B, dtype=np.float64).reshape(3))
+    vm = np.zeros_like(v)
+    lib().or_cyclotronic(v.shape[0], _p(v, ctypes.c_double), _p(E, ctypes.c_double), _p(Bv, ctypes.c_double),
+                         qm, dt, _p(vm, ctypes.c_double))
+    return v, vm
+
+
 def push_pc(m: Map, g: Grid, qm, dt, B, cell, off, vel, Ev, kmode=0):
     """As ``push`` with the predictor-corrector position update (Eqs. step2-
     step4): k interpolated from the vertices (kmode 0, the paper's method) or
@@ -470,7 +499,7 @@ class OracleSim:
     there (q w per particle, from the start) and floats at phi_wall."""
 
     def __init__(self, m: Map, g: Grid, species, shape=B2, dt=0.1, B=(0.0, 0.0, 0.0),
-                 background=None, deposit="fixed", rtol=1e-13, ke_axes=3, mover="exact"):
+                 background=None, deposit="fixed", rtol=1e-13, ke_axes=3, mover="exact", push="boris"):
         self.m, self.g, self.sp = m, g, species
         self.shape, self.dt, self.B = shape, dt, np.asarray(B, dtype=np.float64)
         self.bg = background
@@ -482,6 +511,13 @@ class OracleSim:
         self.ke = None
         self.ke_axes = ke_axes  # velocity components in the kinetic-energy sum
         self.mover = push_pc if mover == "pc" else push
+        # cyclotronic: the velocity step resolves the gyration exactly (with the
+        # exact position update); the kinetic energy is then that of the
+        # velocity at t_n, v + (q/m) E dt / 2, and the initial push-back is the
+        # half electric impulse alone
+        self.cyclo = push == "cyclotronic"
+        if self.cyclo:
+            self.mover = push_cyclo
         self.floating = g.bc_lo[0] == FLOATING
         self.phi_wall = 0.0
         self.wall_charge = 0.0
@@ -513,18 +549,24 @@ class OracleSim:
         self.solve()
         for s in self.sp:
             E = gather(self.g, self.Ev, s["cell"], s["off"])
-            s["vel"] = boris(s["vel"], E, self.B, s["q"] / s["m"], -0.5 * self.dt)
+            s["vel"] = boris(s["vel"], E, np.zeros(3) if self.cyclo else self.B, s["q"] / s["m"], -0.5 * self.dt)
 
     def step(self):
         ke = 0.0
         self.counts = []
         for s in self.sp:
             v_old = s["vel"].copy()
+            if self.cyclo:
+                Ep = gather(self.g, self.Ev, s["cell"], s["off"])
+                v_mid = v_old + 0.5 * (s["q"] / s["m"]) * self.dt * Ep
             s["cell"], s["off"], s["vel"], cnt = self.mover(self.m, self.g, s["q"] / s["m"], self.dt,
                                                             self.B, s["cell"], s["off"], s["vel"], self.Ev)
             alive = s["cell"] >= 0
             k = self.ke_axes
-            ke += 0.5 * s["m"] * s["w"] * float(np.sum(v_old[alive, :k] * s["vel"][alive, :k]))
+            if self.cyclo:
+                ke += 0.5 * s["m"] * s["w"] * float(np.sum(v_mid[alive, :k] ** 2))
+            else:
+                ke += 0.5 * s["m"] * s["w"] * float(np.sum(v_old[alive, :k] * s["vel"][alive, :k]))
             self.counts.append(cnt)
             # drop particles that left, then append this step's injection
             s["cell"], s["off"], s["vel"] = s["cell"][alive], s["off"][alive], s["vel"][alive]

@@ -1132,6 +1132,47 @@ void or_boris(long np, double* v, const double* E, const double* B, double qm, d
   for (long p = 0; p < np; ++p) boris(v + 3 * p, E + 3 * p, B, qm, dt);
 }
 
+/* Cyclotronic step (Sec. "Particle mover": with a uniform background B the
+   gyration is resolved exactly, so that the time step need not resolve
+   omega_c): the velocity takes the electric impulse (q/m) E dt, then the
+   particle gyrates exactly in B for dt.  With w = (q/m)|B|, b = B/|B|,
+   v = v_par b + v_perp and theta = w dt:
+     v(dt)   = v_par b + v_perp cos(theta) + (v_perp x b) sin(theta),
+     x(dt)-x = dt [v_par b + v_perp sin(theta)/theta + (v_perp x b)(1 - cos(theta))/theta].
+   vmean receives the bracket (the mean velocity over the step); B = 0 is the
+   leap-frog step.  Series for |theta| < 1e-4. */
+static void cyclotronic(double* v, const double* E, const double* B, double qm, double dt, double* vmean) {
+  for (int a = 0; a < 3; ++a) v[a] += qm * E[a] * dt;
+  double bn = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+  if (bn == 0.0) {
+    for (int a = 0; a < 3; ++a) vmean[a] = v[a];
+    return;
+  }
+  double b[3] = {B[0] / bn, B[1] / bn, B[2] / bn};
+  double th = qm * bn * dt;
+  double vpar = v[0] * b[0] + v[1] * b[1] + v[2] * b[2];
+  double vp[3], w[3];
+  for (int a = 0; a < 3; ++a) vp[a] = v[a] - vpar * b[a];
+  cross(vp, b, w);
+  double c = cos(th), s = sin(th), s1, s2;
+  if (fabs(th) < 1e-4) {
+    s1 = 1.0 - th * th / 6.0;
+    s2 = th / 2.0 - th * th * th / 24.0;
+  } else {
+    s1 = s / th;
+    s2 = (1.0 - c) / th;
+  }
+  for (int a = 0; a < 3; ++a) {
+    vmean[a] = vpar * b[a] + vp[a] * s1 + w[a] * s2;
+    v[a] = vpar * b[a] + vp[a] * c + w[a] * s;
+  }
+}
+
+void or_cyclotronic(long np, double* v, const double* E, const double* B, double qm, double dt,
+                    double* vmean) {
+  for (long p = 0; p < np; ++p) cyclotronic(v + 3 * p, E + 3 * p, B, qm, dt, vmean + 3 * p);
+}
+
 /* Logical position from absolute xi: returns 0 alive, 1 absorbed at a lower
    wall, 2 left through an upper wall. */
 static int place(const or_grid* g, double* xi, int32_t* cell, double* off, int* wall_axis) {
@@ -1177,6 +1218,46 @@ static int place(const or_grid* g, double* xi, int32_t* cell, double* off, int* 
    cell = -1 (lower wall, absorbed) or -2 (upper wall, outflow).  In 2D v_z is
    pushed as the third component (zero field, rotated only by B).
    counts[0] absorbed, counts[1] outflow. */
+/* The hybrid mover with the cyclotronic velocity step: the position update
+   maps x(xi^n) + dt vmean back to logical space exactly (vmean the mean
+   velocity of the exact gyration over the step). */
+int or_push_cyclo(const or_map* m, const or_grid* g, double qm, double dt, const double* B, long np,
+                  int32_t* cell, double* off, double* vel, const double* Ev, long* counts) {
+  int d = g->dim;
+  long absorbed = 0, outflow = 0;
+#pragma omp parallel for schedule(static) reduction(+ : absorbed, outflow)
+  for (long p = 0; p < np; ++p) {
+    if (cell[p] < 0) continue;
+    double E[3], vm[3];
+    gather_one(g, Ev, cell[p], off + 3 * p, E);
+    cyclotronic(vel + 3 * p, E, B, qm, dt, vm);
+    int idx[3];
+    cell_coords(g, cell[p], idx);
+    double xi0[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) xi0[a] = (idx[a] + off[3 * p + a]) / g->n[a];
+    double x0[3], j[3][3];
+    map_x_jac(m, xi0, x0, j);
+    double xt[3];
+    for (int a = 0; a < 3; ++a) xt[a] = (a < d) ? x0[a] + dt * vm[a] : 0.0;
+    double xi1[3];
+    map_invert(m, xt, xi0, xi1);
+    int wa = -1;
+    int st = place(g, xi1, &cell[p], off + 3 * p, &wa);
+    if (st == 1) {
+      cell[p] = -1;
+      absorbed++;
+    } else if (st == 2) {
+      cell[p] = -2;
+      outflow++;
+    }
+  }
+  if (counts) {
+    counts[0] = absorbed;
+    counts[1] = outflow;
+  }
+  return 0;
+}
+
 int or_push(const or_map* m, const or_grid* g, double qm, double dt, const double* B, long np,
             int32_t* cell, double* off, double* vel, const double* Ev, long* counts) {
   int d = g->dim;
