@@ -499,7 +499,7 @@ class OracleSim:
     there (q w per particle, from the start) and floats at phi_wall."""
 
     def __init__(self, m: Map, g: Grid, species, shape=B2, dt=0.1, B=(0.0, 0.0, 0.0),
-                 background=None, deposit="fixed", rtol=1e-13, ke_axes=3, mover="exact", push="boris"):
+                 background=None, deposit="fixed", rtol=1e-13, ke_axes=3, mover="exact", pusher="boris"):
         self.m, self.g, self.sp = m, g, species
         self.shape, self.dt, self.B = shape, dt, np.asarray(B, dtype=np.float64)
         self.bg = background
@@ -515,7 +515,7 @@ class OracleSim:
         # exact position update); the kinetic energy is then that of the
         # velocity at t_n, v + (q/m) E dt / 2, and the initial push-back is the
         # half electric impulse alone
-        self.cyclo = push == "cyclotronic"
+        self.cyclo = pusher == "cyclotronic"
         if self.cyclo:
             self.mover = push_cyclo
         self.floating = g.bc_lo[0] == FLOATING
