@@ -108,9 +108,10 @@ def copy_calibrate(nbytes, reps):
 _STREAM = None
 
 
-def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, graphs=False, mover=0):
+def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, graphs=False, mover=0, pusher=0):
     """graphs: step in graph mode, on a stream of its own (default priority);
-    mover: 0 Newton map inversion, 1 predictor-corrector."""
+    mover: 0 Newton map inversion, 1 predictor-corrector; pusher: 0 Boris,
+    1 cyclotronic."""
     global _STREAM
     import torch
     from paper_1311_2286_amd import cpic as C
@@ -127,7 +128,8 @@ def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, grap
                 r_out=case.r_out, bc_lo=case.bc_lo, bc_hi=case.bc_hi, phi_lo=case.phi_lo,
                 phi_hi=case.phi_hi, shape=shape, precision=precision, dt=case.dt, B0=case.B,
                 background=case.background, mg_rtol=mg_rtol, mg_max_cycles=mg_cycles,
-                sort_every=sort_every, track_ids=False, stream=stream, mover=mover, vertices=vertices)
+                sort_every=sort_every, track_ids=False, stream=stream, mover=mover, vertices=vertices,
+                pusher=pusher)
     del vertices
     if graphs:
         sim.set_graphs(True)
@@ -151,11 +153,11 @@ def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, grap
 
 
 def run_path(case, parts, precision, shape, steps, warmup, sort_every, mg_rtol, mg_cycles,
-             graphs=False, mover=0):
+             graphs=False, mover=0, pusher=0):
     import torch
     from paper_1311_2286_amd import cpic as C
     t0 = time.time()
-    sim = make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, graphs, mover)
+    sim = make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, graphs, mover, pusher)
     sim.initialize()
     sim.sync()
     log("precision", precision, "set up + initialise %.1f s" % (time.time() - t0))
@@ -337,7 +339,7 @@ def run_serving(nreq, nsteps, budget, slots, load, mg_rtol, mg_cycles, seed=1311
 
 
 def extra_workload(name, shape_name, precision, steps, warmup, sort_every, mg_rtol, mg_cycles, mover=0,
-                   tabulated=False):
+                   tabulated=False, pusher=0):
     """Throughput of another workload (same fields as the headline path);
     tabulated: on its map sampled at the vertices (a tabulated map)."""
     from paper_1311_2286_amd import cpic as C
@@ -353,12 +355,14 @@ def extra_workload(name, shape_name, precision, steps, warmup, sort_every, mg_rt
                                 workers=16) for sid in range(len(case.species))]
     log("%s: generated %d particles in %.1f s" % (name, sum(p["cell"].size for p in parts),
                                                   time.time() - t0))
-    r = run_path(case, parts, precision, shape, steps, warmup, sort_every, mg_rtol, mg_cycles, mover=mover)
+    r = run_path(case, parts, precision, shape, steps, warmup, sort_every, mg_rtol, mg_cycles, mover=mover,
+                 pusher=pusher)
     del parts
     torch.cuda.empty_cache()
     out = {"workload": "%s%s, %s deposit, %s%s" % (name, ", tabulated map" if tabulated else "", shape_name.upper(),
                                                   "FP64" if precision else "FP32",
-                                                  ", predictor-corrector mover" if mover else ""),
+                                                  (", predictor-corrector mover" if mover else "")
+                                                  + (", cyclotronic step" if pusher else "")),
            "particles": r["pushes"], "steps": steps, "pushes_per_s": r["pushes_per_s"],
            "ms_per_step": r["ms_per_step"], "p50_step_ms": r["p50_step_ms"], "p99_step_ms": r["p99_step_ms"],
            "particle_kernel_pushes_per_s": r["kernel_pushes_per_s"], "achieved_GBs": r["achieved_GBs"],
@@ -590,17 +594,19 @@ def main():
         log("cpu", json.dumps(cpu))
     extra = {}
     if not args.no_extra:
-        for key, (name, shp, prec, steps, mover, tab) in {
-                "box3d_128_b1": ("box3d_128", "b1", C.FP32, 10, 0, False),
-                "box3d_128_b1_fp64": ("box3d_128", "b1", C.FP64, 10, 0, False),
-                "box3d_128_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC, False),
-                "box3d_128_tabulated": ("box3d_128", "b2", C.FP32, 10, 0, True),
-                "box3d_128_tabulated_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC, True),
-                "probe2d_512": ("probe2d_512", "b2", C.FP32, 20, 0, False),
-                "box3d_magnetized": ("box3d_magnetized", "b2", C.FP32, 10, 0, False)}.items():
+        for key, (name, shp, prec, steps, mover, tab, push) in {
+                "box3d_128_b1": ("box3d_128", "b1", C.FP32, 10, 0, False, 0),
+                "box3d_128_b1_fp64": ("box3d_128", "b1", C.FP64, 10, 0, False, 0),
+                "box3d_128_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC, False, 0),
+                "box3d_128_tabulated": ("box3d_128", "b2", C.FP32, 10, 0, True, 0),
+                "box3d_128_tabulated_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC, True, 0),
+                "probe2d_512": ("probe2d_512", "b2", C.FP32, 20, 0, False, 0),
+                "box3d_magnetized": ("box3d_magnetized", "b2", C.FP32, 10, 0, False, 0),
+                "box3d_magnetized_cyclotronic": ("box3d_magnetized", "b2", C.FP32, 10, 0, False,
+                                                 C.PUSH_CYCLOTRONIC)}.items():
             try:
                 extra[key] = extra_workload(name, shp, prec, steps, 2, args.sort_every, args.mg_rtol,
-                                            args.mg_cycles, mover, tab)
+                                            args.mg_cycles, mover, tab, push)
             except Exception as e:  # reported, never fatal for the headline line
                 extra[key] = {"error": repr(e)}
         try:

@@ -152,6 +152,20 @@ enum {
                             CIC vertex weights (Eq. step3) */
 };
 
+/* Velocity step (cpic_grid_desc.pusher) */
+enum {
+  CPIC_PUSH_BORIS = 0,       /* leap-frog with the Boris rotation (default) */
+  CPIC_PUSH_CYCLOTRONIC = 1  /* with a uniform background B, the gyration resolved exactly (Sec. "Particle
+                                mover"; Sec. "Tests" runs at omega_ce dt ~ 1): the electric impulse
+                                (q/m) E dt, then the exact helix over dt -- the velocity rotated by
+                                theta = (q/m)|B| dt about B, the position moved by dt times the mean
+                                velocity of the gyration (then mapped back by the position update).
+                                Stored velocities are those just before the next impulse; the start-up
+                                in cpic_initialize is the half impulse alone; the kinetic energy is that
+                                of v + (q/m) E dt / 2.  Needs CPIC_MOVER_NEWTON (else
+                                CPIC_E_UNSUPPORTED); without B it is the leap-frog step. */
+};
+
 typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);
@@ -201,6 +215,7 @@ typedef struct {
   int track_ids;        /* carry a uint32 particle id through sorts */
   int mg_method;        /* CPIC_MG_FCG (0) or CPIC_MG_VCYCLE */
   int mover;            /* CPIC_MOVER_NEWTON (0) or CPIC_MOVER_PC */
+  int pusher;           /* CPIC_PUSH_BORIS (0) or CPIC_PUSH_CYCLOTRONIC */
 } cpic_grid_desc;
 
 typedef struct {

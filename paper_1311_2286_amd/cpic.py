@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcpic.so")
 
 MAP_IDENTITY, MAP_SINUSOIDAL, MAP_POLAR_LOG, MAP_SPHERICAL_RZ, MAP_TABULATED = 0, 1, 2, 3, 4
+PUSH_BORIS, PUSH_CYCLOTRONIC = 0, 1
 BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN, BC_FLOATING = 0, 1, 2, 3
 PBC_PERIODIC, PBC_ABSORB, PBC_OUTFLOW = 0, 1, 2
 SHAPE_B1, SHAPE_B2 = 1, 2
@@ -49,7 +50,8 @@ class GridDesc(ctypes.Structure):
                 ("B0", ctypes.c_double * 3), ("background", ctypes.c_int),
                 ("background_n0", ctypes.c_double), ("mg_rtol", ctypes.c_double),
                 ("mg_max_cycles", ctypes.c_int), ("sort_every", ctypes.c_int),
-                ("track_ids", ctypes.c_int), ("mg_method", ctypes.c_int), ("mover", ctypes.c_int)]
+                ("track_ids", ctypes.c_int), ("mg_method", ctypes.c_int), ("mover", ctypes.c_int),
+                ("pusher", ctypes.c_int)]
 
 
 class SpeciesDesc(ctypes.Structure):
@@ -217,12 +219,12 @@ def make_map_desc(map_kind, dim, L=(1.0, 1.0, 1.0), eps=0.0, r_in=1.0, r_out=2.0
 def make_grid_desc(n, bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), phi_lo=(0.0, 0.0, 0.0),
                    phi_hi=(0.0, 0.0, 0.0), shape=SHAPE_B2, precision=FP32, dt=0.1,
                    B0=(0.0, 0.0, 0.0), background=False, background_n0=1.0, mg_rtol=1e-10,
-                   mg_max_cycles=30, sort_every=1, track_ids=False, mg_method=0, mover=0):
+                   mg_max_cycles=30, sort_every=1, track_ids=False, mg_method=0, mover=0, pusher=0):
     return GridDesc((ctypes.c_int * 3)(*_pad(n, 1)), (ctypes.c_int * 3)(*_pad(bc_lo, 0)),
                     (ctypes.c_int * 3)(*_pad(bc_hi, 0)), (ctypes.c_double * 3)(*_pad(phi_lo, 0.0)),
                     (ctypes.c_double * 3)(*_pad(phi_hi, 0.0)), shape, precision, dt,
                     (ctypes.c_double * 3)(*_pad(B0, 0.0)), int(background), background_n0,
-                    mg_rtol, mg_max_cycles, sort_every, int(track_ids), int(mg_method), int(mover))
+                    mg_rtol, mg_max_cycles, sort_every, int(track_ids), int(mg_method), int(mover), int(pusher))
 
 
 def make_species_desc(q, m, w, capacity=0, pbc_lo=(0, 0, 0), pbc_hi=(0, 0, 0), inject=None,
@@ -241,7 +243,7 @@ class Sim:
                  bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), phi_lo=(0.0, 0.0, 0.0), phi_hi=(0.0, 0.0, 0.0),
                  shape=SHAPE_B2, precision=FP32, dt=0.1, B0=(0.0, 0.0, 0.0), background=False,
                  background_n0=1.0, mg_rtol=1e-10, mg_max_cycles=30, sort_every=1, track_ids=False,
-                 stream=None, torch_alloc=True, mg_method=0, mover=0, omega=0, vertices=None):
+                 stream=None, torch_alloc=True, mg_method=0, mover=0, omega=0, vertices=None, pusher=0):
         self.lib = load()
         pad = lambda t, v: tuple(t)[:3] + (v,) * (3 - len(tuple(t)[:3]))
         self.dim = dim
@@ -257,7 +259,8 @@ class Sim:
                      (ctypes.c_int * 3)(*pad(bc_hi, 0)), (ctypes.c_double * 3)(*pad(phi_lo, 0.0)),
                      (ctypes.c_double * 3)(*pad(phi_hi, 0.0)), shape, precision, dt,
                      (ctypes.c_double * 3)(*pad(B0, 0.0)), int(background), background_n0,
-                     mg_rtol, mg_max_cycles, sort_every, int(track_ids), int(mg_method), int(mover))
+                     mg_rtol, mg_max_cycles, sort_every, int(track_ids), int(mg_method), int(mover),
+                     int(pusher))
         self._alloc = TorchAllocator() if torch_alloc else None
         if stream is None:
             try:

@@ -213,6 +213,8 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   if (grid->background && (d != 2 || !all_periodic)) return CPIC_E_UNSUPPORTED;
   if (grid->mg_method != CPIC_MG_FCG && grid->mg_method != CPIC_MG_VCYCLE) return CPIC_E_ARG;
   if (grid->mover != CPIC_MOVER_NEWTON && grid->mover != CPIC_MOVER_PC) return CPIC_E_ARG;
+  if (grid->pusher != CPIC_PUSH_BORIS && grid->pusher != CPIC_PUSH_CYCLOTRONIC) return CPIC_E_ARG;
+  if (grid->pusher == CPIC_PUSH_CYCLOTRONIC && grid->mover != CPIC_MOVER_NEWTON) return CPIC_E_UNSUPPORTED;
 
   cpic_sim* s = new cpic_sim();
   s->map = *map;
@@ -819,6 +821,18 @@ static void particles_pass(cpic_sim* s, int mode, unsigned count_mask = 0) {
     L.qm = S.desc.q / S.desc.m;
     L.dt = halfstep ? -0.5 * s->grid.dt : s->grid.dt;
     L.magnetic = (s->grid.B0[0] != 0 || s->grid.B0[1] != 0 || s->grid.B0[2] != 0);
+    if (s->grid.pusher == CPIC_PUSH_CYCLOTRONIC && L.magnetic) {
+      // exact gyration: theta = (q/m) |B| dt, b = B / |B|
+      const double bn = sqrt(s->grid.B0[0] * s->grid.B0[0] + s->grid.B0[1] * s->grid.B0[1] +
+                             s->grid.B0[2] * s->grid.B0[2]);
+      const double th = L.qm * bn * s->grid.dt;
+      L.cyclo = 1;
+      for (int i = 0; i < 3; ++i) L.cyc_b[i] = s->grid.B0[i] / bn;
+      L.cyc_c = cos(th);
+      L.cyc_s = sin(th);
+      L.cyc_s1 = fabs(th) < 1e-4 ? 1.0 - th * th / 6.0 : sin(th) / th;
+      L.cyc_s2 = fabs(th) < 1e-4 ? th / 2.0 - th * th * th / 24.0 : (1.0 - cos(th)) / th;
+    }
     L.vz_active = (s->g.dim == 3) || L.magnetic;
     L.S1 = s->S1;
     L.newton_maxit = 8;

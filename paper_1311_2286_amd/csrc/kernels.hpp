@@ -27,6 +27,10 @@ struct ParticleLaunch {
   double qm, dt;
   double B[3];
   int magnetic, vz_active;
+  // cyclotronic velocity step (PUSH): b = B/|B| and, with theta = qm |B| dt,
+  // cos, sin, sin(theta)/theta and (1 - cos(theta))/theta
+  int cyclo;
+  double cyc_b[3], cyc_c, cyc_s, cyc_s1, cyc_s2;
   int S1;
   int newton_maxit;
   double newton_tol;

@@ -233,6 +233,49 @@ __device__ inline bool move_tab(const Geo& g, const int* idx, const double* f0, 
   return conv;
 }
 
+// Cyclotronic velocity step (a uniform B): the electric impulse, then the
+// exact rotation by theta about b; vm receives the mean velocity of the
+// gyration over the step (the position moves by dt vm).  c, s, s1, s2: cos,
+// sin, sin(theta)/theta, (1 - cos(theta))/theta.
+template <typename R>
+__device__ __forceinline__ void cyclotronic_step(R* v, const R* E, R qm, R dt, const R* b, R c, R s, R s1, R s2,
+                                                 R* vm) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) v[a] += qm * E[a] * dt;
+  const R vpar = v[0] * b[0] + v[1] * b[1] + v[2] * b[2];
+  R vp[3], w[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) vp[a] = v[a] - vpar * b[a];
+  w[0] = vp[1] * b[2] - vp[2] * b[1];
+  w[1] = vp[2] * b[0] - vp[0] * b[2];
+  w[2] = vp[0] * b[1] - vp[1] * b[0];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    vm[a] = vpar * b[a] + vp[a] * s1 + w[a] * s2;
+    v[a] = vpar * b[a] + vp[a] * c + w[a] * s;
+  }
+}
+
+// The mean velocity of the last cyclotronic step from the velocity it left,
+// rotating that back by theta (for a position update redone in FP64).
+template <typename R>
+__device__ __forceinline__ void cyclotronic_mean(const R* vn, const R* b, R c, R s, R s1, R s2, R* vm) {
+  const R vpar = vn[0] * b[0] + vn[1] * b[1] + vn[2] * b[2];
+  R u[3], uxb[3], vp[3], w[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[a] = vn[a] - vpar * b[a];
+  uxb[0] = u[1] * b[2] - u[2] * b[1];
+  uxb[1] = u[2] * b[0] - u[0] * b[2];
+  uxb[2] = u[0] * b[1] - u[1] * b[0];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) vp[a] = u[a] * c - uxb[a] * s;
+  w[0] = vp[1] * b[2] - vp[2] * b[1];
+  w[1] = vp[2] * b[0] - vp[0] * b[2];
+  w[2] = vp[0] * b[1] - vp[1] * b[0];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) vm[a] = vpar * b[a] + vp[a] * s1 + w[a] * s2;
+}
+
 template <int D, int MAP>
 __device__ __forceinline__ bool move_fallback(const Geo& g, const int* idx, const double* f0,
                                               const double* disp, double kappa, double* d) {
@@ -485,6 +528,8 @@ struct PartArgs {
   R B[3];
   int magnetic;
   int vz_active;
+  int cyclo;  // cyclotronic velocity step: constants of the exact gyration
+  R cyc_b[3], cyc_c, cyc_s, cyc_s1, cyc_s2;
   int mode;
   int S1;
   int newton_maxit;
@@ -791,7 +836,8 @@ __device__ __forceinline__ bool gather_E_window(const R* __restrict__ ewin, cons
   return true;
 }
 
-template <int D, int MAP, int SHAPE, typename R, bool FIXED>
+// CYC: the cyclotronic velocity step (a uniform B) in place of Boris
+template <int D, int MAP, int SHAPE, typename R, bool FIXED, bool CYC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && MAP != MAP_TABULATED) ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel(
     PartArgs<R> a) {
   using TS = TileShape<D>;
@@ -902,12 +948,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
       R E[3];
       if (!gather_E_window<D, R>(ewin, g, origin, idx, f, E)) gather_E<D, R>(a.Ev, g, idx, f, E);
       R vo0 = v[0], vo1 = v[1], vo2 = v[2];
-      boris_push<R>(v, E, a.B, a.qm, a.dt, a.magnetic != 0);
-      a.v0[p] = v[0];
-      a.v1[p] = v[1];
-      if (a.vz_active) a.v2[p] = v[2];
-      if (a.mode == MODE_HALFSTEP) continue;
-      ke += (double)(vo0 * v[0] + vo1 * v[1] + vo2 * v[2]);
+      if (CYC && a.mode == MODE_PUSH) {
+        // cyclotronic step: exact gyration; the position moves with the mean
+        // velocity of the gyration, which takes v's place once v is stored
+        R vm[3];
+        cyclotronic_step<R>(v, E, a.qm, a.dt, a.cyc_b, a.cyc_c, a.cyc_s, a.cyc_s1, a.cyc_s2, vm);
+        a.v0[p] = v[0];
+        a.v1[p] = v[1];
+        if (a.vz_active) a.v2[p] = v[2];
+        // kinetic energy of the velocity at t_n: before the impulse plus half of it
+        const R h = (R)0.5 * a.qm * a.dt;
+        const R m0 = vo0 + h * E[0], m1 = vo1 + h * E[1], m2 = vo2 + h * E[2];
+        ke += (double)(m0 * m0 + m1 * m1 + m2 * m2);
+        v[0] = vm[0];
+        v[1] = vm[1];
+        v[2] = vm[2];
+      } else {
+        // Boris (the cyclotronic start-up is the half impulse alone)
+        boris_push<R>(v, E, a.B, a.qm, a.dt, a.magnetic != 0 && !CYC);
+        a.v0[p] = v[0];
+        a.v1[p] = v[1];
+        if (a.vz_active) a.v2[p] = v[2];
+        if (a.mode == MODE_HALFSTEP) continue;
+        ke += (double)(vo0 * v[0] + vo1 * v[1] + vo2 * v[2]);
+      }
 
       R d[3] = {(R)0, (R)0, (R)0};
       bool conv;
@@ -1110,12 +1174,16 @@ __global__ __launch_bounds__(256) void fallback_kernel(PartArgs<R> a, int shape)
     const int key = a.key[p];
     int idx[3] = {key_i(key, g), key_j(key, g), (D == 3) ? key_k(key, g) : 0};
     double f[3] = {(double)a.off0[p], (double)a.off1[p], (D == 3) ? (double)a.off2[p] : 0.0};
-    double v[3] = {(double)a.v0[p], (double)a.v1[p], 0.0};
+    double v[3] = {(double)a.v0[p], (double)a.v1[p], a.vz_active ? (double)a.v2[p] : 0.0};
+    if (a.cyclo) {
+      // the displacement of a cyclotronic step: the mean velocity of the gyration
+      const double b[3] = {(double)a.cyc_b[0], (double)a.cyc_b[1], (double)a.cyc_b[2]};
+      double vn[3] = {v[0], v[1], v[2]};
+      cyclotronic_mean<double>(vn, b, (double)a.cyc_c, (double)a.cyc_s, (double)a.cyc_s1, (double)a.cyc_s2, v);
+    }
     double disp[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0};
     for (int ax = 0; ax < D; ++ax)
       disp[ax] = (MAP == MAP_SINUSOIDAL) ? (double)a.dt * v[ax] / g.dxc[ax] : (double)a.dt * v[ax];
-    if (D == 3) disp[D - 1] = (MAP == MAP_SINUSOIDAL) ? (double)a.dt * (double)a.v2[p] / g.dxc[D - 1]
-                                                      : (double)a.dt * (double)a.v2[p];
     bool ok = move_fallback<D, MAP>(g, idx, f, disp, (double)a.kappa, d);
     ++done;
     failed += ok ? 0 : 1;
@@ -1600,6 +1668,12 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   a.qm = (R)L.qm;
   a.dt = (R)L.dt;
   a.magnetic = L.magnetic;
+  a.cyclo = L.cyclo;
+  for (int i = 0; i < 3; ++i) a.cyc_b[i] = (R)L.cyc_b[i];
+  a.cyc_c = (R)L.cyc_c;
+  a.cyc_s = (R)L.cyc_s;
+  a.cyc_s1 = (R)L.cyc_s1;
+  a.cyc_s2 = (R)L.cyc_s2;
   a.vz_active = L.vz_active;
   a.mode = L.mode;
   a.S1 = L.S1;
@@ -1618,7 +1692,11 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   a.fb_cap = L.fb_cap;
   if (L.max_items <= 0) return;
   constexpr bool FIXED = std::is_same<R, float>::value;
-  hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED>), dim3(L.max_items), dim3(256), 0, st,
+  if (L.cyclo)
+    hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED, true>), dim3(L.max_items), dim3(256), 0, st,
+                     a);
+  else
+    hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED, false>), dim3(L.max_items), dim3(256), 0, st,
                      a);
   if constexpr (MAP != MAP_IDENTITY && MAP != MAP_TABLE_PC) {
     if (L.mode == MODE_PUSH)

@@ -1,0 +1,144 @@
+"""GPU parity of the cyclotronic velocity step (cpic_grid_desc.pusher =
+CPIC_PUSH_CYCLOTRONIC; Sec. "Particle mover": the gyration in a uniform B
+resolved exactly) against the oracle's, through the C ABI.
+
+Bars: one push from identical states at omega_ce dt = 2 (Boris would turn by
+2 atan(1) = 1.57 instead of 2 per step), FP32: positions 2e-5 cell,
+velocities 2e-5 of the particle's |v| + |q/m E dt| (the rotation mixes the
+components); FP64: 1e-9 cell, 1e-11.
+Three full FP64 steps: potential within 1e-8 of its maximum, positions within
+1e-9 cell, kinetic energy within 1e-10.  And, independent of the oracle, 40
+FP64 pushes in B alone follow the exact helix written out in the test."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1311_2286_amd import workloads as W
+from _helpers import gpu_sim, oracle_objects, oracle_species, by_id, logical_cells, periodic_diff
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def C():
+    from paper_1311_2286_amd import cpic
+    return cpic
+
+
+def mag_case():
+    # 3D box, sinusoidal map, B = 20 z: omega_ce dt = 2
+    return W.small_case(dim=3, n=(16, 16, 10), ppc=4.0, B=(0.0, 0.0, 20.0), case_id=180)
+
+
+def mag2d_case():
+    return W.small_case(dim=2, n=(40, 24), ppc=6.0, B=(0.3, 0.0, 20.0), case_id=181)
+
+
+@pytest.mark.parametrize("name", ["3d", "2d"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_push_one_step(name, precision):
+    case = mag_case() if name == "3d" else mag2d_case()
+    sim, parts = gpu_sim(case, precision=precision, pusher=C().PUSH_CYCLOTRONIC)
+    ec = 4 if case.dim == 3 else 2
+    nv = sim.field_bytes(C().FIELD_EV) // (4 if precision == 0 else 8) // ec
+    E = W.synthetic_ev(case, nv, dtype=np.float64 if precision else np.float32)
+    Ebuf = np.zeros((nv, ec), dtype=E.dtype)
+    Ebuf[:, : case.dim] = E[:, : case.dim]
+    sim.set_field(C().FIELD_EV, Ebuf)
+    sim.stage(C().STAGE_PUSH)
+    m, g = oracle_objects(case)
+    E64 = np.zeros((nv, 3))
+    E64[:, : case.dim] = Ebuf[:, : case.dim].astype(np.float64)
+    for sid, s in enumerate(case.species):
+        o = W.to_oracle(parts[sid])
+        cell, off, vel, cnt = O.push_cyclo(m, g, s.q / s.m, case.dt, case.B, o["cell"], o["off"], o["vel"], E64)
+        got = by_id(sim.get_particles(sid))
+        pg = logical_cells(case, got["cell"], got["off"].astype(np.float64))
+        po = logical_cells(case, cell, off)
+        dpos = np.abs(periodic_diff(case, pg, po))
+        vg = got["vel"].T.astype(np.float64)
+        Eo = O.gather(g, E64, o["cell"], o["off"])
+        # a rotation by 2 rad mixes the components: the scale is the particle's
+        # speed (plus its velocity change), not the component's
+        scale = (np.linalg.norm(o["vel"], axis=1) + np.linalg.norm(s.q / s.m * Eo * case.dt, axis=1))[:, None]
+        dv = np.abs(vg - vel)
+        if precision == 0:
+            assert dpos.max() < 2e-5, dpos.max()
+            assert np.all(dv <= 2e-5 * (scale + 1e-3)), (dv / (scale + 1e-3)).max()
+        else:
+            assert dpos.max() < 1e-9, dpos.max()
+            assert np.all(dv <= 1e-11 * (scale + 1e-3)), (dv / (scale + 1e-3)).max()
+    assert sim.diag().newton_failed == 0
+    sim.close()
+
+
+def test_three_steps_fp64_match_the_oracle():
+    case = mag_case()
+    sim, parts = gpu_sim(case, precision=1, pusher=C().PUSH_CYCLOTRONIC, mg_rtol=1e-13)
+    m, g = oracle_objects(case)
+    osim = O.OracleSim(m, g, oracle_species(case, parts), dt=case.dt, B=case.B, deposit="f64", rtol=1e-13,
+                       pusher="cyclotronic")
+    sim.initialize()
+    osim.initialize()
+    for k in range(3):
+        sim.step(1)
+        osim.step()
+        phi = sim.get_field(C().FIELD_PHI)
+        assert np.max(np.abs(phi - osim.phi)) < 1e-8 * np.max(np.abs(osim.phi)), k
+        d = sim.diag()
+        assert abs(d.kinetic - osim.ke) <= 1e-10 * abs(osim.ke), (k, d.kinetic, osim.ke)
+    for sid in range(len(case.species)):
+        got = by_id(sim.get_particles(sid))
+        o = osim.sp[sid]
+        order = np.argsort(parts[sid]["id"])
+        pg = logical_cells(case, got["cell"], got["off"].astype(np.float64))
+        po = logical_cells(case, o["cell"][order], o["off"][order])
+        assert np.abs(periodic_diff(case, pg, po)).max() < 1e-9
+    sim.close()
+
+
+def test_gyration_follows_the_exact_helix():
+    # identity map, no electric field, B = 20 z, omega dt = -2 for electrons:
+    # 40 pushes of a handful of particles against the closed-form helix
+    L = (64.0, 64.0, 64.0)
+    case = W.Case("helix", 3, W.IDENTITY, (16, 16, 16), L=L, dt=0.1, B=(0.0, 0.0, 20.0),
+                  species=[W.electrons(1.0, 1.0, count=64)], case_id=182)
+    sim, parts = gpu_sim(case, precision=1, pusher=C().PUSH_CYCLOTRONIC)
+    nv = sim.field_bytes(C().FIELD_EV) // 8 // 4
+    sim.set_field(C().FIELD_EV, np.zeros((nv, 4)))
+    for _ in range(40):
+        sim.stage(C().STAGE_PUSH)
+    got = by_id(sim.get_particles(0))
+    p = parts[0]
+    n = np.array(case.n)
+    c0 = p["cell"].astype(np.int64)
+    idx0 = np.stack([c0 % n[0], (c0 // n[0]) % n[1], c0 // (n[0] * n[1])], axis=1)
+    x0 = (idx0 + p["off"].T) / n * np.array(L)
+    v0 = p["vel"].T
+    w = -1.0 * 20.0
+    t = 40 * 0.1
+    vp = v0.copy()
+    vp[:, 2] = 0.0
+    vxb = np.cross(vp, [0.0, 0.0, 1.0])
+    x_ex = x0 + vp * np.sin(w * t) / w + vxb * (1 - np.cos(w * t)) / w
+    x_ex[:, 2] += v0[:, 2] * t
+    x_ex = np.mod(x_ex, np.array(L))
+    c1 = got["cell"].astype(np.int64)
+    idx1 = np.stack([c1 % n[0], (c1 // n[0]) % n[1], c1 // (n[0] * n[1])], axis=1)
+    x1 = (idx1 + got["off"].T) / n * np.array(L)
+    dd = x1 - x_ex
+    dd -= np.round(dd / np.array(L)) * np.array(L)
+    assert np.abs(dd).max() < 1e-9, np.abs(dd).max()
+    v_ex = vp * np.cos(w * t) + vxb * np.sin(w * t)
+    v_ex[:, 2] = v0[:, 2]
+    np.testing.assert_allclose(got["vel"].T, v_ex, atol=1e-11)
+    sim.close()
