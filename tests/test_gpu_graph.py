@@ -54,14 +54,21 @@ def _same(a, b, exact):
     return db
 
 
-@pytest.mark.parametrize("name,precision", [("2d", 0), ("3d", 0), ("2d", 1)])
+@pytest.mark.parametrize("name,precision", [("2d", 0), ("3d", 0), ("2d", 1), ("3d_cyclotronic", 0)])
 def test_graph_steps_are_bitwise_the_ordinary_steps(name, precision):
     import torch
     st = torch.cuda.Stream()
-    case = (W.small_case(dim=2, n=(40, 24), ppc=8.0) if name == "2d"
-            else W.small_case(dim=3, n=(20, 12, 16), ppc=4.0))
-    a, _ = gpu_sim(case, precision=precision, sort_every=3, mg_rtol=1e-9, stream=st.cuda_stream)
-    b, _ = gpu_sim(case, precision=precision, sort_every=3, mg_rtol=1e-9, stream=st.cuda_stream)
+    pusher = 0
+    if name == "2d":
+        case = W.small_case(dim=2, n=(40, 24), ppc=8.0)
+    elif name == "3d":
+        case = W.small_case(dim=3, n=(20, 12, 16), ppc=4.0)
+    else:
+        # the cyclotronic variant of the particle kernel, omega_ce dt = 2
+        case = W.small_case(dim=3, n=(20, 12, 16), ppc=4.0, B=(0.0, 0.0, 20.0))
+        pusher = C().PUSH_CYCLOTRONIC
+    a, _ = gpu_sim(case, precision=precision, sort_every=3, mg_rtol=1e-9, stream=st.cuda_stream, pusher=pusher)
+    b, _ = gpu_sim(case, precision=precision, sort_every=3, mg_rtol=1e-9, stream=st.cuda_stream, pusher=pusher)
     b.set_graphs(True)
     a.initialize()
     b.initialize()
