@@ -68,6 +68,18 @@ def test_status_strings_and_argument_validation_without_gpu():
     m.omega = 1
     g.bc_lo[0] = g.bc_hi[0] = cpic.BC_DIRICHLET
     assert L.cpic_create(ctypes.byref(m), ctypes.byref(g), None, None, ctypes.byref(h)) == -9  # sinusoidal
+    # velocity step: unknown value; the cyclotronic step needs the Newton position update
+    m.omega = 0
+    g.bc_lo[0] = g.bc_hi[0] = cpic.BC_PERIODIC
+    g.pusher = 7
+    assert L.cpic_create(ctypes.byref(m), ctypes.byref(g), None, None, ctypes.byref(h)) == -1
+    g.pusher = cpic.PUSH_CYCLOTRONIC
+    g.mover = cpic.MOVER_PC
+    assert L.cpic_create(ctypes.byref(m), ctypes.byref(g), None, None, ctypes.byref(h)) == -9
+    # a tabulated map needs its vertex table
+    g.pusher, g.mover = 0, 0
+    tab = cpic.MapDesc(cpic.MAP_TABULATED, 2, (ctypes.c_double * 3)(1, 1, 1), 0.0, 1, 2, 0, None)
+    assert L.cpic_create(ctypes.byref(tab), ctypes.byref(g), None, None, ctypes.byref(h)) == -1
 
 
 def test_python_structures_match_the_header_layout(tmp_path):
