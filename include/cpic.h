@@ -276,8 +276,11 @@ cpic_status cpic_set_particles(cpic_sim* sim, int species_id, size_t n, const in
                                int on_device);
 
 /* Copy particles out (synchronises).  Arrays as in cpic_set_particles with
-   room for cap particles; *n receives the live count.  Order is the library's
-   (tile-sorted); ids identify particles when track_ids is set. */
+   room for cap particles; *n receives the number of slots in use: the live
+   particles and, until their species' next tile sort, those that left since
+   the last one, with cell -1 (absorbed) or -2 (left through an upper wall).
+   Order is the library's (tile-sorted, particles injected since the last sort
+   after the others); ids identify particles when track_ids is set. */
 cpic_status cpic_get_particles(cpic_sim* sim, int species_id, size_t cap, int32_t* cell,
                                void* off, void* vel, uint32_t* ids, size_t* n, int on_device);
 

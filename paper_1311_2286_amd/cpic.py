@@ -326,9 +326,14 @@ class Sim:
                                                 _ptr(ids), int(on_dev)), "set_particles")
 
     def get_particles(self, sid, cap=None):
+        """All slots in use (see cpic_get_particles): the live particles and,
+        until the species' next sort, those that left (cell -1 or -2)."""
         if cap is None:
-            d = self.diag()
-            cap = int(d.count[sid])
+            n = ctypes.c_size_t()
+            st = self.lib.cpic_get_particles(self.h, sid, 0, None, None, None, None, ctypes.byref(n), 0)
+            if st not in (0, -4):  # -4: the slot count came back in n
+                self._check(st, "get_particles")
+            cap = int(n.value)
         cell = np.zeros(max(cap, 1), dtype=np.int32)
         off = np.zeros((self.dim, max(cap, 1)), dtype=self.rdtype)
         vel = np.zeros((3, max(cap, 1)), dtype=self.rdtype)

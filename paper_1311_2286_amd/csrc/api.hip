@@ -43,6 +43,7 @@ struct Species {
   double* ke_part = nullptr;
   // absorbed, outflow, fallback, far, nonconv, injected, dropped, ids issued
   unsigned long long* counters = nullptr;
+  unsigned long long* dead_mark = nullptr;  // counters[0..1] (absorbed, outflow) at the last sort
   double inject_lam = 0.0;
   int* fb_queue = nullptr;  // particles handed to the FP64 fallback kernel
   int* fb_count = nullptr;
@@ -618,8 +619,9 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
   S.item_tile = (int*)A(sizeof(int) * S.max_items);
   S.item_begin = (int*)A(sizeof(int) * S.max_items);
   S.item_end = (int*)A(sizeof(int) * S.max_items);
-  S.ke_part = (double*)A(sizeof(double) * S.max_items);
+  S.ke_part = (double*)A(sizeof(double) * (S.max_items + TAIL_ITEMS));  // + the appended particles' items
   S.counters = (unsigned long long*)A(sizeof(unsigned long long) * 8);
+  S.dead_mark = (unsigned long long*)A(sizeof(unsigned long long) * 2);
   S.fb_queue = (int*)A(sizeof(int) * S.cap);
   S.fb_count = (int*)A(sizeof(int) * 2);
   if (!ok) return fail(s, CPIC_E_NOMEM, "species allocation failed");
@@ -627,6 +629,7 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
   launch_fill_u8(S.d_n, 0, sizeof(int) * 2, st);
   launch_fill_u8(S.n_items, 0, sizeof(int) * 2, st);
   launch_fill_u8(S.counters, 0, sizeof(unsigned long long) * 8, st);
+  launch_fill_u8(S.dead_mark, 0, sizeof(unsigned long long) * 2, st);
   launch_fill_u8(S.Q, 0, 8 * (size_t)s->g.ncells, st);
   s->sp.push_back(S);
   *sid = (int)s->sp.size() - 1;
@@ -760,6 +763,8 @@ static void sort_species(cpic_sim* s, Species& S, bool counts_ready) {
   L.item_end = S.item_end;
   L.counts_ready = counts_ready ? 1 : 0;
   launch_tile_sort(L, s->stream);
+  // the sort compacts away the particles that left: remember how many had
+  (void)hipMemcpyAsync(S.dead_mark, S.counters, sizeof(unsigned long long) * 2, hipMemcpyDeviceToDevice, s->stream);
   S.cur = b;
 }
 
@@ -816,6 +821,7 @@ static void particles_pass(cpic_sim* s, int mode, unsigned count_mask = 0) {
     L.item_end = S.item_end;
     L.n_items = S.n_items;
     L.max_items = S.max_items;
+    L.d_n = S.d_n;
     L.Ev = s->G.Ev;
     L.Q = S.Q;
     L.qm = S.desc.q / S.desc.m;
@@ -857,6 +863,9 @@ static void particles_pass(cpic_sim* s, int mode, unsigned count_mask = 0) {
     for (int k = 0; k < r.nspecies; ++k) {
       r.part[k] = s->sp[k].ke_part;
       r.n_items[k] = s->sp[k].n_items;
+      // the particle kernels of the maps that allow injection run TAIL_ITEMS
+      // more work items (the particles appended since the last sort)
+      r.tail[k] = (s->g.kind == CPIC_MAP_IDENTITY || s->g.kind == CPIC_MAP_POLAR_LOG || s->kc) ? TAIL_ITEMS : 0;
       r.scale[k] = 0.5 * s->sp[k].desc.m * s->sp[k].desc.w;
     }
     r.out = s->ke;
@@ -960,14 +969,15 @@ static void record_cycles(cpic_sim* s) {
 // drift since its last sort (steps x the largest increment seen so far,
 // copied back asynchronously) is below one cell, the slack of the tile
 // windows, and at least every 16 sort_every steps.  Injecting species sort
-// every step (appended particles join a tile at a sort).
+// every sort_every steps: their appended particles, processed meanwhile by one
+// extra work item through the global paths, join their tiles at a sort.
 static unsigned sort_mask(const cpic_sim* s) {
   const int K = s->grid.sort_every;
   unsigned mask = 0;
   for (size_t k = 0; k < s->sp.size(); ++k) {
     const Species& S = s->sp[k];
     const int after = S.since_sort + 1;
-    bool sort = S.desc.inject != 0;
+    bool sort = S.desc.inject != 0 && after >= K;
     if (!sort && after >= K) {
       float dmax = 0.0f;
       if (s->drift_host) {
@@ -1226,12 +1236,13 @@ extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
   HIPCHK(s, hipMemcpyAsync(sc, s->G.scalars, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
   if (s->G.floating) HIPCHK(s, hipMemcpyAsync(wall, s->G.scalars + 10, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
   HIPCHK(s, hipMemcpyAsync(fl, s->G.mg_flag, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
-  std::vector<unsigned long long> cnt(8 * s->sp.size());
+  std::vector<unsigned long long> cnt(8 * s->sp.size()), mark(2 * s->sp.size());
   std::vector<int> ns(s->sp.size());
   std::vector<uint64_t> qs(2 * s->sp.size());
   for (size_t k = 0; k < s->sp.size(); ++k) {
     Species& S = s->sp[k];
     HIPCHK(s, hipMemcpyAsync(&cnt[8 * k], S.counters, sizeof(unsigned long long) * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipMemcpyAsync(&mark[2 * k], S.dead_mark, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost, st));
     HIPCHK(s, hipMemcpyAsync(&ns[k], S.d_n, sizeof(int), hipMemcpyDeviceToHost, st));
     if (s->grid.precision == CPIC_FP32) {
       launch_qsum((const uint64_t*)S.Q, s->g.ncells, s->qsum, st);
@@ -1248,7 +1259,8 @@ extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
   out->mg_relres = sc[0] > 0 ? sqrt(sc[1] / sc[0]) : 0.0;
   out->mg_cycles = fl[1];
   for (size_t k = 0; k < s->sp.size() && k < 8; ++k) {
-    out->count[k] = ns[k];
+    // slots in use less the particles that left since the last sort
+    out->count[k] = ns[k] - (long long)((cnt[8 * k] + cnt[8 * k + 1]) - (mark[2 * k] + mark[2 * k + 1]));
     out->absorbed[k] = (long long)cnt[8 * k + 0];
     out->outflow[k] = (long long)cnt[8 * k + 1];
     out->newton_fallback += (long long)cnt[8 * k + 2];

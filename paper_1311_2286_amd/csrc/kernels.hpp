@@ -21,6 +21,7 @@ struct ParticleLaunch {
   const int* item_end;
   const int* n_items;
   int max_items;
+  const int* d_n;   // live count, appended (injected) particles included
   const void* Ev;
   void* Q;
   int pbc_lo[3], pbc_hi[3];
@@ -47,10 +48,15 @@ struct ParticleLaunch {
   unsigned long long* counters;
 };
 
+// work items of the particles appended (injected) since a species' last sort:
+// the kernels of maps that allow injection split them over this many items
+constexpr int TAIL_ITEMS = 64;
+
 struct KeReduce {
   int nspecies;
   const double* part[8];
   const int* n_items[8];
+  int tail[8];  // the per-item sums hold this many more slots: the appended particles' items
   double scale[8];
   double* out;
 };

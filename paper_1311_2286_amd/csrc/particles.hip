@@ -518,6 +518,7 @@ struct PartArgs {
   const int* item_begin;
   const int* item_end;
   const int* n_items;
+  const int* d_n;  // live count, particles appended since the last sort included
   const R* Ev;
   const R* kc;  // predictor-corrector mover: n_a dxi^a/dx^b at every vertex (row-major D x D,
                 // padded to KC_STRIDE<D> values so a vertex is whole 16-byte loads)
@@ -836,6 +837,17 @@ __device__ __forceinline__ bool gather_E_window(const R* __restrict__ ewin, cons
   return true;
 }
 
+// Slot range of the t-th of the TAIL_ITEMS work items that share the particles
+// appended since the last sort: [end of the last sorted item, live count).
+template <typename R>
+__device__ inline void tail_range(const PartArgs<R>& a, int nit, int t, int& begin, int& end) {
+  const int b0 = nit > 0 ? a.item_end[nit - 1] : 0;
+  const int total = *a.d_n - b0;
+  const int per = (total + TAIL_ITEMS - 1) / TAIL_ITEMS;
+  begin = b0 + min(total, t * per);
+  end = b0 + min(total, (t + 1) * per);
+}
+
 // CYC: the cyclotronic velocity step (a uniform B) in place of Boris
 template <int D, int MAP, int SHAPE, typename R, bool FIXED, bool CYC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && MAP != MAP_TABULATED) ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel(
@@ -854,12 +866,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
   __shared__ unsigned long long red_u[8][5];
   __shared__ int tbins[TB_N];  // new tiles of the particles (see count_new_tile)
 
+  // maps that allow injection: TAIL_ITEMS more work items share the particles
+  // appended since the last sort (they follow the sorted ones), through the
+  // global gather and deposit paths, so an injecting species need not sort
+  // every step
+  constexpr bool TAIL = MAP == MAP_IDENTITY || MAP == MAP_POLAR_LOG || MAP == MAP_TABLE_PC;
   const int item = blockIdx.x;
-  if (item >= *a.n_items) return;
   const Geo& g = a.g;
-  const int tile = a.item_tile[item];
-  const int begin = a.item_begin[item];
-  const int end = a.item_end[item];
+  int tile, begin, end;
+  if constexpr (TAIL) {
+    const int nit = *a.n_items;
+    if (item >= nit + TAIL_ITEMS) return;
+    if (item < nit) {
+      tile = a.item_tile[item];
+      begin = a.item_begin[item];
+      end = a.item_end[item];
+    } else {
+      tile = 0;
+      tail_range(a, nit, item - nit, begin, end);
+      if (begin >= end) {
+        if (threadIdx.x == 0 && a.mode == MODE_PUSH) a.ke_part[item] = 0.0;
+        return;
+      }
+    }
+  } else {
+    if (item >= *a.n_items) return;
+    tile = a.item_tile[item];
+    begin = a.item_begin[item];
+    end = a.item_end[item];
+  }
   int origin[3];
   origin[0] = (tile % g.nt[0]) * TS::T0;
   origin[1] = ((tile / g.nt[0]) % g.nt[1]) * TS::T1;
@@ -1049,7 +1084,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
       int other = 0;
       for (int b = 0; b < TB_N; ++b) other += b == TB_OWN ? 0 : tbins[b];
       // the item's bounds are read again rather than kept live across the loop
-      tbins[TB_OWN] = (a.item_end[item] - a.item_begin[item]) - other;
+      int nb;
+      if constexpr (TAIL) {
+        const int nit = *a.n_items;
+        if (item < nit) {
+          nb = a.item_end[item] - a.item_begin[item];
+        } else {
+          int b0, e0;
+          tail_range(a, nit, item - nit, b0, e0);
+          nb = e0 - b0;
+        }
+      } else {
+        nb = a.item_end[item] - a.item_begin[item];
+      }
+      tbins[TB_OWN] = nb - other;
     }
     __syncthreads();
     if (threadIdx.x < 27) {
@@ -1656,6 +1704,7 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   a.item_begin = L.item_begin;
   a.item_end = L.item_end;
   a.n_items = L.n_items;
+  a.d_n = L.d_n;
   a.Ev = (const R*)L.Ev;
   a.kc = (const R*)L.kc;
   a.Q = L.Q;
@@ -1692,11 +1741,13 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   a.fb_cap = L.fb_cap;
   if (L.max_items <= 0) return;
   constexpr bool FIXED = std::is_same<R, float>::value;
+  // the appended particles' items (maps that allow injection)
+  const int tail = (MAP == MAP_IDENTITY || MAP == MAP_POLAR_LOG || MAP == MAP_TABLE_PC) ? TAIL_ITEMS : 0;
   if (L.cyclo)
-    hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED, true>), dim3(L.max_items), dim3(256), 0, st,
+    hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED, true>), dim3(L.max_items + tail), dim3(256), 0, st,
                      a);
   else
-    hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED, false>), dim3(L.max_items), dim3(256), 0, st,
+    hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED, false>), dim3(L.max_items + tail), dim3(256), 0, st,
                      a);
   if constexpr (MAP != MAP_IDENTITY && MAP != MAP_TABLE_PC) {
     if (L.mode == MODE_PUSH)
@@ -1822,7 +1873,7 @@ __global__ __launch_bounds__(256) void ke_reduce_kernel(KeReduce r) {
   __shared__ double sh[256];
   double total = 0.0;
   for (int k = 0; k < r.nspecies; ++k) {
-    const int n = *r.n_items[k];
+    const int n = *r.n_items[k] + r.tail[k];
     double t = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) t += r.part[k][i];
     sh[threadIdx.x] = t;

@@ -88,11 +88,14 @@ def test_injection_draw_by_draw(precision):
     sim.close()
 
 
-def test_probe_steps_counts_match_oracle():
+@pytest.mark.parametrize("sort_every", [1, 3])
+def test_probe_steps_counts_match_oracle(sort_every):
+    # sort_every 3: between sorts the injected particles are moved by the extra
+    # work item of appended particles
     case = probe_case(ppc=4.0)
     seed = 78
     sim, parts = gpu_sim(case, precision=1, inject=True, seed=seed, capacity_factor=1.6,
-                         mg_rtol=1e-13)
+                         mg_rtol=1e-13, sort_every=sort_every)
     m, g = oracle_objects(case)
     sp = oracle_species(case, parts)
     for sid, s in enumerate(case.species):
@@ -100,7 +103,7 @@ def test_probe_steps_counts_match_oracle():
     osim = O.OracleSim(m, g, sp, dt=case.dt, deposit="f64", rtol=1e-13, ke_axes=2)
     sim.initialize()
     osim.initialize()
-    for k in range(3):
+    for k in range(5):
         sim.step(1)
         osim.step()
         d = sim.diag()
