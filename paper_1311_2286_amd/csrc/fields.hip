@@ -453,6 +453,28 @@ __device__ inline double block_sum(double v) {
   return s;  // valid in thread 0
 }
 
+// Workgroups are dealt to the eight XCDs round-robin in launch order.  The
+// stencil kernels below take their tile from a remapped index instead, so that
+// each XCD walks a contiguous run of tiles (whole z-planes in order) and finds
+// the neighbour rows and planes it reads in its own L2.  The map is a
+// bijection (identity unless the tile count divides by eight); `blk` is the
+// logical tile number, which orders the per-block partial sums as before.
+struct Tile3 {
+  int bx, by, bz, blk;
+};
+__device__ inline Tile3 xcd_tile() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int nb = gx * gy * (int)gridDim.z;
+  const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int t = (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+  Tile3 r;
+  r.bx = t % gx;
+  r.by = (t / gx) % gy;
+  r.bz = t / (gx * gy);
+  r.blk = t;
+  return r;
+}
+
 // kind 0: sum a*b; kind 1: sum a; kind 2: sum a*a
 __global__ __launch_bounds__(256) void reduce_partial_kernel(const double* a, const double* b, long long n,
                                                              int kind, double* partials,
@@ -575,9 +597,10 @@ __global__ __launch_bounds__(256) void smooth_kernel(LevelArgsT<T> a, const T* _
                                                      const T* __restrict__ rhs, T* out, double cr, double cd,
                                                      const T* dprev, T* dout, const int* flag, double* partials) {
   if (flag[0]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
+  const Tile3 T3 = xcd_tile();
+  const int i = T3.bx * blockDim.x + threadIdx.x;
+  const int j = T3.by * blockDim.y + threadIdx.y;
+  const int k = T3.bz;
   double rr = 0.0;
   if (i < a.n[0] && j < a.n[1]) {
     const int idx[3] = {i, j, k};
@@ -592,7 +615,7 @@ __global__ __launch_bounds__(256) void smooth_kernel(LevelArgsT<T> a, const T* _
   if (partials) {
     double t = block_sum(rr);
     if (threadIdx.x == 0 && threadIdx.y == 0)
-      partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = t;
+      partials[T3.blk] = t;
   }
 }
 
@@ -769,9 +792,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void residual_kernel(LevelArgsT<T> a, const T* __restrict__ phi,
                                                        const T* __restrict__ rhs, T* res, const int* flag) {
   if (flag[0]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
+  const Tile3 T3 = xcd_tile();
+  const int i = T3.bx * blockDim.x + threadIdx.x;
+  const int j = T3.by * blockDim.y + threadIdx.y;
+  const int k = T3.bz;
   if (i >= a.n[0] || j >= a.n[1]) return;
   const int idx[3] = {i, j, k};
   const int c = i + a.n[0] * (j + a.n[1] * k);
@@ -1228,9 +1252,10 @@ __global__ void residual_norm_kernel(LevelArgs a, const double* __restrict__ phi
                                      const double* __restrict__ rhs, double* partials,
                                      const int* flag) {
   if (flag[0]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
+  const Tile3 T3 = xcd_tile();
+  const int i = T3.bx * blockDim.x + threadIdx.x;
+  const int j = T3.by * blockDim.y + threadIdx.y;
+  const int k = T3.bz;
   double rr = 0.0;
   if (i < a.n[0] && j < a.n[1]) {
     const int idx[3] = {i, j, k};
@@ -1240,7 +1265,7 @@ __global__ void residual_norm_kernel(LevelArgs a, const double* __restrict__ phi
   }
   double t = block_sum(rr);
   if (threadIdx.x == 0 && threadIdx.y == 0)
-    partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = t;
+    partials[T3.blk] = t;
 }
 
 __global__ void mg_reset_kernel(int* flag) {
@@ -1566,9 +1591,10 @@ __global__ __launch_bounds__(256) void fcg_residual_kernel(LevelArgs a, const do
                                                            const double* __restrict__ b, double* r, float* r32,
                                                            float* z, double* partials, const int* flag) {
   if (flag[0]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
+  const Tile3 T3 = xcd_tile();
+  const int i = T3.bx * blockDim.x + threadIdx.x;
+  const int j = T3.by * blockDim.y + threadIdx.y;
+  const int k = T3.bz;
   double rr = 0.0;
   if (i < a.n[0] && j < a.n[1]) {
     const int idx[3] = {i, j, k};
@@ -1580,7 +1606,7 @@ __global__ __launch_bounds__(256) void fcg_residual_kernel(LevelArgs a, const do
     rr = v * v;
   }
   const double t = block_sum(rr);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = t;
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[T3.blk] = t;
 }
 
 // w = A z and the block sums of z.w, q.z (first iteration: 0), z.r
@@ -1589,9 +1615,10 @@ __global__ __launch_bounds__(256) void fcg_apply_kernel(LevelArgs a, const float
                                                         double* w, double* partials, int nblk, int first,
                                                         const int* flag) {
   if (flag[0]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
+  const Tile3 T3 = xcd_tile();
+  const int i = T3.bx * blockDim.x + threadIdx.x;
+  const int j = T3.by * blockDim.y + threadIdx.y;
+  const int k = T3.bz;
   double zw = 0.0, qz = 0.0, zr = 0.0;
   if (i < a.n[0] && j < a.n[1]) {
     const int idx[3] = {i, j, k};
@@ -1603,7 +1630,7 @@ __global__ __launch_bounds__(256) void fcg_apply_kernel(LevelArgs a, const float
     qz = first ? 0.0 : q[c] * zc;
     zr = zc * r[c];
   }
-  const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int blk = T3.blk;
   double t = block_sum(zw);
   if (threadIdx.x == 0 && threadIdx.y == 0) partials[blk] = t;
   t = block_sum(qz);
