@@ -456,9 +456,14 @@ __device__ inline double block_sum(double v) {
 // Workgroups are dealt to the eight XCDs round-robin in launch order.  The
 // stencil kernels below take their tile from a remapped index instead, so that
 // each XCD walks a contiguous run of tiles (whole z-planes in order) and finds
-// the neighbour rows and planes it reads in its own L2.  The map is a
-// bijection (identity unless the tile count divides by eight); `blk` is the
-// logical tile number, which orders the per-block partial sums as before.
+// the neighbour rows and planes it reads in its own L2.  That pays only while
+// three planes of the stencil's arrays fit in one XCD's 4 MB L2: planes of at
+// most XCD_PLANE_TILES tiles (16,384 cells: 3 x 44 B x 16,384 = 2.2 MB in
+// FP32); larger planes keep the launch order, which spreads every plane over
+// all eight L2s.  The map is a bijection (identity unless the tile count
+// divides by eight); `blk` is the logical tile number, which orders the
+// per-block partial sums as before.
+constexpr int XCD_PLANE_TILES = 64;
 struct Tile3 {
   int bx, by, bz, blk;
 };
@@ -466,7 +471,7 @@ __device__ inline Tile3 xcd_tile() {
   const int gx = gridDim.x, gy = gridDim.y;
   const int nb = gx * gy * (int)gridDim.z;
   const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-  const int t = (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+  const int t = ((nb & 7) == 0 && gx * gy <= XCD_PLANE_TILES) ? (b & 7) * (nb >> 3) + (b >> 3) : b;
   Tile3 r;
   r.bx = t % gx;
   r.by = (t / gx) % gy;
