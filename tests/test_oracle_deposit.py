@@ -179,3 +179,52 @@ def test_background_total_is_physical_volume(shape):
     m0 = O.make_map(O.IDENTITY, 2, (3.0, 2.0), 0.0)
     I0 = O.ion_background(m0, g, shape, n0=1.0)
     np.testing.assert_allclose(I0, 6.0 / 192, rtol=1e-13)
+
+
+def _spline_ft(shape, k):
+    """Fourier transform at wavenumber k (radians per cell) of the unit-area
+    B-spline of the deposit: the box function convolved with itself once (b1,
+    the CIC hat) or twice (b2), so sinc(k/2)^2 resp. ^3."""
+    s = np.sinc(k / (2.0 * np.pi))  # numpy's sinc is sin(pi x) / (pi x)
+    return s ** (3 if shape == O.B2 else 2)
+
+
+@pytest.mark.parametrize("shape", [O.B2, O.B1])
+def test_background_per_cell_closed_form_2d(shape):
+    # Sinusoidal map (Eq. map2) in box units: J = 1 + 2 pi eps sin 2 pi (xi + eta),
+    # a single Fourier mode.  The shape is even, so its integral against
+    # sin(theta_c + k u) is sin(theta_c) times the spline's transform at k:
+    #   I_c = n0 dV [1 + 2 pi eps sin 2 pi (xi_c + eta_c) * prod_a FT(2 pi h_a)]
+    # with (xi_c, eta_c) the cell centre and h_a = 1 / n_a in box units.  A node
+    # set shifted by half a cell, a wrong spline order or a dropped Jacobian
+    # factor all move I_c by far more than the tolerance.
+    L, eps, n = (3.0, 2.0), 0.1, (16, 12)
+    m = O.make_map(O.SINUSOIDAL, 2, L, eps)
+    g = O.make_grid(n)
+    I = O.ion_background(m, g, shape, n0=1.7)
+    i, j = np.meshgrid(np.arange(n[0]), np.arange(n[1]), indexing="ij")
+    xc, yc = (i + 0.5) / n[0], (j + 0.5) / n[1]
+    damp = _spline_ft(shape, 2 * np.pi / n[0]) * _spline_ft(shape, 2 * np.pi / n[1])
+    dV = L[0] * L[1] / (n[0] * n[1])
+    ref = 1.7 * dV * (1.0 + 2 * np.pi * eps * np.sin(2 * np.pi * (xc + yc)) * damp)
+    # cell c = i + n0 j
+    got = I.reshape(n[1], n[0]).T
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=0)
+
+
+def test_background_per_cell_closed_form_3d():
+    # 3D map x^i = L (xi^i + eps s1 s2 s3): J = 1 + 2 pi eps (c1 s2 s3 + s1 c2 s3
+    # + s1 s2 c3) in box units; each term is a product of one cosine and two
+    # sines of the three axes, so every axis contributes its factor FT(2 pi h_a).
+    eps, n = 0.05, (6, 5, 4)
+    m = O.make_map(O.SINUSOIDAL, 3, (1.0, 1.0, 1.0), eps)
+    g = O.make_grid(n)
+    I = O.ion_background(m, g, O.B2, n0=1.0)
+    i, j, k = np.meshgrid(np.arange(n[0]), np.arange(n[1]), np.arange(n[2]), indexing="ij")
+    a = [2 * np.pi * (i + 0.5) / n[0], 2 * np.pi * (j + 0.5) / n[1], 2 * np.pi * (k + 0.5) / n[2]]
+    s, c = [np.sin(t) for t in a], [np.cos(t) for t in a]
+    P = c[0] * s[1] * s[2] + s[0] * c[1] * s[2] + s[0] * s[1] * c[2]
+    damp = np.prod([_spline_ft(O.B2, 2 * np.pi / nn) for nn in n])
+    ref = (1.0 + 2 * np.pi * eps * P * damp) / (n[0] * n[1] * n[2])
+    got = I.reshape(n[2], n[1], n[0]).transpose(2, 1, 0)
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=0)
