@@ -256,6 +256,9 @@ typedef struct {
                                 drift less than a cell between sorts is sorted less often) */
   double phi_wall;           /* potential of a floating wall (CPIC_BC_FLOATING), else 0 */
   double wall_charge;        /* charge it holds: sum of q w over the particles it absorbed */
+  long long inject_lost[8];  /* cumulative injected particles whose entry flight (a random fraction of
+                                the step from the face) left the domain at once: never live, not in
+                                injected[] */
 } cpic_diag;
 
 /* Create a simulation on the current HIP device.  hip_stream may be NULL
@@ -270,7 +273,14 @@ cpic_status cpic_add_species(cpic_sim* sim, const cpic_species_desc* desc, int* 
 
 /* Copy n particles in (host pointers, or device pointers when on_device != 0).
    cell: int32 [n]; off: [dim][n]; vel: [3][n] (float for CPIC_FP32, double for
-   CPIC_FP64); ids: uint32 [n] or NULL (ids 0..n-1).  n <= capacity. */
+   CPIC_FP64); ids: uint32 [n] or NULL (ids 0..n-1).  n <= capacity (else
+   CPIC_E_BUDGET).  Host input is validated first: cells out of range or
+   offsets outside [0, 1) give CPIC_E_ARG; on the FP32 path, 2^16 or more
+   particles within one 3^d block of cells give CPIC_E_OVERFLOW, as their
+   fixed-point deposit (at most 2^{d S1} = 2^48 per particle and cell) could
+   pass 64 bits in the block's centre cell.  Both leave the simulation
+   unchanged.  Device input is range-checked on the device (CPIC_E_ARG); a
+   deposit that wraps later is reported by cpic_get_diag / cpic_sync. */
 cpic_status cpic_set_particles(cpic_sim* sim, int species_id, size_t n, const int32_t* cell,
                                const void* off, const void* vel, const uint32_t* ids,
                                int on_device);
@@ -295,7 +305,8 @@ cpic_status cpic_step(cpic_sim* sim, int nsteps);
 cpic_status cpic_run_stage(cpic_sim* sim, int stage);
 
 /* Field copies (synchronise).  species_id is used by CPIC_FIELD_Q only.
-   bytes must equal the field's size. */
+   bytes must equal the field's size.  cpic_set_field rejects host input that
+   holds a NaN or an infinity (CPIC_E_NONFINITE) before copying anything. */
 cpic_status cpic_get_field(cpic_sim* sim, int which, int species_id, void* dst, size_t bytes,
                            int on_device);
 cpic_status cpic_set_field(cpic_sim* sim, int which, int species_id, const void* src,
@@ -304,10 +315,17 @@ cpic_status cpic_set_field(cpic_sim* sim, int which, int species_id, const void*
 /* Size in bytes of a field (for get/set). */
 size_t cpic_field_bytes(const cpic_sim* sim, int which);
 
-/* Diagnostics (synchronises). */
+/* Diagnostics (synchronises).  Also checks the state: returns
+   CPIC_E_NONFINITE (diagnostics filled) when the potential, the charge or the
+   vertex field holds a NaN or an infinity, and CPIC_E_OVERFLOW (diagnostics
+   filled) when a species' fixed-point deposit wrapped -- its exact total
+   sum_c Q_s differs from (particles deposited) x 2^{d S1}, which every
+   particle adds exactly; after that cpic_step returns CPIC_E_OVERFLOW until
+   cpic_set_particles loads new particles.  Neither changes the simulation. */
 cpic_status cpic_get_diag(cpic_sim* sim, cpic_diag* out);
 
-/* Wait for all work on the simulation's stream. */
+/* Wait for all work on the simulation's stream, then run the checks of
+   cpic_get_diag (CPIC_E_NONFINITE, CPIC_E_OVERFLOW). */
 cpic_status cpic_sync(cpic_sim* sim);
 
 /* Per-step durations (ms) of every step since timing was last enabled by

@@ -34,6 +34,7 @@ EXPORTED = ["cpic_create", "cpic_add_species", "cpic_set_particles", "cpic_get_p
             "cpic_server_submit", "cpic_server_pump", "cpic_server_poll", "cpic_server_get_stats",
             "cpic_server_destroy"]
 MAX_SPECIES = 8
+E_ARG, E_MAP, E_NOMEM, E_BUDGET, E_HIP, E_OVERFLOW, E_NONFINITE, E_STATE, E_UNSUPPORTED = range(-1, -10, -1)
 E_PENDING = 1
 
 
@@ -78,7 +79,7 @@ class Diag(ctypes.Structure):
                 ("far_deposits", ctypes.c_longlong), ("newton_failed", ctypes.c_longlong),
                 ("injected", ctypes.c_longlong * 8), ("step_graphs", ctypes.c_int),
                 ("sorts", ctypes.c_longlong * 8), ("phi_wall", ctypes.c_double),
-                ("wall_charge", ctypes.c_double)]
+                ("wall_charge", ctypes.c_double), ("inject_lost", ctypes.c_longlong * 8)]
 
 
 class CaseDesc(ctypes.Structure):

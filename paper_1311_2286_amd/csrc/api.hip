@@ -21,6 +21,11 @@ using namespace cpic;
 namespace {
 
 constexpr int MAX_SPECIES = 8;
+constexpr int NCOUNTERS = 10;
+// Records of the last steps copied back to the host (solver iterations used,
+// particle drift), one slot per step in a ring; step n waits for the record of
+// step n - 2, so what it launches is a fixed function of the device state.
+constexpr int HIST = 4;
 
 struct Species {
   cpic_species_desc desc;
@@ -41,9 +46,10 @@ struct Species {
   int* item_end = nullptr;
   int max_items = 0;
   double* ke_part = nullptr;
-  // absorbed, outflow, fallback, far, nonconv, injected, dropped, ids issued
+  // absorbed, outflow, fallback, far, nonconv, injected, dropped, ids issued, injected but
+  // gone at once, deposited since Q was cleared (NCOUNTERS)
   unsigned long long* counters = nullptr;
-  unsigned long long* dead_mark = nullptr;  // counters[0..1] (absorbed, outflow) at the last sort
+  unsigned long long* dead_mark = nullptr;  // counters[0..8] at the last sort (departures since then)
   double inject_lam = 0.0;
   int* fb_queue = nullptr;  // particles handed to the FP64 fallback kernel
   int* fb_count = nullptr;
@@ -75,10 +81,12 @@ struct cpic_sim {
   bool phi_prev_valid = false;  // G.phi_prev holds the previous step's potential
   void* kc = nullptr;           // predictor-corrector mover: vertex table of n_a dxi^a/dx^b
   bool graphs = false;          // replay recorded HIP graphs of the step
-  int* cycles_host = nullptr;   // pinned: V-cycles of a recent solve (written by async copies)
-  bool cycles_known = false;
   unsigned* drift_dev = nullptr;   // per species: running max of a particle's increment (cells, FP32 bits)
-  unsigned* drift_host = nullptr;  // pinned copy of a recent drift_dev (written by async copies)
+  int* cycles_host = nullptr;      // pinned [HIST]: V-cycles of the solve of step n in slot n % HIST
+  unsigned* drift_host = nullptr;  // pinned [HIST][8]: drift_dev after step n in slot n % HIST
+  hipEvent_t hist_ev[HIST] = {};   // recorded after the copies of step n, slot n % HIST
+  long long hist_from = 0;         // records of steps before this one are not used
+  bool overflowed = false;         // a fixed-point deposit wrapped (sticky until new particles)
   struct StepGraph {
     uint64_t key;
     hipGraphExec_t exec;
@@ -465,18 +473,24 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   launch_jacobian_centres(G, st);
   launch_vertex_metric(G, st);
   if (s->kc) launch_kc_table(g, G.Kv, s->kc, G.fp64, st);
-  if (hipHostMalloc((void**)&s->cycles_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&s->cycles_host, sizeof(int) * HIST, hipHostMallocDefault) != hipSuccess) {
     s->cycles_host = nullptr;
     cpic_destroy(s);
     return CPIC_E_NOMEM;
   }
-  *s->cycles_host = -1;
-  if (hipHostMalloc((void**)&s->drift_host, sizeof(unsigned) * 8, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&s->drift_host, sizeof(unsigned) * 8 * HIST, hipHostMallocDefault) != hipSuccess) {
     s->drift_host = nullptr;
     cpic_destroy(s);
     return CPIC_E_NOMEM;
   }
-  memset(s->drift_host, 0, sizeof(unsigned) * 8);
+  for (int i = 0; i < HIST; ++i) s->cycles_host[i] = -1;
+  memset(s->drift_host, 0, sizeof(unsigned) * 8 * HIST);
+  for (int i = 0; i < HIST; ++i)
+    if (hipEventCreateWithFlags(&s->hist_ev[i], hipEventDisableTiming) != hipSuccess) {
+      s->hist_ev[i] = nullptr;
+      cpic_destroy(s);
+      return CPIC_E_HIP;
+    }
   if (compute_smoother_bounds(G, st) != 0 || setup_coarse_inverse(G, st) != 0 || setup_floating_wall(G, st) != 0) {
     cpic_destroy(s);
     return CPIC_E_HIP;
@@ -620,16 +634,16 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
   S.item_begin = (int*)A(sizeof(int) * S.max_items);
   S.item_end = (int*)A(sizeof(int) * S.max_items);
   S.ke_part = (double*)A(sizeof(double) * (S.max_items + TAIL_ITEMS));  // + the appended particles' items
-  S.counters = (unsigned long long*)A(sizeof(unsigned long long) * 8);
-  S.dead_mark = (unsigned long long*)A(sizeof(unsigned long long) * 2);
+  S.counters = (unsigned long long*)A(sizeof(unsigned long long) * NCOUNTERS);
+  S.dead_mark = (unsigned long long*)A(sizeof(unsigned long long) * NCOUNTERS);
   S.fb_queue = (int*)A(sizeof(int) * S.cap);
   S.fb_count = (int*)A(sizeof(int) * 2);
   if (!ok) return fail(s, CPIC_E_NOMEM, "species allocation failed");
   hipStream_t st = s->stream;
   launch_fill_u8(S.d_n, 0, sizeof(int) * 2, st);
   launch_fill_u8(S.n_items, 0, sizeof(int) * 2, st);
-  launch_fill_u8(S.counters, 0, sizeof(unsigned long long) * 8, st);
-  launch_fill_u8(S.dead_mark, 0, sizeof(unsigned long long) * 2, st);
+  launch_fill_u8(S.counters, 0, sizeof(unsigned long long) * NCOUNTERS, st);
+  launch_fill_u8(S.dead_mark, 0, sizeof(unsigned long long) * NCOUNTERS, st);
   launch_fill_u8(S.Q, 0, 8 * (size_t)s->g.ncells, st);
   s->sp.push_back(S);
   *sid = (int)s->sp.size() - 1;
@@ -640,6 +654,40 @@ extern "C" cpic_status cpic_add_species(cpic_sim* s, const cpic_species_desc* de
 // ----------------------------------------------------------------------------
 // particles in / out
 // ----------------------------------------------------------------------------
+// Headroom of the fixed-point deposit: a particle adds at most 2^{d S1} = 2^48
+// to any cell, and only to cells within one of its own per axis, so a cell's
+// uint64 sum cannot wrap while every 3^d block of cells holds fewer than 2^16
+// particles.  True when some block holds more (host arrays).
+static bool crowded(const cpic_sim* s, size_t n, const int32_t* cell) {
+  if (n < (1u << 16)) return false;
+  const Geo& g = s->g;
+  std::vector<uint32_t> cnt((size_t)g.ncells, 0u);
+  for (size_t p = 0; p < n; ++p) ++cnt[(size_t)cell[p]];
+  // sums over windows of three cells, one axis at a time (wrapped on periodic
+  // axes, cut at walls)
+  std::vector<uint64_t> a(cnt.begin(), cnt.end()), b((size_t)g.ncells);
+  const long long str[3] = {1, g.n[0], (long long)g.n[0] * g.n[1]};
+  for (int ax = 0; ax < g.dim; ++ax) {
+    const int nn = g.n[ax];
+    for (long long c = 0; c < g.ncells; ++c) {
+      const int i = (int)((c / str[ax]) % nn);
+      uint64_t v = a[(size_t)c];
+      for (int o = -1; o <= 1; o += 2) {
+        int j = i + o;
+        if (g.periodic[ax]) j = (j + nn) % nn;
+        else if (j < 0 || j >= nn) continue;
+        if (j == i) continue;
+        v += a[(size_t)(c + (long long)(j - i) * str[ax])];
+      }
+      b[(size_t)c] = v;
+    }
+    a.swap(b);
+  }
+  for (uint64_t v : a)
+    if (v >= (1u << 16)) return true;
+  return false;
+}
+
 extern "C" cpic_status cpic_set_particles(cpic_sim* s, int sid, size_t n, const int32_t* cell,
                                           const void* off, const void* vel, const uint32_t* ids,
                                           int on_device) {
@@ -661,6 +709,9 @@ extern "C" cpic_status cpic_set_particles(cpic_sim* s, int sid, size_t n, const 
         double v = rs == 8 ? ((const double*)off)[a * n + p] : ((const float*)off)[a * n + p];
         if (!(v >= 0.0 && v < 1.0)) return fail(s, CPIC_E_ARG, "offset outside [0, 1)");
       }
+    if (rs == 4 && crowded(s, n, cell))
+      return fail(s, CPIC_E_OVERFLOW, "a cell's 3^d neighbourhood holds 2^16 or more particles: its fixed-point "
+                                      "deposit could exceed 64 bits");
   }
   const int buf = S.cur;
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -679,9 +730,10 @@ extern "C" cpic_status cpic_set_particles(cpic_sim* s, int sid, size_t n, const 
       launch_iota(S.id[buf], (int)n, st);
   }
   launch_fill_u8(s->flags, 0, sizeof(int) * 8, st);
-  // new particles: their drift is unknown again
+  // new particles: their drift is unknown again, older records are not used
   launch_fill_u8(s->drift_dev + sid, 0, sizeof(unsigned), st);
-  if (s->drift_host) s->drift_host[sid] = 0u;
+  s->hist_from = s->step;
+  s->overflowed = false;
   launch_lin_to_key(lin_tmp, S.key[buf], (int)n, s->g, s->flags, st);
   if (on_device)
     for (int a = 0; a < d; ++a) launch_offsets_check(S.off[buf][a], (long long)n, rs == 8, s->flags + 1, st);
@@ -764,7 +816,8 @@ static void sort_species(cpic_sim* s, Species& S, bool counts_ready) {
   L.counts_ready = counts_ready ? 1 : 0;
   launch_tile_sort(L, s->stream);
   // the sort compacts away the particles that left: remember how many had
-  (void)hipMemcpyAsync(S.dead_mark, S.counters, sizeof(unsigned long long) * 2, hipMemcpyDeviceToDevice, s->stream);
+  (void)hipMemcpyAsync(S.dead_mark, S.counters, sizeof(unsigned long long) * NCOUNTERS, hipMemcpyDeviceToDevice,
+                       s->stream);
   S.cur = b;
 }
 
@@ -791,6 +844,7 @@ static void zero_deposits(cpic_sim* s, int mode) {
   if (mode == MODE_HALFSTEP) return;
   for (auto& S : s->sp) {
     launch_fill_u8(S.Q, 0, 8 * (size_t)s->g.ncells, s->stream);
+    launch_fill_u8(S.counters + 9, 0, sizeof(unsigned long long), s->stream);
     launch_fill_u8(S.fb_count, 0, sizeof(int) * 2, s->stream);
   }
 }
@@ -947,31 +1001,25 @@ static void solve_pass(cpic_sim* s, int cycles = -1) {
   launch_gauge(s->G, s->stream);
 }
 
-// Cycles to launch in a time step: one more than the last solve whose count
-// has reached the host (copied back asynchronously), at most the cap; the cap
-// until a count is known.  The count moves slowly from step to step; a solve
-// that would need more stops at the launched count, its relative residual in
-// the diagnostics, and the next step launches more.
-static int step_cycles(const cpic_sim* s) {
-  const int last = s->cycles_host ? *(volatile int*)s->cycles_host : -1;
-  if (last < 0 || !s->cycles_known) return s->grid.mg_max_cycles;
+// Cycles to launch in a time step: one more than the solve of step n - 2
+// needed (its record waited for, so the count is a fixed function of the
+// device state, whatever the host's timing), at most the cap; the cap while
+// no record is usable (last < 0).  A solve that would need more stops at the
+// launched count, its relative residual in the diagnostics, and later steps
+// launch more.
+static int step_cycles(const cpic_sim* s, int last) {
+  if (last < 0) return s->grid.mg_max_cycles;
   return std::min(s->grid.mg_max_cycles, last + 1);
-}
-
-static void record_cycles(cpic_sim* s) {
-  if (!s->cycles_host) return;
-  (void)hipMemcpyAsync(s->cycles_host, s->G.mg_flag + 1, sizeof(int), hipMemcpyDeviceToHost, s->stream);
-  s->cycles_known = true;
 }
 
 // Species to tile-sort at the end of the coming step.  A species sorts at
 // most every sort_every steps; it sorts then unless a bound on its particles'
-// drift since its last sort (steps x the largest increment seen so far,
-// copied back asynchronously) is below one cell, the slack of the tile
-// windows, and at least every 16 sort_every steps.  Injecting species sort
+// drift since its last sort (steps x the largest increment seen up to step
+// n - 2, from its record; none: unknown) is below one cell, the slack of the
+// tile windows, and at least every 16 sort_every steps.  Injecting species sort
 // every sort_every steps: their appended particles, processed meanwhile by one
 // extra work item through the global paths, join their tiles at a sort.
-static unsigned sort_mask(const cpic_sim* s) {
+static unsigned sort_mask(const cpic_sim* s, const unsigned* drift) {
   const int K = s->grid.sort_every;
   unsigned mask = 0;
   for (size_t k = 0; k < s->sp.size(); ++k) {
@@ -980,10 +1028,7 @@ static unsigned sort_mask(const cpic_sim* s) {
     bool sort = S.desc.inject != 0 && after >= K;
     if (!sort && after >= K) {
       float dmax = 0.0f;
-      if (s->drift_host) {
-        const unsigned bits = ((volatile unsigned*)s->drift_host)[k];
-        memcpy(&dmax, &bits, sizeof(dmax));
-      }
+      if (drift) memcpy(&dmax, &drift[k], sizeof(dmax));
       sort = !(dmax > 0.0f) || (float)after * dmax >= 1.0f || after >= 16 * K;
     }
     if (sort) mask |= 1u << k;
@@ -1026,7 +1071,7 @@ extern "C" cpic_status cpic_initialize(cpic_sim* s) {
   s->initialized = true;
   s->step = 0;
   s->phi_prev_valid = false;
-  s->cycles_known = false;
+  s->hist_from = 0;
   return check_async(s);
 }
 
@@ -1124,12 +1169,23 @@ extern "C" cpic_status cpic_step(cpic_sim* s, int nsteps) {
   if (!s || nsteps < 0) return CPIC_E_ARG;
   if (s->poisoned) return fail(s, CPIC_E_STATE, "simulation poisoned by an earlier device error");
   if (!s->initialized) return fail(s, CPIC_E_STATE, "cpic_initialize has not been called");
+  if (s->overflowed) return fail(s, CPIC_E_OVERFLOW, "an earlier fixed-point deposit wrapped");
   for (int k = 0; k < nsteps; ++k) {
     ensure_sorted(s);
     StepEvents* ev = s->timing ? next_events(s) : nullptr;
     const bool inj = any_injection(s);
-    const unsigned mask = sort_mask(s);
-    const int cycles = step_cycles(s);
+    // the record of step n - 2 (the one before the step still in flight)
+    const long long n = s->step;
+    int last = -1;
+    const unsigned* drift = nullptr;
+    if (n - 2 >= s->hist_from) {
+      const int slot = (int)((n - 2) % HIST);
+      HIPCHK(s, hipEventSynchronize(s->hist_ev[slot]));
+      last = s->cycles_host[slot];
+      drift = s->drift_host + 8 * slot;
+    }
+    const unsigned mask = sort_mask(s, drift);
+    const int cycles = step_cycles(s, last);
     // injection draws depend on the step number, a kernel argument: no graphs
     if (!(s->graphs && !inj && graph_step(s, mask, cycles, ev))) step_body(s, ev, inj, mask, cycles);
     for (size_t q = 0; q < s->sp.size(); ++q) {
@@ -1141,10 +1197,12 @@ extern "C" cpic_status cpic_step(cpic_sim* s, int nsteps) {
         ++S.since_sort;
       }
     }
-    record_cycles(s);
-    if (s->drift_host)
-      (void)hipMemcpyAsync(s->drift_host, s->drift_dev, sizeof(unsigned) * s->sp.size(), hipMemcpyDeviceToHost,
-                           s->stream);
+    // this step's record
+    const int slot = (int)(n % HIST);
+    HIPCHK(s, hipMemcpyAsync(s->cycles_host + slot, s->G.mg_flag + 1, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->drift_host + 8 * slot, s->drift_dev, sizeof(unsigned) * s->sp.size(),
+                             hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipEventRecord(s->hist_ev[slot], s->stream));
   }
   return check_async(s);
 }
@@ -1211,13 +1269,44 @@ extern "C" cpic_status cpic_set_field(cpic_sim* s, int which, int sid, const voi
   void* dst = field_ptr(s, which, sid);
   if (!dst || need == 0) return fail(s, CPIC_E_ARG, "unknown field / species");
   if (bytes != need) return fail(s, CPIC_E_ARG, "field size mismatch");
+  if (!on_device && which != CPIC_FIELD_Q) {
+    // floating-point fields from the host must be finite
+    const bool f32 = which == CPIC_FIELD_EV && real_size(s) == 4;
+    const size_t cnt = bytes / (f32 ? 4 : 8);
+    for (size_t i = 0; i < cnt; ++i)
+      if (!(f32 ? isfinite(((const float*)src)[i]) : isfinite(((const double*)src)[i])))
+        return fail(s, CPIC_E_NONFINITE, "field value is not finite");
+  }
   HIPCHK(s, hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
   // a potential set from outside starts a new time history
   if (which == CPIC_FIELD_PHI) s->phi_prev_valid = false;
-  if (which == CPIC_FIELD_PHI || which == CPIC_FIELD_CHARGE) s->cycles_known = false;
+  if (which == CPIC_FIELD_PHI || which == CPIC_FIELD_CHARGE) s->hist_from = s->step;
   return check_async(s);
+}
+
+// Non-finite values in the potential, the charge or the vertex field: the
+// count is added to flags[3] (asynchronous; read after a synchronisation).
+static void launch_field_checks(cpic_sim* s) {
+  hipStream_t st = s->stream;
+  launch_fill_u8(s->flags + 3, 0, sizeof(int), st);
+  const long long nc = s->g.ncells;
+  launch_nonfinite_check(field_ptr(s, CPIC_FIELD_PHI, 0), nc, 1, s->flags + 3, st);
+  launch_nonfinite_check(s->G.charge, nc, 1, s->flags + 3, st);
+  launch_nonfinite_check(s->G.Ev, (long long)ecomp(s) * s->g.nverts, s->grid.precision == CPIC_FP64 ? 1 : 0,
+                         s->flags + 3, st);
+}
+
+// The fixed-point deposit of a species wrapped when its exact total differs
+// from (particles deposited since Q was cleared) x 2^{d S1}: every particle
+// adds exactly 2^{d S1} over its target cells (walls fold, they do not drop),
+// so a cell whose uint64 sum passed 2^64 leaves the total short.
+static bool deposit_wrapped(const cpic_sim* s, uint64_t lo, uint64_t hi, unsigned long long deposited) {
+  const int sh = s->g.dim * s->S1;  // 48
+  const uint64_t elo = (uint64_t)deposited << sh;
+  const uint64_t ehi = sh ? (uint64_t)deposited >> (64 - sh) : 0;
+  return lo != elo || hi != ehi;
 }
 
 extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
@@ -1230,19 +1319,24 @@ extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
   double ke = 0.0;
   HIPCHK(s, hipMemcpyAsync(&ke, s->ke, sizeof(double), hipMemcpyDeviceToHost, st));
   launch_field_energy(s->G, s->tmp_scalar, st);
+  launch_field_checks(s);
   double we = 0.0, sc[2] = {0, 0}, wall[2] = {0, 0};
-  int fl[2] = {0, 0};
+  int fl[2] = {0, 0}, nonfinite = 0;
   HIPCHK(s, hipMemcpyAsync(&we, s->tmp_scalar, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(s, hipMemcpyAsync(sc, s->G.scalars, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
   if (s->G.floating) HIPCHK(s, hipMemcpyAsync(wall, s->G.scalars + 10, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
   HIPCHK(s, hipMemcpyAsync(fl, s->G.mg_flag, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
-  std::vector<unsigned long long> cnt(8 * s->sp.size()), mark(2 * s->sp.size());
-  std::vector<int> ns(s->sp.size());
-  std::vector<uint64_t> qs(2 * s->sp.size());
-  for (size_t k = 0; k < s->sp.size(); ++k) {
+  HIPCHK(s, hipMemcpyAsync(&nonfinite, s->flags + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+  const size_t ns_ = s->sp.size();
+  std::vector<unsigned long long> cnt(NCOUNTERS * ns_), mark(NCOUNTERS * ns_);
+  std::vector<int> ns(ns_);
+  std::vector<uint64_t> qs(2 * ns_);
+  for (size_t k = 0; k < ns_; ++k) {
     Species& S = s->sp[k];
-    HIPCHK(s, hipMemcpyAsync(&cnt[8 * k], S.counters, sizeof(unsigned long long) * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(s, hipMemcpyAsync(&mark[2 * k], S.dead_mark, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipMemcpyAsync(&cnt[NCOUNTERS * k], S.counters, sizeof(unsigned long long) * NCOUNTERS,
+                             hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipMemcpyAsync(&mark[NCOUNTERS * k], S.dead_mark, sizeof(unsigned long long) * NCOUNTERS,
+                             hipMemcpyDeviceToHost, st));
     HIPCHK(s, hipMemcpyAsync(&ns[k], S.d_n, sizeof(int), hipMemcpyDeviceToHost, st));
     if (s->grid.precision == CPIC_FP32) {
       launch_qsum((const uint64_t*)S.Q, s->g.ncells, s->qsum, st);
@@ -1258,26 +1352,43 @@ extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
   out->wall_charge = wall[1];
   out->mg_relres = sc[0] > 0 ? sqrt(sc[1] / sc[0]) : 0.0;
   out->mg_cycles = fl[1];
-  for (size_t k = 0; k < s->sp.size() && k < 8; ++k) {
-    // slots in use less the particles that left since the last sort
-    out->count[k] = ns[k] - (long long)((cnt[8 * k] + cnt[8 * k + 1]) - (mark[2 * k] + mark[2 * k + 1]));
-    out->absorbed[k] = (long long)cnt[8 * k + 0];
-    out->outflow[k] = (long long)cnt[8 * k + 1];
-    out->newton_fallback += (long long)cnt[8 * k + 2];
-    out->far_deposits += (long long)cnt[8 * k + 3];
-    out->newton_failed += (long long)cnt[8 * k + 4];
-    out->injected[k] = (long long)cnt[8 * k + 5];
+  bool wrapped = false;
+  for (size_t k = 0; k < ns_ && k < 8; ++k) {
+    const unsigned long long* c = &cnt[NCOUNTERS * k];
+    const unsigned long long* m = &mark[NCOUNTERS * k];
+    // slots in use less the particles that left since the last sort (absorbed,
+    // outflow, injected ones whose entry flight left at once)
+    out->count[k] = ns[k] - (long long)((c[0] + c[1] + c[8]) - (m[0] + m[1] + m[8]));
+    out->absorbed[k] = (long long)c[0];
+    out->outflow[k] = (long long)c[1];
+    out->newton_fallback += (long long)c[2];
+    out->far_deposits += (long long)c[3];
+    out->newton_failed += (long long)c[4];
+    out->injected[k] = (long long)c[5];
+    out->inject_lost[k] = (long long)c[8];
     out->sorts[k] = s->sp[k].sorts;
     out->qsum_lo[k] = qs[2 * k];
     out->qsum_hi[k] = qs[2 * k + 1];
+    if (s->grid.precision == CPIC_FP32 && deposit_wrapped(s, qs[2 * k], qs[2 * k + 1], c[9])) wrapped = true;
   }
-  return check_async(s);
+  cpic_status rc = check_async(s);
+  if (rc != CPIC_OK) return rc;
+  if (wrapped) {
+    s->overflowed = true;
+    return fail(s, CPIC_E_OVERFLOW, "a cell's fixed-point deposit passed 2^64 (too many particles in one place)");
+  }
+  if (nonfinite) return fail(s, CPIC_E_NONFINITE, "the potential, charge or vertex field holds non-finite values");
+  return CPIC_OK;
 }
 
 extern "C" cpic_status cpic_sync(cpic_sim* s) {
   if (!s) return CPIC_E_ARG;
   HIPCHK(s, hipStreamSynchronize(s->stream));
-  return check_async(s);
+  cpic_status rc = check_async(s);
+  if (rc != CPIC_OK) return rc;
+  // the checks of cpic_get_diag: deposit headroom, non-finite fields
+  cpic_diag d;
+  return cpic_get_diag(s, &d);
 }
 
 extern "C" cpic_status cpic_set_timing(cpic_sim* s, int enable) {
@@ -1331,6 +1442,8 @@ extern "C" void cpic_destroy(cpic_sim* s) {
   for (auto& gph : s->step_graphs) (void)hipGraphExecDestroy(gph.exec);
   if (s->cycles_host) (void)hipHostFree(s->cycles_host);
   if (s->drift_host) (void)hipHostFree(s->drift_host);
+  for (int i = 0; i < HIST; ++i)
+    if (s->hist_ev[i]) (void)hipEventDestroy(s->hist_ev[i]);
   for (auto& e : s->evs)
     for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e.e[i]);
   sim_free_all(s);

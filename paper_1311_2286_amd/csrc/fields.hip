@@ -2166,13 +2166,23 @@ void launch_qsum(const uint64_t* Q, long long n, uint64_t* out2, hipStream_t st)
   hipLaunchKernelGGL(qsum_final_kernel, dim3(1), dim3(1), 0, st, part, RED_BLOCKS, (unsigned long long*)out2);
 }
 
-__global__ void nonfinite_kernel(const double* x, long long n, int* bad) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && !isfinite(x[i])) atomicAdd(bad, 1);
+// Count of non-finite entries of x[0..n) (NaN or infinite) added to *bad.
+template <typename T>
+__global__ __launch_bounds__(256) void nonfinite_kernel(const T* __restrict__ x, long long n, int* bad) {
+  int cnt = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    cnt += isfinite(x[i]) ? 0 : 1;
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(bad, cnt);
 }
-void launch_nonfinite_check(const double* x, long long n, int* bad, hipStream_t st) {
-  unsigned blocks = (unsigned)((n + 255) / 256);
-  if (n > 0) hipLaunchKernelGGL(nonfinite_kernel, dim3(blocks), dim3(256), 0, st, x, n, bad);
+void launch_nonfinite_check(const void* x, long long n, int fp64, int* bad, hipStream_t st) {
+  if (n <= 0) return;
+  const long long want = (n + 255) / 256;
+  const unsigned blocks = (unsigned)(want < RED_BLOCKS ? want : RED_BLOCKS);
+  if (fp64)
+    hipLaunchKernelGGL(nonfinite_kernel<double>, dim3(blocks), dim3(256), 0, st, (const double*)x, n, bad);
+  else
+    hipLaunchKernelGGL(nonfinite_kernel<float>, dim3(blocks), dim3(256), 0, st, (const float*)x, n, bad);
 }
 
 }  // namespace cpic

@@ -223,6 +223,7 @@ void launch_efield(const GridCtx& G, hipStream_t st);
 void launch_rho(const GridCtx& G, double* rho, hipStream_t st);
 void launch_field_energy(const GridCtx& G, double* out, hipStream_t st);
 void launch_qsum(const uint64_t* Q, long long n, uint64_t* out2, hipStream_t st);
-void launch_nonfinite_check(const double* x, long long n, int* bad, hipStream_t st);
+// adds the number of non-finite entries of x (double when fp64, else float) to *bad
+void launch_nonfinite_check(const void* x, long long n, int fp64, int* bad, hipStream_t st);
 
 }  // namespace cpic

@@ -542,6 +542,9 @@ struct PartArgs {
   double* ke_part;
   int* tcount;  // when set (steps followed by a tile sort): live particles per new tile, dead last
   unsigned* drift;  // PUSH: running maximum of a particle's increment (cells, FP32 bits)
+  // [0] absorbed, [1] outflow, [2] FP64 fallbacks, [3] far deposits, [4] missed tolerance,
+  // [5] injected, [6] dropped for capacity, [7] next identifier, [8] injected particles whose
+  // entry flight left the domain, [9] particles deposited since Q was last cleared
   unsigned long long* counters;
   int* fb_queue;  // particles left to the FP64 fallback kernel
   int* fb_count;
@@ -863,7 +866,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
   constexpr int KD = D * D;
   __shared__ R kwin[KWIN ? FW::N * KD : 1];
   __shared__ double red_d[8];
-  __shared__ unsigned long long red_u[8][5];
+  __shared__ unsigned long long red_u[8][6];
   __shared__ int tbins[TB_N];  // new tiles of the particles (see count_new_tile)
 
   // maps that allow injection: TAIL_ITEMS more work items share the particles
@@ -936,7 +939,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
   __syncthreads();
 
   double ke = 0.0;
-  unsigned long long absorbed = 0, outflow = 0, far = 0;
+  unsigned long long absorbed = 0, outflow = 0, far = 0, ndep = 0;
   float dmax = 0.0f;  // largest increment of this thread's particles (cells)
 
 
@@ -1047,6 +1050,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
       if (D == 3) a.off2[p] = f[2];
     }
     deposit_particle<D, SHAPE, R, FIXED, QT>(g, origin, win, a.Q, idx, f, a.S1, far);
+    ++ndep;
   }
 
   if (deposit) {
@@ -1127,25 +1131,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
     if (lane == 0 && dmax > 0.0f) atomicMax(a.drift, __float_as_uint(dmax));
   }
   double kes = wave_sum(ke);
-  unsigned long long cs[5] = {wave_sum_u64(absorbed), wave_sum_u64(outflow), 0ull, wave_sum_u64(far),
-                              0ull};
+  unsigned long long cs[6] = {wave_sum_u64(absorbed), wave_sum_u64(outflow), 0ull, wave_sum_u64(far),
+                              0ull, deposit ? wave_sum_u64(ndep) : 0ull};
   if (lane == 0) {
     red_d[wv] = kes;
-    for (int i = 0; i < 5; ++i) red_u[wv][i] = cs[i];
+    for (int i = 0; i < 6; ++i) red_u[wv][i] = cs[i];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     const int nw = (blockDim.x + 63) / 64;
     double s = 0.0;
-    unsigned long long u[5] = {0, 0, 0, 0, 0};
+    unsigned long long u[6] = {0, 0, 0, 0, 0, 0};
     for (int w = 0; w < nw; ++w) {
       s += red_d[w];
-      for (int i = 0; i < 5; ++i) u[i] += red_u[w][i];
+      for (int i = 0; i < 6; ++i) u[i] += red_u[w][i];
     }
     // per-item slot, summed in a fixed order afterwards (deterministic energy)
     if (a.mode == MODE_PUSH) a.ke_part[item] = s;
     for (int i = 0; i < 5; ++i)
       if (u[i]) atomicAdd(&a.counters[i], u[i]);
+    if (u[5]) atomicAdd(&a.counters[9], u[5]);
   }
 }
 
@@ -1216,7 +1221,7 @@ template <int D, int MAP, typename R, bool FIXED>
 __global__ __launch_bounds__(256) void fallback_kernel(PartArgs<R> a, int shape) {
   const Geo& g = a.g;
   const int n = min(*a.fb_count, a.fb_cap);
-  unsigned long long done = 0, failed = 0, absorbed = 0, outflow = 0;
+  unsigned long long done = 0, failed = 0, absorbed = 0, outflow = 0, ndep = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int p = a.fb_queue[i];
     const int key = a.key[p];
@@ -1264,12 +1269,14 @@ __global__ __launch_bounds__(256) void fallback_kernel(PartArgs<R> a, int shape)
     a.off1[p] = fr[1];
     if (D == 3) a.off2[p] = fr[2];
     deposit_global<D, R, FIXED>(g, shape, a.S1, idx, fr, a.Q);
+    ++ndep;
   }
   if (done) {
     atomicAdd(&a.counters[2], done);
     if (failed) atomicAdd(&a.counters[4], failed);
     if (absorbed) atomicAdd(&a.counters[0], absorbed);
     if (outflow) atomicAdd(&a.counters[1], outflow);
+    if (ndep) atomicAdd(&a.counters[9], ndep);
   }
 }
 
@@ -1300,7 +1307,8 @@ struct InjectArgs {
   double lam, vth, dt, kappa;
   double s_drift;  // inward drift of the injected Maxwellian in thermal speeds (0: at rest)
   uint32_t k0, k1, step, species;
-  unsigned long long* counters;  // [5] injected, [6] dropped for capacity, [7] next identifier
+  unsigned long long* counters;  // [5] injected, [6] dropped for capacity, [7] next identifier,
+                                 // [8] entry flight left the domain, [9] deposited
   int* count_out;
   int* tcount;  // when set: the injected particles' tiles are counted for the next sort
 };
@@ -1416,7 +1424,10 @@ __global__ __launch_bounds__(256) void inject_kernel(InjectArgs<R> a) {
   // identifiers follow the draw index k, so they do not depend on scheduling
   if (a.id) a.id[slot] = (uint32_t)(a.counters[7] + (unsigned long long)k);
   if (dead) {
+    // its slot stays in use until the next sort: counted, so the live count
+    // (slots less the departures since the last sort) leaves it out
     a.key[slot] = -2;
+    atomicAdd(&a.counters[8], 1ull);
     if (a.tcount) atomicAdd(&a.tcount[g.ntiles], 1);
     return;
   }
@@ -1429,6 +1440,7 @@ __global__ __launch_bounds__(256) void inject_kernel(InjectArgs<R> a) {
   for (int ax = 0; ax < D; ++ax) a.off[ax][slot] = fo[ax];
   for (int c = 0; c < 3; ++c) a.vel[c][slot] = (R)v[c];
   atomicAdd(&a.counters[5], 1ull);
+  atomicAdd(&a.counters[9], 1ull);
   deposit_global<D, R, FIXED>(g, a.shape, a.S1, idx, fo, a.Q);
 }
 

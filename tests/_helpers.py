@@ -77,3 +77,25 @@ def periodic_diff(case, a, b):
             n = case.n[ax]
             d[:, ax] -= np.round(d[:, ax] / n) * n
     return d
+
+
+def check_push(case, precision, tag, got_cell, got_off, got_vel, cell, off, vel, vel0, acc_dt,
+               pos_tol=1e-5, vel_tol=1e-5):
+    """One push from identical states, GPU against oracle, particle by
+    particle (the same particles, in the same order, on both sides).
+    Positions: largest |difference| in cells <= pos_tol (FP32) or 1e-12
+    (FP64).  Velocities: |dv| <= vel_tol (|v0| + |q/m E dt|) per particle
+    (FP32), 1e-12 (FP64), vector norms.  Returns the two measured maxima."""
+    pg = logical_cells(case, got_cell, got_off.astype(np.float64))
+    po = logical_cells(case, cell, off)
+    dpos = float(np.abs(periodic_diff(case, pg, po)).max()) if cell.size else 0.0
+    dvv = got_vel.T.astype(np.float64) - vel
+    if case.dim == 2 and not any(case.B):
+        dvv[:, 2] = 0.0  # v_z is not advanced without a magnetic field in 2D
+    scale = np.linalg.norm(vel0, axis=1) + np.linalg.norm(acc_dt, axis=1)
+    rv = float((np.linalg.norm(dvv, axis=1) / scale).max()) if cell.size else 0.0
+    print("[push %s p%d] max |dxi| %.2e cell, max |dv| / (|v| + |a dt|) %.2e" % (tag, precision, dpos, rv))
+    pt, vt = (pos_tol, vel_tol) if precision == 0 else (1e-12, 1e-12)
+    assert dpos <= pt, (tag, dpos)
+    assert rv <= vt, (tag, rv)
+    return dpos, rv

@@ -17,9 +17,11 @@ it computes one by one, else through properties:
   - vertex field of a synthetic potential within 1e-6 of its maximum;
   - one push in a synthetic vertex field: 32,768 particles per species, drawn
     at random, against the oracle's push of the same particles (the same ones
-    leave through the walls; positions 2e-5 cell, velocities
-    2e-5 (|v| + |q/m E dt|)), and on the periodic boxes the exact total of
-    the deposit after the push (N 2^{d S1})."""
+    leave through the walls; positions 1e-5 cell, velocities
+    1e-5 (|v| + |q/m E dt|) per particle), and the deposit that push made,
+    over every cell bit-exact against the oracle's deposit of all the live
+    particles at their new positions (read back from the GPU); on the
+    periodic boxes also the exact total (N 2^{d S1})."""
 import time
 
 import numpy as np
@@ -27,7 +29,7 @@ import pytest
 
 import oracle as O
 from paper_1311_2286_amd import workloads as W
-from _helpers import gpu_sim, oracle_objects, logical_cells, periodic_diff
+from _helpers import check_push, gpu_sim, oracle_objects, logical_cells, periodic_diff
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -138,20 +140,24 @@ def test_full_size(name):
         gc = got["cell"][at]
         assert np.array_equal(gc >= 0, cell >= 0)
         live = cell >= 0
-        pg = logical_cells(case, gc[live], got["off"][:, at][:, live].astype(np.float64))
-        po = logical_cells(case, cell[live], off[live])
-        dpos = np.abs(periodic_diff(case, pg, po))
-        vg = got["vel"][:, at].T.astype(np.float64)
         Eo = O.gather(g, E64, o["cell"], o["off"])
-        scale = np.abs(o["vel"]) + np.abs(s.q / s.m * Eo * case.dt)
-        dv = np.abs(vg - vel)
-        if d_ == 2 and not any(case.B):
-            dv[:, 2] = 0.0  # v_z is not advanced without a magnetic field in 2D
-        assert dpos.max() < 2e-5, dpos.max()
-        assert np.all(dv <= 2e-5 * (scale + 1e-3)), (dv / (scale + 1e-3)).max()
-        del got, where
+        dpos, _ = check_push(case, 0, "%s sid %d" % (name, sid), gc[live], got["off"][:, at][:, live],
+                             got["vel"][:, at][:, live], cell[live], off[live], vel[live], o["vel"][live],
+                             (s.q / s.m * case.dt) * Eo[live])
         say(t0, "push of species %d: %d sampled particles (%d leave), max |dxi| %.2e cell"
-            % (sid, pick.size, int((~live).sum()), dpos.max()))
+            % (sid, pick.size, int((~live).sum()), dpos))
+        # the deposit the timed kernel made: every cell, bit-exact against the
+        # oracle's deposit of the live particles at their new positions
+        gl = got["cell"] >= 0
+        gcell = np.ascontiguousarray(got["cell"][gl])
+        goff = np.zeros((gcell.size, 3))
+        goff[:, :d_] = got["off"][:, gl].T  # exact widening of the FP32 offsets
+        del got, where
+        Qo = O.deposit_fixed(g, 2, S1, gcell, goff)
+        assert gcell.size == dg.count[sid]
+        assert np.array_equal(sim.get_field(C().FIELD_Q, sid), Qo), sid
+        del gcell, goff, Qo
+        say(t0, "deposit of the push, species %d: bit-exact over all %d cells" % (sid, case.ncells))
     if all(bc == W.PERIODIC for bc in case.bc_lo[:d_]):
         for sid in range(len(case.species)):
             assert C().qsum(dg, sid) == parts[sid]["cell"].size << (d_ * S1)

@@ -4,11 +4,17 @@ the same seeded inputs.
 Bars (written in each test):
   - deposit, FP32 path: bit-exact (integer weights, order-free sums);
   - deposit, FP64 path: 1e-12 of the largest cell value (FP64 atomics reorder);
-  - charge: 1e-14 relative; potential: 1e-8 of max |phi| (both solves at
-    residual 1e-12 / 1e-13);
+  - charge: 1e-14 relative; potential: 1e-9 of max |phi| (both solves at
+    residual 1e-12 / 1e-13; measured 2.4e-13);
   - vertex field: 1e-6 of max |E| (FP32 storage), 1e-10 (FP64);
-  - one push from identical states, FP32: positions 2e-5 cell, velocities
-    2e-5 (|v| + |q/m E dt|); FP64: 1e-9 cell, 1e-11.
+  - one push from identical states, FP32: positions 1e-5 cell (measured
+    4.2e-6; 2e-5 on the strongly distorted grid, J_min = 0.057, where the
+    map's FP32 residual is amplified by 1/J: measured 1.4e-5), velocities
+    |dv| <= 1e-5 (|v| + |q/m E dt|) per particle (vector norms; measured
+    3.2e-6 with the Boris rotation); FP64: 1e-12 cell and 1e-12;
+  - three full steps from the same initial state (the oracle carries FP64
+    positions from then on): potential 1e-6 relative on the FP32 path
+    (measured 4e-8), 1e-10 on FP64 (3.5e-13); kinetic energy 1e-7 / 1e-12.
 Grids are ragged (not multiples of the 16x16 / 8x8x8 tiles) and span several
 tiles; tiny grids exercise the deposit window wrapping onto itself."""
 import math
@@ -117,7 +123,8 @@ def test_charge_solve_and_field(name, precision):
     assert np.max(np.abs(ch - osim.charge)) <= 1e-14 * np.max(np.abs(osim.charge)) + 1e-300
     osim.solve()
     phi = sim.get_field(C().FIELD_PHI)
-    assert np.max(np.abs(phi - osim.phi)) <= 1e-8 * np.max(np.abs(osim.phi))
+    print("[parity] %s p%d phi rel %.2e" % (name, precision, np.max(np.abs(phi - osim.phi)) / np.max(np.abs(osim.phi))))
+    assert np.max(np.abs(phi - osim.phi)) <= 1e-9 * np.max(np.abs(osim.phi))
     d = sim.diag()
     assert d.mg_relres <= 1e-12 and d.mg_cycles > 0
     Ev = sim.get_field(C().FIELD_EV)[:, : case.dim].astype(np.float64)
@@ -152,7 +159,7 @@ def test_probe_vacuum_solution():
     sim.close()
 
 
-def _push_compare(case, precision, shape=2, expect_fallback=False):
+def _push_compare(case, precision, shape=2, expect_fallback=False, pos_tol=1e-5):
     sim, parts = gpu_sim(case, precision=precision, shape=shape)
     nv = sim.field_bytes(C().FIELD_EV) // (4 if precision == 0 else 8) // (4 if case.dim == 3 else 2)
     E = W.synthetic_ev(case, nv, dtype=np.float64 if precision else np.float32)
@@ -175,16 +182,19 @@ def _push_compare(case, precision, shape=2, expect_fallback=False):
         dpos = np.abs(periodic_diff(case, pg, po))
         vg = got["vel"].T.astype(np.float64)
         Eo = O.gather(g, E64, o["cell"], o["off"])
-        scale = np.abs(o["vel"]) + np.abs(s.q / s.m * Eo * case.dt)
-        dv = np.abs(vg - vel)
+        dvv = vg - vel
         if case.dim == 2 and not any(case.B):
-            dv[:, 2] = 0.0  # v_z is not advanced without a magnetic field in 2D
+            dvv[:, 2] = 0.0  # v_z is not advanced without a magnetic field in 2D
+        # per particle: |dv| against |v| + |q/m E dt| (vector norms)
+        scale = np.linalg.norm(o["vel"], axis=1) + np.linalg.norm(s.q / s.m * Eo * case.dt, axis=1)
+        rv = np.linalg.norm(dvv, axis=1) / scale
+        print("[parity] push %s p%d sid %d dpos %.2e dv %.2e" % (case.name, precision, sid, dpos.max(), rv.max()))
         if precision == 0:
-            assert dpos.max() < 2e-5, dpos.max()
-            assert np.all(dv <= 2e-5 * (scale + 1e-3)), (dv / (scale + 1e-3)).max()
+            assert dpos.max() <= pos_tol, dpos.max()
+            assert rv.max() <= 1e-5, rv.max()
         else:
-            assert dpos.max() < 1e-9, dpos.max()
-            assert np.all(dv <= 1e-11 * (scale + 1e-3)), (dv / (scale + 1e-3)).max()
+            assert dpos.max() <= 1e-12, dpos.max()
+            assert rv.max() <= 1e-12, rv.max()
     d = sim.diag()
     assert d.newton_failed == 0
     if expect_fallback is not None:
@@ -207,7 +217,7 @@ def test_push_strong_distortion_and_fast_particles():
     # eps = 0.15 (J_min = 0.057), thermal speed 8: particles cross several
     # cells per step and the FP32 Newton must still hold its tolerance.
     case = W.small_case(dim=2, n=(40, 24), eps=0.15, ppc=6.0, L=(1.0, 1.0), vth_e=0.2)
-    _push_compare(case, 0, expect_fallback=True)
+    _push_compare(case, 0, expect_fallback=True, pos_tol=2e-5)
     _push_compare(case, 1, expect_fallback=None)
 
 
@@ -228,16 +238,18 @@ def test_initialize_and_three_steps(precision):
         osim.step()
         phi = sim.get_field(C().FIELD_PHI)
         rel = np.max(np.abs(phi - osim.phi)) / np.max(np.abs(osim.phi))
-        assert rel < (1e-4 if precision == 0 else 1e-8), (k, rel)
+        assert rel < (1e-6 if precision == 0 else 1e-10), (k, rel)
         for sid in range(len(case.species)):
             got = by_id(sim.get_particles(sid))
             o = osim.sp[sid]
             dpos = np.abs(periodic_diff(case, logical_cells(case, got["cell"], got["off"].astype(float)),
                                         logical_cells(case, o["cell"], o["off"])))
-            assert dpos.max() < (1e-4 if precision == 0 else 1e-9), (k, dpos.max())
+            print("[parity] 3 steps p%d k %d sid %d dpos %.2e" % (precision, k, sid, dpos.max()))
+            assert dpos.max() < (1e-5 if precision == 0 else 1e-9), (k, dpos.max())
         d = sim.diag()
         rel_ke = abs(d.kinetic - osim.ke) / abs(osim.ke)
-        assert rel_ke < (1e-5 if precision == 0 else 1e-10), rel_ke
+        print("[parity] 3 steps p%d k %d phi %.2e ke %.2e" % (precision, k, rel, rel_ke))
+        assert rel_ke < (1e-7 if precision == 0 else 1e-12), rel_ke
     sim.close()
 
 

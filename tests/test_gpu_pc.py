@@ -2,10 +2,12 @@
 CPIC_MOVER_PC; Sec. "Particle mover", Eqs. step2-step4) against the oracle's
 push_pc, through the C ABI.
 
-Bars: one push from identical states, FP32: positions 2e-5 cell, velocities
-2e-5 (|v| + |q/m E dt|); FP64: 1e-9 cell, 1e-11 -- as for the Newton mover.
-Three full steps, FP64, 2D sinusoidal map: potential within 1e-8 of its
-maximum and every particle within 1e-9 cell of the oracle run with the same
+Bars: one push from identical states, FP32: positions 1e-5 cell (2e-5 on the
+strongly distorted grid, J_min = 0.057), velocities
+|dv| <= 1e-5 (|v| + |q/m E dt|) per particle; FP64: 1e-12 cell and 1e-12 --
+as for the Newton mover.
+Three full steps, FP64, 2D sinusoidal map: potential within 1e-10 of its
+maximum and every particle within 1e-10 cell of the oracle run with the same
 mover.  Cases: 2D and 3D sinusoidal maps (ragged, several tiles), the
 identity map, a magnetised 3D box, the polar-log annulus with walls,
 particles fast enough to leave the interpolation cell in the predictor, and
@@ -17,7 +19,7 @@ import pytest
 
 import oracle as O
 from paper_1311_2286_amd import workloads as W
-from _helpers import gpu_sim, oracle_objects, oracle_species, by_id, logical_cells, periodic_diff
+from _helpers import check_push, gpu_sim, oracle_objects, oracle_species, by_id, logical_cells, periodic_diff
 
 pytestmark = pytest.mark.gpu
 
@@ -86,21 +88,12 @@ def test_push_one_step(name, precision):
         live.append(int(alive.sum()))
         gl = got["cell"] >= 0
         assert np.array_equal(gl, alive)
-        pg = logical_cells(case, got["cell"][gl], got["off"][:, gl].astype(np.float64))
-        po = logical_cells(case, cell[alive], off[alive])
-        dpos = np.abs(periodic_diff(case, pg, po))
-        vg = got["vel"].T.astype(np.float64)
         Eo = O.gather(g, E64, o["cell"], o["off"])
-        scale = np.abs(o["vel"]) + np.abs(s.q / s.m * Eo * case.dt)
-        dv = np.abs(vg - vel)
-        if case.dim == 2 and not any(case.B):
-            dv[:, 2] = 0.0  # v_z is not advanced without a magnetic field in 2D
-        if precision == 0:
-            assert dpos.max() < 2e-5, dpos.max()
-            assert np.all(dv <= 2e-5 * (scale + 1e-3)), (dv / (scale + 1e-3)).max()
-        else:
-            assert dpos.max() < 1e-9, dpos.max()
-            assert np.all(dv <= 1e-11 * (scale + 1e-3)), (dv / (scale + 1e-3)).max()
+        # the strongly distorted grid (J_min = 0.057): its FP32 metric is
+        # amplified by 1/J, as for the Newton mover (measured 1.4e-5 cell)
+        check_push(case, precision, "pc %s sid %d" % (name, sid), got["cell"][gl], got["off"][:, gl],
+                   got["vel"][:, gl], cell[alive], off[alive], vel[alive], o["vel"][alive],
+                   (s.q / s.m * case.dt) * Eo[alive], pos_tol=2e-5 if name == "2d_fast" else 1e-5)
     assert d.newton_fallback == 0 and d.newton_failed == 0
     if precision == 0:
         S1 = 24 if case.dim == 2 else 16
@@ -122,12 +115,16 @@ def test_three_steps_fp64_match_the_oracle(name):
         sim.step(1)
         osim.step()
         phi = sim.get_field(C().FIELD_PHI)
-        assert np.max(np.abs(phi - osim.phi)) < 1e-8 * np.max(np.abs(osim.phi)), k
+        rel = np.max(np.abs(phi - osim.phi)) / np.max(np.abs(osim.phi))
+        print("[pc 3 steps %s] k %d phi %.2e" % (name, k, rel))
+        assert rel < 1e-10, k
     for sid in range(len(case.species)):
         got = by_id(sim.get_particles(sid))
         o = osim.sp[sid]
         order = np.argsort(parts[sid]["id"])
         pg = logical_cells(case, got["cell"], got["off"].astype(np.float64))
         po = logical_cells(case, o["cell"][order], o["off"][order])
-        assert np.abs(periodic_diff(case, pg, po)).max() < 1e-9
+        dmax = np.abs(periodic_diff(case, pg, po)).max()
+        print("[pc 3 steps %s] sid %d dpos %.2e" % (name, sid, dmax))
+        assert dmax < 1e-10
     sim.close()
