@@ -418,7 +418,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   G.phi_prev = (double*)A(cb);
   s->ke = (double*)A(sizeof(double) * 2);
   s->flags = (int*)A(sizeof(int) * 8);
-  s->qsum = (uint64_t*)A(sizeof(uint64_t) * (2 + 2 * 256));
+  s->qsum = (uint64_t*)A(sizeof(uint64_t) * QSUM_WORDS * MAX_SPECIES);
   s->tmp_scalar = (double*)A(sizeof(double) * 4);
   if (!ok) {
     sim_free_all(s);
@@ -1286,16 +1286,24 @@ extern "C" cpic_status cpic_set_field(cpic_sim* s, int which, int sid, const voi
   return check_async(s);
 }
 
-// Non-finite values in the potential, the charge or the vertex field: the
-// count is added to flags[3] (asynchronous; read after a synchronisation).
-static void launch_field_checks(cpic_sim* s) {
+// Device buffers the diagnostics' reductions work in.
+struct DiagScratch {
+  double* partials;  // REDUCE_BLOCKS doubles: per-workgroup sums of the field energy
+  double* we;        // the field-energy sum
+  int* nonfinite;    // count of non-finite field values (cleared by a kernel first)
+  uint64_t* qsum;    // MAX_SPECIES x QSUM_WORDS words: exact charge totals and their partials
+};
+
+// Non-finite values in the potential, the charge or the vertex field, counted
+// into *bad (asynchronous; read after a synchronisation).
+static void launch_field_checks(cpic_sim* s, int* bad) {
   hipStream_t st = s->stream;
-  launch_fill_u8(s->flags + 3, 0, sizeof(int), st);
+  launch_fill_u8(bad, 0, sizeof(int), st);
   const long long nc = s->g.ncells;
-  launch_nonfinite_check(field_ptr(s, CPIC_FIELD_PHI, 0), nc, 1, s->flags + 3, st);
-  launch_nonfinite_check(s->G.charge, nc, 1, s->flags + 3, st);
-  launch_nonfinite_check(s->G.Ev, (long long)ecomp(s) * s->g.nverts, s->grid.precision == CPIC_FP64 ? 1 : 0,
-                         s->flags + 3, st);
+  launch_nonfinite_check(field_ptr(s, CPIC_FIELD_PHI, 0), nc, 1, bad, st);
+  launch_nonfinite_check(s->G.charge, nc, 1, bad, st);
+  launch_nonfinite_check(s->G.Ev, (long long)ecomp(s) * s->g.nverts, s->grid.precision == CPIC_FP64 ? 1 : 0, bad,
+                         st);
 }
 
 // The fixed-point deposit of a species wrapped when its exact total differs
@@ -1309,40 +1317,39 @@ static bool deposit_wrapped(const cpic_sim* s, uint64_t lo, uint64_t hi, unsigne
   return lo != elo || hi != ehi;
 }
 
-extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
-  if (!s || !out) return CPIC_E_ARG;
+// Diagnostics and state checks with the reductions in `sc`; host staging in
+// fixed-size arrays, one synchronisation.
+static cpic_status diag_impl(cpic_sim* s, cpic_diag* out, const DiagScratch& sc) {
   memset(out, 0, sizeof(*out));
   hipStream_t st = s->stream;
   out->step = s->step;
   out->nspecies = (int)s->sp.size();
   out->step_graphs = (int)s->step_graphs.size();
-  double ke = 0.0;
-  HIPCHK(s, hipMemcpyAsync(&ke, s->ke, sizeof(double), hipMemcpyDeviceToHost, st));
-  launch_field_energy(s->G, s->tmp_scalar, st);
-  launch_field_checks(s);
-  double we = 0.0, sc[2] = {0, 0}, wall[2] = {0, 0};
+  const int nsp = (int)s->sp.size();
+  double ke = 0.0, we = 0.0, sc2[2] = {0, 0}, wall[2] = {0, 0};
   int fl[2] = {0, 0}, nonfinite = 0;
-  HIPCHK(s, hipMemcpyAsync(&we, s->tmp_scalar, sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(s, hipMemcpyAsync(sc, s->G.scalars, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+  unsigned long long cnt[MAX_SPECIES][NCOUNTERS], mark[MAX_SPECIES][NCOUNTERS];
+  int ns[MAX_SPECIES] = {0};
+  uint64_t qs[MAX_SPECIES][2] = {{0, 0}};
+  HIPCHK(s, hipMemcpyAsync(&ke, s->ke, sizeof(double), hipMemcpyDeviceToHost, st));
+  launch_field_energy(s->G, sc.partials, sc.we, st);
+  launch_field_checks(s, sc.nonfinite);
+  const bool fixed = s->grid.precision == CPIC_FP32;
+  for (int k = 0; k < nsp; ++k)
+    if (fixed) launch_qsum((const uint64_t*)s->sp[k].Q, s->g.ncells, sc.qsum + (size_t)k * QSUM_WORDS, st);
+  HIPCHK(s, hipMemcpyAsync(&we, sc.we, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipMemcpyAsync(sc2, s->G.scalars, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
   if (s->G.floating) HIPCHK(s, hipMemcpyAsync(wall, s->G.scalars + 10, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
   HIPCHK(s, hipMemcpyAsync(fl, s->G.mg_flag, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
-  HIPCHK(s, hipMemcpyAsync(&nonfinite, s->flags + 3, sizeof(int), hipMemcpyDeviceToHost, st));
-  const size_t ns_ = s->sp.size();
-  std::vector<unsigned long long> cnt(NCOUNTERS * ns_), mark(NCOUNTERS * ns_);
-  std::vector<int> ns(ns_);
-  std::vector<uint64_t> qs(2 * ns_);
-  for (size_t k = 0; k < ns_; ++k) {
+  HIPCHK(s, hipMemcpyAsync(&nonfinite, sc.nonfinite, sizeof(int), hipMemcpyDeviceToHost, st));
+  for (int k = 0; k < nsp; ++k) {
     Species& S = s->sp[k];
-    HIPCHK(s, hipMemcpyAsync(&cnt[NCOUNTERS * k], S.counters, sizeof(unsigned long long) * NCOUNTERS,
-                             hipMemcpyDeviceToHost, st));
-    HIPCHK(s, hipMemcpyAsync(&mark[NCOUNTERS * k], S.dead_mark, sizeof(unsigned long long) * NCOUNTERS,
-                             hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipMemcpyAsync(cnt[k], S.counters, sizeof(unsigned long long) * NCOUNTERS, hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipMemcpyAsync(mark[k], S.dead_mark, sizeof(unsigned long long) * NCOUNTERS, hipMemcpyDeviceToHost, st));
     HIPCHK(s, hipMemcpyAsync(&ns[k], S.d_n, sizeof(int), hipMemcpyDeviceToHost, st));
-    if (s->grid.precision == CPIC_FP32) {
-      launch_qsum((const uint64_t*)S.Q, s->g.ncells, s->qsum, st);
-      HIPCHK(s, hipMemcpyAsync(&qs[2 * k], s->qsum, sizeof(uint64_t) * 2, hipMemcpyDeviceToHost, st));
-      HIPCHK(s, hipStreamSynchronize(st));
-    }
+    if (fixed)
+      HIPCHK(s, hipMemcpyAsync(qs[k], sc.qsum + (size_t)k * QSUM_WORDS, sizeof(uint64_t) * 2, hipMemcpyDeviceToHost,
+                               st));
   }
   HIPCHK(s, hipStreamSynchronize(st));
   out->kinetic = ke;
@@ -1350,12 +1357,12 @@ extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
   out->field_energy = 0.5 * we + 0.5 * wall[1] * wall[0];
   out->phi_wall = wall[0];
   out->wall_charge = wall[1];
-  out->mg_relres = sc[0] > 0 ? sqrt(sc[1] / sc[0]) : 0.0;
+  out->mg_relres = sc2[0] > 0 ? sqrt(sc2[1] / sc2[0]) : 0.0;
   out->mg_cycles = fl[1];
   bool wrapped = false;
-  for (size_t k = 0; k < ns_ && k < 8; ++k) {
-    const unsigned long long* c = &cnt[NCOUNTERS * k];
-    const unsigned long long* m = &mark[NCOUNTERS * k];
+  for (int k = 0; k < nsp; ++k) {
+    const unsigned long long* c = cnt[k];
+    const unsigned long long* m = mark[k];
     // slots in use less the particles that left since the last sort (absorbed,
     // outflow, injected ones whose entry flight left at once)
     out->count[k] = ns[k] - (long long)((c[0] + c[1] + c[8]) - (m[0] + m[1] + m[8]));
@@ -1367,9 +1374,9 @@ extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
     out->injected[k] = (long long)c[5];
     out->inject_lost[k] = (long long)c[8];
     out->sorts[k] = s->sp[k].sorts;
-    out->qsum_lo[k] = qs[2 * k];
-    out->qsum_hi[k] = qs[2 * k + 1];
-    if (s->grid.precision == CPIC_FP32 && deposit_wrapped(s, qs[2 * k], qs[2 * k + 1], c[9])) wrapped = true;
+    out->qsum_lo[k] = qs[k][0];
+    out->qsum_hi[k] = qs[k][1];
+    if (fixed && deposit_wrapped(s, qs[k][0], qs[k][1], c[9])) wrapped = true;
   }
   cpic_status rc = check_async(s);
   if (rc != CPIC_OK) return rc;
@@ -1379,6 +1386,12 @@ extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
   }
   if (nonfinite) return fail(s, CPIC_E_NONFINITE, "the potential, charge or vertex field holds non-finite values");
   return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
+  if (!s || !out) return CPIC_E_ARG;
+  const DiagScratch sc = {s->G.partials, s->tmp_scalar, s->flags + 3, s->qsum};
+  return diag_impl(s, out, sc);
 }
 
 extern "C" cpic_status cpic_sync(cpic_sim* s) {

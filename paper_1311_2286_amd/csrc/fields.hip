@@ -434,7 +434,7 @@ void launch_charge(const GridCtx& G, const ChargeSpecies& cs, double bg_charge, 
 // ----------------------------------------------------------------------------
 // deterministic reductions: fixed grid of 256 blocks, fixed-order tree
 // ----------------------------------------------------------------------------
-constexpr int RED_BLOCKS = 256;
+constexpr int RED_BLOCKS = REDUCE_BLOCKS;
 
 __device__ inline double block_sum(double v) {
   __shared__ double sh[16];
@@ -2117,8 +2117,8 @@ void launch_rho(const GridCtx& G, double* rho, hipStream_t st) {
   hipLaunchKernelGGL(rho_kernel, dim3(blocks), dim3(256), 0, st, G.g.ncells, G.lev[0].dV, G.charge, G.Jc, rho);
 }
 
-void launch_field_energy(const GridCtx& G, double* out, hipStream_t st) {
-  reduce(G.charge, G.floating ? G.phi_full : G.lev[0].phi, G.g.ncells, 0, G.partials, out, st);
+void launch_field_energy(const GridCtx& G, double* partials, double* out, hipStream_t st) {
+  reduce(G.charge, G.floating ? G.phi_full : G.lev[0].phi, G.g.ncells, 0, partials, out, st);
   // W_E = 1/2 sum charge phi: the factor is applied by the host
 }
 

@@ -221,7 +221,13 @@ void launch_vertex_metric(const GridCtx& G, hipStream_t st);
 void launch_map_table(const Geo& g, double* jtab, hipStream_t st);
 void launch_efield(const GridCtx& G, hipStream_t st);
 void launch_rho(const GridCtx& G, double* rho, hipStream_t st);
-void launch_field_energy(const GridCtx& G, double* out, hipStream_t st);
+// deterministic reductions use a fixed grid of REDUCE_BLOCKS workgroups
+constexpr int REDUCE_BLOCKS = 256;
+// sum_c charge_c phi_c into *out; partials: REDUCE_BLOCKS doubles of scratch
+void launch_field_energy(const GridCtx& G, double* partials, double* out, hipStream_t st);
+// exact 128-bit sum of Q[0..n) into out2[0] (low word), out2[1] (high word);
+// out2 holds QSUM_WORDS words (the per-workgroup partials follow the result)
+constexpr int QSUM_WORDS = 2 + 2 * REDUCE_BLOCKS;
 void launch_qsum(const uint64_t* Q, long long n, uint64_t* out2, hipStream_t st);
 // adds the number of non-finite entries of x (double when fp64, else float) to *bad
 void launch_nonfinite_check(const void* x, long long n, int fp64, int* bad, hipStream_t st);
