@@ -324,6 +324,19 @@ size_t cpic_field_bytes(const cpic_sim* sim, int which);
    cpic_set_particles loads new particles.  Neither changes the simulation. */
 cpic_status cpic_get_diag(cpic_sim* sim, cpic_diag* out);
 
+/* cpic_get_diag for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid allocation):
+   the same diagnostics and checks, bit for bit, computed in a fixed scratch
+   array of 35,200 bytes that the library keeps per device for the life of the
+   process (field-energy partial sums, the non-finite count, and the 128-bit
+   charge sums of up to CPIC_MAX_SPECIES species; a simulation with more
+   species gets CPIC_E_BUDGET).  Allocates nothing, on the device or the host,
+   on success.  Every call on one device shares that array: calls that overlap
+   on one device (several host threads, or streams whose calls are in flight
+   together) race and must be serialised by the caller.  CPIC_E_HIP when the
+   array's address cannot be found on the simulation's device. */
+cpic_status cpic_get_diag_noalloc(cpic_sim* sim, cpic_diag* out);
+
 /* Wait for all work on the simulation's stream, then run the checks of
    cpic_get_diag (CPIC_E_NONFINITE, CPIC_E_OVERFLOW). */
 cpic_status cpic_sync(cpic_sim* sim);

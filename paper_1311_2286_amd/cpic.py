@@ -32,7 +32,7 @@ EXPORTED = ["cpic_create", "cpic_add_species", "cpic_set_particles", "cpic_get_p
             "cpic_field_bytes", "cpic_get_diag", "cpic_sync", "cpic_set_timing", "cpic_get_timing",
             "cpic_status_str", "cpic_last_error", "cpic_destroy", "cpic_set_graphs", "cpic_server_create",
             "cpic_server_submit", "cpic_server_pump", "cpic_server_poll", "cpic_server_get_stats",
-            "cpic_server_destroy"]
+            "cpic_server_destroy", "cpic_get_diag_noalloc"]
 MAX_SPECIES = 8
 E_ARG, E_MAP, E_NOMEM, E_BUDGET, E_HIP, E_OVERFLOW, E_NONFINITE, E_STATE, E_UNSUPPORTED = range(-1, -10, -1)
 E_PENDING = 1
@@ -137,6 +137,7 @@ def load():
     L.cpic_field_bytes.argtypes = [vp, i32]
     L.cpic_field_bytes.restype = sz
     L.cpic_get_diag.argtypes = [vp, P(Diag)]
+    L.cpic_get_diag_noalloc.argtypes = [vp, P(Diag)]
     L.cpic_sync.argtypes = [vp]
     L.cpic_set_timing.argtypes = [vp, i32]
     L.cpic_get_timing.argtypes = [vp, i32, vp, vp, vp, vp, P(i32)]
@@ -156,7 +157,7 @@ def load():
     L.cpic_server_destroy.restype = None
     for name in ("cpic_create", "cpic_add_species", "cpic_set_particles", "cpic_get_particles",
                  "cpic_initialize", "cpic_step", "cpic_run_stage", "cpic_get_field",
-                 "cpic_set_field", "cpic_get_diag", "cpic_sync", "cpic_set_timing",
+                 "cpic_set_field", "cpic_get_diag", "cpic_get_diag_noalloc", "cpic_sync", "cpic_set_timing",
                  "cpic_get_timing", "cpic_set_graphs", "cpic_server_create", "cpic_server_submit",
                  "cpic_server_pump", "cpic_server_poll", "cpic_server_get_stats"):
         getattr(L, name).restype = ctypes.c_int
@@ -391,6 +392,13 @@ class Sim:
     def diag(self):
         d = Diag()
         self._check(self.lib.cpic_get_diag(self.h, ctypes.byref(d)), "get_diag")
+        return d
+
+    def diag_noalloc(self):
+        """cpic_get_diag_noalloc: the diagnostics computed in the library's
+        per-device scratch array (allocates nothing)."""
+        d = Diag()
+        self._check(self.lib.cpic_get_diag_noalloc(self.h, ctypes.byref(d)), "get_diag_noalloc")
         return d
 
     def set_graphs(self, on=True):

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -64,6 +65,7 @@ struct StepEvents {
 }  // namespace
 
 struct cpic_sim {
+  int device = 0;  // the HIP device current at creation
   cpic_map_desc map;
   cpic_grid_desc grid;
   cpic_allocator alloc;
@@ -162,6 +164,47 @@ static cpic_status check_async(cpic_sim* s) {
 }
 
 // ----------------------------------------------------------------------------
+// Scratch of cpic_get_diag_noalloc: the reductions of the diagnostics work in
+// a file-scope device array instead of buffers the simulation allocated.  Each
+// device holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns for that device (the array's
+// name is a host-side stand-in).  Layout: REDUCE_BLOCKS doubles of field-energy
+// partials, the energy sum and the non-finite count, then QSUM_WORDS words of
+// exact-charge sums per species.
+// ----------------------------------------------------------------------------
+constexpr size_t SCR_PARTIALS = 0;
+constexpr size_t SCR_WE = SCR_PARTIALS + sizeof(double) * REDUCE_BLOCKS;
+constexpr size_t SCR_NONFINITE = SCR_WE + sizeof(double);
+constexpr size_t SCR_QSUM = (SCR_NONFINITE + sizeof(int) + 255) & ~(size_t)255;
+constexpr int SCR_SPECIES = MAX_SPECIES;
+constexpr size_t SCRATCH_BYTES = SCR_QSUM + sizeof(uint64_t) * QSUM_WORDS * SCR_SPECIES;  // 35,200 bytes
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_DEVICES = 64;
+static std::mutex scratch_mu;
+static void* scratch_addr[SCRATCH_DEVICES] = {};
+
+// Address of `scratch` on device `dev`, looked up once per device with that
+// device current; nullptr when the lookup fails.
+static void* scratch_on(int dev) {
+  if (dev < 0 || dev >= SCRATCH_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_addr[dev]) return scratch_addr[dev];
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+  if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != dev) (void)hipSetDevice(cur);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  scratch_addr[dev] = p;
+  return p;
+}
+
+// ----------------------------------------------------------------------------
 // creation
 // ----------------------------------------------------------------------------
 extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_desc* grid,
@@ -225,7 +268,13 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   if (grid->pusher != CPIC_PUSH_BORIS && grid->pusher != CPIC_PUSH_CYCLOTRONIC) return CPIC_E_ARG;
   if (grid->pusher == CPIC_PUSH_CYCLOTRONIC && grid->mover != CPIC_MOVER_NEWTON) return CPIC_E_UNSUPPORTED;
 
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return CPIC_E_HIP;
   cpic_sim* s = new cpic_sim();
+  s->device = device;
+  // per-device set-up of the no-allocation diagnostics' scratch (its entry
+  // point reports a failed lookup; nothing else needs it)
+  (void)scratch_on(device);
   s->map = *map;
   s->grid = *grid;
   if (s->grid.mg_rtol <= 0) s->grid.mg_rtol = 1e-10;
@@ -1391,6 +1440,16 @@ static cpic_status diag_impl(cpic_sim* s, cpic_diag* out, const DiagScratch& sc)
 extern "C" cpic_status cpic_get_diag(cpic_sim* s, cpic_diag* out) {
   if (!s || !out) return CPIC_E_ARG;
   const DiagScratch sc = {s->G.partials, s->tmp_scalar, s->flags + 3, s->qsum};
+  return diag_impl(s, out, sc);
+}
+
+extern "C" cpic_status cpic_get_diag_noalloc(cpic_sim* s, cpic_diag* out) {
+  if (!s || !out) return CPIC_E_ARG;
+  if ((int)s->sp.size() > SCR_SPECIES) return fail(s, CPIC_E_BUDGET, "more species than the diagnostics scratch holds");
+  unsigned char* base = (unsigned char*)scratch_on(s->device);
+  if (!base) return fail(s, CPIC_E_HIP, "address of the diagnostics scratch on this device not available");
+  const DiagScratch sc = {(double*)(base + SCR_PARTIALS), (double*)(base + SCR_WE), (int*)(base + SCR_NONFINITE),
+                          (uint64_t*)(base + SCR_QSUM)};
   return diag_impl(s, out, sc);
 }
 
