@@ -80,47 +80,32 @@ __host__ __device__ inline int tile_of_key(int key, const Geo& g) {
 }
 
 // ---------------------------------------------------------------------------
-// Trigonometric helpers.  sin/cos of 2 pi u for the base position: in FP32,
-// u is reduced to the nearest quarter turn, r = u - q/4 with |r| <= 1/8
-// (exact for |u| < 2^21), and sin/cos of x = 2 pi r come from their Taylor
-// series to degree 9 and 8 (truncation below 2e-9 and 3e-8 for
-// |x| <= pi/4), then rotated by q quarter turns; in FP64, the device
-// library's sinpi/cospi.  Increments sin(2 pi u) and cos(2 pi u) - 1 for the
-// small Newton steps are evaluated without cancellation: Taylor polynomials
-// for |2 pi u| < 0.8 in FP32 (truncation below 2e-9 there), sinpi of the half
-// angle in FP64.
+// Trigonometric helpers.  sin/cos of 2 pi u at the base position: in FP32 the
+// hardware instructions, which take their argument in revolutions (valid for
+// |u| <= 256; measured largest absolute error 1.3e-7 on [0, 1], the rounding of
+// FP32 near 1) -- the Newton residual uses them only multiplied by the small
+// increments below, so their error is damped; in FP64, the device library's
+// sinpi/cospi.  Increments sin(2 pi u) and cos(2 pi u) - 1 for the Newton
+// steps need relative accuracy (their error is amplified by the map amplitude
+// over the Jacobian): Taylor polynomials of degree 9 and 10 in x = 2 pi u,
+// truncation below 3e-9 for |x| < 0.8, without branches; beyond (a move of
+// more than 0.13 of the grid in one step) the device library.
 // ---------------------------------------------------------------------------
 __device__ inline void sincos2pi(float u, float& s, float& c) {
-  const float q = rintf(4.0f * u);
-  const float x = 6.28318530717958648f * (u - 0.25f * q);
-  const float x2 = x * x;
-  const float sx = x * (1.0f + x2 * (-1.0f / 6.0f + x2 * (1.0f / 120.0f + x2 * (-1.0f / 5040.0f + x2 * (1.0f / 362880.0f)))));
-  const float cx = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24.0f + x2 * (-1.0f / 720.0f + x2 * (1.0f / 40320.0f))));
-  const int k = ((int)q) & 3;
-  // rotate (cos x, sin x) by k quarter turns
-  const float s1 = (k & 1) ? cx : sx;
-  const float c1 = (k & 1) ? sx : cx;
-  s = (k & 2) ? -s1 : s1;
-  c = ((k + 1) & 2) ? -c1 : c1;
+  s = __builtin_amdgcn_sinf(u);
+  c = __builtin_amdgcn_cosf(u);
 }
 __device__ inline void sincos2pi(double u, double& s, double& c) { sincospi(2.0 * u, &s, &c); }
 
 __device__ inline void incr2pi(float u, float& sn, float& cm1) {
-  float th = 6.28318530717958648f * u;
-  if (fabsf(th) < 0.1f) {
-    // the common Newton step (a fraction of a cell on a grid of many cells):
-    // truncation below 3e-11 at degree 5 and 6
-    float t2 = th * th;
-    sn = th * (1.0f - t2 * (1.0f / 6.0f) * (1.0f - t2 * (1.0f / 20.0f)));
-    cm1 = -0.5f * t2 * (1.0f - t2 * (1.0f / 12.0f) * (1.0f - t2 * (1.0f / 30.0f)));
-  } else if (fabsf(th) < 0.8f) {
-    float t2 = th * th;
-    sn = th * (1.0f - t2 * (1.0f / 6.0f) *
-                          (1.0f - t2 * (1.0f / 20.0f) * (1.0f - t2 * (1.0f / 42.0f) * (1.0f - t2 * (1.0f / 72.0f)))));
-    cm1 = -0.5f * t2 *
-          (1.0f - t2 * (1.0f / 12.0f) *
-                      (1.0f - t2 * (1.0f / 30.0f) * (1.0f - t2 * (1.0f / 56.0f) * (1.0f - t2 * (1.0f / 90.0f)))));
-  } else {
+  const float th = 6.28318530717958648f * u;
+  const float t2 = th * th;
+  sn = th * (1.0f - t2 * (1.0f / 6.0f) *
+                        (1.0f - t2 * (1.0f / 20.0f) * (1.0f - t2 * (1.0f / 42.0f) * (1.0f - t2 * (1.0f / 72.0f)))));
+  cm1 = -0.5f * t2 *
+        (1.0f - t2 * (1.0f / 12.0f) *
+                    (1.0f - t2 * (1.0f / 30.0f) * (1.0f - t2 * (1.0f / 56.0f) * (1.0f - t2 * (1.0f / 90.0f)))));
+  if (!(fabsf(th) < 0.8f)) {
     float s, c;
     sincospif(2.0f * u, &s, &c);
     sn = s;
@@ -152,7 +137,7 @@ __device__ inline double newton_rcp(double x) { return 1.0 / x; }
 // below tol cells, or when the quadratic-convergence bound kappa s^2 on the
 // remaining error is below tol / 4 (kappa = max second derivative over twice
 // the smallest Jacobian of the increment map, from the host).  J0 receives
-// the (box-unit) Jacobian at xi^n.
+// the smallest (box-unit) Jacobian met: at xi^n and at every Newton iterate.
 // ---------------------------------------------------------------------------
 
 // Sinusoidal map, x^a = L_a (xi^a + eps P), P = prod_k sin(2 pi xi^k) (Eq. map2
@@ -231,6 +216,7 @@ __device__ __forceinline__ bool newton_sinusoidal(const Geo& g, const int* idx, 
       Jn += e[a] * gg[a];
       gF += gg[a] * F[a];
     }
+    J0 = fmin(J0, Jn);
     R q = gF * newton_rcp(Jn);
     R mx = (R)0;
 #pragma unroll

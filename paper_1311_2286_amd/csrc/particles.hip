@@ -333,6 +333,9 @@ __device__ __forceinline__ bool move_delta(const Geo& g, const int* idx, const R
     R vdt[2] = {dt * v[0], dt * v[1]};
     conv = newton_polar<R>(g, idx, f, vdt, d, tol, kappa, maxit, J0);
   }
+  // FP32 residuals lose about 1/J of their accuracy: strongly stretched cells
+  // (J < 1/4 of the undistorted cell at the start or at any iterate) go to
+  // the FP64 fallback
   const bool low_j = std::is_same<R, float>::value && J0 < (R)0.25;
   return conv && !low_j;
 }
@@ -478,22 +481,28 @@ __device__ __forceinline__ void move_pc(const Geo& g, const R* __restrict__ kc, 
 // absorbing condition) or -2 (left through an outflow wall).
 template <int D, typename R>
 __device__ __forceinline__ int place_particle(const Geo& g, const int* pbc_lo, const int* pbc_hi,
-                                              int* idx, R* f, const R* d) {
+                                              int* idx, R* f, const R* d, int* shift = nullptr) {
   int dead = 0;
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) {
     R u = f[ax] + d[ax];
     R fl = floor(u);
     R nf = u - fl;
-    int ni = idx[ax] + (int)fl;
+    int sh = (int)fl;
     if (nf >= (R)1) {
       nf = (R)0;
-      ni += 1;
+      sh += 1;
     }
+    int ni = idx[ax] + sh;
+    if (shift) shift[ax] = sh;
     const int n = g.n[ax];
     if (g.periodic[ax]) {
-      ni %= n;
-      if (ni < 0) ni += n;
+      // one period at most in the common case; a division only beyond it
+      ni = ni < 0 ? ni + n : (ni >= n ? ni - n : ni);
+      if ((unsigned)ni >= (unsigned)n) {
+        ni %= n;
+        if (ni < 0) ni += n;
+      }
     } else if (ni < 0) {
       dead = (pbc_lo[ax] == PBC_ABSORB) ? -1 : -2;
     } else if (ni >= n) {
@@ -503,6 +512,18 @@ __device__ __forceinline__ int place_particle(const Geo& g, const int* pbc_lo, c
     f[ax] = nf;
   }
   return dead;
+}
+
+// Element i of a particle array.  For 4-byte elements the byte offset is a
+// 32-bit unsigned value (species capacities stay below 2^30), so each access
+// takes the scalar base + 32-bit vector offset form and needs no 64-bit
+// address arithmetic of its own.
+template <typename T>
+__device__ __forceinline__ T& pel(T* base, int i) {
+  if constexpr (sizeof(T) == 4)
+    return *(T*)((char*)base + (unsigned)i * 4u);
+  else
+    return base[i];
 }
 
 template <typename R>
@@ -551,10 +572,12 @@ struct PartArgs {
   int fb_cap;
 };
 
+// lcell: when set, the particle's cell in deposit-window coordinates
+// (idx - origin + G, wrapped), known from the gather's field-window index.
 template <int D, int SHAPE, typename R, bool FIXED, typename QT>
 __device__ __forceinline__ void deposit_particle(const Geo& g, const int* origin, QT* win, void* Qg,
                                         const int* idx, const R* f, int S1,
-                                        unsigned long long& far) {
+                                        unsigned long long& far, const int* lcell = nullptr) {
   using TS = TileShape<D>;
   typedef typename std::conditional<FIXED, uint32_t, R>::type WT;
   const int Wd[3] = {TS::W0, TS::W1, TS::W2};
@@ -608,12 +631,18 @@ __device__ __forceinline__ void deposit_particle(const Geo& g, const int* origin
       continue;
     }
     const int n = g.n[a];
-    int l = idx[a] - origin[a] + TS::G;
-    if (g.periodic[a]) {
-      if (l < 0) l += n;
-      else if (l >= Wd[a]) l -= n;
+    int l;
+    if (lcell) {
+      l = lcell[a];
+      if (!g.periodic[a]) fast = fast && idx[a] + sft >= 0 && idx[a] + sft + NT - 1 <= n - 1;
     } else {
-      fast = fast && idx[a] + sft >= 0 && idx[a] + sft + NT - 1 <= n - 1;
+      l = idx[a] - origin[a] + TS::G;
+      if (g.periodic[a]) {
+        if (l < 0) l += n;
+        else if (l >= Wd[a]) l -= n;
+      } else {
+        fast = fast && idx[a] + sft >= 0 && idx[a] + sft + NT - 1 <= n - 1;
+      }
     }
     l += sft;
     fast = fast && l >= 0 && l + NT - 1 <= Wd[a] - 1;
@@ -785,9 +814,10 @@ __device__ __forceinline__ void count_new_tile(const Geo& g, const int* idx, int
 // gather from LDS.  Components are packed (2 in 2D, 3 in 3D; the padding slot
 // of the global array is not staged).
 // Same weights and summation order as gather_E, so both give identical sums.
+// lout: the cell's local index in the field window (vertex origin - 1 is 0)
 template <int D, typename R>
 __device__ __forceinline__ bool gather_E_window(const R* __restrict__ ewin, const Geo& g, const int* origin,
-                                                const int* idx, const R* f, R* E) {
+                                                const int* idx, const R* f, R* E, int* lout) {
   using FW = FieldWindow<D>;
   const int Ew[3] = {FW::E0, FW::E1, FW::E2};
   int l[3] = {0, 0, 0};
@@ -796,6 +826,7 @@ __device__ __forceinline__ bool gather_E_window(const R* __restrict__ ewin, cons
   for (int a = 0; a < D; ++a) {
     l[a] = wrap_local(idx[a], origin[a] - 1, g.n[a], g.periodic[a] != 0);
     in = in && l[a] >= 0 && l[a] + 1 < Ew[a];
+    lout[a] = l[a];
   }
   if (!in) return false;
   // all 2^D vertices are loaded first (one base address, constant offsets),
@@ -920,10 +951,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
       for (int ax = D - 1; ax >= 0; --ax) {
         int x = origin[ax] - 1 + lv[ax];
         const int nv = g.nv[ax];
-        if (g.periodic[ax])
-          x = ((x % nv) + nv) % nv;
-        else
+        if (g.periodic[ax]) {
+          // x lies in [-1, n + 2]; grids narrower than the window wrap more than once
+          while (x < 0) x += nv;
+          while (x >= nv) x -= nv;
+        } else {
           ok = ok && x >= 0 && x < nv;
+        }
         v = v * nv + x;
       }
       if (ok) {
@@ -950,14 +984,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
   int nkey = -1;
   R nf0 = (R)0, nf1 = (R)0, nf2 = (R)0, nv0 = (R)0, nv1 = (R)0, nv2 = (R)0;
   if (p < end) {
-    nkey = a.key[p];
-    nf0 = a.off0[p];
-    nf1 = a.off1[p];
-    if (D == 3) nf2 = a.off2[p];
+    nkey = pel(a.key, p);
+    nf0 = pel(a.off0, p);
+    nf1 = pel(a.off1, p);
+    if (D == 3) nf2 = pel(a.off2, p);
     if (need_v) {
-      nv0 = a.v0[p];
-      nv1 = a.v1[p];
-      if (a.vz_active) nv2 = a.v2[p];
+      nv0 = pel(a.v0, p);
+      nv1 = pel(a.v1, p);
+      if (a.vz_active) nv2 = pel(a.v2, p);
     }
   }
   for (; p < end; p += (int)blockDim.x) {
@@ -966,14 +1000,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
     R v[3] = {nv0, nv1, nv2};
     const int pn = p + (int)blockDim.x;
     if (pn < end) {
-      nkey = a.key[pn];
-      nf0 = a.off0[pn];
-      nf1 = a.off1[pn];
-      if (D == 3) nf2 = a.off2[pn];
+      nkey = pel(a.key, pn);
+      nf0 = pel(a.off0, pn);
+      nf1 = pel(a.off1, pn);
+      if (D == 3) nf2 = pel(a.off2, pn);
       if (need_v) {
-        nv0 = a.v0[pn];
-        nv1 = a.v1[pn];
-        if (a.vz_active) nv2 = a.v2[pn];
+        nv0 = pel(a.v0, pn);
+        nv1 = pel(a.v1, pn);
+        if (a.vz_active) nv2 = pel(a.v2, pn);
       }
     }
     if (key < 0) {
@@ -981,19 +1015,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
       continue;
     }
     int idx[3] = {key_i(key, g), key_j(key, g), (D == 3) ? key_k(key, g) : 0};
+    // the new cell in deposit-window coordinates, when the field window served
+    // the gather: its local index + G - 1 + the cell shift of the move
+    int lcell[3] = {0, 0, 0};
+    bool have_l = false;
 
     if (need_v) {
       R E[3];
-      if (!gather_E_window<D, R>(ewin, g, origin, idx, f, E)) gather_E<D, R>(a.Ev, g, idx, f, E);
+      int le[3] = {0, 0, 0};
+      have_l = gather_E_window<D, R>(ewin, g, origin, idx, f, E, le);
+      if (!have_l) gather_E<D, R>(a.Ev, g, idx, f, E);
       R vo0 = v[0], vo1 = v[1], vo2 = v[2];
       if (CYC && a.mode == MODE_PUSH) {
         // cyclotronic step: exact gyration; the position moves with the mean
         // velocity of the gyration, which takes v's place once v is stored
         R vm[3];
         cyclotronic_step<R>(v, E, a.qm, a.dt, a.cyc_b, a.cyc_c, a.cyc_s, a.cyc_s1, a.cyc_s2, vm);
-        a.v0[p] = v[0];
-        a.v1[p] = v[1];
-        if (a.vz_active) a.v2[p] = v[2];
+        pel(a.v0, p) = v[0];
+        pel(a.v1, p) = v[1];
+        if (a.vz_active) pel(a.v2, p) = v[2];
         // kinetic energy of the velocity at t_n: before the impulse plus half of it
         const R h = (R)0.5 * a.qm * a.dt;
         const R m0 = vo0 + h * E[0], m1 = vo1 + h * E[1], m2 = vo2 + h * E[2];
@@ -1004,9 +1044,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
       } else {
         // Boris (the cyclotronic start-up is the half impulse alone)
         boris_push<R>(v, E, a.B, a.qm, a.dt, a.magnetic != 0 && !CYC);
-        a.v0[p] = v[0];
-        a.v1[p] = v[1];
-        if (a.vz_active) a.v2[p] = v[2];
+        pel(a.v0, p) = v[0];
+        pel(a.v1, p) = v[1];
+        if (a.vz_active) pel(a.v2, p) = v[2];
         if (a.mode == MODE_HALFSTEP) continue;
         ke += (double)(vo0 * v[0] + vo1 * v[1] + vo2 * v[2]);
       }
@@ -1035,21 +1075,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
       }
 #pragma unroll
       for (int ax = 0; ax < D; ++ax) dmax = fmaxf(dmax, fabsf((float)d[ax]));
-      int dead = place_particle<D, R>(g, a.pbc_lo, a.pbc_hi, idx, f, d);
+      int sh[3] = {0, 0, 0};
+      int dead = place_particle<D, R>(g, a.pbc_lo, a.pbc_hi, idx, f, d, sh);
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) lcell[ax] = le[ax] + TS::G - 1 + sh[ax];
       if (dead) {
-        a.key[p] = dead;
+        pel(a.key, p) = dead;
         absorbed += dead == -1 ? 1 : 0;
         outflow += dead == -2 ? 1 : 0;
         if (tcount) atomicAdd(&tbins[TB_DEAD], 1);
         continue;
       }
-      a.key[p] = make_key(idx[0], idx[1], idx[2], g);
+      pel(a.key, p) = make_key(idx[0], idx[1], idx[2], g);
       if (tcount) count_new_tile<D>(g, idx, tci, tcj, tck, tbins, a.tcount);
-      a.off0[p] = f[0];
-      a.off1[p] = f[1];
-      if (D == 3) a.off2[p] = f[2];
+      pel(a.off0, p) = f[0];
+      pel(a.off1, p) = f[1];
+      if (D == 3) pel(a.off2, p) = f[2];
     }
-    deposit_particle<D, SHAPE, R, FIXED, QT>(g, origin, win, a.Q, idx, f, a.S1, far);
+    deposit_particle<D, SHAPE, R, FIXED, QT>(g, origin, win, a.Q, idx, f, a.S1, far, have_l ? lcell : nullptr);
     ++ndep;
   }
 
@@ -1575,11 +1618,13 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const int* __restrict__
     int c = counts[t];
     start[t] = (int)pbase;
     cursor[t] = (int)pbase;
+    // the tile's particles in k equal parts (a full chunk and a small
+    // remainder would cost the remainder a whole workgroup's set-up)
     int k = (c + chunk - 1) / chunk;
     for (int j = 0; j < k; ++j) {
       item_tile[ibase + j] = t;
-      item_begin[ibase + j] = (int)(pbase + (long long)j * chunk);
-      item_end[ibase + j] = (int)min(pbase + (long long)(j + 1) * chunk, pbase + c);
+      item_begin[ibase + j] = (int)(pbase + (long long)j * c / k);
+      item_end[ibase + j] = (int)(pbase + (long long)(j + 1) * c / k);
     }
     pbase += c;
     ibase += k;
