@@ -289,11 +289,12 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   s->chunk = (d == 2) ? 4096 : 16384;
   {
     // Newton on the map increment converges quadratically: the error after a
-    // step s is at most kappa s^2 with kappa = (max |F''|) / 2 * max |F'^{-1}|
-    // (max-norms over the domain, in cells).  Sinusoidal: entries of F'' are
-    // bounded by e_max (2 pi / n_min)^2, |F'^{-1}| by 1 + 2 pi |eps| d n_max /
-    // (n_min J_min).  Polar-log: second derivatives ~ k_max^2, inverse ~ 1/k_min
-    // with k = (ln R / n0, 2 pi / n1).
+    // step s is at most kappa |s|^2 (in cells).  Sinusoidal: the residual
+    // after the step is e R, |R| <= (1/2) w_max^2 |s|_1^2 with w = 2 pi / n,
+    // and the inverse of the mean-value Jacobian (I + e g^T) maps e to e / J,
+    // so kappa = e_max w_max^2 / (2 J_min) with the 1-norm of the step.
+    // Polar-log: second derivatives ~ k_max^2, inverse ~ 1/k_min with
+    // k = (ln R / n0, 2 pi / n1), max-norm of the step.
     int nmin = grid->n[0], nmax = grid->n[0];
     for (int a = 1; a < d; ++a) {
       nmin = std::min(nmin, grid->n[a]);
@@ -304,8 +305,7 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
       double jmin = 1.0 - 2.0 * M_PI * fabs(map->eps) * bound;
       double emax = fabs(map->eps) * nmax;
       double w = 2.0 * M_PI / nmin;
-      double cinv = 1.0 + 2.0 * M_PI * fabs(map->eps) * d * (double)nmax / ((double)nmin * jmin);
-      s->kappa = 0.5 * d * d * emax * w * w * cinv;
+      s->kappa = 0.5 * emax * w * w / jmin;
     } else if (map->kind == CPIC_MAP_POLAR_LOG) {
       double kx = log(map->r_out / map->r_in) / grid->n[0], ky = 2.0 * M_PI / grid->n[1];
       double kmax = std::max(kx, ky), kmin = std::min(kx, ky);

@@ -145,7 +145,11 @@ __device__ inline double newton_rcp(double x) { return 1.0 / x; }
 //   F_a(delta) = delta_a + e_a [P(xi + delta h) - P(xi)] - r_a = 0,
 // e_a = eps n_a, r_a = dt v_a n_a / L_a.  Jacobian I + e g^T with
 // g_m = (2 pi / n_m) cos(2 pi xi_m') prod_{k != m} sin(2 pi xi_k'), inverted by
-// Sherman-Morrison; 1 + g.e is the box Jacobian at xi'.
+// Sherman-Morrison; 1 + g.e is the box Jacobian at xi'.  Stopping bound:
+// after a step s the residual is e R with |R| <= (1/2) w_max^2 (sum |s_a|)^2
+// (the second derivatives of P in cells are at most w_max^2, w = 2 pi / n),
+// and the mean-value Jacobian, again I + e g^T, maps e R to e R / J, so the
+// error is at most kappa (sum |s_a|)^2 with kappa = e_max w_max^2 / (2 J_min).
 template <int D, typename R>
 __device__ __forceinline__ bool newton_sinusoidal(const Geo& g, const int* idx, const R* f,
                                                   const R* r, R* d, R tol, R kappa, int maxit,
@@ -175,13 +179,14 @@ __device__ __forceinline__ bool newton_sinusoidal(const Geo& g, const int* idx, 
     }
     J0 = Jn;
     const R q = gr * newton_rcp(Jn);
-    R mx = (R)0;
+    R mx = (R)0, l1 = (R)0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       d[a] = r[a] - e[a] * q;
       mx = fmax(mx, fabs(d[a]));
+      l1 += fabs(d[a]);
     }
-    if (mx < tol || kappa * mx * mx < (R)0.25 * tol) return true;
+    if (mx < tol || kappa * l1 * l1 < (R)0.25 * tol) return true;
   }
   for (int it = 1; it < maxit; ++it) {
     R sn[D], cn[D], ds[D];
@@ -218,14 +223,15 @@ __device__ __forceinline__ bool newton_sinusoidal(const Geo& g, const int* idx, 
     }
     J0 = fmin(J0, Jn);
     R q = gF * newton_rcp(Jn);
-    R mx = (R)0;
+    R mx = (R)0, l1 = (R)0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       R dd = -(F[a] - e[a] * q);
       d[a] += dd;
       mx = fmax(mx, fabs(dd));
+      l1 += fabs(dd);
     }
-    if (mx < tol || kappa * mx * mx < (R)0.25 * tol) return true;
+    if (mx < tol || kappa * l1 * l1 < (R)0.25 * tol) return true;
   }
   return false;
 }
