@@ -259,6 +259,8 @@ typedef struct {
   long long inject_lost[8];  /* cumulative injected particles whose entry flight (a random fraction of
                                 the step from the face) left the domain at once: never live, not in
                                 injected[] */
+  long long batched_steps;   /* steps whose field phase ran batched with other simulations
+                                (cpic_step_batch) */
 } cpic_diag;
 
 /* Create a simulation on the current HIP device.  hip_stream may be NULL
@@ -300,6 +302,39 @@ cpic_status cpic_initialize(cpic_sim* sim);
 
 /* Advance nsteps full PIC cycles (asynchronous). */
 cpic_status cpic_step(cpic_sim* sim, int nsteps);
+
+/* Advance each of n simulations by one PIC cycle (asynchronous), with their
+   field phases batched (the throughput path of a server running many small
+   cases).  Each result is bit for bit what cpic_step(sims[i], 1) gives.  The
+   particle phases run case by case; the field phase (charge, the flexible-CG
+   solve of Sec. "Field solve" with its V-cycle preconditioner, the vertex
+   field) runs as one launch per kernel over all cases when every case has
+   FP32 particles, the flexible-CG method, no floating wall, no injection, a
+   stream shared with the others, and the same grid dimensions, boundary
+   types and restriction; a small grid's field phase is launch-bound, and the
+   batch pays those launches once.  Otherwise the cases are stepped one after
+   the other.  The solve of each case stops at its own convergence and cycle
+   budget.  Each simulation may appear once; n >= 1.  status (NULL, or n
+   entries) receives each case's outcome: a case that cpic_step would refuse
+   (CPIC_E_STATE, CPIC_E_OVERFLOW) is left out and keeps its state while the
+   others step; a runtime error during the batched launches (CPIC_E_HIP) is
+   reported for every case of the batch.  The batch's argument buffer (a few
+   hundred bytes per kernel and case) comes from the allocator of the first
+   case stepped and is freed by its cpic_destroy; when it cannot be allocated
+   the field phases run case by case.  Returns CPIC_OK, else the first
+   failing case's status. */
+cpic_status cpic_step_batch(cpic_sim* const* sims, int n, cpic_status* status);
+
+/* *sig receives 0 when cpic_step_batch cannot batch the simulation's field
+   phase (see there), else a value that two simulations share when their
+   field phases can be batched together (on a shared stream).  Valid once the
+   species are added. */
+cpic_status cpic_batch_signature(const cpic_sim* sim, uint64_t* sig);
+
+/* Move the simulation to another stream (NULL: the default stream): waits for
+   the work queued on the current one (synchronises), and everything after
+   runs on the new one. */
+cpic_status cpic_set_stream(cpic_sim* sim, void* hip_stream);
 
 /* Run one stage (asynchronous); see CPIC_STAGE_*. */
 cpic_status cpic_run_stage(cpic_sim* sim, int stage);
@@ -418,19 +453,25 @@ typedef struct {
   long long pushes;       /* over completed cases */
   long long step_samples;
   double step_p50_ms, step_p99_ms; /* over every step of every completed case */
+  long long batched_steps; /* case steps taken by cpic_step_batch with other cases */
 } cpic_server_stats;
 
 /* hbm_budget_bytes: device memory the cases may hold together; max_slots:
    cases resident at once (1..64); alloc: as for cpic_create (NULL: hipMalloc);
-   hip_stream: NULL to give every slot its own stream (created and destroyed
-   by the server), else every case runs on that stream. */
+   hip_stream: NULL to give the server max_slots streams (created and
+   destroyed by it, and one more where new cases are set up), else every case
+   runs on that stream.  Running cases of one batch signature
+   (cpic_batch_signature) share a stream and step together through
+   cpic_step_batch; the others take the least loaded stream.  The
+   environment variable CPIC_SERVER_NO_BATCH set at creation turns batching off. */
 cpic_status cpic_server_create(size_t hbm_budget_bytes, int max_slots, const cpic_allocator* alloc,
                                void* hip_stream, cpic_server** out);
 /* Queue a case; *ticket identifies it.  Validates the description (CPIC_E_ARG)
    and copies the particle arrays. */
 cpic_status cpic_server_submit(cpic_server* srv, const cpic_case_desc* desc, uint64_t* ticket);
-/* Run up to max_iterations rounds of: admit, one step of every running case,
-   retire finished cases.  Returns CPIC_OK when nothing is queued or running
+/* Run up to max_iterations rounds of: admit, one step of every running case
+   (the cases of a batch group through one cpic_step_batch), retire finished
+   cases.  Returns CPIC_OK when nothing is queued or running
    afterwards, CPIC_E_PENDING otherwise. */
 cpic_status cpic_server_pump(cpic_server* srv, int max_iterations);
 /* CPIC_E_PENDING until the case is done, then CPIC_OK with *out filled

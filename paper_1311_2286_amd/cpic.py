@@ -32,7 +32,8 @@ EXPORTED = ["cpic_create", "cpic_add_species", "cpic_set_particles", "cpic_get_p
             "cpic_field_bytes", "cpic_get_diag", "cpic_sync", "cpic_set_timing", "cpic_get_timing",
             "cpic_status_str", "cpic_last_error", "cpic_destroy", "cpic_set_graphs", "cpic_server_create",
             "cpic_server_submit", "cpic_server_pump", "cpic_server_poll", "cpic_server_get_stats",
-            "cpic_server_destroy", "cpic_get_diag_noalloc"]
+            "cpic_server_destroy", "cpic_get_diag_noalloc", "cpic_step_batch",
+            "cpic_batch_signature", "cpic_set_stream"]
 MAX_SPECIES = 8
 E_ARG, E_MAP, E_NOMEM, E_BUDGET, E_HIP, E_OVERFLOW, E_NONFINITE, E_STATE, E_UNSUPPORTED = range(-1, -10, -1)
 E_PENDING = 1
@@ -79,7 +80,8 @@ class Diag(ctypes.Structure):
                 ("far_deposits", ctypes.c_longlong), ("newton_failed", ctypes.c_longlong),
                 ("injected", ctypes.c_longlong * 8), ("step_graphs", ctypes.c_int),
                 ("sorts", ctypes.c_longlong * 8), ("phi_wall", ctypes.c_double),
-                ("wall_charge", ctypes.c_double), ("inject_lost", ctypes.c_longlong * 8)]
+                ("wall_charge", ctypes.c_double), ("inject_lost", ctypes.c_longlong * 8),
+                ("batched_steps", ctypes.c_longlong)]
 
 
 class CaseDesc(ctypes.Structure):
@@ -110,7 +112,8 @@ class ServerStats(ctypes.Structure):
                 ("budget_bytes", ctypes.c_size_t),
                 ("used_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
                 ("pushes", ctypes.c_longlong), ("step_samples", ctypes.c_longlong),
-                ("step_p50_ms", ctypes.c_double), ("step_p99_ms", ctypes.c_double)]
+                ("step_p50_ms", ctypes.c_double), ("step_p99_ms", ctypes.c_double),
+                ("batched_steps", ctypes.c_longlong)]
 
 
 _lib = None
@@ -131,6 +134,9 @@ def load():
     L.cpic_get_particles.argtypes = [vp, i32, sz, vp, vp, vp, vp, P(sz), i32]
     L.cpic_initialize.argtypes = [vp]
     L.cpic_step.argtypes = [vp, i32]
+    L.cpic_step_batch.argtypes = [P(vp), i32, P(i32)]
+    L.cpic_batch_signature.argtypes = [vp, P(ctypes.c_uint64)]
+    L.cpic_set_stream.argtypes = [vp, vp]
     L.cpic_run_stage.argtypes = [vp, i32]
     L.cpic_get_field.argtypes = [vp, i32, i32, vp, sz, i32]
     L.cpic_set_field.argtypes = [vp, i32, i32, vp, sz, i32]
@@ -156,7 +162,8 @@ def load():
     L.cpic_server_destroy.argtypes = [vp]
     L.cpic_server_destroy.restype = None
     for name in ("cpic_create", "cpic_add_species", "cpic_set_particles", "cpic_get_particles",
-                 "cpic_initialize", "cpic_step", "cpic_run_stage", "cpic_get_field",
+                 "cpic_initialize", "cpic_step", "cpic_step_batch", "cpic_batch_signature", "cpic_set_stream",
+                 "cpic_run_stage", "cpic_get_field",
                  "cpic_set_field", "cpic_get_diag", "cpic_get_diag_noalloc", "cpic_sync", "cpic_set_timing",
                  "cpic_get_timing", "cpic_set_graphs", "cpic_server_create", "cpic_server_submit",
                  "cpic_server_pump", "cpic_server_poll", "cpic_server_get_stats"):
@@ -401,6 +408,17 @@ class Sim:
         self._check(self.lib.cpic_get_diag_noalloc(self.h, ctypes.byref(d)), "get_diag_noalloc")
         return d
 
+    def batch_signature(self):
+        """0 when the field phase cannot be batched, else the value that
+        simulations batchable together share (cpic_batch_signature)."""
+        v = ctypes.c_uint64()
+        self._check(self.lib.cpic_batch_signature(self.h, ctypes.byref(v)), "batch_signature")
+        return int(v.value)
+
+    def set_stream(self, stream):
+        self._check(self.lib.cpic_set_stream(self.h, ctypes.c_void_p(stream)), "set_stream")
+        self.stream = stream
+
     def set_graphs(self, on=True):
         """Replay recorded HIP graphs of the step (needs a non-null stream)."""
         self._check(self.lib.cpic_set_graphs(self.h, int(on)), "set_graphs")
@@ -415,6 +433,20 @@ class Sim:
                                              ctypes.byref(n)), "get_timing")
         k = min(n.value, max_samples)
         return dict(push=bufs[0][:k], solve=bufs[1][:k], sort=bufs[2][:k], step=bufs[3][:k])
+
+
+def step_batch(sims):
+    """One step of each simulation, field phases batched (cpic_step_batch).
+    Returns the per-case statuses; raises when any is an error."""
+    sims = list(sims)
+    arr = (ctypes.c_void_p * len(sims))(*[s.h for s in sims])
+    status = (ctypes.c_int * len(sims))()
+    st = load().cpic_step_batch(arr, len(sims), status)
+    if st != 0:
+        msgs = ["case %d: %d %s" % (i, status[i], s.lib.cpic_last_error(s.h).decode())
+                for i, s in enumerate(sims) if status[i] != 0]
+        raise CpicError(st, "step_batch: %s" % "; ".join(msgs))
+    return list(status)
 
 
 def qsum(d: Diag, sid: int) -> int:

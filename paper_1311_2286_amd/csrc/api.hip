@@ -89,6 +89,8 @@ struct cpic_sim {
   hipEvent_t hist_ev[HIST] = {};   // recorded after the copies of step n, slot n % HIST
   long long hist_from = 0;         // records of steps before this one are not used
   bool overflowed = false;         // a fixed-point deposit wrapped (sticky until new particles)
+  BatchArgs batch_args;            // argument structs of batched field phases led by this simulation
+  long long batched_steps = 0;     // steps whose field phase ran batched
   struct StepGraph {
     uint64_t key;
     hipGraphExec_t exec;
@@ -133,6 +135,22 @@ static void* sim_alloc(cpic_sim* s, size_t bytes) {
   }
   if (p) s->allocs.push_back({p, bytes});
   return p;
+}
+
+// the batch argument buffer: the simulation's allocator, outside its list
+// (the buffer may be replaced by a larger one while the simulation lives)
+static void* batch_dev_alloc(size_t bytes, void* ctx) {
+  cpic_sim* s = (cpic_sim*)ctx;
+  void* p = nullptr;
+  if (s->has_alloc) return s->alloc.alloc(bytes, s->alloc.ctx);
+  return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+static void batch_dev_free(void* p, void* ctx) {
+  cpic_sim* s = (cpic_sim*)ctx;
+  if (s->has_alloc)
+    s->alloc.free(p, s->alloc.ctx);
+  else
+    (void)hipFree(p);
 }
 
 static void sim_free_all(cpic_sim* s) {
@@ -285,6 +303,9 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     s->has_alloc = true;
   }
   s->stream = (hipStream_t)hip_stream;
+  s->batch_args.dev_alloc = batch_dev_alloc;
+  s->batch_args.dev_free = batch_dev_free;
+  s->batch_args.ctx = s;
   s->S1 = (d == 2) ? 24 : 16;
   s->chunk = (d == 2) ? 4096 : 16384;
   {
@@ -1033,10 +1054,11 @@ static void charge_pass(cpic_sim* s) {
 }
 
 // cycles: V-cycles to launch (the solve stops on the device once converged;
-// cycles launched after that return at once but still cost their launches)
-static void solve_pass(cpic_sim* s, int cycles = -1) {
+// cycles launched after that return at once but still cost their launches);
+// cap: the cycles the solve may use (<= 0: as many as launched)
+static void solve_pass(cpic_sim* s, int cycles = -1, int cap = 0) {
   launch_rhs(s->G, s->stream);
-  launch_mg_solve(s->G, s->grid.mg_rtol, cycles > 0 ? cycles : s->grid.mg_max_cycles, 2, 2, s->stream);
+  launch_mg_solve(s->G, s->grid.mg_rtol, cycles > 0 ? cycles : s->grid.mg_max_cycles, 2, 2, s->stream, cap);
   if (s->G.floating) {
     WallCharge wc;
     memset(&wc, 0, sizeof(wc));
@@ -1134,13 +1156,12 @@ static StepEvents* next_events(cpic_sim* s) {
   return &s->evs[s->ev_used++];
 }
 
-// The kernels of one step after ensure_sorted (asynchronous, no host reads);
-// the species in sort_mask are tile-sorted at its end.
-static void step_body(cpic_sim* s, StepEvents* ev, bool inj, unsigned sort_mask, int cycles) {
+// Particle phase of a step: cleared deposits (and tile counts of the species
+// sorted at its end, counted by the step's particle and injection kernels, so
+// that the sort needs no histogram), the particle kernels, the injection.
+static void particle_phase(cpic_sim* s, StepEvents* ev, bool inj, unsigned sort_mask) {
   if (ev) hipEventRecord(ev->e[0], s->stream);
   zero_deposits(s, MODE_PUSH);
-  // a species sorted at the end of the step has its new tiles counted by the
-  // step's particle and injection kernels (the sort then needs no histogram)
   for (size_t k = 0; k < s->sp.size(); ++k)
     if (sort_mask >> k & 1u)
       launch_fill_u8(s->sp[k].counts, 0, sizeof(int) * (size_t)(s->g.ntiles + 2), s->stream);
@@ -1148,16 +1169,33 @@ static void step_body(cpic_sim* s, StepEvents* ev, bool inj, unsigned sort_mask,
   particles_pass(s, MODE_PUSH, sort_mask);
   if (ev) hipEventRecord(ev->e[2], s->stream);
   if (inj) inject_pass(s, s->step, sort_mask);
+}
+
+// Field phase of a step: charge, the solve's initial guess extrapolated
+// linearly from the last two steps, the solve (launching `cycles`, using at
+// most `cap`), the vertex field.
+static void field_phase(cpic_sim* s, int cycles, int cap) {
   charge_pass(s);
-  // initial guess of the solve: phi extrapolated linearly from the last two steps
   launch_extrapolate_guess(s->G, s->phi_prev_valid ? 1 : 0, s->stream);
   s->phi_prev_valid = true;
-  solve_pass(s, cycles);
+  solve_pass(s, cycles, cap);
   launch_efield(s->G, s->stream);
+}
+
+// End of a step: the tile sort of the species in sort_mask.
+static void step_end(cpic_sim* s, StepEvents* ev, unsigned sort_mask) {
   if (ev) hipEventRecord(ev->e[3], s->stream);
   ++s->step;
   sort_species_mask(s, sort_mask, true);
   if (ev) hipEventRecord(ev->e[4], s->stream);
+}
+
+// The kernels of one step after ensure_sorted (asynchronous, no host reads);
+// the species in sort_mask are tile-sorted at its end.
+static void step_body(cpic_sim* s, StepEvents* ev, bool inj, unsigned sort_mask, int cycles) {
+  particle_phase(s, ev, inj, sort_mask);
+  field_phase(s, cycles, cycles);
+  step_end(s, ev, sort_mask);
 }
 
 // One step as a HIP graph: every step variant (buffer parity of each species,
@@ -1214,46 +1252,203 @@ static bool graph_step(cpic_sim* s, unsigned sort_mask, int cycles, StepEvents* 
   return true;
 }
 
-extern "C" cpic_status cpic_step(cpic_sim* s, int nsteps) {
-  if (!s || nsteps < 0) return CPIC_E_ARG;
+// Host decisions of the coming step from the record of step n - 2 (waited
+// for): the species to sort at its end and the solver cycles to launch.
+static cpic_status step_prelude(cpic_sim* s, unsigned* mask, int* cycles) {
+  const long long n = s->step;
+  int last = -1;
+  const unsigned* drift = nullptr;
+  if (n - 2 >= s->hist_from) {
+    const int slot = (int)((n - 2) % HIST);
+    HIPCHK(s, hipEventSynchronize(s->hist_ev[slot]));
+    last = s->cycles_host[slot];
+    drift = s->drift_host + 8 * slot;
+  }
+  *mask = sort_mask(s, drift);
+  *cycles = step_cycles(s, last);
+  return CPIC_OK;
+}
+
+// Host bookkeeping after a step's launches: sort counters, and the step's
+// record (solver cycles, drift) copied back for step n + 2.
+static cpic_status step_record(cpic_sim* s, unsigned mask, long long n) {
+  for (size_t q = 0; q < s->sp.size(); ++q) {
+    Species& S = s->sp[q];
+    if (mask >> q & 1u) {
+      S.since_sort = 0;
+      ++S.sorts;
+    } else {
+      ++S.since_sort;
+    }
+  }
+  const int slot = (int)(n % HIST);
+  HIPCHK(s, hipMemcpyAsync(s->cycles_host + slot, s->G.mg_flag + 1, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->drift_host + 8 * slot, s->drift_dev, sizeof(unsigned) * s->sp.size(),
+                           hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipEventRecord(s->hist_ev[slot], s->stream));
+  return CPIC_OK;
+}
+
+static cpic_status step_checks(cpic_sim* s) {
   if (s->poisoned) return fail(s, CPIC_E_STATE, "simulation poisoned by an earlier device error");
   if (!s->initialized) return fail(s, CPIC_E_STATE, "cpic_initialize has not been called");
   if (s->overflowed) return fail(s, CPIC_E_OVERFLOW, "an earlier fixed-point deposit wrapped");
+  return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_step(cpic_sim* s, int nsteps) {
+  if (!s || nsteps < 0) return CPIC_E_ARG;
+  const cpic_status chk = step_checks(s);
+  if (chk != CPIC_OK) return chk;
   for (int k = 0; k < nsteps; ++k) {
     ensure_sorted(s);
     StepEvents* ev = s->timing ? next_events(s) : nullptr;
     const bool inj = any_injection(s);
-    // the record of step n - 2 (the one before the step still in flight)
     const long long n = s->step;
-    int last = -1;
-    const unsigned* drift = nullptr;
-    if (n - 2 >= s->hist_from) {
-      const int slot = (int)((n - 2) % HIST);
-      HIPCHK(s, hipEventSynchronize(s->hist_ev[slot]));
-      last = s->cycles_host[slot];
-      drift = s->drift_host + 8 * slot;
-    }
-    const unsigned mask = sort_mask(s, drift);
-    const int cycles = step_cycles(s, last);
+    unsigned mask = 0;
+    int cycles = 0;
+    cpic_status rc = step_prelude(s, &mask, &cycles);
+    if (rc != CPIC_OK) return rc;
     // injection draws depend on the step number, a kernel argument: no graphs
     if (!(s->graphs && !inj && graph_step(s, mask, cycles, ev))) step_body(s, ev, inj, mask, cycles);
-    for (size_t q = 0; q < s->sp.size(); ++q) {
-      Species& S = s->sp[q];
-      if (mask >> q & 1u) {
-        S.since_sort = 0;
-        ++S.sorts;
-      } else {
-        ++S.since_sort;
-      }
-    }
-    // this step's record
-    const int slot = (int)(n % HIST);
-    HIPCHK(s, hipMemcpyAsync(s->cycles_host + slot, s->G.mg_flag + 1, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipMemcpyAsync(s->drift_host + 8 * slot, s->drift_dev, sizeof(unsigned) * s->sp.size(),
-                             hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipEventRecord(s->hist_ev[slot], s->stream));
+    rc = step_record(s, mask, n);
+    if (rc != CPIC_OK) return rc;
   }
   return check_async(s);
+}
+
+// The field phases of simulations that share a grid shape can be batched:
+// FP32 particles, flexible CG with the point smoother (not the line
+// relaxation of strongly anisotropic operators), no floating wall, no
+// injection, on the same stream.
+static bool batchable(const cpic_sim* s) {
+  return s->grid.precision == CPIC_FP32 && s->grid.mg_method == CPIC_MG_FCG && !s->G.floating &&
+         s->G.anisotropy <= 50.0 && !any_injection(s) && s->G.kr != nullptr;
+}
+static bool same_shape(const cpic_sim* a, const cpic_sim* b) {
+  if (a->g.dim != b->g.dim || a->G.nlev != b->G.nlev || a->stream != b->stream) return false;
+  for (int k = 0; k < 3; ++k)
+    if (a->g.n[k] != b->g.n[k] || a->G.bc_lo[k] != b->G.bc_lo[k] || a->G.bc_hi[k] != b->G.bc_hi[k]) return false;
+  return a->G.restrict_transpose == b->G.restrict_transpose;
+}
+
+
+extern "C" cpic_status cpic_step_batch(cpic_sim* const* sims, int n, cpic_status* status) {
+  if (!sims || n < 1) return CPIC_E_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!sims[i]) return CPIC_E_ARG;
+    for (int j = 0; j < i; ++j)
+      if (sims[j] == sims[i]) return fail(sims[i], CPIC_E_ARG, "a simulation appears twice in the batch");
+  }
+  cpic_status first = CPIC_OK;
+  auto report = [&](int i, cpic_status rc) {
+    if (status) status[i] = rc;
+    if (first == CPIC_OK) first = rc;
+  };
+  // the cases that pass the checks step; the others keep their state
+  std::vector<int> idx;
+  for (int i = 0; i < n; ++i) {
+    const cpic_status rc = step_checks(sims[i]);
+    if (status) status[i] = rc;
+    if (rc != CPIC_OK)
+      report(i, rc);
+    else
+      idx.push_back(i);
+  }
+  const int m = (int)idx.size();
+  bool batch = m > 1;
+  for (int i = 0; i < m && batch; ++i) batch = batchable(sims[idx[i]]) && same_shape(sims[idx[i]], sims[idx[0]]);
+  if (!batch) {
+    for (int i : idx) {
+      const cpic_status rc = cpic_step(sims[i], 1);
+      if (rc != CPIC_OK) report(i, rc);
+    }
+    return first;
+  }
+  std::vector<cpic_sim*> S((size_t)m);
+  for (int i = 0; i < m; ++i) S[i] = sims[idx[i]];
+  // a failure past this point (a runtime error) is reported for every case of the batch
+  auto fail_all = [&](cpic_status rc) {
+    for (int i : idx) report(i, rc);
+    return first;
+  };
+  std::vector<unsigned> mask((size_t)m);
+  std::vector<int> cycles((size_t)m);
+  std::vector<long long> step0((size_t)m);
+  std::vector<StepEvents*> ev((size_t)m);
+  int launch = 0;
+  for (int i = 0; i < m; ++i) {
+    ensure_sorted(S[i]);
+    ev[i] = S[i]->timing ? next_events(S[i]) : nullptr;
+    step0[i] = S[i]->step;
+    const cpic_status rc = step_prelude(S[i], &mask[i], &cycles[i]);
+    if (rc != CPIC_OK) return fail_all(rc);
+    launch = std::max(launch, cycles[i]);
+  }
+  for (int i = 0; i < m; ++i) particle_phase(S[i], ev[i], false, mask[i]);
+  // the field phases: recorded case by case, replayed as one launch per kernel
+  std::vector<BatchRecorder> recs((size_t)m);
+  std::vector<BatchRecorder*> rp((size_t)m);
+  std::vector<int> prev((size_t)m);
+  for (int i = 0; i < m; ++i) {
+    prev[i] = S[i]->phi_prev_valid ? 1 : 0;
+    g_batch_rec = &recs[i];
+    field_phase(S[i], launch, cycles[i]);
+    g_batch_rec = nullptr;
+    rp[i] = &recs[i];
+  }
+  const int rr = replay_batch(rp.data(), m, S[0]->batch_args, S[0]->stream);
+  if (rr == -3) {
+    for (int i = 0; i < m; ++i) S[i]->poisoned = true;
+    return fail_all(fail(S[0], CPIC_E_HIP, "batched field phase: runtime error"));
+  }
+  if (rr != 0) {
+    // the cases recorded different sequences, or no memory for the batch's
+    // arguments: their field phases one by one
+    for (int i = 0; i < m; ++i) {
+      S[i]->phi_prev_valid = prev[i] != 0;
+      field_phase(S[i], cycles[i], cycles[i]);
+    }
+  } else {
+    for (int i = 0; i < m; ++i) ++S[i]->batched_steps;
+  }
+  for (int i = 0; i < m; ++i) {
+    step_end(S[i], ev[i], mask[i]);
+    const cpic_status rc = step_record(S[i], mask[i], step0[i]);
+    if (rc != CPIC_OK) return fail_all(rc);
+  }
+  for (int i = 0; i < m; ++i) {
+    const cpic_status rc = check_async(S[i]);
+    if (rc != CPIC_OK) return fail_all(rc);
+  }
+  return first;
+}
+
+extern "C" cpic_status cpic_set_stream(cpic_sim* s, void* hip_stream) {
+  if (!s) return CPIC_E_ARG;
+  // work already queued finishes first: everything after runs on the new stream
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  s->stream = (hipStream_t)hip_stream;
+  return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_batch_signature(const cpic_sim* s, uint64_t* sig) {
+  if (!s || !sig) return CPIC_E_ARG;
+  *sig = 0;
+  if (!batchable(s)) return CPIC_OK;
+  // what same_shape compares, hashed (FNV-1a); never 0
+  int words[16] = {s->g.dim, s->G.nlev, s->G.restrict_transpose};
+  int k = 3;
+  for (int a = 0; a < 3; ++a) {
+    words[k++] = s->g.n[a];
+    words[k++] = s->G.bc_lo[a];
+    words[k++] = s->G.bc_hi[a];
+  }
+  uint64_t h = 1469598103934665603ull;
+  const unsigned char* b = (const unsigned char*)words;
+  for (size_t i = 0; i < sizeof(int) * (size_t)k; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  *sig = h | 1u;
+  return CPIC_OK;
 }
 
 extern "C" cpic_status cpic_set_graphs(cpic_sim* s, int enable) {
@@ -1374,6 +1569,7 @@ static cpic_status diag_impl(cpic_sim* s, cpic_diag* out, const DiagScratch& sc)
   out->step = s->step;
   out->nspecies = (int)s->sp.size();
   out->step_graphs = (int)s->step_graphs.size();
+  out->batched_steps = s->batched_steps;
   const int nsp = (int)s->sp.size();
   double ke = 0.0, we = 0.0, sc2[2] = {0, 0}, wall[2] = {0, 0};
   int fl[2] = {0, 0}, nonfinite = 0;
@@ -1516,6 +1712,7 @@ extern "C" void cpic_destroy(cpic_sim* s) {
   if (s->drift_host) (void)hipHostFree(s->drift_host);
   for (int i = 0; i < HIST; ++i)
     if (s->hist_ev[i]) (void)hipEventDestroy(s->hist_ev[i]);
+  free_batch_args(s->batch_args);
   for (auto& e : s->evs)
     for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e.e[i]);
   sim_free_all(s);

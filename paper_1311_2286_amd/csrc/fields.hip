@@ -21,6 +21,7 @@
 // kernels of later cycles return at once once the flag is set.
 #include <string.h>
 
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -102,7 +103,7 @@ __global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v, siz
 }
 
 void launch_fill_u8(void* p, unsigned char v, size_t bytes, hipStream_t st) {
-  if (bytes == 0) return;
+  if (bytes == 0 || batch_unsupported()) return;
   if (v == 0 && bytes % 8 == 0 && ((uintptr_t)p % 8) == 0) {
     size_t n = bytes / 8;
     unsigned blocks = (unsigned)((n + 255) / 256);
@@ -113,6 +114,75 @@ void launch_fill_u8(void* p, unsigned char v, size_t bytes, hipStream_t st) {
   unsigned blocks = (unsigned)((bytes + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(fill_u8_kernel, dim3(blocks), dim3(256), 0, st, (unsigned char*)p, v, bytes);
+}
+
+// Block coordinates and grid extent of one case's launch: its own launch, or
+// its slice of a batched launch (cases stacked along z).
+struct Blk {
+  int x, y, z, gx, gy, gz;
+};
+__device__ inline Blk blk_single() {
+  return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, (int)gridDim.x, (int)gridDim.y, (int)gridDim.z};
+}
+__device__ inline Blk blk_batch(int gz) {
+  return {(int)blockIdx.x, (int)blockIdx.y, (int)(blockIdx.z % gz), (int)gridDim.x, (int)gridDim.y, gz};
+}
+
+// kinds of the batched field-phase kernels (record tags)
+enum BatchKind : int {
+  BK_CHARGE = 1, BK_EXTRAP, BK_RHS, BK_SUB, BK_REDP, BK_REDF, BK_RESET, BK_FCGRES, BK_FCGAPPLY, BK_FCGCOEF,
+  BK_FCGUPD, BK_SMOOTH_F, BK_SMOOTH_D, BK_RESID_F, BK_RESID_D, BK_RSUM_F, BK_RSUM_D, BK_RTR_F, BK_RTR_D,
+  BK_PROL_F, BK_PROL_D, BK_SMALL_F, BK_SMALL_D, BK_EF2F, BK_EF2D, BK_EF3F, BK_EF3D, BK_COUNT
+};
+template <typename T>
+constexpr int kind_of(int kf, int kd) {
+  return std::is_same<T, float>::value ? kf : kd;
+}
+
+// Kernels of the field phase as ops: an argument struct and a body that takes
+// the case's block coordinates, launched alone or batched (see kernels.hpp).
+template <typename Op>
+__global__ __launch_bounds__(256) void op_single256(typename Op::Args a) {
+  Op::body(a, blk_single());
+}
+template <typename Op>
+__global__ __launch_bounds__(256) void op_batch256(const typename Op::Args* __restrict__ a, int gz) {
+  Op::body(a[blockIdx.z / gz], blk_batch(gz));
+}
+template <typename Op>
+__global__ __launch_bounds__(1024) void op_single1024(typename Op::Args a) {
+  Op::body(a, blk_single());
+}
+template <typename Op>
+__global__ __launch_bounds__(1024) void op_batch1024(const typename Op::Args* __restrict__ a, int gz) {
+  Op::body(a[blockIdx.z / gz], blk_batch(gz));
+}
+
+thread_local BatchRecorder* g_batch_rec = nullptr;
+
+template <typename Op>
+static void op_launch(dim3 grid, dim3 block, const typename Op::Args& a, hipStream_t st) {
+  if (g_batch_rec) {
+    BatchRec r;
+    r.kind = Op::KIND;
+    r.grid = grid;
+    r.block = block;
+    r.args.assign((const unsigned char*)&a, (const unsigned char*)&a + sizeof(a));
+    g_batch_rec->recs.push_back(std::move(r));
+    return;
+  }
+  if (Op::BOUND == 1024)
+    hipLaunchKernelGGL(op_single1024<Op>, grid, block, 0, st, a);
+  else
+    hipLaunchKernelGGL(op_single256<Op>, grid, block, 0, st, a);
+}
+template <typename Op>
+static void op_replay(dim3 grid, dim3 block, const void* args, int n, hipStream_t st) {
+  const dim3 g(grid.x, grid.y, grid.z * (unsigned)n);
+  if (Op::BOUND == 1024)
+    hipLaunchKernelGGL(op_batch1024<Op>, g, block, 0, st, (const typename Op::Args*)args, (int)grid.z);
+  else
+    hipLaunchKernelGGL(op_batch256<Op>, g, block, 0, st, (const typename Op::Args*)args, (int)grid.z);
 }
 
 // ----------------------------------------------------------------------------
@@ -411,9 +481,23 @@ void launch_background(const GridCtx& G, int shape, double n0, hipStream_t st) {
 // ----------------------------------------------------------------------------
 // charge per cell: sum_s q_s w_s Q_s (integer Q scaled by 2^-d S1) + background
 // ----------------------------------------------------------------------------
-__global__ void charge_kernel(long long nc, ChargeSpecies cs, const double* bg, double bgq,
-                              double* charge) {
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+struct charge_kernelOp {
+  static constexpr int KIND = BK_CHARGE, BOUND = 256;
+  struct Args {
+    long long nc;
+    ChargeSpecies cs;
+    const double* bg;
+    double bgq;
+    double* charge;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    long long nc = k_.nc;
+    const ChargeSpecies& cs = k_.cs;
+    const double* bg = k_.bg;
+    double bgq = k_.bgq;
+    double* charge = k_.charge;
+
+  long long c = (long long)b_.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   double s = 0.0;
   for (int k = 0; k < cs.n; ++k) {
@@ -423,12 +507,13 @@ __global__ void charge_kernel(long long nc, ChargeSpecies cs, const double* bg, 
   }
   if (bg) s = s + bgq * bg[c];
   charge[c] = s;
-}
+
+  }
+};
 
 void launch_charge(const GridCtx& G, const ChargeSpecies& cs, double bg_charge, hipStream_t st) {
   unsigned blocks = (unsigned)((G.g.ncells + 255) / 256);
-  hipLaunchKernelGGL(charge_kernel, dim3(blocks), dim3(256), 0, st, G.g.ncells, cs, G.background,
-                     bg_charge, G.charge);
+  op_launch<charge_kernelOp>(dim3(blocks), dim3(256), charge_kernelOp::Args{G.g.ncells, cs, G.background, bg_charge, G.charge}, st);
 }
 
 // ----------------------------------------------------------------------------
@@ -467,10 +552,10 @@ constexpr int XCD_PLANE_TILES = 64;
 struct Tile3 {
   int bx, by, bz, blk;
 };
-__device__ inline Tile3 xcd_tile() {
-  const int gx = gridDim.x, gy = gridDim.y;
-  const int nb = gx * gy * (int)gridDim.z;
-  const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+__device__ inline Tile3 xcd_tile(const Blk& B) {
+  const int gx = B.gx, gy = B.gy;
+  const int nb = gx * gy * B.gz;
+  const int b = B.x + gx * (B.y + gy * B.z);
   const int t = ((nb & 7) == 0 && gx * gy <= XCD_PLANE_TILES) ? (b & 7) * (nb >> 3) + (b >> 3) : b;
   Tile3 r;
   r.bx = t % gx;
@@ -479,27 +564,65 @@ __device__ inline Tile3 xcd_tile() {
   r.blk = t;
   return r;
 }
+__device__ inline Tile3 xcd_tile() { return xcd_tile(blk_single()); }
+
 
 // kind 0: sum a*b; kind 1: sum a; kind 2: sum a*a
-__global__ __launch_bounds__(256) void reduce_partial_kernel(const double* a, const double* b, long long n,
-                                                             int kind, double* partials,
-                                                             const int* flag) {
+struct reduce_partial_kernelOp {
+  static constexpr int KIND = BK_REDP, BOUND = 256;
+  struct Args {
+    const double* a;
+    const double* b;
+    long long n;
+    int kind;
+    double* partials;
+    const int* flag;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    const double* a = k_.a;
+    const double* b = k_.b;
+    long long n = k_.n;
+    int kind = k_.kind;
+    double* partials = k_.partials;
+    const int* flag = k_.flag;
+
   if (flag && flag[0]) return;
   double s = 0.0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
+  for (long long i = (long long)b_.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)b_.gx * blockDim.x) {
     double x = a[i];
     s += (kind == 0) ? x * b[i] : (kind == 1 ? x : x * x);
   }
   double t = block_sum(s);
-  if (threadIdx.x == 0) partials[blockIdx.x] = t;
-}
+  if (threadIdx.x == 0) partials[b_.x] = t;
+
+  }
+};
 
 // op 0: out = sum; op 1: MG convergence test vs scalars[0] (|b|^2):
 //   sets flag[0] when sum <= rtol^2 |b|^2 (or |b| == 0), counts cycles in flag[1]
-__global__ __launch_bounds__(1024) void reduce_final_kernel(const double* partials, int nb, double* out,
-                                                           int op, double rtol2, const double* bnorm2,
-                                                           int* flag, int count_cycle) {
+struct reduce_final_kernelOp {
+  static constexpr int KIND = BK_REDF, BOUND = 1024;
+  struct Args {
+    const double* partials;
+    int nb;
+    double* out;
+    int op;
+    double rtol2;
+    const double* bnorm2;
+    int* flag;
+    int count_cycle;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    const double* partials = k_.partials;
+    int nb = k_.nb;
+    double* out = k_.out;
+    int op = k_.op;
+    double rtol2 = k_.rtol2;
+    const double* bnorm2 = k_.bnorm2;
+    int* flag = k_.flag;
+    int count_cycle = k_.count_cycle;
+
   if (op == 1 && flag[0]) return;
   double s = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partials[i];
@@ -510,40 +633,70 @@ __global__ __launch_bounds__(1024) void reduce_final_kernel(const double* partia
     if (op == 1) {
       if (count_cycle) flag[1] += 1;
       if (t <= rtol2 * (*bnorm2) || *bnorm2 == 0.0) flag[0] = 1;
+      if (count_cycle && flag[1] >= flag[2]) flag[0] = 1;  // the solve's cycle budget is spent
     }
   }
-}
+
+  }
+};
 
 static void reduce(const double* a, const double* b, long long n, int kind, double* partials, double* out,
                    hipStream_t st) {
-  hipLaunchKernelGGL(reduce_partial_kernel, dim3(RED_BLOCKS), dim3(256), 0, st, a, b, n, kind, partials,
-                     (const int*)nullptr);
-  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, partials, RED_BLOCKS, out, 0, 0.0,
-                     (const double*)nullptr, (int*)nullptr, 0);
+  op_launch<reduce_partial_kernelOp>(dim3(RED_BLOCKS), dim3(256), reduce_partial_kernelOp::Args{a, b, n, kind, partials, (const int*)nullptr}, st);
+  op_launch<reduce_final_kernelOp>(dim3(1), dim3(256), reduce_final_kernelOp::Args{partials, RED_BLOCKS, out, 0, 0.0, (const double*)nullptr, (int*)nullptr, 0}, st);
 }
 
 // ----------------------------------------------------------------------------
 // right-hand side: b = -charge - bdir, projected to zero sum when singular
 // ----------------------------------------------------------------------------
-__global__ void rhs_kernel(long long nc, const double* charge, const double* bdir, double* rhs) {
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+struct rhs_kernelOp {
+  static constexpr int KIND = BK_RHS, BOUND = 256;
+  struct Args {
+    long long nc;
+    const double* charge;
+    const double* bdir;
+    double* rhs;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    long long nc = k_.nc;
+    const double* charge = k_.charge;
+    const double* bdir = k_.bdir;
+    double* rhs = k_.rhs;
+
+  long long c = (long long)b_.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   rhs[c] = -charge[c] - bdir[c];
-}
-__global__ void sub_scalar_kernel(long long n, double* x, const double* s, double scale) {
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+
+  }
+};
+struct sub_scalar_kernelOp {
+  static constexpr int KIND = BK_SUB, BOUND = 256;
+  struct Args {
+    long long n;
+    double* x;
+    const double* s;
+    double scale;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    long long n = k_.n;
+    double* x = k_.x;
+    const double* s = k_.s;
+    double scale = k_.scale;
+
+  long long c = (long long)b_.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   x[c] -= (*s) * scale;
-}
+
+  }
+};
 
 void launch_rhs(const GridCtx& G, hipStream_t st) {
   const Level& L = G.lev[0];
   unsigned blocks = (unsigned)((L.ncells + 255) / 256);
-  hipLaunchKernelGGL(rhs_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, G.charge, G.bdir, L.rhs);
+  op_launch<rhs_kernelOp>(dim3(blocks), dim3(256), rhs_kernelOp::Args{L.ncells, G.charge, G.bdir, L.rhs}, st);
   if (G.all_periodic) {
     reduce(L.rhs, nullptr, L.ncells, 1, G.partials, G.scalars + 3, st);
-    hipLaunchKernelGGL(sub_scalar_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, L.rhs, G.scalars + 3,
-                       1.0 / (double)L.ncells);
+    op_launch<sub_scalar_kernelOp>(dim3(blocks), dim3(256), sub_scalar_kernelOp::Args{L.ncells, L.rhs, G.scalars + 3, 1.0 / (double)L.ncells}, st);
   }
 }
 
@@ -598,11 +751,34 @@ __device__ inline T apply_A(const LevelArgsT<T>& a, const TV* __restrict__ phi_i
 // With partials != null the squared residual of the input is summed per block
 // (fixed order) for the convergence test.
 template <typename T>
-__global__ __launch_bounds__(256) void smooth_kernel(LevelArgsT<T> a, const T* __restrict__ phi,
-                                                     const T* __restrict__ rhs, T* out, double cr, double cd,
-                                                     const T* dprev, T* dout, const int* flag, double* partials) {
+struct smooth_kernelOp {
+  static constexpr int KIND = kind_of<T>(BK_SMOOTH_F, BK_SMOOTH_D), BOUND = 256;
+  struct Args {
+    LevelArgsT<T> a;
+    const T* phi;
+    const T* rhs;
+    T* out;
+    double cr;
+    double cd;
+    const T* dprev;
+    T* dout;
+    const int* flag;
+    double* partials;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    const LevelArgsT<T>& a = k_.a;
+    const T* __restrict__ phi = k_.phi;
+    const T* __restrict__ rhs = k_.rhs;
+    T* out = k_.out;
+    double cr = k_.cr;
+    double cd = k_.cd;
+    const T* dprev = k_.dprev;
+    T* dout = k_.dout;
+    const int* flag = k_.flag;
+    double* partials = k_.partials;
+
   if (flag[0]) return;
-  const Tile3 T3 = xcd_tile();
+  const Tile3 T3 = xcd_tile(b_);
   const int i = T3.bx * blockDim.x + threadIdx.x;
   const int j = T3.by * blockDim.y + threadIdx.y;
   const int k = T3.bz;
@@ -622,7 +798,9 @@ __global__ __launch_bounds__(256) void smooth_kernel(LevelArgsT<T> a, const T* _
     if (threadIdx.x == 0 && threadIdx.y == 0)
       partials[T3.blk] = t;
   }
-}
+
+  }
+};
 
 // Line relaxation on segments (anisotropic operators): every thread owns a
 // run of LINE_SEG consecutive cells along axis `ax`; the residual
@@ -794,10 +972,24 @@ __global__ __launch_bounds__(256) void gershgorin_kernel(LevelArgs a, double* ou
 
 // residual r = rhs - A phi (coalesced pass over the fine level)
 template <typename T>
-__global__ __launch_bounds__(256) void residual_kernel(LevelArgsT<T> a, const T* __restrict__ phi,
-                                                       const T* __restrict__ rhs, T* res, const int* flag) {
+struct residual_kernelOp {
+  static constexpr int KIND = kind_of<T>(BK_RESID_F, BK_RESID_D), BOUND = 256;
+  struct Args {
+    LevelArgsT<T> a;
+    const T* phi;
+    const T* rhs;
+    T* res;
+    const int* flag;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    const LevelArgsT<T>& a = k_.a;
+    const T* __restrict__ phi = k_.phi;
+    const T* __restrict__ rhs = k_.rhs;
+    T* res = k_.res;
+    const int* flag = k_.flag;
+
   if (flag[0]) return;
-  const Tile3 T3 = xcd_tile();
+  const Tile3 T3 = xcd_tile(b_);
   const int i = T3.bx * blockDim.x + threadIdx.x;
   const int j = T3.by * blockDim.y + threadIdx.y;
   const int k = T3.bz;
@@ -805,7 +997,9 @@ __global__ __launch_bounds__(256) void residual_kernel(LevelArgsT<T> a, const T*
   const int idx[3] = {i, j, k};
   const int c = i + a.n[0] * (j + a.n[1] * k);
   res[c] = rhs[c] - apply_A(a, phi, idx, c);
-}
+
+  }
+};
 
 // Two restrictions.  Summing the 2^d children's residuals is the cheaper and,
 // on near-isotropic grids, the faster one; but with the bilinear prolongation
@@ -833,11 +1027,33 @@ __device__ inline T restrict_cell(const LevelArgsT<T>& fa, const T* __restrict__
 
 // summing restriction of a residual array (multi-workgroup levels)
 template <typename T>
-__global__ __launch_bounds__(256) void restrict_sum_kernel(int dim, int nf0, int nf1, const T* __restrict__ res,
-                                                           int nc0, int nc1, T* crhs, T* cphi, const int* flag) {
+struct restrict_sum_kernelOp {
+  static constexpr int KIND = kind_of<T>(BK_RSUM_F, BK_RSUM_D), BOUND = 256;
+  struct Args {
+    int dim;
+    int nf0;
+    int nf1;
+    const T* res;
+    int nc0;
+    int nc1;
+    T* crhs;
+    T* cphi;
+    const int* flag;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    int dim = k_.dim;
+    int nf0 = k_.nf0;
+    int nf1 = k_.nf1;
+    const T* __restrict__ res = k_.res;
+    int nc0 = k_.nc0;
+    int nc1 = k_.nc1;
+    T* crhs = k_.crhs;
+    T* cphi = k_.cphi;
+    const int* flag = k_.flag;
+
   if (flag[0]) return;
-  const int I0 = blockIdx.x * blockDim.x + threadIdx.x, I1 = blockIdx.y * blockDim.y + threadIdx.y;
-  const int I2 = blockIdx.z;
+  const int I0 = b_.x * blockDim.x + threadIdx.x, I1 = b_.y * blockDim.y + threadIdx.y;
+  const int I2 = b_.z;
   if (I0 >= nc0 || I1 >= nc1) return;
   const int C = I0 + nc0 * (I1 + nc1 * I2);
   const int f = 2 * I0 + nf0 * (2 * I1 + nf1 * (dim == 3 ? 2 * I2 : 0));
@@ -848,7 +1064,9 @@ __global__ __launch_bounds__(256) void restrict_sum_kernel(int dim, int nf0, int
   }
   crhs[C] = s;
   cphi[C] = (T)0;
-}
+
+  }
+};
 
 // Transpose of the prolongation:  Per axis, coarse
 // cell I receives from fine cells 2I and 2I+1 with weight 3/4 and from 2I-1
@@ -903,18 +1121,40 @@ __device__ inline T restrict_transpose(const LevelArgsT<T>& fa, const T* __restr
 
 // coarse rhs = P^T (fine residual); coarse phi = 0
 template <typename T>
-__global__ __launch_bounds__(256) void restrict_kernel(LevelArgsT<T> fa, const T* __restrict__ res, int nc0, int nc1,
-                                                       int nc2, T* crhs, T* cphi, const int* flag) {
+struct restrict_kernelOp {
+  static constexpr int KIND = kind_of<T>(BK_RTR_F, BK_RTR_D), BOUND = 256;
+  struct Args {
+    LevelArgsT<T> fa;
+    const T* res;
+    int nc0;
+    int nc1;
+    int nc2;
+    T* crhs;
+    T* cphi;
+    const int* flag;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    const LevelArgsT<T>& fa = k_.fa;
+    const T* __restrict__ res = k_.res;
+    int nc0 = k_.nc0;
+    int nc1 = k_.nc1;
+    int nc2 = k_.nc2;
+    T* crhs = k_.crhs;
+    T* cphi = k_.cphi;
+    const int* flag = k_.flag;
+
   if (flag[0]) return;
-  const int I0 = blockIdx.x * blockDim.x + threadIdx.x, I1 = blockIdx.y * blockDim.y + threadIdx.y;
-  const int I2 = blockIdx.z;
+  const int I0 = b_.x * blockDim.x + threadIdx.x, I1 = b_.y * blockDim.y + threadIdx.y;
+  const int I2 = b_.z;
   if (I0 >= nc0 || I1 >= nc1) return;
   const int cn[3] = {nc0, nc1, nc2};
   const int I[3] = {I0, I1, I2};
   const int C = I0 + nc0 * (I1 + nc1 * I2);
   crhs[C] = restrict_transpose(fa, res, cn, I);
   cphi[C] = (T)0;
-}
+
+  }
+};
 
 // (3/4, 1/4)-tensor interpolation of the coarse correction at fine cell idx
 template <typename T>
@@ -963,16 +1203,36 @@ __device__ inline T prolong_cell(const LevelArgsT<T>& fa, const T* __restrict__ 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void prolong_kernel(LevelArgsT<T> fa, T* phi, const T* __restrict__ cphi, int nc0,
-                                                      int nc1, int nc2, const int* flag) {
+struct prolong_kernelOp {
+  static constexpr int KIND = kind_of<T>(BK_PROL_F, BK_PROL_D), BOUND = 256;
+  struct Args {
+    LevelArgsT<T> fa;
+    T* phi;
+    const T* cphi;
+    int nc0;
+    int nc1;
+    int nc2;
+    const int* flag;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    const LevelArgsT<T>& fa = k_.fa;
+    T* phi = k_.phi;
+    const T* __restrict__ cphi = k_.cphi;
+    int nc0 = k_.nc0;
+    int nc1 = k_.nc1;
+    int nc2 = k_.nc2;
+    const int* flag = k_.flag;
+
   if (flag[0]) return;
   const int cn[3] = {nc0, nc1, nc2};
-  const int idx[3] = {(int)(blockIdx.x * blockDim.x + threadIdx.x), (int)(blockIdx.y * blockDim.y + threadIdx.y),
-                      (int)blockIdx.z};
+  const int idx[3] = {(int)(b_.x * blockDim.x + threadIdx.x), (int)(b_.y * blockDim.y + threadIdx.y),
+                      (int)b_.z};
   if (idx[0] >= fa.n[0] || idx[1] >= fa.n[1]) return;
   const int c = idx[0] + fa.n[0] * (idx[1] + fa.n[1] * idx[2]);
   phi[c] += prolong_cell(fa, cphi, cn, idx);
-}
+
+  }
+};
 
 // The V-cycle below level ls (all levels of at most SMALL_CELLS cells) in one
 // workgroup: smoothing, restriction, coarsest solve (conjugate gradients, in
@@ -1163,8 +1423,24 @@ __device__ inline void block_smooth(const LevelArgsT<T>& a, const T* phi, const 
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels<T> S, int nu1, int nu2, double coarse_tol2,
-                                                            int singular, const int* flag) {
+struct small_vcycle_kernelOp {
+  static constexpr int KIND = kind_of<T>(BK_SMALL_F, BK_SMALL_D), BOUND = 1024;
+  struct Args {
+    SmallLevels<T> S;
+    int nu1;
+    int nu2;
+    double coarse_tol2;
+    int singular;
+    const int* flag;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    const SmallLevels<T>& S = k_.S;
+    int nu1 = k_.nu1;
+    int nu2 = k_.nu2;
+    double coarse_tol2 = k_.coarse_tol2;
+    int singular = k_.singular;
+    const int* flag = k_.flag;
+
   if (flag[0]) return;
   const T omega = (T)0.8;
   const int last = S.nl - 1;
@@ -1251,7 +1527,9 @@ __global__ __launch_bounds__(1024) void small_vcycle_kernel(SmallLevels<T> S, in
       block_smooth(a, S.phi2[l], S.rhs[l], S.phi[l], omega);
     }
   }
-}
+
+  }
+};
 
 __global__ void residual_norm_kernel(LevelArgs a, const double* __restrict__ phi,
                                      const double* __restrict__ rhs, double* partials,
@@ -1273,10 +1551,22 @@ __global__ void residual_norm_kernel(LevelArgs a, const double* __restrict__ phi
     partials[T3.blk] = t;
 }
 
-__global__ void mg_reset_kernel(int* flag) {
-  flag[0] = 0;
-  flag[1] = 0;
-}
+// start of a solve: not converged, no cycle done, at most `cap` cycles (a
+// solve launched with more, as a batch of cases launches the largest count,
+// stops at its own)
+struct mg_reset_kernelOp {
+  static constexpr int KIND = BK_RESET, BOUND = 256;
+  struct Args {
+    int* flag;
+    int cap;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    int* flag = k_.flag;
+    flag[0] = 0;
+    flag[1] = 0;
+    flag[2] = k_.cap;
+  }
+};
 
 static dim3 grid3(const Level& L) {
   return dim3((unsigned)((L.n[0] + 63) / 64), (unsigned)((L.n[1] + 3) / 4), (unsigned)L.n[2]);
@@ -1401,14 +1691,12 @@ static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStre
     }
     const bool last = s + 1 == nu;
     double* pp = last ? partials : (s == 0 ? first_partials : nullptr);
-    hipLaunchKernelGGL(smooth_kernel<T>, gr, BLOCK3, 0, st, a, in, (const T*)v.rhs, out, cr, cd,
-                       (const T*)(s == 0 ? nullptr : v.aux), last ? (T*)nullptr : v.aux, (const int*)G.mg_flag, pp);
+    op_launch<smooth_kernelOp<T>>(gr, BLOCK3, typename smooth_kernelOp<T>::Args{a, in, (const T*)v.rhs, out, cr, cd, (const T*)(s == 0 ? nullptr : v.aux), last ? (T*)nullptr : v.aux, (const int*)G.mg_flag, pp}, st);
     if (s == 0 && first_partials) {
       // the residual entering the first step is the solve's initial residual:
       // stop here when the initial guess already meets the tolerance
       const int nblk = (int)(gr.x * gr.y * gr.z);
-      hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(1024), 0, st, (const double*)first_partials, nblk,
-                         G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 0);
+      op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{(const double*)first_partials, nblk, G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 0}, st);
     }
   }
 }
@@ -1434,7 +1722,7 @@ __global__ __launch_bounds__(256) void anisotropy_kernel(LevelArgs a, unsigned* 
 int compute_smoother_bounds(GridCtx& G, hipStream_t st) {
   {
     const Level& L = G.lev[0];
-    unsigned* tmp = (unsigned*)G.mg_flag + 2;
+    unsigned* tmp = (unsigned*)G.mg_flag + 3;  // scratch word ([2] is the cycle budget of a solve)
     launch_fill_u8(tmp, 0, sizeof(unsigned), st);
     hipLaunchKernelGGL(anisotropy_kernel, dim3((unsigned)((L.ncells + 255) / 256)), dim3(256), 0, st, level_args(G, 0),
                        tmp);
@@ -1465,24 +1753,40 @@ int compute_smoother_bounds(GridCtx& G, hipStream_t st) {
 
 // phi <- 2 phi - prev, prev <- old phi (linear extrapolation in time of the
 // initial guess); with extrapolate = 0 only prev <- phi.
-__global__ void extrapolate_kernel(long long n, double* phi, double* prev, int extrapolate) {
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+struct extrapolate_kernelOp {
+  static constexpr int KIND = BK_EXTRAP, BOUND = 256;
+  struct Args {
+    long long n;
+    double* phi;
+    double* prev;
+    int extrapolate;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    long long n = k_.n;
+    double* phi = k_.phi;
+    double* prev = k_.prev;
+    int extrapolate = k_.extrapolate;
+
+  long long c = (long long)b_.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const double t = phi[c];
   if (extrapolate) phi[c] = 2.0 * t - prev[c];
   prev[c] = t;
-}
+
+  }
+};
 
 void launch_extrapolate_guess(const GridCtx& G, int extrapolate, hipStream_t st) {
   const Level& L = G.lev[0];
   unsigned blocks = (unsigned)((L.ncells + 255) / 256);
-  hipLaunchKernelGGL(extrapolate_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, L.phi, G.phi_prev, extrapolate);
+  op_launch<extrapolate_kernelOp>(dim3(blocks), dim3(256), extrapolate_kernelOp::Args{L.ncells, L.phi, G.phi_prev, extrapolate}, st);
 }
 
 // nu sweeps of segment line relaxation along every axis (phi -> phi2 -> phi ...;
 // nu * dim is even, so the result is back in phi)
 template <typename T>
 static void line_sweeps(const GridCtx& G, int l, int nu, bool reverse, hipStream_t st) {
+  if (batch_unsupported()) return;
   const Level& L = G.lev[l];
   const LevelArgsT<T> a = level_args_t<T>(G, l);
   const LevelVec<T> v = level_vec<T>(G, l);
@@ -1549,8 +1853,7 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
     // Inside a V-cycle the coarsest level needs only a modest relative residual
     // (1e-6); when it is the whole grid of an FP64 solve it is solved to 1e-13.
     const double coarse_tol2 = (l == 0 && S.nl == 1 && sizeof(T) == 8) ? 1e-26 : 1e-12;
-    hipLaunchKernelGGL(small_vcycle_kernel<T>, dim3(1), dim3(1024), 0, st, S, nu1, nu2, coarse_tol2,
-                       G.all_periodic, (const int*)G.mg_flag);
+    op_launch<small_vcycle_kernelOp<T>>(dim3(1), dim3(1024), typename small_vcycle_kernelOp<T>::Args{S, nu1, nu2, coarse_tol2, G.all_periodic, (const int*)G.mg_flag}, st);
     return;
   }
   const Level& L = G.lev[l];
@@ -1560,17 +1863,13 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
   smooth_level<T>(G, l, nu1, false, nullptr, st, first_partials, rtol2);
   const Level& C = G.lev[l + 1];
   const LevelVec<T> cv = level_vec<T>(G, l + 1);
-  hipLaunchKernelGGL(residual_kernel<T>, gr, BLOCK3, 0, st, a, (const T*)v.phi, (const T*)v.rhs, v.res,
-                     (const int*)G.mg_flag);
+  op_launch<residual_kernelOp<T>>(gr, BLOCK3, typename residual_kernelOp<T>::Args{a, (const T*)v.phi, (const T*)v.rhs, v.res, (const int*)G.mg_flag}, st);
   if (G.restrict_transpose)
-    hipLaunchKernelGGL(restrict_kernel<T>, grid3(C), BLOCK3, 0, st, a, (const T*)v.res, C.n[0], C.n[1], C.n[2],
-                       cv.rhs, cv.phi, (const int*)G.mg_flag);
+    op_launch<restrict_kernelOp<T>>(grid3(C), BLOCK3, typename restrict_kernelOp<T>::Args{a, (const T*)v.res, C.n[0], C.n[1], C.n[2], cv.rhs, cv.phi, (const int*)G.mg_flag}, st);
   else
-    hipLaunchKernelGGL(restrict_sum_kernel<T>, grid3(C), BLOCK3, 0, st, G.g.dim, L.n[0], L.n[1], (const T*)v.res,
-                       C.n[0], C.n[1], cv.rhs, cv.phi, (const int*)G.mg_flag);
+    op_launch<restrict_sum_kernelOp<T>>(grid3(C), BLOCK3, typename restrict_sum_kernelOp<T>::Args{G.g.dim, L.n[0], L.n[1], (const T*)v.res, C.n[0], C.n[1], cv.rhs, cv.phi, (const int*)G.mg_flag}, st);
   vcycle<T>(G, l + 1, nu1, nu2, nullptr, st);
-  hipLaunchKernelGGL(prolong_kernel<T>, gr, BLOCK3, 0, st, a, v.phi, (const T*)cv.phi, C.n[0], C.n[1], C.n[2],
-                     (const int*)G.mg_flag);
+  op_launch<prolong_kernelOp<T>>(gr, BLOCK3, typename prolong_kernelOp<T>::Args{a, v.phi, (const T*)cv.phi, C.n[0], C.n[1], C.n[2], (const int*)G.mg_flag}, st);
   smooth_level<T>(G, l, nu2, true, partials, st);
 }
 
@@ -1592,11 +1891,30 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
 // Level 0's FP32 vectors hold z (phi) and the FP32 copy of r (rhs).
 // Device scalars: [4] z.w  [5] q.z  [6] z.r  [7] p.q  [8] alpha  [9] beta.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void fcg_residual_kernel(LevelArgs a, const double* __restrict__ x,
-                                                           const double* __restrict__ b, double* r, float* r32,
-                                                           float* z, double* partials, const int* flag) {
+struct fcg_residual_kernelOp {
+  static constexpr int KIND = BK_FCGRES, BOUND = 256;
+  struct Args {
+    LevelArgs a;
+    const double* x;
+    const double* b;
+    double* r;
+    float* r32;
+    float* z;
+    double* partials;
+    const int* flag;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    const LevelArgs& a = k_.a;
+    const double* __restrict__ x = k_.x;
+    const double* __restrict__ b = k_.b;
+    double* r = k_.r;
+    float* r32 = k_.r32;
+    float* z = k_.z;
+    double* partials = k_.partials;
+    const int* flag = k_.flag;
+
   if (flag[0]) return;
-  const Tile3 T3 = xcd_tile();
+  const Tile3 T3 = xcd_tile(b_);
   const int i = T3.bx * blockDim.x + threadIdx.x;
   const int j = T3.by * blockDim.y + threadIdx.y;
   const int k = T3.bz;
@@ -1612,15 +1930,37 @@ __global__ __launch_bounds__(256) void fcg_residual_kernel(LevelArgs a, const do
   }
   const double t = block_sum(rr);
   if (threadIdx.x == 0 && threadIdx.y == 0) partials[T3.blk] = t;
-}
+
+  }
+};
 
 // w = A z and the block sums of z.w, q.z (first iteration: 0), z.r
-__global__ __launch_bounds__(256) void fcg_apply_kernel(LevelArgs a, const float* __restrict__ z,
-                                                        const double* __restrict__ r, const double* __restrict__ q,
-                                                        double* w, double* partials, int nblk, int first,
-                                                        const int* flag) {
+struct fcg_apply_kernelOp {
+  static constexpr int KIND = BK_FCGAPPLY, BOUND = 256;
+  struct Args {
+    LevelArgs a;
+    const float* z;
+    const double* r;
+    const double* q;
+    double* w;
+    double* partials;
+    int nblk;
+    int first;
+    const int* flag;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    const LevelArgs& a = k_.a;
+    const float* __restrict__ z = k_.z;
+    const double* __restrict__ r = k_.r;
+    const double* __restrict__ q = k_.q;
+    double* w = k_.w;
+    double* partials = k_.partials;
+    int nblk = k_.nblk;
+    int first = k_.first;
+    const int* flag = k_.flag;
+
   if (flag[0]) return;
-  const Tile3 T3 = xcd_tile();
+  const Tile3 T3 = xcd_tile(b_);
   const int i = T3.bx * blockDim.x + threadIdx.x;
   const int j = T3.by * blockDim.y + threadIdx.y;
   const int k = T3.bz;
@@ -1642,11 +1982,27 @@ __global__ __launch_bounds__(256) void fcg_apply_kernel(LevelArgs a, const float
   if (threadIdx.x == 0 && threadIdx.y == 0) partials[nblk + blk] = t;
   t = block_sum(zr);
   if (threadIdx.x == 0 && threadIdx.y == 0) partials[2 * nblk + blk] = t;
-}
+
+  }
+};
 
 // one workgroup: the three sums (fixed order), then beta, p.q and alpha
-__global__ __launch_bounds__(1024) void fcg_coef_kernel(const double* __restrict__ partials, int nblk, double* sc,
-                                                        int first, const int* flag) {
+struct fcg_coef_kernelOp {
+  static constexpr int KIND = BK_FCGCOEF, BOUND = 1024;
+  struct Args {
+    const double* partials;
+    int nblk;
+    double* sc;
+    int first;
+    const int* flag;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    const double* __restrict__ partials = k_.partials;
+    int nblk = k_.nblk;
+    double* sc = k_.sc;
+    int first = k_.first;
+    const int* flag = k_.flag;
+
   if (flag[0]) return;
   double v[3];
   for (int m = 0; m < 3; ++m) {
@@ -1668,18 +2024,46 @@ __global__ __launch_bounds__(1024) void fcg_coef_kernel(const double* __restrict
     sc[8] = pq != 0.0 ? zr / pq : 0.0;
     sc[9] = beta;
   }
-}
+
+  }
+};
 
 // p, q, x, r updated; the FP32 copy of r and a cleared z for the next V-cycle;
 // block sums of |r|^2
-__global__ __launch_bounds__(256) void fcg_update_kernel(LevelArgs a, const double* __restrict__ sc, float* z,
-                                                         double* p, const double* __restrict__ w, double* q,
-                                                         double* x, double* r, float* r32, int first,
-                                                         double* partials, const int* flag) {
+struct fcg_update_kernelOp {
+  static constexpr int KIND = BK_FCGUPD, BOUND = 256;
+  struct Args {
+    LevelArgs a;
+    const double* sc;
+    float* z;
+    double* p;
+    const double* w;
+    double* q;
+    double* x;
+    double* r;
+    float* r32;
+    int first;
+    double* partials;
+    const int* flag;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    const LevelArgs& a = k_.a;
+    const double* __restrict__ sc = k_.sc;
+    float* z = k_.z;
+    double* p = k_.p;
+    const double* __restrict__ w = k_.w;
+    double* q = k_.q;
+    double* x = k_.x;
+    double* r = k_.r;
+    float* r32 = k_.r32;
+    int first = k_.first;
+    double* partials = k_.partials;
+    const int* flag = k_.flag;
+
   if (flag[0]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
+  const int i = b_.x * blockDim.x + threadIdx.x;
+  const int j = b_.y * blockDim.y + threadIdx.y;
+  const int k = b_.z;
   double rr = 0.0;
   if (i < a.n[0] && j < a.n[1]) {
     const int c = i + a.n[0] * (j + a.n[1] * k);
@@ -1697,30 +2081,25 @@ __global__ __launch_bounds__(256) void fcg_update_kernel(LevelArgs a, const doub
     rr = rc * rc;
   }
   const double t = block_sum(rr);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = t;
-}
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[b_.x + b_.gx * (b_.y + b_.gy * b_.z)] = t;
+
+  }
+};
 
 static int launch_fcg_solve(const GridCtx& G, double rtol2, int max_iter, int nu1, int nu2, hipStream_t st) {
   const Level& L = G.lev[0];
   LevelArgs a = level_args(G, 0);
   const dim3 gr = grid3(L);
   const int nblk = (int)(gr.x * gr.y * gr.z);
-  hipLaunchKernelGGL(fcg_residual_kernel, gr, BLOCK3, 0, st, a, (const double*)L.phi, (const double*)L.rhs, G.kr,
-                     L.f_rhs, L.f_phi, G.mg_partials, (const int*)G.mg_flag);
-  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(1024), 0, st, (const double*)G.mg_partials, nblk,
-                     G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 0);
+  op_launch<fcg_residual_kernelOp>(gr, BLOCK3, fcg_residual_kernelOp::Args{a, (const double*)L.phi, (const double*)L.rhs, G.kr, L.f_rhs, L.f_phi, G.mg_partials, (const int*)G.mg_flag}, st);
+  op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{(const double*)G.mg_partials, nblk, G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 0}, st);
   for (int it = 0; it < max_iter; ++it) {
     const int first = it == 0;
     vcycle<float>(G, 0, nu1, nu2, nullptr, st);
-    hipLaunchKernelGGL(fcg_apply_kernel, gr, BLOCK3, 0, st, a, (const float*)L.f_phi, (const double*)G.kr,
-                       (const double*)G.kq, G.kw, G.k_partials, nblk, first, (const int*)G.mg_flag);
-    hipLaunchKernelGGL(fcg_coef_kernel, dim3(1), dim3(1024), 0, st, (const double*)G.k_partials, nblk, G.scalars,
-                       first, (const int*)G.mg_flag);
-    hipLaunchKernelGGL(fcg_update_kernel, gr, BLOCK3, 0, st, a, (const double*)G.scalars, L.f_phi, G.kp,
-                       (const double*)G.kw, G.kq, L.phi, G.kr, L.f_rhs, first, G.mg_partials,
-                       (const int*)G.mg_flag);
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(1024), 0, st, (const double*)G.mg_partials, nblk,
-                       G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 1);
+    op_launch<fcg_apply_kernelOp>(gr, BLOCK3, fcg_apply_kernelOp::Args{a, (const float*)L.f_phi, (const double*)G.kr, (const double*)G.kq, G.kw, G.k_partials, nblk, first, (const int*)G.mg_flag}, st);
+    op_launch<fcg_coef_kernelOp>(dim3(1), dim3(1024), fcg_coef_kernelOp::Args{(const double*)G.k_partials, nblk, G.scalars, first, (const int*)G.mg_flag}, st);
+    op_launch<fcg_update_kernelOp>(gr, BLOCK3, fcg_update_kernelOp::Args{a, (const double*)G.scalars, L.f_phi, G.kp, (const double*)G.kw, G.kq, L.phi, G.kr, L.f_rhs, first, G.mg_partials, (const int*)G.mg_flag}, st);
+    op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{(const double*)G.mg_partials, nblk, G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 1}, st);
   }
   return max_iter;
 }
@@ -1749,26 +2128,24 @@ void launch_operator_f32(const GridCtx& G, hipStream_t st) {
 // uses the updated residual; with plain V-cycles the test after a cycle uses
 // the residual entering its last sweep (an upper bound of the final one in
 // practice).
-int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st) {
+int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st, int cap) {
   const Level& L = G.lev[0];
   LevelArgs a = level_args(G, 0);
   const dim3 gr = grid3(L);
   const int nblk = (int)(gr.x * gr.y * gr.z);
-  hipLaunchKernelGGL(mg_reset_kernel, dim3(1), dim3(1), 0, st, G.mg_flag);
+  op_launch<mg_reset_kernelOp>(dim3(1), dim3(1), mg_reset_kernelOp::Args{G.mg_flag, cap > 0 ? cap : max_cycles}, st);
   // |b|^2
-  hipLaunchKernelGGL(reduce_partial_kernel, dim3(RED_BLOCKS), dim3(256), 0, st, L.rhs, (const double*)nullptr,
-                     L.ncells, 2, G.partials, (const int*)nullptr);
-  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, G.partials, RED_BLOCKS, G.scalars + 0, 0,
-                     0.0, (const double*)nullptr, (int*)nullptr, 0);
+  op_launch<reduce_partial_kernelOp>(dim3(RED_BLOCKS), dim3(256), reduce_partial_kernelOp::Args{L.rhs, (const double*)nullptr, L.ncells, 2, G.partials, (const int*)nullptr}, st);
+  op_launch<reduce_final_kernelOp>(dim3(1), dim3(256), reduce_final_kernelOp::Args{G.partials, RED_BLOCKS, G.scalars + 0, 0, 0.0, (const double*)nullptr, (int*)nullptr, 0}, st);
   const double rtol2 = rtol * rtol;
   if (G.kr) return launch_fcg_solve(G, rtol2, max_cycles, nu1, nu2, st);
+  if (batch_unsupported()) return max_cycles;
   const bool small = first_small_level(G) == 0;
   if (small) {
     // initial residual (on a multi-workgroup level 0 the first smoothing step
     // of the first cycle computes it)
     hipLaunchKernelGGL(residual_norm_kernel, gr, BLOCK3, 0, st, a, L.phi, L.rhs, G.mg_partials, G.mg_flag);
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(1024), 0, st, G.mg_partials, nblk, G.scalars + 1, 1,
-                       rtol2, G.scalars + 0, G.mg_flag, 0);
+    op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{G.mg_partials, nblk, G.scalars + 1, 1, rtol2, G.scalars + 0, G.mg_flag, 0}, st);
   }
   for (int cyc = 0; cyc < max_cycles; ++cyc) {
     if (small) {
@@ -1777,8 +2154,7 @@ int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int 
     } else {
       vcycle<double>(G, 0, nu1, nu2, G.mg_partials, st, cyc == 0 ? G.mg_partials : nullptr, rtol2);
     }
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(1024), 0, st, G.mg_partials, nblk, G.scalars + 1, 1,
-                       rtol2, G.scalars + 0, G.mg_flag, 1);
+    op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{G.mg_partials, nblk, G.scalars + 1, 1, rtol2, G.scalars + 0, G.mg_flag, 1}, st);
   }
   return max_cycles;
 }
@@ -1795,8 +2171,7 @@ void launch_gauge(const GridCtx& G, hipStream_t st) {
   const Level& L = G.lev[0];
   reduce(G.Jc, L.phi, L.ncells, 0, G.partials, G.scalars + 2, st);
   unsigned blocks = (unsigned)((L.ncells + 255) / 256);
-  hipLaunchKernelGGL(sub_scalar_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, L.phi, G.scalars + 2,
-                     1.0 / G.sumJ);
+  op_launch<sub_scalar_kernelOp>(dim3(blocks), dim3(256), sub_scalar_kernelOp::Args{L.ncells, L.phi, G.scalars + 2, 1.0 / G.sumJ}, st);
 }
 
 // ----------------------------------------------------------------------------
@@ -1918,10 +2293,24 @@ struct FieldBC {
 // directly; the others go through the boundary ghosts.  Both paths sum the
 // pairs in the same order.
 template <int d, typename R>
-__global__ __launch_bounds__(256) void efield_kernel(Geo g, FieldBC bc, const double* __restrict__ phi,
-                                                     const double* __restrict__ Kv, R* Ev) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
+struct efield_kernelOp {
+  static constexpr int KIND = (d == 3 ? kind_of<R>(BK_EF3F, BK_EF3D) : kind_of<R>(BK_EF2F, BK_EF2D)), BOUND = 256;
+  struct Args {
+    Geo g;
+    FieldBC bc;
+    const double* phi;
+    const double* Kv;
+    R* Ev;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    const Geo& g = k_.g;
+    const FieldBC& bc = k_.bc;
+    const double* __restrict__ phi = k_.phi;
+    const double* __restrict__ Kv = k_.Kv;
+    R* Ev = k_.Ev;
+
+  const int x = b_.x * blockDim.x + threadIdx.x, y = b_.y * blockDim.y + threadIdx.y;
+  const int z = b_.z;
   if (x >= g.nv[0] || y >= g.nv[1]) return;
   const int vi[3] = {x, y, z};
   const long long v = x + (long long)g.nv[0] * (y + (long long)g.nv[1] * z);
@@ -1978,7 +2367,9 @@ __global__ __launch_bounds__(256) void efield_kernel(Geo g, FieldBC bc, const do
     Ev[v * EC + b] = (R)e;
   }
   if (d == 3) Ev[v * EC + 3] = (R)0;
-}
+
+  }
+};
 
 void launch_efield(const GridCtx& G, hipStream_t st) {
   const Geo& g = G.g;
@@ -1993,16 +2384,16 @@ void launch_efield(const GridCtx& G, hipStream_t st) {
   const dim3 bl(64, 4, 1);
   if (g.dim == 3) {
     if (G.fp64)
-      hipLaunchKernelGGL((efield_kernel<3, double>), gr, bl, 0, st, g, bc, G.lev[0].phi, G.Kv, (double*)G.Ev);
+      op_launch<efield_kernelOp<3, double>>(gr, bl, efield_kernelOp<3, double>::Args{g, bc, G.lev[0].phi, G.Kv, (double*)G.Ev}, st);
     else
-      hipLaunchKernelGGL((efield_kernel<3, float>), gr, bl, 0, st, g, bc, G.lev[0].phi, G.Kv, (float*)G.Ev);
+      op_launch<efield_kernelOp<3, float>>(gr, bl, efield_kernelOp<3, float>::Args{g, bc, G.lev[0].phi, G.Kv, (float*)G.Ev}, st);
   } else {
     if (G.fp64)
-      hipLaunchKernelGGL((efield_kernel<2, double>), gr, bl, 0, st, g, bc, G.lev[0].phi, G.Kv, (double*)G.Ev);
+      op_launch<efield_kernelOp<2, double>>(gr, bl, efield_kernelOp<2, double>::Args{g, bc, G.lev[0].phi, G.Kv, (double*)G.Ev}, st);
     else
-      hipLaunchKernelGGL((efield_kernel<2, float>), gr, bl, 0, st, g, bc, G.lev[0].phi, G.Kv, (float*)G.Ev);
+      op_launch<efield_kernelOp<2, float>>(gr, bl, efield_kernelOp<2, float>::Args{g, bc, G.lev[0].phi, G.Kv, (float*)G.Ev}, st);
   }
-  if (G.floating) {
+  if (G.floating && !batch_unsupported()) {
     // E of phi_0 (wall at 0) plus phi_w times E of phi_1
     const long long n = (long long)g.nverts * (g.dim == 3 ? 4 : 2);
     const unsigned blocks = (unsigned)((n + 255) / 256);
@@ -2058,6 +2449,7 @@ __global__ void phi_full_kernel(long long n, const double* __restrict__ phi0, co
 }
 
 void launch_floating_wall(const GridCtx& G, const WallCharge& wc, hipStream_t st) {
+  if (batch_unsupported()) return;
   const Level& L = G.lev[0];
   hipLaunchKernelGGL(floating_wall_kernel, dim3(1), dim3(1024), 0, st, level_args(G, 0), (const double*)L.phi, wc,
                      G.scalars);
@@ -2183,6 +2575,132 @@ void launch_nonfinite_check(const void* x, long long n, int fp64, int* bad, hipS
     hipLaunchKernelGGL(nonfinite_kernel<double>, dim3(blocks), dim3(256), 0, st, (const double*)x, n, bad);
   else
     hipLaunchKernelGGL(nonfinite_kernel<float>, dim3(blocks), dim3(256), 0, st, (const float*)x, n, bad);
+}
+
+}  // namespace cpic
+
+namespace cpic {
+
+// ----------------------------------------------------------------------------
+// replay of recorded field phases as batched launches (see kernels.hpp)
+// ----------------------------------------------------------------------------
+static void replay_one(int kind, dim3 g, dim3 b, const void* a, int n, hipStream_t st) {
+  switch (kind) {
+    case BK_CHARGE: op_replay<charge_kernelOp>(g, b, a, n, st); break;
+    case BK_EXTRAP: op_replay<extrapolate_kernelOp>(g, b, a, n, st); break;
+    case BK_RHS: op_replay<rhs_kernelOp>(g, b, a, n, st); break;
+    case BK_SUB: op_replay<sub_scalar_kernelOp>(g, b, a, n, st); break;
+    case BK_REDP: op_replay<reduce_partial_kernelOp>(g, b, a, n, st); break;
+    case BK_REDF: op_replay<reduce_final_kernelOp>(g, b, a, n, st); break;
+    case BK_RESET: op_replay<mg_reset_kernelOp>(g, b, a, n, st); break;
+    case BK_FCGRES: op_replay<fcg_residual_kernelOp>(g, b, a, n, st); break;
+    case BK_FCGAPPLY: op_replay<fcg_apply_kernelOp>(g, b, a, n, st); break;
+    case BK_FCGCOEF: op_replay<fcg_coef_kernelOp>(g, b, a, n, st); break;
+    case BK_FCGUPD: op_replay<fcg_update_kernelOp>(g, b, a, n, st); break;
+    case BK_SMOOTH_F: op_replay<smooth_kernelOp<float>>(g, b, a, n, st); break;
+    case BK_SMOOTH_D: op_replay<smooth_kernelOp<double>>(g, b, a, n, st); break;
+    case BK_RESID_F: op_replay<residual_kernelOp<float>>(g, b, a, n, st); break;
+    case BK_RESID_D: op_replay<residual_kernelOp<double>>(g, b, a, n, st); break;
+    case BK_RSUM_F: op_replay<restrict_sum_kernelOp<float>>(g, b, a, n, st); break;
+    case BK_RSUM_D: op_replay<restrict_sum_kernelOp<double>>(g, b, a, n, st); break;
+    case BK_RTR_F: op_replay<restrict_kernelOp<float>>(g, b, a, n, st); break;
+    case BK_RTR_D: op_replay<restrict_kernelOp<double>>(g, b, a, n, st); break;
+    case BK_PROL_F: op_replay<prolong_kernelOp<float>>(g, b, a, n, st); break;
+    case BK_PROL_D: op_replay<prolong_kernelOp<double>>(g, b, a, n, st); break;
+    case BK_SMALL_F: op_replay<small_vcycle_kernelOp<float>>(g, b, a, n, st); break;
+    case BK_SMALL_D: op_replay<small_vcycle_kernelOp<double>>(g, b, a, n, st); break;
+    case BK_EF2F: op_replay<efield_kernelOp<2, float>>(g, b, a, n, st); break;
+    case BK_EF2D: op_replay<efield_kernelOp<2, double>>(g, b, a, n, st); break;
+    case BK_EF3F: op_replay<efield_kernelOp<3, float>>(g, b, a, n, st); break;
+    case BK_EF3D: op_replay<efield_kernelOp<3, double>>(g, b, a, n, st); break;
+    default: break;
+  }
+}
+
+int replay_batch(BatchRecorder* const* cases, int n, BatchArgs& ba, hipStream_t st) {
+  if (n < 1) return 0;
+  const BatchRecorder& r0 = *cases[0];
+  // every case must have recorded the same sequence of launches
+  for (int c = 0; c < n; ++c) {
+    const BatchRecorder& rc = *cases[c];
+    if (rc.unsupported || rc.recs.size() != r0.recs.size()) return -1;
+    for (size_t i = 0; i < rc.recs.size(); ++i) {
+      const BatchRec &a = rc.recs[i], &b = r0.recs[i];
+      if (a.kind != b.kind || a.args.size() != b.args.size() || a.grid.x != b.grid.x || a.grid.y != b.grid.y ||
+          a.grid.z != b.grid.z || a.block.x != b.block.x || a.block.y != b.block.y || a.block.z != b.block.z)
+        return -1;
+      // the batched grid stacks the cases along z
+      if ((size_t)a.grid.z * (size_t)n > 65535) return -1;
+    }
+  }
+  // argument structs: record i of every case as an array Args[n] (the kernel
+  // indexes it with the struct's own size), each array 16-byte aligned
+  std::vector<size_t> offs(r0.recs.size());
+  size_t total = 0;
+  for (size_t i = 0; i < r0.recs.size(); ++i) {
+    total = (total + 15) & ~(size_t)15;
+    offs[i] = total;
+    total += r0.recs[i].args.size() * (size_t)n;
+  }
+  ba.staging.assign(total, 0);
+  for (size_t i = 0; i < r0.recs.size(); ++i) {
+    const size_t sz = r0.recs[i].args.size();
+    for (int c = 0; c < n; ++c) memcpy(ba.staging.data() + offs[i] + sz * (size_t)c, cases[c]->recs[i].args.data(), sz);
+  }
+  if (total > ba.bytes || total > ba.pinned_bytes) {
+    // larger buffers; the old ones may still be read by work in flight on st
+    if (hipStreamSynchronize(st) != hipSuccess) return -3;
+    free_batch_args(ba);
+    const size_t want = total + total / 2 + 4096;
+    ba.dev = ba.dev_alloc ? ba.dev_alloc(want, ba.ctx) : nullptr;
+    if (!ba.dev) return -2;
+    ba.bytes = want;
+    for (int k = 0; k < 2; ++k) {
+      if (hipHostMalloc(&ba.pinned[k], want, hipHostMallocDefault) != hipSuccess) {
+        ba.pinned[k] = nullptr;
+        free_batch_args(ba);
+        return -2;
+      }
+      if (hipEventCreateWithFlags(&ba.copied[k], hipEventDisableTiming) != hipSuccess) {
+        ba.copied[k] = nullptr;
+        free_batch_args(ba);
+        return -2;
+      }
+      if (hipEventRecord(ba.copied[k], st) != hipSuccess) return -3;
+    }
+    ba.pinned_bytes = want;
+  }
+  // most steps record the same arguments as the last one: upload on change
+  // (stream-ordered, so launches still in flight read the previous contents)
+  if (ba.uploaded != ba.staging) {
+    const int k = ba.slot;
+    ba.slot ^= 1;
+    if (hipEventSynchronize(ba.copied[k]) != hipSuccess) return -3;
+    memcpy(ba.pinned[k], ba.staging.data(), total);
+    if (hipMemcpyAsync(ba.dev, ba.pinned[k], total, hipMemcpyHostToDevice, st) != hipSuccess) return -3;
+    if (hipEventRecord(ba.copied[k], st) != hipSuccess) return -3;
+    ba.uploaded = ba.staging;
+  }
+  for (size_t i = 0; i < r0.recs.size(); ++i) {
+    const BatchRec& rec = r0.recs[i];
+    replay_one(rec.kind, rec.grid, rec.block, (const unsigned char*)ba.dev + offs[i], n, st);
+  }
+  return 0;
+}
+
+void free_batch_args(BatchArgs& ba) {
+  if (ba.dev && ba.dev_free) ba.dev_free(ba.dev, ba.ctx);
+  ba.dev = nullptr;
+  ba.bytes = 0;
+  for (int k = 0; k < 2; ++k) {
+    if (ba.pinned[k]) (void)hipHostFree(ba.pinned[k]);
+    if (ba.copied[k]) (void)hipEventDestroy(ba.copied[k]);
+    ba.pinned[k] = nullptr;
+    ba.copied[k] = nullptr;
+  }
+  ba.pinned_bytes = 0;
+  ba.slot = 0;
+  ba.uploaded.clear();
 }
 
 }  // namespace cpic

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace cpic {
@@ -199,7 +201,9 @@ struct ChargeSpecies {
 };
 void launch_charge(const GridCtx& G, const ChargeSpecies& cs, double bg_charge, hipStream_t st);
 void launch_rhs(const GridCtx& G, hipStream_t st);
-int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st);
+// cap: the cycles this solve may use (<= 0: max_cycles); a solve launched with
+// more cycles than its cap stops at the cap on the device
+int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st, int cap = 0);
 int compute_smoother_bounds(GridCtx& G, hipStream_t st);
 void launch_operator_f32(const GridCtx& G, hipStream_t st);
 int setup_coarse_inverse(GridCtx& G, hipStream_t st);
@@ -231,5 +235,57 @@ constexpr int QSUM_WORDS = 2 + 2 * REDUCE_BLOCKS;
 void launch_qsum(const uint64_t* Q, long long n, uint64_t* out2, hipStream_t st);
 // adds the number of non-finite entries of x (double when fp64, else float) to *bad
 void launch_nonfinite_check(const void* x, long long n, int fp64, int* bad, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Batched field phase (serving).  Every launch of the field phase (charge,
+// extrapolated guess, right side, the flexible-CG solve with its FP32 V-cycle,
+// gauge, vertex field) goes through one launcher per kernel.  Without a
+// recorder it launches at once.  With the calling thread's recorder set, it
+// records the kernel's kind, grid, block and argument struct instead.
+// Simulations of the same grid shape record the same sequence, in which the
+// arguments differ (pointers, per-case scalars); replay_batch() then runs each
+// record as ONE launch over all of them: the grid's z extent times the number
+// of cases, the case index in blockIdx.z / z, every case's argument struct
+// read from one device buffer.  Each case computes exactly what its own launch
+// would: its kernels see their own block coordinates.
+// ---------------------------------------------------------------------------
+struct BatchRec {
+  int kind;
+  dim3 grid, block;
+  std::vector<unsigned char> args;
+};
+struct BatchRecorder {
+  std::vector<BatchRec> recs;
+  bool unsupported = false;  // a launch without a batched form was attempted while recording
+};
+extern thread_local BatchRecorder* g_batch_rec;
+// records a launch that has no batched form (the batch falls back to per-case steps)
+inline bool batch_unsupported() {
+  if (!g_batch_rec) return false;
+  g_batch_rec->unsupported = true;
+  return true;
+}
+// Device buffer of one batch's argument structs, with the host copy they are
+// assembled in, the last uploaded contents, and two pinned upload buffers used
+// in turn (each reused only after the event recorded behind its last copy).
+struct BatchArgs {
+  // device allocation of the buffer (the owning simulation's allocator)
+  void* (*dev_alloc)(size_t bytes, void* ctx) = nullptr;
+  void (*dev_free)(void* p, void* ctx) = nullptr;
+  void* ctx = nullptr;
+  void* dev = nullptr;
+  size_t bytes = 0;
+  std::vector<unsigned char> staging, uploaded;
+  void* pinned[2] = {nullptr, nullptr};
+  hipEvent_t copied[2] = {nullptr, nullptr};
+  size_t pinned_bytes = 0;
+  int slot = 0;
+};
+// Replays the recorded sequences of n cases as batched launches on st.
+// Returns 0; -1 (nothing launched) when the sequences differ or a case
+// recorded an unsupported launch; -2 (nothing launched) when the argument
+// buffers could not be allocated; -3 on a runtime error.
+int replay_batch(BatchRecorder* const* cases, int n, BatchArgs& ba, hipStream_t st);
+void free_batch_args(BatchArgs& ba);
 
 }  // namespace cpic

@@ -1,6 +1,7 @@
 // server.hip -- request loop over independent simulation cases (the serving
 // side of the library): FIFO admission by slot and HBM budget, resident cases
-// advanced one step per pump iteration on per-slot streams, results and
+// advanced one step per pump iteration (cases of one grid shape together, their
+// field phases batched, on a shared stream; the others on per-slot streams), results and
 // per-step latencies collected when a case finishes.  Host code on top of the
 // public C ABI (cpic.h) and the HIP runtime.
 #include <hip/hip_runtime.h>
@@ -10,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <deque>
+#include <map>
 #include <unordered_map>
 #include <vector>
 
@@ -39,6 +41,8 @@ struct Case {
   std::vector<double> vertices;                             // host copy of a tabulated map
   cpic_sim* sim = nullptr;
   hipStream_t stream = nullptr;
+  int stream_index = -1;
+  uint64_t group = 0;      // batch signature (0: the case steps alone)
   int slot = -1;
   int steps_enqueued = 0;
   hipEvent_t done_ev = nullptr;
@@ -69,6 +73,12 @@ struct cpic_server {
   std::vector<double> step_samples;
   cpic_allocator counting;  // handed to every case
   bool no_graphs = false;   // cases step without recorded graphs (CPIC_SERVER_NO_GRAPHS set)
+  bool no_batch = false;    // cases step one by one (CPIC_SERVER_NO_BATCH set)
+  std::vector<int> stream_load;  // active cases per stream
+  // batch groups: signature -> (stream index, active cases); cases of a group share a stream
+  std::unordered_map<uint64_t, std::pair<int, int>> groups;
+  hipStream_t admit_stream = nullptr;  // new cases are set up here, then join their stream
+  long long batched_steps = 0;   // case steps taken inside batches
 };
 
 namespace {
@@ -103,6 +113,28 @@ void budget_free(void* p, void* ctx) {
 
 size_t real_bytes(const cpic_grid_desc& g) { return g.precision == CPIC_FP64 ? 8 : 4; }
 
+// The stream of a new case: its group's, else the least loaded one.
+int pick_stream(cpic_server* s, uint64_t key) {
+  if (key) {
+    auto it = s->groups.find(key);
+    if (it != s->groups.end()) return it->second.first;
+  }
+  int best = 0;
+  for (int i = 1; i < (int)s->stream_load.size(); ++i)
+    if (s->stream_load[i] < s->stream_load[best]) best = i;
+  return best;
+}
+
+void leave_stream(cpic_server* s, Case* c) {
+  if (c->stream_index < 0) return;
+  --s->stream_load[c->stream_index];
+  if (c->group) {
+    auto it = s->groups.find(c->group);
+    if (it != s->groups.end() && --it->second.second == 0) s->groups.erase(it);
+  }
+  c->stream_index = -1;
+}
+
 void fail_case(cpic_server* s, Case* c, int status) {
   c->result.status = status;
   c->done = true;
@@ -113,7 +145,8 @@ void fail_case(cpic_server* s, Case* c, int status) {
 int admit_one(cpic_server* s, Case* c, int slot) {
   const cpic_case_desc& d = c->desc;
   cpic_sim* sim = nullptr;
-  int rc = cpic_create(&d.map, &d.grid, &s->counting, (void*)s->streams[slot % s->streams.size()], &sim);
+  hipStream_t st0 = s->admit_stream ? s->admit_stream : s->streams[0];
+  int rc = cpic_create(&d.map, &d.grid, &s->counting, (void*)st0, &sim);
   if (rc != CPIC_OK) return rc;
   for (int k = 0; k < d.nspecies && rc == CPIC_OK; ++k) {
     cpic_species_desc sd = d.species[k];
@@ -128,13 +161,26 @@ int admit_one(cpic_server* s, Case* c, int slot) {
   if (rc == CPIC_OK) rc = cpic_set_timing(sim, 1);
   // one host launch per step: the loop over many small cases is host-bound otherwise
   if (rc == CPIC_OK && !s->no_graphs) rc = cpic_set_graphs(sim, 1);
+  // the stream: its batch group's, else the least loaded one
+  uint64_t key = 0;
+  if (rc == CPIC_OK && !s->no_batch) rc = cpic_batch_signature(sim, &key);
+  const int si = pick_stream(s, key);
+  if (rc == CPIC_OK && s->streams[si] != st0) rc = cpic_set_stream(sim, (void*)s->streams[si]);
   if (rc != CPIC_OK) {
     cpic_destroy(sim);
     return rc;
   }
   c->sim = sim;
   c->slot = slot;
-  c->stream = s->streams[slot % s->streams.size()];
+  c->stream = s->streams[si];
+  c->stream_index = si;
+  ++s->stream_load[si];
+  c->group = key;
+  if (key) {
+    auto& g = s->groups[key];
+    if (g.second == 0) g.first = si;
+    ++g.second;
+  }
   c->t_admit = now_ms();
   c->result.queue_ms = c->t_admit - c->t_submit;
   return CPIC_OK;
@@ -209,6 +255,7 @@ void retire(cpic_server* s, Case* c) {
   (void)hipEventDestroy(c->done_ev);
   c->done_ev = nullptr;
   s->slot_busy[c->slot] = 0;
+  leave_stream(s, c);
   c->done = true;
   // release the host copies of the initial particles
   c->cell.clear();
@@ -243,6 +290,11 @@ extern "C" cpic_status cpic_server_create(size_t hbm_budget_bytes, int max_slots
     s->streams.push_back((hipStream_t)hip_stream);
   } else {
     s->own_streams = true;
+    if (hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking) != hipSuccess) {
+      s->admit_stream = nullptr;
+      cpic_server_destroy(s);
+      return CPIC_E_HIP;
+    }
     for (int i = 0; i < max_slots; ++i) {
       hipStream_t st = nullptr;
       if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -253,7 +305,9 @@ extern "C" cpic_status cpic_server_create(size_t hbm_budget_bytes, int max_slots
     }
   }
   s->slot_busy.assign((size_t)max_slots, 0);
+  s->stream_load.assign(s->streams.size(), 0);
   s->no_graphs = getenv("CPIC_SERVER_NO_GRAPHS") != nullptr;
+  s->no_batch = getenv("CPIC_SERVER_NO_BATCH") != nullptr;
   *out = s;
   return CPIC_OK;
 }
@@ -321,10 +375,35 @@ extern "C" cpic_status cpic_server_pump(cpic_server* s, int max_iterations) {
   for (int it = 0; it < max_iterations; ++it) {
     admit(s);
     if (s->active.empty()) break;
-    // one step of every running case, each on its slot's stream
+    // one step of every running case: the cases of a batch group together
+    // (their field phases batched), the others each on its own
+    std::map<uint64_t, std::vector<Case*>> batches;
+    std::vector<Case*> alone;
     for (Case* c : s->active) {
       if (c->finishing) continue;
-      int rc = cpic_step(c->sim, 1);
+      if (!c->group)
+        alone.push_back(c);
+      else
+        batches[c->group].push_back(c);
+    }
+    std::vector<std::pair<Case*, int>> stepped;
+    for (Case* c : alone) stepped.push_back({c, (int)cpic_step(c->sim, 1)});
+    for (auto& kv : batches) {
+      std::vector<Case*>& cs = kv.second;
+      if (cs.size() == 1) {
+        stepped.push_back({cs[0], (int)cpic_step(cs[0]->sim, 1)});
+        continue;
+      }
+      std::vector<cpic_sim*> sims;
+      for (Case* c : cs) sims.push_back(c->sim);
+      std::vector<cpic_status> st(cs.size(), CPIC_OK);
+      (void)cpic_step_batch(sims.data(), (int)sims.size(), st.data());
+      for (size_t i = 0; i < cs.size(); ++i) stepped.push_back({cs[i], (int)st[i]});
+      s->batched_steps += (long long)cs.size();
+    }
+    for (auto& cr : stepped) {
+      Case* c = cr.first;
+      const int rc = cr.second;
       if (rc != CPIC_OK) {
         c->result.status = rc;
         c->finishing = true;
@@ -356,6 +435,7 @@ extern "C" cpic_status cpic_server_pump(cpic_server* s, int max_iterations) {
           c->sim = nullptr;
           if (c->done_ev) (void)hipEventDestroy(c->done_ev);
           s->slot_busy[c->slot] = 0;
+          leave_stream(s, c);
           s->blocked = false;
           fail_case(s, c, status);
         } else {
@@ -395,6 +475,7 @@ extern "C" cpic_status cpic_server_get_stats(cpic_server* s, cpic_server_stats* 
   out->step_samples = (long long)s->step_samples.size();
   out->step_p50_ms = percentile(s->step_samples, 50.0);
   out->step_p99_ms = percentile(s->step_samples, 99.0);
+  out->batched_steps = s->batched_steps;
   return CPIC_OK;
 }
 
@@ -405,7 +486,9 @@ extern "C" void cpic_server_destroy(cpic_server* s) {
     if (c->done_ev) (void)hipEventDestroy(c->done_ev);
   }
   for (auto& kv : s->cases) delete kv.second;
-  if (s->own_streams)
+  if (s->own_streams) {
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    if (s->admit_stream) (void)hipStreamDestroy(s->admit_stream);
+  }
   delete s;
 }

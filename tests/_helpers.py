@@ -8,7 +8,7 @@ from paper_1311_2286_amd import workloads as W
 
 def gpu_sim(case, precision=0, shape=2, track_ids=True, mg_rtol=1e-12, mg_max_cycles=80,
             sort_every=1, count=None, capacity_factor=1.0, inject=False, seed=0, stream=None, mover=0,
-            pusher=0):
+            pusher=0, mg_method=0):
     """inject: every species gets flux injection at the outer wall with
     n0 = 1 and its own thermal speed, keyed by `seed`."""
     from paper_1311_2286_amd import cpic as C
@@ -23,7 +23,7 @@ def gpu_sim(case, precision=0, shape=2, track_ids=True, mg_rtol=1e-12, mg_max_cy
                 phi_hi=case.phi_hi, shape=shape, precision=precision, dt=case.dt, B0=case.B,
                 background=case.background, mg_rtol=mg_rtol, mg_max_cycles=mg_max_cycles,
                 sort_every=sort_every, track_ids=track_ids, stream=stream, mover=mover, vertices=vertices,
-                pusher=pusher)
+                pusher=pusher, mg_method=mg_method)
     parts = []
     for sid, s in enumerate(case.species):
         p = W.generate_species(case, sid, dtype=dt, count=count)

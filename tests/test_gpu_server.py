@@ -1,7 +1,8 @@
 """GPU tests of the serving loop (cpic_server_* in include/cpic.h): independent
 2D periodic sinusoidal-map cases (the paper's distorted-mesh test setting,
 Eq. map2) of different grids, perturbation amplitudes and temperatures,
-admitted by slot and HBM budget and advanced together on per-slot streams.
+admitted by slot and HBM budget and advanced together on per-slot streams;
+cases of one grid and map step together, their field phases batched.
 
 Bars:
   - a case's result is the same run alone, in a mix with other cases, and as
@@ -9,9 +10,12 @@ Bars:
     counts and the final potential bitwise, kinetic energy to 1e-13 relative
     (its FP64 per-work-item sums follow the order of particles inside a tile,
     which the tile sort does not fix);
+  - the same with batching turned off (CPIC_SERVER_NO_BATCH);
   - the budget is never exceeded, cases that do not fit wait for memory and
     then complete; a case larger than the whole budget fails with
     CPIC_E_BUDGET without disturbing the others."""
+import os
+
 import numpy as np
 import pytest
 
@@ -155,3 +159,22 @@ def test_tabulated_map_case_is_copied_at_submit_and_matches_a_plain_run():
     assert d.field_energy == res["field_energy"]
     assert np.array_equal(sim.get_field(c.FIELD_PHI), res["phi"])
     sim.close()
+
+
+def test_batched_server_equals_unbatched():
+    # four cases of one grid and map (different seeds and temperatures) step
+    # as one batch group; a fifth of another grid steps alone
+    group = [serving_case(48, 0.10, 12.0, v, 430 + k) for k, v in enumerate((1.0, 0.7, 1.3, 0.9))]
+    mix = group + [CASES[0]]
+    res_b, st_b = run_server(mix, slots=5, budget=1 << 30)
+    os.environ["CPIC_SERVER_NO_BATCH"] = "1"
+    try:
+        res_u, st_u = run_server(mix, slots=5, budget=1 << 30)
+    finally:
+        del os.environ["CPIC_SERVER_NO_BATCH"]
+    print("[server] batched steps %d / %d, p50 %.3f ms vs %.3f ms" %
+          (st_b["batched_steps"], st_u["batched_steps"], st_b["step_p50_ms"], st_u["step_p50_ms"]), flush=True)
+    assert all(r["status"] == 0 for r in res_b + res_u)
+    for a, b in zip(res_b, res_u):
+        same(a, b)
+    assert st_b["batched_steps"] == len(group) * NSTEPS and st_u["batched_steps"] == 0
