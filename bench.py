@@ -46,7 +46,18 @@ def workload(name):
 def bytes_per_particle(dim, precision, magnetic):
     """Algorithmic HBM bytes per particle push: state read once and written
     once.  FP32: int32 cell + dim FP32 offsets + FP32 velocities (2 in 2D
-    without B, else 3); FP64: int32 cell + dim FP64 offsets + 3 FP64 v."""
+    without B, else 3).  Plain FP64: the logical position and the velocity,
+    dim + 3 (2 in 2D without B) FP64 values -- the library stores the position
+    as an int32 cell and FP64 offsets, 8 B more per particle than counted."""
+    nv = 3 if (dim == 3 or magnetic) else 2
+    if precision == 1:
+        return 2 * (8 * dim + 8 * nv)
+    return 2 * (4 + 4 * dim + 4 * nv)
+
+
+def layout_bytes_per_particle(dim, precision, magnetic):
+    """Bytes the library's layout moves per particle push (int32 cell kept on
+    the FP64 path too)."""
     r = 8 if precision == 1 else 4
     nv = 3 if (dim == 3 or magnetic) else 2
     return 2 * (4 + dim * r + nv * r)
@@ -108,7 +119,8 @@ def copy_calibrate(nbytes, reps):
 _STREAM = None
 
 
-def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, graphs=False, mover=0, pusher=0):
+def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, graphs=False, mover=0, pusher=0,
+             track_ids=False):
     """graphs: step in graph mode, on a stream of its own (default priority);
     mover: 0 Newton map inversion, 1 predictor-corrector; pusher: 0 Boris,
     1 cyclotronic."""
@@ -128,7 +140,7 @@ def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, grap
                 r_out=case.r_out, bc_lo=case.bc_lo, bc_hi=case.bc_hi, phi_lo=case.phi_lo,
                 phi_hi=case.phi_hi, shape=shape, precision=precision, dt=case.dt, B0=case.B,
                 background=case.background, mg_rtol=mg_rtol, mg_max_cycles=mg_cycles,
-                sort_every=sort_every, track_ids=False, stream=stream, mover=mover, vertices=vertices,
+                sort_every=sort_every, track_ids=track_ids, stream=stream, mover=mover, vertices=vertices,
                 pusher=pusher)
     del vertices
     if graphs:
@@ -142,7 +154,7 @@ def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, grap
         # bounded problems (the probe): Maxwellian flux injection at the outer
         # wall keeps the plasma supplied; room for the particle count to grow
         inject = dict(n0=1.0, vth=s.vth) if bounded else None
-        cap = int(n * 1.2) if bounded else n
+        cap = int(n * 1.3) if bounded else n
         sim.add_species(s.q, s.m, case.weight(s), cap, pbc_lo=pbc_lo, pbc_hi=pbc_hi, inject=inject,
                         seed=1311 + sid)
         from paper_1311_2286_amd import workloads as W
@@ -251,6 +263,139 @@ def cpu_baseline(case, sample, shape, single_sample=1 << 18):
                 single_thread_value=n_one / t_one,
                 single_thread_sample="%d particles per species, %.1f s on 1 thread" % (single_sample, t_one),
                 cpu_model=_cpu_model())
+
+
+def cpu_configs(shape):
+    """The oracle timed on the host cores for the other configurations (all
+    its OpenMP threads): the 2D Langmuir workload whole (65,536 electrons, ion
+    background, 200 steps: push, deposit and the FP64 field solve every step);
+    one full step of the probe (52M particles: push, deposit, field solve on
+    512^2); one push + deposit pass of the magnetised box on an 8.4M-particle
+    sample per species (a whole step of 268M particles takes minutes)."""
+    import oracle as O
+    from paper_1311_2286_amd import workloads as W
+    out = {}
+    threads = O.num_threads()
+    # config 1: the whole run
+    case = W.case1()
+    m, g = O.make_map(**case.map_args()), O.make_grid(**case.grid_args())
+    p = W.generate_species(case, 0, dtype=np.float32, workers=16)
+    sp = [dict(q=case.species[0].q, m=case.species[0].m, w=case.weight(case.species[0]), **W.to_oracle(p))]
+    t0 = time.perf_counter()
+    bg = O.ion_background(m, g, shape)
+    osim = O.OracleSim(m, g, sp, shape=shape, dt=case.dt, background=bg, deposit="fixed", rtol=1e-13,
+                       ke_axes=2)
+    osim.initialize()
+    for _ in range(case.steps):
+        osim.step()
+    t = time.perf_counter() - t0
+    out["langmuir2d"] = {"value": p["cell"].size * case.steps / t, "unit": "particle pushes/s", "cores": threads,
+                         "sample": "the whole run: %d electrons, %d steps (push, deposit, FP64 solve to 1e-13), "
+                                   "%.1f s" % (p["cell"].size, case.steps, t)}
+    del osim, sp, p
+    # config 3: one full step
+    case = W.case3()
+    m, g = O.make_map(**case.map_args()), O.make_grid(**case.grid_args())
+    nv = O.nverts(g)
+    E = W.synthetic_ev(case, nv, dtype=np.float64, scale=0.05)
+    t_push, n = 0.0, 0
+    Q = []
+    for sid, sp_ in enumerate(case.species):
+        q = W.to_oracle(W.generate_species(case, sid, dtype=np.float32, workers=16))
+        t0 = time.perf_counter()
+        cell, off, vel, _ = O.push(m, g, sp_.q / sp_.m, case.dt, case.B, q["cell"], q["off"], q["vel"], E)
+        Q.append(O.deposit_fixed(g, shape, 24, cell[cell >= 0], off[cell >= 0]))
+        t_push += time.perf_counter() - t0
+        n += q["cell"].size
+        del q, cell, off, vel
+    t0 = time.perf_counter()
+    charge = O.charge_from_Q(Q, [dict(q=s_.q, w=case.weight(s_)) for s_ in case.species], 2, 24)
+    phi, _, _ = O.poisson_solve(m, g, charge, rtol=1e-10)
+    O.efield(m, g, phi)
+    t_solve = time.perf_counter() - t0
+    out["probe2d_512"] = {"value": n / (t_push + t_solve), "unit": "particle pushes/s", "cores": threads,
+                          "sample": "one full step: %d particles pushed and deposited (%.1f s), field solve of "
+                                    "512^2 to 1e-10 (%.1f s)" % (n, t_push, t_solve)}
+    del Q, charge
+    # config 5: push + deposit pass on a sample
+    case = W.case5()
+    m, g = O.make_map(**case.map_args()), O.make_grid(**case.grid_args())
+    E = W.synthetic_ev(case, O.nverts(g), dtype=np.float64, scale=0.05)
+    t_all, n = 0.0, 0
+    for sid, sp_ in enumerate(case.species):
+        q = W.to_oracle(W.generate_species(case, sid, dtype=np.float32, count=1 << 23, workers=16))
+        t0 = time.perf_counter()
+        cell, off, vel, _ = O.push(m, g, sp_.q / sp_.m, case.dt, case.B, q["cell"], q["off"], q["vel"], E)
+        O.deposit_fixed(g, shape, 16, cell, off)
+        t_all += time.perf_counter() - t0
+        n += q["cell"].size
+        del q, cell, off, vel
+    out["box3d_magnetized"] = {"value": n / t_all, "unit": "particle pushes/s", "cores": threads,
+                               "sample": "%d particles per species (first of each seeded stream), one gather + "
+                                         "Boris + map inversion + deposit pass, %.1f s" % (n // 2, t_all)}
+    return out
+
+
+def error_vs_oracle(shape, sort_every, mg_rtol, mg_cycles, steps=6):
+    """Error of the timed configuration (FP32 particles, fixed-point deposit,
+    the solver at the benchmark's tolerance and iteration cap, the tile sort
+    schedule) against the FP64 oracle, from the same initial state, on the
+    headline recipe at 24^3 cells (32 e + 32 i per cell): after each step the
+    largest relative difference of the charge per cell (rho), the potential
+    and the vertex field (to their maxima), of the field energy, and the
+    largest trajectory difference in cells; against the oracle with the same
+    fixed-point deposit rule and against the plain FP64 oracle (unquantised
+    deposit).  Largest over the steps."""
+    import oracle as O
+    from paper_1311_2286_amd import cpic as C
+    from paper_1311_2286_amd import workloads as W
+    n = (24, 24, 24)
+    case = W.Case("box3d_24", 3, W.SINUSOIDAL, n, L=(24.0, 24.0, 24.0), eps=0.05, dt=0.1,
+                  species=[W.electrons(1.0, 32.0), W.ions(ppc=32.0)], delta=0.01, case_id=2)
+    parts = [W.generate_species(case, sid, dtype=np.float32) for sid in range(2)]
+    sim = make_sim(case, C.FP32, shape, sort_every, mg_rtol, mg_cycles, parts, track_ids=True)
+    m, g = O.make_map(**case.map_args()), O.make_grid(**case.grid_args())
+    sims = {}
+    for tag, dep in (("fixed_deposit_oracle", "fixed"), ("plain_fp64_oracle", "f64")):
+        sp = [dict(q=s.q, m=s.m, w=case.weight(s), **W.to_oracle(parts[k])) for k, s in enumerate(case.species)]
+        sims[tag] = O.OracleSim(m, g, sp, shape=shape, dt=case.dt, deposit=dep, rtol=1e-13, ke_axes=3)
+        sims[tag].initialize()
+    sim.initialize()
+    rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    worst = {tag: {} for tag in sims}
+    for _ in range(steps):
+        sim.step(1)
+        ch, phi = sim.get_field(C.FIELD_CHARGE), sim.get_field(C.FIELD_PHI)
+        Ev = sim.get_field(C.FIELD_EV)[:, :3].astype(np.float64)
+        we = sim.diag().field_energy
+        got = []
+        for sid in range(2):
+            gp = sim.get_particles(sid)
+            o = np.argsort(gp["id"])
+            c = gp["cell"][o].astype(np.int64)
+            got.append(np.stack([c % n[0] + gp["off"][0][o], (c // n[0]) % n[1] + gp["off"][1][o],
+                                 c // (n[0] * n[1]) + gp["off"][2][o]], axis=1))
+        for tag, osim in sims.items():
+            osim.step()
+            e = {"rho": rel(ch, osim.charge), "phi": rel(phi, osim.phi), "E": rel(Ev, osim.Ev[:, :3]),
+                 "W_E": abs(we - osim.field_energy()) / abs(osim.field_energy())}
+            tr = 0.0
+            for sid in range(2):
+                oc = osim.sp[sid]["cell"].astype(np.int64)
+                oo = osim.sp[sid]["off"]
+                po = np.stack([oc % n[0] + oo[:, 0], (oc // n[0]) % n[1] + oo[:, 1],
+                               oc // (n[0] * n[1]) + oo[:, 2]], axis=1)
+                dd = got[sid] - po
+                dd -= np.round(dd / np.array(n)) * np.array(n)
+                tr = max(tr, float(np.abs(dd).max()))
+            e["trajectory_cells"] = tr
+            for k, v in e.items():
+                worst[tag][k] = max(worst[tag].get(k, 0.0), v)
+    sim.close()
+    out = {"workload": "box3d recipe at 24^3 (eps 0.05, 32 e + 32 i per cell), %d steps, FP32 path at the "
+                       "benchmark's solver settings (rtol %g, at most %d iterations) and sort schedule"
+                       % (steps, mg_rtol, mg_cycles), "largest_over_steps": worst}
+    return out
 
 
 def serving_requests(nreq, seed=1311):
@@ -589,9 +734,20 @@ def main():
         log("fp64", json.dumps(r64))
     del parts
     cpu = None
+    errors = None
     if not args.no_cpu:
         cpu = cpu_baseline(case, args.cpu_sample, shape)
         log("cpu", json.dumps(cpu))
+        try:
+            cpu["other_configs"] = cpu_configs(shape)
+        except Exception as e:  # reported, never fatal for the headline line
+            cpu["other_configs"] = {"error": repr(e)}
+        log("cpu configs", json.dumps(cpu["other_configs"]))
+        try:
+            errors = error_vs_oracle(shape, args.sort_every, args.mg_rtol, args.mg_cycles)
+        except Exception as e:
+            errors = {"error": repr(e)}
+        log("errors", json.dumps(errors))
     extra = {}
     if not args.no_extra:
         for key, (name, shp, prec, steps, mover, tab, push) in {
@@ -600,12 +756,15 @@ def main():
                 "box3d_128_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC, False, 0),
                 "box3d_128_tabulated": ("box3d_128", "b2", C.FP32, 10, 0, True, 0),
                 "box3d_128_tabulated_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC, True, 0),
-                "probe2d_512": ("probe2d_512", "b2", C.FP32, 20, 0, False, 0),
+                "probe2d_512": ("probe2d_512", "b2", C.FP32, 200, 0, False, 0),
                 "box3d_magnetized": ("box3d_magnetized", "b2", C.FP32, 10, 0, False, 0),
                 "box3d_magnetized_cyclotronic": ("box3d_magnetized", "b2", C.FP32, 10, 0, False,
                                                  C.PUSH_CYCLOTRONIC)}.items():
+            # the probe is timed in its injected steady state: the last 200 of the
+            # configuration's 2,000 steps
+            warm = 1800 if name == "probe2d_512" else 2
             try:
-                extra[key] = extra_workload(name, shp, prec, steps, 2, args.sort_every, args.mg_rtol,
+                extra[key] = extra_workload(name, shp, prec, steps, warm, args.sort_every, args.mg_rtol,
                                             args.mg_cycles, mover, tab, push)
             except Exception as e:  # reported, never fatal for the headline line
                 extra[key] = {"error": repr(e)}
@@ -653,6 +812,7 @@ def main():
                      "bytes_per_launch": r32["bytes_per_launch"],
                      "launch_ms": r32["launch_ms"]},
         "cpu_baseline": cpu,
+        "error_vs_oracle": errors,
     }
     if r64 is not None:
         out["fp64_path"] = {"value": r64["pushes_per_s"], "unit": "particle pushes/s",
@@ -662,6 +822,8 @@ def main():
                             "achieved_GBs": r64["achieved_GBs"],
                             "frac": r64["achieved_GBs"] / HBM_PEAK_GBS,
                             "bytes_per_launch": r64["bytes_per_launch"],
+                            "bytes_per_particle": r64["bytes_per_particle"],
+                            "layout_bytes_per_particle": layout_bytes_per_particle(case.dim, 1, any(case.B)),
                             "launch_ms": r64["launch_ms"],
                             "phase_ms": {"particles": r64["push_ms"], "field": r64["solve_ms"],
                                          "sort": r64["sort_ms"]}}
