@@ -480,6 +480,7 @@ def run_serving(nreq, nsteps, budget, slots, load, mg_rtol, mg_cycles, seed=1311
             "request_latency_p50_s": float(np.percentile(lat, 50)) / 1e3,
             "request_latency_p99_s": float(np.percentile(lat, 99)) / 1e3,
             "peak_active": st["peak_active"], "peak_bytes": st["peak_bytes"],
+            "batched_case_steps": st["batched_steps"],
             "budget_bytes": budget, "slots": slots}
 
 
@@ -690,6 +691,8 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=500)
     ap.add_argument("--serve-load", type=float, default=8.0,
                     help="arrival rate in units of 1 / (mean service time alone)")
+    ap.add_argument("--serve-budget-gib", type=float, default=1.0,
+                    help="HBM budget of the serving stream's cases")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path; "
@@ -704,15 +707,17 @@ def main():
     if args.serve:
         from paper_1311_2286_amd import cpic as C
         C.load()
-        sv = run_serving(args.serve_requests, args.serve_steps, 1 << 30, 32, args.serve_load,
+        budget = int(args.serve_budget_gib * (1 << 30))
+        sv = run_serving(args.serve_requests, args.serve_steps, budget, 32, args.serve_load,
                          args.mg_rtol, args.mg_cycles)
         print(json.dumps({"metric": "served particle pushes/s; p50/p99 step ms", "value": sv["pushes_per_s"],
                           "unit": "particle pushes/s", "n_gpus": 1, "higher_is_better": True,
                           "dtype": "f32", "data": "synthetic",
                           "config": {"workload": "serving stream: %d requests, 2D periodic sinusoidal "
                                                  "maps, grids 32^2..256^2, %d steps each, HBM budget "
-                                                 "1 GiB, 32 slots" % (args.serve_requests,
-                                                                      args.serve_steps)},
+                                                 "%g GiB, 32 slots" % (args.serve_requests,
+                                                                       args.serve_steps,
+                                                                       args.serve_budget_gib)},
                           "serving": sv}), flush=True)
         return
     from paper_1311_2286_amd import cpic as C
@@ -780,6 +785,15 @@ def main():
             extra["mover_timing"] = mover_timing()
         except Exception as e:
             extra["mover_timing"] = {"error": repr(e)}
+        # the serving stream, shortened: 32 requests of 200 steps under a 4 GiB budget
+        try:
+            sv = run_serving(32, 200, 4 << 30, 32, 8.0, args.mg_rtol, args.mg_cycles)
+            sv["workload"] = ("serving stream: 32 requests, 2D periodic sinusoidal maps, grids 32^2..256^2, "
+                              "200 steps each, Poisson arrivals at 8 / (mean service time alone), HBM budget "
+                              "4 GiB, 32 slots; same-shape cases batched")
+            extra["serving"] = sv
+        except Exception as e:
+            extra["serving"] = {"error": repr(e)}
     n_p = r32["pushes"]
     out = {
         "metric": METRIC,

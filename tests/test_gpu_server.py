@@ -178,3 +178,32 @@ def test_batched_server_equals_unbatched():
     for a, b in zip(res_b, res_u):
         same(a, b)
     assert st_b["batched_steps"] == len(group) * NSTEPS and st_u["batched_steps"] == 0
+
+
+def test_requests_admitted_while_others_run_equal_alone():
+    # continuous batching: requests arrive while others are running (two of
+    # them join the batch group of a running case mid-way through its steps);
+    # every result equals the case served alone
+    group = [serving_case(48, 0.10, 12.0, v, 440 + k) for k, v in enumerate((1.0, 0.8, 1.2))]
+    other = serving_case(32, 0.05, 16.0, 1.0, 445)
+    alone = [run_server([c], slots=1, budget=1 << 30)[0][0] for c in group + [other]]
+    srv = C().Server(1 << 30, 4)
+    prepared = [descs(c) for c in group + [other]]
+    tickets = [srv.submit(*prepared[0], NSTEPS, want_phi=True)]
+    srv.pump(3)  # the first case is 3 steps in when the others arrive
+    assert srv.poll(tickets[0]) is None
+    tickets.append(srv.submit(*prepared[3], NSTEPS, want_phi=True))
+    srv.pump(2)
+    tickets += [srv.submit(*p, NSTEPS, want_phi=True) for p in prepared[1:3]]
+    for _ in range(100000):
+        if srv.pump(1):
+            break
+    res = [srv.poll(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    order = [0, 3, 1, 2]
+    for r, k in zip(res, order):
+        assert r["status"] == 0
+        same(r, alone[k])
+    # the late members stepped together with the first while it ran
+    assert stats["batched_steps"] > 0
