@@ -591,11 +591,11 @@ def field_solve_anisotropic(N=2048, stretches=(10.0, 40.0), rtol=1e-10):
     u, v = np.meshgrid(xi, xi, indexing="xy")
     charge = (np.sin(3 * np.pi * u) * np.sin(5 * np.pi * v)).ravel() / N ** 2
     rows = []
-    for Ly in stretches:
+    for Ly, method in [(ly, m) for m in (0, C.MG_BOXMG) for ly in stretches]:
         cap, times = 400, []
         for attempt in range(2):
             sim = C.Sim(C.MAP_IDENTITY, 2, (N, N), L=(1.0, Ly), bc_lo=(1, 1), bc_hi=(1, 1), precision=C.FP64,
-                        mg_rtol=rtol, mg_max_cycles=cap)
+                        mg_rtol=rtol, mg_max_cycles=cap, mg_method=method)
             try:
                 sim.set_field(C.FIELD_CHARGE, charge)
                 for r in range(3 if attempt else 1):
@@ -609,7 +609,8 @@ def field_solve_anisotropic(N=2048, stretches=(10.0, 40.0), rtol=1e-10):
             finally:
                 sim.close()
             cap = d.mg_cycles + 1
-        rows.append({"grid": "%d^2" % N, "box": [1.0, Ly], "coefficient_ratio": Ly * Ly, "cycles": d.mg_cycles,
+        rows.append({"grid": "%d^2" % N, "box": [1.0, Ly], "coefficient_ratio": Ly * Ly,
+                     "method": "boxmg" if method else "fcg", "cycles": d.mg_cycles,
                      "relres": d.mg_relres, "solve_ms": 1e3 * float(np.median(times[1:]))})
         log("aniso", json.dumps(rows[-1]))
     torch.cuda.empty_cache()
@@ -617,7 +618,7 @@ def field_solve_anisotropic(N=2048, stretches=(10.0, 40.0), rtol=1e-10):
             "grids": rows}
 
 
-def field_solve_mms(sizes=(1024, 2048, 4096), rtol=1e-10, reps=3):
+def field_solve_mms(sizes=(1024, 2048, 4096), rtol=1e-10, reps=3, method=0):
     """The field solve alone on the paper's manufactured-solution test (spherical
     r-z map, Omega = r, Eq. mms; Table t1's grids and tolerance): cycles, time
     per solve from a zero initial guess and the RMS error against Eq. mms.
@@ -635,7 +636,7 @@ def field_solve_mms(sizes=(1024, 2048, 4096), rtol=1e-10, reps=3):
         for attempt in range(2):
             sim = C.Sim(W.SPHERICAL_RZ, 2, (N, N), r_in=W.MMS_R1, r_out=W.MMS_R2, omega=1,
                         bc_lo=(C.BC_DIRICHLET, C.BC_NEUMANN), bc_hi=(C.BC_DIRICHLET, C.BC_NEUMANN),
-                        precision=C.FP64, mg_rtol=rtol, mg_max_cycles=cap)
+                        precision=C.FP64, mg_rtol=rtol, mg_max_cycles=cap, mg_method=method)
             try:
                 sim.set_field(C.FIELD_CHARGE, charge)
                 times = []
@@ -660,8 +661,11 @@ def field_solve_mms(sizes=(1024, 2048, 4096), rtol=1e-10, reps=3):
         torch.cuda.empty_cache()
         log("mms", json.dumps(row))
         out.append(row)
+    how = ("one FP32 V(2,2) cycle per iteration (point Chebyshev smoother, rediscretised coarse operators)"
+           if method == 0 else "one FP32 V(1,2) cycle per iteration with variational coarse operators and zebra "
+                               "line relaxation (CPIC_MG_BOXMG)")
     return {"workload": "field solve of the spherical r-z manufactured solution (Omega = r), FCG with "
-                        "one FP32 V-cycle per iteration, rtol %g, from a zero initial guess" % rtol,
+                        "%s, rtol %g, from a zero initial guess" % (how, rtol),
             "grids": out}
 
 
@@ -777,6 +781,10 @@ def main():
             extra["field_solve_mms"] = field_solve_mms()
         except Exception as e:
             extra["field_solve_mms"] = {"error": repr(e)}
+        try:
+            extra["field_solve_mms_boxmg"] = field_solve_mms(method=C.MG_BOXMG)
+        except Exception as e:
+            extra["field_solve_mms_boxmg"] = {"error": repr(e)}
         try:
             extra["field_solve_anisotropic"] = field_solve_anisotropic()
         except Exception as e:

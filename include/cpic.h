@@ -138,7 +138,13 @@ enum {
   CPIC_MG_FCG = 0,    /* flexible conjugate gradients, one V-cycle per iteration as the
                          preconditioner (default: converges on strongly distorted,
                          anisotropic grids where V-cycles alone can diverge) */
-  CPIC_MG_VCYCLE = 1  /* plain V-cycles */
+  CPIC_MG_VCYCLE = 1, /* plain V-cycles */
+  CPIC_MG_BOXMG = 2   /* 2D: flexible conjugate gradients preconditioned by a V(1,2) cycle with
+                         variational coarse operators (P^T A P, P the cell-centred bilinear
+                         interpolation) and zebra line relaxation along both axes (Sec.
+                         "Field solver": the robust solver for anisotropic, strongly
+                         varying operators); grids of 4..4096 cells per axis, else
+                         CPIC_E_UNSUPPORTED */
 };
 
 /* Position update of the mover (cpic_grid_desc.mover) */
@@ -213,7 +219,7 @@ typedef struct {
                            in cells) is below one cell -- slow species are sorted less often,
                            at least every 16 sort_every steps; injecting species every step */
   int track_ids;        /* carry a uint32 particle id through sorts */
-  int mg_method;        /* CPIC_MG_FCG (0) or CPIC_MG_VCYCLE */
+  int mg_method;        /* CPIC_MG_FCG (0), CPIC_MG_VCYCLE or CPIC_MG_BOXMG */
   int mover;            /* CPIC_MOVER_NEWTON (0) or CPIC_MOVER_PC */
   int pusher;           /* CPIC_PUSH_BORIS (0) or CPIC_PUSH_CYCLOTRONIC */
 } cpic_grid_desc;

@@ -21,7 +21,7 @@ BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN, BC_FLOATING = 0, 1, 2, 3
 PBC_PERIODIC, PBC_ABSORB, PBC_OUTFLOW = 0, 1, 2
 SHAPE_B1, SHAPE_B2 = 1, 2
 FP32, FP64 = 0, 1
-MG_FCG, MG_VCYCLE = 0, 1
+MG_FCG, MG_VCYCLE, MG_BOXMG = 0, 1, 2
 MOVER_NEWTON, MOVER_PC = 0, 1
 FIELD_Q, FIELD_CHARGE, FIELD_PHI, FIELD_EV, FIELD_JC, FIELD_RHO, FIELD_BACKGROUND = range(7)
 (STAGE_SORT, STAGE_DEPOSIT, STAGE_CHARGE, STAGE_SOLVE, STAGE_EFIELD, STAGE_PUSH, STAGE_HALFSTEP,

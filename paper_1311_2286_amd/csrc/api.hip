@@ -281,7 +281,11 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   if (grid->precision != CPIC_FP32 && grid->precision != CPIC_FP64) return CPIC_E_ARG;
   if (!(grid->dt > 0) || !isfinite(grid->dt)) return CPIC_E_ARG;
   if (grid->background && (d != 2 || !all_periodic)) return CPIC_E_UNSUPPORTED;
-  if (grid->mg_method != CPIC_MG_FCG && grid->mg_method != CPIC_MG_VCYCLE) return CPIC_E_ARG;
+  if (grid->mg_method != CPIC_MG_FCG && grid->mg_method != CPIC_MG_VCYCLE && grid->mg_method != CPIC_MG_BOXMG)
+    return CPIC_E_ARG;
+  if (grid->mg_method == CPIC_MG_BOXMG &&
+      (map->dim != 2 || grid->n[0] < 4 || grid->n[1] < 4 || grid->n[0] > 4096 || grid->n[1] > 4096))
+    return CPIC_E_UNSUPPORTED;
   if (grid->mover != CPIC_MOVER_NEWTON && grid->mover != CPIC_MOVER_PC) return CPIC_E_ARG;
   if (grid->pusher != CPIC_PUSH_BORIS && grid->pusher != CPIC_PUSH_CYCLOTRONIC) return CPIC_E_ARG;
   if (grid->pusher == CPIC_PUSH_CYCLOTRONIC && grid->mover != CPIC_MOVER_NEWTON) return CPIC_E_UNSUPPORTED;
@@ -456,9 +460,16 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   if (G.lev[nl - 1].ncells <= DENSE_MAX) {
     const size_t nn = (size_t)G.lev[nl - 1].ncells * (size_t)G.lev[nl - 1].ncells;
     G.cinv64 = (double*)A(sizeof(double) * nn);
-    if (grid->mg_method == CPIC_MG_FCG) G.cinv32 = (float*)A(sizeof(float) * nn);
+    if (grid->mg_method != CPIC_MG_VCYCLE) G.cinv32 = (float*)A(sizeof(float) * nn);
   }
-  if (grid->mg_method == CPIC_MG_FCG) {
+  G.boxmg = grid->mg_method == CPIC_MG_BOXMG;
+  if (G.boxmg)
+    for (int l = 1; l < nl; ++l) {
+      Level& L = G.lev[l];
+      L.gal64 = (double*)A(sizeof(double) * 25 * (size_t)L.ncells);
+      L.gal32 = (float*)A(sizeof(float) * 25 * (size_t)L.ncells);
+    }
+  if (grid->mg_method != CPIC_MG_VCYCLE) {
     for (int l = 0; l < nl; ++l) {
       Level& L = G.lev[l];
       const size_t fb = sizeof(float) * (size_t)L.ncells;
@@ -561,7 +572,8 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
       cpic_destroy(s);
       return CPIC_E_HIP;
     }
-  if (compute_smoother_bounds(G, st) != 0 || setup_coarse_inverse(G, st) != 0 || setup_floating_wall(G, st) != 0) {
+  if (compute_smoother_bounds(G, st) != 0 || setup_galerkin(G, st) != 0 || setup_coarse_inverse(G, st) != 0 ||
+      setup_floating_wall(G, st) != 0) {
     cpic_destroy(s);
     return CPIC_E_HIP;
   }

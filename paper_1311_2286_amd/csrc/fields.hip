@@ -1595,12 +1595,16 @@ __global__ __launch_bounds__(256) void dense_operator_kernel(LevelArgs a, double
 // problems: A has the constant null vector 1 and 1^T A = 0, so
 // B = A - beta 1 1^T is invertible and for zero-sum b the solution of B x = b
 // has zero sum and solves A x = b.  The inverse is stored in FP64 and FP32.
+void launch_dense_galerkin(const GridCtx& G, double* M, hipStream_t st);
 int setup_coarse_inverse(GridCtx& G, hipStream_t st) {
   if (!G.cinv64) return 0;
   const int l = G.nlev - 1;
   const int n = (int)G.lev[l].ncells;
   LevelArgs a = level_args(G, l);
-  hipLaunchKernelGGL(dense_operator_kernel, dim3(n), dim3(256), 0, st, a, G.cinv64);
+  if (G.boxmg)
+    launch_dense_galerkin(G, G.cinv64, st);
+  else
+    hipLaunchKernelGGL(dense_operator_kernel, dim3(n), dim3(256), 0, st, a, G.cinv64);
   std::vector<double> M((size_t)n * n), Inv((size_t)n * n, 0.0);
   if (hipMemcpyAsync(M.data(), G.cinv64, sizeof(double) * M.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
@@ -2086,6 +2090,7 @@ struct fcg_update_kernelOp {
   }
 };
 
+static void boxmg_vcycle(const GridCtx& G, int l, hipStream_t st);
 static int launch_fcg_solve(const GridCtx& G, double rtol2, int max_iter, int nu1, int nu2, hipStream_t st) {
   const Level& L = G.lev[0];
   LevelArgs a = level_args(G, 0);
@@ -2095,7 +2100,10 @@ static int launch_fcg_solve(const GridCtx& G, double rtol2, int max_iter, int nu
   op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{(const double*)G.mg_partials, nblk, G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 0}, st);
   for (int it = 0; it < max_iter; ++it) {
     const int first = it == 0;
-    vcycle<float>(G, 0, nu1, nu2, nullptr, st);
+    if (G.boxmg)
+      boxmg_vcycle(G, 0, st);
+    else
+      vcycle<float>(G, 0, nu1, nu2, nullptr, st);
     op_launch<fcg_apply_kernelOp>(gr, BLOCK3, fcg_apply_kernelOp::Args{a, (const float*)L.f_phi, (const double*)G.kr, (const double*)G.kq, G.kw, G.k_partials, nblk, first, (const int*)G.mg_flag}, st);
     op_launch<fcg_coef_kernelOp>(dim3(1), dim3(1024), fcg_coef_kernelOp::Args{(const double*)G.k_partials, nblk, G.scalars, first, (const int*)G.mg_flag}, st);
     op_launch<fcg_update_kernelOp>(gr, BLOCK3, fcg_update_kernelOp::Args{a, (const double*)G.scalars, L.f_phi, G.kp, (const double*)G.kw, G.kq, L.phi, G.kr, L.f_rhs, first, G.mg_partials, (const int*)G.mg_flag}, st);
@@ -2580,6 +2588,545 @@ void launch_nonfinite_check(const void* x, long long n, int fp64, int* bad, hipS
 }  // namespace cpic
 
 namespace cpic {
+
+// ----------------------------------------------------------------------------
+// Variational coarse operators and zebra line relaxation (2D)
+// ----------------------------------------------------------------------------
+// The paper's solver (Sec. "Field solver") builds its coarse operators
+// variationally, A_{l+1} = P^T A_l P, and relaxes along grid lines where the
+// operator is anisotropic.  Here the two serve as the preconditioner of the
+// flexible-CG solve (CPIC_MG_BOXMG, 2D).  P is the cell-centred bilinear
+// interpolation of prolong_cell (per axis 3/4 from the own coarse cell and 1/4
+// from the neighbour on the fine cell's side; at a wall the neighbour is the
+// ghost of the correction, -e behind a Dirichlet wall and e behind a Neumann
+// one) and the restriction is its transpose.  With them every coarse operator
+// couples a cell with the 5 x 5 block around it: 25 coefficients per cell,
+// stored offset-major, coef[o * ncells + c] for the offset (dx, dy) with
+// o = dx + 2 + 5 (dy + 2).  The smoother is line Gauss-Seidel in zebra order:
+// every line along x, then every line along y, the lines of one colour at a
+// time.  The colour count is the smallest that leaves the lines of a colour
+// uncoupled (2 for the 9-point level 0, 4 for the 25-point coarse levels), so
+// the lines of a colour are relaxed together, one wave per line.
+
+constexpr int GAL_NO = 25;
+
+// interpolation of fine index x along one axis of nc coarse cells: weight wp
+// from the own coarse cell p = x / 2, wq from the neighbour q on x's side
+// (wrapped on a periodic axis; -1 with wq = 0 behind a wall)
+struct GalP {
+  int p, q;
+  double wp, wq;
+};
+__device__ inline GalP gal_p(int x, int nc, int periodic, int dir_lo, int dir_hi) {
+  GalP r;
+  r.p = x >> 1;
+  int q = r.p + ((x & 1) ? 1 : -1);
+  r.wp = 0.75;
+  r.wq = 0.25;
+  if (q < 0 || q >= nc) {
+    if (periodic) {
+      q = q < 0 ? q + nc : q - nc;
+    } else {
+      r.wp += (q < 0 ? dir_lo : dir_hi) ? -0.25 : 0.25;
+      r.wq = 0.0;
+      q = -1;
+    }
+  }
+  r.q = q;
+  return r;
+}
+
+// weight of fine index x in the interpolation from coarse cell I
+__device__ inline double gal_w(int x, int I, int nc, int periodic, int dir_lo, int dir_hi) {
+  const GalP g = gal_p(x, nc, periodic, dir_lo, dir_hi);
+  return (g.p == I ? g.wp : 0.0) + (g.q == I ? g.wq : 0.0);
+}
+
+// Coefficient A(c, c + (dx, dy)) of a 2D level: from the 9-point upper-half
+// stencil (level 0: diag, S[0] +x, S[1] +y, S[3] +x+y, S[4] +x-y; the lower
+// half read at the neighbour) or from 25 offset-major coefficients.  Zero
+// when the neighbour lies behind a wall.
+template <typename T>
+struct Stencil2 {
+  int n0, n1, per0, per1;
+  const T* diag;
+  const T* S[5];  // +x, +y, (unused), +x+y, +x-y
+  const T* g25;   // 25 offset-major coefficients, or null for the 9-point form
+  __device__ inline bool nb(int i, int j, int dx, int dy, int* c) const {
+    int x = i + dx, y = j + dy;
+    if (x < 0 || x >= n0) {
+      if (!per0) return false;
+      x = x < 0 ? x + n0 : x - n0;
+    }
+    if (y < 0 || y >= n1) {
+      if (!per1) return false;
+      y = y < 0 ? y + n1 : y - n1;
+    }
+    *c = x + n0 * y;
+    return true;
+  }
+  __device__ inline T coef(int i, int j, int dx, int dy) const {
+    int t;
+    if (!nb(i, j, dx, dy, &t)) return (T)0;
+    const int c = i + n0 * j;
+    if (g25) return g25[(size_t)(dx + 2 + 5 * (dy + 2)) * ((size_t)n0 * n1) + c];
+    if (dx == 0 && dy == 0) return diag[c];
+    // the pair (c, t) is stored at its lower cell
+    const T* s = nullptr;
+    int at = c;
+    if (dy == 0) {
+      s = S[0];
+      at = dx > 0 ? c : t;
+    } else if (dx == 0) {
+      s = S[1];
+      at = dy > 0 ? c : t;
+    } else if (dx == dy) {
+      s = S[3];
+      at = dx > 0 ? c : t;
+    } else {
+      s = S[4];
+      at = dx > 0 ? c : t;
+    }
+    return s ? s[at] : (T)0;
+  }
+};
+
+template <typename T>
+static Stencil2<T> stencil2(const GridCtx& G, int l);
+template <>
+Stencil2<double> stencil2<double>(const GridCtx& G, int l) {
+  const Level& L = G.lev[l];
+  Stencil2<double> s;
+  s.n0 = L.n[0];
+  s.n1 = L.n[1];
+  s.per0 = G.g.periodic[0];
+  s.per1 = G.g.periodic[1];
+  s.diag = L.diag;
+  for (int k = 0; k < 5; ++k) s.S[k] = L.S[k];
+  s.g25 = l > 0 ? L.gal64 : nullptr;
+  return s;
+}
+template <>
+Stencil2<float> stencil2<float>(const GridCtx& G, int l) {
+  const Level& L = G.lev[l];
+  Stencil2<float> s;
+  s.n0 = L.n[0];
+  s.n1 = L.n[1];
+  s.per0 = G.g.periodic[0];
+  s.per1 = G.g.periodic[1];
+  s.diag = L.f_diag;
+  for (int k = 0; k < 5; ++k) s.S[k] = L.f_S[k];
+  s.g25 = l > 0 ? L.gal32 : nullptr;
+  return s;
+}
+
+// A_{l+1} = P^T A_l P, one thread per coarse cell I: every fine cell f that I
+// interpolates to (a 4 x 4 block), every coupling (f, g) of the fine operator,
+// every coarse cell J that interpolates to g.  Offsets J - I are taken in
+// [-2, 2] (on a periodic axis of 4 coarse cells +2 and -2 name the same cell
+// and the coupling is kept under -2).
+template <int FR>
+__global__ __launch_bounds__(256) void galerkin_kernel(Stencil2<double> A, int nc0, int nc1, int dlo0, int dhi0,
+                                                       int dlo1, int dhi1, double* out) {
+  const int C = blockIdx.x * blockDim.x + threadIdx.x;
+  if (C >= nc0 * nc1) return;
+  const int I0 = C % nc0, I1 = C / nc0;
+  double acc[GAL_NO];
+  for (int o = 0; o < GAL_NO; ++o) acc[o] = 0.0;
+  for (int ty = -1; ty <= 2; ++ty) {
+    int fy = 2 * I1 + ty;
+    if (fy < 0 || fy >= A.n1) {
+      if (!A.per1) continue;
+      fy = fy < 0 ? fy + A.n1 : fy - A.n1;
+    }
+    const double wy = gal_w(fy, I1, nc1, A.per1, dlo1, dhi1);
+    if (wy == 0.0) continue;
+    for (int tx = -1; tx <= 2; ++tx) {
+      int fx = 2 * I0 + tx;
+      if (fx < 0 || fx >= A.n0) {
+        if (!A.per0) continue;
+        fx = fx < 0 ? fx + A.n0 : fx - A.n0;
+      }
+      const double wf = gal_w(fx, I0, nc0, A.per0, dlo0, dhi0) * wy;
+      if (wf == 0.0) continue;
+      for (int oy = -FR; oy <= FR; ++oy)
+        for (int ox = -FR; ox <= FR; ++ox) {
+          const double a = A.coef(fx, fy, ox, oy);
+          if (a == 0.0) continue;
+          int g;
+          A.nb(fx, fy, ox, oy, &g);
+          const GalP px = gal_p(g % A.n0, nc0, A.per0, dlo0, dhi0);
+          const GalP py = gal_p(g / A.n0, nc1, A.per1, dlo1, dhi1);
+          const int jx[2] = {px.p, px.q}, jy[2] = {py.p, py.q};
+          const double wx[2] = {px.wp, px.wq}, wyy[2] = {py.wp, py.wq};
+          for (int b = 0; b < 2; ++b) {
+            if (wyy[b] == 0.0) continue;
+            int dy = jy[b] - I1;
+            if (A.per1) dy = ((dy + 2) % nc1 + nc1) % nc1 - 2;
+            for (int q = 0; q < 2; ++q) {
+              if (wx[q] == 0.0) continue;
+              int dx = jx[q] - I0;
+              if (A.per0) dx = ((dx + 2) % nc0 + nc0) % nc0 - 2;
+              acc[dx + 2 + 5 * (dy + 2)] += wf * a * wx[q] * wyy[b];
+            }
+          }
+        }
+    }
+  }
+  const size_t nc = (size_t)nc0 * nc1;
+  for (int o = 0; o < GAL_NO; ++o) out[(size_t)o * nc + C] = acc[o];
+}
+
+__global__ void f64_to_f32_kernel(long long n, const double* __restrict__ a, float* b) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+int setup_galerkin(GridCtx& G, hipStream_t st) {
+  if (!G.boxmg) return 0;
+  for (int l = 0; l + 1 < G.nlev; ++l) {
+    const Level& C = G.lev[l + 1];
+    const Stencil2<double> A = stencil2<double>(G, l);
+    const unsigned blocks = (unsigned)((C.ncells + 255) / 256);
+    const int d0 = G.bc_lo[0] == BC_DIRICHLET, e0 = G.bc_hi[0] == BC_DIRICHLET;
+    const int d1 = G.bc_lo[1] == BC_DIRICHLET, e1 = G.bc_hi[1] == BC_DIRICHLET;
+    if (l == 0)
+      hipLaunchKernelGGL(galerkin_kernel<1>, dim3(blocks), dim3(256), 0, st, A, C.n[0], C.n[1], d0, e0, d1, e1,
+                         C.gal64);
+    else
+      hipLaunchKernelGGL(galerkin_kernel<2>, dim3(blocks), dim3(256), 0, st, A, C.n[0], C.n[1], d0, e0, d1, e1,
+                         C.gal64);
+    const long long n = (long long)GAL_NO * C.ncells;
+    hipLaunchKernelGGL(f64_to_f32_kernel, dim3((unsigned)std::min<long long>((n + 255) / 256, 4096)), dim3(256), 0,
+                       st, n, (const double*)C.gal64, C.gal32);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// column j of the coarsest operator of the variational hierarchy, A e_j (one
+// workgroup per column)
+__global__ __launch_bounds__(256) void dense_galerkin_kernel(Stencil2<double> A, double* M) {
+  const int n = A.n0 * A.n1;
+  const int j = blockIdx.x;
+  const int R = A.g25 ? 2 : 1;  // a single-level hierarchy keeps the 9-point level 0
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int i0 = i % A.n0, i1 = i / A.n0;
+    double s = 0.0;
+    for (int dy = -R; dy <= R; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        int t;
+        if (A.nb(i0, i1, dx, dy, &t) && t == j) s += A.coef(i0, i1, dx, dy);
+      }
+    M[(size_t)j * n + i] = s;
+  }
+}
+void launch_dense_galerkin(const GridCtx& G, double* M, hipStream_t st) {
+  const int l = G.nlev - 1;
+  hipLaunchKernelGGL(dense_galerkin_kernel, dim3((unsigned)G.lev[l].ncells), dim3(256), 0, st,
+                     stencil2<double>(G, l), M);
+}
+
+// ---- one wave per line: partitioned elimination + cyclic reduction ---------
+// The line's tridiagonal system (the couplings along the line; every other
+// coupling stays in the residual) is split into K segments of consecutive
+// cells, one per lane (K a power of two, at most 64, segments of at least two
+// cells).  Each lane eliminates its segment's interior rows, leaving them in
+// terms of the segment's first and last unknowns; the first and last rows of
+// all segments form a tridiagonal system of 2K rows (cyclic on a periodic
+// line), solved by parallel cyclic reduction; the interior follows.  Element i
+// of segment k sits at LDS index i + k (one pad word per segment keeps the
+// lanes' strided accesses on different banks).
+constexpr int LINE_MAXN = 4096;
+constexpr int LINE_LDS_WORDS = 3 * (LINE_MAXN + 64) + 4 * 128;
+
+struct LineSeg {
+  int K, m, rem;
+  __device__ inline int start(int k) const { return k * m + (k < rem ? k : rem); }
+  __device__ inline int seg(int i) const {
+    const int big = rem * (m + 1);
+    return i < big ? i / (m + 1) : rem + (i - big) / m;
+  }
+};
+
+template <typename T, bool G25>
+struct LineRelaxArgs {
+  Stencil2<T> A;
+  T* x;
+  const T* rhs;
+  int axis;   // 0: lines along x (one per row j), 1: along y (one per column i)
+  int color;  // this launch relaxes the lines color, color + ncolor, ...
+  int ncolor;
+  const int* flag;
+};
+
+template <typename T, bool G25>
+__global__ __launch_bounds__(64) void line_relax_kernel(LineRelaxArgs<T, G25> k) {
+  if (k.flag[0]) return;
+  extern __shared__ float lds[];
+  const Stencil2<T>& A = k.A;
+  const int ax = k.axis;
+  const int n = ax == 0 ? A.n0 : A.n1;          // cells along the line
+  const int line = k.color + k.ncolor * blockIdx.x;  // the cross coordinate
+  const int per = ax == 0 ? A.per0 : A.per1;
+  const int lane = threadIdx.x;
+  LineSeg S;
+  S.K = 1;
+  while (S.K * 2 <= 64 && S.K * 4 <= n) S.K *= 2;
+  S.m = n / S.K;
+  S.rem = n % S.K;
+  const int stride = n + S.K;
+  float* Rv = lds;               // rhs, then h
+  float* Dv = lds + stride;      // diagonal, then f
+  float* Uv = lds + 2 * stride;  // upper coupling, then g
+  float* red = lds + 3 * stride; // reduced system: a, b, c, d of 2K rows
+  // residual b - A x of every cell of the line and its line couplings
+  for (int t = lane; t < n; t += 64) {
+    const int i = ax == 0 ? t : line, j = ax == 0 ? line : t;
+    const int c = i + A.n0 * j;
+    T r = k.rhs[c];
+    constexpr int R = G25 ? 2 : 1;
+    for (int dy = -R; dy <= R; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        int nbc;
+        if (!A.nb(i, j, dx, dy, &nbc)) continue;
+        r -= A.coef(i, j, dx, dy) * k.x[nbc];
+      }
+    const int p = t + S.seg(t);
+    Rv[p] = (float)r;
+    Dv[p] = (float)A.coef(i, j, 0, 0);
+    // coupling to the next cell of the line (zero at the end of a bounded line)
+    Uv[p] = (float)(ax == 0 ? A.coef(i, j, 1, 0) : A.coef(i, j, 0, 1));
+  }
+  __syncthreads();
+  // this lane's segment [s, e]; its boundary rows before elimination
+  const int K = S.K;
+  float ra[2] = {0.f, 0.f}, rb[2], rc[2], rd[2];
+  const int s = S.start(lane), e = S.start(lane + 1) - 1;
+  const int ps = s + lane, pe = e + lane;
+  if (lane < K) {
+    // a_i = coupling to the previous cell = U of the previous cell
+    const int prev = s > 0 ? s - 1 : n - 1;
+    ra[0] = (s > 0 || per) ? Uv[prev + S.seg(prev)] : 0.f;
+    rb[0] = Dv[ps];
+    rc[0] = Uv[ps];
+    rd[0] = Rv[ps];
+    ra[1] = Uv[pe - 1];  // segments hold at least two cells
+    rb[1] = Dv[pe];
+    rc[1] = (e < n - 1 || per) ? Uv[pe] : 0.f;
+    rd[1] = Rv[pe];
+    if (e - s >= 2) {
+      // forward over the interior rows s+1 .. e-1 (fill-in on x_s):
+      // f_i x_s + x_i + g_i x_{i+1} = h_i
+      float a = Uv[ps];  // coupling of row s+1 to row s
+      float fp = 0.f, gp = 0.f, hp = 0.f;
+      for (int i = s + 1; i < e; ++i) {
+        const int p = i + lane;
+        const float b = Dv[p], c = Uv[p], d = Rv[p];
+        float f, g, h;
+        if (i == s + 1) {
+          const float im = 1.f / b;
+          f = a * im;
+          g = c * im;
+          h = d * im;
+        } else {
+          const float im = 1.f / (b - a * gp);
+          f = -a * fp * im;
+          g = c * im;
+          h = (d - a * hp) * im;
+        }
+        Dv[p] = f;
+        Uv[p] = g;
+        Rv[p] = h;
+        fp = f;
+        gp = g;
+        hp = h;
+        a = c;
+      }
+      // backward: x_i = h'_i - f'_i x_s - g'_i x_e
+      float fn = fp, gn = gp, hn = hp;  // row e-1 as is
+      for (int i = e - 2; i > s; --i) {
+        const int p = i + lane;
+        const float g = Uv[p];
+        const float h = Rv[p] - g * hn, f = Dv[p] - g * fn, gg = -g * gn;
+        Rv[p] = h;
+        Dv[p] = f;
+        Uv[p] = gg;
+        fn = f;
+        gn = gg;
+        hn = h;
+      }
+      // first and last rows in terms of x_{prev}, x_s, x_e, x_{next}
+      const float f1 = Dv[ps + 1], g1 = Uv[ps + 1], h1 = Rv[ps + 1];
+      rd[0] -= rc[0] * h1;
+      rb[0] -= rc[0] * f1;
+      rc[0] = -rc[0] * g1;
+      const float fe = Dv[pe - 1], ge = Uv[pe - 1], he = Rv[pe - 1];
+      rd[1] -= ra[1] * he;
+      rb[1] -= ra[1] * ge;
+      ra[1] = -ra[1] * fe;
+    }
+  }
+  // parallel cyclic reduction over the 2K boundary rows (row 2k: x_s of
+  // segment k, row 2k+1: its x_e), cyclic indices
+  const int M = 2 * K;
+  float* RA = red;
+  float* RB = red + 128;
+  float* RC = red + 256;
+  float* RD = red + 384;
+  if (lane < K)
+    for (int q = 0; q < 2; ++q) {
+      RA[2 * lane + q] = ra[q];
+      RB[2 * lane + q] = rb[q];
+      RC[2 * lane + q] = rc[q];
+      RD[2 * lane + q] = rd[q];
+    }
+  __syncthreads();
+  for (int off = 1; off < M; off *= 2) {
+    float na[2], nbv[2], nc[2], nd[2];
+    if (lane < K)
+      for (int q = 0; q < 2; ++q) {
+        const int r = 2 * lane + q;
+        const int im = (r - off + M) % M, ip = (r + off) % M;
+        const float k1 = RA[r] / RB[im], k2 = RC[r] / RB[ip];
+        na[q] = -k1 * RA[im];
+        nc[q] = -k2 * RC[ip];
+        nbv[q] = RB[r] - k1 * RC[im] - k2 * RA[ip];
+        nd[q] = RD[r] - k1 * RD[im] - k2 * RD[ip];
+      }
+    __syncthreads();
+    if (lane < K)
+      for (int q = 0; q < 2; ++q) {
+        const int r = 2 * lane + q;
+        RA[r] = na[q];
+        RB[r] = nbv[q];
+        RC[r] = nc[q];
+        RD[r] = nd[q];
+      }
+    __syncthreads();
+  }
+  // couplings now reach 2K rows away: the row itself
+  float xs = 0.f, xe = 0.f;
+  if (lane < K) {
+    xs = RD[2 * lane] / (RB[2 * lane] + RA[2 * lane] + RC[2 * lane]);
+    xe = RD[2 * lane + 1] / (RB[2 * lane + 1] + RA[2 * lane + 1] + RC[2 * lane + 1]);
+  }
+  // corrections of the segment (the interior from the eliminated rows)
+  if (lane < K)
+    for (int i = s; i <= e; ++i) {
+      float dlt;
+      if (i == s)
+        dlt = xs;
+      else if (i == e)
+        dlt = xe;
+      else {
+        const int p = i + lane;
+        dlt = Rv[p] - Dv[p] * xs - Uv[p] * xe;
+      }
+      const int c = ax == 0 ? i + A.n0 * line : line + A.n0 * i;
+      k.x[c] += (T)dlt;
+    }
+}
+
+// residual of a 25-point level
+__global__ __launch_bounds__(256) void residual25_kernel(Stencil2<float> A, const float* __restrict__ x,
+                                                         const float* __restrict__ rhs, float* res, const int* flag) {
+  if (flag[0]) return;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= A.n0 * A.n1) return;
+  const int i = c % A.n0, j = c / A.n0;
+  float r = rhs[c];
+  for (int dy = -2; dy <= 2; ++dy)
+    for (int dx = -2; dx <= 2; ++dx) {
+      int t;
+      if (!A.nb(i, j, dx, dy, &t)) continue;
+      r -= A.coef(i, j, dx, dy) * x[t];
+    }
+  res[c] = r;
+}
+
+// x = Cinv rhs on the coarsest level (one workgroup)
+__global__ __launch_bounds__(1024) void dense_solve_kernel(int n, const float* __restrict__ cinv,
+                                                           const float* __restrict__ rhs, float* x, const int* flag) {
+  if (flag[0]) return;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    float s = 0.f;
+    for (int j = 0; j < n; ++j) s += cinv[(size_t)j * n + i] * rhs[j];
+    x[i] = s;
+  }
+}
+
+// colours of the lines along `axis` on a level: the smallest count c >= 2 R
+// (R the stencil's reach across lines) that divides the line count when the
+// cross axis is periodic (lines 0 and n - 1 are then neighbours)
+static int line_colors(int nlines, int per, int reach) {
+  for (int c = 2 * reach; c < nlines; ++c)
+    if (!per || nlines % c == 0) return c;
+  return nlines;
+}
+
+static void line_sweep(const GridCtx& G, int l, int axis, bool reverse, hipStream_t st) {
+  const Level& L = G.lev[l];
+  const int nl = axis == 0 ? L.n[1] : L.n[0];  // number of lines
+  const int per = axis == 0 ? G.g.periodic[1] : G.g.periodic[0];
+  const int reach = l > 0 ? 2 : 1;
+  const int nc = line_colors(nl, per, reach);
+  const int n = axis == 0 ? L.n[0] : L.n[1];
+  const size_t lds = sizeof(float) * (3 * (size_t)(n + 64) + 4 * 128);
+  for (int q = 0; q < nc; ++q) {
+    const int col = reverse ? nc - 1 - q : q;
+    const unsigned lines = (unsigned)((nl - col + nc - 1) / nc);
+    if (l > 0) {
+      LineRelaxArgs<float, true> a{stencil2<float>(G, l), L.f_phi, L.f_rhs, axis, col, nc, G.mg_flag};
+      hipLaunchKernelGGL((line_relax_kernel<float, true>), dim3(lines), dim3(64), lds, st, a);
+    } else {
+      LineRelaxArgs<float, false> a{stencil2<float>(G, l), L.f_phi, L.f_rhs, axis, col, nc, G.mg_flag};
+      hipLaunchKernelGGL((line_relax_kernel<float, false>), dim3(lines), dim3(64), lds, st, a);
+    }
+  }
+}
+
+// one relaxation: lines along x, then along y (post-smoothing: the reverse)
+static void line_relax(const GridCtx& G, int l, bool post, hipStream_t st) {
+  if (!post) {
+    line_sweep(G, l, 0, false, st);
+    line_sweep(G, l, 1, false, st);
+  } else {
+    line_sweep(G, l, 1, true, st);
+    line_sweep(G, l, 0, true, st);
+  }
+}
+
+// V(1,2) cycle of the variational hierarchy on the FP32 vectors (level 0:
+// z = f_phi, zero on entry, from r = f_rhs): one relaxation before the coarse
+// correction, two after (on the spherical r-z test, 5 flexible-CG iterations to
+// 1e-10 at 1024^2 where V(1,1) takes 7 and V(2,2) 5 at a third more work)
+static void boxmg_vcycle(const GridCtx& G, int l, hipStream_t st) {
+  const Level& L = G.lev[l];
+  if (l == G.nlev - 1) {
+    if (G.cinv32) {
+      hipLaunchKernelGGL(dense_solve_kernel, dim3(1), dim3(1024), 0, st, (int)L.ncells, (const float*)G.cinv32,
+                         (const float*)L.f_rhs, L.f_phi, (const int*)G.mg_flag);
+    } else {
+      for (int s = 0; s < 4; ++s) line_relax(G, l, s & 1, st);
+    }
+    return;
+  }
+  line_relax(G, l, false, st);
+  const Level& C = G.lev[l + 1];
+  const LevelArgsT<float> fa = level_args_f32(G, l);
+  if (l == 0) {
+    op_launch<residual_kernelOp<float>>(grid3(L), BLOCK3, residual_kernelOp<float>::Args{fa, (const float*)L.f_phi, (const float*)L.f_rhs, L.f_res, (const int*)G.mg_flag}, st);
+  } else {
+    hipLaunchKernelGGL(residual25_kernel, dim3((unsigned)((L.ncells + 255) / 256)), dim3(256), 0, st,
+                       stencil2<float>(G, l), (const float*)L.f_phi, (const float*)L.f_rhs, L.f_res,
+                       (const int*)G.mg_flag);
+  }
+  op_launch<restrict_kernelOp<float>>(grid3(C), BLOCK3, restrict_kernelOp<float>::Args{fa, (const float*)L.f_res, C.n[0], C.n[1], C.n[2], C.f_rhs, C.f_phi, (const int*)G.mg_flag}, st);
+  boxmg_vcycle(G, l + 1, st);
+  op_launch<prolong_kernelOp<float>>(grid3(L), BLOCK3, prolong_kernelOp<float>::Args{fa, L.f_phi, (const float*)C.f_phi, C.n[0], C.n[1], C.n[2], (const int*)G.mg_flag}, st);
+  line_relax(G, l, true, st);
+  line_relax(G, l, true, st);
+}
 
 // ----------------------------------------------------------------------------
 // replay of recorded field phases as batched launches (see kernels.hpp)

@@ -148,6 +148,10 @@ struct Level {
   float* f_rhs;
   float* f_res;
   float* f_aux;
+  // variational coarse operator (levels >= 1 of CPIC_MG_BOXMG, 2D): 25
+  // coefficients per cell, offset-major, FP64 and its FP32 copy
+  double* gal64;
+  float* gal32;
 };
 
 struct GridCtx {
@@ -180,6 +184,7 @@ struct GridCtx {
   double* phi_full;   // phi_0 + phi_w phi_1 (the potential); scalars [10] phi_w [11] Q_w [12] F(phi_1)
   double anisotropy;      // largest ratio of a level-0 cell's face coefficients
   int restrict_transpose; // restriction = transpose of the prolongation (else summing)
+  int boxmg;              // preconditioner: variational coarse operators + zebra line relaxation (2D)
   double* cinv64;     // dense inverse of the coarsest operator (<= DENSE_MAX cells), or null
   float* cinv32;      // its FP32 copy (flexible-CG preconditioner)
   double* kr;         // residual b - A x
@@ -208,6 +213,8 @@ int compute_smoother_bounds(GridCtx& G, hipStream_t st);
 void launch_operator_f32(const GridCtx& G, hipStream_t st);
 int setup_coarse_inverse(GridCtx& G, hipStream_t st);
 int setup_floating_wall(GridCtx& G, hipStream_t st);
+// coarse operators P^T A P of the CPIC_MG_BOXMG hierarchy (set-up, before the coarse inverse)
+int setup_galerkin(GridCtx& G, hipStream_t st);
 // charge of a floating wall: sum over species of q w (particles it absorbed)
 struct WallCharge {
   int nsp;
