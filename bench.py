@@ -669,6 +669,29 @@ def field_solve_mms(sizes=(1024, 2048, 4096), rtol=1e-10, reps=3, method=0):
             "grids": out}
 
 
+def extra_table(C):
+    """The other workloads: name -> (workload, shape, precision, steps, mover,
+    tabulated map, pusher)."""
+    return {
+        "box3d_128_b1": ("box3d_128", "b1", C.FP32, 10, 0, False, 0),
+        "box3d_128_b1_fp64": ("box3d_128", "b1", C.FP64, 10, 0, False, 0),
+        "box3d_128_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC, False, 0),
+        "box3d_128_tabulated": ("box3d_128", "b2", C.FP32, 10, 0, True, 0),
+        "box3d_128_tabulated_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC, True, 0),
+        "probe2d_512": ("probe2d_512", "b2", C.FP32, 200, 0, False, 0),
+        "box3d_magnetized": ("box3d_magnetized", "b2", C.FP32, 10, 0, False, 0),
+        "box3d_magnetized_cyclotronic": ("box3d_magnetized", "b2", C.FP32, 10, 0, False, C.PUSH_CYCLOTRONIC)}
+
+
+def run_extra(C, key, args, steps=None):
+    name, shp, prec, n, mover, tab, push = extra_table(C)[key]
+    # the probe is timed in its injected steady state: the last 200 of the
+    # configuration's 2,000 steps
+    warm = 1800 if name == "probe2d_512" else 2
+    return extra_workload(name, shp, prec, steps or n, warm, args.sort_every, args.mg_rtol, args.mg_cycles,
+                          mover, tab, push)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -677,9 +700,11 @@ def main():
     ap.add_argument("--workload", default="box3d_128")
     ap.add_argument("--shape", default="b2", choices=["b2", "b1"])
     ap.add_argument("--sort-every", type=int, default=4)
-    # relative residual 1e-5: far below the particle noise of the charge density
-    # (about 1/sqrt(32) per cell here); the cap is not reached in practice
-    ap.add_argument("--mg-rtol", type=float, default=1e-5)
+    # relative residual 4e-6: far below the particle noise of the charge density
+    # (about 1/sqrt(32) per cell here) and small enough that phi and E stay within
+    # 1e-5 of the FP64 oracle (with 1e-5, E reached 1.35e-5 on the 2D Langmuir
+    # case); the cap is not reached in practice
+    ap.add_argument("--mg-rtol", type=float, default=4e-6)
     ap.add_argument("--mg-cycles", type=int, default=10)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -687,6 +712,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=24 << 20)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (B1 deposit, probe, magnetised box)")
+    ap.add_argument("--only-extra", default=None,
+                    help="only run this one of the other workloads (e.g. box3d_128_tabulated) and print its "
+                         "result")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--serve", action="store_true",
@@ -707,6 +735,12 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibrate:
         copy_calibrate(1 << 30, 5)
+        return
+    if args.only_extra:
+        from paper_1311_2286_amd import cpic as C
+        C.load()
+        print(json.dumps({"workload": args.only_extra,
+                          "result": run_extra(C, args.only_extra, args, args.steps)}), flush=True)
         return
     if args.serve:
         from paper_1311_2286_amd import cpic as C
@@ -759,22 +793,9 @@ def main():
         log("errors", json.dumps(errors))
     extra = {}
     if not args.no_extra:
-        for key, (name, shp, prec, steps, mover, tab, push) in {
-                "box3d_128_b1": ("box3d_128", "b1", C.FP32, 10, 0, False, 0),
-                "box3d_128_b1_fp64": ("box3d_128", "b1", C.FP64, 10, 0, False, 0),
-                "box3d_128_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC, False, 0),
-                "box3d_128_tabulated": ("box3d_128", "b2", C.FP32, 10, 0, True, 0),
-                "box3d_128_tabulated_pc": ("box3d_128", "b2", C.FP32, 10, C.MOVER_PC, True, 0),
-                "probe2d_512": ("probe2d_512", "b2", C.FP32, 200, 0, False, 0),
-                "box3d_magnetized": ("box3d_magnetized", "b2", C.FP32, 10, 0, False, 0),
-                "box3d_magnetized_cyclotronic": ("box3d_magnetized", "b2", C.FP32, 10, 0, False,
-                                                 C.PUSH_CYCLOTRONIC)}.items():
-            # the probe is timed in its injected steady state: the last 200 of the
-            # configuration's 2,000 steps
-            warm = 1800 if name == "probe2d_512" else 2
+        for key in extra_table(C):
             try:
-                extra[key] = extra_workload(name, shp, prec, steps, warm, args.sort_every, args.mg_rtol,
-                                            args.mg_cycles, mover, tab, push)
+                extra[key] = run_extra(C, key, args)
             except Exception as e:  # reported, never fatal for the headline line
                 extra[key] = {"error": repr(e)}
         try:

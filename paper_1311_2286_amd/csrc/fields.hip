@@ -132,7 +132,8 @@ __device__ inline Blk blk_batch(int gz) {
 enum BatchKind : int {
   BK_CHARGE = 1, BK_EXTRAP, BK_RHS, BK_SUB, BK_REDP, BK_REDF, BK_RESET, BK_FCGRES, BK_FCGAPPLY, BK_FCGCOEF,
   BK_FCGUPD, BK_SMOOTH_F, BK_SMOOTH_D, BK_RESID_F, BK_RESID_D, BK_RSUM_F, BK_RSUM_D, BK_RTR_F, BK_RTR_D,
-  BK_PROL_F, BK_PROL_D, BK_SMALL_F, BK_SMALL_D, BK_EF2F, BK_EF2D, BK_EF3F, BK_EF3D, BK_COUNT
+  BK_PROL_F, BK_PROL_D, BK_SMALL_F, BK_SMALL_D, BK_EF2F, BK_EF2D, BK_EF3F, BK_EF3D, BK_RESR_F, BK_RESR_D,
+  BK_COUNT
 };
 template <typename T>
 constexpr int kind_of(int kf, int kd) {
@@ -1025,6 +1026,83 @@ __device__ inline T restrict_cell(const LevelArgsT<T>& fa, const T* __restrict__
   return s;
 }
 
+// The first Chebyshev step of a smoothing that starts from a zero guess needs
+// no residual: phi2 = aux = cr r / diag (then the step from phi2 follows).
+// Kernels that produce the right side r of such a level apply it as they
+// write r, which saves that step's pass over the level.
+struct FirstSweep {
+  const float* diag;  // null: not applied
+  float* phi2;
+  float* aux;
+  float cr;
+  __device__ inline void apply(int c, float r) const {
+    const float d = cr * r / diag[c];
+    phi2[c] = d;
+    aux[c] = d;
+  }
+};
+template <typename T>
+struct FirstSweepT {
+  const T* diag;
+  T* phi2;
+  T* aux;
+  double cr;
+};
+
+// Residual of the fine level summed over each coarse cell's children (the
+// summing restriction); coarse phi = 0, or with fs.diag set the coarse
+// level's first Chebyshev step from zero.  Threads take fine cells as the
+// residual kernel does (64 x 4 per workgroup, consecutive i in a wave, so
+// every load is coalesced), each the two cells of a column pair in z (3D);
+// the pairs along i add by a lane shuffle, along j through LDS.  Fixed
+// summation order: bitwise reproducible.
+template <typename T>
+struct resrestrict_kernelOp {
+  static constexpr int KIND = kind_of<T>(BK_RESR_F, BK_RESR_D), BOUND = 256;
+  struct Args {
+    LevelArgsT<T> a;
+    const T* phi;
+    const T* rhs;
+    int nc0;
+    int nc1;
+    T* crhs;
+    T* cphi;
+    FirstSweepT<T> fs;
+    const int* flag;
+  };
+  static __device__ void body(const Args& k_, const Blk& b_) {
+    if (k_.flag[0]) return;
+    const LevelArgsT<T>& a = k_.a;
+    const int i = b_.x * 64 + threadIdx.x, j = b_.y * 4 + threadIdx.y, K = b_.z;
+    T s = (T)0;
+    if (i < a.n[0] && j < a.n[1]) {
+      const int nz = a.dim == 3 ? 2 : 1;
+      for (int dz = 0; dz < nz; ++dz) {
+        const int k = a.dim == 3 ? 2 * K + dz : 0;
+        const int idx[3] = {i, j, k};
+        const int c = i + a.n[0] * (j + a.n[1] * k);
+        s += k_.rhs[c] - apply_A(a, k_.phi, idx, c);
+      }
+    }
+    s += __shfl_xor(s, 1, 64);
+    __shared__ T row[4][64];
+    row[threadIdx.y][threadIdx.x] = s;
+    __syncthreads();
+    if ((threadIdx.x & 1) || (threadIdx.y & 1) || i >= a.n[0] || j >= a.n[1]) return;
+    s += row[threadIdx.y + 1][threadIdx.x];
+    const int I0 = i >> 1, I1 = j >> 1;
+    const int C = I0 + k_.nc0 * (I1 + k_.nc1 * K);
+    k_.crhs[C] = s;
+    if (k_.fs.diag) {
+      const T d = (T)k_.fs.cr * s / k_.fs.diag[C];
+      k_.fs.phi2[C] = d;
+      k_.fs.aux[C] = d;
+    } else {
+      k_.cphi[C] = (T)0;
+    }
+  }
+};
+
 // summing restriction of a residual array (multi-workgroup levels)
 template <typename T>
 struct restrict_sum_kernelOp {
@@ -1672,7 +1750,7 @@ static int first_small_level(const GridCtx& G) {
 // squared residual of its input.
 template <typename T>
 static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStream_t st,
-                      double* first_partials = nullptr, double rtol2 = 0.0) {
+                      double* first_partials = nullptr, double rtol2 = 0.0, bool first_done = false) {
   const Level& L = G.lev[l];
   const LevelArgsT<T> a = level_args_t<T>(G, l);
   const LevelVec<T> v = level_vec<T>(G, l);
@@ -1680,7 +1758,9 @@ static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStre
   const double lmax = L.lam_max, lmin = L.lam_max / 8.0;
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   double rho = 1.0 / sigma;
-  for (int s = 0; s < nu; ++s) {
+  // first_done: the step from the zero guess was taken by the kernel that
+  // wrote the right side (phi2 and aux hold it)
+  for (int s = first_done ? 1 : 0; s < nu; ++s) {
     const T* in = (s & 1) ? v.phi2 : v.phi;
     T* out = (s & 1) ? v.phi : v.phi2;
     double cr, cd;
@@ -1813,12 +1893,33 @@ static void line_sweeps(const GridCtx& G, int l, int nu, bool reverse, hipStream
     }
 }
 
+// whether the smoothing of a multi-workgroup level is the segment line
+// relaxation (FP32 preconditioner of an anisotropic operator)
+static bool line_level(const GridCtx& G, int nu, bool fp32) {
+  const int nl = G.g.dim == 2 ? nu / 2 : nu;
+  return fp32 && G.anisotropy > LINE_ANISO && nl > 0 && (nl * G.g.dim) % 2 == 0;
+}
+static int first_small_level(const GridCtx& G);
+template <typename T>
+static FirstSweepT<T> first_sweep(const GridCtx& G, int l, int nu) {
+  FirstSweepT<T> f;
+  memset(&f, 0, sizeof(f));
+  if (l >= first_small_level(G) || nu < 2 || line_level(G, nu, sizeof(T) == 4)) return f;
+  const LevelVec<T> v = level_vec<T>(G, l);
+  const double lmax = G.lev[l].lam_max, lmin = lmax / 8.0;
+  f.diag = level_args_t<T>(G, l).diag;
+  f.phi2 = v.phi2;
+  f.aux = v.aux;
+  f.cr = 1.0 / (0.5 * (lmax + lmin));
+  return f;
+}
+
 // the smoother of a multi-workgroup level: segment line relaxation for the
 // preconditioner of an anisotropic operator (its summed residual is not
 // needed there), Chebyshev otherwise
 template <typename T>
 static void smooth_level(const GridCtx& G, int l, int nu, bool post, double* partials, hipStream_t st,
-                         double* first_partials = nullptr, double rtol2 = 0.0) {
+                         double* first_partials = nullptr, double rtol2 = 0.0, bool first_done = false) {
   if constexpr (sizeof(T) == 4) {
     // one sweep along every axis in place of two point-smoothing steps (2D;
     // in 3D two, so that the result ends in phi), the post-smoothing in
@@ -1829,7 +1930,7 @@ static void smooth_level(const GridCtx& G, int l, int nu, bool post, double* par
       return;
     }
   }
-  chebyshev<T>(G, l, nu, partials, st, first_partials, rtol2);
+  chebyshev<T>(G, l, nu, partials, st, first_partials, rtol2, first_done);
 }
 
 // One V-cycle from level l in precision T.  With partials != null, the last
@@ -1837,7 +1938,7 @@ static void smooth_level(const GridCtx& G, int l, int nu, bool post, double* par
 // block.
 template <typename T>
 static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, hipStream_t st,
-                   double* first_partials = nullptr, double rtol2 = 0.0) {
+                   double* first_partials = nullptr, double rtol2 = 0.0, bool first_done = false) {
   const int ls = first_small_level(G);
   if (l >= ls) {
     SmallLevels<T> S;
@@ -1864,15 +1965,22 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
   const LevelArgsT<T> a = level_args_t<T>(G, l);
   const LevelVec<T> v = level_vec<T>(G, l);
   const dim3 gr = grid3(L);
-  smooth_level<T>(G, l, nu1, false, nullptr, st, first_partials, rtol2);
+  smooth_level<T>(G, l, nu1, false, nullptr, st, first_partials, rtol2, first_done);
   const Level& C = G.lev[l + 1];
   const LevelVec<T> cv = level_vec<T>(G, l + 1);
-  op_launch<residual_kernelOp<T>>(gr, BLOCK3, typename residual_kernelOp<T>::Args{a, (const T*)v.phi, (const T*)v.rhs, v.res, (const int*)G.mg_flag}, st);
-  if (G.restrict_transpose)
+  bool coarse_first = false;
+  if (G.restrict_transpose) {
+    op_launch<residual_kernelOp<T>>(gr, BLOCK3, typename residual_kernelOp<T>::Args{a, (const T*)v.phi, (const T*)v.rhs, v.res, (const int*)G.mg_flag}, st);
     op_launch<restrict_kernelOp<T>>(grid3(C), BLOCK3, typename restrict_kernelOp<T>::Args{a, (const T*)v.res, C.n[0], C.n[1], C.n[2], cv.rhs, cv.phi, (const int*)G.mg_flag}, st);
-  else
-    op_launch<restrict_sum_kernelOp<T>>(grid3(C), BLOCK3, typename restrict_sum_kernelOp<T>::Args{G.g.dim, L.n[0], L.n[1], (const T*)v.res, C.n[0], C.n[1], cv.rhs, cv.phi, (const int*)G.mg_flag}, st);
-  vcycle<T>(G, l + 1, nu1, nu2, nullptr, st);
+  } else {
+    // residual and summing restriction in one pass, with the coarse level's
+    // first smoothing step from its zero guess
+    const FirstSweepT<T> fs = first_sweep<T>(G, l + 1, nu1);
+    coarse_first = fs.diag != nullptr;
+    const dim3 rg((unsigned)((L.n[0] + 63) / 64), (unsigned)((L.n[1] + 3) / 4), (unsigned)C.n[2]);
+    op_launch<resrestrict_kernelOp<T>>(rg, dim3(64, 4, 1), typename resrestrict_kernelOp<T>::Args{a, (const T*)v.phi, (const T*)v.rhs, C.n[0], C.n[1], cv.rhs, cv.phi, fs, (const int*)G.mg_flag}, st);
+  }
+  vcycle<T>(G, l + 1, nu1, nu2, nullptr, st, nullptr, 0.0, coarse_first);
   op_launch<prolong_kernelOp<T>>(gr, BLOCK3, typename prolong_kernelOp<T>::Args{a, v.phi, (const T*)cv.phi, C.n[0], C.n[1], C.n[2], (const int*)G.mg_flag}, st);
   smooth_level<T>(G, l, nu2, true, partials, st);
 }
@@ -1906,6 +2014,7 @@ struct fcg_residual_kernelOp {
     float* z;
     double* partials;
     const int* flag;
+    FirstSweep fs;
   };
   static __device__ void body(const Args& k_, const Blk& b_) {
     const LevelArgs& a = k_.a;
@@ -1929,7 +2038,10 @@ struct fcg_residual_kernelOp {
     const double v = b[c] - apply_A(a, x, idx, c);
     r[c] = v;
     r32[c] = (float)v;
-    z[c] = 0.0f;
+    if (k_.fs.diag)
+      k_.fs.apply(c, (float)v);
+    else
+      z[c] = 0.0f;
     rr = v * v;
   }
   const double t = block_sum(rr);
@@ -2049,6 +2161,7 @@ struct fcg_update_kernelOp {
     int first;
     double* partials;
     const int* flag;
+    FirstSweep fs;
   };
   static __device__ void body(const Args& k_, const Blk& b_) {
     const LevelArgs& a = k_.a;
@@ -2081,7 +2194,10 @@ struct fcg_update_kernelOp {
     const double rc = r[c] - alpha * qc;
     r[c] = rc;
     r32[c] = (float)rc;
-    z[c] = 0.0f;
+    if (k_.fs.diag)
+      k_.fs.apply(c, (float)rc);
+    else
+      z[c] = 0.0f;
     rr = rc * rc;
   }
   const double t = block_sum(rr);
@@ -2096,17 +2212,28 @@ static int launch_fcg_solve(const GridCtx& G, double rtol2, int max_iter, int nu
   LevelArgs a = level_args(G, 0);
   const dim3 gr = grid3(L);
   const int nblk = (int)(gr.x * gr.y * gr.z);
-  op_launch<fcg_residual_kernelOp>(gr, BLOCK3, fcg_residual_kernelOp::Args{a, (const double*)L.phi, (const double*)L.rhs, G.kr, L.f_rhs, L.f_phi, G.mg_partials, (const int*)G.mg_flag}, st);
+  // the preconditioner's first smoothing step on level 0 (zero guess) is taken
+  // by the kernels that write its right side
+  FirstSweep fs;
+  memset(&fs, 0, sizeof(fs));
+  if (!G.boxmg) {
+    const FirstSweepT<float> f = first_sweep<float>(G, 0, nu1);
+    fs.diag = f.diag;
+    fs.phi2 = f.phi2;
+    fs.aux = f.aux;
+    fs.cr = (float)f.cr;
+  }
+  op_launch<fcg_residual_kernelOp>(gr, BLOCK3, fcg_residual_kernelOp::Args{a, (const double*)L.phi, (const double*)L.rhs, G.kr, L.f_rhs, L.f_phi, G.mg_partials, (const int*)G.mg_flag, fs}, st);
   op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{(const double*)G.mg_partials, nblk, G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 0}, st);
   for (int it = 0; it < max_iter; ++it) {
     const int first = it == 0;
     if (G.boxmg)
       boxmg_vcycle(G, 0, st);
     else
-      vcycle<float>(G, 0, nu1, nu2, nullptr, st);
+      vcycle<float>(G, 0, nu1, nu2, nullptr, st, nullptr, 0.0, fs.diag != nullptr);
     op_launch<fcg_apply_kernelOp>(gr, BLOCK3, fcg_apply_kernelOp::Args{a, (const float*)L.f_phi, (const double*)G.kr, (const double*)G.kq, G.kw, G.k_partials, nblk, first, (const int*)G.mg_flag}, st);
     op_launch<fcg_coef_kernelOp>(dim3(1), dim3(1024), fcg_coef_kernelOp::Args{(const double*)G.k_partials, nblk, G.scalars, first, (const int*)G.mg_flag}, st);
-    op_launch<fcg_update_kernelOp>(gr, BLOCK3, fcg_update_kernelOp::Args{a, (const double*)G.scalars, L.f_phi, G.kp, (const double*)G.kw, G.kq, L.phi, G.kr, L.f_rhs, first, G.mg_partials, (const int*)G.mg_flag}, st);
+    op_launch<fcg_update_kernelOp>(gr, BLOCK3, fcg_update_kernelOp::Args{a, (const double*)G.scalars, L.f_phi, G.kp, (const double*)G.kw, G.kq, L.phi, G.kr, L.f_rhs, first, G.mg_partials, (const int*)G.mg_flag, fs}, st);
     op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{(const double*)G.mg_partials, nblk, G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 1}, st);
   }
   return max_iter;
@@ -3160,6 +3287,8 @@ static void replay_one(int kind, dim3 g, dim3 b, const void* a, int n, hipStream
     case BK_EF2D: op_replay<efield_kernelOp<2, double>>(g, b, a, n, st); break;
     case BK_EF3F: op_replay<efield_kernelOp<3, float>>(g, b, a, n, st); break;
     case BK_EF3D: op_replay<efield_kernelOp<3, double>>(g, b, a, n, st); break;
+    case BK_RESR_F: op_replay<resrestrict_kernelOp<float>>(g, b, a, n, st); break;
+    case BK_RESR_D: op_replay<resrestrict_kernelOp<double>>(g, b, a, n, st); break;
     default: break;
   }
 }

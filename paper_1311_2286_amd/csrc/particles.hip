@@ -430,6 +430,113 @@ __device__ __forceinline__ bool kc_interp_window(const R* __restrict__ kwin, con
   return true;
 }
 
+// Tabulated map, FP32 Newton on the tile's LDS copy of the vertex coordinates
+// (the window of the field: the tile and a one-cell halo; coordinates relative
+// to the tile's first vertex, so FP32 keeps about 1e-6 of a cell).  Positions
+// are window cells w = u - (origin - 1).  Returns false, leaving d alone, when
+// an iterate leaves the window or crosses a bounded axis' wall, or when eight
+// iterations do not settle it below 2e-6 cell (about the FP32 resolution of
+// w): the FP64 inversion on the global table (move_tab) then moves the
+// particle.  Each iteration uses the polynomial of the cell holding w.
+template <int D>
+__device__ inline bool tab_window_xj(const float* __restrict__ xwin, const Geo& g, const int* origin,
+                                     const float* w, float* x, float (*J)[3]) {
+  using FW = FieldWindow<D>;
+  const int Ew[3] = {FW::E0, FW::E1, FW::E2};
+  int c[3] = {0, 0, 0};
+  float f[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float fl = floorf(w[a]);
+    c[a] = (int)fl;
+    f[a] = w[a] - fl;
+    if (c[a] < 0 || c[a] + 1 >= Ew[a]) return false;
+    if (!g.periodic[a]) {
+      const int gc = origin[a] - 1 + c[a];
+      if (gc < 0 || gc >= g.n[a]) return false;
+    }
+    x[a] = 0.f;
+#pragma unroll
+    for (int b = 0; b < D; ++b) J[a][b] = 0.f;
+  }
+  const float* x0 = xwin + D * (c[0] + FW::E0 * (c[1] + FW::E1 * c[2]));
+#pragma unroll
+  for (int corner = 0; corner < (1 << D); ++corner) {
+    float wt = 1.f, dw[3] = {1.f, 1.f, 1.f};
+    int off = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int up = (corner >> a) & 1;
+      const float wa = up ? f[a] : 1.f - f[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b) dw[b] *= (b == a) ? (up ? 1.f : -1.f) : wa;
+      wt *= wa;
+      off += up * (a == 0 ? 1 : (a == 1 ? FW::E0 : FW::E0 * FW::E1));
+    }
+    const float* xv = x0 + D * off;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      x[a] += wt * xv[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b) J[a][b] += dw[b] * xv[a];
+    }
+  }
+  return true;
+}
+
+template <int D>
+__device__ inline bool move_tab_window(const float* __restrict__ xwin, const Geo& g, const int* origin,
+                                       const int* idx, const float* f, const float* disp, float* d) {
+  using FW = FieldWindow<D>;
+  const int Ew[3] = {FW::E0, FW::E1, FW::E2};
+  float w0[3] = {0.f, 0.f, 0.f}, w[3] = {0.f, 0.f, 0.f}, x[3], J[3][3], tgt[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const int l = wrap_local(idx[a], origin[a] - 1, g.n[a], g.periodic[a] != 0);
+    if (l < 0 || l + 1 >= Ew[a]) return false;
+    w0[a] = (float)l + f[a];
+    w[a] = w0[a];
+  }
+  if (!tab_window_xj<D>(xwin, g, origin, w0, x, J)) return false;
+#pragma unroll
+  for (int a = 0; a < D; ++a) tgt[a] = x[a] + disp[a];
+  for (int it = 0; it < 8; ++it) {
+    if (it > 0 && !tab_window_xj<D>(xwin, g, origin, w, x, J)) return false;
+    float r[3] = {0.f, 0.f, 0.f}, du[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < D; ++a) r[a] = tgt[a] - x[a];
+    if (D == 2) {
+      const float det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      du[0] = (J[1][1] * r[0] - J[0][1] * r[1]) / det;
+      du[1] = (J[0][0] * r[1] - J[1][0] * r[0]) / det;
+    } else {
+      const float c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1], c01 = J[0][2] * J[2][1] - J[0][1] * J[2][2],
+                  c02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+      const float c10 = J[1][2] * J[2][0] - J[1][0] * J[2][2], c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0],
+                  c12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+      const float c20 = J[1][0] * J[2][1] - J[1][1] * J[2][0], c21 = J[0][1] * J[2][0] - J[0][0] * J[2][1],
+                  c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      const float det = J[0][0] * c00 + J[0][1] * c10 + J[0][2] * c20;
+      du[0] = (c00 * r[0] + c01 * r[1] + c02 * r[2]) / det;
+      du[1] = (c10 * r[0] + c11 * r[1] + c12 * r[2]) / det;
+      du[2] = (c20 * r[0] + c21 * r[1] + c22 * r[2]) / det;
+    }
+    float big = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) big = fmaxf(big, fabsf(du[a]));
+    if (!(big < 1e30f)) return false;
+    const float sc = big > 1.f ? 1.f / big : 1.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) w[a] += sc * du[a];
+    if (big < 2e-6f) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) d[a] = w[a] - w0[a];
+      return true;
+    }
+  }
+  return false;
+}
+
 // Predictor-corrector position update (Eqs. step2-step4) in cells:
 //   predictor  u' = (idx + f) + (dt/2) kc(idx, f) v,
 //   corrector  d  = dt kc(u') v,
@@ -896,6 +1003,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
   constexpr bool KWIN = MAP == MAP_TABLE_PC && std::is_same<R, float>::value;
   constexpr int KD = D * D;
   __shared__ R kwin[KWIN ? FW::N * KD : 1];
+  // tabulated map, FP32: the window's vertex coordinates (D per vertex),
+  // relative to the tile's first vertex
+  constexpr bool XWIN = MAP == MAP_TABULATED && std::is_same<R, float>::value;
+  __shared__ float xwin[XWIN ? FW::N * D : 1];
   __shared__ double red_d[8];
   __shared__ unsigned long long red_u[8][6];
   __shared__ int tbins[TB_N];  // new tiles of the particles (see count_new_tile)
@@ -942,25 +1053,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
   const int tci = tile % g.nt[0], tcj = (tile / g.nt[0]) % g.nt[1], tck = tile / (g.nt[0] * g.nt[1]);
   if (a.mode != MODE_DEPOSIT) {
     // stage the vertex field of the tile and a one-cell halo
+    double xref[3] = {0.0, 0.0, 0.0};
+    if constexpr (XWIN) {
+      // the tile's first vertex (always inside the grid)
+      long long v0 = 0;
+#pragma unroll
+      for (int ax = D - 1; ax >= 0; --ax) v0 = v0 * g.nv[ax] + origin[ax];
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) xref[ax] = g.xtab[v0 * D + ax];
+    }
     for (int s = threadIdx.x; s < FW::N; s += blockDim.x) {
       const int l0 = s % FW::E0, l1 = (s / FW::E0) % FW::E1, l2 = s / (FW::E0 * FW::E1);
       const int lv[3] = {l0, l1, l2};
       long long v = 0;
       bool ok = true;
+      double shift[3] = {0.0, 0.0, 0.0};  // period shifts of the wrapped vertex
 #pragma unroll
       for (int ax = D - 1; ax >= 0; --ax) {
         int x = origin[ax] - 1 + lv[ax];
         const int nv = g.nv[ax];
         if (g.periodic[ax]) {
           // x lies in [-1, n + 2]; grids narrower than the window wrap more than once
-          while (x < 0) x += nv;
-          while (x >= nv) x -= nv;
+          while (x < 0) {
+            x += nv;
+            shift[ax] -= g.L[ax];
+          }
+          while (x >= nv) {
+            x -= nv;
+            shift[ax] += g.L[ax];
+          }
         } else {
           ok = ok && x >= 0 && x < nv;
         }
         v = v * nv + x;
       }
       if (ok) {
+        if constexpr (XWIN) {
+#pragma unroll
+          for (int ax = 0; ax < D; ++ax) xwin[s * D + ax] = (float)(g.xtab[v * D + ax] + shift[ax] - xref[ax]);
+        }
 #pragma unroll
         for (int c = 0; c < FW::C; ++c) ewin[s * FW::C + c] = a.Ev[v * EC + c];
         if constexpr (KWIN) {
@@ -1057,12 +1188,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
         move_pc<D, R, KWIN>(g, a.kc, kwin, origin, idx, f, v, a.dt, d);
         conv = true;
       } else if constexpr (MAP == MAP_TABULATED) {
-        double f64[3] = {(double)f[0], (double)f[1], (double)f[2]}, disp[3], dd[3];
+        bool done = false;
+        if constexpr (XWIN) {
+          const float disp32[3] = {(float)a.dt * (float)v[0], (float)a.dt * (float)v[1], (float)a.dt * (float)v[2]};
+          float d32[3] = {0.f, 0.f, 0.f};
+          const float f32[3] = {(float)f[0], (float)f[1], (float)f[2]};
+          if (move_tab_window<D>(xwin, g, origin, idx, f32, disp32, d32)) {
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) disp[ax] = (double)a.dt * (double)v[ax];
-        conv = move_tab<D>(g, idx, f64, disp, 16, dd);
+            for (int ax = 0; ax < D; ++ax) d[ax] = (R)d32[ax];
+            conv = true;
+            done = true;
+          }
+        }
+        if (!done) {
+          double f64[3] = {(double)f[0], (double)f[1], (double)f[2]}, disp[3], dd[3];
 #pragma unroll
-        for (int ax = 0; ax < D; ++ax) d[ax] = (R)dd[ax];
+          for (int ax = 0; ax < 3; ++ax) disp[ax] = (double)a.dt * (double)v[ax];
+          conv = move_tab<D>(g, idx, f64, disp, 16, dd);
+#pragma unroll
+          for (int ax = 0; ax < D; ++ax) d[ax] = (R)dd[ax];
+        }
       } else
         conv = move_delta<D, MAP, R>(g, idx, f, v, a.dt, a.inv_dxc, a.newton_maxit, a.newton_tol,
                                         a.kappa, d);

@@ -1,7 +1,7 @@
 """Error of the timed configuration against the FP64 oracle.
 
 The benchmark runs the FP32 / fixed-point path with the Poisson solve stopped
-at a relative residual of 1e-5 (at most 10 iterations per solve, launched as
+at a relative residual of 4e-6 (at most 10 iterations per solve, launched as
 one more than the solve of two steps before needed) and a tile sort every 4
 steps.  This runs the same settings on the benchmark's recipe at a size the
 oracle finishes in seconds (the 3D sinusoidal box, eps = 0.05, one Debye
@@ -17,9 +17,10 @@ Two oracles: the FP64 particle path with the same fixed-point deposit rule
 path with the unquantised FP64 deposit (adds the quantisation of the weights
 to 2^-S1: S1 = 16 per axis in 3D, 24 in 2D).
 
-Bars (the benchmark spec: fields within 1e-5 relative in FP32): phi and E within 1e-5
-of the oracle with the same deposit rule; the plain-FP64 differences are
-reported."""
+Bars: phi and E within 1e-5 of the oracle with the same deposit rule (the
+FP32 path's field accuracy; the solve's tolerance is the largest term, and
+4e-6 keeps the fields below 1e-5 where 1e-5 reached 1.35e-5 on the Langmuir
+case); the plain-FP64 differences are reported."""
 import numpy as np
 import pytest
 
@@ -29,7 +30,7 @@ from _helpers import gpu_sim, oracle_objects, oracle_species, by_id, logical_cel
 
 pytestmark = pytest.mark.gpu
 
-BENCH = dict(mg_rtol=1e-5, mg_max_cycles=10, sort_every=4)
+BENCH = dict(mg_rtol=4e-6, mg_max_cycles=10, sort_every=4)
 
 
 @pytest.fixture(scope="module", autouse=True)
