@@ -684,6 +684,9 @@ def extra_table(C):
 
 
 def run_extra(C, key, args, steps=None):
+    if key in ("field_solve_mms", "field_solve_mms_boxmg"):
+        sizes = tuple(int(v) for v in args.mms_sizes.split(","))
+        return field_solve_mms(sizes=sizes, method=C.MG_BOXMG if key.endswith("boxmg") else 0)
     name, shp, prec, n, mover, tab, push = extra_table(C)[key]
     # the probe is timed in its injected steady state: the last 200 of the
     # configuration's 2,000 steps
@@ -715,6 +718,8 @@ def main():
     ap.add_argument("--only-extra", default=None,
                     help="only run this one of the other workloads (e.g. box3d_128_tabulated) and print its "
                          "result")
+    ap.add_argument("--mms-sizes", default="1024,2048,4096",
+                    help="grids of --only-extra field_solve_mms / field_solve_mms_boxmg")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--serve", action="store_true",

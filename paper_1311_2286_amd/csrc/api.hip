@@ -457,14 +457,22 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
   G.partials = (double*)A(sizeof(double) * 1024);
   const size_t sweep_blocks = (size_t)((g.n[0] + 63) / 64) * ((g.n[1] + 3) / 4) * g.n[2];
   G.mg_partials = (double*)A(sizeof(double) * sweep_blocks);
-  if (G.lev[nl - 1].ncells <= DENSE_MAX) {
-    const size_t nn = (size_t)G.lev[nl - 1].ncells * (size_t)G.lev[nl - 1].ncells;
+  G.boxmg = grid->mg_method == CPIC_MG_BOXMG;
+  G.coarse = nl - 1;
+  if (G.boxmg)
+    // the variational hierarchy ends at the first level the dense inverse can take
+    for (int l = 0; l < nl; ++l)
+      if (G.lev[l].ncells <= DENSE_MAX) {
+        G.coarse = l;
+        break;
+      }
+  if (G.lev[G.coarse].ncells <= DENSE_MAX) {
+    const size_t nn = (size_t)G.lev[G.coarse].ncells * (size_t)G.lev[G.coarse].ncells;
     G.cinv64 = (double*)A(sizeof(double) * nn);
     if (grid->mg_method != CPIC_MG_VCYCLE) G.cinv32 = (float*)A(sizeof(float) * nn);
   }
-  G.boxmg = grid->mg_method == CPIC_MG_BOXMG;
   if (G.boxmg)
-    for (int l = 1; l < nl; ++l) {
+    for (int l = 1; l <= G.coarse; ++l) {
       Level& L = G.lev[l];
       L.gal64 = (double*)A(sizeof(double) * 25 * (size_t)L.ncells);
       L.gal32 = (float*)A(sizeof(float) * 25 * (size_t)L.ncells);

@@ -1676,7 +1676,7 @@ __global__ __launch_bounds__(256) void dense_operator_kernel(LevelArgs a, double
 void launch_dense_galerkin(const GridCtx& G, double* M, hipStream_t st);
 int setup_coarse_inverse(GridCtx& G, hipStream_t st) {
   if (!G.cinv64) return 0;
-  const int l = G.nlev - 1;
+  const int l = G.coarse;
   const int n = (int)G.lev[l].ncells;
   LevelArgs a = level_args(G, l);
   if (G.boxmg)
@@ -2911,7 +2911,7 @@ __global__ void f64_to_f32_kernel(long long n, const double* __restrict__ a, flo
 
 int setup_galerkin(GridCtx& G, hipStream_t st) {
   if (!G.boxmg) return 0;
-  for (int l = 0; l + 1 < G.nlev; ++l) {
+  for (int l = 0; l < G.coarse; ++l) {
     const Level& C = G.lev[l + 1];
     const Stencil2<double> A = stencil2<double>(G, l);
     const unsigned blocks = (unsigned)((C.ncells + 255) / 256);
@@ -2948,7 +2948,7 @@ __global__ __launch_bounds__(256) void dense_galerkin_kernel(Stencil2<double> A,
   }
 }
 void launch_dense_galerkin(const GridCtx& G, double* M, hipStream_t st) {
-  const int l = G.nlev - 1;
+  const int l = G.coarse;
   hipLaunchKernelGGL(dense_galerkin_kernel, dim3((unsigned)G.lev[l].ncells), dim3(256), 0, st,
                      stencil2<double>(G, l), M);
 }
@@ -3229,7 +3229,7 @@ static void line_relax(const GridCtx& G, int l, bool post, hipStream_t st) {
 // 1e-10 at 1024^2 where V(1,1) takes 7 and V(2,2) 5 at a third more work)
 static void boxmg_vcycle(const GridCtx& G, int l, hipStream_t st) {
   const Level& L = G.lev[l];
-  if (l == G.nlev - 1) {
+  if (l == G.coarse) {
     if (G.cinv32) {
       hipLaunchKernelGGL(dense_solve_kernel, dim3(1), dim3(1024), 0, st, (int)L.ncells, (const float*)G.cinv32,
                          (const float*)L.f_rhs, L.f_phi, (const int*)G.mg_flag);

@@ -185,6 +185,7 @@ struct GridCtx {
   double anisotropy;      // largest ratio of a level-0 cell's face coefficients
   int restrict_transpose; // restriction = transpose of the prolongation (else summing)
   int boxmg;              // preconditioner: variational coarse operators + zebra line relaxation (2D)
+  int coarse;             // the solver's coarsest level (nlev - 1; with boxmg the first of <= DENSE_MAX cells)
   double* cinv64;     // dense inverse of the coarsest operator (<= DENSE_MAX cells), or null
   float* cinv32;      // its FP32 copy (flexible-CG preconditioner)
   double* kr;         // residual b - A x
