@@ -320,7 +320,9 @@ cpic_status cpic_step(cpic_sim* sim, int nsteps);
    types and restriction; a small grid's field phase is launch-bound, and the
    batch pays those launches once.  Otherwise the cases are stepped one after
    the other.  The solve of each case stops at its own convergence and cycle
-   budget.  Each simulation may appear once; n >= 1.  status (NULL, or n
+   budget.  With graph mode on for the first case stepped (cpic_set_graphs)
+   and a stream that can be captured, each batched sequence is captured once
+   as a HIP graph and replayed with one launch per step.  Each simulation may appear once; n >= 1.  status (NULL, or n
    entries) receives each case's outcome: a case that cpic_step would refuse
    (CPIC_E_STATE, CPIC_E_OVERFLOW) is left out and keeps its state while the
    others step; a runtime error during the batched launches (CPIC_E_HIP) is

@@ -1417,6 +1417,7 @@ extern "C" cpic_status cpic_step_batch(cpic_sim* const* sims, int n, cpic_status
     g_batch_rec = nullptr;
     rp[i] = &recs[i];
   }
+  S[0]->batch_args.graphs_on = S[0]->graphs;
   const int rr = replay_batch(rp.data(), m, S[0]->batch_args, S[0]->stream);
   if (rr == -3) {
     for (int i = 0; i < m; ++i) S[i]->poisoned = true;

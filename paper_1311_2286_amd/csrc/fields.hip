@@ -3357,6 +3357,41 @@ int replay_batch(BatchRecorder* const* cases, int n, BatchArgs& ba, hipStream_t 
     if (hipEventRecord(ba.copied[k], st) != hipSuccess) return -3;
     ba.uploaded = ba.staging;
   }
+  if (ba.graphs_on) {
+    // one graph launch per step instead of one launch per kernel: the graph
+    // holds the launches (their arguments are read from the buffer, uploaded
+    // above), so it serves every step with the same sequence
+    uint64_t key = 1469598103934665603ull;
+    auto mix = [&key](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
+    mix((uint64_t)n);
+    mix((uint64_t)(uintptr_t)ba.dev);
+    for (const BatchRec& rec : r0.recs) {
+      mix((uint64_t)rec.kind);
+      mix(((uint64_t)rec.grid.x << 32) ^ ((uint64_t)rec.grid.y << 16) ^ rec.grid.z);
+      mix(((uint64_t)rec.block.x << 32) ^ ((uint64_t)rec.block.y << 16) ^ rec.block.z);
+      mix((uint64_t)rec.args.size());
+    }
+    for (const auto& g : ba.graphs)
+      if (g.first == key) return hipGraphLaunch(g.second, st) == hipSuccess ? 0 : -3;
+    if (ba.graphs.size() < 64 && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      for (size_t i = 0; i < r0.recs.size(); ++i) {
+        const BatchRec& rec = r0.recs[i];
+        replay_one(rec.kind, rec.grid, rec.block, (const unsigned char*)ba.dev + offs[i], n, st);
+      }
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      const bool ok = hipStreamEndCapture(st, &graph) == hipSuccess && graph &&
+                      hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      if (graph) (void)hipGraphDestroy(graph);
+      if (ok && hipGraphLaunch(exec, st) == hipSuccess) {
+        ba.graphs.push_back({key, exec});
+        return 0;
+      }
+      // nothing ran: launch directly
+      if (exec) (void)hipGraphExecDestroy(exec);
+    }
+    (void)hipGetLastError();  // e.g. the null stream cannot be captured
+  }
   for (size_t i = 0; i < r0.recs.size(); ++i) {
     const BatchRec& rec = r0.recs[i];
     replay_one(rec.kind, rec.grid, rec.block, (const unsigned char*)ba.dev + offs[i], n, st);
@@ -3377,6 +3412,8 @@ void free_batch_args(BatchArgs& ba) {
   ba.pinned_bytes = 0;
   ba.slot = 0;
   ba.uploaded.clear();
+  for (auto& g : ba.graphs) (void)hipGraphExecDestroy(g.second);
+  ba.graphs.clear();
 }
 
 }  // namespace cpic

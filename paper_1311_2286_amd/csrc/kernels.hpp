@@ -288,6 +288,10 @@ struct BatchArgs {
   hipEvent_t copied[2] = {nullptr, nullptr};
   size_t pinned_bytes = 0;
   int slot = 0;
+  // replayed sequences captured as HIP graphs (keyed by the sequence's kernels
+  // and grids, the case count and the buffer), when graphs_on
+  bool graphs_on = false;
+  std::vector<std::pair<uint64_t, hipGraphExec_t>> graphs;
 };
 // Replays the recorded sequences of n cases as batched launches on st.
 // Returns 0; -1 (nothing launched) when the sequences differ or a case

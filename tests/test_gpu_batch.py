@@ -3,7 +3,8 @@ phases of several simulations of one grid shape (charge, right side, the
 flexible-CG solve with its FP32 V-cycle preconditioner, vertex field) run as
 one launch per kernel over all of them, the case index in the grid's z extent.
 
-Bar: bitwise.  The batched kernels compute for each case exactly what its own
+Bar: bitwise (also when the batch's field phase is replayed as a captured
+HIP graph).  The batched kernels compute for each case exactly what its own
 launch computes, so after the same steps every case's potential, vertex field,
 charge, exact deposits, solver cycles and residual and its particles (matched
 by id: the order inside a tile after a sort is the atomics') equal those of
@@ -53,11 +54,13 @@ def variants(dim, k0, n=None, bc=None):
     return out
 
 
-def make(case, **kw):
+def make(case, graphs=False, **kw):
     args = dict(precision=0, mg_rtol=1e-10, mg_max_cycles=40, sort_every=2)
     args.update(kw)
     sim, _ = gpu_sim(case, **args)
     sim.initialize()
+    if graphs:
+        sim.set_graphs(True)
     return sim
 
 
@@ -207,3 +210,12 @@ def test_batch_signature_and_set_stream():
     assert sa.diag().batched_steps == 1 and sb.diag().batched_steps == 1
     for s in (sa, sb, other, vc):
         s.close()
+
+
+def test_batch_with_graphs_equals_alone():
+    # graph mode on a created stream: a batch's field phase is captured once
+    # per sequence and replayed as one graph launch per step
+    torch = pytest.importorskip("torch")
+    st = torch.cuda.Stream()
+    run_pair(variants(2, 581), True, steps=8, stream=st.cuda_stream, graphs=True)
+    run_pair(variants(3, 585), True, steps=8, stream=st.cuda_stream, graphs=True)
