@@ -90,6 +90,7 @@ struct cpic_sim {
   long long hist_from = 0;         // records of steps before this one are not used
   bool overflowed = false;         // a fixed-point deposit wrapped (sticky until new particles)
   BatchArgs batch_args;            // argument structs of batched field phases led by this simulation
+  BatchArgs batch_pargs;           // argument structs of batched particle kernels led by it
   long long batched_steps = 0;     // steps whose field phase ran batched
   struct StepGraph {
     uint64_t key;
@@ -307,9 +308,11 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
     s->has_alloc = true;
   }
   s->stream = (hipStream_t)hip_stream;
-  s->batch_args.dev_alloc = batch_dev_alloc;
-  s->batch_args.dev_free = batch_dev_free;
-  s->batch_args.ctx = s;
+  for (BatchArgs* ba : {&s->batch_args, &s->batch_pargs}) {
+    ba->dev_alloc = batch_dev_alloc;
+    ba->dev_free = batch_dev_free;
+    ba->ctx = s;
+  }
   s->S1 = (d == 2) ? 24 : 16;
   s->chunk = (d == 2) ? 4096 : 16384;
   {
@@ -939,11 +942,11 @@ static void zero_deposits(cpic_sim* s, int mode) {
   }
 }
 
-// particle kernels of all species (deposit arrays must have been zeroed)
-// count_mask: species whose new tiles are counted for a sort at the end of the step
-static void particles_pass(cpic_sim* s, int mode, unsigned count_mask = 0) {
+// the particle-kernel launch of species k (count_mask: species whose new
+// tiles are counted for a sort at the end of the step)
+static ParticleLaunch make_launch(cpic_sim* s, size_t k, int mode, unsigned count_mask) {
   const bool halfstep = mode == MODE_HALFSTEP;
-  for (size_t k = 0; k < s->sp.size(); ++k) {
+  {
     Species& S = s->sp[k];
     ParticleLaunch L;
     memset(&L, 0, sizeof(L));
@@ -998,9 +1001,13 @@ static void particles_pass(cpic_sim* s, int mode, unsigned count_mask = 0) {
     L.kc = s->kc;
     L.drift = mode == MODE_PUSH ? s->drift_dev + k : nullptr;
     L.counters = S.counters;
-    launch_particles(L, s->stream);
+    return L;
   }
-  if (mode == MODE_PUSH) {
+}
+
+// the kinetic energy of the step: fixed-order sum of the work items' partials
+static void ke_pass(cpic_sim* s) {
+  {
     KeReduce r;
     memset(&r, 0, sizeof(r));
     r.nspecies = (int)s->sp.size();
@@ -1015,6 +1022,13 @@ static void particles_pass(cpic_sim* s, int mode, unsigned count_mask = 0) {
     r.out = s->ke;
     launch_ke_reduce(r, s->stream);
   }
+}
+
+// particle kernels of all species (deposit arrays must have been zeroed)
+// count_mask: species whose new tiles are counted for a sort at the end of the step
+static void particles_pass(cpic_sim* s, int mode, unsigned count_mask = 0) {
+  for (size_t k = 0; k < s->sp.size(); ++k) launch_particles(make_launch(s, k, mode, count_mask), s->stream);
+  if (mode == MODE_PUSH) ke_pass(s);
 }
 
 static bool any_injection(const cpic_sim* s) {
@@ -1405,7 +1419,41 @@ extern "C" cpic_status cpic_step_batch(cpic_sim* const* sims, int n, cpic_status
     if (rc != CPIC_OK) return fail_all(rc);
     launch = std::max(launch, cycles[i]);
   }
-  for (int i = 0; i < m; ++i) particle_phase(S[i], ev[i], false, mask[i]);
+  // particle phases: the deposit clears of every case in one launch, then
+  // the particle kernels of every case and species as one launch (plus one
+  // for the FP64 fallback), when they share a kernel
+  {
+    std::vector<FillRange> zr;
+    for (int i = 0; i < m; ++i) {
+      cpic_sim* s = S[i];
+      if (ev[i]) hipEventRecord(ev[i]->e[0], s->stream);
+      zr.push_back({s->ke, sizeof(double)});
+      for (size_t k = 0; k < s->sp.size(); ++k) {
+        Species& P = s->sp[k];
+        zr.push_back({P.Q, 8 * (size_t)s->g.ncells});
+        zr.push_back({P.counters + 9, sizeof(unsigned long long)});
+        zr.push_back({P.fb_count, sizeof(int) * 2});
+        if (mask[i] >> k & 1u) zr.push_back({P.counts, sizeof(int) * (size_t)(s->g.ntiles + 2)});
+      }
+    }
+    launch_zero_ranges(zr.data(), (int)zr.size(), S[0]->stream);
+    std::vector<ParticleLaunch> pl;
+    for (int i = 0; i < m; ++i) {
+      if (ev[i]) hipEventRecord(ev[i]->e[1], S[i]->stream);
+      for (size_t k = 0; k < S[i]->sp.size(); ++k) pl.push_back(make_launch(S[i], k, MODE_PUSH, mask[i]));
+    }
+    const int pr = launch_particles_batch(pl.data(), (int)pl.size(), S[0]->batch_pargs, S[0]->stream);
+    if (pr == -3) {
+      for (int i = 0; i < m; ++i) S[i]->poisoned = true;
+      return fail_all(fail(S[0], CPIC_E_HIP, "batched particle kernels: runtime error"));
+    }
+    if (pr != 0)
+      for (const ParticleLaunch& L : pl) launch_particles(L, S[0]->stream);
+    for (int i = 0; i < m; ++i) {
+      ke_pass(S[i]);
+      if (ev[i]) hipEventRecord(ev[i]->e[2], S[i]->stream);
+    }
+  }
   // the field phases: recorded case by case, replayed as one launch per kernel
   std::vector<BatchRecorder> recs((size_t)m);
   std::vector<BatchRecorder*> rp((size_t)m);
@@ -1734,6 +1782,7 @@ extern "C" void cpic_destroy(cpic_sim* s) {
   for (int i = 0; i < HIST; ++i)
     if (s->hist_ev[i]) (void)hipEventDestroy(s->hist_ev[i]);
   free_batch_args(s->batch_args);
+  free_batch_args(s->batch_pargs);
   for (auto& e : s->evs)
     for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e.e[i]);
   sim_free_all(s);

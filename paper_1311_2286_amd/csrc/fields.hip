@@ -102,6 +102,36 @@ __global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v, siz
   for (; i < n; i += stride) p[i] = v;
 }
 
+struct ZeroRanges {
+  unsigned* p[32];
+  unsigned long long words[32];
+};
+// workgroup row blockIdx.y zeroes range y, grid-stride over its words
+__global__ __launch_bounds__(256) void zero_ranges_kernel(ZeroRanges r) {
+  unsigned* p = r.p[blockIdx.y];
+  const unsigned long long n = r.words[blockIdx.y];
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+void launch_zero_ranges(const FillRange* r, int n, hipStream_t st) {
+  for (int b = 0; b < n; b += 32) {
+    ZeroRanges z;
+    memset(&z, 0, sizeof(z));
+    const int m = std::min(32, n - b);
+    unsigned long long most = 0;
+    for (int i = 0; i < m; ++i) {
+      z.p[i] = (unsigned*)r[b + i].p;
+      z.words[i] = r[b + i].bytes / 4;
+      most = std::max(most, z.words[i]);
+    }
+    if (most == 0) continue;
+    const unsigned bx = (unsigned)std::min<unsigned long long>((most + 255) / 256, 1024);
+    hipLaunchKernelGGL(zero_ranges_kernel, dim3(bx, (unsigned)m), dim3(256), 0, st, z);
+  }
+}
+
 void launch_fill_u8(void* p, unsigned char v, size_t bytes, hipStream_t st) {
   if (bytes == 0 || batch_unsupported()) return;
   if (v == 0 && bytes % 8 == 0 && ((uintptr_t)p % 8) == 0) {
@@ -3293,6 +3323,45 @@ static void replay_one(int kind, dim3 g, dim3 b, const void* a, int n, hipStream
   }
 }
 
+int batch_upload(BatchArgs& ba, hipStream_t st) {
+  const size_t total = ba.staging.size();
+  if (total > ba.bytes || total > ba.pinned_bytes) {
+    // larger buffers; the old ones may still be read by work in flight on st
+    if (hipStreamSynchronize(st) != hipSuccess) return -3;
+    free_batch_args(ba);
+    const size_t want = total + total / 2 + 4096;
+    ba.dev = ba.dev_alloc ? ba.dev_alloc(want, ba.ctx) : nullptr;
+    if (!ba.dev) return -2;
+    ba.bytes = want;
+    for (int k = 0; k < 2; ++k) {
+      if (hipHostMalloc(&ba.pinned[k], want, hipHostMallocDefault) != hipSuccess) {
+        ba.pinned[k] = nullptr;
+        free_batch_args(ba);
+        return -2;
+      }
+      if (hipEventCreateWithFlags(&ba.copied[k], hipEventDisableTiming) != hipSuccess) {
+        ba.copied[k] = nullptr;
+        free_batch_args(ba);
+        return -2;
+      }
+      if (hipEventRecord(ba.copied[k], st) != hipSuccess) return -3;
+    }
+    ba.pinned_bytes = want;
+  }
+  // most steps bring the same contents as the last one: upload on change
+  // (stream-ordered, so launches still in flight read the previous contents)
+  if (ba.uploaded != ba.staging) {
+    const int k = ba.slot;
+    ba.slot ^= 1;
+    if (hipEventSynchronize(ba.copied[k]) != hipSuccess) return -3;
+    memcpy(ba.pinned[k], ba.staging.data(), total);
+    if (hipMemcpyAsync(ba.dev, ba.pinned[k], total, hipMemcpyHostToDevice, st) != hipSuccess) return -3;
+    if (hipEventRecord(ba.copied[k], st) != hipSuccess) return -3;
+    ba.uploaded = ba.staging;
+  }
+  return 0;
+}
+
 int replay_batch(BatchRecorder* const* cases, int n, BatchArgs& ba, hipStream_t st) {
   if (n < 1) return 0;
   const BatchRecorder& r0 = *cases[0];
@@ -3323,40 +3392,8 @@ int replay_batch(BatchRecorder* const* cases, int n, BatchArgs& ba, hipStream_t 
     const size_t sz = r0.recs[i].args.size();
     for (int c = 0; c < n; ++c) memcpy(ba.staging.data() + offs[i] + sz * (size_t)c, cases[c]->recs[i].args.data(), sz);
   }
-  if (total > ba.bytes || total > ba.pinned_bytes) {
-    // larger buffers; the old ones may still be read by work in flight on st
-    if (hipStreamSynchronize(st) != hipSuccess) return -3;
-    free_batch_args(ba);
-    const size_t want = total + total / 2 + 4096;
-    ba.dev = ba.dev_alloc ? ba.dev_alloc(want, ba.ctx) : nullptr;
-    if (!ba.dev) return -2;
-    ba.bytes = want;
-    for (int k = 0; k < 2; ++k) {
-      if (hipHostMalloc(&ba.pinned[k], want, hipHostMallocDefault) != hipSuccess) {
-        ba.pinned[k] = nullptr;
-        free_batch_args(ba);
-        return -2;
-      }
-      if (hipEventCreateWithFlags(&ba.copied[k], hipEventDisableTiming) != hipSuccess) {
-        ba.copied[k] = nullptr;
-        free_batch_args(ba);
-        return -2;
-      }
-      if (hipEventRecord(ba.copied[k], st) != hipSuccess) return -3;
-    }
-    ba.pinned_bytes = want;
-  }
-  // most steps record the same arguments as the last one: upload on change
-  // (stream-ordered, so launches still in flight read the previous contents)
-  if (ba.uploaded != ba.staging) {
-    const int k = ba.slot;
-    ba.slot ^= 1;
-    if (hipEventSynchronize(ba.copied[k]) != hipSuccess) return -3;
-    memcpy(ba.pinned[k], ba.staging.data(), total);
-    if (hipMemcpyAsync(ba.dev, ba.pinned[k], total, hipMemcpyHostToDevice, st) != hipSuccess) return -3;
-    if (hipEventRecord(ba.copied[k], st) != hipSuccess) return -3;
-    ba.uploaded = ba.staging;
-  }
+  const int up = batch_upload(ba, st);
+  if (up != 0) return up;
   if (ba.graphs_on) {
     // one graph launch per step instead of one launch per kernel: the graph
     // holds the launches (their arguments are read from the buffer, uploaded

@@ -117,6 +117,13 @@ void launch_key_to_lin(const int32_t* key, int32_t* lin, int n, const Geo& g, hi
 void launch_iota(uint32_t* id, int n, hipStream_t st);
 void launch_offsets_check(const void* o, long long n, int fp64, int* bad, hipStream_t st);
 void launch_fill_u8(void* p, unsigned char v, size_t bytes, hipStream_t st);
+// zeroes n ranges of 4-byte-aligned memory (sizes multiples of 4) in as few
+// launches as possible (32 ranges per launch)
+struct FillRange {
+  void* p;
+  size_t bytes;
+};
+void launch_zero_ranges(const FillRange* r, int n, hipStream_t st);
 
 // ---------------------------------------------------------------- grid side
 // One multigrid level: cell-centred grid, coefficient arrays (FP64).
@@ -298,6 +305,15 @@ struct BatchArgs {
 // recorded an unsupported launch; -2 (nothing launched) when the argument
 // buffers could not be allocated; -3 on a runtime error.
 int replay_batch(BatchRecorder* const* cases, int n, BatchArgs& ba, hipStream_t st);
+// Brings ba.staging to ba.dev (stream-ordered; grows the buffers, uploads only
+// when the contents changed).  0; -2 allocation failed (nothing queued); -3
+// runtime error.
+int batch_upload(BatchArgs& ba, hipStream_t st);
+// The particle kernels of n launches of one kind (the same template: precision,
+// dimension, map, mover, shape, pusher, mode) as one launch over all their
+// work items, then one fallback launch: 0; -1 the launches differ (nothing
+// queued); -2 / -3 as batch_upload.  The argument buffer is ba's.
+int launch_particles_batch(const ParticleLaunch* L, int n, BatchArgs& ba, hipStream_t st);
 void free_batch_args(BatchArgs& ba);
 
 }  // namespace cpic

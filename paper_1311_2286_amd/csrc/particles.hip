@@ -13,6 +13,7 @@
 //
 // Particles are structure-of-arrays; a tile's particles are contiguous after a
 // sort, so every workgroup streams its run with coalesced loads and stores.
+#include <cstring>
 #include <type_traits>
 
 #include "common.hpp"
@@ -989,10 +990,12 @@ __device__ inline void tail_range(const PartArgs<R>& a, int nit, int t, int& beg
   end = b0 + min(total, (t + 1) * per);
 }
 
-// CYC: the cyclotronic velocity step (a uniform B) in place of Boris
+// CYC: the cyclotronic velocity step (a uniform B) in place of Boris.
+// One work item (a tile's particles, or a slice of those appended since the
+// last sort) per workgroup; launched alone (particle_kernel) or for many
+// simulations at once (particle_kernel_batch).
 template <int D, int MAP, int SHAPE, typename R, bool FIXED, bool CYC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && MAP != MAP_TABULATED) ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel(
-    PartArgs<R> a) {
+__device__ __forceinline__ void particle_body(const PartArgs<R>& a, const int item) {
   using TS = TileShape<D>;
   using FW = FieldWindow<D>;
   constexpr int EC = (D == 3) ? 4 : 2;  // components per vertex in the global array
@@ -1016,7 +1019,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
   // global gather and deposit paths, so an injecting species need not sort
   // every step
   constexpr bool TAIL = MAP == MAP_IDENTITY || MAP == MAP_POLAR_LOG || MAP == MAP_TABLE_PC;
-  const int item = blockIdx.x;
   const Geo& g = a.g;
   int tile, begin, end;
   if constexpr (TAIL) {
@@ -1342,6 +1344,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
   }
 }
 
+template <int D, int MAP, int SHAPE, typename R, bool FIXED, bool CYC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && MAP != MAP_TABULATED) ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel(
+    PartArgs<R> a) {
+  particle_body<D, MAP, SHAPE, R, FIXED, CYC>(a, blockIdx.x);
+}
+
+// The work items of several simulations (or species) in one launch: entry e
+// owns the workgroups base[e] .. base[e + 1] - 1, with its own arguments.
+template <int D, int MAP, int SHAPE, typename R, bool FIXED, bool CYC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && MAP != MAP_TABULATED) ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel_batch(
+    const PartArgs<R>* __restrict__ A, const int* __restrict__ base, int n) {
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (base[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  particle_body<D, MAP, SHAPE, R, FIXED, CYC>(A[lo], b - base[lo]);
+}
+
 // Deposit of one particle straight into HBM (global atomics): used for the
 // few particles handled outside the tile kernel (FP64 fallback, injection).
 template <int D, typename R, bool FIXED>
@@ -1406,7 +1431,7 @@ __device__ inline void deposit_global(const Geo& g, int shape, int S1, const int
 // Newton (continuation over the physical displacement), boundaries, deposit.
 // Their new velocity is already stored.
 template <int D, int MAP, typename R, bool FIXED>
-__global__ __launch_bounds__(256) void fallback_kernel(PartArgs<R> a, int shape) {
+__device__ __forceinline__ void fallback_body(const PartArgs<R>& a, int shape) {
   const Geo& g = a.g;
   const int n = min(*a.fb_count, a.fb_cap);
   unsigned long long done = 0, failed = 0, absorbed = 0, outflow = 0, ndep = 0;
@@ -1466,6 +1491,16 @@ __global__ __launch_bounds__(256) void fallback_kernel(PartArgs<R> a, int shape)
     if (outflow) atomicAdd(&a.counters[1], outflow);
     if (ndep) atomicAdd(&a.counters[9], ndep);
   }
+}
+
+template <int D, int MAP, typename R, bool FIXED>
+__global__ __launch_bounds__(256) void fallback_kernel(PartArgs<R> a, int shape) {
+  fallback_body<D, MAP, R, FIXED>(a, shape);
+}
+// one row of workgroups (blockIdx.y) per entry
+template <int D, int MAP, typename R, bool FIXED>
+__global__ __launch_bounds__(256) void fallback_kernel_batch(const PartArgs<R>* __restrict__ A, int shape) {
+  fallback_body<D, MAP, R, FIXED>(A[blockIdx.y], shape);
 }
 
 // ----------------------------------------------------------------------------
@@ -1892,8 +1927,8 @@ __global__ void offsets_check_kernel(const R* __restrict__ o, long long n, int* 
 // ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
-template <int D, int MAP, int SHAPE, typename R>
-static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
+template <typename R>
+static PartArgs<R> make_part_args(const ParticleLaunch& L) {
   PartArgs<R> a;
   a.key = L.key;
   a.off0 = (R*)L.off[0];
@@ -1941,6 +1976,18 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   a.fb_queue = L.fb_queue;
   a.fb_count = L.fb_count;
   a.fb_cap = L.fb_cap;
+  return a;
+}
+
+// work items of the maps that allow injection: the appended particles' slices
+template <int MAP>
+constexpr int tail_items() {
+  return (MAP == MAP_IDENTITY || MAP == MAP_POLAR_LOG || MAP == MAP_TABLE_PC) ? TAIL_ITEMS : 0;
+}
+
+template <int D, int MAP, int SHAPE, typename R>
+static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
+  const PartArgs<R> a = make_part_args<R>(L);
   if (L.max_items <= 0) return;
   constexpr bool FIXED = std::is_same<R, float>::value;
   // the appended particles' items (maps that allow injection)
@@ -1957,8 +2004,47 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   }
 }
 
+template <int D, int MAP, int SHAPE, typename R>
+static int launch_particle_batch_t(const ParticleLaunch* Ls, int n, BatchArgs& ba, hipStream_t st) {
+  constexpr bool FIXED = std::is_same<R, float>::value;
+  constexpr int tail = tail_items<MAP>();
+  std::vector<PartArgs<R>> args;
+  std::vector<int> base(1, 0);
+  for (int i = 0; i < n; ++i) {
+    if (Ls[i].max_items <= 0) continue;
+    args.push_back(make_part_args<R>(Ls[i]));
+    base.push_back(base.back() + Ls[i].max_items + tail);
+  }
+  if (args.empty()) return 0;
+  const size_t off_base = (sizeof(PartArgs<R>) * args.size() + 15) & ~(size_t)15;
+  ba.staging.assign(off_base + sizeof(int) * base.size(), 0);
+  std::memcpy(ba.staging.data(), args.data(), sizeof(PartArgs<R>) * args.size());
+  std::memcpy(ba.staging.data() + off_base, base.data(), sizeof(int) * base.size());
+  const int rc = batch_upload(ba, st);
+  if (rc != 0) return rc;
+  const PartArgs<R>* dA = (const PartArgs<R>*)ba.dev;
+  const int* dB = (const int*)((const unsigned char*)ba.dev + off_base);
+  const int ne = (int)args.size();
+  if (Ls[0].cyclo)
+    hipLaunchKernelGGL((particle_kernel_batch<D, MAP, SHAPE, R, FIXED, true>), dim3(base.back()), dim3(256), 0, st,
+                       dA, dB, ne);
+  else
+    hipLaunchKernelGGL((particle_kernel_batch<D, MAP, SHAPE, R, FIXED, false>), dim3(base.back()), dim3(256), 0, st,
+                       dA, dB, ne);
+  if constexpr (MAP != MAP_IDENTITY && MAP != MAP_TABLE_PC) {
+    if (Ls[0].mode == MODE_PUSH)
+      hipLaunchKernelGGL((fallback_kernel_batch<D, MAP, R, FIXED>), dim3(64, ne), dim3(256), 0, st, dA, Ls[0].shape);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
 template <int D, int MAP, typename R>
-static int launch_particle_shape(const ParticleLaunch& L, hipStream_t st) {
+static int launch_particle_shape(const ParticleLaunch& L, hipStream_t st, const ParticleLaunch* batch = nullptr,
+                                 int n = 0, BatchArgs* ba = nullptr) {
+  if (batch) {
+    return L.shape == SHAPE_B2 ? launch_particle_batch_t<D, MAP, SHAPE_B2, R>(batch, n, *ba, st)
+                               : launch_particle_batch_t<D, MAP, SHAPE_B1, R>(batch, n, *ba, st);
+  }
   if (L.shape == SHAPE_B2)
     launch_particle_t<D, MAP, SHAPE_B2, R>(L, st);
   else
@@ -1967,25 +2053,26 @@ static int launch_particle_shape(const ParticleLaunch& L, hipStream_t st) {
 }
 
 template <typename R>
-static int launch_particle_r(const ParticleLaunch& L, hipStream_t st) {
+static int launch_particle_r(const ParticleLaunch& L, hipStream_t st, const ParticleLaunch* B = nullptr, int n = 0,
+                             BatchArgs* ba = nullptr) {
   const int D = L.g.dim, M = L.g.kind;
   if (L.kc) {
-    if (D == 2) return launch_particle_shape<2, MAP_TABLE_PC, R>(L, st);
-    if (D == 3) return launch_particle_shape<3, MAP_TABLE_PC, R>(L, st);
+    if (D == 2) return launch_particle_shape<2, MAP_TABLE_PC, R>(L, st, B, n, ba);
+    if (D == 3) return launch_particle_shape<3, MAP_TABLE_PC, R>(L, st, B, n, ba);
     return -1;
   }
   if (M == MAP_TABULATED) {
-    if (D == 2) return launch_particle_shape<2, MAP_TABULATED, R>(L, st);
-    if (D == 3) return launch_particle_shape<3, MAP_TABULATED, R>(L, st);
+    if (D == 2) return launch_particle_shape<2, MAP_TABULATED, R>(L, st, B, n, ba);
+    if (D == 3) return launch_particle_shape<3, MAP_TABULATED, R>(L, st, B, n, ba);
     return -1;
   }
   if (D == 2) {
-    if (M == MAP_IDENTITY) return launch_particle_shape<2, MAP_IDENTITY, R>(L, st);
-    if (M == MAP_SINUSOIDAL) return launch_particle_shape<2, MAP_SINUSOIDAL, R>(L, st);
-    if (M == MAP_POLAR_LOG) return launch_particle_shape<2, MAP_POLAR_LOG, R>(L, st);
+    if (M == MAP_IDENTITY) return launch_particle_shape<2, MAP_IDENTITY, R>(L, st, B, n, ba);
+    if (M == MAP_SINUSOIDAL) return launch_particle_shape<2, MAP_SINUSOIDAL, R>(L, st, B, n, ba);
+    if (M == MAP_POLAR_LOG) return launch_particle_shape<2, MAP_POLAR_LOG, R>(L, st, B, n, ba);
   } else if (D == 3) {
-    if (M == MAP_IDENTITY) return launch_particle_shape<3, MAP_IDENTITY, R>(L, st);
-    if (M == MAP_SINUSOIDAL) return launch_particle_shape<3, MAP_SINUSOIDAL, R>(L, st);
+    if (M == MAP_IDENTITY) return launch_particle_shape<3, MAP_IDENTITY, R>(L, st, B, n, ba);
+    if (M == MAP_SINUSOIDAL) return launch_particle_shape<3, MAP_SINUSOIDAL, R>(L, st, B, n, ba);
   }
   return -1;
 }
@@ -2015,6 +2102,19 @@ void launch_kc_table(const Geo& g, const double* Kv, void* kc, int fp64, hipStre
 
 int launch_particles(const ParticleLaunch& L, hipStream_t st) {
   return L.fp64 ? launch_particle_r<double>(L, st) : launch_particle_r<float>(L, st);
+}
+
+int launch_particles_batch(const ParticleLaunch* L, int n, BatchArgs& ba, hipStream_t st) {
+  if (n < 1) return 0;
+  // one template for all: precision, dimension, map (and its mover), shape,
+  // pusher and mode must agree
+  for (int i = 1; i < n; ++i) {
+    const ParticleLaunch &a = L[i], &b = L[0];
+    if (a.fp64 != b.fp64 || a.g.dim != b.g.dim || a.g.kind != b.g.kind || (a.kc != nullptr) != (b.kc != nullptr) ||
+        a.shape != b.shape || a.cyclo != b.cyclo || a.mode != b.mode)
+      return -1;
+  }
+  return L[0].fp64 ? launch_particle_r<double>(L[0], st, L, n, &ba) : launch_particle_r<float>(L[0], st, L, n, &ba);
 }
 
 template <int D, int MAP, typename R>
