@@ -344,6 +344,13 @@ cpic_status cpic_batch_signature(const cpic_sim* sim, uint64_t* sig);
    runs on the new one. */
 cpic_status cpic_set_stream(cpic_sim* sim, void* hip_stream);
 
+/* *ready = 1 when the next cpic_step (or cpic_step_batch) of the simulation
+   would not wait for the device: a step decides its solver cycles and sorts
+   from the record of the step two before, which it waits for; 0 while that
+   step is still running.  Lets a caller driving many simulations step the
+   ones that are ready first. */
+cpic_status cpic_step_ready(const cpic_sim* sim, int* ready);
+
 /* Run one stage (asynchronous); see CPIC_STAGE_*. */
 cpic_status cpic_run_stage(cpic_sim* sim, int stage);
 
@@ -477,9 +484,10 @@ cpic_status cpic_server_create(size_t hbm_budget_bytes, int max_slots, const cpi
 /* Queue a case; *ticket identifies it.  Validates the description (CPIC_E_ARG)
    and copies the particle arrays. */
 cpic_status cpic_server_submit(cpic_server* srv, const cpic_case_desc* desc, uint64_t* ticket);
-/* Run up to max_iterations rounds of: admit, one step of every running case
-   (the cases of a batch group through one cpic_step_batch), retire finished
-   cases.  Returns CPIC_OK when nothing is queued or running
+/* Run up to max_iterations rounds of: admit, one step of the running cases
+   (the cases of a batch group through one cpic_step_batch; cases or groups
+   whose step would wait for the device, see cpic_step_ready, wait for a later
+   round unless none is ready), retire finished cases.  Returns CPIC_OK when nothing is queued or running
    afterwards, CPIC_E_PENDING otherwise. */
 cpic_status cpic_server_pump(cpic_server* srv, int max_iterations);
 /* CPIC_E_PENDING until the case is done, then CPIC_OK with *out filled

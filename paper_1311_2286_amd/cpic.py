@@ -33,7 +33,7 @@ EXPORTED = ["cpic_create", "cpic_add_species", "cpic_set_particles", "cpic_get_p
             "cpic_status_str", "cpic_last_error", "cpic_destroy", "cpic_set_graphs", "cpic_server_create",
             "cpic_server_submit", "cpic_server_pump", "cpic_server_poll", "cpic_server_get_stats",
             "cpic_server_destroy", "cpic_get_diag_noalloc", "cpic_step_batch",
-            "cpic_batch_signature", "cpic_set_stream"]
+            "cpic_batch_signature", "cpic_set_stream", "cpic_step_ready"]
 MAX_SPECIES = 8
 E_ARG, E_MAP, E_NOMEM, E_BUDGET, E_HIP, E_OVERFLOW, E_NONFINITE, E_STATE, E_UNSUPPORTED = range(-1, -10, -1)
 E_PENDING = 1
@@ -137,6 +137,7 @@ def load():
     L.cpic_step_batch.argtypes = [P(vp), i32, P(i32)]
     L.cpic_batch_signature.argtypes = [vp, P(ctypes.c_uint64)]
     L.cpic_set_stream.argtypes = [vp, vp]
+    L.cpic_step_ready.argtypes = [vp, P(i32)]
     L.cpic_run_stage.argtypes = [vp, i32]
     L.cpic_get_field.argtypes = [vp, i32, i32, vp, sz, i32]
     L.cpic_set_field.argtypes = [vp, i32, i32, vp, sz, i32]
@@ -163,7 +164,7 @@ def load():
     L.cpic_server_destroy.restype = None
     for name in ("cpic_create", "cpic_add_species", "cpic_set_particles", "cpic_get_particles",
                  "cpic_initialize", "cpic_step", "cpic_step_batch", "cpic_batch_signature", "cpic_set_stream",
-                 "cpic_run_stage", "cpic_get_field",
+                 "cpic_step_ready", "cpic_run_stage", "cpic_get_field",
                  "cpic_set_field", "cpic_get_diag", "cpic_get_diag_noalloc", "cpic_sync", "cpic_set_timing",
                  "cpic_get_timing", "cpic_set_graphs", "cpic_server_create", "cpic_server_submit",
                  "cpic_server_pump", "cpic_server_poll", "cpic_server_get_stats"):
@@ -418,6 +419,12 @@ class Sim:
     def set_stream(self, stream):
         self._check(self.lib.cpic_set_stream(self.h, ctypes.c_void_p(stream)), "set_stream")
         self.stream = stream
+
+    def step_ready(self):
+        """True when the next step would not wait for the device."""
+        r = ctypes.c_int(0)
+        self._check(self.lib.cpic_step_ready(self.h, ctypes.byref(r)), "step_ready")
+        return bool(r.value)
 
     def set_graphs(self, on=True):
         """Replay recorded HIP graphs of the step (needs a non-null stream)."""

@@ -1316,10 +1316,23 @@ static cpic_status step_record(cpic_sim* s, unsigned mask, long long n) {
     }
   }
   const int slot = (int)(n % HIST);
-  HIPCHK(s, hipMemcpyAsync(s->cycles_host + slot, s->G.mg_flag + 1, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(s, hipMemcpyAsync(s->drift_host + 8 * slot, s->drift_dev, sizeof(unsigned) * s->sp.size(),
-                           hipMemcpyDeviceToHost, s->stream));
+  launch_step_record(s->G.mg_flag + 1, s->drift_dev, (int)s->sp.size(), s->cycles_host + slot,
+                     s->drift_host + 8 * slot, s->stream);
   HIPCHK(s, hipEventRecord(s->hist_ev[slot], s->stream));
+  return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_step_ready(const cpic_sim* s, int* ready) {
+  if (!s || !ready) return CPIC_E_ARG;
+  *ready = 1;
+  const long long n = s->step;
+  if (n - 2 >= s->hist_from) {
+    const hipError_t q = hipEventQuery(s->hist_ev[(int)((n - 2) % HIST)]);
+    if (q == hipErrorNotReady)
+      *ready = 0;
+    else if (q != hipSuccess)
+      return CPIC_E_HIP;
+  }
   return CPIC_OK;
 }
 

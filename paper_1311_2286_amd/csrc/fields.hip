@@ -132,6 +132,23 @@ void launch_zero_ranges(const FillRange* r, int n, hipStream_t st) {
   }
 }
 
+// A step's record for the host (the solver's cycles and the species' drift),
+// written into pinned host memory, which the host reads after the event
+// recorded behind this launch: one small launch in place of two copies.
+__global__ void step_record_kernel(const int* __restrict__ cycles_dev, const unsigned* __restrict__ drift_dev, int nsp,
+                                   int* cycles_host, unsigned* drift_host) {
+  const int t = threadIdx.x;
+  if (t == 0) cycles_host[0] = cycles_dev[0];
+  if (t < nsp) drift_host[t] = drift_dev[t];
+  __threadfence_system();
+}
+
+void launch_step_record(const int* cycles_dev, const unsigned* drift_dev, int nsp, int* cycles_host,
+                        unsigned* drift_host, hipStream_t st) {
+  hipLaunchKernelGGL(step_record_kernel, dim3(1), dim3(64), 0, st, cycles_dev, drift_dev, nsp, cycles_host,
+                     drift_host);
+}
+
 void launch_fill_u8(void* p, unsigned char v, size_t bytes, hipStream_t st) {
   if (bytes == 0 || batch_unsupported()) return;
   if (v == 0 && bytes % 8 == 0 && ((uintptr_t)p % 8) == 0) {

@@ -124,6 +124,10 @@ struct FillRange {
   size_t bytes;
 };
 void launch_zero_ranges(const FillRange* r, int n, hipStream_t st);
+// copies the step's record (cycles_dev[0], drift_dev[0 .. nsp)) into pinned
+// host memory
+void launch_step_record(const int* cycles_dev, const unsigned* drift_dev, int nsp, int* cycles_host,
+                        unsigned* drift_host, hipStream_t st);
 
 // ---------------------------------------------------------------- grid side
 // One multigrid level: cell-centred grid, coefficient arrays (FP64).

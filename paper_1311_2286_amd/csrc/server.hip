@@ -375,21 +375,38 @@ extern "C" cpic_status cpic_server_pump(cpic_server* s, int max_iterations) {
   for (int it = 0; it < max_iterations; ++it) {
     admit(s);
     if (s->active.empty()) break;
-    // one step of every running case: the cases of a batch group together
-    // (their field phases batched), the others each on its own
+    // one step of the running cases: the cases of a batch group together
+    // (their field phases batched), the others each on its own; units whose
+    // step would wait for the device (cpic_step_ready) are left for the next
+    // iteration while others can be stepped, so that the host keeps queueing
+    // work instead of blocking on one stream
     std::map<uint64_t, std::vector<Case*>> batches;
-    std::vector<Case*> alone;
+    std::vector<std::vector<Case*>> units;
     for (Case* c : s->active) {
       if (c->finishing) continue;
       if (!c->group)
-        alone.push_back(c);
+        units.push_back({c});
       else
         batches[c->group].push_back(c);
     }
+    for (auto& kv : batches) units.push_back(std::move(kv.second));
+    std::vector<char> go(units.size(), 0);
+    bool any = false;
+    for (size_t u = 0; u < units.size(); ++u) {
+      int ok = 1;
+      for (Case* c : units[u]) {
+        int r = 1;
+        if (cpic_step_ready(c->sim, &r) != CPIC_OK) r = 1;  // the step reports the error
+        ok &= r;
+      }
+      go[u] = (char)ok;
+      any |= ok != 0;
+    }
+    if (!any) std::fill(go.begin(), go.end(), (char)1);
     std::vector<std::pair<Case*, int>> stepped;
-    for (Case* c : alone) stepped.push_back({c, (int)cpic_step(c->sim, 1)});
-    for (auto& kv : batches) {
-      std::vector<Case*>& cs = kv.second;
+    for (size_t u = 0; u < units.size(); ++u) {
+      if (!go[u]) continue;
+      std::vector<Case*>& cs = units[u];
       if (cs.size() == 1) {
         stepped.push_back({cs[0], (int)cpic_step(cs[0]->sim, 1)});
         continue;

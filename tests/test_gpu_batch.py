@@ -212,6 +212,24 @@ def test_batch_signature_and_set_stream():
         s.close()
 
 
+def test_step_ready():
+    # ready while the step two before has completed on the device: the first
+    # two steps never wait; after a synchronisation every step is ready
+    torch = pytest.importorskip("torch")
+    s = make(variants(2, 591)[0])
+    assert s.step_ready()
+    s.step(1)
+    assert s.step_ready()
+    for _ in range(4):
+        s.step(1)
+        r = s.step_ready()
+        assert r in (True, False)
+    torch.cuda.synchronize()
+    s.diag()
+    assert s.step_ready()
+    s.close()
+
+
 def test_batch_with_graphs_equals_alone():
     # graph mode on a created stream: a batch's field phase is captured once
     # per sequence and replayed as one graph launch per step
