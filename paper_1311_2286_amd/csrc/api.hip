@@ -491,6 +491,11 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
       L.f_rhs = (float*)A(fb);
       L.f_res = (float*)A(fb);
       L.f_aux = (float*)A(fb);
+      if (!G.boxmg && L.ncells > SMALL_CELLS) {
+        const size_t hb = sizeof(unsigned short) * (size_t)L.ncells;
+        for (int k = 0; k < 9; ++k) L.h_S[k] = L.S[k] ? (unsigned short*)A(hb) : nullptr;
+        L.h_diag = (unsigned short*)A(hb);
+      }
     }
     G.kr = (double*)A(cb);
     G.kp = (double*)A(cb);
@@ -556,7 +561,10 @@ extern "C" cpic_status cpic_create(const cpic_map_desc* map, const cpic_grid_des
       for (float* v : {L.f_phi, L.f_phi2, L.f_rhs, L.f_res, L.f_aux}) launch_fill_u8(v, 0, fb, st);
     }
   }
-  launch_operator_f32(G, st);
+  if (launch_operator_f32(G, st) != 0) {
+    cpic_destroy(s);
+    return CPIC_E_HIP;
+  }
   launch_fill_u8(G.charge, 0, cb, st);
   launch_fill_u8(G.Ev, 0, real_size(s) * ecomp(s) * (size_t)g.nverts, st);
   launch_fill_u8(s->ke, 0, sizeof(double) * 2, st);

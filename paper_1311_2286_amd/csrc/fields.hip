@@ -19,6 +19,7 @@
 // rediscretised from the analytic map at each level, coarsest level solved
 // by one workgroup.  Convergence is tested on the device (no host sync); the
 // kernels of later cycles return at once once the flag is set.
+#include <hip/hip_fp16.h>
 #include <string.h>
 
 #include <type_traits>
@@ -180,11 +181,15 @@ enum BatchKind : int {
   BK_CHARGE = 1, BK_EXTRAP, BK_RHS, BK_SUB, BK_REDP, BK_REDF, BK_RESET, BK_FCGRES, BK_FCGAPPLY, BK_FCGCOEF,
   BK_FCGUPD, BK_SMOOTH_F, BK_SMOOTH_D, BK_RESID_F, BK_RESID_D, BK_RSUM_F, BK_RSUM_D, BK_RTR_F, BK_RTR_D,
   BK_PROL_F, BK_PROL_D, BK_SMALL_F, BK_SMALL_D, BK_EF2F, BK_EF2D, BK_EF3F, BK_EF3D, BK_RESR_F, BK_RESR_D,
-  BK_COUNT
+  BK_SMOOTH_H, BK_RESR_H, BK_COUNT
 };
 template <typename T>
 constexpr int kind_of(int kf, int kd) {
   return std::is_same<T, float>::value ? kf : kd;
+}
+template <typename T, typename C>
+constexpr int kind_of(int kf, int kd, int kh) {
+  return std::is_same<C, __half>::value ? kh : kind_of<T>(kf, kd);
 }
 
 // Kernels of the field phase as ops: an argument struct and a body that takes
@@ -238,7 +243,10 @@ static void op_replay(dim3 grid, dim3 block, const void* args, int n, hipStream_
 // ----------------------------------------------------------------------------
 // T: type of the operator coefficients (FP64; FP32 for the V-cycle used as a
 // preconditioner of the flexible-CG solve)
-template <typename T>
+// C: the storage type of the explicit stencil (T, or FP16 scaled by a power
+// of two for the preconditioner's multi-workgroup levels: the stencil then
+// holds 2^-e times the coefficients and cinv = 2^e)
+template <typename T, typename C = T>
 struct LevelArgsT {
   int dim;
   int n[3];
@@ -250,9 +258,26 @@ struct LevelArgsT {
   const double* wf[3];
   const double* wlo[3];
   const double* we[3];
-  const T* S[9];
-  const T* diag;
+  const C* S[9];
+  const C* diag;
+  T cinv;
 };
+
+template <typename T, typename C>
+__device__ __forceinline__ T coef_val(C v) {
+  if constexpr (std::is_same<C, __half>::value)
+    return (T)__half2float(v);
+  else
+    return (T)v;
+}
+// diagonal of the operator at cell c
+template <typename T, typename C>
+__device__ __forceinline__ T diag_at(const LevelArgsT<T, C>& a, int c) {
+  if constexpr (std::is_same<C, T>::value)
+    return a.diag[c];
+  else
+    return coef_val<T>(a.diag[c]) * a.cinv;
+}
 using LevelArgs = LevelArgsT<double>;
 
 static LevelArgs level_args(const GridCtx& G, int l) {
@@ -273,6 +298,7 @@ static LevelArgs level_args(const GridCtx& G, int l) {
   }
   for (int k = 0; k < 9; ++k) a.S[k] = L.S[k];
   a.diag = L.diag;
+  a.cinv = 1.0;
   return a;
 }
 
@@ -296,6 +322,31 @@ static LevelArgsT<float> level_args_f32(const GridCtx& G, int l) {
   }
   for (int k = 0; k < 9; ++k) a.S[k] = L.f_S[k];
   a.diag = L.f_diag;
+  a.cinv = 1.0f;
+  return a;
+}
+
+// the FP16 copy of a level's operator (null diag when the level has none)
+static LevelArgsT<float, __half> level_args_h(const GridCtx& G, int l) {
+  const LevelArgsT<float> f = level_args_f32(G, l);
+  const Level& L = G.lev[l];
+  LevelArgsT<float, __half> a;
+  a.dim = f.dim;
+  a.mixed = f.mixed;
+  a.dV = f.dV;
+  for (int i = 0; i < 3; ++i) {
+    a.n[i] = f.n[i];
+    a.periodic[i] = f.periodic[i];
+    a.dir[i][0] = f.dir[i][0];
+    a.dir[i][1] = f.dir[i][1];
+    a.h[i] = f.h[i];
+    a.wf[i] = f.wf[i];
+    a.wlo[i] = f.wlo[i];
+    a.we[i] = f.we[i];
+  }
+  for (int k = 0; k < 9; ++k) a.S[k] = (const __half*)L.h_S[k];
+  a.diag = (const __half*)L.h_diag;
+  a.cinv = L.h_inv;
   return a;
 }
 
@@ -754,8 +805,8 @@ void launch_rhs(const GridCtx& G, hipStream_t st) {
 // (A phi)_c from the explicit stencil: diag, the upper-half coefficients of c
 // and, by symmetry, those stored at the lower neighbours.  Across a wall the
 // lower neighbour term is absent and the upper coefficient is zero.
-template <typename T, typename TV>
-__device__ inline T apply_A(const LevelArgsT<T>& a, const TV* __restrict__ phi_in, const int* idx, long long cl) {
+template <typename T, typename TV, typename C>
+__device__ inline T apply_A(const LevelArgsT<T, C>& a, const TV* __restrict__ phi_in, const int* idx, long long cl) {
   const int c = (int)cl;
   const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
   const int sy = n0, sz = n0 * n1;
@@ -767,28 +818,29 @@ __device__ inline T apply_A(const LevelArgsT<T>& a, const TV* __restrict__ phi_i
     const TV* p;
     __device__ T operator[](long long i) const { return (T)p[i]; }
   } phi{phi_in};
-  T acc = a.diag[c] * phi[c];
-  acc += a.S[0][c] * phi[c + dxp];
-  if (dxm) acc += a.S[0][c + dxm] * phi[c + dxm];
-  acc += a.S[1][c] * phi[c + dyp];
-  if (dym) acc += a.S[1][c + dym] * phi[c + dym];
+  T acc = coef_val<T>(a.diag[c]) * phi[c];
+  acc += coef_val<T>(a.S[0][c]) * phi[c + dxp];
+  if (dxm) acc += coef_val<T>(a.S[0][c + dxm]) * phi[c + dxm];
+  acc += coef_val<T>(a.S[1][c]) * phi[c + dyp];
+  if (dym) acc += coef_val<T>(a.S[1][c + dym]) * phi[c + dym];
   if (a.dim == 3) {
     const int dzp = (idx[2] + 1 < n2 ? 1 : (a.periodic[2] ? 1 - n2 : 0)) * sz;
     const int dzm = (idx[2] > 0 ? -1 : (a.periodic[2] ? n2 - 1 : 0)) * sz;
-    acc += a.S[2][c] * phi[c + dzp];
-    if (dzm) acc += a.S[2][c + dzm] * phi[c + dzm];
+    acc += coef_val<T>(a.S[2][c]) * phi[c + dzp];
+    if (dzm) acc += coef_val<T>(a.S[2][c + dzm]) * phi[c + dzm];
     if (a.mixed) {
-      acc += a.S[3][c] * phi[c + dxp + dyp] + a.S[3][c + dxm + dym] * phi[c + dxm + dym];
-      acc += a.S[4][c] * phi[c + dxp + dym] + a.S[4][c + dxm + dyp] * phi[c + dxm + dyp];
-      acc += a.S[5][c] * phi[c + dxp + dzp] + a.S[5][c + dxm + dzm] * phi[c + dxm + dzm];
-      acc += a.S[6][c] * phi[c + dxp + dzm] + a.S[6][c + dxm + dzp] * phi[c + dxm + dzp];
-      acc += a.S[7][c] * phi[c + dyp + dzp] + a.S[7][c + dym + dzm] * phi[c + dym + dzm];
-      acc += a.S[8][c] * phi[c + dyp + dzm] + a.S[8][c + dym + dzp] * phi[c + dym + dzp];
+      acc += coef_val<T>(a.S[3][c]) * phi[c + dxp + dyp] + coef_val<T>(a.S[3][c + dxm + dym]) * phi[c + dxm + dym];
+      acc += coef_val<T>(a.S[4][c]) * phi[c + dxp + dym] + coef_val<T>(a.S[4][c + dxm + dyp]) * phi[c + dxm + dyp];
+      acc += coef_val<T>(a.S[5][c]) * phi[c + dxp + dzp] + coef_val<T>(a.S[5][c + dxm + dzm]) * phi[c + dxm + dzm];
+      acc += coef_val<T>(a.S[6][c]) * phi[c + dxp + dzm] + coef_val<T>(a.S[6][c + dxm + dzp]) * phi[c + dxm + dzp];
+      acc += coef_val<T>(a.S[7][c]) * phi[c + dyp + dzp] + coef_val<T>(a.S[7][c + dym + dzm]) * phi[c + dym + dzm];
+      acc += coef_val<T>(a.S[8][c]) * phi[c + dyp + dzm] + coef_val<T>(a.S[8][c + dym + dzp]) * phi[c + dym + dzp];
     }
   } else if (a.mixed) {
-    acc += a.S[3][c] * phi[c + dxp + dyp] + a.S[3][c + dxm + dym] * phi[c + dxm + dym];
-    acc += a.S[4][c] * phi[c + dxp + dym] + a.S[4][c + dxm + dyp] * phi[c + dxm + dyp];
+    acc += coef_val<T>(a.S[3][c]) * phi[c + dxp + dyp] + coef_val<T>(a.S[3][c + dxm + dym]) * phi[c + dxm + dym];
+    acc += coef_val<T>(a.S[4][c]) * phi[c + dxp + dym] + coef_val<T>(a.S[4][c + dxm + dyp]) * phi[c + dxm + dyp];
   }
+  if constexpr (!std::is_same<C, T>::value) acc *= a.cinv;
   return acc;
 }
 
@@ -798,11 +850,11 @@ __device__ inline T apply_A(const LevelArgsT<T>& a, const TV* __restrict__ phi_i
 // Chebyshev steps of the multigrid smoother use the three-term recurrence.
 // With partials != null the squared residual of the input is summed per block
 // (fixed order) for the convergence test.
-template <typename T>
+template <typename T, typename C = T>
 struct smooth_kernelOp {
-  static constexpr int KIND = kind_of<T>(BK_SMOOTH_F, BK_SMOOTH_D), BOUND = 256;
+  static constexpr int KIND = kind_of<T, C>(BK_SMOOTH_F, BK_SMOOTH_D, BK_SMOOTH_H), BOUND = 256;
   struct Args {
-    LevelArgsT<T> a;
+    LevelArgsT<T, C> a;
     const T* phi;
     const T* rhs;
     T* out;
@@ -814,7 +866,7 @@ struct smooth_kernelOp {
     double* partials;
   };
   static __device__ void body(const Args& k_, const Blk& b_) {
-    const LevelArgsT<T>& a = k_.a;
+    const LevelArgsT<T, C>& a = k_.a;
     const T* __restrict__ phi = k_.phi;
     const T* __restrict__ rhs = k_.rhs;
     T* out = k_.out;
@@ -835,7 +887,7 @@ struct smooth_kernelOp {
     const int idx[3] = {i, j, k};
     const int c = i + a.n[0] * (j + a.n[1] * k);
     const T r = rhs[c] - apply_A(a, phi, idx, c);
-    T dn = (T)cr * r / a.diag[c];
+    T dn = (T)cr * r / diag_at(a, c);
     if (dprev) dn += (T)cd * dprev[c];
     out[c] = phi[c] + dn;
     if (dout) dout[c] = dn;
@@ -1103,11 +1155,11 @@ struct FirstSweepT {
 // every load is coalesced), each the two cells of a column pair in z (3D);
 // the pairs along i add by a lane shuffle, along j through LDS.  Fixed
 // summation order: bitwise reproducible.
-template <typename T>
+template <typename T, typename CT = T>
 struct resrestrict_kernelOp {
-  static constexpr int KIND = kind_of<T>(BK_RESR_F, BK_RESR_D), BOUND = 256;
+  static constexpr int KIND = kind_of<T, CT>(BK_RESR_F, BK_RESR_D, BK_RESR_H), BOUND = 256;
   struct Args {
-    LevelArgsT<T> a;
+    LevelArgsT<T, CT> a;
     const T* phi;
     const T* rhs;
     int nc0;
@@ -1119,7 +1171,7 @@ struct resrestrict_kernelOp {
   };
   static __device__ void body(const Args& k_, const Blk& b_) {
     if (k_.flag[0]) return;
-    const LevelArgsT<T>& a = k_.a;
+    const LevelArgsT<T, CT>& a = k_.a;
     const int i = b_.x * 64 + threadIdx.x, j = b_.y * 4 + threadIdx.y, K = b_.z;
     T s = (T)0;
     if (i < a.n[0] && j < a.n[1]) {
@@ -1364,7 +1416,6 @@ struct prolong_kernelOp {
 // LDS by one wavefront when the level is small enough), prolongation, with
 // workgroup barriers between the phases.  Each phase costs a few L2 round
 // trips, so only levels of a few hundred cells are worth keeping here.
-constexpr int SMALL_CELLS = 512;
 constexpr int MAX_SMALL = 8;
 constexpr int COARSE_LDS = 384;  // coarsest levels up to this many cells are solved in LDS
 template <typename T>
@@ -1796,8 +1847,9 @@ static int first_small_level(const GridCtx& G) {
 // and the result ends in phi.  With partials != null the last step sums the
 // squared residual of its input.
 template <typename T>
-static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStream_t st,
-                      double* first_partials = nullptr, double rtol2 = 0.0, bool first_done = false) {
+static T* chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStream_t st,
+                   double* first_partials = nullptr, double rtol2 = 0.0, bool first_done = false,
+                   T* start = nullptr) {
   const Level& L = G.lev[l];
   const LevelArgsT<T> a = level_args_t<T>(G, l);
   const LevelVec<T> v = level_vec<T>(G, l);
@@ -1805,11 +1857,14 @@ static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStre
   const double lmax = L.lam_max, lmin = L.lam_max / 8.0;
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   double rho = 1.0 / sigma;
-  // first_done: the step from the zero guess was taken by the kernel that
-  // wrote the right side (phi2 and aux hold it)
+  // the sweeps alternate between the start buffer (phi unless given) and the
+  // other one; first_done: the step from the zero guess was taken by the
+  // kernel that wrote the right side (phi2 and aux hold it)
+  T* A = start ? start : v.phi;
+  T* B = A == v.phi ? v.phi2 : v.phi;
   for (int s = first_done ? 1 : 0; s < nu; ++s) {
-    const T* in = (s & 1) ? v.phi2 : v.phi;
-    T* out = (s & 1) ? v.phi : v.phi2;
+    const T* in = (s & 1) ? B : A;
+    T* out = (s & 1) ? A : B;
     double cr, cd;
     if (s == 0) {
       cr = 1.0 / theta;
@@ -1822,7 +1877,18 @@ static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStre
     }
     const bool last = s + 1 == nu;
     double* pp = last ? partials : (s == 0 ? first_partials : nullptr);
-    op_launch<smooth_kernelOp<T>>(gr, BLOCK3, typename smooth_kernelOp<T>::Args{a, in, (const T*)v.rhs, out, cr, cd, (const T*)(s == 0 ? nullptr : v.aux), last ? (T*)nullptr : v.aux, (const int*)G.mg_flag, pp}, st);
+    const T* dprev = s == 0 ? nullptr : v.aux;
+    T* dout = last ? nullptr : v.aux;
+    bool done = false;
+    if constexpr (sizeof(T) == 4) {
+      if (L.h_diag) {
+        const LevelArgsT<float, __half> ah = level_args_h(G, l);
+        op_launch<smooth_kernelOp<float, __half>>(gr, BLOCK3, typename smooth_kernelOp<float, __half>::Args{ah, in, (const T*)v.rhs, out, cr, cd, dprev, dout, (const int*)G.mg_flag, pp}, st);
+        done = true;
+      }
+    }
+    if (!done)
+      op_launch<smooth_kernelOp<T>>(gr, BLOCK3, typename smooth_kernelOp<T>::Args{a, in, (const T*)v.rhs, out, cr, cd, dprev, dout, (const int*)G.mg_flag, pp}, st);
     if (s == 0 && first_partials) {
       // the residual entering the first step is the solve's initial residual:
       // stop here when the initial guess already meets the tolerance
@@ -1830,6 +1896,7 @@ static void chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStre
       op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{(const double*)first_partials, nblk, G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 0}, st);
     }
   }
+  return (nu & 1) ? B : A;
 }
 
 // Largest ratio of a cell's face coefficients (w_a = J g^aa dV / h_a^2) on
@@ -1951,7 +2018,7 @@ template <typename T>
 static FirstSweepT<T> first_sweep(const GridCtx& G, int l, int nu) {
   FirstSweepT<T> f;
   memset(&f, 0, sizeof(f));
-  if (l >= first_small_level(G) || nu < 2 || line_level(G, nu, sizeof(T) == 4)) return f;
+  if (l >= first_small_level(G) || nu < 1 || line_level(G, nu, sizeof(T) == 4)) return f;
   const LevelVec<T> v = level_vec<T>(G, l);
   const double lmax = G.lev[l].lam_max, lmin = lmax / 8.0;
   f.diag = level_args_t<T>(G, l).diag;
@@ -1965,27 +2032,32 @@ static FirstSweepT<T> first_sweep(const GridCtx& G, int l, int nu) {
 // preconditioner of an anisotropic operator (its summed residual is not
 // needed there), Chebyshev otherwise
 template <typename T>
-static void smooth_level(const GridCtx& G, int l, int nu, bool post, double* partials, hipStream_t st,
-                         double* first_partials = nullptr, double rtol2 = 0.0, bool first_done = false) {
+static T* smooth_level(const GridCtx& G, int l, int nu, bool post, double* partials, hipStream_t st,
+                       double* first_partials = nullptr, double rtol2 = 0.0, bool first_done = false,
+                       T* start = nullptr) {
   if constexpr (sizeof(T) == 4) {
     // one sweep along every axis in place of two point-smoothing steps (2D;
     // in 3D two, so that the result ends in phi), the post-smoothing in
     // reverse axis order so that the V-cycle stays symmetric
     const int nl = G.g.dim == 2 ? nu / 2 : nu;
-    if (G.anisotropy > LINE_ANISO && !partials && !first_partials && nl > 0 && (nl * G.g.dim) % 2 == 0) {
+    const T* phi = level_vec<T>(G, l).phi;
+    if (G.anisotropy > LINE_ANISO && !partials && !first_partials && nl > 0 && (nl * G.g.dim) % 2 == 0 &&
+        (!start || start == phi)) {
       line_sweeps<T>(G, l, nl, post, st);
-      return;
+      return level_vec<T>(G, l).phi;
     }
   }
-  chebyshev<T>(G, l, nu, partials, st, first_partials, rtol2, first_done);
+  return chebyshev<T>(G, l, nu, partials, st, first_partials, rtol2, first_done, start);
 }
 
 // One V-cycle from level l in precision T.  With partials != null, the last
 // smoothing sweep on level 0 also sums the squared residual (of its input) per
 // block.
+// Returns the buffer holding the level's result (phi, or phi2 after an odd
+// number of sweeps).
 template <typename T>
-static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, hipStream_t st,
-                   double* first_partials = nullptr, double rtol2 = 0.0, bool first_done = false) {
+static T* vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, hipStream_t st,
+                 double* first_partials = nullptr, double rtol2 = 0.0, bool first_done = false) {
   const int ls = first_small_level(G);
   if (l >= ls) {
     SmallLevels<T> S;
@@ -2006,18 +2078,18 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
     // (1e-6); when it is the whole grid of an FP64 solve it is solved to 1e-13.
     const double coarse_tol2 = (l == 0 && S.nl == 1 && sizeof(T) == 8) ? 1e-26 : 1e-12;
     op_launch<small_vcycle_kernelOp<T>>(dim3(1), dim3(1024), typename small_vcycle_kernelOp<T>::Args{S, nu1, nu2, coarse_tol2, G.all_periodic, (const int*)G.mg_flag}, st);
-    return;
+    return S.phi[0];
   }
   const Level& L = G.lev[l];
   const LevelArgsT<T> a = level_args_t<T>(G, l);
   const LevelVec<T> v = level_vec<T>(G, l);
   const dim3 gr = grid3(L);
-  smooth_level<T>(G, l, nu1, false, nullptr, st, first_partials, rtol2, first_done);
+  T* cur = smooth_level<T>(G, l, nu1, false, nullptr, st, first_partials, rtol2, first_done);
   const Level& C = G.lev[l + 1];
   const LevelVec<T> cv = level_vec<T>(G, l + 1);
   bool coarse_first = false;
   if (G.restrict_transpose) {
-    op_launch<residual_kernelOp<T>>(gr, BLOCK3, typename residual_kernelOp<T>::Args{a, (const T*)v.phi, (const T*)v.rhs, v.res, (const int*)G.mg_flag}, st);
+    op_launch<residual_kernelOp<T>>(gr, BLOCK3, typename residual_kernelOp<T>::Args{a, (const T*)cur, (const T*)v.rhs, v.res, (const int*)G.mg_flag}, st);
     op_launch<restrict_kernelOp<T>>(grid3(C), BLOCK3, typename restrict_kernelOp<T>::Args{a, (const T*)v.res, C.n[0], C.n[1], C.n[2], cv.rhs, cv.phi, (const int*)G.mg_flag}, st);
   } else {
     // residual and summing restriction in one pass, with the coarse level's
@@ -2025,11 +2097,20 @@ static void vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, 
     const FirstSweepT<T> fs = first_sweep<T>(G, l + 1, nu1);
     coarse_first = fs.diag != nullptr;
     const dim3 rg((unsigned)((L.n[0] + 63) / 64), (unsigned)((L.n[1] + 3) / 4), (unsigned)C.n[2]);
-    op_launch<resrestrict_kernelOp<T>>(rg, dim3(64, 4, 1), typename resrestrict_kernelOp<T>::Args{a, (const T*)v.phi, (const T*)v.rhs, C.n[0], C.n[1], cv.rhs, cv.phi, fs, (const int*)G.mg_flag}, st);
+    bool done = false;
+    if constexpr (sizeof(T) == 4) {
+      if (L.h_diag) {
+        const LevelArgsT<float, __half> ah = level_args_h(G, l);
+        op_launch<resrestrict_kernelOp<float, __half>>(rg, dim3(64, 4, 1), typename resrestrict_kernelOp<float, __half>::Args{ah, (const T*)cur, (const T*)v.rhs, C.n[0], C.n[1], cv.rhs, cv.phi, fs, (const int*)G.mg_flag}, st);
+        done = true;
+      }
+    }
+    if (!done)
+      op_launch<resrestrict_kernelOp<T>>(rg, dim3(64, 4, 1), typename resrestrict_kernelOp<T>::Args{a, (const T*)cur, (const T*)v.rhs, C.n[0], C.n[1], cv.rhs, cv.phi, fs, (const int*)G.mg_flag}, st);
   }
-  vcycle<T>(G, l + 1, nu1, nu2, nullptr, st, nullptr, 0.0, coarse_first);
-  op_launch<prolong_kernelOp<T>>(gr, BLOCK3, typename prolong_kernelOp<T>::Args{a, v.phi, (const T*)cv.phi, C.n[0], C.n[1], C.n[2], (const int*)G.mg_flag}, st);
-  smooth_level<T>(G, l, nu2, true, partials, st);
+  const T* ce = vcycle<T>(G, l + 1, nu1, nu2, nullptr, st, nullptr, 0.0, coarse_first);
+  op_launch<prolong_kernelOp<T>>(gr, BLOCK3, typename prolong_kernelOp<T>::Args{a, cur, ce, C.n[0], C.n[1], C.n[2], (const int*)G.mg_flag}, st);
+  return smooth_level<T>(G, l, nu2, true, partials, st, nullptr, 0.0, false, cur);
 }
 
 // ----------------------------------------------------------------------------
@@ -2198,7 +2279,8 @@ struct fcg_update_kernelOp {
   struct Args {
     LevelArgs a;
     const double* sc;
-    float* z;
+    const float* z;  // the preconditioner's result
+    float* z0;       // its level-0 start buffer: cleared (zero guess) unless fs takes the first step
     double* p;
     const double* w;
     double* q;
@@ -2213,7 +2295,7 @@ struct fcg_update_kernelOp {
   static __device__ void body(const Args& k_, const Blk& b_) {
     const LevelArgs& a = k_.a;
     const double* __restrict__ sc = k_.sc;
-    float* z = k_.z;
+    const float* z = k_.z;
     double* p = k_.p;
     const double* __restrict__ w = k_.w;
     double* q = k_.q;
@@ -2244,7 +2326,7 @@ struct fcg_update_kernelOp {
     if (k_.fs.diag)
       k_.fs.apply(c, (float)rc);
     else
-      z[c] = 0.0f;
+      k_.z0[c] = 0.0f;
     rr = rc * rc;
   }
   const double t = block_sum(rr);
@@ -2274,13 +2356,16 @@ static int launch_fcg_solve(const GridCtx& G, double rtol2, int max_iter, int nu
   op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{(const double*)G.mg_partials, nblk, G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 0}, st);
   for (int it = 0; it < max_iter; ++it) {
     const int first = it == 0;
+    // z: the preconditioner's result (level 0's FP32 phi, or phi2 after an
+    // odd number of sweeps)
+    const float* z = L.f_phi;
     if (G.boxmg)
       boxmg_vcycle(G, 0, st);
     else
-      vcycle<float>(G, 0, nu1, nu2, nullptr, st, nullptr, 0.0, fs.diag != nullptr);
-    op_launch<fcg_apply_kernelOp>(gr, BLOCK3, fcg_apply_kernelOp::Args{a, (const float*)L.f_phi, (const double*)G.kr, (const double*)G.kq, G.kw, G.k_partials, nblk, first, (const int*)G.mg_flag}, st);
+      z = vcycle<float>(G, 0, nu1, nu2, nullptr, st, nullptr, 0.0, fs.diag != nullptr);
+    op_launch<fcg_apply_kernelOp>(gr, BLOCK3, fcg_apply_kernelOp::Args{a, z, (const double*)G.kr, (const double*)G.kq, G.kw, G.k_partials, nblk, first, (const int*)G.mg_flag}, st);
     op_launch<fcg_coef_kernelOp>(dim3(1), dim3(1024), fcg_coef_kernelOp::Args{(const double*)G.k_partials, nblk, G.scalars, first, (const int*)G.mg_flag}, st);
-    op_launch<fcg_update_kernelOp>(gr, BLOCK3, fcg_update_kernelOp::Args{a, (const double*)G.scalars, L.f_phi, G.kp, (const double*)G.kw, G.kq, L.phi, G.kr, L.f_rhs, first, G.mg_partials, (const int*)G.mg_flag, fs}, st);
+    op_launch<fcg_update_kernelOp>(gr, BLOCK3, fcg_update_kernelOp::Args{a, (const double*)G.scalars, z, L.f_phi, G.kp, (const double*)G.kw, G.kq, L.phi, G.kr, L.f_rhs, first, G.mg_partials, (const int*)G.mg_flag, fs}, st);
     op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{(const double*)G.mg_partials, nblk, G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 1}, st);
   }
   return max_iter;
@@ -2292,19 +2377,61 @@ __global__ void to_f32_kernel(long long n, const double* __restrict__ src, float
   if (c < n) dst[c] = (float)src[c];
 }
 
-void launch_operator_f32(const GridCtx& G, hipStream_t st) {
+// largest magnitude of an array (as the bits of a non-negative float, whose
+// order is that of the unsigned integers)
+__global__ void absmax_kernel(long long n, const double* __restrict__ src, unsigned* out) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  float m = c < n ? (float)fabs(src[c]) : 0.0f;
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(out, __float_as_uint(m));
+}
+
+__global__ void to_f16_kernel(long long n, const double* __restrict__ src, double scale, __half* dst) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) dst[c] = __float2half_rn((float)(src[c] * scale));
+}
+
+int launch_operator_f32(GridCtx& G, hipStream_t st) {
   for (int l = 0; l < G.nlev; ++l) {
-    const Level& L = G.lev[l];
+    Level& L = G.lev[l];
     if (!L.f_diag) continue;
     const unsigned blocks = (unsigned)((L.ncells + 255) / 256);
     hipLaunchKernelGGL(to_f32_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.diag, L.f_diag);
     for (int k = 0; k < 9; ++k)
       if (L.S[k] && L.f_S[k])
         hipLaunchKernelGGL(to_f32_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.S[k], L.f_S[k]);
+    if (!L.h_diag) continue;
+    // scale 2^-e with 2^e the smallest power of two at or above the largest
+    // coefficient: FP16 keeps 11 bits of every coefficient above 2^-14 of it
+    unsigned* tmp = (unsigned*)G.mg_flag + 3;
+    launch_fill_u8(tmp, 0, sizeof(unsigned), st);
+    hipLaunchKernelGGL(absmax_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.diag, tmp);
+    for (int k = 0; k < 9; ++k)
+      if (L.S[k]) hipLaunchKernelGGL(absmax_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.S[k], tmp);
+    unsigned bits = 0;
+    if (hipMemcpyAsync(&bits, tmp, sizeof(bits), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return -1;
+    float amax;
+    memcpy(&amax, &bits, sizeof(amax));
+    int e = 0;
+    if (amax > 0.0f && std::isfinite(amax)) {
+      (void)frexp((double)amax, &e);  // amax = m 2^e, 1/2 <= m < 1
+    }
+    const double scale = ldexp(1.0, -e);
+    L.h_inv = (float)ldexp(1.0, e);
+    hipLaunchKernelGGL(to_f16_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.diag, scale,
+                       (__half*)L.h_diag);
+    for (int k = 0; k < 9; ++k)
+      if (L.S[k] && L.h_S[k])
+        hipLaunchKernelGGL(to_f16_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.S[k], scale,
+                           (__half*)L.h_S[k]);
   }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Solve A phi = rhs on level 0 (phi holds the initial guess).  Returns the
+// Solve A phi = rhs on level 0 (phi holds the initial guess; the plain
+// V-cycles need nu1 + nu2 even, so that their result lands in phi).  Returns the
 // number of cycles launched; the number executed is in mg_flag[1].  With the
 // Krylov vectors present each cycle is one flexible-CG iteration and the test
 // uses the updated residual; with plain V-cycles the test after a cycle uses
@@ -3335,6 +3462,8 @@ static void replay_one(int kind, dim3 g, dim3 b, const void* a, int n, hipStream
     case BK_EF3F: op_replay<efield_kernelOp<3, float>>(g, b, a, n, st); break;
     case BK_EF3D: op_replay<efield_kernelOp<3, double>>(g, b, a, n, st); break;
     case BK_RESR_F: op_replay<resrestrict_kernelOp<float>>(g, b, a, n, st); break;
+    case BK_RESR_H: op_replay<resrestrict_kernelOp<float, __half>>(g, b, a, n, st); break;
+    case BK_SMOOTH_H: op_replay<smooth_kernelOp<float, __half>>(g, b, a, n, st); break;
     case BK_RESR_D: op_replay<resrestrict_kernelOp<double>>(g, b, a, n, st); break;
     default: break;
   }

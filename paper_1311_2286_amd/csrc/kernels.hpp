@@ -159,6 +159,13 @@ struct Level {
   float* f_rhs;
   float* f_res;
   float* f_aux;
+  // FP16 copy of the operator scaled by 2^-e (largest magnitude at most 1),
+  // h_inv = 2^e: the preconditioner's smoothing and residual on the levels of
+  // more than a few hundred cells, where they are bound by memory traffic
+  // (null elsewhere)
+  unsigned short* h_S[9];
+  unsigned short* h_diag;
+  float h_inv;
   // variational coarse operator (levels >= 1 of CPIC_MG_BOXMG, 2D): 25
   // coefficients per cell, offset-major, FP64 and its FP32 copy
   double* gal64;
@@ -222,7 +229,9 @@ void launch_rhs(const GridCtx& G, hipStream_t st);
 // more cycles than its cap stops at the cap on the device
 int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int nu2, hipStream_t st, int cap = 0);
 int compute_smoother_bounds(GridCtx& G, hipStream_t st);
-void launch_operator_f32(const GridCtx& G, hipStream_t st);
+// FP32 (and, where allocated, scaled FP16) copies of every level's operator;
+// waits for the stream; -1 on a HIP error
+int launch_operator_f32(GridCtx& G, hipStream_t st);
 int setup_coarse_inverse(GridCtx& G, hipStream_t st);
 int setup_floating_wall(GridCtx& G, hipStream_t st);
 // coarse operators P^T A P of the CPIC_MG_BOXMG hierarchy (set-up, before the coarse inverse)
@@ -234,6 +243,9 @@ struct WallCharge {
   double qw[8];
 };
 void launch_floating_wall(const GridCtx& G, const WallCharge& wc, hipStream_t st);
+// levels of at most this many cells are smoothed inside one workgroup (the
+// V-cycle's tail kernel)
+constexpr int SMALL_CELLS = 512;
 constexpr int DENSE_MAX = 640;  // coarsest levels up to this many cells are solved by a dense inverse
 // operators more anisotropic than this (face-coefficient ratio within a cell)
 // use the transpose of the prolongation as restriction
