@@ -79,6 +79,39 @@ __host__ __device__ inline int tile_of_key(int key, const Geo& g) {
   return ti + g.nt[0] * (tj + g.nt[1] * tk);
 }
 
+// Per thread of a one-dimensional workgroup, the sums over m < M of
+// p[m * ld + i] for i = threadIdx.x + k blockDim.x < n, in a fixed order: U
+// running sums per array over interleaved strides (U M loads in flight per
+// thread instead of one chain of dependent loads), added pairwise at the end.
+template <int M, int U>
+__device__ inline void strided_sums(const double* __restrict__ p, int ld, int n, double* out) {
+  const int B = blockDim.x;
+  double a[M][U];
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[m][u] = 0.0;
+  int i = threadIdx.x;
+  for (; i + (U - 1) * B < n; i += U * B) {
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int u = 0; u < U; ++u) a[m][u] += p[m * (size_t)ld + i + u * B];
+  }
+  for (; i < n; i += B) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) a[m][0] += p[m * (size_t)ld + i];
+  }
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+#pragma unroll
+    for (int w = 1; w < U; w *= 2)
+#pragma unroll
+      for (int u = 0; u + w < U; u += 2 * w) a[m][u] += a[m][u + w];
+    out[m] = a[m][0];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Trigonometric helpers.  sin/cos of 2 pi u at the base position: in FP32 the
 // hardware instructions, which take their argument in revolutions (valid for

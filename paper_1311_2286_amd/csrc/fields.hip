@@ -686,12 +686,20 @@ struct reduce_partial_kernelOp {
     const int* flag = k_.flag;
 
   if (flag && flag[0]) return;
-  double s = 0.0;
-  for (long long i = (long long)b_.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)b_.gx * blockDim.x) {
-    double x = a[i];
-    s += (kind == 0) ? x * b[i] : (kind == 1 ? x : x * x);
+  // grid-stride, four running sums (four loads in flight), added pairwise
+  const long long stride = (long long)b_.gx * blockDim.x;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  auto term = [&](long long i) {
+    const double x = a[i];
+    return (kind == 0) ? x * b[i] : (kind == 1 ? x : x * x);
+  };
+  long long i = (long long)b_.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += term(i + u * stride);
   }
+  for (; i < n; i += stride) acc[0] += term(i);
+  const double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   double t = block_sum(s);
   if (threadIdx.x == 0) partials[b_.x] = t;
 
@@ -723,9 +731,9 @@ struct reduce_final_kernelOp {
     int count_cycle = k_.count_cycle;
 
   if (op == 1 && flag[0]) return;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partials[i];
-  // fixed-order: each thread's strided sum, then the block tree
+  double s;
+  strided_sums<1, 8>(partials, 0, nb, &s);
+  // fixed-order: each thread's strided sums, then the block tree
   double t = block_sum(s);
   if (threadIdx.x == 0) {
     *out = t;
@@ -1659,9 +1667,22 @@ struct small_vcycle_kernelOp {
       }
       for (int c = threadIdx.x; c < ncl; c += blockDim.x) lb[c] = (T)((double)S.rhs[last][c] - bmean);
       __syncthreads();
-      for (int i = threadIdx.x; i < ncl; i += blockDim.x) {
+      // the workgroup's threads split the columns into ng groups (thread
+      // i + ncl g takes rows i, columns j = g mod ng), so that each thread has
+      // ncl / ng loads to wait for instead of ncl; the groups' sums are added
+      // in group order
+      const int ng = ncl <= (int)blockDim.x ? (int)blockDim.x / ncl : 1;
+      __shared__ T part[1024];
+      for (int t = threadIdx.x; t < ncl * ng; t += blockDim.x) {
+        const int i = t % ncl, g = t / ncl;
         T acc = (T)0;
-        for (int j = 0; j < ncl; ++j) acc += S.cinv[(size_t)j * ncl + i] * lb[j];
+        for (int j = g; j < ncl; j += ng) acc += S.cinv[(size_t)j * ncl + i] * lb[j];
+        part[t] = acc;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < ncl; i += blockDim.x) {
+        T acc = part[i];
+        for (int g = 1; g < ng; ++g) acc += part[i + ncl * g];
         S.phi[last][i] = acc;
       }
       __syncthreads();
@@ -2248,12 +2269,9 @@ struct fcg_coef_kernelOp {
     const int* flag = k_.flag;
 
   if (flag[0]) return;
-  double v[3];
-  for (int m = 0; m < 3; ++m) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partials[m * nblk + i];
-    v[m] = block_sum(s);
-  }
+  double v[3], s[3];
+  strided_sums<3, 4>(partials, nblk, nblk, s);
+  for (int m = 0; m < 3; ++m) v[m] = block_sum(s[m]);
   if (threadIdx.x == 0) {
     const double zw = v[0], qz = v[1], zr = v[2];
     const double pq_prev = sc[7];

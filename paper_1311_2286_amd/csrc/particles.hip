@@ -2176,8 +2176,8 @@ __global__ __launch_bounds__(256) void ke_reduce_kernel(KeReduce r) {
   double total = 0.0;
   for (int k = 0; k < r.nspecies; ++k) {
     const int n = *r.n_items[k] + r.tail[k];
-    double t = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) t += r.part[k][i];
+    double t;
+    strided_sums<1, 8>(r.part[k], 0, n, &t);
     sh[threadIdx.x] = t;
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
