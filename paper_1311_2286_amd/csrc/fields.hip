@@ -1109,30 +1109,6 @@ struct residual_kernelOp {
   }
 };
 
-// Two restrictions.  Summing the 2^d children's residuals is the cheaper and,
-// on near-isotropic grids, the faster one; but with the bilinear prolongation
-// it makes the V-cycle non-symmetric, and flexible CG can then stall on
-// strongly anisotropic operators.  There the transpose of the prolongation is
-// used, which makes the V-cycle symmetric and keeps the conjugate-gradient
-// convergence guarantee (the choice is made once, at set-up).
-//
-// Summing restriction of the residual computed on the fly (small levels):
-template <typename T>
-__device__ inline T restrict_cell(const LevelArgsT<T>& fa, const T* __restrict__ phi, const T* __restrict__ rhs,
-                                  const int* I) {
-  const int d = fa.dim;
-  T s = (T)0;
-  const int nz = (d == 3) ? 2 : 1;
-  for (int sz = 0; sz < nz; ++sz)
-    for (int sy = 0; sy < 2; ++sy)
-      for (int sx = 0; sx < 2; ++sx) {
-        int idx[3] = {2 * I[0] + sx, 2 * I[1] + sy, (d == 3) ? 2 * I[2] + sz : 0};
-        int c = idx[0] + fa.n[0] * (idx[1] + fa.n[1] * idx[2]);
-        s += rhs[c] - apply_A(fa, phi, idx, c);
-      }
-  return s;
-}
-
 // The first Chebyshev step of a smoothing that starts from a zero guess needs
 // no residual: phi2 = aux = cr r / diag (then the step from phi2 follows).
 // Kernels that produce the right side r of such a level apply it as they
@@ -1156,6 +1132,13 @@ struct FirstSweepT {
   double cr;
 };
 
+// Two restrictions.  Summing the 2^d children's residuals is the cheaper and,
+// on near-isotropic grids, the faster one; but with the bilinear prolongation
+// it makes the V-cycle non-symmetric, and flexible CG can then stall on
+// strongly anisotropic operators.  There the transpose of the prolongation is
+// used, which makes the V-cycle symmetric and keeps the conjugate-gradient
+// convergence guarantee (the choice is made once, at set-up).
+//
 // Residual of the fine level summed over each coarse cell's children (the
 // summing restriction); coarse phi = 0, or with fs.diag set the coarse
 // level's first Chebyshev step from zero.  Threads take fine cells as the
@@ -1636,17 +1619,28 @@ struct small_vcycle_kernelOp {
     }
     const LevelArgsT<T>& ca = S.a[l + 1];
     const int ncc = ca.n[0] * ca.n[1] * ca.n[2];
-    if (S.transpose) {
-      const int nc = a.n[0] * a.n[1] * a.n[2];
-      for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        int idx[3] = {c % a.n[0], (c / a.n[0]) % a.n[1], c / (a.n[0] * a.n[1])};
-        S.res[l][c] = S.rhs[l][c] - apply_A(a, S.phi[l], idx, c);
-      }
-      __syncthreads();
+    // the residual of every fine cell at once, then the coarse right side
+    // from it (the summing restriction adds the children x fastest, then y, z)
+    const int nc = a.n[0] * a.n[1] * a.n[2];
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      int idx[3] = {c % a.n[0], (c / a.n[0]) % a.n[1], c / (a.n[0] * a.n[1])};
+      S.res[l][c] = S.rhs[l][c] - apply_A(a, S.phi[l], idx, c);
     }
+    __syncthreads();
     for (int C = threadIdx.x; C < ncc; C += blockDim.x) {
       int I[3] = {C % ca.n[0], (C / ca.n[0]) % ca.n[1], C / (ca.n[0] * ca.n[1])};
-      S.rhs[l + 1][C] = S.transpose ? restrict_transpose(a, S.res[l], ca.n, I) : restrict_cell(a, S.phi[l], S.rhs[l], I);
+      T r;
+      if (S.transpose) {
+        r = restrict_transpose(a, S.res[l], ca.n, I);
+      } else {
+        r = (T)0;
+        const int nz = (a.dim == 3) ? 2 : 1;
+        for (int sz = 0; sz < nz; ++sz)
+          for (int sy = 0; sy < 2; ++sy)
+            for (int sx = 0; sx < 2; ++sx)
+              r += S.res[l][2 * I[0] + sx + a.n[0] * (2 * I[1] + sy + a.n[1] * ((a.dim == 3) ? 2 * I[2] + sz : 0))];
+      }
+      S.rhs[l + 1][C] = r;
       S.phi[l + 1][C] = 0.0;
     }
     __syncthreads();
@@ -1675,9 +1669,15 @@ struct small_vcycle_kernelOp {
       __shared__ T part[1024];
       for (int t = threadIdx.x; t < ncl * ng; t += blockDim.x) {
         const int i = t % ncl, g = t / ncl;
-        T acc = (T)0;
-        for (int j = g; j < ncl; j += ng) acc += S.cinv[(size_t)j * ncl + i] * lb[j];
-        part[t] = acc;
+        // eight running sums, so that eight loads of the inverse are in flight
+        T acc[8] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+        int j = g;
+        for (; j + 7 * ng < ncl; j += 8 * ng) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[u] += S.cinv[(size_t)(j + u * ng) * ncl + i] * lb[j + u * ng];
+        }
+        for (; j < ncl; j += ng) acc[0] += S.cinv[(size_t)j * ncl + i] * lb[j];
+        part[t] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
       }
       __syncthreads();
       for (int i = threadIdx.x; i < ncl; i += blockDim.x) {
