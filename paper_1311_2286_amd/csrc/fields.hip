@@ -619,6 +619,10 @@ void launch_charge(const GridCtx& G, const ChargeSpecies& cs, double bg_charge, 
 // deterministic reductions: fixed grid of 256 blocks, fixed-order tree
 // ----------------------------------------------------------------------------
 constexpr int RED_BLOCKS = REDUCE_BLOCKS;
+// the field phase's sums over the level-0 cells (right side, |b|^2, gauge):
+// four workgroups per CU keep enough loads in flight for HBM; G.partials holds
+// this many partial sums
+constexpr int FIELD_RED_BLOCKS = 1024;
 
 __device__ inline double block_sum(double v) {
   __shared__ double sh[16];
@@ -747,10 +751,11 @@ struct reduce_final_kernelOp {
   }
 };
 
+// blocks: the number of partial sums, which partials must hold
 static void reduce(const double* a, const double* b, long long n, int kind, double* partials, double* out,
-                   hipStream_t st) {
-  op_launch<reduce_partial_kernelOp>(dim3(RED_BLOCKS), dim3(256), reduce_partial_kernelOp::Args{a, b, n, kind, partials, (const int*)nullptr}, st);
-  op_launch<reduce_final_kernelOp>(dim3(1), dim3(256), reduce_final_kernelOp::Args{partials, RED_BLOCKS, out, 0, 0.0, (const double*)nullptr, (int*)nullptr, 0}, st);
+                   hipStream_t st, int blocks = FIELD_RED_BLOCKS) {
+  op_launch<reduce_partial_kernelOp>(dim3(blocks), dim3(256), reduce_partial_kernelOp::Args{a, b, n, kind, partials, (const int*)nullptr}, st);
+  op_launch<reduce_final_kernelOp>(dim3(1), dim3(256), reduce_final_kernelOp::Args{partials, blocks, out, 0, 0.0, (const double*)nullptr, (int*)nullptr, 0}, st);
 }
 
 // ----------------------------------------------------------------------------
@@ -2462,8 +2467,8 @@ int launch_mg_solve(const GridCtx& G, double rtol, int max_cycles, int nu1, int 
   const int nblk = (int)(gr.x * gr.y * gr.z);
   op_launch<mg_reset_kernelOp>(dim3(1), dim3(1), mg_reset_kernelOp::Args{G.mg_flag, cap > 0 ? cap : max_cycles}, st);
   // |b|^2
-  op_launch<reduce_partial_kernelOp>(dim3(RED_BLOCKS), dim3(256), reduce_partial_kernelOp::Args{L.rhs, (const double*)nullptr, L.ncells, 2, G.partials, (const int*)nullptr}, st);
-  op_launch<reduce_final_kernelOp>(dim3(1), dim3(256), reduce_final_kernelOp::Args{G.partials, RED_BLOCKS, G.scalars + 0, 0, 0.0, (const double*)nullptr, (int*)nullptr, 0}, st);
+  op_launch<reduce_partial_kernelOp>(dim3(FIELD_RED_BLOCKS), dim3(256), reduce_partial_kernelOp::Args{L.rhs, (const double*)nullptr, L.ncells, 2, G.partials, (const int*)nullptr}, st);
+  op_launch<reduce_final_kernelOp>(dim3(1), dim3(256), reduce_final_kernelOp::Args{G.partials, FIELD_RED_BLOCKS, G.scalars + 0, 0, 0.0, (const double*)nullptr, (int*)nullptr, 0}, st);
   const double rtol2 = rtol * rtol;
   if (G.kr) return launch_fcg_solve(G, rtol2, max_cycles, nu1, nu2, st);
   if (batch_unsupported()) return max_cycles;
@@ -2837,7 +2842,7 @@ void launch_rho(const GridCtx& G, double* rho, hipStream_t st) {
 }
 
 void launch_field_energy(const GridCtx& G, double* partials, double* out, hipStream_t st) {
-  reduce(G.charge, G.floating ? G.phi_full : G.lev[0].phi, G.g.ncells, 0, partials, out, st);
+  reduce(G.charge, G.floating ? G.phi_full : G.lev[0].phi, G.g.ncells, 0, partials, out, st, RED_BLOCKS);
   // W_E = 1/2 sum charge phi: the factor is applied by the host
 }
 
