@@ -863,9 +863,18 @@ __device__ inline T apply_A(const LevelArgsT<T, C>& a, const TV* __restrict__ ph
 // Chebyshev steps of the multigrid smoother use the three-term recurrence.
 // With partials != null the squared residual of the input is summed per block
 // (fixed order) for the convergence test.
+// levels of at least this many cells take two cells per thread in the FP32
+// smoothing sweeps
+constexpr long long SMOOTH_ZP_CELLS = 1 << 20;
 template <typename T, typename C = T>
 struct smooth_kernelOp {
   static constexpr int KIND = kind_of<T, C>(BK_SMOOTH_F, BK_SMOOTH_D, BK_SMOOTH_H), BOUND = 256;
+  // at most ZP cells per thread along z (Args::zp of them; the launch grid's
+  // z extent is ceil(n2 / zp)): two on the large FP32 levels, so that each
+  // wave has twice the loads in flight; one on the others, whose few blocks
+  // need every thread, and on the FP64 sweeps, whose per-block partial sums
+  // the plain V-cycles read
+  static constexpr int ZP = sizeof(T) == 4 ? 2 : 1;
   struct Args {
     LevelArgsT<T, C> a;
     const T* phi;
@@ -877,6 +886,7 @@ struct smooth_kernelOp {
     T* dout;
     const int* flag;
     double* partials;
+    int zp;
   };
   static __device__ void body(const Args& k_, const Blk& b_) {
     const LevelArgsT<T, C>& a = k_.a;
@@ -894,17 +904,32 @@ struct smooth_kernelOp {
   const Tile3 T3 = xcd_tile(b_);
   const int i = T3.bx * blockDim.x + threadIdx.x;
   const int j = T3.by * blockDim.y + threadIdx.y;
-  const int k = T3.bz;
   double rr = 0.0;
   if (i < a.n[0] && j < a.n[1]) {
-    const int idx[3] = {i, j, k};
-    const int c = i + a.n[0] * (j + a.n[1] * k);
-    const T r = rhs[c] - apply_A(a, phi, idx, c);
-    T dn = (T)cr * r / diag_at(a, c);
-    if (dprev) dn += (T)cd * dprev[c];
-    out[c] = phi[c] + dn;
-    if (dout) dout[c] = dn;
-    rr = (double)r * (double)r;
+    // the residuals of the thread's cells first, then the stores
+    T r[ZP];
+    int cz[ZP];
+#pragma unroll
+    for (int z = 0; z < ZP; ++z) {
+      const int k = T3.bz * k_.zp + z;
+      cz[z] = -1;
+      r[z] = (T)0;
+      if (z < k_.zp && k < a.n[2]) {
+        const int idx[3] = {i, j, k};
+        cz[z] = i + a.n[0] * (j + a.n[1] * k);
+        r[z] = rhs[cz[z]] - apply_A(a, phi, idx, cz[z]);
+      }
+    }
+#pragma unroll
+    for (int z = 0; z < ZP; ++z) {
+      const int c = cz[z];
+      if (c < 0) continue;
+      T dn = (T)cr * r[z] / diag_at(a, c);
+      if (dprev) dn += (T)cd * dprev[c];
+      out[c] = phi[c] + dn;
+      if (dout) dout[c] = dn;
+      rr += (double)r[z] * (double)r[z];
+    }
   }
   if (partials) {
     double t = block_sum(rr);
@@ -1879,7 +1904,8 @@ static T* chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStream
   const Level& L = G.lev[l];
   const LevelArgsT<T> a = level_args_t<T>(G, l);
   const LevelVec<T> v = level_vec<T>(G, l);
-  const dim3 gr = grid3(L);
+  const int zp = L.ncells >= SMOOTH_ZP_CELLS ? smooth_kernelOp<T>::ZP : 1;
+  const dim3 gr(grid3(L).x, grid3(L).y, (unsigned)((L.n[2] + zp - 1) / zp));
   const double lmax = L.lam_max, lmin = L.lam_max / 8.0;
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   double rho = 1.0 / sigma;
@@ -1909,12 +1935,12 @@ static T* chebyshev(const GridCtx& G, int l, int nu, double* partials, hipStream
     if constexpr (sizeof(T) == 4) {
       if (L.h_diag) {
         const LevelArgsT<float, __half> ah = level_args_h(G, l);
-        op_launch<smooth_kernelOp<float, __half>>(gr, BLOCK3, typename smooth_kernelOp<float, __half>::Args{ah, in, (const T*)v.rhs, out, cr, cd, dprev, dout, (const int*)G.mg_flag, pp}, st);
+        op_launch<smooth_kernelOp<float, __half>>(gr, BLOCK3, typename smooth_kernelOp<float, __half>::Args{ah, in, (const T*)v.rhs, out, cr, cd, dprev, dout, (const int*)G.mg_flag, pp, zp}, st);
         done = true;
       }
     }
     if (!done)
-      op_launch<smooth_kernelOp<T>>(gr, BLOCK3, typename smooth_kernelOp<T>::Args{a, in, (const T*)v.rhs, out, cr, cd, dprev, dout, (const int*)G.mg_flag, pp}, st);
+      op_launch<smooth_kernelOp<T>>(gr, BLOCK3, typename smooth_kernelOp<T>::Args{a, in, (const T*)v.rhs, out, cr, cd, dprev, dout, (const int*)G.mg_flag, pp, zp}, st);
     if (s == 0 && first_partials) {
       // the residual entering the first step is the solve's initial residual:
       // stop here when the initial guess already meets the tolerance
@@ -2169,6 +2195,7 @@ struct fcg_residual_kernelOp {
     double* partials;
     const int* flag;
     FirstSweep fs;
+    int zp;  // cells per thread along z (1 or 2; the grid's z extent is ceil(n2 / zp))
   };
   static __device__ void body(const Args& k_, const Blk& b_) {
     const LevelArgs& a = k_.a;
@@ -2184,19 +2211,33 @@ struct fcg_residual_kernelOp {
   const Tile3 T3 = xcd_tile(b_);
   const int i = T3.bx * blockDim.x + threadIdx.x;
   const int j = T3.by * blockDim.y + threadIdx.y;
-  const int k = T3.bz;
   double rr = 0.0;
   if (i < a.n[0] && j < a.n[1]) {
-    const int idx[3] = {i, j, k};
-    const int c = i + a.n[0] * (j + a.n[1] * k);
-    const double v = b[c] - apply_A(a, x, idx, c);
-    r[c] = v;
-    r32[c] = (float)v;
-    if (k_.fs.diag)
-      k_.fs.apply(c, (float)v);
-    else
-      z[c] = 0.0f;
-    rr = v * v;
+    double vz[2];
+    int cz[2] = {-1, -1};
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+      const int k = T3.bz * k_.zp + dz;
+      vz[dz] = 0.0;
+      if (dz < k_.zp && k < a.n[2]) {
+        const int idx[3] = {i, j, k};
+        cz[dz] = i + a.n[0] * (j + a.n[1] * k);
+        vz[dz] = b[cz[dz]] - apply_A(a, x, idx, cz[dz]);
+      }
+    }
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+      const int c = cz[dz];
+      if (c < 0) continue;
+      const double v = vz[dz];
+      r[c] = v;
+      r32[c] = (float)v;
+      if (k_.fs.diag)
+        k_.fs.apply(c, (float)v);
+      else
+        z[c] = 0.0f;
+      rr += v * v;
+    }
   }
   const double t = block_sum(rr);
   if (threadIdx.x == 0 && threadIdx.y == 0) partials[T3.blk] = t;
@@ -2217,6 +2258,7 @@ struct fcg_apply_kernelOp {
     int nblk;
     int first;
     const int* flag;
+    int zp;  // cells per thread along z (1 or 2)
   };
   static __device__ void body(const Args& k_, const Blk& b_) {
     const LevelArgs& a = k_.a;
@@ -2233,17 +2275,31 @@ struct fcg_apply_kernelOp {
   const Tile3 T3 = xcd_tile(b_);
   const int i = T3.bx * blockDim.x + threadIdx.x;
   const int j = T3.by * blockDim.y + threadIdx.y;
-  const int k = T3.bz;
   double zw = 0.0, qz = 0.0, zr = 0.0;
   if (i < a.n[0] && j < a.n[1]) {
-    const int idx[3] = {i, j, k};
-    const int c = i + a.n[0] * (j + a.n[1] * k);
-    const double wc = apply_A(a, z, idx, c);
-    const double zc = (double)z[c];
-    w[c] = wc;
-    zw = zc * wc;
-    qz = first ? 0.0 : q[c] * zc;
-    zr = zc * r[c];
+    double wz[2];
+    int cz[2] = {-1, -1};
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+      const int k = T3.bz * k_.zp + dz;
+      wz[dz] = 0.0;
+      if (dz < k_.zp && k < a.n[2]) {
+        const int idx[3] = {i, j, k};
+        cz[dz] = i + a.n[0] * (j + a.n[1] * k);
+        wz[dz] = apply_A(a, z, idx, cz[dz]);
+      }
+    }
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+      const int c = cz[dz];
+      if (c < 0) continue;
+      const double wc = wz[dz];
+      const double zc = (double)z[c];
+      w[c] = wc;
+      zw += zc * wc;
+      qz += first ? 0.0 : q[c] * zc;
+      zr += zc * r[c];
+    }
   }
   const int blk = T3.blk;
   double t = block_sum(zw);
@@ -2314,6 +2370,7 @@ struct fcg_update_kernelOp {
     double* partials;
     const int* flag;
     FirstSweep fs;
+    int zp;  // cells per thread along z (1 or 2)
   };
   static __device__ void body(const Args& k_, const Blk& b_) {
     const LevelArgs& a = k_.a;
@@ -2332,11 +2389,12 @@ struct fcg_update_kernelOp {
   if (flag[0]) return;
   const int i = b_.x * blockDim.x + threadIdx.x;
   const int j = b_.y * blockDim.y + threadIdx.y;
-  const int k = b_.z;
   double rr = 0.0;
-  if (i < a.n[0] && j < a.n[1]) {
+  const double alpha = sc[8], beta = sc[9];
+  for (int dz = 0; dz < k_.zp; ++dz) {
+    const int k = b_.z * k_.zp + dz;
+    if (i >= a.n[0] || j >= a.n[1] || k >= a.n[2]) continue;
     const int c = i + a.n[0] * (j + a.n[1] * k);
-    const double alpha = sc[8], beta = sc[9];
     const double zc = (double)z[c];
     const double pc = first ? zc : zc + beta * p[c];
     const double qc = first ? w[c] : w[c] + beta * q[c];
@@ -2350,7 +2408,7 @@ struct fcg_update_kernelOp {
       k_.fs.apply(c, (float)rc);
     else
       k_.z0[c] = 0.0f;
-    rr = rc * rc;
+    rr += rc * rc;
   }
   const double t = block_sum(rr);
   if (threadIdx.x == 0 && threadIdx.y == 0) partials[b_.x + b_.gx * (b_.y + b_.gy * b_.z)] = t;
@@ -2362,7 +2420,10 @@ static void boxmg_vcycle(const GridCtx& G, int l, hipStream_t st);
 static int launch_fcg_solve(const GridCtx& G, double rtol2, int max_iter, int nu1, int nu2, hipStream_t st) {
   const Level& L = G.lev[0];
   LevelArgs a = level_args(G, 0);
-  const dim3 gr = grid3(L);
+  // the level-0 kernels of the iteration: two cells per thread along z on
+  // large grids (more loads in flight per wave)
+  const int zp = L.ncells >= SMOOTH_ZP_CELLS ? 2 : 1;
+  const dim3 gr(grid3(L).x, grid3(L).y, (unsigned)((L.n[2] + zp - 1) / zp));
   const int nblk = (int)(gr.x * gr.y * gr.z);
   // the preconditioner's first smoothing step on level 0 (zero guess) is taken
   // by the kernels that write its right side
@@ -2375,7 +2436,7 @@ static int launch_fcg_solve(const GridCtx& G, double rtol2, int max_iter, int nu
     fs.aux = f.aux;
     fs.cr = (float)f.cr;
   }
-  op_launch<fcg_residual_kernelOp>(gr, BLOCK3, fcg_residual_kernelOp::Args{a, (const double*)L.phi, (const double*)L.rhs, G.kr, L.f_rhs, L.f_phi, G.mg_partials, (const int*)G.mg_flag, fs}, st);
+  op_launch<fcg_residual_kernelOp>(gr, BLOCK3, fcg_residual_kernelOp::Args{a, (const double*)L.phi, (const double*)L.rhs, G.kr, L.f_rhs, L.f_phi, G.mg_partials, (const int*)G.mg_flag, fs, zp}, st);
   op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{(const double*)G.mg_partials, nblk, G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 0}, st);
   for (int it = 0; it < max_iter; ++it) {
     const int first = it == 0;
@@ -2386,9 +2447,9 @@ static int launch_fcg_solve(const GridCtx& G, double rtol2, int max_iter, int nu
       boxmg_vcycle(G, 0, st);
     else
       z = vcycle<float>(G, 0, nu1, nu2, nullptr, st, nullptr, 0.0, fs.diag != nullptr);
-    op_launch<fcg_apply_kernelOp>(gr, BLOCK3, fcg_apply_kernelOp::Args{a, z, (const double*)G.kr, (const double*)G.kq, G.kw, G.k_partials, nblk, first, (const int*)G.mg_flag}, st);
+    op_launch<fcg_apply_kernelOp>(gr, BLOCK3, fcg_apply_kernelOp::Args{a, z, (const double*)G.kr, (const double*)G.kq, G.kw, G.k_partials, nblk, first, (const int*)G.mg_flag, zp}, st);
     op_launch<fcg_coef_kernelOp>(dim3(1), dim3(1024), fcg_coef_kernelOp::Args{(const double*)G.k_partials, nblk, G.scalars, first, (const int*)G.mg_flag}, st);
-    op_launch<fcg_update_kernelOp>(gr, BLOCK3, fcg_update_kernelOp::Args{a, (const double*)G.scalars, z, L.f_phi, G.kp, (const double*)G.kw, G.kq, L.phi, G.kr, L.f_rhs, first, G.mg_partials, (const int*)G.mg_flag, fs}, st);
+    op_launch<fcg_update_kernelOp>(gr, BLOCK3, fcg_update_kernelOp::Args{a, (const double*)G.scalars, z, L.f_phi, G.kp, (const double*)G.kw, G.kq, L.phi, G.kr, L.f_rhs, first, G.mg_partials, (const int*)G.mg_flag, fs, zp}, st);
     op_launch<reduce_final_kernelOp>(dim3(1), dim3(1024), reduce_final_kernelOp::Args{(const double*)G.mg_partials, nblk, G.scalars + 1, 1, rtol2, (const double*)(G.scalars + 0), G.mg_flag, 1}, st);
   }
   return max_iter;
