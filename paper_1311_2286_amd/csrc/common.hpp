@@ -117,18 +117,20 @@ __device__ inline void strided_sums(const double* __restrict__ p, int ld, int n,
 // hardware instructions, which take their argument in revolutions (valid for
 // |u| <= 256; measured largest absolute error 1.3e-7 on [0, 1], the rounding of
 // FP32 near 1) -- the Newton residual uses them only multiplied by the small
-// increments below, so their error is damped; in FP64, the device library's
-// sinpi/cospi.  Increments sin(2 pi u) and cos(2 pi u) - 1 for the Newton
-// steps need relative accuracy (their error is amplified by the map amplitude
-// over the Jacobian): Taylor polynomials of degree 9 and 10 in x = 2 pi u,
-// truncation below 3e-9 for |x| < 0.8, without branches; beyond (a move of
-// more than 0.13 of the grid in one step) the device library.
+// increments below, so their error is damped; in FP64, the turn reduced by
+// its nearest quarter (exactly) and the increment polynomials below on the
+// remainder (|x| <= pi/4), rotated by the quarter.  Increments sin(2 pi u)
+// and cos(2 pi u) - 1 for the Newton steps need relative accuracy (their
+// error is amplified by the map amplitude over the Jacobian): Taylor
+// polynomials in x = 2 pi u, in nested form, of degree 9 and 10 in FP32
+// (truncation below 3e-9 for |x| < 0.8) and 19 and 20 in FP64 (below 1e-21),
+// without branches; beyond |x| = 0.8 (a move of more than 0.13 of the grid in
+// one step) the device library.
 // ---------------------------------------------------------------------------
 __device__ inline void sincos2pi(float u, float& s, float& c) {
   s = __builtin_amdgcn_sinf(u);
   c = __builtin_amdgcn_cosf(u);
 }
-__device__ inline void sincos2pi(double u, double& s, double& c) { sincospi(2.0 * u, &s, &c); }
 
 __device__ inline void incr2pi(float u, float& sn, float& cm1) {
   const float th = 6.28318530717958648f * u;
@@ -145,10 +147,52 @@ __device__ inline void incr2pi(float u, float& sn, float& cm1) {
     cm1 = c - 1.0f;
   }
 }
+// sin x and cos x - 1 for |x| < 0.8 (FP64)
+__device__ inline void taylor_sin_cm1(double x, double& sn, double& cm1) {
+  const double t = x * x;
+  sn = x * (1.0 - t * (1.0 / 6.0) *
+                      (1.0 - t * (1.0 / 20.0) *
+                                 (1.0 - t * (1.0 / 42.0) *
+                                            (1.0 - t * (1.0 / 72.0) *
+                                                       (1.0 - t * (1.0 / 110.0) *
+                                                                  (1.0 - t * (1.0 / 156.0) *
+                                                                             (1.0 - t * (1.0 / 210.0) *
+                                                                                        (1.0 - t * (1.0 / 272.0) *
+                                                                                                   (1.0 - t * (1.0 / 342.0))))))))));
+  cm1 = -0.5 * t *
+        (1.0 - t * (1.0 / 12.0) *
+                   (1.0 - t * (1.0 / 30.0) *
+                              (1.0 - t * (1.0 / 56.0) *
+                                         (1.0 - t * (1.0 / 90.0) *
+                                                    (1.0 - t * (1.0 / 132.0) *
+                                                               (1.0 - t * (1.0 / 182.0) *
+                                                                          (1.0 - t * (1.0 / 240.0) *
+                                                                                     (1.0 - t * (1.0 / 306.0) *
+                                                                                                (1.0 - t * (1.0 / 380.0))))))))));
+}
+
+__device__ inline void sincos2pi(double u, double& s, double& c) {
+  const double q = rint(4.0 * u);                    // nearest quarter turn
+  const double x = 6.283185307179586 * fma(-0.25, q, u);  // u - q/4 is exact
+  double sr, cm1;
+  taylor_sin_cm1(x, sr, cm1);
+  const double cr = 1.0 + cm1;
+  switch ((int)((long long)q & 3)) {
+    case 0: s = sr; c = cr; break;
+    case 1: s = cr; c = -sr; break;
+    case 2: s = -sr; c = -cr; break;
+    default: s = -cr; c = sr; break;
+  }
+}
+
 __device__ inline void incr2pi(double u, double& sn, double& cm1) {
-  sn = sinpi(2.0 * u);
-  double h = sinpi(u);
-  cm1 = -2.0 * h * h;
+  const double x = 6.283185307179586 * u;
+  taylor_sin_cm1(x, sn, cm1);
+  if (!(fabs(x) < 0.8)) {
+    sn = sinpi(2.0 * u);
+    double h = sinpi(u);
+    cm1 = -2.0 * h * h;
+  }
 }
 
 template <typename R> __device__ inline R r_expm1(R x);
