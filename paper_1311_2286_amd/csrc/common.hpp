@@ -147,7 +147,8 @@ __device__ inline void incr2pi(float u, float& sn, float& cm1) {
     cm1 = c - 1.0f;
   }
 }
-// sin x and cos x - 1 for |x| < 0.8 (FP64)
+// sin x and cos x - 1 for |x| < 0.8 (FP64), in nested form (few live
+// constants: the particle kernel keeps its register budget)
 __device__ inline void taylor_sin_cm1(double x, double& sn, double& cm1) {
   const double t = x * x;
   sn = x * (1.0 - t * (1.0 / 6.0) *
@@ -172,17 +173,16 @@ __device__ inline void taylor_sin_cm1(double x, double& sn, double& cm1) {
 }
 
 __device__ inline void sincos2pi(double u, double& s, double& c) {
-  const double q = rint(4.0 * u);                    // nearest quarter turn
+  const double q = rint(4.0 * u);                         // nearest quarter turn
   const double x = 6.283185307179586 * fma(-0.25, q, u);  // u - q/4 is exact
   double sr, cm1;
   taylor_sin_cm1(x, sr, cm1);
   const double cr = 1.0 + cm1;
-  switch ((int)((long long)q & 3)) {
-    case 0: s = sr; c = cr; break;
-    case 1: s = cr; c = -sr; break;
-    case 2: s = -sr; c = -cr; break;
-    default: s = -cr; c = sr; break;
-  }
+  // rotation by k quarter turns: (s, c) = (sr, cr), (cr, -sr), (-sr, -cr), (-cr, sr)
+  const int k = (int)((long long)q & 3);
+  const double a = (k & 1) ? cr : sr, b = (k & 1) ? sr : cr;
+  s = (k & 2) ? -a : a;
+  c = (k == 1 || k == 2) ? -b : b;
 }
 
 __device__ inline void incr2pi(double u, double& sn, double& cm1) {
