@@ -146,6 +146,9 @@ def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, grap
     if graphs:
         sim.set_graphs(True)
     bounded = any(b != 0 for b in case.bc_lo[: case.dim])
+    # the particles cross PCIe once, here (host arrays in, resident in HBM
+    # from then on): timed, for the rate that includes the upload
+    upload_s, upload_bytes = 0.0, 0
     for sid, s in enumerate(case.species):
         p = parts[sid]
         n = p["cell"].size
@@ -159,8 +162,14 @@ def make_sim(case, precision, shape, sort_every, mg_rtol, mg_cycles, parts, grap
                         seed=1311 + sid)
         from paper_1311_2286_amd import workloads as W
         q = W.as_dtype(p, np.float64 if precision == 1 else np.float32)
+        torch.cuda.synchronize()
+        t_up = time.perf_counter()
         sim.set_particles(sid, q["cell"], q["off"], q["vel"])
+        sim.sync()
+        upload_s += time.perf_counter() - t_up
+        upload_bytes += q["cell"].nbytes + q["off"].nbytes + q["vel"].nbytes
         del q
+    sim.upload_s, sim.upload_bytes = upload_s, upload_bytes
     return sim
 
 
@@ -190,6 +199,7 @@ def run_path(case, parts, precision, shape, steps, warmup, sort_every, mg_rtol, 
     if any(b != 0 for b in case.bc_lo[: case.dim]):
         n_p = int(sum(d.count[k] for k in range(d.nspecies)))  # after injection and absorption
     res = dict(wall_s=wall, ms_per_step=1e3 * wall / steps, pushes=n_p,
+               upload_s=sim.upload_s, upload_bytes=sim.upload_bytes,
                pushes_per_s=n_p * steps / wall,
                push_ms=float(np.mean(tm["push"])), solve_ms=float(np.mean(tm["solve"])),
                sort_ms=float(np.mean(tm["sort"])),
@@ -861,6 +871,11 @@ def main():
                      "launch_ms": r32["launch_ms"]},
         "cpu_baseline": cpu,
         "error_vs_oracle": errors,
+        # the particles' one upload from host arrays (pageable numpy), not in
+        # the timed steps: its rate and the pushes/s of the timed steps with it
+        "host_upload": {"bytes": r32["upload_bytes"], "s": r32["upload_s"],
+                        "GB_per_s": r32["upload_bytes"] / max(r32["upload_s"], 1e-12) / 1e9,
+                        "pushes_per_s_with_upload": r32["pushes"] * args.steps / (r32["wall_s"] + r32["upload_s"])},
     }
     if r64 is not None:
         out["fp64_path"] = {"value": r64["pushes_per_s"], "unit": "particle pushes/s",
