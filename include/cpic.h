@@ -310,9 +310,12 @@ cpic_status cpic_initialize(cpic_sim* sim);
 cpic_status cpic_step(cpic_sim* sim, int nsteps);
 
 /* Advance each of n simulations by one PIC cycle (asynchronous), with their
-   field phases batched (the throughput path of a server running many small
+   phases batched (the throughput path of a server running many small
    cases).  Each result is bit for bit what cpic_step(sims[i], 1) gives.  The
-   particle phases run case by case; the field phase (charge, the flexible-CG
+   particle phase runs as one launch over the work items of every case and
+   species whose particle kernel is the same (precision, dimension, map kind,
+   deposit shape, mover, pusher; else case by case), with the deposit clears
+   of all cases in one launch; the field phase (charge, the flexible-CG
    solve of Sec. "Field solve" with its V-cycle preconditioner, the vertex
    field) runs as one launch per kernel over all cases when every case has
    FP32 particles, the flexible-CG method, no floating wall, no injection, a
@@ -326,10 +329,10 @@ cpic_status cpic_step(cpic_sim* sim, int nsteps);
    entries) receives each case's outcome: a case that cpic_step would refuse
    (CPIC_E_STATE, CPIC_E_OVERFLOW) is left out and keeps its state while the
    others step; a runtime error during the batched launches (CPIC_E_HIP) is
-   reported for every case of the batch.  The batch's argument buffer (a few
-   hundred bytes per kernel and case) comes from the allocator of the first
-   case stepped and is freed by its cpic_destroy; when it cannot be allocated
-   the field phases run case by case.  Returns CPIC_OK, else the first
+   reported for every case of the batch.  The batch's argument buffers (a few
+   hundred bytes per kernel and case) come from the allocator of the first
+   case stepped and are freed by its cpic_destroy; when they cannot be
+   allocated the phases run case by case.  Returns CPIC_OK, else the first
    failing case's status. */
 cpic_status cpic_step_batch(cpic_sim* const* sims, int n, cpic_status* status);
 
