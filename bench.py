@@ -697,6 +697,10 @@ def run_extra(C, key, args, steps=None):
     if key in ("field_solve_mms", "field_solve_mms_boxmg"):
         sizes = tuple(int(v) for v in args.mms_sizes.split(","))
         return field_solve_mms(sizes=sizes, method=C.MG_BOXMG if key.endswith("boxmg") else 0)
+    if key == "field_solve_anisotropic":
+        return field_solve_anisotropic()
+    if key == "mover_timing":
+        return mover_timing()
     name, shp, prec, n, mover, tab, push = extra_table(C)[key]
     # the probe is timed in its injected steady state: the last 200 of the
     # configuration's 2,000 steps

@@ -2470,10 +2470,22 @@ __global__ void absmax_kernel(long long n, const double* __restrict__ src, unsig
   if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(out, __float_as_uint(m));
 }
 
+// smallest magnitude of an array (bits of a non-negative float; *out starts
+// at +inf)
+__global__ void absmin_kernel(long long n, const double* __restrict__ src, unsigned* out) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  float m = c < n ? (float)fabs(src[c]) : __int_as_float(0x7f800000);
+  for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMin(out, __float_as_uint(m));
+}
+
 __global__ void to_f16_kernel(long long n, const double* __restrict__ src, double scale, __half* dst) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c < n) dst[c] = __float2half_rn((float)(src[c] * scale));
 }
+
+// largest ratio of two diagonal entries of a level for its FP16 stencil copy
+constexpr float HALF_ROW_RANGE = 64.0f;
 
 int launch_operator_f32(GridCtx& G, hipStream_t st) {
   for (int l = 0; l < G.nlev; ++l) {
@@ -2486,13 +2498,33 @@ int launch_operator_f32(GridCtx& G, hipStream_t st) {
         hipLaunchKernelGGL(to_f32_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.S[k], L.f_S[k]);
     if (!L.h_diag) continue;
     // scale 2^-e with 2^e the smallest power of two at or above the largest
-    // coefficient: FP16 keeps 11 bits of every coefficient above 2^-14 of it
+    // coefficient: FP16 keeps 11 bits of every coefficient above 2^-14 of it.
+    // Operators whose rows differ in scale by more than HALF_ROW_RANGE (the
+    // diagonal's range: e.g. the axisymmetric r-z plane, rows ~ r) keep the
+    // FP32 stencil: the small rows' coefficients would lose their precision
+    // relative to their own row, and the preconditioner its strength
     unsigned* tmp = (unsigned*)G.mg_flag + 3;
+    unsigned bits = 0, dbits = 0;
+    const unsigned inf_bits = 0x7f800000u;
+    if (hipMemcpyAsync(tmp, &inf_bits, sizeof(unsigned), hipMemcpyHostToDevice, st) != hipSuccess) return -1;
+    hipLaunchKernelGGL(absmin_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.diag, tmp);
+    if (hipMemcpyAsync(&dbits, tmp, sizeof(dbits), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return -1;
     launch_fill_u8(tmp, 0, sizeof(unsigned), st);
     hipLaunchKernelGGL(absmax_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.diag, tmp);
+    if (hipMemcpyAsync(&bits, tmp, sizeof(bits), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return -1;
+    float dmin, dmax;
+    memcpy(&dmin, &dbits, sizeof(dmin));
+    memcpy(&dmax, &bits, sizeof(dmax));
+    if (!(dmin > 0.0f) || !(dmax <= HALF_ROW_RANGE * dmin)) {
+      L.h_diag = nullptr;  // (the copies stay allocated, unused)
+      continue;
+    }
     for (int k = 0; k < 9; ++k)
       if (L.S[k]) hipLaunchKernelGGL(absmax_kernel, dim3(blocks), dim3(256), 0, st, L.ncells, (const double*)L.S[k], tmp);
-    unsigned bits = 0;
     if (hipMemcpyAsync(&bits, tmp, sizeof(bits), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       return -1;
