@@ -97,6 +97,11 @@ def test_second_order_convergence_and_bounded_iterations():
     for r in ratios[1:]:
         assert abs(r - paper_value("mms_error_ratio_256")) < 0.15, ratios
     assert max(cycles) <= min(cycles) + 6, cycles
+    # the geometric preconditioner's strength on this operator (rows scale
+    # with r): 12, 12, 13, 14, 15, 16 iterations measured from 64^2 to 2048^2;
+    # a weakened preconditioner (e.g. reduced-precision stencil copies of its
+    # small rows) shows up here first
+    assert cycles[-1] <= 16, cycles
 
 
 def test_boxmg_iterations_meet_table_t1():
