@@ -1411,6 +1411,7 @@ struct prolong_kernelOp {
     int nc1;
     int nc2;
     const int* flag;
+    int zp;  // fine cells per thread along z (1 or 2; the grid's z extent is ceil(n2 / zp))
   };
   static __device__ void body(const Args& k_, const Blk& b_) {
     const LevelArgsT<T>& fa = k_.fa;
@@ -1423,11 +1424,23 @@ struct prolong_kernelOp {
 
   if (flag[0]) return;
   const int cn[3] = {nc0, nc1, nc2};
-  const int idx[3] = {(int)(b_.x * blockDim.x + threadIdx.x), (int)(b_.y * blockDim.y + threadIdx.y),
-                      (int)b_.z};
-  if (idx[0] >= fa.n[0] || idx[1] >= fa.n[1]) return;
-  const int c = idx[0] + fa.n[0] * (idx[1] + fa.n[1] * idx[2]);
-  phi[c] += prolong_cell(fa, cphi, cn, idx);
+  const int i = (int)(b_.x * blockDim.x + threadIdx.x), j = (int)(b_.y * blockDim.y + threadIdx.y);
+  if (i >= fa.n[0] || j >= fa.n[1]) return;
+  T e[2];
+  int cz[2] = {-1, -1};
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz) {
+    const int k = (int)b_.z * k_.zp + dz;
+    e[dz] = (T)0;
+    if (dz < k_.zp && k < fa.n[2]) {
+      const int idx[3] = {i, j, k};
+      cz[dz] = i + fa.n[0] * (j + fa.n[1] * k);
+      e[dz] = prolong_cell(fa, cphi, cn, idx);
+    }
+  }
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+    if (cz[dz] >= 0) phi[cz[dz]] += e[dz];
 
   }
 };
@@ -2161,7 +2174,12 @@ static T* vcycle(const GridCtx& G, int l, int nu1, int nu2, double* partials, hi
       op_launch<resrestrict_kernelOp<T>>(rg, dim3(64, 4, 1), typename resrestrict_kernelOp<T>::Args{a, (const T*)cur, (const T*)v.rhs, C.n[0], C.n[1], cv.rhs, cv.phi, fs, (const int*)G.mg_flag}, st);
   }
   const T* ce = vcycle<T>(G, l + 1, nu1, nu2, nullptr, st, nullptr, 0.0, coarse_first);
-  op_launch<prolong_kernelOp<T>>(gr, BLOCK3, typename prolong_kernelOp<T>::Args{a, cur, ce, C.n[0], C.n[1], C.n[2], (const int*)G.mg_flag}, st);
+  {
+    // two fine cells per thread along z on large levels (more loads in flight)
+    const int zp = L.ncells >= SMOOTH_ZP_CELLS ? 2 : 1;
+    const dim3 pg(gr.x, gr.y, (unsigned)((L.n[2] + zp - 1) / zp));
+    op_launch<prolong_kernelOp<T>>(pg, BLOCK3, typename prolong_kernelOp<T>::Args{a, cur, ce, C.n[0], C.n[1], C.n[2], (const int*)G.mg_flag, zp}, st);
+  }
   return smooth_level<T>(G, l, nu2, true, partials, st, nullptr, 0.0, false, cur);
 }
 
@@ -3540,7 +3558,7 @@ static void boxmg_vcycle(const GridCtx& G, int l, hipStream_t st) {
   }
   op_launch<restrict_kernelOp<float>>(grid3(C), BLOCK3, restrict_kernelOp<float>::Args{fa, (const float*)L.f_res, C.n[0], C.n[1], C.n[2], C.f_rhs, C.f_phi, (const int*)G.mg_flag}, st);
   boxmg_vcycle(G, l + 1, st);
-  op_launch<prolong_kernelOp<float>>(grid3(L), BLOCK3, prolong_kernelOp<float>::Args{fa, L.f_phi, (const float*)C.f_phi, C.n[0], C.n[1], C.n[2], (const int*)G.mg_flag}, st);
+  op_launch<prolong_kernelOp<float>>(grid3(L), BLOCK3, prolong_kernelOp<float>::Args{fa, L.f_phi, (const float*)C.f_phi, C.n[0], C.n[1], C.n[2], (const int*)G.mg_flag, 1}, st);
   line_relax(G, l, true, st);
   line_relax(G, l, true, st);
 }
