@@ -3603,6 +3603,15 @@ static void replay_one(int kind, dim3 g, dim3 b, const void* a, int n, hipStream
   }
 }
 
+// The argument buffer's copy from pinned host memory (read by the kernel
+// through its device address) to the device buffer: launching it costs the
+// host a few microseconds, an asynchronous copy call several times that.
+__global__ __launch_bounds__(256) void args_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                        long long n16) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n16; i += (long long)gridDim.x * 256)
+    dst[i] = src[i];
+}
+
 int batch_upload(BatchArgs& ba, hipStream_t st) {
   const size_t total = ba.staging.size();
   if (total > ba.bytes || total > ba.pinned_bytes) {
@@ -3619,6 +3628,7 @@ int batch_upload(BatchArgs& ba, hipStream_t st) {
         free_batch_args(ba);
         return -2;
       }
+      if (hipHostGetDevicePointer(&ba.pinned_dev[k], ba.pinned[k], 0) != hipSuccess) ba.pinned_dev[k] = nullptr;
       if (hipEventCreateWithFlags(&ba.copied[k], hipEventDisableTiming) != hipSuccess) {
         ba.copied[k] = nullptr;
         free_batch_args(ba);
@@ -3635,7 +3645,18 @@ int batch_upload(BatchArgs& ba, hipStream_t st) {
     ba.slot ^= 1;
     if (hipEventSynchronize(ba.copied[k]) != hipSuccess) return -3;
     memcpy(ba.pinned[k], ba.staging.data(), total);
-    if (hipMemcpyAsync(ba.dev, ba.pinned[k], total, hipMemcpyHostToDevice, st) != hipSuccess) return -3;
+    // whole 16-byte words: both buffers hold at least total + 4096 bytes
+    const long long n16 = (long long)((total + 15) / 16);
+    if (n16 == 0) {
+      // nothing to copy
+    } else if (ba.pinned_dev[k] && (((uintptr_t)ba.pinned_dev[k] | (uintptr_t)ba.dev) & 15) == 0) {
+      const unsigned blocks = (unsigned)std::min<long long>(64, (n16 + 255) / 256);
+      hipLaunchKernelGGL(args_copy_kernel, dim3(blocks), dim3(256), 0, st, (const uint4*)ba.pinned_dev[k],
+                         (uint4*)ba.dev, n16);
+      if (hipGetLastError() != hipSuccess) return -3;
+    } else if (hipMemcpyAsync(ba.dev, ba.pinned[k], total, hipMemcpyHostToDevice, st) != hipSuccess) {
+      return -3;
+    }
     if (hipEventRecord(ba.copied[k], st) != hipSuccess) return -3;
     ba.uploaded = ba.staging;
   }
@@ -3724,6 +3745,7 @@ void free_batch_args(BatchArgs& ba) {
     if (ba.pinned[k]) (void)hipHostFree(ba.pinned[k]);
     if (ba.copied[k]) (void)hipEventDestroy(ba.copied[k]);
     ba.pinned[k] = nullptr;
+    ba.pinned_dev[k] = nullptr;
     ba.copied[k] = nullptr;
   }
   ba.pinned_bytes = 0;

@@ -308,6 +308,7 @@ struct BatchArgs {
   size_t bytes = 0;
   std::vector<unsigned char> staging, uploaded;
   void* pinned[2] = {nullptr, nullptr};
+  void* pinned_dev[2] = {nullptr, nullptr};  // their addresses for kernels
   hipEvent_t copied[2] = {nullptr, nullptr};
   size_t pinned_bytes = 0;
   int slot = 0;
