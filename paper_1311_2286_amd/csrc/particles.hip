@@ -1344,8 +1344,17 @@ __device__ __forceinline__ void particle_body(const PartArgs<R>& a, const int it
   }
 }
 
+// Threads per workgroup of the particle kernel: 512 for the 3D
+// predictor-corrector, whose LDS windows (about 78 KB) leave room for two
+// workgroups per CU, so that a CU keeps 16 waves in flight instead of 8; 256
+// for the others.
+template <int D, int MAP>
+constexpr int pk_threads() {
+  return (D == 3 && MAP == MAP_TABLE_PC) ? 512 : 256;
+}
+
 template <int D, int MAP, int SHAPE, typename R, bool FIXED, bool CYC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && MAP != MAP_TABULATED) ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel(
+__global__ __launch_bounds__((pk_threads<D, MAP>())) __attribute__((amdgpu_waves_per_eu((FIXED && MAP != MAP_TABULATED) ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel(
     PartArgs<R> a) {
   particle_body<D, MAP, SHAPE, R, FIXED, CYC>(a, blockIdx.x);
 }
@@ -1353,7 +1362,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && M
 // The work items of several simulations (or species) in one launch: entry e
 // owns the workgroups base[e] .. base[e + 1] - 1, with its own arguments.
 template <int D, int MAP, int SHAPE, typename R, bool FIXED, bool CYC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FIXED && MAP != MAP_TABULATED) ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel_batch(
+__global__ __launch_bounds__((pk_threads<D, MAP>())) __attribute__((amdgpu_waves_per_eu((FIXED && MAP != MAP_TABULATED) ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel_batch(
     const PartArgs<R>* __restrict__ A, const int* __restrict__ base, int n) {
   const int b = (int)blockIdx.x;
   int lo = 0, hi = n;
@@ -1993,10 +2002,10 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
   // the appended particles' items (maps that allow injection)
   const int tail = (MAP == MAP_IDENTITY || MAP == MAP_POLAR_LOG || MAP == MAP_TABLE_PC) ? TAIL_ITEMS : 0;
   if (L.cyclo)
-    hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED, true>), dim3(L.max_items + tail), dim3(256), 0, st,
+    hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED, true>), dim3(L.max_items + tail), dim3((pk_threads<D, MAP>())), 0, st,
                      a);
   else
-    hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED, false>), dim3(L.max_items + tail), dim3(256), 0, st,
+    hipLaunchKernelGGL((particle_kernel<D, MAP, SHAPE, R, FIXED, false>), dim3(L.max_items + tail), dim3((pk_threads<D, MAP>())), 0, st,
                      a);
   if constexpr (MAP != MAP_IDENTITY && MAP != MAP_TABLE_PC) {
     if (L.mode == MODE_PUSH)
@@ -2026,10 +2035,10 @@ static int launch_particle_batch_t(const ParticleLaunch* Ls, int n, BatchArgs& b
   const int* dB = (const int*)((const unsigned char*)ba.dev + off_base);
   const int ne = (int)args.size();
   if (Ls[0].cyclo)
-    hipLaunchKernelGGL((particle_kernel_batch<D, MAP, SHAPE, R, FIXED, true>), dim3(base.back()), dim3(256), 0, st,
+    hipLaunchKernelGGL((particle_kernel_batch<D, MAP, SHAPE, R, FIXED, true>), dim3(base.back()), dim3((pk_threads<D, MAP>())), 0, st,
                        dA, dB, ne);
   else
-    hipLaunchKernelGGL((particle_kernel_batch<D, MAP, SHAPE, R, FIXED, false>), dim3(base.back()), dim3(256), 0, st,
+    hipLaunchKernelGGL((particle_kernel_batch<D, MAP, SHAPE, R, FIXED, false>), dim3(base.back()), dim3((pk_threads<D, MAP>())), 0, st,
                        dA, dB, ne);
   if constexpr (MAP != MAP_IDENTITY && MAP != MAP_TABLE_PC) {
     if (Ls[0].mode == MODE_PUSH)
