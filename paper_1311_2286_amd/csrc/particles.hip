@@ -1203,12 +1203,18 @@ __device__ __forceinline__ void particle_body(const PartArgs<R>& a, const int it
           }
         }
         if (!done) {
-          double f64[3] = {(double)f[0], (double)f[1], (double)f[2]}, disp[3], dd[3];
+          if constexpr (XWIN) {
+            // the FP64 fallback kernel inverts it on the global table (kept out
+            // of this kernel, whose registers it would otherwise set)
+            conv = false;
+          } else {
+            double f64[3] = {(double)f[0], (double)f[1], (double)f[2]}, disp[3], dd[3];
 #pragma unroll
-          for (int ax = 0; ax < 3; ++ax) disp[ax] = (double)a.dt * (double)v[ax];
-          conv = move_tab<D>(g, idx, f64, disp, 16, dd);
+            for (int ax = 0; ax < 3; ++ax) disp[ax] = (double)a.dt * (double)v[ax];
+            conv = move_tab<D>(g, idx, f64, disp, 16, dd);
 #pragma unroll
-          for (int ax = 0; ax < D; ++ax) d[ax] = (R)dd[ax];
+            for (int ax = 0; ax < D; ++ax) d[ax] = (R)dd[ax];
+          }
         }
       } else
         conv = move_delta<D, MAP, R>(g, idx, f, v, a.dt, a.inv_dxc, a.newton_maxit, a.newton_tol,
@@ -1350,11 +1356,18 @@ __device__ __forceinline__ void particle_body(const PartArgs<R>& a, const int it
 // for the others.
 template <int D, int MAP>
 constexpr int pk_threads() {
-  return (D == 3 && MAP == MAP_TABLE_PC) ? 512 : 256;
+  return (D == 3 && (MAP == MAP_TABLE_PC || MAP == MAP_TABULATED)) ? 512 : 256;
+}
+// Waves per SIMD the register allocation aims at: what the LDS windows allow
+// (3D predictor-corrector: two 512-thread workgroups per CU; 3D tabulated
+// Newton: three 256-thread workgroups), five elsewhere; two for FP64.
+template <int D, int MAP, bool FIXED>
+constexpr int pk_waves() {
+  return !FIXED ? 2 : (D == 3 && (MAP == MAP_TABLE_PC || MAP == MAP_TABULATED)) ? 4 : 5;
 }
 
 template <int D, int MAP, int SHAPE, typename R, bool FIXED, bool CYC>
-__global__ __launch_bounds__((pk_threads<D, MAP>())) __attribute__((amdgpu_waves_per_eu((FIXED && MAP != MAP_TABULATED) ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel(
+__global__ __launch_bounds__((pk_threads<D, MAP>())) __attribute__((amdgpu_waves_per_eu(pk_waves<D, MAP, FIXED>(), 8))) void particle_kernel(
     PartArgs<R> a) {
   particle_body<D, MAP, SHAPE, R, FIXED, CYC>(a, blockIdx.x);
 }
@@ -1362,7 +1375,7 @@ __global__ __launch_bounds__((pk_threads<D, MAP>())) __attribute__((amdgpu_waves
 // The work items of several simulations (or species) in one launch: entry e
 // owns the workgroups base[e] .. base[e + 1] - 1, with its own arguments.
 template <int D, int MAP, int SHAPE, typename R, bool FIXED, bool CYC>
-__global__ __launch_bounds__((pk_threads<D, MAP>())) __attribute__((amdgpu_waves_per_eu((FIXED && MAP != MAP_TABULATED) ? ((D == 3 && MAP == MAP_TABLE_PC) ? 4 : 5) : 2, 8))) void particle_kernel_batch(
+__global__ __launch_bounds__((pk_threads<D, MAP>())) __attribute__((amdgpu_waves_per_eu(pk_waves<D, MAP, FIXED>(), 8))) void particle_kernel_batch(
     const PartArgs<R>* __restrict__ A, const int* __restrict__ base, int n) {
   const int b = (int)blockIdx.x;
   int lo = 0, hi = n;
