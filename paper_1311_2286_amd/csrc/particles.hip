@@ -1515,6 +1515,11 @@ __device__ __forceinline__ void fallback_body(const PartArgs<R>& a, int shape) {
   }
 }
 
+// Workgroups of the fallback launch (grid-stride over the queue, whose length
+// only the device knows): one per CU, so that a step with many FP64 updates
+// (the tabulated map's window failures) spreads them over the whole GPU.
+constexpr int FB_BLOCKS = 256;
+
 template <int D, int MAP, typename R, bool FIXED>
 __global__ __launch_bounds__(256) void fallback_kernel(PartArgs<R> a, int shape) {
   fallback_body<D, MAP, R, FIXED>(a, shape);
@@ -2022,7 +2027,7 @@ static void launch_particle_t(const ParticleLaunch& L, hipStream_t st) {
                      a);
   if constexpr (MAP != MAP_IDENTITY && MAP != MAP_TABLE_PC) {
     if (L.mode == MODE_PUSH)
-      hipLaunchKernelGGL((fallback_kernel<D, MAP, R, FIXED>), dim3(64), dim3(256), 0, st, a, L.shape);
+      hipLaunchKernelGGL((fallback_kernel<D, MAP, R, FIXED>), dim3(FB_BLOCKS), dim3(256), 0, st, a, L.shape);
   }
 }
 
@@ -2055,7 +2060,7 @@ static int launch_particle_batch_t(const ParticleLaunch* Ls, int n, BatchArgs& b
                        dA, dB, ne);
   if constexpr (MAP != MAP_IDENTITY && MAP != MAP_TABLE_PC) {
     if (Ls[0].mode == MODE_PUSH)
-      hipLaunchKernelGGL((fallback_kernel_batch<D, MAP, R, FIXED>), dim3(64, ne), dim3(256), 0, st, dA, Ls[0].shape);
+      hipLaunchKernelGGL((fallback_kernel_batch<D, MAP, R, FIXED>), dim3(FB_BLOCKS, ne), dim3(256), 0, st, dA, Ls[0].shape);
   }
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
