@@ -1517,8 +1517,10 @@ __device__ __forceinline__ void fallback_body(const PartArgs<R>& a, int shape) {
 
 // Workgroups of the fallback launch (grid-stride over the queue, whose length
 // only the device knows): one per CU, so that a step with many FP64 updates
-// (the tabulated map's window failures) spreads them over the whole GPU.
+// (the tabulated map's window failures) spreads them over the whole GPU; a
+// batched launch, whose entries are small cases, takes fewer per entry.
 constexpr int FB_BLOCKS = 256;
+constexpr int FB_BATCH_BLOCKS = 64;
 
 template <int D, int MAP, typename R, bool FIXED>
 __global__ __launch_bounds__(256) void fallback_kernel(PartArgs<R> a, int shape) {
@@ -2060,7 +2062,7 @@ static int launch_particle_batch_t(const ParticleLaunch* Ls, int n, BatchArgs& b
                        dA, dB, ne);
   if constexpr (MAP != MAP_IDENTITY && MAP != MAP_TABLE_PC) {
     if (Ls[0].mode == MODE_PUSH)
-      hipLaunchKernelGGL((fallback_kernel_batch<D, MAP, R, FIXED>), dim3(FB_BLOCKS, ne), dim3(256), 0, st, dA, Ls[0].shape);
+      hipLaunchKernelGGL((fallback_kernel_batch<D, MAP, R, FIXED>), dim3(FB_BATCH_BLOCKS, ne), dim3(256), 0, st, dA, Ls[0].shape);
   }
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
