@@ -1351,16 +1351,17 @@ __device__ __forceinline__ void particle_body(const PartArgs<R>& a, const int it
 }
 
 // Threads per workgroup of the particle kernel: 512 for the 3D
-// predictor-corrector, whose LDS windows (about 78 KB) leave room for two
-// workgroups per CU, so that a CU keeps 16 waves in flight instead of 8; 256
-// for the others.
+// predictor-corrector and tabulated-map Newton kernels, whose LDS windows
+// (about 78 and 46 KB) leave room for two such workgroups per CU, so that a
+// CU keeps 16 waves in flight (8 and 12 with 256-thread workgroups); 256 for
+// the others.
 template <int D, int MAP>
 constexpr int pk_threads() {
   return (D == 3 && (MAP == MAP_TABLE_PC || MAP == MAP_TABULATED)) ? 512 : 256;
 }
-// Waves per SIMD the register allocation aims at: what the LDS windows allow
-// (3D predictor-corrector: two 512-thread workgroups per CU; 3D tabulated
-// Newton: three 256-thread workgroups), five elsewhere; two for FP64.
+// Waves per SIMD the register allocation aims at: four for the 3D kernels of
+// 512-thread workgroups (two per CU), five for the other FP32 kernels, two
+// for FP64.
 template <int D, int MAP, bool FIXED>
 constexpr int pk_waves() {
   return !FIXED ? 2 : (D == 3 && (MAP == MAP_TABLE_PC || MAP == MAP_TABULATED)) ? 4 : 5;
