@@ -10,6 +10,8 @@ fixed-point deposit (Eqs. pg, Wpc, b2; CIC) of the live particles at the
 positions the GPU moved them to, read back through cpic_get_particles -- the
 same positions on both sides.  A misplaced window flush or far deposit keeps
 the total but fails this."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -54,7 +56,14 @@ CASES = {
                                         case_id=121),
     # walls: absorption at the probe, outflow at the outer wall
     "2d_probe": probe_case,
+    # the probe on its tabulated map, Newton on the interpolant: updates that
+    # leave the LDS window or cross a wall go to the FP64 fallback kernel
+    "2d_probe_tab": lambda: dataclasses.replace(probe_case(), tabulated=True, case_id=122),
+    "3d_sin_tab": lambda: dataclasses.replace(W.small_case(dim=3, n=(20, 12, 16), ppc=4.0, case_id=123),
+                                              tabulated=True),
 }
+# cases whose position update is Newton on a tabulated map
+NEWTON_TAB = ("2d_probe_tab", "3d_sin_tab")
 
 
 def live_deposit(case, sim, g, shape, sid):
@@ -69,7 +78,8 @@ def live_deposit(case, sim, g, shape, sid):
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_push_deposit_bit_exact(name, shape):
     case = CASES[name]()
-    sim, parts = gpu_sim(case, precision=0, shape=shape)
+    kw = {"mover": C().MOVER_NEWTON} if name in NEWTON_TAB else {}
+    sim, parts = gpu_sim(case, precision=0, shape=shape, **kw)
     nv = sim.field_bytes(C().FIELD_EV) // 4 // (4 if case.dim == 3 else 2)
     E = W.synthetic_ev(case, nv, dtype=np.float32)
     ec = 4 if case.dim == 3 else 2
@@ -86,7 +96,7 @@ def test_push_deposit_bit_exact(name, shape):
         assert nlive == d.count[sid]
     if name == "3d_fast":
         assert d.far_deposits > 0
-    if name == "2d_fallback":
+    if name in ("2d_fallback", "2d_probe_tab"):
         assert d.newton_fallback > 0
     if name == "2d_probe":
         assert sum(d.absorbed[:2]) + sum(d.outflow[:2]) > 0
